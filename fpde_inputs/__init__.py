@@ -1,0 +1,9 @@
+"""Seeded synthetic inputs (meshes, noise) shared by the oracle and the GPU library.
+
+Holds none of the method's arithmetic; see ``meshes`` for the generators.
+"""
+from .meshes import (Mesh, kuhn_cube, hull_mesh, radius_ratio, workload_mesh,
+                     WORKLOADS, sphere_points, ellipsoid_points, morton_renumber)
+
+__all__ = ["Mesh", "kuhn_cube", "hull_mesh", "radius_ratio", "workload_mesh",
+           "WORKLOADS", "sphere_points", "ellipsoid_points", "morton_renumber"]

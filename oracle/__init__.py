@@ -1,0 +1,384 @@
+"""Plain FP64 CPU oracle for the 3-D fractional FEM stiffness assembly and solve.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the GPU library.  The heavy loops
+live in ``fpde_oracle.c`` (plain C, ``-O2 -ffp-contract=off``); this module
+marshals arguments, supplies the closed-form scalars (Gamma, digamma, the
+Riesz constant), the textbook solves (LAPACK Cholesky through SciPy, plain
+CG) and the manufactured solution on the unit cube.
+
+Problem (the Riesz instance of form 1 of the paper's uniform variational
+form, Sec. 1 eq. equ:varsss, on a convex polyhedron with zero extension):
+
+    -sum_i K_i d^alpha u / d|x_i|^alpha = f,   1 < alpha <= 2,
+
+with d^alpha/d|x|^alpha = -(D_L^alpha + D_R^alpha) / (2 cos(pi alpha / 2)).
+Splitting each one-sided operator into two of order gamma = alpha/2 gives
+
+    a(u, v) = c_alpha sum_i K_i [(D_L^g u, D_R^g v) + (D_R^g u, D_L^g v)],
+    c_alpha = 1 / (2 cos(pi alpha / 2))  (< 0 on (1, 2); -1/2 at alpha = 2),
+
+which is symmetric positive definite and equals sum_i K_i (d_i u, d_i v) at
+alpha = 2.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "fpde_oracle.c"
+_LIB = _HERE / "_fpde_oracle.so"
+
+ORC_EPATH = -5
+DEFAULT_CAP = 4096
+
+
+def build(force: bool = True) -> Path:
+    """Compile the C oracle with gcc (plain FP64, no FMA contraction)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp")
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                        "-fPIC", "-shared", "-o", str(tmp), str(_SRC), "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        build(force=True)
+    L = ctypes.CDLL(str(_LIB))
+    P = ctypes.c_void_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.orc_mesh_create.restype = P
+    L.orc_mesh_create.argtypes = [P, i64, P, i64, P]
+    L.orc_mesh_free.argtypes = [P]
+    L.orc_mesh_ndof.restype = i64
+    L.orc_mesh_ndof.argtypes = [P]
+    L.orc_mesh_dof.argtypes = [P, P]
+    L.orc_mesh_nbr.argtypes = [P, P]
+    L.orc_mesh_affine.argtypes = [P, P, P]
+    L.orc_quadrature.argtypes = [i32, P, P]
+    L.orc_gauss_points.argtypes = [P, i32, P, P]
+    L.orc_paths.argtypes = [P, i32, i64, i64, i32, P, P, P, P]
+    L.orc_exit_pattern.argtypes = [P, i64, P, i32, i32, P, P]
+    L.orc_ray_values.argtypes = [P, i32, i64, i32, i32, dbl, dbl, dbl, dbl, i32, i32, P, P]
+    L.orc_assemble.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P]
+    L.orc_apply.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, P]
+    L.orc_adjoint_sums.argtypes = [P, i32, dbl, dbl, dbl, i32, P, P, P, P]
+    L.orc_load.argtypes = [P, i32, P, P]
+    L.orc_exhaustive.argtypes = [P, P, P, P, P]
+    L.orc_walk_from.argtypes = [P, i64, P, i32, i32, i32, P, P, P]
+    _lib = L
+    return L
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        super().__init__(f"oracle status {status} {what}")
+        self.status = status
+
+
+# --------------------------------------------------------------------------
+# Closed-form scalars
+# --------------------------------------------------------------------------
+def c_alpha(alpha: float) -> float:
+    """c_alpha = 1 / (2 cos(pi alpha / 2)): minus the Riesz normalisation."""
+    return 1.0 / (2.0 * math.cos(math.pi * alpha / 2.0))
+
+
+def dc_alpha(alpha: float) -> float:
+    """d c_alpha / d alpha = (pi/4) sin(pi alpha/2) / cos^2(pi alpha/2)."""
+    c = math.cos(math.pi * alpha / 2.0)
+    return (math.pi / 4.0) * math.sin(math.pi * alpha / 2.0) / (c * c)
+
+
+def order_scalars(alpha: float):
+    """gamma = alpha/2, 1/Gamma(2-gamma), 1/Gamma(1-gamma), psi(2-gamma)/2."""
+    from scipy.special import rgamma, digamma
+    g = alpha / 2.0
+    return g, float(rgamma(2.0 - g)), float(rgamma(1.0 - g)), 0.5 * float(digamma(2.0 - g))
+
+
+def quadrature(nq: int):
+    L = _load()
+    bary = np.zeros((nq, 4))
+    w = np.zeros(nq)
+    st = L.orc_quadrature(nq, _p(bary), _p(w))
+    if st != 0:
+        raise OracleError(st, f"no {nq}-point rule")
+    return bary, w
+
+
+# --------------------------------------------------------------------------
+# Mesh-bound operations
+# --------------------------------------------------------------------------
+class OracleMesh:
+    def __init__(self, xyz, tet, cap: int = DEFAULT_CAP):
+        L = _load()
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tet = np.ascontiguousarray(tet, dtype=np.int32)
+        self.cap = int(cap)
+        st = ctypes.c_int(0)
+        h = L.orc_mesh_create(_p(self.xyz), self.xyz.shape[0], _p(self.tet), self.tet.shape[0],
+                              ctypes.byref(st))
+        if not h:
+            raise OracleError(st.value, "mesh")
+        self._h = ctypes.c_void_p(h)
+        self.n_vert = self.xyz.shape[0]
+        self.n_tet = self.tet.shape[0]
+        self.ndof = int(L.orc_mesh_ndof(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_mesh_free(self._h)
+            self._h = None
+
+    # mesh data -----------------------------------------------------------
+    @property
+    def dof(self) -> np.ndarray:
+        out = np.empty(self.n_vert, dtype=np.int32)
+        _lib.orc_mesh_dof(self._h, _p(out))
+        return out
+
+    @property
+    def nbr(self) -> np.ndarray:
+        out = np.empty((self.n_tet, 4), dtype=np.int32)
+        _lib.orc_mesh_nbr(self._h, _p(out))
+        return out
+
+    def affine(self):
+        M = np.empty((self.n_tet, 3, 3))
+        vol = np.empty(self.n_tet)
+        _lib.orc_mesh_affine(self._h, _p(M), _p(vol))
+        return M, vol
+
+    def gauss_points(self, nq: int):
+        G = self.n_tet * nq
+        x = np.empty((G, 3))
+        w = np.empty(G)
+        st = _lib.orc_gauss_points(self._h, nq, _p(x), _p(w))
+        if st != 0:
+            raise OracleError(st)
+        return x, w
+
+    # paths ---------------------------------------------------------------
+    def paths(self, nq: int, h0: int = 0, count: int | None = None, lists: bool = False):
+        """Half-ray h = g*6 + 2*i + side: (length, FNV-1a hash[, ids, r_end])."""
+        if count is None:
+            count = self.n_tet * nq * 6 - h0
+        ln = np.zeros(count, dtype=np.int32)
+        hs = np.zeros(count, dtype=np.uint64)
+        ids = np.full((count, self.cap), -1, dtype=np.int32) if lists else None
+        rend = np.zeros((count, self.cap)) if lists else None
+        st = _lib.orc_paths(self._h, nq, h0, count, self.cap, _p(ln), _p(hs),
+                            _p(ids) if lists else None, _p(rend) if lists else None)
+        if st != 0:
+            raise OracleError(st, "paths")
+        if lists:
+            return ln, hs, ids, rend
+        return ln, hs
+
+    def exit_pattern(self, t: int, u0, i: int, s: int):
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        k = np.zeros(4)
+        rr = np.zeros(2)
+        z = _lib.orc_exit_pattern(self._h, t, _p(u0), i, s, _p(k), _p(rr))
+        return z, k, rr
+
+    def walk(self, t0: int, u0, i: int, s: int):
+        """Path of the ray u0 + r s e_i from inside element t0: (ids, r_end)."""
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        ids = np.empty(self.cap, dtype=np.int32)
+        rend = np.empty(self.cap)
+        n = ctypes.c_int(0)
+        st = _lib.orc_walk_from(self._h, t0, _p(u0), i, s, self.cap, _p(ids), _p(rend), ctypes.byref(n))
+        if st != 0:
+            raise OracleError(st, "walk")
+        return ids[: n.value].copy(), rend[: n.value].copy()
+
+    def exhaustive(self, u0, d):
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        lo = np.empty(self.n_tet)
+        hi = np.empty(self.n_tet)
+        _lib.orc_exhaustive(self._h, _p(u0), _p(d), _p(lo), _p(hi))
+        return lo, hi
+
+    # derivative vectors --------------------------------------------------
+    def ray_values(self, nq: int, g: int, i: int, side: int, alpha: float, mode: int = 0):
+        """mode 0: interior dofs; 1: all vertices with the end-point term;
+        2: d/dalpha of mode 0."""
+        gm, ig2, ig1, hp = order_scalars(alpha)
+        ids = np.empty(4 * self.cap, dtype=np.int32)
+        vals = np.empty(4 * self.cap)
+        n = _lib.orc_ray_values(self._h, nq, g, i, side, gm, ig2, ig1, hp, mode, self.cap,
+                                _p(ids), _p(vals))
+        if n < 0:
+            raise OracleError(n, "ray")
+        return ids[:n].copy(), vals[:n].copy()
+
+    # assembly ------------------------------------------------------------
+    def assemble(self, nq: int, alpha: float, K=(1.0, 1.0, 1.0)) -> np.ndarray:
+        gm, ig2, _, _ = order_scalars(alpha)
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        A = np.zeros((self.ndof, self.ndof))
+        st = _lib.orc_assemble(self._h, nq, gm, ig2, c_alpha(alpha), _p(Kc), self.cap, _p(A))
+        if st != 0:
+            raise OracleError(st, "assemble")
+        return A
+
+    def apply(self, nq: int, alpha: float, K, x) -> np.ndarray:
+        gm, ig2, _, _ = order_scalars(alpha)
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.ndof)
+        st = _lib.orc_apply(self._h, nq, gm, ig2, c_alpha(alpha), _p(Kc), self.cap, _p(x), _p(y))
+        if st != 0:
+            raise OracleError(st, "apply")
+        return y
+
+    def load(self, nq: int, f_gauss=None) -> np.ndarray:
+        b = np.zeros(self.ndof)
+        f = None if f_gauss is None else np.ascontiguousarray(f_gauss, dtype=np.float64)
+        st = _lib.orc_load(self._h, nq, _p(f) if f is not None else None, _p(b))
+        if st != 0:
+            raise OracleError(st, "load")
+        return b
+
+    def adjoint_sums(self, nq: int, alpha: float, u, lam):
+        gm, ig2, _, hp = order_scalars(alpha)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        S = np.zeros(3)
+        T = np.zeros(3)
+        st = _lib.orc_adjoint_sums(self._h, nq, gm, ig2, hp, self.cap, _p(u), _p(lam), _p(S), _p(T))
+        if st != 0:
+            raise OracleError(st, "adjoint")
+        return S, T
+
+    # whole problems ------------------------------------------------------
+    def gradient(self, nq: int, alpha: float, K, u, gbar, A=None):
+        """d(loss)/d(alpha), d(loss)/dK for u = A(alpha,K)^{-1} b with
+        dloss/du = gbar: lam = A^{-1} gbar, dJ/dtheta = -lam^T (dA/dtheta) u."""
+        if A is None:
+            A = self.assemble(nq, alpha, K)
+        lam = solve_spd(A, gbar)
+        S, T = self.adjoint_sums(nq, alpha, u, lam)
+        ca, dca = c_alpha(alpha), dc_alpha(alpha)
+        K = np.asarray(K, dtype=np.float64)
+        dK = -ca * S
+        da = -float(np.sum(K * (dca * S + ca * T)))
+        return da, dK
+
+
+# --------------------------------------------------------------------------
+# Solves (textbook routines)
+# --------------------------------------------------------------------------
+def solve_spd(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """LAPACK Cholesky (dpotrf/dpotrs via SciPy)."""
+    from scipy.linalg import cho_factor, cho_solve
+    return cho_solve(cho_factor(A, lower=True), b)
+
+
+def cg(apply, b: np.ndarray, tol: float = 1e-13, maxiter: int = 10000):
+    """Plain conjugate gradients on a symmetric positive definite operator."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    bn = math.sqrt(float(b @ b))
+    it = 0
+    while math.sqrt(rr) > tol * bn and it < maxiter:
+        q = apply(p)
+        a = rr / float(p @ q)
+        x += a * p
+        r -= a * q
+        rr2 = float(r @ r)
+        p = r + (rr2 / rr) * p
+        rr = rr2
+        it += 1
+    return x, it
+
+
+# --------------------------------------------------------------------------
+# Manufactured solution on the unit cube
+# --------------------------------------------------------------------------
+def mms_phi(s):
+    return s * s * (1.0 - s) ** 2
+
+
+def mms_Phi(s, alpha: float):
+    """Left RL derivative of order alpha of s^2 - 2 s^3 + s^4 from 0:
+    D^alpha s^n = Gamma(n+1)/Gamma(n+1-alpha) s^(n-alpha)."""
+    from scipy.special import rgamma
+    s = np.asarray(s, dtype=np.float64)
+    return (2.0 * s ** (2 - alpha) * rgamma(3 - alpha)
+            - 12.0 * s ** (3 - alpha) * rgamma(4 - alpha)
+            + 24.0 * s ** (4 - alpha) * rgamma(5 - alpha))
+
+
+def mms_exact(x: np.ndarray) -> np.ndarray:
+    return mms_phi(x[:, 0]) * mms_phi(x[:, 1]) * mms_phi(x[:, 2])
+
+
+def mms_source(x: np.ndarray, alpha: float, K=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """f = sum_i K_i c_alpha [Phi(x_i) + Phi(1 - x_i)] prod_{m != i} phi(x_m)."""
+    ca = c_alpha(alpha)
+    f = np.zeros(x.shape[0])
+    ph = [mms_phi(x[:, d]) for d in range(3)]
+    for i in range(3):
+        other = np.ones(x.shape[0])
+        for d in range(3):
+            if d != i:
+                other = other * ph[d]
+        f += K[i] * ca * (mms_Phi(x[:, i], alpha) + mms_Phi(1.0 - x[:, i], alpha)) * other
+    return f
+
+
+def solve_problem(mesh: OracleMesh, nq: int, alpha: float, K=(1.0, 1.0, 1.0), f_gauss=None):
+    A = mesh.assemble(nq, alpha, K)
+    b = mesh.load(nq, f_gauss)
+    return A, b, solve_spd(A, b)
+
+
+def nodal_full(mesh: OracleMesh, u_dof: np.ndarray) -> np.ndarray:
+    """Nodal values on all vertices (zero on the boundary)."""
+    dof = mesh.dof
+    full = np.zeros(mesh.n_vert)
+    full[dof >= 0] = u_dof[dof[dof >= 0]]
+    return full
+
+
+def l2_error(mesh: OracleMesh, u_dof: np.ndarray, exact, nq: int = 11) -> float:
+    """||u - u_h||_{L2} with the nq-point rule on every element."""
+    bary, _ = quadrature(nq)
+    x, w = mesh.gauss_points(nq)
+    full = nodal_full(mesh, u_dof)
+    uh = np.einsum("qj,tj->tq", bary, full[mesh.tet]).reshape(-1)
+    e = exact(x) - uh
+    return math.sqrt(float(np.sum(w * e * e)))
+
+
+def h_max(mesh: OracleMesh) -> float:
+    p = mesh.xyz[mesh.tet]
+    h = 0.0
+    for a in range(4):
+        for b in range(a + 1, 4):
+            h = max(h, float(np.linalg.norm(p[:, a] - p[:, b], axis=1).max()))
+    return h

@@ -1,0 +1,758 @@
+/*
+ * Plain FP64 CPU oracle for the P1 finite-element discretisation of the
+ * steady Riesz fractional diffusion problem on a convex tetrahedral mesh
+ * (Yang, Nie, Yuan & Wang, "Finite Element Methods for Fractional PDEs in
+ * Three Dimensions").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file.  It shares no code with the
+ * GPU library and is deliberately slow and literal: straight loops, a fixed
+ * iteration order, FP64 throughout, no FMA contraction (built with
+ * -ffp-contract=off).
+ *
+ * What it computes (all citations are to the paper):
+ *   - chord bounds a_i(x), b_i(x) of the convex domain along e_i (Sec. 1,
+ *     eq. (1)): reached as the end of the walked path;
+ *   - the integration path of a Gauss point: the ray-simplex intersection in
+ *     volume coordinates (Sec. 2.2, eqs. eq:ck, eq:condrs2, eq:cond, equ:ac),
+ *     the go-out m-face read from the zero pattern of the volume coordinates
+ *     at r_max (Sec. 2.2, Fig. 2) and the move to the adjacent element;
+ *   - the order-gamma left/right Riemann-Liouville derivatives (Sec. 1,
+ *     eq. def, m = 1) of the P1 basis functions, summed segment by segment
+ *     along the path (Sec. 2.1, the decomposition into D_{i,s_k}), in the
+ *     closed form obtained by integrating the linear basis function by parts
+ *     on each segment;
+ *   - the element quadrature of the bilinear form (Sec. 2.1, (K_E)_kl) and
+ *     the global dense matrix K = sum_E K_E, here for the Riesz operator split
+ *     into (D_L^gamma u, D_R^gamma v) + (D_R^gamma u, D_L^gamma v)
+ *     (form 1 of eq. equ:varsss with alpha = beta = gamma);
+ *   - the load vector, a matrix-free product with K and the sums needed for
+ *     the adjoint derivatives with respect to the order and the coefficients.
+ *
+ * Readings where the paper is silent (each one is stated where it is used):
+ *   - zero component of a volume coordinate: |k| <= 1e-12;
+ *   - several elements share the go-out edge/vertex: take the one with the
+ *     smallest id among those in which the ray advances (relative 1e-12);
+ *   - the ray origin u0 stays the Gauss point for every element it crosses.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EPS_BARY 1e-12   /* zero test on a volume coordinate */
+#define ORC_EPS_ADV 1e-12    /* relative advance required past an edge/vertex */
+
+enum {
+  ORC_OK = 0,
+  ORC_EINVAL = -1,
+  ORC_ENONMANIFOLD = -2,
+  ORC_EDEGENERATE = -3,
+  ORC_EPATH = -5,
+  ORC_ENOMEM = -10
+};
+
+typedef struct {
+  int64_t nv, nt;
+  double *xyz;      /* nv*3 */
+  int32_t *tet;     /* nt*4 */
+  int32_t *nbr;     /* nt*4: across face f (opposite local vertex f), -1 = boundary */
+  double *M;        /* nt*9: A^{-1}, row r = gradient of volume coordinate k_{r+1} */
+  double *vol;      /* nt */
+  int32_t *vt_off;  /* nv+1 */
+  int32_t *vt_tet;  /* 4*nt, ascending tet id per vertex */
+  int32_t *dof;     /* nv: interior degree of freedom or -1 */
+  int64_t ndof;
+} orc_mesh;
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature on the reference tetrahedron (Sec. 2.1 uses "Gaussian         */
+/* quadrature" without naming a rule).  Barycentric points, weights sum 1.  */
+/* ------------------------------------------------------------------------ */
+int orc_quadrature(int nq, double *bary /* nq*4 */, double *w /* nq */) {
+  if (nq == 1) {
+    for (int j = 0; j < 4; j++) bary[j] = 0.25;
+    w[0] = 1.0;
+    return ORC_OK;
+  }
+  if (nq == 4) {
+    /* degree 2: permutations of (a,b,b,b) */
+    double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0;
+    double b = (5.0 - sqrt(5.0)) / 20.0;
+    for (int q = 0; q < 4; q++) {
+      for (int j = 0; j < 4; j++) bary[q * 4 + j] = (j == q) ? a : b;
+      w[q] = 0.25;
+    }
+    return ORC_OK;
+  }
+  if (nq == 11) {
+    /* degree 4 (Keast): centroid (negative weight), a 4-point orbit of
+       (11/14, 1/14, 1/14, 1/14) and a 6-point orbit of (a, a, b, b) with
+       a,b = (1 +- sqrt(5/14))/4. */
+    int q = 0;
+    for (int j = 0; j < 4; j++) bary[j] = 0.25;
+    w[q++] = -148.0 / 1875.0;
+    for (int v = 0; v < 4; v++, q++) {
+      for (int j = 0; j < 4; j++) bary[q * 4 + j] = (j == v) ? 11.0 / 14.0 : 1.0 / 14.0;
+      w[q] = 343.0 / 7500.0;
+    }
+    double a = (1.0 + sqrt(5.0 / 14.0)) / 4.0;
+    double b = (1.0 - sqrt(5.0 / 14.0)) / 4.0;
+    static const int pairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int p = 0; p < 6; p++, q++) {
+      for (int j = 0; j < 4; j++) bary[q * 4 + j] = b;
+      bary[q * 4 + pairs[p][0]] = a;
+      bary[q * 4 + pairs[p][1]] = a;
+      w[q] = 56.0 / 375.0;
+    }
+    return ORC_OK;
+  }
+  return ORC_EINVAL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh: element adjacency ("adjacent information of the triangulation",    */
+/* Sec. 2.2), m-face incidence via vertex->element lists, and A^{-1} per    */
+/* element (Sec. 2.2: A = (e~1, e~2, e~3), e~i = v_i - v_0).                */
+/* ------------------------------------------------------------------------ */
+typedef struct { int32_t v[3]; int32_t t; int32_t f; } orc_face;
+
+static int face_cmp(const void *pa, const void *pb) {
+  const orc_face *a = (const orc_face *)pa, *b = (const orc_face *)pb;
+  for (int k = 0; k < 3; k++) {
+    if (a->v[k] != b->v[k]) return a->v[k] < b->v[k] ? -1 : 1;
+  }
+  if (a->t != b->t) return a->t < b->t ? -1 : 1;
+  return a->f - b->f;
+}
+
+static void sort3(int32_t *v) {
+  int32_t t;
+  if (v[0] > v[1]) { t = v[0]; v[0] = v[1]; v[1] = t; }
+  if (v[1] > v[2]) { t = v[1]; v[1] = v[2]; v[2] = t; }
+  if (v[0] > v[1]) { t = v[0]; v[0] = v[1]; v[1] = t; }
+}
+
+void orc_mesh_free(orc_mesh *m) {
+  if (!m) return;
+  free(m->xyz); free(m->tet); free(m->nbr); free(m->M); free(m->vol);
+  free(m->vt_off); free(m->vt_tet); free(m->dof);
+  free(m);
+}
+
+static double orc_cross_x(const double *a, const double *b) { return a[1] * b[2] - a[2] * b[1]; }
+static double orc_cross_y(const double *a, const double *b) { return a[2] * b[0] - a[0] * b[2]; }
+static double orc_cross_z(const double *a, const double *b) { return a[0] * b[1] - a[1] * b[0]; }
+
+orc_mesh *orc_mesh_create(const double *xyz, int64_t nv, const int32_t *tet, int64_t nt, int *status) {
+  *status = ORC_OK;
+  if (nv <= 0 || nt <= 0 || !xyz || !tet) { *status = ORC_EINVAL; return NULL; }
+  for (int64_t k = 0; k < 4 * nt; k++) {
+    if (tet[k] < 0 || tet[k] >= nv) { *status = ORC_EINVAL; return NULL; }
+  }
+  orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+  m->nv = nv; m->nt = nt;
+  m->xyz = (double *)malloc(sizeof(double) * 3 * nv);
+  m->tet = (int32_t *)malloc(sizeof(int32_t) * 4 * nt);
+  m->nbr = (int32_t *)malloc(sizeof(int32_t) * 4 * nt);
+  m->M = (double *)malloc(sizeof(double) * 9 * nt);
+  m->vol = (double *)malloc(sizeof(double) * nt);
+  m->vt_off = (int32_t *)calloc(nv + 1, sizeof(int32_t));
+  m->vt_tet = (int32_t *)malloc(sizeof(int32_t) * 4 * nt);
+  m->dof = (int32_t *)malloc(sizeof(int32_t) * nv);
+  memcpy(m->xyz, xyz, sizeof(double) * 3 * nv);
+  memcpy(m->tet, tet, sizeof(int32_t) * 4 * nt);
+
+  /* A^{-1} by the adjugate: rows (e2 x e3, e3 x e1, e1 x e2) / det */
+  for (int64_t t = 0; t < nt; t++) {
+    const double *v0 = xyz + 3 * (int64_t)tet[4 * t + 0];
+    double e[3][3];
+    for (int c = 1; c <= 3; c++) {
+      const double *vc = xyz + 3 * (int64_t)tet[4 * t + c];
+      for (int d = 0; d < 3; d++) e[c - 1][d] = vc[d] - v0[d];
+    }
+    double c1[3] = {orc_cross_x(e[1], e[2]), orc_cross_y(e[1], e[2]), orc_cross_z(e[1], e[2])};
+    double c2[3] = {orc_cross_x(e[2], e[0]), orc_cross_y(e[2], e[0]), orc_cross_z(e[2], e[0])};
+    double c3[3] = {orc_cross_x(e[0], e[1]), orc_cross_y(e[0], e[1]), orc_cross_z(e[0], e[1])};
+    double det = e[0][0] * c1[0] + e[0][1] * c1[1] + e[0][2] * c1[2];
+    double L = 0.0;
+    for (int c = 0; c < 3; c++) {
+      double l = sqrt(e[c][0] * e[c][0] + e[c][1] * e[c][1] + e[c][2] * e[c][2]);
+      if (l > L) L = l;
+    }
+    if (!(fabs(det) > 1e-13 * L * L * L)) { *status = ORC_EDEGENERATE; orc_mesh_free(m); return NULL; }
+    double *Mt = m->M + 9 * t;
+    for (int d = 0; d < 3; d++) {
+      Mt[0 + d] = c1[d] / det;
+      Mt[3 + d] = c2[d] / det;
+      Mt[6 + d] = c3[d] / det;
+    }
+    m->vol[t] = fabs(det) / 6.0;
+  }
+
+  /* face matching: face f of element t is opposite local vertex f */
+  orc_face *F = (orc_face *)malloc(sizeof(orc_face) * 4 * nt);
+  for (int64_t t = 0; t < nt; t++) {
+    for (int f = 0; f < 4; f++) {
+      orc_face *x = &F[4 * t + f];
+      int k = 0;
+      for (int j = 0; j < 4; j++) if (j != f) x->v[k++] = tet[4 * t + j];
+      sort3(x->v);
+      if (x->v[0] == x->v[1] || x->v[1] == x->v[2]) { free(F); *status = ORC_EDEGENERATE; orc_mesh_free(m); return NULL; }
+      x->t = (int32_t)t; x->f = f;
+      m->nbr[4 * t + f] = -1;
+    }
+  }
+  qsort(F, 4 * nt, sizeof(orc_face), face_cmp);
+  int64_t a = 0;
+  while (a < 4 * nt) {
+    int64_t b = a + 1;
+    while (b < 4 * nt && F[b].v[0] == F[a].v[0] && F[b].v[1] == F[a].v[1] && F[b].v[2] == F[a].v[2]) b++;
+    if (b - a > 2) { free(F); *status = ORC_ENONMANIFOLD; orc_mesh_free(m); return NULL; }
+    if (b - a == 2) {
+      m->nbr[4 * F[a].t + F[a].f] = F[a + 1].t;
+      m->nbr[4 * F[a + 1].t + F[a + 1].f] = F[a].t;
+    }
+    a = b;
+  }
+  free(F);
+
+  /* boundary vertices: vertices of faces without a neighbour */
+  char *bnd = (char *)calloc(nv, 1);
+  char *used = (char *)calloc(nv, 1);
+  for (int64_t t = 0; t < nt; t++) {
+    for (int j = 0; j < 4; j++) used[tet[4 * t + j]] = 1;
+    for (int f = 0; f < 4; f++) {
+      if (m->nbr[4 * t + f] < 0) {
+        for (int j = 0; j < 4; j++) if (j != f) bnd[tet[4 * t + j]] = 1;
+      }
+    }
+  }
+  m->ndof = 0;
+  for (int64_t v = 0; v < nv; v++) m->dof[v] = (used[v] && !bnd[v]) ? (int32_t)(m->ndof++) : -1;
+  free(bnd); free(used);
+
+  /* vertex -> element lists, ascending element id */
+  for (int64_t k = 0; k < 4 * nt; k++) m->vt_off[tet[k] + 1]++;
+  for (int64_t v = 0; v < nv; v++) m->vt_off[v + 1] += m->vt_off[v];
+  int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * nv);
+  for (int64_t v = 0; v < nv; v++) fill[v] = m->vt_off[v];
+  for (int64_t t = 0; t < nt; t++)
+    for (int j = 0; j < 4; j++) m->vt_tet[fill[tet[4 * t + j]]++] = (int32_t)t;
+  free(fill);
+  return m;
+}
+
+int64_t orc_mesh_ndof(const orc_mesh *m) { return m->ndof; }
+void orc_mesh_dof(const orc_mesh *m, int32_t *out) { memcpy(out, m->dof, sizeof(int32_t) * m->nv); }
+void orc_mesh_nbr(const orc_mesh *m, int32_t *out) { memcpy(out, m->nbr, sizeof(int32_t) * 4 * m->nt); }
+void orc_mesh_affine(const orc_mesh *m, double *M, double *vol) {
+  memcpy(M, m->M, sizeof(double) * 9 * m->nt);
+  memcpy(vol, m->vol, sizeof(double) * m->nt);
+}
+
+/* Gauss points x_g = sum_q beta_q v_q, summed in vertex order without FMA,
+   and weights w_g = w_q |E|; g = element * nq + q. */
+int orc_gauss_points(const orc_mesh *m, int nq, double *x /* G*3 */, double *w /* G */) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  for (int64_t t = 0; t < m->nt; t++) {
+    for (int q = 0; q < nq; q++) {
+      int64_t g = t * nq + q;
+      for (int d = 0; d < 3; d++) {
+        double s = 0.0;
+        for (int j = 0; j < 4; j++) s = s + bary[q * 4 + j] * m->xyz[3 * (int64_t)m->tet[4 * t + j] + d];
+        x[3 * g + d] = s;
+      }
+      w[g] = wq[q] * m->vol[t];
+    }
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray-simplex intersection in volume coordinates (Sec. 2.2).               */
+/* For the ray u0 + r d, d = s e_i: b~ = (A^{-1}(u0 - v0), 1 - e^T A^{-1} b)  */
+/* and d~ = (A^{-1} d, -e^T A^{-1} d); the ray is inside while              */
+/* b~ + r d~ >= 0.  Index 0 of the arrays below is the coordinate k_0 = 1 - */
+/* sum k_i (vertex v_0); index j = 1..3 is k_j (vertex v_j).               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double bt[4], dt[4];
+  double r_min, r_max;
+  double kmax[4];
+} orc_isect;
+
+static void orc_intersect(const orc_mesh *m, int64_t t, const double *u0, int i, int s, orc_isect *o) {
+  const double *Mt = m->M + 9 * t;
+  const double *v0 = m->xyz + 3 * (int64_t)m->tet[4 * t];
+  double b[3] = {u0[0] - v0[0], u0[1] - v0[1], u0[2] - v0[2]};
+  for (int r = 0; r < 3; r++) {
+    o->bt[r + 1] = (Mt[3 * r + 0] * b[0] + Mt[3 * r + 1] * b[1]) + Mt[3 * r + 2] * b[2];
+    o->dt[r + 1] = (s > 0) ? Mt[3 * r + i] : -Mt[3 * r + i];
+  }
+  o->bt[0] = 1.0 - ((o->bt[1] + o->bt[2]) + o->bt[3]);
+  o->dt[0] = -((o->dt[1] + o->dt[2]) + o->dt[3]);
+  /* eq:cond: r >= 0 and b~_j + r d~_j >= 0 for every j */
+  o->r_max = INFINITY;
+  o->r_min = 0.0;
+  for (int j = 0; j < 4; j++) {
+    if (o->dt[j] < 0.0) {
+      double r = -o->bt[j] / o->dt[j];
+      if (r < o->r_max) o->r_max = r;
+    } else if (o->dt[j] > 0.0) {
+      double r = -o->bt[j] / o->dt[j];
+      if (r > o->r_min) o->r_min = r;
+    }
+  }
+  /* equ:ac: volume coordinates of the go-out point */
+  for (int j = 0; j < 4; j++) {
+    double p = o->r_max * o->dt[j];
+    o->kmax[j] = o->bt[j] + p;
+  }
+}
+
+/* Exposed for the face-classification test: volume coordinates at the
+   go-out point and its zero pattern (bit j set <=> k_j is zero). */
+int orc_exit_pattern(const orc_mesh *m, int64_t t, const double *u0, int i, int s,
+                     double *kmax /* 4 */, double *rminmax /* 2 */) {
+  orc_isect o;
+  orc_intersect(m, t, u0, i, s, &o);
+  int z = 0;
+  for (int j = 0; j < 4; j++) {
+    kmax[j] = o.kmax[j];
+    if (fabs(o.kmax[j]) <= ORC_EPS_BARY) z |= 1 << j;
+  }
+  rminmax[0] = o.r_min;
+  rminmax[1] = o.r_max;
+  return z;
+}
+
+/* The path of one half-ray (Sec. 2.2): start in the Gauss point's own
+   element; in each element take the go-out point r_max and its zero pattern
+   Z.  |Z| = 1: go-out point on a face -> the (at most one) element across it,
+   none = boundary reached.  |Z| >= 2: an edge or vertex; search the elements
+   that contain that m-face and continue in the one (smallest id) in which
+   the ray advances; none = boundary reached.
+   Emits (element, r_max) for every element in which the ray advances. */
+int orc_walk(const orc_mesh *m, int64_t t0, const double *u0, int i, int s, int cap,
+             int32_t *tets, double *r_end, int *n_out) {
+  int64_t t = t0;
+  double r_cur = 0.0;
+  int n = 0;
+  for (int step = 0; step < cap + 64; step++) {
+    orc_isect o;
+    orc_intersect(m, t, u0, i, s, &o);
+    if (!(o.r_max < INFINITY)) return ORC_EPATH;
+    if (o.r_max > r_cur) {
+      if (n >= cap) return ORC_EPATH;
+      tets[n] = (int32_t)t;
+      r_end[n] = o.r_max;
+      n++;
+      r_cur = o.r_max;
+    }
+    int Z[4], nz = 0;
+    for (int j = 0; j < 4; j++) if (fabs(o.kmax[j]) <= ORC_EPS_BARY) Z[nz++] = j;
+    if (nz == 0) return ORC_EPATH;
+    if (nz == 1) {
+      int32_t nx = m->nbr[4 * t + Z[0]];
+      if (nx < 0) { *n_out = n; return ORC_OK; }
+      t = nx;
+      continue;
+    }
+    /* edge (|Z| = 2) or vertex (|Z| = 3): the m-face spanned by the
+       vertices whose volume coordinate is not zero (Fig. 2) */
+    int32_t keep[4];
+    int nk = 0;
+    for (int j = 0; j < 4; j++) {
+      int in_z = 0;
+      for (int k = 0; k < nz; k++) if (Z[k] == j) in_z = 1;
+      if (!in_z) keep[nk++] = m->tet[4 * t + j];
+    }
+    if (nk == 0) return ORC_EPATH;
+    int64_t best = -1;
+    for (int32_t p = m->vt_off[keep[0]]; p < m->vt_off[keep[0] + 1]; p++) {
+      int64_t c = m->vt_tet[p];
+      if (c == t) continue;
+      int has_all = 1;
+      for (int k = 1; k < nk; k++) {
+        int found = 0;
+        for (int j = 0; j < 4; j++) if (m->tet[4 * c + j] == keep[k]) found = 1;
+        if (!found) has_all = 0;
+      }
+      if (!has_all) continue;
+      orc_isect oc;
+      orc_intersect(m, c, u0, i, s, &oc);
+      if (oc.r_max - r_cur > ORC_EPS_ADV * r_cur) { best = c; break; }
+    }
+    if (best < 0) { *n_out = n; return ORC_OK; }
+    t = best;
+  }
+  return ORC_EPATH;
+}
+
+/* FNV-1a (64 bit) over the element ids of a path, 4 little-endian bytes each */
+static uint64_t orc_fnv1a(const int32_t *ids, int n) {
+  uint64_t h = 14695981039346656037ULL;
+  for (int k = 0; k < n; k++) {
+    uint32_t u = (uint32_t)ids[k];
+    for (int b = 0; b < 4; b++) {
+      h ^= (uint64_t)((u >> (8 * b)) & 0xffu);
+      h *= 1099511628211ULL;
+    }
+  }
+  return h;
+}
+
+/* Half-ray h = g*6 + 2*i + side (side 0: -e_i, side 1: +e_i). */
+static void orc_ray_origin(const orc_mesh *m, int nq, const double *bary, int64_t g, double *u0) {
+  int64_t t = g / nq;
+  int q = (int)(g % nq);
+  for (int d = 0; d < 3; d++) {
+    double s = 0.0;
+    for (int j = 0; j < 4; j++) s = s + bary[q * 4 + j] * m->xyz[3 * (int64_t)m->tet[4 * t + j] + d];
+    u0[d] = s;
+  }
+}
+
+int orc_paths(const orc_mesh *m, int nq, int64_t h0, int64_t count, int cap,
+              int32_t *len, uint64_t *hash, int32_t *ids /* count*cap or NULL */,
+              double *rend /* count*cap or NULL */) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int st = ORC_OK;
+  for (int64_t k = 0; k < count; k++) {
+    int64_t h = h0 + k;
+    int64_t g = h / 6;
+    int dir = (int)(h % 6), i = dir / 2, s = (dir & 1) ? 1 : -1;
+    double u0[3];
+    orc_ray_origin(m, nq, bary, g, u0);
+    int n = 0;
+    st = orc_walk(m, g / nq, u0, i, s, cap, tb, rb, &n);
+    if (st != ORC_OK) break;
+    len[k] = n;
+    hash[k] = orc_fnv1a(tb, n);
+    if (ids) for (int j = 0; j < n; j++) ids[k * cap + j] = tb[j];
+    if (rend) for (int j = 0; j < n; j++) rend[k * cap + j] = rb[j];
+  }
+  free(tb); free(rb);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closed-form RL derivative of the P1 basis functions along a path.        */
+/* On segment s_k = [r_{k-1}, r_k] (distances from the Gauss point x along   */
+/* the ray) the basis function psi_l has the constant slope                  */
+/* sigma_{k,l} = d psi_l / d x_i on E_k.  From eq. def with m = 1 and         */
+/* integration by parts, each segment contributes                            */
+/*   left  (ray -e_i):  +sigma (r_k^{1-g} - r_{k-1}^{1-g}) / Gamma(2-g)       */
+/*   right (ray +e_i):  -sigma (r_k^{1-g} - r_{k-1}^{1-g}) / Gamma(2-g)       */
+/* with 0^{1-g} = 0 at the Gauss point itself, plus for a basis function    */
+/* that is non-zero at the path end p_a (p_b) the boundary term             */
+/*   psi_l(p_end) * r_end^{-g} / Gamma(1-g)                                  */
+/* (zero for every interior node, kept for the all-nodes check).            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double *acc;     /* nv, zero outside calls */
+  int32_t *touched; int nt_; char *mark;
+} orc_work;
+
+static orc_work *orc_work_new(int64_t nv) {
+  orc_work *w = (orc_work *)malloc(sizeof(orc_work));
+  w->acc = (double *)calloc(nv, sizeof(double));
+  w->mark = (char *)calloc(nv, 1);
+  w->touched = (int32_t *)malloc(sizeof(int32_t) * nv);
+  w->nt_ = 0;
+  return w;
+}
+static void orc_work_free(orc_work *w) { free(w->acc); free(w->mark); free(w->touched); free(w); }
+
+static void orc_touch(orc_work *w, int32_t v, double val) {
+  if (!w->mark[v]) { w->mark[v] = 1; w->touched[w->nt_++] = v; }
+  w->acc[v] += val;
+}
+
+static int icmp32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* slope of the volume coordinate of local vertex j along e_i on element t */
+static double orc_slope(const orc_mesh *m, int64_t t, int j, int i) {
+  const double *Mt = m->M + 9 * t;
+  if (j > 0) return Mt[3 * (j - 1) + i];
+  return -((Mt[0 + i] + Mt[3 + i]) + Mt[6 + i]);
+}
+
+typedef struct {
+  double gamma;
+  double inv_g2;   /* 1/Gamma(2-gamma) */
+  double inv_g1;   /* 1/Gamma(1-gamma) (0 at gamma = 1) */
+  double half_psi0;/* psi(2-gamma)/2, for the alpha-derivative */
+} orc_order;
+
+static double orc_pow_seg(double r, double e) { return (r > 0.0) ? pow(r, e) : 0.0; }
+static double orc_lnpow(double r, double e) { return (r > 0.0) ? log(r) * pow(r, e) : 0.0; }
+
+/* Sparse vector of D^gamma psi_l (x) over nodes for one half-ray.
+   mode 0: interior dofs, value; mode 1: all nodes incl. boundary term;
+   mode 2: interior dofs, derivative of the value with respect to alpha
+   (gamma = alpha/2).  Output: node ids (vertex ids for mode 1, dofs else),
+   ascending, and values.  Returns count or a negative status. */
+static int orc_ray_vector(const orc_mesh *m, int nq, const double *bary, int64_t g, int i, int side,
+                          const orc_order *ord, int mode, int cap, orc_work *w,
+                          int32_t *out_id, double *out_val, int32_t *tb, double *rb) {
+  double u0[3];
+  orc_ray_origin(m, nq, bary, g, u0);
+  int s = side ? 1 : -1;
+  int n = 0;
+  int st = orc_walk(m, g / nq, u0, i, s, cap, tb, rb, &n);
+  if (st != ORC_OK) return st;
+  double e = 1.0 - ord->gamma;
+  double sgn = side ? -1.0 : 1.0;
+  double r_lo = 0.0;
+  for (int k = 0; k < n; k++) {
+    int64_t t = tb[k];
+    double r_hi = rb[k];
+    double dP;
+    if (mode == 2) {
+      /* d/dalpha of r^{1-g}/Gamma(2-g): -(1/2) ln r r^{1-g} G + (psi0/2) r^{1-g} G */
+      double P = orc_pow_seg(r_hi, e) - orc_pow_seg(r_lo, e);
+      double Q = orc_lnpow(r_hi, e) - orc_lnpow(r_lo, e);
+      dP = ord->inv_g2 * (ord->half_psi0 * P - 0.5 * Q);
+    } else {
+      dP = ord->inv_g2 * (orc_pow_seg(r_hi, e) - orc_pow_seg(r_lo, e));
+    }
+    for (int j = 0; j < 4; j++) {
+      int32_t v = m->tet[4 * t + j];
+      if (mode != 1 && m->dof[v] < 0) continue;
+      double sigma = orc_slope(m, t, j, i);
+      orc_touch(w, v, sgn * sigma * dP);
+    }
+    r_lo = r_hi;
+  }
+  if (mode == 1 && n > 0) {
+    /* boundary term at the path end: psi_l(p_end) (r_end)^{-gamma}/Gamma(1-gamma) */
+    orc_isect o;
+    int64_t t = tb[n - 1];
+    orc_intersect(m, t, u0, i, s, &o);
+    double rend = rb[n - 1];
+    double c = ord->inv_g1 * pow(rend, -ord->gamma);
+    for (int j = 0; j < 4; j++) {
+      double lam = o.kmax[j];
+      if (lam != 0.0) orc_touch(w, m->tet[4 * t + j], lam * c);
+    }
+  }
+  int cnt = w->nt_;
+  qsort(w->touched, cnt, sizeof(int32_t), icmp32);
+  for (int k = 0; k < cnt; k++) {
+    int32_t v = w->touched[k];
+    out_id[k] = (mode == 1) ? v : m->dof[v];
+    out_val[k] = w->acc[v];
+    w->acc[v] = 0.0;
+    w->mark[v] = 0;
+  }
+  w->nt_ = 0;
+  return cnt;
+}
+
+static void orc_fill_order(orc_order *o, double gamma, double inv_g2, double inv_g1, double half_psi0) {
+  o->gamma = gamma; o->inv_g2 = inv_g2; o->inv_g1 = inv_g1; o->half_psi0 = half_psi0;
+}
+
+/* One half-ray's vector for the tests (mode as in orc_ray_vector). */
+int orc_ray_values(const orc_mesh *m, int nq, int64_t g, int i, int side, double gamma,
+                   double inv_g2, double inv_g1, double half_psi0, int mode, int cap,
+                   int32_t *out_id, double *out_val) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  orc_order ord;
+  orc_fill_order(&ord, gamma, inv_g2, inv_g1, half_psi0);
+  orc_work *w = orc_work_new(m->nv);
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int r = orc_ray_vector(m, nq, bary, g, i, side, &ord, mode, cap, w, out_id, out_val, tb, rb);
+  free(tb); free(rb); orc_work_free(w);
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense assembly (Sec. 2.1):                                              */
+/*   K_jk = sum_i K_i c_alpha sum_g w_g [L_gi(k) R_gi(j) + R_gi(k) L_gi(j)]  */
+/* with L = D_L^gamma psi, R = D_R^gamma psi at the Gauss point and          */
+/* c_alpha = 1/(2 cos(pi alpha/2)).  Both products are written out as        */
+/* separate (j,k) loops.  A is ndof x ndof row-major, zeroed by the caller.  */
+/* ------------------------------------------------------------------------ */
+int orc_assemble(const orc_mesh *m, int nq, double gamma, double inv_g2, double c_alpha,
+                 const double *Kc, int cap, double *A) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  orc_order ord;
+  orc_fill_order(&ord, gamma, inv_g2, 0.0, 0.0);
+  orc_work *w = orc_work_new(m->nv);
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int32_t *Li = (int32_t *)malloc(sizeof(int32_t) * 4 * cap), *Ri = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+  double *Lv = (double *)malloc(sizeof(double) * 4 * cap), *Rv = (double *)malloc(sizeof(double) * 4 * cap);
+  int64_t n = m->ndof;
+  int st = ORC_OK;
+  for (int64_t g = 0; g < m->nt * nq && st == ORC_OK; g++) {
+    double wg = wq[g % nq] * m->vol[g / nq];
+    for (int i = 0; i < 3; i++) {
+      int nl = orc_ray_vector(m, nq, bary, g, i, 0, &ord, 0, cap, w, Li, Lv, tb, rb);
+      if (nl < 0) { st = nl; break; }
+      int nr = orc_ray_vector(m, nq, bary, g, i, 1, &ord, 0, cap, w, Ri, Rv, tb, rb);
+      if (nr < 0) { st = nr; break; }
+      double W = wg * Kc[i] * c_alpha;
+      for (int a = 0; a < nr; a++)
+        for (int b = 0; b < nl; b++) A[Ri[a] * n + Li[b]] += W * (Rv[a] * Lv[b]);
+      for (int a = 0; a < nl; a++)
+        for (int b = 0; b < nr; b++) A[Li[a] * n + Ri[b]] += W * (Lv[a] * Rv[b]);
+    }
+  }
+  free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);
+  return st;
+}
+
+/* Matrix-free product y = K x (same sums as orc_assemble, never forming K). */
+int orc_apply(const orc_mesh *m, int nq, double gamma, double inv_g2, double c_alpha,
+              const double *Kc, int cap, const double *x, double *y) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  orc_order ord;
+  orc_fill_order(&ord, gamma, inv_g2, 0.0, 0.0);
+  orc_work *w = orc_work_new(m->nv);
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int32_t *Li = (int32_t *)malloc(sizeof(int32_t) * 4 * cap), *Ri = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+  double *Lv = (double *)malloc(sizeof(double) * 4 * cap), *Rv = (double *)malloc(sizeof(double) * 4 * cap);
+  for (int64_t j = 0; j < m->ndof; j++) y[j] = 0.0;
+  int st = ORC_OK;
+  for (int64_t g = 0; g < m->nt * nq && st == ORC_OK; g++) {
+    double wg = wq[g % nq] * m->vol[g / nq];
+    for (int i = 0; i < 3; i++) {
+      int nl = orc_ray_vector(m, nq, bary, g, i, 0, &ord, 0, cap, w, Li, Lv, tb, rb);
+      if (nl < 0) { st = nl; break; }
+      int nr = orc_ray_vector(m, nq, bary, g, i, 1, &ord, 0, cap, w, Ri, Rv, tb, rb);
+      if (nr < 0) { st = nr; break; }
+      double W = wg * Kc[i] * c_alpha;
+      double lx = 0.0, rx = 0.0;
+      for (int b = 0; b < nl; b++) lx += Lv[b] * x[Li[b]];
+      for (int b = 0; b < nr; b++) rx += Rv[b] * x[Ri[b]];
+      for (int a = 0; a < nr; a++) y[Ri[a]] += W * (Rv[a] * lx);
+      for (int a = 0; a < nl; a++) y[Li[a]] += W * (Lv[a] * rx);
+    }
+  }
+  free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);
+  return st;
+}
+
+/* Sums for the adjoint (lambda = K^{-1} dJ/du, K symmetric):
+     S_i = sum_g w_g [(lam.R)(L.u) + (lam.L)(R.u)]
+     T_i = sum_g w_g [(lam.R')(L.u) + (lam.R)(L'.u) + (lam.L')(R.u) + (lam.L)(R'.u)]
+   with ' = d/dalpha.  Then dJ/dK_i = -c_alpha S_i and
+   dJ/dalpha = -sum_i K_i (c'_alpha S_i + c_alpha T_i). */
+int orc_adjoint_sums(const orc_mesh *m, int nq, double gamma, double inv_g2, double half_psi0,
+                     int cap, const double *u, const double *lam, double *S /* 3 */, double *T /* 3 */) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  orc_order ord;
+  orc_fill_order(&ord, gamma, inv_g2, 0.0, half_psi0);
+  orc_work *w = orc_work_new(m->nv);
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int32_t *id = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+  double *v = (double *)malloc(sizeof(double) * 4 * cap);
+  int st = ORC_OK;
+  for (int i = 0; i < 3; i++) { S[i] = 0.0; T[i] = 0.0; }
+  for (int64_t g = 0; g < m->nt * nq && st == ORC_OK; g++) {
+    double wg = wq[g % nq] * m->vol[g / nq];
+    for (int i = 0; i < 3; i++) {
+      double d[2][2][2]; /* [side][value|alpha-derivative][dot with u | lam] */
+      for (int side = 0; side < 2 && st == ORC_OK; side++) {
+        for (int mode = 0; mode < 2; mode++) {
+          int nn = orc_ray_vector(m, nq, bary, g, i, side, &ord, mode ? 2 : 0, cap, w, id, v, tb, rb);
+          if (nn < 0) { st = nn; break; }
+          double du = 0.0, dl = 0.0;
+          for (int k = 0; k < nn; k++) { du += v[k] * u[id[k]]; dl += v[k] * lam[id[k]]; }
+          d[side][mode][0] = du;
+          d[side][mode][1] = dl;
+        }
+      }
+      if (st != ORC_OK) break;
+      /* side 0 = L, side 1 = R; mode 0 = value, 1 = d/dalpha */
+      double lamR = d[1][0][1], Lu = d[0][0][0], lamL = d[0][0][1], Ru = d[1][0][0];
+      double lamRp = d[1][1][1], Lpu = d[0][1][0], lamLp = d[0][1][1], Rpu = d[1][1][0];
+      S[i] += wg * (lamR * Lu + lamL * Ru);
+      T[i] += wg * (lamRp * Lu + lamR * Lpu + lamLp * Ru + lamL * Rpu);
+    }
+  }
+  free(tb); free(rb); free(id); free(v); orc_work_free(w);
+  return st;
+}
+
+/* Load vector b_j = sum_g w_g f(x_g) psi_j(x_g); f_gauss may be NULL (f = 1). */
+int orc_load(const orc_mesh *m, int nq, const double *f_gauss, double *b) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  for (int64_t j = 0; j < m->ndof; j++) b[j] = 0.0;
+  for (int64_t t = 0; t < m->nt; t++) {
+    for (int q = 0; q < nq; q++) {
+      int64_t g = t * nq + q;
+      double f = f_gauss ? f_gauss[g] : 1.0;
+      double wg = wq[q] * m->vol[t];
+      for (int j = 0; j < 4; j++) {
+        int32_t d = m->dof[m->tet[4 * t + j]];
+        if (d >= 0) b[d] += wg * f * bary[q * 4 + j];
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exhaustive line/element intersection, the method the path search          */
+/* replaces (Sec. 2.2): every element is clipped against its four face       */
+/* planes (outward normals from vertex cross products, no A^{-1}).            */
+/* lo/hi receive the parameter interval along u0 + r d (r unrestricted), or */
+/* lo > hi when the line misses the element.                                 */
+/* ------------------------------------------------------------------------ */
+void orc_exhaustive(const orc_mesh *m, const double *u0, const double *d, double *lo, double *hi) {
+  static const int fv[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+  for (int64_t t = 0; t < m->nt; t++) {
+    double a = -INFINITY, b = INFINITY;
+    for (int f = 0; f < 4; f++) {
+      const double *p0 = m->xyz + 3 * (int64_t)m->tet[4 * t + fv[f][0]];
+      const double *p1 = m->xyz + 3 * (int64_t)m->tet[4 * t + fv[f][1]];
+      const double *p2 = m->xyz + 3 * (int64_t)m->tet[4 * t + fv[f][2]];
+      const double *po = m->xyz + 3 * (int64_t)m->tet[4 * t + f];
+      double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+      double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+      double nrm[3] = {orc_cross_x(e1, e2), orc_cross_y(e1, e2), orc_cross_z(e1, e2)};
+      double side = nrm[0] * (po[0] - p0[0]) + nrm[1] * (po[1] - p0[1]) + nrm[2] * (po[2] - p0[2]);
+      if (side > 0) { nrm[0] = -nrm[0]; nrm[1] = -nrm[1]; nrm[2] = -nrm[2]; }
+      /* inside: nrm.(u0 + r d - p0) <= 0 */
+      double c0 = nrm[0] * (u0[0] - p0[0]) + nrm[1] * (u0[1] - p0[1]) + nrm[2] * (u0[2] - p0[2]);
+      double c1 = nrm[0] * d[0] + nrm[1] * d[1] + nrm[2] * d[2];
+      if (c1 == 0.0) {
+        if (c0 > 0.0) { a = 1.0; b = 0.0; }
+      } else if (c1 > 0.0) {
+        double r = -c0 / c1;
+        if (r < b) b = r;
+      } else {
+        double r = -c0 / c1;
+        if (r > a) a = r;
+      }
+    }
+    lo[t] = a;
+    hi[t] = b;
+  }
+}
+
+/* The walk from an arbitrary point u0 inside element t0 (test helper). */
+int orc_walk_from(const orc_mesh *m, int64_t t0, const double *u0, int i, int s, int cap,
+                  int32_t *tets, double *r_end, int *n_out) {
+  return orc_walk(m, t0, u0, i, s, cap, tets, r_end, n_out);
+}
