@@ -1,0 +1,211 @@
+/*
+ * fpde.h - C ABI of the MI355X (gfx950) library for the P1 finite-element
+ * discretisation of steady Riesz fractional diffusion on convex tetrahedral
+ * meshes (Yang, Nie, Yuan & Wang, "Finite Element Methods for Fractional
+ * PDEs in Three Dimensions").
+ *
+ * Problem: -sum_i K_i d^alpha u / d|x_i|^alpha = f in a convex polyhedron,
+ * u = 0 outside (Sec. 1 eq. (1) for the chord bounds a_i(x), b_i(x); Sec. 3
+ * for the zero extension), 1 < alpha <= 2.  The Riesz operator is
+ * -(D_L^alpha + D_R^alpha) / (2 cos(pi alpha / 2)) and its weak form is
+ * split into order-gamma = alpha/2 left/right Riemann-Liouville derivatives
+ * (Sec. 1 eq. def, form 1 of eq. equ:varsss with alpha = beta):
+ *
+ *   K_jk = c_alpha sum_i K_i sum_g w_g [L_gi(k) R_gi(j) + R_gi(k) L_gi(j)],
+ *   c_alpha = 1 / (2 cos(pi alpha / 2)),
+ *
+ * with L_gi(l) = D_L^gamma psi_l(x_g), R_gi(l) = D_R^gamma psi_l(x_g) along
+ * e_i at Gauss point x_g with weight w_g (Sec. 2.1, element quadrature of
+ * (K_E)_kl).  Each derivative is summed over the segments of the Gauss
+ * point's integration path (Sec. 2.1) found by the ray-simplex walk of
+ * Sec. 2.2.  Unknowns are the interior nodes (not on a boundary face),
+ * numbered by increasing vertex id.
+ *
+ * Conventions for every call:
+ *   - Return value: FPDE_OK (0) or a negative fpde_status; outputs are
+ *     unspecified after an error.  No C++ exception crosses the ABI.
+ *   - "dev" pointers are device memory on the mesh's device, owned by the
+ *     caller; "host" pointers are host memory owned by the caller.  The
+ *     library owns only the mesh handle, its device copy of the mesh and its
+ *     scratch buffers (freed by fpde_mesh_destroy).
+ *   - stream: a hipStream_t (NULL = legacy default stream).  Kernels are
+ *     enqueued on it; calls that must report a device-side status or a size
+ *     synchronise it once before returning (stated per call).
+ *   - Matrices are dense, row-major with leading dimension lda >= n_dof.
+ *     The stiffness matrix is symmetric, so row/column order is immaterial.
+ *   - One handle must not be used by two host threads at once.
+ */
+#ifndef FPDE_H
+#define FPDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fpde_mesh fpde_mesh; /* opaque, library-owned */
+
+typedef enum {
+  FPDE_OK = 0,
+  FPDE_EINVAL = -1,            /* bad argument (null pointer, size, lda, rule) */
+  FPDE_EMESH_NONMANIFOLD = -2, /* a face shared by more than two elements */
+  FPDE_EMESH_DEGENERATE = -3,  /* zero-volume element or repeated vertex */
+  FPDE_EPATH = -5,             /* a walk found no continuation or exceeded max_steps */
+  FPDE_EALPHA = -6,            /* alpha outside (1, 2] or K_i <= 0 */
+  FPDE_ENOTSPD = -7,           /* Cholesky met a pivot <= 0 */
+  FPDE_ENOCONV = -8,           /* iterative refinement missed its tolerance */
+  FPDE_EHIP = -9,              /* a HIP runtime call failed */
+  FPDE_ENOMEM = -10,           /* device allocation failed */
+  FPDE_EUNSUPPORTED = -11      /* valid but not implemented combination */
+} fpde_status;
+
+enum { FPDE_FP64 = 0, FPDE_MIXED = 1 };
+enum { FPDE_SRC_ONE = 0, FPDE_SRC_USER = 1, FPDE_SRC_CUBE_MMS = 2 };
+
+typedef struct {
+  double alpha;     /* Riesz order, 1 < alpha <= 2 */
+  double K[3];      /* diffusion coefficients K_1..K_3 > 0 */
+  int quad_points;  /* element rule: 4 (degree 2) or 11 (degree 4) points */
+  int precision;    /* FPDE_FP64 or FPDE_MIXED */
+  int source;       /* FPDE_SRC_ONE (f = 1), FPDE_SRC_USER (f given at the
+                       Gauss points), FPDE_SRC_CUBE_MMS (manufactured source
+                       of u = prod x_i^2 (1 - x_i)^2 on the unit cube) */
+  int max_steps;    /* cap on elements per half-ray, 0 = 4096 */
+  double ir_tol;    /* FPDE_MIXED: stop at ||b - K u|| / ||b|| <= ir_tol, 0 = 1e-8 */
+  int ir_max_iter;  /* FPDE_MIXED: refinement sweeps, 0 = 30 */
+} fpde_params;
+
+typedef struct {
+  int ir_iters;              /* refinement sweeps done (0 for FPDE_FP64) */
+  double final_rel_residual; /* ||b - K u||_2 / ||b||_2 in FP64 */
+  int64_t failed_pivot;      /* column of the first pivot <= 0, or -1 */
+} fpde_solve_info;
+
+/* Status text (static storage). */
+const char *fpde_status_string(int status);
+
+/*
+ * Mesh set-up (Sec. 2.1 partition T_h; Sec. 2.2 "adjacent information of the
+ * triangulation" and the m-face incidence used at edge/vertex go-out points).
+ *   xyz:  host, n_vert x 3 FP64 vertex coordinates.
+ *   tet:  host, n_tet x 4 int32 vertex ids in [0, n_vert), any orientation.
+ * Copies both to the current HIP device, then builds on the device: per
+ * element A^{-1} (A = (v1-v0, v2-v0, v3-v0)) and |E|, the neighbour across
+ * each face (face f opposite local vertex f), boundary faces and nodes, the
+ * interior numbering and vertex -> element lists.  Synchronises `stream`.
+ * Errors: FPDE_EINVAL (sizes, ids out of range), FPDE_EMESH_NONMANIFOLD,
+ * FPDE_EMESH_DEGENERATE, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tet, int64_t n_tet,
+                     void *stream, fpde_mesh **out);
+void fpde_mesh_destroy(fpde_mesh *m);
+
+/* Sizes: interior unknowns, boundary faces, elements (any pointer may be NULL). */
+int fpde_mesh_info(const fpde_mesh *m, int64_t *n_dof, int64_t *n_boundary_faces, int64_t *n_tet);
+
+/* host, n_vert int32: unknown index of each vertex, -1 on the boundary. */
+int fpde_dof_map(const fpde_mesh *m, int32_t *dof);
+
+/*
+ * Symbolic phase ("template", Sec. 2.3): walks every half-ray of the
+ * quad_points rule once, records how many entries each derivative vector has
+ * and builds the node -> entry transpose used by the accumulation.  Depends
+ * on the mesh and rule only, so it is reused for every alpha and K.  Called
+ * implicitly by fpde_assemble when missing; synchronises `stream`.
+ * Errors: FPDE_EINVAL (rule), FPDE_EPATH, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_plan(fpde_mesh *m, int quad_points, int max_steps, void *stream);
+
+/*
+ * Integration paths (Sec. 2.2) of the half-rays (g, dir) for Gauss points
+ * g in [g0, g0 + count) of the quad_points rule, dir = 2 i + side
+ * (i = axis 0..2, side 0: -e_i, side 1: +e_i).  Gauss point g lies in element
+ * g / quad_points.
+ *   len:  dev, count int32: elements on the path.
+ *   hash: dev, count uint64: FNV-1a 64 over the element ids (4 little-endian
+ *         bytes each, in path order).
+ *   ids:  dev or NULL, count x max_steps int32: the element ids.
+ *   rend: dev or NULL, count x max_steps FP64: distance from x_g at which the
+ *         path leaves each element.
+ * Synchronises `stream`.  Errors: FPDE_EINVAL, FPDE_EPATH.
+ */
+int fpde_paths(fpde_mesh *m, int quad_points, int dir, int64_t g0, int64_t count, int max_steps,
+               int32_t *len, uint64_t *hash, int32_t *ids, double *rend, void *stream);
+
+/*
+ * Derivative vectors of one direction: for Gauss points g in [g0, g0+count)
+ * and dir = 2 i + side, the sparse vector D^gamma psi_l(x_g) (left for
+ * side 0, right for side 1) over interior nodes l, gamma = alpha / 2.
+ *   off:  host, count + 1 int64 (written): entries of ray k are
+ *         [off[k], off[k+1]) of dof/val.
+ *   dof:  host, capacity int32; val: host, capacity FP64.  A node may appear
+ *         more than once in one ray (the values then add up).
+ * Requires fpde_plan for the rule.  Synchronises `stream`.
+ * Errors: FPDE_EINVAL (capacity too small: off[count] is still written),
+ * FPDE_EALPHA, FPDE_EPATH.
+ */
+int fpde_ray_values(fpde_mesh *m, int quad_points, double alpha, int dir, int64_t g0, int64_t count,
+                    int64_t *off, int32_t *dof, double *val, int64_t capacity, void *stream);
+
+/*
+ * Assembly (Sec. 2.1-2.3): the stiffness matrix and load vector.
+ *   A: dev, n_dof x lda, FP64 (precision FPDE_FP64) or FP32 (FPDE_MIXED);
+ *      every entry of the leading n_dof x n_dof block is written.
+ *   b: dev, n_dof FP64, b_j = sum_g w_g f(x_g) psi_j(x_g); may be NULL.
+ *   f_gauss: dev, n_tet * quad_points FP64 source values at the Gauss points
+ *      (index element * quad_points + q) for FPDE_SRC_USER, else ignored.
+ * Synchronises `stream` (walk status).
+ * Errors: FPDE_EINVAL, FPDE_EALPHA, FPDE_EPATH, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_t lda, double *b,
+                  const double *f_gauss, void *stream);
+
+/*
+ * Matrix-free product y = K x in FP64 (the sums of fpde_assemble, never
+ * forming K): the residual of the refinement in FPDE_MIXED.
+ *   x, y: dev, n_dof FP64.  Synchronises `stream`.
+ */
+int fpde_apply(fpde_mesh *m, const fpde_params *p, const double *x, double *y, void *stream);
+
+/*
+ * Dense solve of K u = b (the "Solve linear equations" stage, Table 4).
+ *   FPDE_FP64:  A (FP64, from fpde_assemble) is overwritten by its Cholesky
+ *               factor L (lower triangle, K = L L^T); u = L^{-T} L^{-1} b.
+ *   FPDE_MIXED: A (FP32) is overwritten by its FP32 Cholesky factor; u is
+ *               refined with FP64 residuals b - K u from fpde_apply until
+ *               ||r|| / ||b|| <= ir_tol.
+ *   b, u: dev, n_dof FP64 (may alias).  info: host, may be NULL.
+ * Synchronises `stream`.
+ * Errors: FPDE_EINVAL, FPDE_ENOTSPD, FPDE_ENOCONV, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_solve(fpde_mesh *m, const fpde_params *p, void *A, int64_t lda, const double *b, double *u,
+               fpde_solve_info *info, void *stream);
+
+/*
+ * Solve with an existing factor (from fpde_solve): u = K^{-1} b with the same
+ * precision handling (FPDE_MIXED refines against fpde_apply).  Used for the
+ * adjoint solve K lam = dJ/du (K is symmetric).
+ */
+int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const void *L, int64_t lda,
+                        const double *b, double *u, fpde_solve_info *info, void *stream);
+
+/*
+ * Adjoint sums for the gradient of a loss J(u) through assembly and solve
+ * (u = K^{-1} b, b independent of alpha and K): with lam = K^{-1} dJ/du,
+ *   dJ/dK_i   = -c_alpha S_i
+ *   dJ/dalpha = -sum_i K_i (c'_alpha S_i + c_alpha T_i)
+ *   S_i = sum_g w_g [(lam.R)(L.u) + (lam.L)(R.u)]
+ *   T_i = sum_g w_g [(lam.R')(L.u) + (lam.R)(L'.u) + (lam.L')(R.u) + (lam.L)(R'.u)]
+ * (' = d/dalpha).  The paths are walked again (recomputed, not stored).
+ *   u, lam: dev, n_dof FP64.  grad_alpha, grad_K: host (1 and 3 FP64).
+ * Synchronises `stream`.  Errors: FPDE_EINVAL, FPDE_EALPHA, FPDE_EPATH.
+ */
+int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const double *lam,
+                 double *grad_alpha, double *grad_K, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPDE_H */

@@ -1,0 +1,244 @@
+"""MI355X (gfx950) library for the 3-D P1 finite-element discretisation of
+steady Riesz fractional diffusion (Yang, Nie, Yuan & Wang, "Finite Element
+Methods for Fractional PDEs in Three Dimensions").
+
+Thin ctypes binding of ``libfpde.so`` (C ABI declared in ``include/fpde.h``):
+argument marshalling only.  Every step (mesh set-up, path walk, closed-form
+derivatives, accumulation, load vector, Cholesky, refinement, adjoint) runs in
+the library's HIP kernels; PyTorch supplies device memory and the stream.
+If the library is missing, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libfpde.so"
+
+FPDE_OK = 0
+FPDE_FP64, FPDE_MIXED = 0, 1
+FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS = 0, 1, 2
+
+STATUS = {
+    0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EMESH_NONMANIFOLD", -3: "FPDE_EMESH_DEGENERATE",
+    -5: "FPDE_EPATH", -6: "FPDE_EALPHA", -7: "FPDE_ENOTSPD", -8: "FPDE_ENOCONV", -9: "FPDE_EHIP",
+    -10: "FPDE_ENOMEM", -11: "FPDE_EUNSUPPORTED",
+}
+
+EXPORTS = [
+    "fpde_status_string", "fpde_mesh_create", "fpde_mesh_destroy", "fpde_mesh_info", "fpde_dof_map",
+    "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
+    "fpde_solve_factored", "fpde_adjoint",
+]
+
+
+class FpdeError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        name = STATUS.get(status, str(status))
+        text = ""
+        try:
+            text = _lib().fpde_status_string(status).decode()
+        except Exception:  # noqa: BLE001 - message only
+            pass
+        super().__init__(f"{what}: {name} ({text})")
+        self.status = status
+
+
+class fpde_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("K", ctypes.c_double * 3), ("quad_points", ctypes.c_int),
+                ("precision", ctypes.c_int), ("source", ctypes.c_int), ("max_steps", ctypes.c_int),
+                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int)]
+
+
+class fpde_solve_info(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int), ("final_rel_residual", ctypes.c_double),
+                ("failed_pivot", ctypes.c_int64)]
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is not None:
+        return _L
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_1811_03339_amd.build")
+    L = ctypes.CDLL(str(LIB_PATH))
+    P, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.fpde_status_string.restype = ctypes.c_char_p
+    L.fpde_status_string.argtypes = [i32]
+    L.fpde_mesh_create.argtypes = [P, i64, P, i64, P, ctypes.POINTER(P)]
+    L.fpde_mesh_destroy.argtypes = [P]
+    L.fpde_mesh_destroy.restype = None
+    L.fpde_mesh_info.argtypes = [P, P, P, P]
+    L.fpde_dof_map.argtypes = [P, P]
+    L.fpde_plan.argtypes = [P, i32, i32, P]
+    L.fpde_paths.argtypes = [P, i32, i32, i64, i64, i32, P, P, P, P, P]
+    L.fpde_ray_values.argtypes = [P, i32, dbl, i32, i64, i64, P, P, P, i64, P]
+    L.fpde_assemble.argtypes = [P, P, P, i64, P, P, P]
+    L.fpde_apply.argtypes = [P, P, P, P, P]
+    L.fpde_solve.argtypes = [P, P, P, i64, P, P, P, P]
+    L.fpde_solve_factored.argtypes = [P, P, P, i64, P, P, P, P]
+    L.fpde_adjoint.argtypes = [P, P, P, P, P, P, P]
+    for name in EXPORTS:
+        getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
+            None if name == "fpde_mesh_destroy" else ctypes.c_int)
+    _L = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != FPDE_OK:
+        raise FpdeError(st, what)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _np(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def params(alpha: float, K=(1.0, 1.0, 1.0), quad_points: int = 4, precision: int = FPDE_FP64,
+           source: int = FPDE_SRC_ONE, max_steps: int = 0, ir_tol: float = 0.0, ir_max_iter: int = 0):
+    p = fpde_params()
+    p.alpha = float(alpha)
+    for i in range(3):
+        p.K[i] = float(K[i])
+    p.quad_points = int(quad_points)
+    p.precision = int(precision)
+    p.source = int(source)
+    p.max_steps = int(max_steps)
+    p.ir_tol = float(ir_tol)
+    p.ir_max_iter = int(ir_max_iter)
+    return p
+
+
+class Mesh:
+    """Device-resident mesh handle (fpde_mesh_create / fpde_mesh_destroy)."""
+
+    def __init__(self, xyz, tet, stream=None):
+        L = _lib()
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tet = np.ascontiguousarray(tet, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(L.fpde_mesh_create(_np(self.xyz), self.xyz.shape[0], _np(self.tet), self.tet.shape[0],
+                                  _stream(stream), ctypes.byref(h)), "fpde_mesh_create")
+        self._h = h
+        nd, nb, nt = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.fpde_mesh_info(h, ctypes.byref(nd), ctypes.byref(nb), ctypes.byref(nt)), "fpde_mesh_info")
+        self.n_dof, self.n_boundary_faces, self.n_tet = nd.value, nb.value, nt.value
+        self.n_vert = self.xyz.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().fpde_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def dof_map(self) -> np.ndarray:
+        out = np.empty(self.n_vert, dtype=np.int32)
+        _check(_lib().fpde_dof_map(self._h, _np(out)), "fpde_dof_map")
+        return out
+
+    def plan(self, quad_points: int, max_steps: int = 0, stream=None):
+        _check(_lib().fpde_plan(self._h, quad_points, max_steps, _stream(stream)), "fpde_plan")
+
+    def paths(self, quad_points: int, dir: int, g0: int, count: int, max_steps: int = 4096,
+              lists: bool = False, stream=None):
+        import torch
+        dev = torch.device("cuda")
+        ln = torch.empty(count, dtype=torch.int32, device=dev)
+        hs = torch.empty(count, dtype=torch.int64, device=dev)
+        ids = torch.empty((count, max_steps), dtype=torch.int32, device=dev) if lists else None
+        rend = torch.empty((count, max_steps), dtype=torch.float64, device=dev) if lists else None
+        _check(_lib().fpde_paths(self._h, quad_points, dir, g0, count, max_steps, _ptr(ln), _ptr(hs),
+                                 _ptr(ids), _ptr(rend), _stream(stream)), "fpde_paths")
+        return ln, hs, ids, rend
+
+    def ray_values(self, quad_points: int, alpha: float, dir: int, g0: int, count: int, stream=None):
+        off = np.zeros(count + 1, dtype=np.int64)
+        L = _lib()
+        st = L.fpde_ray_values(self._h, quad_points, alpha, dir, g0, count, _np(off), None, None, 0,
+                               _stream(stream))
+        if st not in (FPDE_OK, -1):
+            _check(st, "fpde_ray_values")
+        n = int(off[-1])
+        dof = np.empty(max(n, 1), dtype=np.int32)
+        val = np.empty(max(n, 1), dtype=np.float64)
+        _check(L.fpde_ray_values(self._h, quad_points, alpha, dir, g0, count, _np(off), _np(dof), _np(val), n,
+                                 _stream(stream)), "fpde_ray_values")
+        return off, dof[:n], val[:n]
+
+    def assemble(self, p, A, b=None, f_gauss=None, stream=None):
+        _check(_lib().fpde_assemble(self._h, ctypes.byref(p), _ptr(A), A.stride(0), _ptr(b), _ptr(f_gauss),
+                                    _stream(stream)), "fpde_assemble")
+
+    def apply(self, p, x, y, stream=None):
+        _check(_lib().fpde_apply(self._h, ctypes.byref(p), _ptr(x), _ptr(y), _stream(stream)), "fpde_apply")
+
+    def solve(self, p, A, b, u, stream=None, info: bool = True):
+        """FP64: Cholesky + triangular solves (with info: the FP64 residual is
+        also measured); mixed: FP32 Cholesky + refinement (info always)."""
+        out = fpde_solve_info()
+        _check(_lib().fpde_solve(self._h, ctypes.byref(p), _ptr(A), A.stride(0), _ptr(b), _ptr(u),
+                                 ctypes.byref(out) if info else None, _stream(stream)), "fpde_solve")
+        return out if info else None
+
+    def solve_factored(self, p, L, b, u, stream=None, info: bool = True):
+        out = fpde_solve_info()
+        _check(_lib().fpde_solve_factored(self._h, ctypes.byref(p), _ptr(L), L.stride(0), _ptr(b), _ptr(u),
+                                          ctypes.byref(out) if info else None, _stream(stream)),
+               "fpde_solve_factored")
+        return out if info else None
+
+    def adjoint(self, p, u, lam, stream=None):
+        ga = ctypes.c_double()
+        gk = (ctypes.c_double * 3)()
+        _check(_lib().fpde_adjoint(self._h, ctypes.byref(p), _ptr(u), _ptr(lam), ctypes.byref(ga), gk,
+                                   _stream(stream)), "fpde_adjoint")
+        return ga.value, np.array(list(gk))
+
+
+def new_matrix(mesh: Mesh, precision: int = FPDE_FP64):
+    import torch
+    dt = torch.float64 if precision == FPDE_FP64 else torch.float32
+    n = max(mesh.n_dof, 1)
+    return torch.empty((n, n), dtype=dt, device="cuda")
+
+
+def solve_problem(mesh: Mesh, p, f_gauss=None, stream=None, info: bool = True):
+    """Assemble and solve: returns (u, factor, info) with device tensors."""
+    import torch
+    A = new_matrix(mesh, p.precision)
+    b = torch.empty(max(mesh.n_dof, 1), dtype=torch.float64, device="cuda")
+    mesh.assemble(p, A, b, f_gauss, stream)
+    u = torch.empty_like(b)
+    out = mesh.solve(p, A, b, u, stream, info=info)
+    return u, A, out
+
+
+from .autograd import FracSolve  # noqa: E402
+
+__all__ = ["Mesh", "params", "solve_problem", "new_matrix", "FracSolve", "FpdeError", "fpde_params",
+           "fpde_solve_info", "FPDE_FP64", "FPDE_MIXED", "FPDE_SRC_ONE", "FPDE_SRC_USER", "FPDE_SRC_CUBE_MMS",
+           "EXPORTS", "LIB_PATH"]

@@ -1,0 +1,332 @@
+// Accumulation of the dense stiffness matrix, load vector, matrix-free
+// product and adjoint sums (Sec. 2.1: K = sum_E K_E with element quadrature).
+//
+//   K_jk = sum_i K_i c_alpha sum_g w_g [R_gi(j) L_gi(k) + L_gi(j) R_gi(k)]
+//
+// Row-owner form: row j gathers every derivative-vector entry that sits on
+// node j (the node -> entry transpose built once per mesh and rule) and adds
+// W * value * (the partner half-ray's whole vector) into an FP64 row held in
+// LDS; the finished row is written to HBM once, coalesced.  Each entry of K
+// is therefore written exactly once and no global atomics are used.  The
+// template of Sec. 2.3 (the 0/1 pattern of K) appears here as the partner
+// lists themselves: only node pairs that share a Gauss-point line are ever
+// touched.
+#include <cmath>
+
+#include "fpde_internal.h"
+
+namespace fpde {
+
+int walk_adjoint(fpde_mesh *m, Plan *P, double alpha, const double *u, const double *lam, hipStream_t s);
+
+struct ContractArgs {
+  const int64_t *row_off;
+  const int64_t *inc;
+  const int32_t *ent_ray;
+  const int32_t *ent_dof;
+  const double *ent_val;
+  const int64_t *off;
+  const double *vol;
+  int64_t G, ndof, lda;
+  int nq;
+  int chunk;
+  double wq[11];
+  double KC[3];  // K_i c_alpha
+};
+
+template <class TO>
+__global__ void __launch_bounds__(256) k_contract_rows(ContractArgs c, TO *__restrict__ A) {
+  extern __shared__ double acc[];
+  const int tid = threadIdx.x;
+  for (int64_t row = blockIdx.x; row < c.ndof; row += gridDim.x) {
+    const int64_t p0 = c.row_off[row], p1 = c.row_off[row + 1];
+    for (int64_t c0 = 0; c0 < c.ndof; c0 += c.chunk) {
+      const int64_t cw = (c.ndof - c0) < c.chunk ? (c.ndof - c0) : c.chunk;
+      for (int64_t j = tid; j < cw; j += blockDim.x) acc[j] = 0.0;
+      __syncthreads();
+      for (int64_t p = p0 + tid; p < p1; p += blockDim.x) {
+        const int64_t e = c.inc[p];
+        const int64_t h = c.ent_ray[e];
+        const int dir = (int)(h / c.G);
+        const int64_t g = h - (int64_t)dir * c.G;
+        const int64_t partner = (dir & 1) ? h - c.G : h + c.G;
+        const double W = c.wq[g % c.nq] * c.vol[g / c.nq] * c.KC[dir >> 1];
+        const double coef = W * c.ent_val[e];
+        const int64_t k1 = c.off[partner + 1];
+        for (int64_t k = c.off[partner]; k < k1; k++) {
+          const int64_t d = (int64_t)c.ent_dof[k] - c0;
+          if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], coef * c.ent_val[k]);
+        }
+      }
+      __syncthreads();
+      TO *out = A + row * c.lda + c0;
+      for (int64_t j = tid; j < cw; j += blockDim.x) out[j] = (TO)acc[j];
+      __syncthreads();
+    }
+  }
+}
+
+struct LoadArgs {
+  const int32_t *vert_of_dof, *vt_off, *vt_tet, *tet;
+  const double *xyz, *vol, *f_gauss;
+  int64_t ndof;
+  int src;
+  int nq;
+  const double *qtab;  // device: nq x 4 barycentric coordinates, then nq weights
+  double K[3], c_alpha, alpha, rg3, rg4, rg5;  // 1/Gamma(3-a), 1/Gamma(4-a), 1/Gamma(5-a)
+};
+
+__device__ inline double mms_phi(double s) { return s * s * (1.0 - s) * (1.0 - s); }
+__device__ inline double mms_Phi(double s, const LoadArgs &a) {
+  return 2.0 * pow(s, 2.0 - a.alpha) * a.rg3 - 12.0 * pow(s, 3.0 - a.alpha) * a.rg4 +
+         24.0 * pow(s, 4.0 - a.alpha) * a.rg5;
+}
+
+// b_j = sum over elements E containing node j, points q: w_q |E| f(x_q) lambda_j(x_q)
+__global__ void k_load(LoadArgs a, double *__restrict__ b) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.ndof) return;
+  const int32_t v = a.vert_of_dof[j];
+  double sum = 0.0;
+  for (int32_t p = a.vt_off[v]; p < a.vt_off[v + 1]; p++) {
+    const int64_t t = a.vt_tet[p];
+    int jl = 0;
+    int32_t vv[4];
+    for (int m = 0; m < 4; m++) {
+      vv[m] = a.tet[4 * t + m];
+      if (vv[m] == v) jl = m;
+    }
+    for (int q = 0; q < a.nq; q++) {
+      double f = 1.0;
+      if (a.src == FPDE_SRC_USER) {
+        f = a.f_gauss[t * a.nq + q];
+      } else if (a.src == FPDE_SRC_CUBE_MMS) {
+        double x[3];
+        for (int d = 0; d < 3; d++) {
+          double s = 0.0;
+          for (int m = 0; m < 4; m++) s = s + a.qtab[4 * q + m] * a.xyz[3 * (int64_t)vv[m] + d];
+          x[d] = s;
+        }
+        const double ph[3] = {mms_phi(x[0]), mms_phi(x[1]), mms_phi(x[2])};
+        f = 0.0;
+        for (int i = 0; i < 3; i++) {
+          double other = 1.0;
+          for (int d = 0; d < 3; d++)
+            if (d != i) other *= ph[d];
+          f += a.K[i] * a.c_alpha * (mms_Phi(x[i], a) + mms_Phi(1.0 - x[i], a)) * other;
+        }
+      }
+      const double wg = a.qtab[4 * a.nq + q] * a.vol[t];
+      sum += wg * f * a.qtab[4 * q + jl];
+    }
+  }
+  b[j] = sum;
+}
+
+// d[h] = sum over entries of half-ray h of value * x[dof]
+__global__ void k_ray_dot(const int64_t *__restrict__ off, const int32_t *__restrict__ dof,
+                          const double *__restrict__ val, const double *__restrict__ x, int64_t n_half,
+                          double *__restrict__ d) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n_half) return;
+  double s = 0.0;
+  for (int64_t k = off[h]; k < off[h + 1]; k++) s += val[k] * x[dof[k]];
+  d[h] = s;
+}
+
+// y_j = sum over entries e on node j of W(h_e) value_e d[partner(h_e)]
+__global__ void k_apply_rows(ContractArgs c, const double *__restrict__ d, double *__restrict__ y) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ndof) return;
+  double s = 0.0;
+  for (int64_t p = c.row_off[j]; p < c.row_off[j + 1]; p++) {
+    const int64_t e = c.inc[p];
+    const int64_t h = c.ent_ray[e];
+    const int dir = (int)(h / c.G);
+    const int64_t g = h - (int64_t)dir * c.G;
+    const int64_t partner = (dir & 1) ? h - c.G : h + c.G;
+    const double W = c.wq[g % c.nq] * c.vol[g / c.nq] * c.KC[dir >> 1];
+    s += W * c.ent_val[e] * d[partner];
+  }
+  y[j] = s;
+}
+
+// Per-block partial sums of S_i, T_i (6 values) over Gauss points.
+__global__ void __launch_bounds__(256) k_adjoint_partial(const double *__restrict__ adj, const double *__restrict__ vol,
+                                                         int64_t G, int nq, const double *__restrict__ wq,
+                                                         double *__restrict__ part) {
+  __shared__ double red[6][256];
+  const int tid = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + tid; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+    const double wg = wq[g % nq] * vol[g / nq];
+    for (int i = 0; i < 3; i++) {
+      const double *L = adj + 4 * ((int64_t)(2 * i) * G + g);
+      const double *R = adj + 4 * ((int64_t)(2 * i + 1) * G + g);
+      // [0] value.u  [1] value.lam  [2] d/da value.u  [3] d/da value.lam
+      acc[i] += wg * (R[1] * L[0] + L[1] * R[0]);
+      acc[3 + i] += wg * (R[3] * L[0] + R[1] * L[2] + L[3] * R[0] + L[1] * R[2]);
+    }
+  }
+  for (int k = 0; k < 6; k++) red[k][tid] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int k = 0; k < 6; k++) red[k][tid] += red[k][tid + w];
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int k = 0; k < 6; k++) part[6 * blockIdx.x + k] = red[k][0];
+}
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+static ContractArgs contract_args(fpde_mesh *m, const Plan &P, const fpde_params *p, int64_t lda) {
+  QuadRule rule;
+  quad_rule(P.nq, &rule);
+  Order o = order_scalars(p->alpha);
+  ContractArgs c{};
+  c.row_off = P.row_off;
+  c.inc = P.inc;
+  c.ent_ray = P.ent_ray;
+  c.ent_dof = P.ent_dof;
+  c.ent_val = P.ent_val;
+  c.off = P.off;
+  c.vol = m->vol;
+  c.G = P.G;
+  c.ndof = m->ndof;
+  c.lda = lda;
+  c.nq = P.nq;
+  c.chunk = (int)(m->ndof < 8192 ? (m->ndof > 0 ? m->ndof : 1) : 8192);
+  for (int q = 0; q < 11; q++) c.wq[q] = rule.w[q];
+  for (int i = 0; i < 3; i++) c.KC[i] = p->K[i] * o.c_alpha;
+  return c;
+}
+
+int launch_contract(fpde_mesh *m, const Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
+  ContractArgs c = contract_args(m, P, p, lda);
+  if (m->ndof == 0) return FPDE_OK;
+  const unsigned grid = (unsigned)(m->ndof < 65536 ? m->ndof : 65536);
+  const size_t lds = sizeof(double) * (size_t)c.chunk;
+  if (p->precision == FPDE_MIXED)
+    k_contract_rows<float><<<grid, 256, lds, s>>>(c, (float *)A);
+  else
+    k_contract_rows<double><<<grid, 256, lds, s>>>(c, (double *)A);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_gauss, hipStream_t s) {
+  if (m->ndof == 0) return FPDE_OK;
+  LoadArgs a{};
+  a.vert_of_dof = m->vert_of_dof;
+  a.vt_off = m->vt_off;
+  a.vt_tet = m->vt_tet;
+  a.tet = m->tet;
+  a.xyz = m->xyz;
+  a.vol = m->vol;
+  a.f_gauss = f_gauss;
+  a.ndof = m->ndof;
+  a.src = p->source;
+  a.nq = p->quad_points;
+  a.qtab = m->rules + rule_offset(a.nq);
+  Order o = order_scalars(p->alpha);
+  for (int i = 0; i < 3; i++) a.K[i] = p->K[i];
+  a.c_alpha = o.c_alpha;
+  a.alpha = p->alpha;
+  a.rg3 = 1.0 / std::tgamma(3.0 - p->alpha);
+  a.rg4 = 1.0 / std::tgamma(4.0 - p->alpha);
+  a.rg5 = 1.0 / std::tgamma(5.0 - p->alpha);
+  k_load<<<nblk(m->ndof), 256, 0, s>>>(a, b);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+// y = K x from the stored derivative vectors (plan + values for p->alpha)
+int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
+                  hipStream_t s) {
+  ContractArgs c = contract_args(m, *P, p, 0);
+  k_ray_dot<<<nblk(P->n_half), 256, 0, s>>>(P->off, P->ent_dof, P->ent_val, x, P->n_half, dscratch);
+  k_apply_rows<<<nblk(m->ndof), 256, 0, s>>>(c, dscratch, y);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+int apply_scratch(fpde_mesh *m, Plan *P, double **d) {
+  // the adjoint buffer (4 per half-ray) doubles as the per-half-ray dot scratch
+  if (!P->adj) FPDE_TRY(dalloc(&P->adj, 4 * P->n_half));
+  *d = P->adj;
+  return FPDE_OK;
+}
+
+}  // namespace fpde
+
+using namespace fpde;
+
+extern "C" int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_t lda, double *b,
+                             const double *f_gauss, void *stream) {
+  FPDE_TRY(check_params(m, p));
+  if (!A || lda < m->ndof) return FPDE_EINVAL;
+  if (p->source == FPDE_SRC_USER && !f_gauss && b) return FPDE_EINVAL;
+  hipStream_t s = S(stream);
+  Plan *P = nullptr;
+  FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
+  FPDE_TRY(ensure_values(m, P, p->alpha, s));
+  FPDE_TRY(launch_contract(m, *P, p, A, lda, s));
+  if (b) FPDE_TRY(launch_load(m, p, b, f_gauss, s));
+  int f = take_flag(m, s);
+  if (f != 0) {
+    P->val_alpha = -1.0;
+    return f < 0 ? f : FPDE_EHIP;
+  }
+  return FPDE_OK;
+}
+
+extern "C" int fpde_apply(fpde_mesh *m, const fpde_params *p, const double *x, double *y, void *stream) {
+  FPDE_TRY(check_params(m, p));
+  if (!x || !y) return FPDE_EINVAL;
+  hipStream_t s = S(stream);
+  Plan *P = nullptr;
+  FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
+  FPDE_TRY(ensure_values(m, P, p->alpha, s));
+  double *d = nullptr;
+  FPDE_TRY(apply_scratch(m, P, &d));
+  FPDE_TRY(apply_matfree(m, P, p, x, y, d, s));
+  int f = take_flag(m, s);
+  return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
+}
+
+extern "C" int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const double *lam,
+                            double *grad_alpha, double *grad_K, void *stream) {
+  FPDE_TRY(check_params(m, p));
+  if (!u || !lam || !grad_alpha || !grad_K) return FPDE_EINVAL;
+  hipStream_t s = S(stream);
+  Plan *P = nullptr;
+  FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
+  FPDE_TRY(walk_adjoint(m, P, p->alpha, u, lam, s));
+  const unsigned nb = 512;
+  double *part = nullptr;
+  FPDE_TRY(dalloc(&part, 6 * nb));
+  k_adjoint_partial<<<nb, 256, 0, s>>>(P->adj, m->vol, P->G, P->nq,
+                                       m->rules + rule_offset(P->nq) + 4 * P->nq, part);
+  double h[6 * 512];
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipMemcpyAsync(h, part, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, s);
+  int f = (e1 == hipSuccess && e2 == hipSuccess) ? take_flag(m, s) : FPDE_EHIP;
+  dfree(part);
+  if (f != 0) return f < 0 ? f : FPDE_EHIP;
+  double S_[3] = {0, 0, 0}, T_[3] = {0, 0, 0};
+  for (unsigned b = 0; b < nb; b++)
+    for (int i = 0; i < 3; i++) {
+      S_[i] += h[6 * b + i];
+      T_[i] += h[6 * b + 3 + i];
+    }
+  Order o = order_scalars(p->alpha);
+  double ga = 0.0;
+  for (int i = 0; i < 3; i++) {
+    grad_K[i] = -o.c_alpha * S_[i];
+    ga -= p->K[i] * (o.dc_alpha * S_[i] + o.c_alpha * T_[i]);
+  }
+  *grad_alpha = ga;
+  return FPDE_OK;
+}

@@ -1,0 +1,132 @@
+// Internal declarations shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+#include "fpde.h"
+
+namespace fpde {
+
+// One element as the walk reads it: a single 128-byte record (one cache line
+// of the MI355X L2), so each step of the pointer-chasing walk costs one line.
+//   M[9]   : A^{-1} row-major, row r = gradient of volume coordinate k_{r+1}
+//            (Sec. 2.2: k = A^{-1}(x - v0), A = (v1-v0, v2-v0, v3-v0))
+//   v0[3]  : vertex 0
+//   nbr[4] : element across face f (opposite local vertex f), -1 = boundary
+//   dof[4] : unknown index of local vertex f, -1 on the boundary
+struct alignas(128) TetRec {
+  double M[9];
+  double v0[3];
+  int32_t nbr[4];
+  int32_t dof[4];
+};
+static_assert(sizeof(TetRec) == 128, "element record must be one 128-byte line");
+
+// Element quadrature rule in barycentric coordinates, weights summing to 1.
+struct QuadRule {
+  int nq;
+  double bary[11][4];
+  double w[11];
+};
+int quad_rule(int nq, QuadRule *out);  // FPDE_OK or FPDE_EINVAL
+// offset of the nq-point table inside fpde_mesh::rules
+inline int rule_offset(int nq) { return nq == 4 ? 0 : 4 * 5; }
+
+// Symbolic phase of one rule: derivative-vector sizes and the row transpose.
+// Half-ray index (direction-major): h = dir * G + g, dir = 2 i + side.
+struct Plan {
+  int nq = 0;
+  int max_steps = 0;
+  int64_t G = 0;          // Gauss points
+  int64_t n_half = 0;     // 6 G half-rays
+  int64_t n_ent = 0;      // entries over all half-rays
+  int64_t *off = nullptr;     // n_half + 1: entries of half-ray h
+  int32_t *ent_dof = nullptr; // n_ent
+  int32_t *ent_ray = nullptr; // n_ent: owning half-ray
+  double *ent_val = nullptr;  // n_ent: values for `val_alpha`
+  double val_alpha = -1.0;    // order the values were computed for
+  int64_t *row_off = nullptr; // n_dof + 1
+  int64_t *inc = nullptr;     // n_ent: entry ids grouped by their dof
+  double *adj = nullptr;      // 4 n_half scratch for the adjoint dots
+};
+
+}  // namespace fpde
+
+struct fpde_mesh {
+  int device = 0;
+  int64_t nv = 0, nt = 0, ndof = 0, nbf = 0;
+  double *xyz = nullptr;          // nv*3
+  int32_t *tet = nullptr;         // nt*4
+  fpde::TetRec *rec = nullptr;    // nt
+  double *vol = nullptr;          // nt
+  int32_t *vt_off = nullptr;      // nv+1
+  int32_t *vt_tet = nullptr;      // 4 nt
+  int32_t *dof = nullptr;         // nv
+  int32_t *vert_of_dof = nullptr; // ndof
+  double *rules = nullptr;        // device quadrature tables: [4-point | 11-point],
+                                  // each nq*4 barycentric coordinates then nq weights
+  int32_t *flag = nullptr;        // device status word (0 = ok)
+  int64_t *flag_aux = nullptr;    // device: failing column / ray
+  fpde::Plan plan[2];             // rules with 4 and 11 points
+  // solve scratch
+  double *vec = nullptr;          // 4 ndof FP64
+  double *red = nullptr;          // reduction scratch
+  int64_t red_n = 0;
+};
+
+namespace fpde {
+
+#define FPDE_HIP(call)                        \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return FPDE_EHIP;   \
+  } while (0)
+
+#define FPDE_TRY(call)             \
+  do {                             \
+    int s_ = (call);               \
+    if (s_ != FPDE_OK) return s_;  \
+  } while (0)
+
+template <class T>
+int dalloc(T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return FPDE_ENOMEM;
+  }
+  return FPDE_OK;
+}
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+// Device status word: keeps the first error reported by any thread.
+__device__ inline void set_flag(int32_t *flag, int code) { atomicCAS(flag, 0, code); }
+
+// Reads (and clears) the device status word; synchronises the stream.
+int take_flag(fpde_mesh *m, hipStream_t s, int64_t *aux = nullptr);
+
+int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out);
+int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s);
+int check_params(const fpde_mesh *m, const fpde_params *p);
+void free_plan(Plan &P);
+
+// host-side order scalars
+struct Order {
+  double gamma, e;        // gamma = alpha/2, e = 1 - gamma
+  double inv_g2;          // 1/Gamma(2-gamma)
+  double half_psi0;       // psi(2-gamma)/2
+  double c_alpha, dc_alpha;
+};
+Order order_scalars(double alpha);
+
+}  // namespace fpde

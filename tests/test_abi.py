@@ -1,0 +1,70 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point declared in include/fpde.h, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1811_03339_amd as F
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fpde.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpde_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert len(names) >= 13
+    L = F._lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(F.EXPORTS)
+
+
+def test_status_strings():
+    L = F._lib()
+    for code in F.STATUS:
+        s = L.fpde_status_string(code)
+        assert s and s != b"unknown status"
+    assert L.fpde_status_string(12345) == b"unknown status"
+
+
+def test_mesh_create_rejects_bad_input_without_device():
+    L = F._lib()
+    h = ctypes.c_void_p()
+    xyz = np.zeros((4, 3))
+    tet = np.array([[0, 1, 2, 7]], dtype=np.int32)  # vertex id out of range
+    st = L.fpde_mesh_create(xyz.ctypes.data_as(ctypes.c_void_p), 4, tet.ctypes.data_as(ctypes.c_void_p), 1,
+                            None, ctypes.byref(h))
+    assert st == -1 and not h.value
+    st = L.fpde_mesh_create(None, 4, None, 1, None, ctypes.byref(h))
+    assert st == -1
+    bad = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, np.nan]])
+    tet = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    st = L.fpde_mesh_create(bad.ctypes.data_as(ctypes.c_void_p), 4, tet.ctypes.data_as(ctypes.c_void_p), 1,
+                            None, ctypes.byref(h))
+    assert st == -1
+
+
+def test_calls_on_null_handle_are_rejected():
+    L = F._lib()
+    p = F.params(1.5)
+    assert L.fpde_assemble(None, ctypes.byref(p), None, 0, None, None, None) == -1
+    assert L.fpde_solve(None, ctypes.byref(p), None, 0, None, None, None, None) == -1
+    assert L.fpde_plan(None, 4, 0, None) == -1
+    assert L.fpde_mesh_info(None, None, None, None) == -1
+
+
+def test_params_layout_matches_header():
+    # double alpha; double K[3]; int quad_points, precision, source, max_steps;
+    # double ir_tol; int ir_max_iter
+    assert ctypes.sizeof(F.fpde_params) == 8 + 24 + 16 + 8 + 8
+    assert F.fpde_params.ir_tol.offset == 48
+    assert ctypes.sizeof(F.fpde_solve_info) == 24
