@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark of the fractional FEM hot path on one MI355X.
+
+Workload (synthetic, seeded): the convex hull of 400 random points on the
+unit sphere filled with a jittered body-centred-cubic lattice (19 689
+elements, 3 472 nodes, 3 072 interior unknowns), Riesz orders
+alpha in {1.2, 1.5, 1.8}, K = (1, 0.5, 2), the 4- and 11-point element rules.
+
+One step = for each rule and each alpha: assemble (path walk + closed-form
+derivatives, accumulation of the dense FP64 stiffness matrix, load vector)
+and solve (dense FP64 Cholesky + triangular solves) -- six assembly+solve
+passes.  The mesh set-up and the symbolic plan (the template, built once per
+mesh and rule) happen before the timed region and are reported apart.
+
+value = Gauss-point paths per second over the timed steps (6 half-rays per
+Gauss point, summed over the six passes, divided by the step time).
+The single JSON line on stdout also carries the per-stage times, the
+roofline of the dominant kernel (measured with HIP events inside the library
+on the launch stream), the mixed-precision arm and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "assembly+solve s & Gauss-pt paths/s at N nodes, FP64 vs mixed @1e-6 rel err"
+WORKLOAD = "sphere20k"
+ALPHAS = (1.2, 1.5, 1.8)
+RULES = (4, 11)
+KCOEF = (1.0, 0.5, 2.0)
+HBM_PEAK = 8.0e12        # B/s
+FP64_PEAK = 78.6e12      # FLOP/s, vector and matrix
+PMC_FILE = os.path.join(ROOT, "profiles", "contract_rows_sphere20k_pmc.txt")
+CONTRACT_SRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc", "assemble.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_sha1(path):
+    return hashlib.sha1(open(path, "rb").read()).hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per contraction launch from the committed PMC summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha1") != src_sha1(CONTRACT_SRC):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(mesh_np):
+    """The oracle, unchanged, single-threaded, on one full step."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    with threadpool_limits(limits=1):
+        om = oracle.OracleMesh(mesh_np.xyz, mesh_np.tet)
+        rays = 0
+        t0 = time.perf_counter()
+        for nq in RULES:
+            for a in ALPHAS:
+                A = om.assemble(nq, a, KCOEF)
+                b = om.load(nq)
+                oracle.solve_spd(A, b)
+                rays += 6 * om.n_tet * nq
+        dt = time.perf_counter() - t0
+    return {"value": rays / dt, "unit": "Gauss-pt paths/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full step ({len(RULES)} rules x {len(ALPHAS)} alphas): dense assembly + load + "
+                      f"LAPACK Cholesky, FP64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision arm")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the build is single-GPU)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1811_03339_amd as F
+    from fpde_inputs import workload_mesh
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t = time.perf_counter()
+    mesh = workload_mesh(WORKLOAD)
+    gen_s = time.perf_counter() - t
+    log(f"[bench] mesh {WORKLOAD}: {mesh.n_vert} nodes, {mesh.n_tet} elements ({gen_s:.1f} s to generate)")
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    gm = F.Mesh(mesh.xyz, mesh.tet)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    info = {}
+    for nq in RULES:
+        gm.plan(nq)
+        info[nq] = gm.plan_info(nq)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t)
+    n = gm.n_dof
+    log(f"[bench] n_dof {n}, mesh set-up {setup_ms:.1f} ms, plans {plan_ms:.1f} ms, {info}")
+
+    A = torch.empty((n, n), dtype=torch.float64, device=dev)
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    rays_per_step = sum(6 * gm.n_tet * nq for nq in RULES) * len(ALPHAS)
+
+    def step():
+        for nq in RULES:
+            for a in ALPHAS:
+                p = F.params(a, KCOEF, quad_points=nq)
+                gm.assemble(p, A, b)
+                gm.solve(p, A, b, u, info=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gm.timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(args.steps):
+        step()
+        log(f"[bench] step {k + 1}/{args.steps} done")
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    gm.timing(False)
+    stages = gm.stage_times()
+    ms_per_step = total_ms / args.steps
+    value = rays_per_step * args.steps / (total_ms / 1e3)
+    log(f"[bench] {ms_per_step:.2f} ms/step, {value:.3e} paths/s, stages {stages}")
+
+    # roofline of the dominant single-kernel stage
+    single = {k: stages[k] for k in ("walk", "contract", "load")}
+    dom = max(single, key=lambda k: single[k][0])
+    dom_ms, dom_launches = single[dom]
+    per_pass = {}
+    for nq in RULES:
+        I = info[nq]
+        per_pass[nq] = {
+            "bytes": n * n * 8 + I["entries"] * 12,      # write K once, read every entry once
+            "flops": 4 * I["pairs"],                      # both outer products, multiply + add
+        }
+    roofline = None
+    if dom == "contract" and dom_launches > 0:
+        launches_per_rule = dom_launches / len(RULES)
+        alg_bytes = sum(per_pass[nq]["bytes"] for nq in RULES) * launches_per_rule
+        alg_flops = sum(per_pass[nq]["flops"] for nq in RULES) * launches_per_rule
+        t_s = dom_ms / 1e3
+        if alg_bytes / HBM_PEAK >= alg_flops / FP64_PEAK:
+            ach, peak, unit, bound = alg_bytes / t_s / 1e9, HBM_PEAK / 1e9, "GB/s", "hbm"
+        else:
+            ach, peak, unit, bound = alg_flops / t_s / 1e12, FP64_PEAK / 1e12, "TFLOP/s", "alu"
+        tr = read_traffic()
+        roofline = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                    "traffic": tr, "kernel": "k_contract_rows<double>",
+                    "avg_launch_ms": dom_ms / dom_launches}
+    elif dom_launches > 0:
+        roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "kernel": dom, "avg_launch_ms": dom_ms / dom_launches}
+
+    # mixed-precision arm at alpha = 1.5, 11-point rule
+    mixed = None
+    if not args.no_mixed:
+        p64 = F.params(1.5, KCOEF, quad_points=11)
+        pmx = F.params(1.5, KCOEF, quad_points=11, precision=F.FPDE_MIXED, ir_tol=1e-8)
+        A32 = torch.empty((n, n), dtype=torch.float32, device=dev)
+        u32 = torch.empty_like(u)
+
+        def timed(fn, reps=3):
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r = fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return sorted(ts)[len(ts) // 2], r
+
+        def run64():
+            gm.assemble(p64, A, b)
+            gm.solve(p64, A, b, u, info=False)
+
+        def runmx():
+            gm.assemble(pmx, A32, b)
+            return gm.solve(pmx, A32, b, u32)
+
+        t64, _ = timed(run64)
+        tmx, inf = timed(runmx)
+        err = float((u32 - u).abs().max() / u.abs().max())
+        mixed = {"workload": "alpha=1.5, 11-point rule", "fp64_assembly_solve_s": t64 / 1e3,
+                 "mixed_assembly_solve_s": tmx / 1e3, "speedup_vs_fp64": t64 / tmx,
+                 "rel_err_vs_fp64": err, "ir_iters": inf.ir_iters,
+                 "final_rel_residual": inf.final_rel_residual}
+        log(f"[bench] mixed {mixed}")
+
+    if args.copy_calib:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 1 GiB device-to-device copy done")
+
+    cpu = None if args.no_cpu else cpu_baseline(mesh)
+    if cpu:
+        log(f"[bench] cpu oracle {cpu}")
+
+    passes = len(RULES) * len(ALPHAS)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gauss-pt paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{WORKLOAD}: hull of 400 seeded points on the unit sphere + BCC lattice, "
+                        f"{gm.n_tet} tets, {mesh.n_vert} nodes ({n} interior); alpha {list(ALPHAS)}, "
+                        f"K={list(KCOEF)}, rules {list(RULES)}; FP64 assembly + dense Cholesky; "
+                        f"{passes} assembly+solve passes per step",
+            "n_nodes": mesh.n_vert, "n_dof": n, "n_tet": gm.n_tet,
+            "gauss_points": {str(nq): gm.n_tet * nq for nq in RULES},
+            "parallelism": "single GPU",
+        },
+        "assembly_solve_s_per_pass": ms_per_step / passes / 1e3,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0},
+        "walk_eval_paths_per_s": (rays_per_step * args.steps / (stages["walk"][0] / 1e3)
+                                  if stages["walk"][0] > 0 else None),
+        "setup_ms": setup_ms,
+        "template_plan_ms": plan_ms,
+        "plan": {str(k): v for k, v in info.items()},
+        "roofline": roofline,
+        "mixed": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

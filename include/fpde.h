@@ -204,6 +204,40 @@ int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const void *L, int64
 int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const double *lam,
                  double *grad_alpha, double *grad_K, void *stream);
 
+/*
+ * Stage timing with HIP events recorded on the caller's stream around each
+ * stage launch (no extra synchronisation while recording).
+ * Stages: walk + closed-form evaluation, accumulation kernel, load vector,
+ * Cholesky factorisation (all panels), triangular solves, matrix-free
+ * product, symbolic plan, adjoint re-walk.
+ *   fpde_timing(m, 1) clears the totals and starts recording; (m, 0) stops.
+ *   fpde_stage_times waits for the recorded events, then writes per stage
+ *   the summed milliseconds (host, FPDE_NSTAGES doubles) and the number of
+ *   timed intervals (host, FPDE_NSTAGES int64; either pointer may be NULL).
+ */
+enum {
+  FPDE_STAGE_WALK = 0,
+  FPDE_STAGE_CONTRACT = 1,
+  FPDE_STAGE_LOAD = 2,
+  FPDE_STAGE_POTRF = 3,
+  FPDE_STAGE_TRSV = 4,
+  FPDE_STAGE_APPLY = 5,
+  FPDE_STAGE_PLAN = 6,
+  FPDE_STAGE_ADJOINT = 7,
+  FPDE_NSTAGES = 8
+};
+int fpde_timing(fpde_mesh *m, int enable);
+int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
+
+/*
+ * Sizes of the symbolic plan of a rule (built on demand; see fpde_plan):
+ *   out[0] half-rays (6 G), out[1] derivative-vector entries over all
+ *   half-rays, out[2] sum over (g, i) of |L_gi| |R_gi| (entry pairs the
+ *   accumulation multiplies), out[3] largest number of entries of one
+ *   half-ray.  host, 4 int64.  Synchronises `stream`.
+ */
+int fpde_plan_info(fpde_mesh *m, int quad_points, int64_t *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

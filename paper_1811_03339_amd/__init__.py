@@ -31,8 +31,10 @@ STATUS = {
 EXPORTS = [
     "fpde_status_string", "fpde_mesh_create", "fpde_mesh_destroy", "fpde_mesh_info", "fpde_dof_map",
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
-    "fpde_solve_factored", "fpde_adjoint",
+    "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
 ]
+
+STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint"]
 
 
 class FpdeError(RuntimeError):
@@ -84,6 +86,9 @@ def _lib():
     L.fpde_solve.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_solve_factored.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_adjoint.argtypes = [P, P, P, P, P, P, P]
+    L.fpde_timing.argtypes = [P, i32]
+    L.fpde_stage_times.argtypes = [P, P, P]
+    L.fpde_plan_info.argtypes = [P, i32, P, P]
     for name in EXPORTS:
         getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
             None if name == "fpde_mesh_destroy" else ctypes.c_int)
@@ -162,6 +167,20 @@ class Mesh:
 
     def plan(self, quad_points: int, max_steps: int = 0, stream=None):
         _check(_lib().fpde_plan(self._h, quad_points, max_steps, _stream(stream)), "fpde_plan")
+
+    def plan_info(self, quad_points: int, stream=None) -> dict:
+        out = np.zeros(4, dtype=np.int64)
+        _check(_lib().fpde_plan_info(self._h, quad_points, _np(out), _stream(stream)), "fpde_plan_info")
+        return {"half_rays": int(out[0]), "entries": int(out[1]), "pairs": int(out[2]), "max_entries": int(out[3])}
+
+    def timing(self, enable: bool):
+        _check(_lib().fpde_timing(self._h, 1 if enable else 0), "fpde_timing")
+
+    def stage_times(self) -> dict:
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), dtype=np.int64)
+        _check(_lib().fpde_stage_times(self._h, _np(ms), _np(cnt)), "fpde_stage_times")
+        return {s: (float(ms[k]), int(cnt[k])) for k, s in enumerate(STAGES)}
 
     def paths(self, quad_points: int, dir: int, g0: int, count: int, max_steps: int = 4096,
               lists: bool = False, stream=None):

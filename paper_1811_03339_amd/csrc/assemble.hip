@@ -134,12 +134,15 @@ __global__ void k_ray_dot(const int64_t *__restrict__ off, const int32_t *__rest
   d[h] = s;
 }
 
-// y_j = sum over entries e on node j of W(h_e) value_e d[partner(h_e)]
-__global__ void k_apply_rows(ContractArgs c, const double *__restrict__ d, double *__restrict__ y) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// y_j = sum over entries e on node j of W(h_e) value_e d[partner(h_e)];
+// one wavefront per row, lanes stride over the row's entries
+__global__ void __launch_bounds__(256) k_apply_rows(ContractArgs c, const double *__restrict__ d,
+                                                    double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= c.ndof) return;
   double s = 0.0;
-  for (int64_t p = c.row_off[j]; p < c.row_off[j + 1]; p++) {
+  for (int64_t p = c.row_off[j] + lane; p < c.row_off[j + 1]; p += 64) {
     const int64_t e = c.inc[p];
     const int64_t h = c.ent_ray[e];
     const int dir = (int)(h / c.G);
@@ -148,7 +151,8 @@ __global__ void k_apply_rows(ContractArgs c, const double *__restrict__ d, doubl
     const double W = c.wq[g % c.nq] * c.vol[g / c.nq] * c.KC[dir >> 1];
     s += W * c.ent_val[e] * d[partner];
   }
-  y[j] = s;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) y[j] = s;
 }
 
 // Per-block partial sums of S_i, T_i (6 values) over Gauss points.
@@ -208,10 +212,12 @@ int launch_contract(fpde_mesh *m, const Plan &P, const fpde_params *p, void *A, 
   if (m->ndof == 0) return FPDE_OK;
   const unsigned grid = (unsigned)(m->ndof < 65536 ? m->ndof : 65536);
   const size_t lds = sizeof(double) * (size_t)c.chunk;
+  const long t = timer_begin(m, s);
   if (p->precision == FPDE_MIXED)
     k_contract_rows<float><<<grid, 256, lds, s>>>(c, (float *)A);
   else
     k_contract_rows<double><<<grid, 256, lds, s>>>(c, (double *)A);
+  timer_end(m, FPDE_STAGE_CONTRACT, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }
@@ -237,7 +243,9 @@ int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_g
   a.rg3 = 1.0 / std::tgamma(3.0 - p->alpha);
   a.rg4 = 1.0 / std::tgamma(4.0 - p->alpha);
   a.rg5 = 1.0 / std::tgamma(5.0 - p->alpha);
+  const long t = timer_begin(m, s);
   k_load<<<nblk(m->ndof), 256, 0, s>>>(a, b);
+  timer_end(m, FPDE_STAGE_LOAD, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }
@@ -246,8 +254,10 @@ int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_g
 int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
                   hipStream_t s) {
   ContractArgs c = contract_args(m, *P, p, 0);
+  const long t = timer_begin(m, s);
   k_ray_dot<<<nblk(P->n_half), 256, 0, s>>>(P->off, P->ent_dof, P->ent_val, x, P->n_half, dscratch);
-  k_apply_rows<<<nblk(m->ndof), 256, 0, s>>>(c, dscratch, y);
+  k_apply_rows<<<nblk(m->ndof, 4), 256, 0, s>>>(c, dscratch, y);
+  timer_end(m, FPDE_STAGE_APPLY, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <cstddef>
+#include <vector>
 
 #include "fpde.h"
 
@@ -51,6 +52,20 @@ struct Plan {
   int64_t *row_off = nullptr; // n_dof + 1
   int64_t *inc = nullptr;     // n_ent: entry ids grouped by their dof
   double *adj = nullptr;      // 4 n_half scratch for the adjoint dots
+  int64_t pairs = 0;          // sum over (g, i) of |L| |R|
+  int64_t max_ent = 0;        // largest entry count of one half-ray
+};
+
+// HIP events around stage launches on the caller's stream (fpde_timing).
+struct StageTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Mark {
+    int stage;
+    size_t a, b;
+  };
+  std::vector<Mark> marks;
 };
 
 }  // namespace fpde
@@ -75,6 +90,7 @@ struct fpde_mesh {
   double *vec = nullptr;          // 4 ndof FP64
   double *red = nullptr;          // reduction scratch
   int64_t red_n = 0;
+  fpde::StageTimer timer;
 };
 
 namespace fpde {
@@ -119,6 +135,10 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out);
 int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s);
 int check_params(const fpde_mesh *m, const fpde_params *p);
 void free_plan(Plan &P);
+
+// Stage timing: t = timer_begin(m, s); ...launches...; timer_end(m, stage, t, s)
+long timer_begin(fpde_mesh *m, hipStream_t s);
+void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s);
 
 // host-side order scalars
 struct Order {

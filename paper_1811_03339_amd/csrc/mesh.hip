@@ -429,6 +429,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   dfree(m->xyz); dfree(m->tet); dfree(m->rec); dfree(m->vol); dfree(m->vt_off); dfree(m->vt_tet);
   dfree(m->dof); dfree(m->vert_of_dof); dfree(m->rules); dfree(m->flag); dfree(m->flag_aux); dfree(m->vec); dfree(m->red);
   for (auto &P : m->plan) free_plan(P);
+  for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -443,5 +444,64 @@ extern "C" int fpde_mesh_info(const fpde_mesh *m, int64_t *n_dof, int64_t *n_bou
 extern "C" int fpde_dof_map(const fpde_mesh *m, int32_t *dof) {
   if (!m || !dof) return FPDE_EINVAL;
   FPDE_HIP(hipMemcpy(dof, m->dof, sizeof(int32_t) * m->nv, hipMemcpyDeviceToHost));
+  return FPDE_OK;
+}
+
+namespace fpde {
+
+long timer_begin(fpde_mesh *m, hipStream_t s) {
+  StageTimer &T = m->timer;
+  if (!T.on) return -1;
+  if (T.used >= T.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    T.pool.push_back(e);
+  }
+  const size_t i = T.used++;
+  if (hipEventRecord(T.pool[i], s) != hipSuccess) return -1;
+  return (long)i;
+}
+
+void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s) {
+  StageTimer &T = m->timer;
+  if (t < 0 || !T.on) return;
+  if (T.used >= T.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    T.pool.push_back(e);
+  }
+  const size_t i = T.used++;
+  if (hipEventRecord(T.pool[i], s) != hipSuccess) return;
+  T.marks.push_back({stage, (size_t)t, i});
+}
+
+}  // namespace fpde
+
+extern "C" int fpde_timing(fpde_mesh *m, int enable) {
+  if (!m) return FPDE_EINVAL;
+  if (enable) {
+    FPDE_HIP(hipDeviceSynchronize());
+    m->timer.used = 0;
+    m->timer.marks.clear();
+  }
+  m->timer.on = enable != 0;
+  return FPDE_OK;
+}
+
+extern "C" int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count) {
+  if (!m) return FPDE_EINVAL;
+  double t[FPDE_NSTAGES] = {0};
+  int64_t c[FPDE_NSTAGES] = {0};
+  for (const auto &mk : m->timer.marks) {
+    FPDE_HIP(hipEventSynchronize(m->timer.pool[mk.b]));
+    float e = 0.f;
+    FPDE_HIP(hipEventElapsedTime(&e, m->timer.pool[mk.a], m->timer.pool[mk.b]));
+    t[mk.stage] += (double)e;
+    c[mk.stage] += 1;
+  }
+  for (int k = 0; k < FPDE_NSTAGES; k++) {
+    if (ms) ms[k] = t[k];
+    if (count) count[k] = c[k];
+  }
   return FPDE_OK;
 }

@@ -253,6 +253,13 @@ static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b -
 
 template <class T>
 static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
+  const long t = timer_begin(m, s);
+  struct End {
+    fpde_mesh *m;
+    long t;
+    hipStream_t s;
+    ~End() { timer_end(m, FPDE_STAGE_POTRF, t, s); }
+  } end{m, t, s};
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, k0, m->flag, m->flag_aux);
     const int64_t rest = n - k0 - NB;
@@ -267,7 +274,14 @@ static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
 }
 
 template <class T>
-static int trsv_pair(const T *L, int64_t lda, int64_t n, double *y, hipStream_t s) {
+static int trsv_pair(const T *L, int64_t lda, int64_t n, double *y, fpde_mesh *m, hipStream_t s) {
+  const long t = timer_begin(m, s);
+  struct End {
+    fpde_mesh *m;
+    long t;
+    hipStream_t s;
+    ~End() { timer_end(m, FPDE_STAGE_TRSV, t, s); }
+  } end{m, t, s};
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     k_trsv_lo_diag<T><<<1, 64, 0, s>>>(L, lda, n, k0, y);
     const int64_t rest = n - k0 - NB;
@@ -315,7 +329,7 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
   FPDE_TRY(ensure_vec(m));
   if (p->precision == FPDE_FP64) {
     if (u != b) FPDE_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    FPDE_TRY(trsv_pair<double>((const double *)L, lda, n, u, s));
+    FPDE_TRY(trsv_pair<double>((const double *)L, lda, n, u, m, s));
     if (info) {
       double *y = m->vec, *r = m->vec + n;
       Plan *P = nullptr;
@@ -338,7 +352,7 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
   double *y = m->vec, *r = m->vec + n, *bb = m->vec + 2 * n;
   FPDE_HIP(hipMemcpyAsync(bb, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   FPDE_HIP(hipMemcpyAsync(u, bb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, u, s));
+  FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, u, m, s));
   Plan *P = nullptr;
   FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
   FPDE_TRY(ensure_values(m, P, p->alpha, s));
@@ -355,7 +369,7 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
     FPDE_TRY(norm2(m, r, &rn, s));
     rel = bn > 0 ? rn / bn : rn;
     if (rel <= tol || it >= maxit) break;
-    FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, r, s));
+    FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, r, m, s));
     k_axpy_copy<<<nblk(n), 256, 0, s>>>(u, r, n);
     it++;
   }

@@ -453,6 +453,21 @@ static int build_plan(fpde_mesh *m, Plan &P, int nq, int max_steps, hipStream_t 
   if (f != 0) return fail(f < 0 ? f : FPDE_EHIP);
   dfree(cnt); dfree(cnt64); dfree(rowcnt); dfree(cursor);
   (void)hipFree(tmp);
+  // sizes for reporting: entry pairs the accumulation multiplies
+  {
+    std::vector<int64_t> off(P.n_half + 1);
+    if (hipMemcpy(off.data(), P.off, sizeof(int64_t) * (P.n_half + 1), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(FPDE_EHIP);
+    P.pairs = 0;
+    P.max_ent = 0;
+    for (int i = 0; i < 3; i++)
+      for (int64_t g = 0; g < P.G; g++) {
+        const int64_t hl = (int64_t)(2 * i) * P.G + g, hr = hl + P.G;
+        const int64_t nl = off[hl + 1] - off[hl], nr = off[hr + 1] - off[hr];
+        P.pairs += nl * nr;
+        P.max_ent = std::max(P.max_ent, std::max(nl, nr));
+      }
+  }
   P.val_alpha = -1.0;
   return FPDE_OK;
 }
@@ -466,7 +481,9 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out) {
     return FPDE_OK;
   }
   free_plan(P);
+  const long t = timer_begin(m, s);
   FPDE_TRY(build_plan(m, P, nq, max_steps, s));
+  timer_end(m, FPDE_STAGE_PLAN, t, s);
   *out = &P;
   return FPDE_OK;
 }
@@ -484,7 +501,9 @@ int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s) {
   a.inv_g2 = o.inv_g2;
   a.off = P->off;
   a.ent_val = P->ent_val;
+  const long t = timer_begin(m, s);
   launch_walk<W_VALUES>(a, s);
+  timer_end(m, FPDE_STAGE_WALK, t, s);
   FPDE_HIP(hipGetLastError());
   P->val_alpha = alpha;
   return FPDE_OK;
@@ -506,7 +525,9 @@ int walk_adjoint(fpde_mesh *m, Plan *P, double alpha, const double *u, const dou
   a.u = u;
   a.lam = lam;
   a.adj = P->adj;
+  const long t = timer_begin(m, s);
   launch_walk<W_ADJ>(a, s);
+  timer_end(m, FPDE_STAGE_ADJOINT, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }
@@ -573,5 +594,16 @@ extern "C" int fpde_ray_values(fpde_mesh *m, int quad_points, double alpha, int 
     FPDE_HIP(hipMemcpyAsync(val, P->ent_val + e0, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     FPDE_HIP(hipStreamSynchronize(s));
   }
+  return FPDE_OK;
+}
+
+extern "C" int fpde_plan_info(fpde_mesh *m, int quad_points, int64_t *out, void *stream) {
+  if (!m || !out) return FPDE_EINVAL;
+  Plan *P = nullptr;
+  FPDE_TRY(plan_for(m, quad_points, 0, S(stream), &P));
+  out[0] = P->n_half;
+  out[1] = P->n_ent;
+  out[2] = P->pairs;
+  out[3] = P->max_ent;
   return FPDE_OK;
 }
