@@ -21,41 +21,57 @@ int walk_adjoint(fpde_mesh *m, Plan *P, double alpha, const double *u, const dou
 
 struct ContractArgs {
   const int64_t *row_off;
-  const int64_t *inc;
-  const int32_t *ent_ray;
+  const int4 *meta;       // per incidence: entry, partner offset, partner length << 2 | axis, partner
+  const double *w;        // per incidence: Gauss weight w_g
   const int32_t *ent_dof;
   const double *ent_val;
-  const int64_t *off;
-  const double *vol;
-  int64_t G, ndof, lda;
-  int nq;
+  int64_t ndof, lda;
   int chunk;
-  double wq[11];
-  double KC[3];  // K_i c_alpha
+  double KC0, KC1, KC2;   // K_i c_alpha
+  __device__ __forceinline__ double KC(int i) const { return i == 0 ? KC0 : (i == 1 ? KC1 : KC2); }
 };
 
+// One workgroup (4 wavefronts) per row j.  A wavefront takes 64 incidences
+// of the row at a time: each lane loads one incidence's flattened record and
+// forms its coefficient W value_e; then the two half-wavefronts walk two
+// partner vectors at once, 32 consecutive entries per step (coalesced loads),
+// adding coef * value into the LDS row.  Within one instruction the lanes of
+// a half-wavefront hit distinct columns.
 template <class TO>
 __global__ void __launch_bounds__(256) k_contract_rows(ContractArgs c, TO *__restrict__ A) {
   extern __shared__ double acc[];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, sub = lane & 31;
   for (int64_t row = blockIdx.x; row < c.ndof; row += gridDim.x) {
     const int64_t p0 = c.row_off[row], p1 = c.row_off[row + 1];
     for (int64_t c0 = 0; c0 < c.ndof; c0 += c.chunk) {
       const int64_t cw = (c.ndof - c0) < c.chunk ? (c.ndof - c0) : c.chunk;
       for (int64_t j = tid; j < cw; j += blockDim.x) acc[j] = 0.0;
       __syncthreads();
-      for (int64_t p = p0 + tid; p < p1; p += blockDim.x) {
-        const int64_t e = c.inc[p];
-        const int64_t h = c.ent_ray[e];
-        const int dir = (int)(h / c.G);
-        const int64_t g = h - (int64_t)dir * c.G;
-        const int64_t partner = (dir & 1) ? h - c.G : h + c.G;
-        const double W = c.wq[g % c.nq] * c.vol[g / c.nq] * c.KC[dir >> 1];
-        const double coef = W * c.ent_val[e];
-        const int64_t k1 = c.off[partner + 1];
-        for (int64_t k = c.off[partner]; k < k1; k++) {
-          const int64_t d = (int64_t)c.ent_dof[k] - c0;
-          if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], coef * c.ent_val[k]);
+      for (int64_t pb = p0 + 64 * wave; pb < p1; pb += 256) {
+        const int64_t p = pb + lane;
+        int po = 0, pl = 0;
+        double coef = 0.0;
+        if (p < p1) {
+          const int4 mt = c.meta[p];
+          po = mt.y;
+          pl = mt.z >> 2;
+          coef = c.w[p] * c.KC(mt.z & 3) * c.ent_val[mt.x];
+        }
+        const int nv = (int)((p1 - pb) < 64 ? (p1 - pb) : 64);
+        for (int t = 0; t < nv; t += 2) {
+          // every lane joins each shuffle: a lane masked off by a condition
+          // would not deliver its value to the lanes reading from it
+          const int src = t + half;
+          const int spo = __shfl(po, src, 64);
+          const int spl_all = __shfl(pl, src, 64);
+          const double scf = __shfl(coef, src, 64);
+          const int spl = (src < nv) ? spl_all : 0;
+          for (int k = sub; k < spl; k += 32) {
+            const int64_t d = (int64_t)c.ent_dof[spo + k] - c0;
+            if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf * c.ent_val[spo + k]);
+          }
         }
       }
       __syncthreads();
@@ -143,13 +159,8 @@ __global__ void __launch_bounds__(256) k_apply_rows(ContractArgs c, const double
   if (j >= c.ndof) return;
   double s = 0.0;
   for (int64_t p = c.row_off[j] + lane; p < c.row_off[j + 1]; p += 64) {
-    const int64_t e = c.inc[p];
-    const int64_t h = c.ent_ray[e];
-    const int dir = (int)(h / c.G);
-    const int64_t g = h - (int64_t)dir * c.G;
-    const int64_t partner = (dir & 1) ? h - c.G : h + c.G;
-    const double W = c.wq[g % c.nq] * c.vol[g / c.nq] * c.KC[dir >> 1];
-    s += W * c.ent_val[e] * d[partner];
+    const int4 mt = c.meta[p];
+    s += c.w[p] * c.KC(mt.z & 3) * c.ent_val[mt.x] * d[mt.w];
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) y[j] = s;
@@ -186,24 +197,19 @@ __global__ void __launch_bounds__(256) k_adjoint_partial(const double *__restric
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 static ContractArgs contract_args(fpde_mesh *m, const Plan &P, const fpde_params *p, int64_t lda) {
-  QuadRule rule;
-  quad_rule(P.nq, &rule);
   Order o = order_scalars(p->alpha);
   ContractArgs c{};
   c.row_off = P.row_off;
-  c.inc = P.inc;
-  c.ent_ray = P.ent_ray;
+  c.meta = P.inc_meta;
+  c.w = P.inc_w;
   c.ent_dof = P.ent_dof;
   c.ent_val = P.ent_val;
-  c.off = P.off;
-  c.vol = m->vol;
-  c.G = P.G;
   c.ndof = m->ndof;
   c.lda = lda;
-  c.nq = P.nq;
   c.chunk = (int)(m->ndof < 8192 ? (m->ndof > 0 ? m->ndof : 1) : 8192);
-  for (int q = 0; q < 11; q++) c.wq[q] = rule.w[q];
-  for (int i = 0; i < 3; i++) c.KC[i] = p->K[i] * o.c_alpha;
+  c.KC0 = p->K[0] * o.c_alpha;
+  c.KC1 = p->K[1] * o.c_alpha;
+  c.KC2 = p->K[2] * o.c_alpha;
   return c;
 }
 

@@ -51,6 +51,10 @@ struct Plan {
   double val_alpha = -1.0;    // order the values were computed for
   int64_t *row_off = nullptr; // n_dof + 1
   int64_t *inc = nullptr;     // n_ent: entry ids grouped by their dof
+  // per incidence (row order): {entry id, partner offset, partner length << 2 | axis,
+  // partner half-ray} and the quadrature weight w_g of its Gauss point
+  int4 *inc_meta = nullptr;
+  double *inc_w = nullptr;
   double *adj = nullptr;      // 4 n_half scratch for the adjoint dots
   int64_t pairs = 0;          // sum over (g, i) of |L| |R|
   int64_t max_ent = 0;        // largest entry count of one half-ray
@@ -90,6 +94,8 @@ struct fpde_mesh {
   double *vec = nullptr;          // 4 ndof FP64
   double *red = nullptr;          // reduction scratch
   int64_t red_n = 0;
+  void *linv = nullptr;           // inverses of the factor's 64 x 64 diagonal blocks
+  size_t linv_bytes = 0;
   fpde::StageTimer timer;
 };
 

@@ -430,6 +430,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   dfree(m->dof); dfree(m->vert_of_dof); dfree(m->rules); dfree(m->flag); dfree(m->flag_aux); dfree(m->vec); dfree(m->red);
   for (auto &P : m->plan) free_plan(P);
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
+  if (m->linv) (void)hipFree(m->linv);
   delete m;
 }
 

@@ -2,15 +2,21 @@
 // fractional stiffness matrix.
 //
 // Blocked right-looking Cholesky K = L L^T on a row-major matrix (lower
-// triangle), panel width NB = 64:
-//   potrf : the NB x NB diagonal block, factored in LDS by one workgroup;
-//   trsm  : the panel below it, X L_kk^T = B, one workgroup per 64-row strip;
-//   syrk  : the trailing lower triangle, C -= P P^T, one workgroup per
-//           64 x 64 output tile with an NB-deep inner product.
-// Triangular solves run block by block (diagonal block in LDS + a GEMV over
-// the remaining rows).  The same kernels are instantiated for FP32, which
-// the mixed-precision path factors and then refines against FP64 residuals
-// b - K u computed matrix-free from the FP64 derivative vectors.
+// triangle), panel width NB = 64, three launches per panel:
+//   diag  : one wavefront factors the 64 x 64 diagonal block with each lane
+//           holding one row in registers, then forms inv(L_kk) (lane j owns
+//           column j); both are written out;
+//   panel : X = B inv(L_kk)^T for every 64-row strip below (a plain GEMM,
+//           no sequential dependency), one workgroup per strip;
+//   syrk  : the trailing lower triangle, C -= X X^T, one workgroup per
+//           64 x 64 output tile.
+// Triangular solves use the stored inv(L_kk): one launch per block applies
+// the diagonal inverse and the off-diagonal update together (forward
+// x_k = inv(L_kk) y_k, y_below -= L_below,k x_k; backward
+// u_k = inv(L_kk)^T x_k, x_above -= L_k,above^T u_k).  The same kernels are
+// instantiated for FP32 storage, which the mixed-precision path factors and
+// then refines against FP64 residuals b - K u computed matrix-free from the
+// FP64 derivative vectors.
 #include <cmath>
 #include <vector>
 
@@ -24,118 +30,199 @@ int apply_scratch(fpde_mesh *m, Plan *P, double **d);
 
 constexpr int NB = 64;
 
+// inverse of the lower-triangular L held in LDS (rows >= nb are identity);
+// lane j builds column j of inv(L) in X by forward substitution (L reads
+// are broadcasts, X accesses are one column per lane) and stores it to Linv
+// (row-major 64 x 64).  One wavefront.
+template <class T>
+__device__ __forceinline__ void tri_inverse_to(const double (*Lsh)[NB + 1], double (*X)[NB + 1],
+                                               T *__restrict__ Linv) {
+  const int j = threadIdx.x;
+  for (int i = 0; i < NB; i++) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int k = j; k < i; k++) s = fma(-Lsh[i][k], X[k][j], s);
+    X[i][j] = (i < j) ? 0.0 : s / Lsh[i][i];
+  }
+  for (int i = 0; i < NB; i++) Linv[i * NB + j] = (T)X[i][j];
+}
+
+__device__ __forceinline__ double get44(const double (&a)[4][4], int i, int j) {
+  double v = 0.0;
+#pragma unroll
+  for (int ii = 0; ii < 4; ii++)
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++)
+      if (ii == i && jj == j) v = a[ii][jj];
+  return v;
+}
+__device__ __forceinline__ void set44(double (&a)[4][4], int i, int j, double v) {
+#pragma unroll
+  for (int ii = 0; ii < 4; ii++)
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++)
+      if (ii == i && jj == j) a[ii][jj] = v;
+}
+
+// Factor the 64 x 64 diagonal block at (k0, k0) and invert it.  256 threads
+// in a 16 x 16 grid, each holding a 4 x 4 register tile (rows 4ty.., columns
+// 4tx..).  Step c of the factorization: the owner of (c, c) takes the square
+// root, the owners of column c scale it and publish it in LDS, and every
+// thread applies the rank-1 update to its tile.  The inverse X = L^{-1} is
+// then built the same way (row c of X scaled by 1/l_cc, rows below updated),
+// with L read from LDS.  Rows/columns past the matrix end act as identity.
 template <class T>
 __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                    int32_t *flag, int64_t *aux) {
-  __shared__ T a[NB][NB + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
+                                                    T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
+  __shared__ double Lsh[NB][NB + 1];
+  __shared__ double colb[NB], rowb[NB];
+  __shared__ double piv_s;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-    const int r = idx / nb, c = idx % nb;
-    a[r][c] = A[(k0 + r) * lda + k0 + c];
-  }
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int c = 0; c < nb; c++) {
-    if (tid == 0) {
-      T piv = a[c][c];
-      if (!(piv > (T)0)) {
-        if (!bad) {
-          set_flag(flag, FPDE_ENOTSPD);
-          atomicCAS((unsigned long long *)aux, ~0ull, (unsigned long long)(k0 + c));
-        }
-        bad = 1;
-        piv = (T)1;
-      }
-      a[c][c] = sqrt(piv);
+  double a[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int r = 4 * ty + i, m = 4 * tx + j;
+      if (r < nb && m < nb) a[i][j] = (m <= r) ? (double)A[(k0 + r) * lda + k0 + m] : 0.0;
+      else a[i][j] = (r == m) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    const T d = a[c][c];
-    for (int r = c + 1 + tid; r < nb; r += blockDim.x) a[r][c] = a[r][c] / d;
-    __syncthreads();
-    const int w = nb - c - 1;
-    for (int idx = tid; idx < w * w; idx += blockDim.x) {
-      const int r = c + 1 + idx / w, mm = c + 1 + idx % w;
-      if (mm <= r) a[r][mm] -= a[r][c] * a[mm][c];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-    const int r = idx / nb, c = idx % nb;
-    if (c <= r) A[(k0 + r) * lda + k0 + c] = a[r][c];
-  }
-}
-
-// rows [k0+NB+64 b, ...) of columns [k0, k0+NB): X L_kk^T = B
-template <class T>
-__global__ void __launch_bounds__(256) k_trsm(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0) {
-  __shared__ T L[NB][NB + 1];
-  __shared__ T X[64][NB + 1];
-  const int tid = threadIdx.x;
-  const int64_t r0 = k0 + NB + 64 * (int64_t)blockIdx.x;
-  const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
-  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx % NB;
-    L[r][c] = (c <= r) ? A[(k0 + r) * lda + k0 + c] : (T)0;
-  }
-  for (int idx = tid; idx < rows * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx % NB;
-    X[r][c] = A[(r0 + r) * lda + k0 + c];
-  }
-  __syncthreads();
-  // 4 threads per row: each owns columns c = q (mod 4) of the partial sums
-  const int r = tid >> 2, q = tid & 3;
+  bool bad = false;
   for (int c = 0; c < NB; c++) {
-    if (r < rows && q == 0) X[r][c] = X[r][c] / L[c][c];
+    const int cb = c >> 2, ci = c & 3;
+    if (ty == cb && tx == cb) {
+      double v = get44(a, ci, ci);
+      if (!(v > 0.0)) {
+        bad = true;
+        v = 1.0;
+      }
+      v = sqrt(v);
+      set44(a, ci, ci, v);
+      piv_s = v;
+    }
     __syncthreads();
-    if (r < rows) {
-      const T xc = X[r][c];
-      for (int cc = c + 1 + q; cc < NB; cc += 4) X[r][cc] -= xc * L[cc][c];
+    if (tx == cb) {
+      const double d = piv_s;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = 4 * ty + i;
+        if (r > c) {
+          const double v = get44(a, i, ci) / d;
+          set44(a, i, ci, v);
+          colb[r] = v;
+        }
+      }
+    }
+    __syncthreads();
+    double lr[4], lm[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) lr[i] = colb[4 * ty + i];
+#pragma unroll
+    for (int j = 0; j < 4; j++) lm[j] = colb[4 * tx + j];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int r = 4 * ty + i, m = 4 * tx + j;
+        if (r > c && m > c && m <= r) a[i][j] = fma(-lr[i], lm[j], a[i][j]);
+      }
+  }
+  if (bad) {
+    set_flag(flag, FPDE_ENOTSPD);
+    atomicCAS((unsigned long long *)aux, ~0ull, (unsigned long long)k0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int r = 4 * ty + i, m = 4 * tx + j;
+      const double v = (m <= r) ? a[i][j] : 0.0;
+      Lsh[r][m] = v;
+      if (r < nb && m < nb && m <= r) A[(k0 + r) * lda + k0 + m] = (T)v;
+    }
+  // inverse: X = I, then row c /= l_cc and rows r > c -= l_rc X[c, :]
+  double x[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) x[i][j] = (4 * ty + i == 4 * tx + j) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c < NB; c++) {
+    const int cb = c >> 2, ci = c & 3;
+    if (ty == cb) {
+      const double dinv = 1.0 / Lsh[c][c];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const double v = get44(x, ci, j) * dinv;
+        set44(x, ci, j, v);
+        rowb[4 * tx + j] = v;
+      }
+    }
+    __syncthreads();
+    double xc[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) xc[j] = rowb[4 * tx + j];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int r = 4 * ty + i;
+      if (r > c) {
+        const double l = Lsh[r][c];
+#pragma unroll
+        for (int j = 0; j < 4; j++) x[i][j] = fma(-l, xc[j], x[i][j]);
+      }
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < rows * NB; idx += blockDim.x) {
-    const int rr = idx / NB, c = idx % NB;
-    A[(r0 + rr) * lda + k0 + c] = X[rr][c];
-  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) Linv[(4 * ty + i) * NB + 4 * tx + j] = (T)x[i][j];
 }
 
-// trailing update C[I,J] -= P_I P_J^T over lower tiles I >= J of the matrix
-// starting at row/column k0 + NB; P = columns [k0, k0+NB)
+// inv(L_kk) for every diagonal block of an existing factor (one wave per block)
 template <class T>
-__global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0) {
-  constexpr int KB = 32;
-  __shared__ T PI[64][KB + 1];
-  __shared__ T PJ[64][KB + 1];
-  const int64_t x = blockIdx.x;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= x) I++;
-  while (I * (I + 1) / 2 > x) I--;
-  const int64_t J = x - I * (I + 1) / 2;
-  const int64_t base = k0 + NB;
-  const int64_t ri = base + 64 * I, cj = base + 64 * J;
+__global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t lda, int64_t n, T *__restrict__ Linv) {
+  __shared__ double Lsh[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
+  const int64_t k0 = (int64_t)blockIdx.x * NB;
+  const int r = threadIdx.x;
+  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
+  for (int m = 0; m < NB; m++) {
+    double v;
+    if (r < nb) v = (m <= r && m < nb) ? (double)A[(k0 + r) * lda + k0 + m] : 0.0;
+    else v = (m == r) ? 1.0 : 0.0;
+    Lsh[r][m] = v;
+  }
+  __syncthreads();
+  tri_inverse_to<T>(Lsh, X, Linv + (int64_t)blockIdx.x * NB * NB);
+}
+
+// 64 x 64 tile product acc = P Q^T over a 64-deep inner dimension, P and Q
+// given as row pointers with leading dimensions; rows past `prow`/`qrow`
+// read as zero.  256 threads, 4 x 4 outputs each (rows ty + 16a, cols tx + 16b).
+template <class T>
+__device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
+                                        int64_t ldq, int qrow, T (*sP)[33], T (*sQ)[33], T acc[4][4]) {
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
-  T acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = (T)0;
-  for (int kk = 0; kk < NB; kk += KB) {
-    for (int idx = tid; idx < 64 * KB; idx += blockDim.x) {
-      const int r = idx / KB, c = idx % KB;
-      PI[r][c] = (ri + r < n) ? A[(ri + r) * lda + k0 + kk + c] : (T)0;
-      PJ[r][c] = (cj + r < n) ? A[(cj + r) * lda + k0 + kk + c] : (T)0;
+  for (int kk = 0; kk < NB; kk += 32) {
+    for (int idx = tid; idx < 64 * 32; idx += 256) {
+      const int rr = idx >> 5, c = idx & 31;
+      sP[rr][c] = (rr < prow) ? P[rr * ldp + kk + c] : (T)0;
+      sQ[rr][c] = (rr < qrow) ? Q[rr * ldq + kk + c] : (T)0;
     }
     __syncthreads();
 #pragma unroll 4
-    for (int k = 0; k < KB; k++) {
+    for (int k = 0; k < 32; k++) {
       T av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; a++) av[a] = PI[ty + 16 * a][k];
+      for (int a = 0; a < 4; a++) av[a] = sP[ty + 16 * a][k];
 #pragma unroll
-      for (int b = 0; b < 4; b++) bv[b] = PJ[tx + 16 * b][k];
+      for (int b = 0; b < 4; b++) bv[b] = sQ[tx + 16 * b][k];
 #pragma unroll
       for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -143,6 +230,44 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
     }
     __syncthreads();
   }
+}
+
+// panel: rows [k0+NB+64 b, +64) of columns [k0, k0+NB) become B inv(L_kk)^T
+template <class T>
+__global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
+                                               const T *__restrict__ Linv) {
+  __shared__ T sP[64][33], sQ[64][33];
+  const int64_t r0 = k0 + NB + 64 * (int64_t)blockIdx.x;
+  const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
+  T acc[4][4];
+  tile_nt<T>(A + r0 * lda + k0, lda, rows, Linv, NB, NB, sP, sQ, acc);
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    const int rr = ty + 16 * a;
+    if (rr >= rows) continue;
+#pragma unroll
+    for (int b = 0; b < 4; b++) A[(r0 + rr) * lda + k0 + tx + 16 * b] = acc[a][b];
+  }
+}
+
+// trailing update C[I,J] -= X_I X_J^T over lower tiles I >= J of the matrix
+// starting at row/column k0 + NB; X = columns [k0, k0+NB)
+template <class T>
+__global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0) {
+  __shared__ T sP[64][33], sQ[64][33];
+  const int64_t x = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= x) I++;
+  while (I * (I + 1) / 2 > x) I--;
+  const int64_t J = x - I * (I + 1) / 2;
+  const int64_t base = k0 + NB;
+  const int64_t ri = base + 64 * I, cj = base + 64 * J;
+  const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
+  const int qrow = (int)((n - cj) < 64 ? (n - cj) : 64);
+  T acc[4][4];
+  tile_nt<T>(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sP, sQ, acc);
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
 #pragma unroll
   for (int a = 0; a < 4; a++) {
     const int64_t r = ri + ty + 16 * a;
@@ -156,74 +281,59 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
   }
 }
 
-// forward: y[k0..k0+nb) solved with the diagonal block
+// forward block k: x_k = inv(L_kk) y_k (written by block 0), and
+// y[r] -= L[r, k-block] . x_k for the 64 rows r >= k0 + NB of this workgroup
 template <class T>
-__global__ void __launch_bounds__(64) k_trsv_lo_diag(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
-                                                     double *__restrict__ y) {
-  __shared__ double Ld[NB][NB + 1];
-  __shared__ double yy[NB];
+__global__ void __launch_bounds__(256) k_fwd_block(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
+                                                   const T *__restrict__ Linv, double *__restrict__ y,
+                                                   double *__restrict__ x) {
+  __shared__ double yk[NB], xk[NB];
   const int tid = threadIdx.x;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-    const int r = idx / nb, c = idx % nb;
-    Ld[r][c] = (c <= r) ? (double)L[(k0 + r) * lda + k0 + c] : 0.0;
-  }
-  if (tid < nb) yy[tid] = y[k0 + tid];
+  if (tid < NB) yk[tid] = (tid < nb) ? y[k0 + tid] : 0.0;
   __syncthreads();
-  for (int c = 0; c < nb; c++) {
-    if (tid == 0) yy[c] = yy[c] / Ld[c][c];
-    __syncthreads();
-    if (tid > c && tid < nb) yy[tid] -= Ld[tid][c] * yy[c];
-    __syncthreads();
+  if (tid < NB) {
+    double s = 0.0;
+    for (int m = 0; m < NB; m++) s = fma((double)Linv[tid * NB + m], yk[m], s);
+    xk[tid] = s;
+    if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = s;
   }
-  if (tid < nb) y[k0 + tid] = yy[tid];
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int64_t rbase = k0 + NB + 64 * (int64_t)blockIdx.x;
+  for (int q = w; q < 64; q += 4) {
+    const int64_t r = rbase + q;
+    if (r >= n) break;
+    double v = (double)L[r * lda + k0 + lane] * xk[lane];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) y[r] -= v;
+  }
 }
 
-// forward GEMV: rows r >= k0+NB: y[r] -= L[r, k0:k0+NB] . y[k0:k0+NB]; one wavefront per row
+// backward block k: u_k = inv(L_kk)^T x_k (written by block 0), and
+// x[r] -= sum_c L[k0+c][r] u_k[c] for rows r < k0 (256 per workgroup)
 template <class T>
-__global__ void __launch_bounds__(256) k_gemv_lo(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
-                                                 double *__restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int64_t r = k0 + NB + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= n) return;
-  double v = (double)L[r * lda + k0 + lane] * y[k0 + lane];
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if (lane == 0) y[r] -= v;
-}
-
-// backward: L_kk^T u_k = y_k
-template <class T>
-__global__ void __launch_bounds__(64) k_trsv_up_diag(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
-                                                     double *__restrict__ y) {
-  __shared__ double Ld[NB][NB + 1];
-  __shared__ double yy[NB];
+__global__ void __launch_bounds__(256) k_bwd_block(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
+                                                   const T *__restrict__ Linv, double *__restrict__ x,
+                                                   double *__restrict__ u) {
+  __shared__ double xk[NB], uk[NB];
   const int tid = threadIdx.x;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-    const int r = idx / nb, c = idx % nb;
-    Ld[r][c] = (c <= r) ? (double)L[(k0 + r) * lda + k0 + c] : 0.0;
-  }
-  if (tid < nb) yy[tid] = y[k0 + tid];
+  if (tid < NB) xk[tid] = (tid < nb) ? x[k0 + tid] : 0.0;
   __syncthreads();
-  for (int c = nb - 1; c >= 0; c--) {
-    if (tid == 0) yy[c] = yy[c] / Ld[c][c];
-    __syncthreads();
-    if (tid < c) yy[tid] -= Ld[c][tid] * yy[c];
-    __syncthreads();
+  if (tid < NB) {
+    double s = 0.0;
+    for (int m = 0; m < NB; m++) s = fma((double)Linv[m * NB + tid], xk[m], s);
+    uk[tid] = s;
+    if (blockIdx.x == 0 && tid < nb) u[k0 + tid] = s;
   }
-  if (tid < nb) y[k0 + tid] = yy[tid];
-}
-
-// backward GEMV: rows r < k0: y[r] -= sum_c L[k0+c][r] u[k0+c]
-template <class T>
-__global__ void __launch_bounds__(256) k_gemv_up(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
-                                                 double *__restrict__ y) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= k0) return;
-  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  double s = 0.0;
-  for (int c = 0; c < nb; c++) s += (double)L[(k0 + c) * lda + r] * y[k0 + c];
-  y[r] -= s;
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 256 + tid;
+  if (r < k0) {
+    double s = 0.0;
+    for (int c = 0; c < nb; c++) s = fma((double)L[(k0 + c) * lda + r], uk[c], s);
+    x[r] -= s;
+  }
 }
 
 __global__ void k_axpy_copy(double *__restrict__ u, const double *__restrict__ c, int64_t n) {
@@ -251,47 +361,58 @@ __global__ void __launch_bounds__(256) k_sumsq(const double *__restrict__ x, int
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-template <class T>
-static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
-  const long t = timer_begin(m, s);
-  struct End {
-    fpde_mesh *m;
-    long t;
-    hipStream_t s;
-    ~End() { timer_end(m, FPDE_STAGE_POTRF, t, s); }
-  } end{m, t, s};
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, k0, m->flag, m->flag_aux);
-    const int64_t rest = n - k0 - NB;
-    if (rest > 0) {
-      k_trsm<T><<<nblk(rest, 64), 256, 0, s>>>(A, lda, n, k0);
-      const int64_t Tn = (rest + 63) / 64;
-      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0);
-    }
+// device buffer for the inverses of the diagonal blocks (bytes, reused)
+static int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, void **out) {
+  const size_t need = (size_t)((n + NB - 1) / NB) * NB * NB * elem;
+  if (m->linv_bytes < need) {
+    if (m->linv) (void)hipFree(m->linv);
+    m->linv = nullptr;
+    m->linv_bytes = 0;
+    if (hipMalloc(&m->linv, need) != hipSuccess) return FPDE_ENOMEM;
+    m->linv_bytes = need;
   }
-  FPDE_HIP(hipGetLastError());
+  *out = m->linv;
   return FPDE_OK;
 }
 
 template <class T>
-static int trsv_pair(const T *L, int64_t lda, int64_t n, double *y, fpde_mesh *m, hipStream_t s) {
+static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
+  void *lv = nullptr;
+  FPDE_TRY(ensure_linv(m, n, sizeof(T), &lv));
+  T *Linv = (T *)lv;
   const long t = timer_begin(m, s);
-  struct End {
-    fpde_mesh *m;
-    long t;
-    hipStream_t s;
-    ~End() { timer_end(m, FPDE_STAGE_TRSV, t, s); }
-  } end{m, t, s};
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    k_trsv_lo_diag<T><<<1, 64, 0, s>>>(L, lda, n, k0, y);
+    T *Lk = Linv + (k0 / NB) * NB * NB;
+    k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, k0, Lk, m->flag, m->flag_aux);
     const int64_t rest = n - k0 - NB;
-    if (rest > 0) k_gemv_lo<T><<<nblk(rest, 4), 256, 0, s>>>(L, lda, n, k0, y);
+    if (rest > 0) {
+      k_panel<T><<<nblk(rest, 64), 256, 0, s>>>(A, lda, n, k0, Lk);
+      const int64_t Tn = (rest + 63) / 64;
+      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0);
+    }
+  }
+  timer_end(m, FPDE_STAGE_POTRF, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+// y (n) holds the right-hand side on entry and the solution on exit;
+// x (n) is scratch
+template <class T>
+static int trsv_pair(const T *L, int64_t lda, int64_t n, const T *Linv, double *y, double *x, fpde_mesh *m,
+                     hipStream_t s) {
+  const long t = timer_begin(m, s);
+  for (int64_t k0 = 0; k0 < n; k0 += NB) {
+    const int64_t rest = n - k0 - NB;
+    const unsigned g = rest > 0 ? nblk(rest, 64) : 1;
+    k_fwd_block<T><<<g, 256, 0, s>>>(L, lda, n, k0, Linv + (k0 / NB) * NB * NB, y, x);
   }
   const int64_t last = ((n - 1) / NB) * NB;
   for (int64_t k0 = last; k0 >= 0; k0 -= NB) {
-    k_trsv_up_diag<T><<<1, 64, 0, s>>>(L, lda, n, k0, y);
-    if (k0 > 0) k_gemv_up<T><<<nblk(k0), 256, 0, s>>>(L, lda, n, k0, y);
+    const unsigned g = k0 > 0 ? nblk(k0, 256) : 1;
+    k_bwd_block<T><<<g, 256, 0, s>>>(L, lda, n, k0, Linv + (k0 / NB) * NB * NB, x, y);
   }
+  timer_end(m, FPDE_STAGE_TRSV, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }
@@ -317,8 +438,9 @@ static int norm2(fpde_mesh *m, const double *x, double *out, hipStream_t s) {
   return FPDE_OK;
 }
 
-static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, int64_t lda, const double *b,
-                             double *u, fpde_solve_info *info, hipStream_t s) {
+// Linv must hold the inverses of L's diagonal blocks
+static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, int64_t lda, const void *Linv,
+                             const double *b, double *u, fpde_solve_info *info, hipStream_t s) {
   const int64_t n = m->ndof;
   if (info) {
     info->ir_iters = 0;
@@ -327,11 +449,11 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
   }
   if (n == 0) return FPDE_OK;
   FPDE_TRY(ensure_vec(m));
+  double *y = m->vec, *r = m->vec + n, *bb = m->vec + 2 * n, *xs = m->vec + 3 * n;
   if (p->precision == FPDE_FP64) {
     if (u != b) FPDE_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    FPDE_TRY(trsv_pair<double>((const double *)L, lda, n, u, m, s));
+    FPDE_TRY(trsv_pair<double>((const double *)L, lda, n, (const double *)Linv, u, xs, m, s));
     if (info) {
-      double *y = m->vec, *r = m->vec + n;
       Plan *P = nullptr;
       FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
       FPDE_TRY(ensure_values(m, P, p->alpha, s));
@@ -349,10 +471,9 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
   // mixed: FP32 factor, FP64 residuals from the matrix-free product
   const double tol = p->ir_tol > 0 ? p->ir_tol : 1e-8;
   const int maxit = p->ir_max_iter > 0 ? p->ir_max_iter : 30;
-  double *y = m->vec, *r = m->vec + n, *bb = m->vec + 2 * n;
   FPDE_HIP(hipMemcpyAsync(bb, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   FPDE_HIP(hipMemcpyAsync(u, bb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, u, m, s));
+  FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, (const float *)Linv, u, xs, m, s));
   Plan *P = nullptr;
   FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
   FPDE_TRY(ensure_values(m, P, p->alpha, s));
@@ -369,7 +490,7 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
     FPDE_TRY(norm2(m, r, &rn, s));
     rel = bn > 0 ? rn / bn : rn;
     if (rel <= tol || it >= maxit) break;
-    FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, r, m, s));
+    FPDE_TRY(trsv_pair<float>((const float *)L, lda, n, (const float *)Linv, r, xs, m, s));
     k_axpy_copy<<<nblk(n), 256, 0, s>>>(u, r, n);
     it++;
   }
@@ -406,12 +527,24 @@ extern "C" int fpde_solve(fpde_mesh *m, const fpde_params *p, void *A, int64_t l
     }
     return f < 0 ? f : FPDE_EHIP;
   }
-  return solve_with_factor(m, p, A, lda, b, u, info, s);
+  return solve_with_factor(m, p, A, lda, m->linv, b, u, info, s);
 }
 
 extern "C" int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const void *L, int64_t lda, const double *b,
                                    double *u, fpde_solve_info *info, void *stream) {
   FPDE_TRY(check_params(m, p));
   if (!L || !b || !u || lda < m->ndof) return FPDE_EINVAL;
-  return solve_with_factor(m, p, L, lda, b, u, info, S(stream));
+  hipStream_t s = S(stream);
+  const int64_t n = m->ndof;
+  if (n == 0) return solve_with_factor(m, p, L, lda, nullptr, b, u, info, s);
+  void *lv = nullptr;
+  const size_t elem = p->precision == FPDE_MIXED ? sizeof(float) : sizeof(double);
+  FPDE_TRY(ensure_linv(m, n, elem, &lv));
+  const unsigned nbk = (unsigned)((n + NB - 1) / NB);
+  if (p->precision == FPDE_MIXED)
+    k_trinv<float><<<nbk, 64, 0, s>>>((const float *)L, lda, n, (float *)lv);
+  else
+    k_trinv<double><<<nbk, 64, 0, s>>>((const double *)L, lda, n, (double *)lv);
+  FPDE_HIP(hipGetLastError());
+  return solve_with_factor(m, p, L, lda, lv, b, u, info, s);
 }

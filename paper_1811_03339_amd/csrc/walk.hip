@@ -351,6 +351,24 @@ __global__ void k_row_fill(const int32_t *__restrict__ ent_dof, int64_t n, int64
   }
 }
 
+// flattened per-incidence data for the accumulation (see Plan::inc_meta)
+__global__ void k_inc_meta(const int64_t *__restrict__ inc, const int32_t *__restrict__ ent_ray,
+                           const int64_t *__restrict__ off, const double *__restrict__ vol,
+                           const double *__restrict__ wq, int64_t G, int nq, int64_t n, int4 *__restrict__ meta,
+                           double *__restrict__ w) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t e = inc[p];
+  const int64_t h = ent_ray[e];
+  const int dir = (int)(h / G);
+  const int64_t g = h - (int64_t)dir * G;
+  const int64_t partner = (dir & 1) ? h - G : h + G;
+  const int64_t po = off[partner];
+  const int64_t pl = off[partner + 1] - po;
+  meta[p] = make_int4((int)e, (int)po, (int)((pl << 2) | (dir >> 1)), (int)partner);
+  w[p] = wq[g % nq] * vol[g / nq];
+}
+
 __global__ void k_i32_to_i64(const int32_t *__restrict__ a, int64_t n, int64_t *__restrict__ b) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) b[k] = a[k];
@@ -382,7 +400,7 @@ static void launch_walk(const WalkArgs &a, hipStream_t s) {
 
 void free_plan(Plan &P) {
   dfree(P.off); dfree(P.ent_dof); dfree(P.ent_ray); dfree(P.ent_val); dfree(P.row_off); dfree(P.inc);
-  dfree(P.adj);
+  dfree(P.adj); dfree(P.inc_meta); dfree(P.inc_w);
   P = Plan();
 }
 
@@ -428,6 +446,7 @@ static int build_plan(fpde_mesh *m, Plan &P, int nq, int max_steps, hipStream_t 
   int f = take_flag(m, s);
   if (f != 0) return fail(f < 0 ? f : FPDE_EHIP);
 
+  if (P.n_ent >= (int64_t(1) << 31)) return fail(FPDE_EUNSUPPORTED);  // 32-bit entry ids below
   if ((st = dalloc(&P.ent_dof, P.n_ent)) != FPDE_OK) return fail(st);
   if ((st = dalloc(&P.ent_ray, P.n_ent)) != FPDE_OK) return fail(st);
   if ((st = dalloc(&P.ent_val, P.n_ent)) != FPDE_OK) return fail(st);
@@ -448,6 +467,12 @@ static int build_plan(fpde_mesh *m, Plan &P, int nq, int max_steps, hipStream_t 
       hipSuccess)
     return fail(FPDE_EHIP);
   if (P.n_ent > 0) k_row_fill<<<nblk(P.n_ent), 256, 0, s>>>(P.ent_dof, P.n_ent, cursor, P.inc);
+  if ((st = dalloc(&P.inc_meta, P.n_ent)) != FPDE_OK) return fail(st);
+  if ((st = dalloc(&P.inc_w, P.n_ent)) != FPDE_OK) return fail(st);
+  if (P.n_ent > 0)
+    k_inc_meta<<<nblk(P.n_ent), 256, 0, s>>>(P.inc, P.ent_ray, P.off, m->vol,
+                                             m->rules + rule_offset(nq) + 4 * nq, P.G, nq, P.n_ent,
+                                             P.inc_meta, P.inc_w);
   if (hipGetLastError() != hipSuccess) return fail(FPDE_EHIP);
   f = take_flag(m, s);
   if (f != 0) return fail(f < 0 ? f : FPDE_EHIP);
