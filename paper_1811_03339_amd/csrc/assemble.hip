@@ -60,18 +60,39 @@ __global__ void __launch_bounds__(256) k_contract_rows(ContractArgs c, TO *__res
           coef = c.w[p] * c.KC(mt.z & 3) * c.ent_val[mt.x];
         }
         const int nv = (int)((p1 - pb) < 64 ? (p1 - pb) : 64);
+        // software pipeline over incidence pairs: the first 32 entries of the
+        // next pair are loaded before the current pair's LDS adds.  Every
+        // lane joins each shuffle (a lane masked off by a condition would not
+        // deliver its value to the lanes reading from it).
+        int spo = __shfl(po, half, 64);
+        int spl = __shfl(pl, half, 64);
+        double scf = __shfl(coef, half, 64);
+        if (half >= nv) spl = 0;
+        int dq = sub < spl ? c.ent_dof[spo + sub] : 0;
+        double vq = sub < spl ? c.ent_val[spo + sub] : 0.0;
         for (int t = 0; t < nv; t += 2) {
-          // every lane joins each shuffle: a lane masked off by a condition
-          // would not deliver its value to the lanes reading from it
-          const int src = t + half;
-          const int spo = __shfl(po, src, 64);
-          const int spl_all = __shfl(pl, src, 64);
-          const double scf = __shfl(coef, src, 64);
-          const int spl = (src < nv) ? spl_all : 0;
-          for (int k = sub; k < spl; k += 32) {
-            const int64_t d = (int64_t)c.ent_dof[spo + k] - c0;
-            if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf * c.ent_val[spo + k]);
+          const int src = (t + 2 + half) & 63;
+          const int npo = __shfl(po, src, 64);
+          int npl = __shfl(pl, src, 64);
+          const double ncf = __shfl(coef, src, 64);
+          if (t + 2 + half >= nv) npl = 0;
+          const int ndq = sub < npl ? c.ent_dof[npo + sub] : 0;
+          const double nvq = sub < npl ? c.ent_val[npo + sub] : 0.0;
+          if (sub < spl) {
+            const int64_t d = (int64_t)dq - c0;
+            if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf * vq);
           }
+          for (int k = sub + 32; k < spl; k += 32) {  // long partner vectors
+            const int dk = c.ent_dof[spo + k];
+            const double vk = c.ent_val[spo + k];
+            const int64_t d = (int64_t)dk - c0;
+            if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf * vk);
+          }
+          spo = npo;
+          spl = npl;
+          scf = ncf;
+          dq = ndq;
+          vq = nvq;
         }
       }
       __syncthreads();

@@ -65,17 +65,17 @@ __device__ __forceinline__ void set44(double (&a)[4][4], int i, int j, double v)
 
 // Factor the 64 x 64 diagonal block at (k0, k0) and invert it.  256 threads
 // in a 16 x 16 grid, each holding a 4 x 4 register tile (rows 4ty.., columns
-// 4tx..).  Step c of the factorization: the owner of (c, c) takes the square
-// root, the owners of column c scale it and publish it in LDS, and every
-// thread applies the rank-1 update to its tile.  The inverse X = L^{-1} is
-// then built the same way (row c of X scaled by 1/l_cc, rows below updated),
-// with L read from LDS.  Rows/columns past the matrix end act as identity.
+// 4tx..).  The factorization walks 4-column strips: the strip is factored by
+// one wavefront (lane = row, pivots and multipliers exchanged by shuffles),
+// then every thread applies the rank-4 update to its tile.  The inverse
+// X = L^{-1} proceeds by 4-row blocks in the same way, with L read from LDS.
+// Rows/columns past the matrix end act as identity.
 template <class T>
 __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                                     T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
   __shared__ double Lsh[NB][NB + 1];
-  __shared__ double colb[NB], rowb[NB];
-  __shared__ double piv_s;
+  __shared__ double S[NB][5];
+  __shared__ double rowb4[4][NB];
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
   double a[4][4];
@@ -88,44 +88,67 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
       else a[i][j] = (r == m) ? 1.0 : 0.0;
     }
   bool bad = false;
-  for (int c = 0; c < NB; c++) {
-    const int cb = c >> 2, ci = c & 3;
-    if (ty == cb && tx == cb) {
-      double v = get44(a, ci, ci);
-      if (!(v > 0.0)) {
-        bad = true;
-        v = 1.0;
+  // 4-column strips: the strip's owners publish it, wavefront 0 factors it
+  // (lane r = row r, pivots and multipliers exchanged by shuffles), then
+  // every thread applies the rank-4 update to its tile
+  for (int cb = 0; cb < 16; cb++) {
+    if (tx == cb) {
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) S[4 * ty + i][j] = a[i][j];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int r = tid;
+      double s4[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) s4[j] = S[r][j];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int c = 4 * cb + j;
+        const double piv = __shfl(s4[j], c, 64);
+        const bool ok = piv > 0.0;
+        if (r == c && !ok) bad = true;
+        const double d = sqrt(ok ? piv : 1.0);
+        if (r == c) s4[j] = d;
+        else if (r > c) s4[j] = s4[j] / d;
+#pragma unroll
+        for (int jj = j + 1; jj < 4; jj++) {
+          const double lc = __shfl(s4[j], 4 * cb + jj, 64);
+          if (r >= 4 * cb + jj) s4[jj] = fma(-s4[j], lc, s4[jj]);
+        }
       }
-      v = sqrt(v);
-      set44(a, ci, ci, v);
-      piv_s = v;
+#pragma unroll
+      for (int j = 0; j < 4; j++) S[r][j] = s4[j];
     }
     __syncthreads();
     if (tx == cb) {
-      const double d = piv_s;
+      if (ty >= cb) {
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int r = 4 * ty + i;
-        if (r > c) {
-          const double v = get44(a, i, ci) / d;
-          set44(a, i, ci, v);
-          colb[r] = v;
-        }
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) a[i][j] = S[4 * ty + i][j];
       }
+    } else if (tx > cb && ty >= tx) {
+      double lr[4][4], lm[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          lr[i][k] = S[4 * ty + i][k];
+          lm[i][k] = S[4 * tx + i][k];
+        }
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          if (ty == tx && j > i) continue;  // upper part of a diagonal tile
+#pragma unroll
+          for (int k = 0; k < 4; k++) a[i][j] = fma(-lr[i][k], lm[j][k], a[i][j]);
+        }
     }
     __syncthreads();
-    double lr[4], lm[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) lr[i] = colb[4 * ty + i];
-#pragma unroll
-    for (int j = 0; j < 4; j++) lm[j] = colb[4 * tx + j];
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int r = 4 * ty + i, m = 4 * tx + j;
-        if (r > c && m > c && m <= r) a[i][j] = fma(-lr[i], lm[j], a[i][j]);
-      }
   }
   if (bad) {
     set_flag(flag, FPDE_ENOTSPD);
@@ -147,29 +170,45 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
 #pragma unroll
     for (int j = 0; j < 4; j++) x[i][j] = (4 * ty + i == 4 * tx + j) ? 1.0 : 0.0;
   __syncthreads();
-  for (int c = 0; c < NB; c++) {
-    const int cb = c >> 2, ci = c & 3;
-    if (ty == cb) {
-      const double dinv = 1.0 / Lsh[c][c];
+  // blocks of 4 rows: the owners of rows 4cb..4cb+3 finish them with the
+  // 4 x 4 diagonal block of L (inside one thread's tile), publish them, and
+  // the rows below subtract L[r, 4cb..4cb+3] X[4cb..4cb+3, :]
+  for (int cb = 0; cb < 16; cb++) {
+    if (ty == cb && tx <= cb) {  // X is lower triangular: columns beyond stay 0
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const double v = get44(x, ci, j) * dinv;
-        set44(x, ci, j, v);
-        rowb[4 * tx + j] = v;
+      for (int i = 0; i < 4; i++) {
+        const int c = 4 * cb + i;
+#pragma unroll
+        for (int k = 0; k < i; k++) {
+          const double l = Lsh[c][4 * cb + k];
+#pragma unroll
+          for (int j = 0; j < 4; j++) x[i][j] = fma(-l, x[k][j], x[i][j]);
+        }
+        const double dinv = 1.0 / Lsh[c][c];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          x[i][j] = x[i][j] * dinv;
+          rowb4[i][4 * tx + j] = x[i][j];
+        }
       }
     }
     __syncthreads();
-    double xc[4];
+    if (ty > cb && tx <= cb) {
+      double xr[4][4], l[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) xc[j] = rowb[4 * tx + j];
+      for (int k = 0; k < 4; k++)
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int r = 4 * ty + i;
-      if (r > c) {
-        const double l = Lsh[r][c];
+        for (int j = 0; j < 4; j++) xr[k][j] = rowb4[k][4 * tx + j];
 #pragma unroll
-        for (int j = 0; j < 4; j++) x[i][j] = fma(-l, xc[j], x[i][j]);
-      }
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) l[i][k] = Lsh[4 * ty + i][4 * cb + k];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) x[i][j] = fma(-l[i][k], xr[k][j], x[i][j]);
     }
     __syncthreads();
   }
