@@ -30,7 +30,8 @@
  *     the adjoint derivatives with respect to the order and the coefficients.
  *
  * Readings where the paper is silent (each one is stated where it is used):
- *   - zero component of a volume coordinate: |k| <= 1e-12;
+ *   - zero component of a volume coordinate: |k| <= 1e-12 max(1, |b~|, |r d~|),
+ *     and the coordinate that set r_max is always zero;
  *   - several elements share the go-out edge/vertex: take the one with the
  *     smallest id among those in which the ray advances (relative 1e-12);
  *   - the ray origin u0 stays the Gauss point for every element it crosses.
@@ -281,7 +282,22 @@ typedef struct {
   double bt[4], dt[4];
   double r_min, r_max;
   double kmax[4];
+  int jexit;        /* coordinate whose ratio set r_max (first one on ties) */
 } orc_isect;
+
+/* Zero test on the volume coordinate k~_j at the go-out point: |k~_j| is
+   compared with 1e-12 times the size of the terms b~_j and r_max d~_j it is
+   the difference of (at least 1e-12), because for elements far from the ray
+   origin or badly shaped the rounding error of b~ + r d~ grows with them.
+   The coordinate that set r_max is zero by construction. */
+static int orc_is_zero(const orc_isect *o, int j) {
+  if (j == o->jexit) return 1;
+  double s = fabs(o->bt[j]);
+  double t = fabs(o->r_max * o->dt[j]);
+  if (t > s) s = t;
+  if (s < 1.0) s = 1.0;
+  return fabs(o->kmax[j]) <= ORC_EPS_BARY * s;
+}
 
 static void orc_intersect(const orc_mesh *m, int64_t t, const double *u0, int i, int s, orc_isect *o) {
   const double *Mt = m->M + 9 * t;
@@ -296,10 +312,14 @@ static void orc_intersect(const orc_mesh *m, int64_t t, const double *u0, int i,
   /* eq:cond: r >= 0 and b~_j + r d~_j >= 0 for every j */
   o->r_max = INFINITY;
   o->r_min = 0.0;
+  o->jexit = -1;
   for (int j = 0; j < 4; j++) {
     if (o->dt[j] < 0.0) {
       double r = -o->bt[j] / o->dt[j];
-      if (r < o->r_max) o->r_max = r;
+      if (r < o->r_max) {
+        o->r_max = r;
+        o->jexit = j;
+      }
     } else if (o->dt[j] > 0.0) {
       double r = -o->bt[j] / o->dt[j];
       if (r > o->r_min) o->r_min = r;
@@ -321,7 +341,7 @@ int orc_exit_pattern(const orc_mesh *m, int64_t t, const double *u0, int i, int 
   int z = 0;
   for (int j = 0; j < 4; j++) {
     kmax[j] = o.kmax[j];
-    if (fabs(o.kmax[j]) <= ORC_EPS_BARY) z |= 1 << j;
+    if (orc_is_zero(&o, j)) z |= 1 << j;
   }
   rminmax[0] = o.r_min;
   rminmax[1] = o.r_max;
@@ -352,7 +372,7 @@ int orc_walk(const orc_mesh *m, int64_t t0, const double *u0, int i, int s, int 
       r_cur = o.r_max;
     }
     int Z[4], nz = 0;
-    for (int j = 0; j < 4; j++) if (fabs(o.kmax[j]) <= ORC_EPS_BARY) Z[nz++] = j;
+    for (int j = 0; j < 4; j++) if (orc_is_zero(&o, j)) Z[nz++] = j;
     if (nz == 0) return ORC_EPATH;
     if (nz == 1) {
       int32_t nx = m->nbr[4 * t + Z[0]];

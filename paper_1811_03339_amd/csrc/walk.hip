@@ -68,6 +68,7 @@ struct WalkArgs {
 struct Isect {
   double bt[4], dt[4];
   double r_max;
+  int jexit;  // coordinate whose ratio set r_max (first one on ties)
 };
 
 // entry (r, i) of A^{-1} with a lane-varying axis i, without indexing the
@@ -90,14 +91,19 @@ __device__ __forceinline__ void isect(const TetRec &R, const double *u0, int i, 
   o.bt[0] = 1.0 - ((o.bt[1] + o.bt[2]) + o.bt[3]);
   o.dt[0] = -((o.dt[1] + o.dt[2]) + o.dt[3]);
   double rm = INFINITY;
+  int je = -1;
 #pragma unroll
   for (int j = 0; j < 4; j++) {
     if (o.dt[j] < 0.0) {
       const double r = -o.bt[j] / o.dt[j];
-      rm = (r < rm) ? r : rm;
+      if (r < rm) {
+        rm = r;
+        je = j;
+      }
     }
   }
   o.r_max = rm;
+  o.jexit = je;
 }
 
 __device__ __forceinline__ TetRec load_rec(const TetRec *rec, int64_t t) {
@@ -253,13 +259,19 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
       nseg++;
       r_cur = o.r_max;
     }
-    // zero pattern of the volume coordinates at the go-out point
+    // zero pattern of the volume coordinates at the go-out point: |k_j| is
+    // compared with 1e-12 times the size of the two terms it is the
+    // difference of (at least 1e-12); the coordinate that set r_max is zero
+    // by construction
     int zmask = 0, nz = 0, zf = -1;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const double p = o.r_max * o.dt[j];
       const double kj = o.bt[j] + p;
-      if (fabs(kj) <= 1e-12) {
+      double sc = fabs(o.bt[j]);
+      sc = fabs(p) > sc ? fabs(p) : sc;
+      sc = sc < 1.0 ? 1.0 : sc;
+      if (j == o.jexit || fabs(kj) <= 1e-12 * sc) {
         zmask |= 1 << j;
         nz++;
         zf = j;

@@ -1,0 +1,183 @@
+"""Full-size cases on the GPU, checked on outputs the oracle can afford.
+
+* sphere150k (~152k elements, ~25k unknowns, 11-point rule, alpha = 1.7):
+  sampled paths bit-exact, sampled derivative vectors, K x against the
+  oracle's matrix-free product, FP64 and mixed solutions (mixed within 1e-6
+  of FP64 after refinement to 1e-8).
+* ball40k (~42k elements, ~6.6k unknowns, 4-point rule): adjoint gradients of
+  ||u - u_obs||^2 at alpha = 1.4, K = (1,1,1) against the oracle's adjoint and
+  central differences (h = 1e-6); u_obs from alpha = 1.6, K = (1.2, 0.8, 1.0)
+  plus N(0, 1e-3^2) noise (seed 40).
+* ellipsoid400k (~400k elements, ~67k unknowns, 11-point rule,
+  alpha = 1.3): mixed precision with an FP32 matrix of ~18 GB; sampled paths
+  and derivative vectors against the oracle, K x (FP32, dense) against the
+  FP64 matrix-free product, refinement to 1e-8.
+"""
+import gc
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1811_03339_amd as F
+from fpde_inputs import workload_mesh
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def sampled_paths_and_values(om, gm, nq, alpha, G, rng, n_ranges=2, span=200, n_val=40):
+    for d in range(6):
+        for g0 in rng.integers(0, G - span, size=n_ranges):
+            g0 = int(g0)
+            ln, hs, _, _ = gm.paths(nq, d, g0, span)
+            ln_o, hs_o = om.paths(nq, g0 * 6, span * 6)
+            assert np.array_equal(ln.cpu().numpy(), ln_o.reshape(span, 6)[:, d])
+            assert np.array_equal(hs.cpu().numpy().view(np.uint64), hs_o.reshape(span, 6)[:, d])
+        g0 = int(rng.integers(0, G - n_val))
+        off, dof, val = gm.ray_values(nq, alpha, d, g0, n_val)
+        i, side = divmod(d, 2)
+        for k in range(n_val):
+            got = {}
+            for a, v in zip(dof[off[k]:off[k + 1]], val[off[k]:off[k + 1]]):
+                got[int(a)] = got.get(int(a), 0.0) + float(v)
+            ids, vals = om.ray_values(nq, g0 + k, i, side, alpha)
+            assert set(got) == set(ids.tolist())
+            scale = np.abs(vals).max()
+            for a, v in zip(ids, vals):
+                assert abs(got[int(a)] - v) <= 1e-10 * scale
+
+
+def timed(fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def test_sphere150k_fp64_and_mixed():
+    m = workload_mesh("sphere150k")
+    log(f"[sphere150k] {m.n_vert} vertices, {m.n_tet} elements")
+    om = oracle.OracleMesh(m.xyz, m.tet)
+    gm = F.Mesh(m.xyz, m.tet)
+    n, nq, alpha, K = gm.n_dof, 11, 1.7, (1.0, 1.0, 1.0)
+    rng = np.random.default_rng(150)
+    sampled_paths_and_values(om, gm, nq, alpha, m.n_tet * nq, rng)
+    log("[sphere150k] sampled paths and derivative vectors match")
+    p64 = F.params(alpha, K, quad_points=nq)
+    _, t_plan = timed(lambda: gm.plan(nq))
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    _, t_asm = timed(lambda: gm.assemble(p64, A, b))
+    x = torch.tensor(rng.normal(size=n), device="cuda")
+    Ax = (A @ x).cpu().numpy()
+    y_o = om.apply(nq, alpha, K, x.cpu().numpy())
+    assert rel(Ax, y_o) <= 1e-10
+    assert rel(b.cpu().numpy(), om.load(nq)) <= 1e-10
+    u64 = torch.empty_like(b)
+    info, t_sol = timed(lambda: gm.solve(p64, A, b, u64))
+    assert info.final_rel_residual <= 1e-12
+    log(f"[sphere150k] n={n} plan {t_plan:.2f}s FP64 assemble {t_asm:.3f}s solve {t_sol:.3f}s")
+    del A
+    gc.collect()
+    torch.cuda.empty_cache()
+    pmx = F.params(alpha, K, quad_points=nq, precision=F.FPDE_MIXED, ir_tol=1e-8)
+    A32 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    u32 = torch.empty_like(b)
+    _, t_asm32 = timed(lambda: gm.assemble(pmx, A32, b))
+    info32, t_sol32 = timed(lambda: gm.solve(pmx, A32, b, u32))
+    assert info32.final_rel_residual <= 1e-8
+    err = float((u32 - u64).abs().max() / u64.abs().max())
+    assert err <= 1e-6
+    log(f"[sphere150k] mixed assemble {t_asm32:.3f}s solve {t_sol32:.3f}s ir_iters {info32.ir_iters} "
+        f"rel err vs FP64 {err:.2e} speedup {(t_asm + t_sol) / (t_asm32 + t_sol32):.2f}x")
+    del A32, gm
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_ball40k_adjoint():
+    m = workload_mesh("ball40k")
+    log(f"[ball40k] {m.n_vert} vertices, {m.n_tet} elements")
+    om = oracle.OracleMesh(m.xyz, m.tet)
+    gm = F.Mesh(m.xyz, m.tet)
+    nq = 4
+    alpha, K = 1.4, np.array([1.0, 1.0, 1.0])
+    b_o = om.load(nq)
+    rng = np.random.default_rng(40)
+    u_obs = oracle.solve_spd(om.assemble(nq, 1.6, (1.2, 0.8, 1.0)), b_o)
+    u_obs = u_obs + 1e-3 * rng.normal(size=om.ndof)
+    A_o = om.assemble(nq, alpha, K)
+    u_o = oracle.solve_spd(A_o, b_o)
+    ga_o, gk_o = om.gradient(nq, alpha, K, u_o, 2 * (u_o - u_obs), A=A_o)
+    a_t = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    k_t = torch.tensor(K, dtype=torch.float64, requires_grad=True)
+    obs = torch.tensor(u_obs, device="cuda")
+
+    def fwd_bwd():
+        u = F.FracSolve.apply(a_t, k_t, gm, nq)
+        J = torch.sum((u - obs) ** 2)
+        J.backward()
+        return u
+
+    u, t = timed(fwd_bwd)
+    assert rel(u.detach().cpu().numpy(), u_o) <= 1e-10
+    assert abs(a_t.grad.item() - ga_o) <= 1e-10 * abs(ga_o)
+    assert rel(k_t.grad.numpy(), gk_o) <= 1e-10
+
+    def loss(a, k):
+        uu, _, _ = F.solve_problem(gm, F.params(a, k, quad_points=nq), info=False)
+        return float(torch.sum((uu - obs) ** 2))
+
+    h = 1e-6
+    fd_a = (loss(alpha + h, K) - loss(alpha - h, K)) / (2 * h)
+    assert abs(a_t.grad.item() - fd_a) <= 1e-6 * abs(fd_a)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fd = (loss(alpha, K + e) - loss(alpha, K - e)) / (2 * h)
+        assert abs(k_t.grad[i].item() - fd) <= 1e-6 * abs(fd)
+    log(f"[ball40k] n={gm.n_dof} forward+backward {t:.3f}s dJ/dalpha {a_t.grad.item():.6e} "
+        f"(oracle {ga_o:.6e}, FD {fd_a:.6e})")
+
+
+def test_ellipsoid400k_mixed():
+    t0 = time.perf_counter()
+    m = workload_mesh("ellipsoid400k")
+    log(f"[ellipsoid400k] {m.n_vert} vertices, {m.n_tet} elements ({time.perf_counter() - t0:.0f}s)")
+    om = oracle.OracleMesh(m.xyz, m.tet)
+    gm = F.Mesh(m.xyz, m.tet)
+    n, nq, alpha, K = gm.n_dof, 11, 1.3, (1.0, 1.0, 1.0)
+    rng = np.random.default_rng(400)
+    sampled_paths_and_values(om, gm, nq, alpha, m.n_tet * nq, rng, n_ranges=1, span=100, n_val=20)
+    log("[ellipsoid400k] sampled paths and derivative vectors match")
+    _, t_plan = timed(lambda: gm.plan(nq))
+    info = gm.plan_info(nq)
+    log(f"[ellipsoid400k] plan {t_plan:.2f}s {info}")
+    pmx = F.params(alpha, K, quad_points=nq, precision=F.FPDE_MIXED, ir_tol=1e-8)
+    A32 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    _, t_asm = timed(lambda: gm.assemble(pmx, A32, b))
+    x = torch.tensor(rng.normal(size=n), device="cuda")
+    Ax32 = (A32 @ x.float()).double()
+    y = torch.empty_like(x)
+    gm.apply(pmx, x, y)
+    assert float((Ax32 - y).abs().max() / y.abs().max()) <= 1e-5
+    u = torch.empty_like(b)
+    info32, t_sol = timed(lambda: gm.solve(pmx, A32, b, u))
+    assert info32.final_rel_residual <= 1e-8
+    log(f"[ellipsoid400k] n={n} FP32 matrix {n * n * 4 / 2**30:.1f} GiB, assemble {t_asm:.2f}s, "
+        f"solve {t_sol:.2f}s, ir_iters {info32.ir_iters}, residual {info32.final_rel_residual:.2e}")
+    del A32, gm
+    gc.collect()
+    torch.cuda.empty_cache()
