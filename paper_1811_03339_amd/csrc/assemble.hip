@@ -43,7 +43,14 @@ __global__ void __launch_bounds__(256) k_contract_rows(ContractArgs c, TO *__res
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, sub = lane & 31;
-  for (int64_t row = blockIdx.x; row < c.ndof; row += gridDim.x) {
+  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+  // contiguous range of (Morton-ordered) rows so that rows sharing partner
+  // vectors share that XCD's L2.
+  const int64_t per_xcd = (c.ndof + 7) / 8;
+  const int64_t slots = 8 * per_xcd;
+  for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
+    const int64_t row = (b % 8) * per_xcd + b / 8;
+    if (row >= c.ndof) continue;
     const int64_t p0 = c.row_off[row], p1 = c.row_off[row + 1];
     for (int64_t c0 = 0; c0 < c.ndof; c0 += c.chunk) {
       const int64_t cw = (c.ndof - c0) < c.chunk ? (c.ndof - c0) : c.chunk;
@@ -60,39 +67,64 @@ __global__ void __launch_bounds__(256) k_contract_rows(ContractArgs c, TO *__res
           coef = c.w[p] * c.KC(mt.z & 3) * c.ent_val[mt.x];
         }
         const int nv = (int)((p1 - pb) < 64 ? (p1 - pb) : 64);
-        // software pipeline over incidence pairs: the first 32 entries of the
-        // next pair are loaded before the current pair's LDS adds.  Every
-        // lane joins each shuffle (a lane masked off by a condition would not
-        // deliver its value to the lanes reading from it).
-        int spo = __shfl(po, half, 64);
-        int spl = __shfl(pl, half, 64);
-        double scf = __shfl(coef, half, 64);
-        if (half >= nv) spl = 0;
-        int dq = sub < spl ? c.ent_dof[spo + sub] : 0;
-        double vq = sub < spl ? c.ent_val[spo + sub] : 0.0;
-        for (int t = 0; t < nv; t += 2) {
-          const int src = (t + 2 + half) & 63;
-          const int npo = __shfl(po, src, 64);
-          int npl = __shfl(pl, src, 64);
-          const double ncf = __shfl(coef, src, 64);
-          if (t + 2 + half >= nv) npl = 0;
-          const int ndq = sub < npl ? c.ent_dof[npo + sub] : 0;
-          const double nvq = sub < npl ? c.ent_val[npo + sub] : 0.0;
-          if (sub < spl) {
-            const int64_t d = (int64_t)dq - c0;
-            if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf * vq);
+        // Software pipeline over groups of four incidence pairs (half-wave h
+        // takes incidences t + 2u + h, u = 0..3): the first 32 entries of the
+        // next group are loaded before the current group's LDS adds, so eight
+        // partner vectors are in flight per wavefront.  Every lane joins each
+        // shuffle (a lane masked off by a condition would not deliver its
+        // value to the lanes reading from it).
+        int spo[4], spl[4], dq[4];
+        double scf[4], vq[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int src = 2 * u + half;
+          spo[u] = __shfl(po, src & 63, 64);
+          const int l = __shfl(pl, src & 63, 64);
+          scf[u] = __shfl(coef, src & 63, 64);
+          spl[u] = src < nv ? l : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          dq[u] = sub < spl[u] ? c.ent_dof[spo[u] + sub] : 0;
+          vq[u] = sub < spl[u] ? c.ent_val[spo[u] + sub] : 0.0;
+        }
+        for (int t = 0; t < nv; t += 8) {
+          int npo[4], npl[4], ndq[4];
+          double ncf[4], nvq[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int src = t + 8 + 2 * u + half;
+            npo[u] = __shfl(po, src & 63, 64);
+            const int l = __shfl(pl, src & 63, 64);
+            ncf[u] = __shfl(coef, src & 63, 64);
+            npl[u] = src < nv ? l : 0;
           }
-          for (int k = sub + 32; k < spl; k += 32) {  // long partner vectors
-            const int dk = c.ent_dof[spo + k];
-            const double vk = c.ent_val[spo + k];
-            const int64_t d = (int64_t)dk - c0;
-            if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf * vk);
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            ndq[u] = sub < npl[u] ? c.ent_dof[npo[u] + sub] : 0;
+            nvq[u] = sub < npl[u] ? c.ent_val[npo[u] + sub] : 0.0;
           }
-          spo = npo;
-          spl = npl;
-          scf = ncf;
-          dq = ndq;
-          vq = nvq;
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            if (sub < spl[u]) {
+              const int64_t d = (int64_t)dq[u] - c0;
+              if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf[u] * vq[u]);
+            }
+            for (int k = sub + 32; k < spl[u]; k += 32) {  // long partner vectors
+              const int dk = c.ent_dof[spo[u] + k];
+              const double vk = c.ent_val[spo[u] + k];
+              const int64_t d = (int64_t)dk - c0;
+              if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf[u] * vk);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            spo[u] = npo[u];
+            spl[u] = npl[u];
+            scf[u] = ncf[u];
+            dq[u] = ndq[u];
+            vq[u] = nvq[u];
+          }
         }
       }
       __syncthreads();
@@ -237,7 +269,8 @@ static ContractArgs contract_args(fpde_mesh *m, const Plan &P, const fpde_params
 int launch_contract(fpde_mesh *m, const Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
   ContractArgs c = contract_args(m, P, p, lda);
   if (m->ndof == 0) return FPDE_OK;
-  const unsigned grid = (unsigned)(m->ndof < 65536 ? m->ndof : 65536);
+  const int64_t slots = 8 * ((m->ndof + 7) / 8);  // multiple of 8 keeps each slot on one XCD
+  const unsigned grid = (unsigned)(slots < 65536 ? slots : 65536);
   const size_t lds = sizeof(double) * (size_t)c.chunk;
   const long t = timer_begin(m, s);
   if (p->precision == FPDE_MIXED)
