@@ -2,10 +2,10 @@
 // fractional stiffness matrix.
 //
 // Blocked right-looking Cholesky K = L L^T on a row-major matrix (lower
-// triangle), panel width NB = 64, three launches per panel:
-//   diag  : one wavefront factors the 64 x 64 diagonal block with each lane
-//           holding one row in registers, then forms inv(L_kk) (lane j owns
-//           column j); both are written out;
+// triangle), panel width NB = 64, two launches per panel:
+//   diag  : one workgroup factors the 64 x 64 diagonal block in 4-column
+//           strips and forms inv(L_kk); for every panel after the first this
+//           runs inside the previous trailing update (its tile (0, 0));
 //   panel : X = B inv(L_kk)^T for every 64-row strip below (a plain GEMM,
 //           no sequential dependency), one workgroup per strip;
 //   syrk  : the trailing lower triangle, C -= X X^T, one workgroup per
@@ -46,64 +46,47 @@ __device__ __forceinline__ void tri_inverse_to(const double (*Lsh)[NB + 1], doub
   for (int i = 0; i < NB; i++) Linv[i * NB + j] = (T)X[i][j];
 }
 
-__device__ __forceinline__ double get44(const double (&a)[4][4], int i, int j) {
-  double v = 0.0;
-#pragma unroll
-  for (int ii = 0; ii < 4; ii++)
-#pragma unroll
-    for (int jj = 0; jj < 4; jj++)
-      if (ii == i && jj == j) v = a[ii][jj];
-  return v;
-}
-__device__ __forceinline__ void set44(double (&a)[4][4], int i, int j, double v) {
-#pragma unroll
-  for (int ii = 0; ii < 4; ii++)
-#pragma unroll
-    for (int jj = 0; jj < 4; jj++)
-      if (ii == i && jj == j) a[ii][jj] = v;
-}
+// LDS used by one diagonal-block factorization.
+struct DiagSmem {
+  double L[NB][NB + 1];  // the block on entry (lower part; identity past the matrix end), L on exit
+  double S[NB][5];
+  double rowb4[4][NB];
+};
 
-// Factor the 64 x 64 diagonal block at (k0, k0) and invert it.  256 threads
-// in a 16 x 16 grid, each holding a 4 x 4 register tile (rows 4ty.., columns
-// 4tx..).  The factorization walks 4-column strips: the strip is factored by
-// one wavefront (lane = row, pivots and multipliers exchanged by shuffles),
-// then every thread applies the rank-4 update to its tile.  The inverse
-// X = L^{-1} proceeds by 4-row blocks in the same way, with L read from LDS.
-// Rows/columns past the matrix end act as identity.
+// Factor the 64 x 64 diagonal block held in sm.L (rows/columns >= nb are
+// identity), write L over A's block at (k0, k0) and inv(L) to Linv.  256
+// threads in a 16 x 16 grid, each holding a 4 x 4 register tile (rows 4ty..,
+// columns 4tx..).  The factorization walks 4-column strips: the strip is
+// factored by one wavefront (lane = row, pivots and multipliers exchanged by
+// shuffles), then every thread applies the rank-4 update to its tile.  The
+// inverse X = L^{-1} proceeds by 4-row blocks in the same way.
 template <class T>
-__global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                    T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
-  __shared__ double Lsh[NB][NB + 1];
-  __shared__ double S[NB][5];
-  __shared__ double rowb4[4][NB];
+__device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict__ A, int64_t lda, int64_t k0,
+                            T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
   double a[4][4];
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int r = 4 * ty + i, m = 4 * tx + j;
-      if (r < nb && m < nb) a[i][j] = (m <= r) ? (double)A[(k0 + r) * lda + k0 + m] : 0.0;
-      else a[i][j] = (r == m) ? 1.0 : 0.0;
+      a[i][j] = (m <= r) ? sm.L[r][m] : 0.0;
     }
   bool bad = false;
-  // 4-column strips: the strip's owners publish it, wavefront 0 factors it
-  // (lane r = row r, pivots and multipliers exchanged by shuffles), then
-  // every thread applies the rank-4 update to its tile
+#pragma unroll 1
   for (int cb = 0; cb < 16; cb++) {
     if (tx == cb) {
 #pragma unroll
       for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) S[4 * ty + i][j] = a[i][j];
+        for (int j = 0; j < 4; j++) sm.S[4 * ty + i][j] = a[i][j];
     }
     __syncthreads();
     if (tid < 64) {
       const int r = tid;
       double s4[4];
 #pragma unroll
-      for (int j = 0; j < 4; j++) s4[j] = S[r][j];
+      for (int j = 0; j < 4; j++) s4[j] = sm.S[r][j];
 #pragma unroll
       for (int j = 0; j < 4; j++) {
         const int c = 4 * cb + j;
@@ -120,7 +103,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
         }
       }
 #pragma unroll
-      for (int j = 0; j < 4; j++) S[r][j] = s4[j];
+      for (int j = 0; j < 4; j++) sm.S[r][j] = s4[j];
     }
     __syncthreads();
     if (tx == cb) {
@@ -128,25 +111,23 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-          for (int j = 0; j < 4; j++) a[i][j] = S[4 * ty + i][j];
+          for (int j = 0; j < 4; j++) a[i][j] = sm.S[4 * ty + i][j];
       }
     } else if (tx > cb && ty >= tx) {
-      double lr[4][4], lm[4][4];
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+      for (int k = 0; k < 4; k++) {
+        double lr[4], lm[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-          lr[i][k] = S[4 * ty + i][k];
-          lm[i][k] = S[4 * tx + i][k];
+        for (int i = 0; i < 4; i++) {
+          lr[i] = sm.S[4 * ty + i][k];
+          lm[i] = sm.S[4 * tx + i][k];
         }
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-          if (ty == tx && j > i) continue;  // upper part of a diagonal tile
-#pragma unroll
-          for (int k = 0; k < 4; k++) a[i][j] = fma(-lr[i][k], lm[j][k], a[i][j]);
-        }
+          for (int j = 0; j < 4; j++)
+            if (ty != tx || j <= i) a[i][j] = fma(-lr[i], lm[j], a[i][j]);  // skip a diagonal tile's upper part
+      }
     }
     __syncthreads();
   }
@@ -160,19 +141,19 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
     for (int j = 0; j < 4; j++) {
       const int r = 4 * ty + i, m = 4 * tx + j;
       const double v = (m <= r) ? a[i][j] : 0.0;
-      Lsh[r][m] = v;
+      sm.L[r][m] = v;
       if (r < nb && m < nb && m <= r) A[(k0 + r) * lda + k0 + m] = (T)v;
     }
-  // inverse: X = I, then row c /= l_cc and rows r > c -= l_rc X[c, :]
+  // inverse: X = I, then blocks of 4 rows: the owners of rows 4cb..4cb+3
+  // finish them with the 4 x 4 diagonal block of L (inside one thread's
+  // tile), publish them, and the rows below subtract L[r, block] X[block, :]
   double x[4][4];
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
     for (int j = 0; j < 4; j++) x[i][j] = (4 * ty + i == 4 * tx + j) ? 1.0 : 0.0;
   __syncthreads();
-  // blocks of 4 rows: the owners of rows 4cb..4cb+3 finish them with the
-  // 4 x 4 diagonal block of L (inside one thread's tile), publish them, and
-  // the rows below subtract L[r, 4cb..4cb+3] X[4cb..4cb+3, :]
+#pragma unroll 1
   for (int cb = 0; cb < 16; cb++) {
     if (ty == cb && tx <= cb) {  // X is lower triangular: columns beyond stay 0
 #pragma unroll
@@ -180,35 +161,32 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
         const int c = 4 * cb + i;
 #pragma unroll
         for (int k = 0; k < i; k++) {
-          const double l = Lsh[c][4 * cb + k];
+          const double l = sm.L[c][4 * cb + k];
 #pragma unroll
           for (int j = 0; j < 4; j++) x[i][j] = fma(-l, x[k][j], x[i][j]);
         }
-        const double dinv = 1.0 / Lsh[c][c];
+        const double dinv = 1.0 / sm.L[c][c];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
           x[i][j] = x[i][j] * dinv;
-          rowb4[i][4 * tx + j] = x[i][j];
+          sm.rowb4[i][4 * tx + j] = x[i][j];
         }
       }
     }
     __syncthreads();
     if (ty > cb && tx <= cb) {
-      double xr[4][4], l[4][4];
 #pragma unroll
-      for (int k = 0; k < 4; k++)
+      for (int k = 0; k < 4; k++) {
+        double xr[4], l[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) xr[k][j] = rowb4[k][4 * tx + j];
+        for (int j = 0; j < 4; j++) xr[j] = sm.rowb4[k][4 * tx + j];
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+        for (int i = 0; i < 4; i++) l[i] = sm.L[4 * ty + i][4 * cb + k];
 #pragma unroll
-        for (int k = 0; k < 4; k++) l[i][k] = Lsh[4 * ty + i][4 * cb + k];
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) x[i][j] = fma(-l[i][k], xr[k][j], x[i][j]);
+          for (int j = 0; j < 4; j++) x[i][j] = fma(-l[i], xr[j], x[i][j]);
+      }
     }
     __syncthreads();
   }
@@ -216,6 +194,23 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
   for (int i = 0; i < 4; i++)
 #pragma unroll
     for (int j = 0; j < 4; j++) Linv[(4 * ty + i) * NB + 4 * tx + j] = (T)x[i][j];
+}
+
+// Factor the diagonal block at (k0, k0) on its own (the first panel).
+template <class T>
+__global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
+                                                    T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
+  __shared__ DiagSmem sm;
+  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    const int r = idx >> 6, m = idx & 63;
+    double v;
+    if (r < nb && m < nb) v = (m <= r) ? (double)A[(k0 + r) * lda + k0 + m] : 0.0;
+    else v = (r == m) ? 1.0 : 0.0;
+    sm.L[r][m] = v;
+  }
+  __syncthreads();
+  diag_factor<T>(sm, nb, A, lda, k0, Linv, flag, aux);
 }
 
 // inv(L_kk) for every diagonal block of an existing factor (one wave per block)
@@ -291,10 +286,21 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
 }
 
 // trailing update C[I,J] -= X_I X_J^T over lower tiles I >= J of the matrix
-// starting at row/column k0 + NB; X = columns [k0, k0+NB)
+// starting at row/column k1 = k0 + NB; X = columns [k0, k0+NB).  The
+// workgroup of tile (0, 0) -- the next diagonal block -- keeps its updated
+// tile in LDS and factors it at once (diag_factor), so the next panel's
+// diagonal factorization runs beside the rest of this update instead of
+// after it.
 template <class T>
-__global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0) {
-  __shared__ T sP[64][33], sQ[64][33];
+__global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
+                                              T *__restrict__ Linv_next, int32_t *flag, int64_t *aux) {
+  struct Gemm {
+    T sP[64][33], sQ[64][33];
+  };
+  __shared__ union {
+    Gemm g;
+    DiagSmem d;
+  } sm;
   const int64_t x = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= x) I++;
@@ -305,8 +311,24 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
   const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
   const int qrow = (int)((n - cj) < 64 ? (n - cj) : 64);
   T acc[4][4];
-  tile_nt<T>(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sP, sQ, acc);
+  tile_nt<T>(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sm.g.sP, sm.g.sQ, acc);
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  if (x == 0) {
+    const int nb = prow;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int r = ty + 16 * a, c = tx + 16 * b;
+        double v;
+        if (r < nb && c < nb) v = (c <= r) ? (double)A[(ri + r) * lda + ri + c] - (double)acc[a][b] : 0.0;
+        else v = (r == c) ? 1.0 : 0.0;
+        sm.d.L[r][c] = v;
+      }
+    __syncthreads();
+    diag_factor<T>(sm.d, nb, A, lda, ri, Linv_next, flag, aux);
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 4; a++) {
     const int64_t r = ri + ty + 16 * a;
@@ -420,14 +442,17 @@ static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
   FPDE_TRY(ensure_linv(m, n, sizeof(T), &lv));
   T *Linv = (T *)lv;
   const long t = timer_begin(m, s);
+  // the first diagonal block on its own; every later one is factored by the
+  // workgroup of tile (0, 0) inside the preceding trailing update
+  k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, 0, Linv, m->flag, m->flag_aux);
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     T *Lk = Linv + (k0 / NB) * NB * NB;
-    k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, k0, Lk, m->flag, m->flag_aux);
     const int64_t rest = n - k0 - NB;
     if (rest > 0) {
       k_panel<T><<<nblk(rest, 64), 256, 0, s>>>(A, lda, n, k0, Lk);
       const int64_t Tn = (rest + 63) / 64;
-      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0);
+      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0, Lk + NB * NB, m->flag,
+                                                                m->flag_aux);
     }
   }
   timer_end(m, FPDE_STAGE_POTRF, t, s);
