@@ -94,8 +94,11 @@ struct fpde_mesh {
   double *vec = nullptr;          // 4 ndof FP64
   double *red = nullptr;          // reduction scratch
   int64_t red_n = 0;
-  void *linv = nullptr;           // inverses of the factor's 64 x 64 diagonal blocks
+  void *linv = nullptr;           // inverses of the factor's 64 x 64 diagonal blocks (+ transposes)
   size_t linv_bytes = 0;
+  int *tsync = nullptr;           // triangular solves: per-block flags (2 nblk) and 2 tickets
+  int tsync_n = 0;
+  int tsync_epoch = 0;
   fpde::StageTimer timer;
 };
 

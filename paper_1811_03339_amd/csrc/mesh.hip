@@ -431,6 +431,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   for (auto &P : m->plan) free_plan(P);
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   if (m->linv) (void)hipFree(m->linv);
+  dfree(m->tsync);
   delete m;
 }
 

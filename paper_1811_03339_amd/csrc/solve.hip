@@ -10,10 +10,9 @@
 //           no sequential dependency), one workgroup per strip;
 //   syrk  : the trailing lower triangle, C -= X X^T, one workgroup per
 //           64 x 64 output tile.
-// Triangular solves use the stored inv(L_kk): one launch per block applies
-// the diagonal inverse and the off-diagonal update together (forward
-// x_k = inv(L_kk) y_k, y_below -= L_below,k x_k; backward
-// u_k = inv(L_kk)^T x_k, x_above -= L_k,above^T u_k).  The same kernels are
+// Triangular solves use the stored inv(L_kk) and take one launch per
+// direction: block rows are handed out in dependency order by an atomic
+// ticket and wait for the blocks they need through per-block flags.  The same kernels are
 // instantiated for FP32 storage, which the mixed-precision path factors and
 // then refines against FP64 residuals b - K u computed matrix-free from the
 // FP64 derivative vectors.
@@ -36,14 +35,17 @@ constexpr int NB = 64;
 // (row-major 64 x 64).  One wavefront.
 template <class T>
 __device__ __forceinline__ void tri_inverse_to(const double (*Lsh)[NB + 1], double (*X)[NB + 1],
-                                               T *__restrict__ Linv) {
+                                               T *__restrict__ Linv, T *__restrict__ LinvT) {
   const int j = threadIdx.x;
   for (int i = 0; i < NB; i++) {
     double s = (i == j) ? 1.0 : 0.0;
     for (int k = j; k < i; k++) s = fma(-Lsh[i][k], X[k][j], s);
     X[i][j] = (i < j) ? 0.0 : s / Lsh[i][i];
   }
-  for (int i = 0; i < NB; i++) Linv[i * NB + j] = (T)X[i][j];
+  for (int i = 0; i < NB; i++) {
+    Linv[i * NB + j] = (T)X[i][j];
+    LinvT[j * NB + i] = (T)X[i][j];
+  }
 }
 
 // LDS used by one diagonal-block factorization.
@@ -62,7 +64,8 @@ struct DiagSmem {
 // inverse X = L^{-1} proceeds by 4-row blocks in the same way.
 template <class T>
 __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict__ A, int64_t lda, int64_t k0,
-                            T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
+                                            T *__restrict__ Linv, T *__restrict__ LinvT, int32_t *flag,
+                                            int64_t *aux) {
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   double a[4][4];
 #pragma unroll
@@ -193,13 +196,17 @@ __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict_
 #pragma unroll
   for (int i = 0; i < 4; i++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) Linv[(4 * ty + i) * NB + 4 * tx + j] = (T)x[i][j];
+    for (int j = 0; j < 4; j++) {
+      Linv[(4 * ty + i) * NB + 4 * tx + j] = (T)x[i][j];
+      LinvT[(4 * tx + j) * NB + 4 * ty + i] = (T)x[i][j];
+    }
 }
 
 // Factor the diagonal block at (k0, k0) on its own (the first panel).
 template <class T>
 __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                    T *__restrict__ Linv, int32_t *flag, int64_t *aux) {
+                                                    T *__restrict__ Linv, T *__restrict__ LinvT, int32_t *flag,
+                                                    int64_t *aux) {
   __shared__ DiagSmem sm;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
   for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
@@ -210,12 +217,13 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
     sm.L[r][m] = v;
   }
   __syncthreads();
-  diag_factor<T>(sm, nb, A, lda, k0, Linv, flag, aux);
+  diag_factor<T>(sm, nb, A, lda, k0, Linv, LinvT, flag, aux);
 }
 
 // inv(L_kk) for every diagonal block of an existing factor (one wave per block)
 template <class T>
-__global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t lda, int64_t n, T *__restrict__ Linv) {
+__global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t lda, int64_t n, T *__restrict__ Linv,
+                                              T *__restrict__ LinvT) {
   __shared__ double Lsh[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
   const int64_t k0 = (int64_t)blockIdx.x * NB;
@@ -228,7 +236,7 @@ __global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t l
     Lsh[r][m] = v;
   }
   __syncthreads();
-  tri_inverse_to<T>(Lsh, X, Linv + (int64_t)blockIdx.x * NB * NB);
+  tri_inverse_to<T>(Lsh, X, Linv + (int64_t)blockIdx.x * NB * NB, LinvT + (int64_t)blockIdx.x * NB * NB);
 }
 
 // 64 x 64 tile product acc = P Q^T over a 64-deep inner dimension, P and Q
@@ -293,7 +301,8 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
 // after it.
 template <class T>
 __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                              T *__restrict__ Linv_next, int32_t *flag, int64_t *aux) {
+                                              T *__restrict__ Linv_next, T *__restrict__ LinvT_next, int32_t *flag,
+                                              int64_t *aux) {
   struct Gemm {
     T sP[64][33], sQ[64][33];
   };
@@ -326,7 +335,7 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
         sm.d.L[r][c] = v;
       }
     __syncthreads();
-    diag_factor<T>(sm.d, nb, A, lda, ri, Linv_next, flag, aux);
+    diag_factor<T>(sm.d, nb, A, lda, ri, Linv_next, LinvT_next, flag, aux);
     return;
   }
 #pragma unroll
@@ -342,59 +351,244 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
   }
 }
 
-// forward block k: x_k = inv(L_kk) y_k (written by block 0), and
-// y[r] -= L[r, k-block] . x_k for the 64 rows r >= k0 + NB of this workgroup
+// Triangular solves in one launch per direction.  Each workgroup takes the
+// next block row from an atomic ticket (forward: top to bottom; backward:
+// bottom to top), so block rows are handed out in dependency order: a
+// workgroup only ever waits for block rows whose tickets were taken before
+// its own, by workgroups that are already running, and the first ticket
+// waits for nothing -- no deadlock whatever the residency.  Solved blocks are
+// published with a release store of the call's epoch into a per-block flag.
+// Every wave polls the flags it needs by itself (acquire loads, up to 64
+// flags per poll), so the loop over earlier blocks has no barrier; a poll
+// that exceeds kSpinLimit marks the call failed and every wave still exits.
+constexpr int64_t kSpinLimit = int64_t(1) << 22;
+
+// Whole-wave poll of the flags of blocks c, c + dir, ..., (count <= 64 of
+// them).  Returns how many leading ones carry `epoch` (>= 1), or 0 after
+// kSpinLimit polls without flag c.
+__device__ __forceinline__ int poll_run(const int *flags, int c, int dir, int count, int epoch) {
+  const int lane = threadIdx.x & 63;
+  const int k = lane < count ? lane : count - 1;
+  for (int64_t it = 0; it <= kSpinLimit; it++) {
+    const int v = __hip_atomic_load(&flags[c + dir * k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long pub = __ballot(v == epoch);
+    if (pub & 1ull) {
+      const unsigned long long gap = ~pub;
+      const int run = gap ? __ffsll((long long)gap) - 1 : 64;
+      return run < count ? run : count;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return 0;
+}
+
+// Sixteen per-lane values a[q] -> sum over the wave's 64 lanes of a[q], left
+// in every lane with (lane >> 2) & 15 == q (butterfly that halves the
+// vector at each exchange: 8 + 4 + 2 + 1 + 1 + 1 shuffles).
+__device__ __forceinline__ double wave_sum16(const double (&a)[16]) {
+  const int lane = threadIdx.x & 63;
+  double b[8], c[4], d[2];
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 8; k++) b[k] = (h5 ? a[k + 8] : a[k]) + __shfl_xor(h5 ? a[k] : a[k + 8], 32, 64);
+#pragma unroll
+  for (int k = 0; k < 4; k++) c[k] = (h4 ? b[k + 4] : b[k]) + __shfl_xor(h4 ? b[k] : b[k + 4], 16, 64);
+#pragma unroll
+  for (int k = 0; k < 2; k++) d[k] = (h3 ? c[k + 2] : c[k]) + __shfl_xor(h3 ? c[k] : c[k + 2], 8, 64);
+  double e = (h2 ? d[1] : d[0]) + __shfl_xor(h2 ? d[0] : d[1], 4, 64);
+  e += __shfl_xor(e, 2, 64);
+  e += __shfl_xor(e, 1, 64);
+  return e;
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// forward: x_b = inv(L_bb) (y_b - sum_{c<b} L_bc x_c).  Wave w owns rows
+// 16w..16w+15 of the block row; lane = column within block c.
 template <class T>
-__global__ void __launch_bounds__(256) k_fwd_block(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
-                                                   const T *__restrict__ Linv, double *__restrict__ y,
-                                                   double *__restrict__ x) {
-  __shared__ double yk[NB], xk[NB];
-  const int tid = threadIdx.x;
-  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  if (tid < NB) yk[tid] = (tid < nb) ? y[k0 + tid] : 0.0;
-  __syncthreads();
-  if (tid < NB) {
-    double s = 0.0;
-    for (int m = 0; m < NB; m++) s = fma((double)Linv[tid * NB + m], yk[m], s);
-    xk[tid] = s;
-    if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = s;
+__global__ void __launch_bounds__(256) k_trsv_fwd(const T *__restrict__ L, int64_t lda, int64_t n, int nblk,
+                                                  const T *__restrict__ LinvT, const double *__restrict__ y,
+                                                  double *__restrict__ x, int *flags, int *ticket, int epoch,
+                                                  int32_t *err) {
+  __shared__ int sb, ok;
+  __shared__ double rhs[NB];
+  __shared__ double red[4][NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    sb = atomicAdd(ticket, 1);
+    ok = 1;
   }
   __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int64_t rbase = k0 + NB + 64 * (int64_t)blockIdx.x;
-  for (int q = w; q < 64; q += 4) {
-    const int64_t r = rbase + q;
-    if (r >= n) break;
-    double v = (double)L[r * lda + k0 + lane] * xk[lane];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if (lane == 0) y[r] -= v;
+  const int b = sb;
+  if (b >= nblk) return;
+  const int64_t r0 = (int64_t)b * NB;
+  const int nb = (int)((n - r0) < NB ? (n - r0) : NB);
+  // inv(L_bb)[lane][16w + q], read before any wait
+  double li[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) li[q] = (double)LinvT[(int64_t)b * NB * NB + (int64_t)(16 * w + q) * NB + lane];
+  int64_t roff[16];  // rows past the matrix end repeat the last row; their sums are dropped
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    const int r = 16 * w + q;
+    roff[q] = (r0 + (r < nb ? r : nb - 1)) * lda + lane;
+  }
+  double part[16];
+  T cur[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    part[q] = 0.0;
+    cur[q] = (T)0;
+  }
+  if (b > 0) {  // column block 0 exists left of this block row
+#pragma unroll
+    for (int q = 0; q < 16; q++) cur[q] = L[roff[q]];
+  }
+  bool good = true;
+  int ready = 0;  // blocks [0, ready) known to be published
+  for (int c = 0; c < b; c++) {
+    if (c >= ready) {
+      const int k = poll_run(flags, c, 1, (b - c) < 64 ? (b - c) : 64, epoch);
+      if (k == 0) {
+        good = false;
+        break;
+      }
+      ready = c + k;
+    }
+    const double xv = x[(int64_t)c * NB + lane];
+    const int64_t cn = (int64_t)((c + 1 < b) ? c + 1 : c) * NB;
+    T nxt[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) nxt[q] = L[roff[q] + cn];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      part[q] = fma((double)cur[q], xv, part[q]);
+      cur[q] = nxt[q];
+    }
+  }
+  if (!good && lane == 0) ok = 0;
+  const double sum = wave_sum16(part);
+  if ((lane & 3) == 0) {
+    const int r = 16 * w + (lane >> 2);
+    rhs[r] = (r < nb) ? y[r0 + r] - sum : 0.0;
+  }
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; q++) s = fma(li[q], rhs[16 * w + q], s);
+  red[w][lane] = s;
+  __syncthreads();
+  if (tid < NB) {
+    if (tid < nb) x[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    // the writers make their stores visible device-wide before the flag goes up
+    __threadfence();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ok) set_flag(err, FPDE_EHIP);
   }
 }
 
-// backward block k: u_k = inv(L_kk)^T x_k (written by block 0), and
-// x[r] -= sum_c L[k0+c][r] u_k[c] for rows r < k0 (256 per workgroup)
+// backward: u_b = inv(L_bb)^T (x_b - sum_{c>b} L_cb^T u_c).  Lane = row of
+// the result block (column r0 + lane of L); wave w owns rows 16w..16w+15 of
+// block c.
 template <class T>
-__global__ void __launch_bounds__(256) k_bwd_block(const T *__restrict__ L, int64_t lda, int64_t n, int64_t k0,
-                                                   const T *__restrict__ Linv, double *__restrict__ x,
-                                                   double *__restrict__ u) {
-  __shared__ double xk[NB], uk[NB];
-  const int tid = threadIdx.x;
-  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  if (tid < NB) xk[tid] = (tid < nb) ? x[k0 + tid] : 0.0;
+__global__ void __launch_bounds__(256) k_trsv_bwd(const T *__restrict__ L, int64_t lda, int64_t n, int nblk,
+                                                  const T *__restrict__ Linv, const double *__restrict__ x,
+                                                  double *__restrict__ u, int *flags, int *ticket, int epoch,
+                                                  int32_t *err) {
+  __shared__ int sb, ok;
+  __shared__ double rhs[NB];
+  __shared__ double red[4][NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    sb = atomicAdd(ticket, 1);
+    ok = 1;
+  }
+  __syncthreads();
+  if (sb >= nblk) return;
+  const int b = nblk - 1 - sb;
+  const int64_t r0 = (int64_t)b * NB;
+  const int nb = (int)((n - r0) < NB ? (n - r0) : NB);
+  // inv(L_bb)[16w + q][lane], read before any wait
+  double li[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) li[q] = (double)Linv[(int64_t)b * NB * NB + (int64_t)(16 * w + q) * NB + lane];
+  // only the last block can be partial, and it has no blocks below it, so
+  // every block c > b read here has nbc rows and columns r0 + lane < n
+  auto rows_of = [&](int c) { return (int)((n - (int64_t)c * NB) < NB ? (n - (int64_t)c * NB) : NB); };
+  double part = 0.0;
+  T cur[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) cur[q] = (T)0;
+  if (nblk - 1 > b) {  // the last block row lies below this block
+    const int c = nblk - 1;
+    const int nbc = rows_of(c);
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      const int j = 16 * w + q;
+      cur[q] = L[((int64_t)c * NB + (j < nbc ? j : nbc - 1)) * lda + r0 + lane];
+    }
+  }
+  bool good = true;
+  int ready = nblk;  // blocks [ready, nblk) known to be published
+  for (int c = nblk - 1; c > b; c--) {
+    if (c < ready) {
+      const int k = poll_run(flags, c, -1, (c - b) < 64 ? (c - b) : 64, epoch);
+      if (k == 0) {
+        good = false;
+        break;
+      }
+      ready = c - k + 1;
+    }
+    const int64_t c0 = (int64_t)c * NB;
+    const int nbc = rows_of(c);
+    const int jl = 16 * w + (lane & 15);
+    const double ub = jl < nbc ? u[c0 + jl] : 0.0;
+    const int cn = (c - 1 > b) ? c - 1 : c;
+    const int nbn = rows_of(cn);
+    T nxt[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      const int j = 16 * w + q;
+      nxt[q] = L[((int64_t)cn * NB + (j < nbn ? j : nbn - 1)) * lda + r0 + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      part = fma((double)cur[q], read_lane(ub, q), part);
+      cur[q] = nxt[q];
+    }
+  }
+  if (!good && lane == 0) ok = 0;
+  red[w][lane] = part;
+  __syncthreads();
+  if (tid < NB) rhs[tid] = (tid < nb) ? x[r0 + tid] - ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) : 0.0;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; q++) s = fma(li[q], rhs[16 * w + q], s);
+  __syncthreads();  // red is reused
+  red[w][lane] = s;
   __syncthreads();
   if (tid < NB) {
-    double s = 0.0;
-    for (int m = 0; m < NB; m++) s = fma((double)Linv[m * NB + tid], xk[m], s);
-    uk[tid] = s;
-    if (blockIdx.x == 0 && tid < nb) u[k0 + tid] = s;
+    if (tid < nb) u[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    __threadfence();
   }
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * 256 + tid;
-  if (r < k0) {
-    double s = 0.0;
-    for (int c = 0; c < nb; c++) s = fma((double)L[(k0 + c) * lda + r], uk[c], s);
-    x[r] -= s;
+  if (tid == 0) {
+    __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ok) set_flag(err, FPDE_EHIP);
   }
+}
+
+__global__ void k_zero_i32(int *p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
 }
 
 __global__ void k_axpy_copy(double *__restrict__ u, const double *__restrict__ c, int64_t n) {
@@ -424,7 +618,8 @@ static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b -
 
 // device buffer for the inverses of the diagonal blocks (bytes, reused)
 static int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, void **out) {
-  const size_t need = (size_t)((n + NB - 1) / NB) * NB * NB * elem;
+  // inverses of the diagonal blocks, then their transposes
+  const size_t need = 2 * (size_t)((n + NB - 1) / NB) * NB * NB * elem;
   if (m->linv_bytes < need) {
     if (m->linv) (void)hipFree(m->linv);
     m->linv = nullptr;
@@ -444,14 +639,16 @@ static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
   const long t = timer_begin(m, s);
   // the first diagonal block on its own; every later one is factored by the
   // workgroup of tile (0, 0) inside the preceding trailing update
-  k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, 0, Linv, m->flag, m->flag_aux);
+  T *LinvT = Linv + ((n + NB - 1) / NB) * NB * NB;
+  k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, 0, Linv, LinvT, m->flag, m->flag_aux);
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     T *Lk = Linv + (k0 / NB) * NB * NB;
     const int64_t rest = n - k0 - NB;
     if (rest > 0) {
       k_panel<T><<<nblk(rest, 64), 256, 0, s>>>(A, lda, n, k0, Lk);
       const int64_t Tn = (rest + 63) / 64;
-      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0, Lk + NB * NB, m->flag,
+      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0, Lk + NB * NB,
+                                                                LinvT + (k0 / NB + 1) * NB * NB, m->flag,
                                                                 m->flag_aux);
     }
   }
@@ -461,21 +658,33 @@ static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
 }
 
 // y (n) holds the right-hand side on entry and the solution on exit;
-// x (n) is scratch
+// x (n) is scratch.  Two launches (forward, backward), each preceded by a
+// reset of its ticket counter.
+static int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s) {
+  if (m->tsync_n < nblk) {
+    dfree(m->tsync);
+    m->tsync_n = 0;
+    const int cnt = 2 * nblk + 2;
+    FPDE_TRY(dalloc(&m->tsync, (size_t)cnt));
+    k_zero_i32<<<(cnt + 255) / 256, 256, 0, s>>>(m->tsync, cnt);
+    m->tsync_n = nblk;
+    m->tsync_epoch = 0;
+  }
+  return FPDE_OK;
+}
+
 template <class T>
 static int trsv_pair(const T *L, int64_t lda, int64_t n, const T *Linv, double *y, double *x, fpde_mesh *m,
                      hipStream_t s) {
+  const int nblk = (int)((n + NB - 1) / NB);
+  FPDE_TRY(ensure_trsv_sync(m, nblk, s));
+  const int epoch = ++m->tsync_epoch;
+  int *fflags = m->tsync, *bflags = m->tsync + nblk, *tickets = m->tsync + 2 * nblk;
+  const T *LinvT = Linv + (size_t)nblk * NB * NB;
   const long t = timer_begin(m, s);
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    const int64_t rest = n - k0 - NB;
-    const unsigned g = rest > 0 ? nblk(rest, 64) : 1;
-    k_fwd_block<T><<<g, 256, 0, s>>>(L, lda, n, k0, Linv + (k0 / NB) * NB * NB, y, x);
-  }
-  const int64_t last = ((n - 1) / NB) * NB;
-  for (int64_t k0 = last; k0 >= 0; k0 -= NB) {
-    const unsigned g = k0 > 0 ? nblk(k0, 256) : 1;
-    k_bwd_block<T><<<g, 256, 0, s>>>(L, lda, n, k0, Linv + (k0 / NB) * NB * NB, x, y);
-  }
+  k_zero_i32<<<1, 64, 0, s>>>(tickets, 2);
+  k_trsv_fwd<T><<<nblk, 256, 0, s>>>(L, lda, n, nblk, LinvT, y, x, fflags, tickets, epoch, m->flag);
+  k_trsv_bwd<T><<<nblk, 256, 0, s>>>(L, lda, n, nblk, Linv, x, y, bflags, tickets + 1, epoch, m->flag);
   timer_end(m, FPDE_STAGE_TRSV, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
@@ -606,9 +815,10 @@ extern "C" int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const voi
   FPDE_TRY(ensure_linv(m, n, elem, &lv));
   const unsigned nbk = (unsigned)((n + NB - 1) / NB);
   if (p->precision == FPDE_MIXED)
-    k_trinv<float><<<nbk, 64, 0, s>>>((const float *)L, lda, n, (float *)lv);
+    k_trinv<float><<<nbk, 64, 0, s>>>((const float *)L, lda, n, (float *)lv, (float *)lv + (size_t)nbk * NB * NB);
   else
-    k_trinv<double><<<nbk, 64, 0, s>>>((const double *)L, lda, n, (double *)lv);
+    k_trinv<double><<<nbk, 64, 0, s>>>((const double *)L, lda, n, (double *)lv,
+                                        (double *)lv + (size_t)nbk * NB * NB);
   FPDE_HIP(hipGetLastError());
   return solve_with_factor(m, p, L, lda, lv, b, u, info, s);
 }

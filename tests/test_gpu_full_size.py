@@ -167,6 +167,7 @@ def test_ellipsoid400k_mixed():
     pmx = F.params(alpha, K, quad_points=nq, precision=F.FPDE_MIXED, ir_tol=1e-8)
     A32 = torch.empty((n, n), dtype=torch.float32, device="cuda")
     b = torch.empty(n, dtype=torch.float64, device="cuda")
+    gm.timing(True)
     _, t_asm = timed(lambda: gm.assemble(pmx, A32, b))
     x = torch.tensor(rng.normal(size=n), device="cuda")
     Ax32 = (A32 @ x.float()).double()
@@ -178,6 +179,8 @@ def test_ellipsoid400k_mixed():
     assert info32.final_rel_residual <= 1e-8
     log(f"[ellipsoid400k] n={n} FP32 matrix {n * n * 4 / 2**30:.1f} GiB, assemble {t_asm:.2f}s, "
         f"solve {t_sol:.2f}s, ir_iters {info32.ir_iters}, residual {info32.final_rel_residual:.2e}")
+    stages = {k: round(v[0], 1) for k, v in gm.stage_times().items() if v[1]}
+    log(f"[ellipsoid400k] stage ms {stages}")
     del A32, gm
     gc.collect()
     torch.cuda.empty_cache()
