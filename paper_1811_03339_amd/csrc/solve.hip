@@ -48,158 +48,212 @@ __device__ __forceinline__ void tri_inverse_to(const double (*Lsh)[NB + 1], doub
   }
 }
 
-// LDS used by one diagonal-block factorization.
+// LDS used by one diagonal-block factorization: the block on entry (lower
+// part; identity past the matrix end); on exit L in the lower triangle and
+// X = inv(L) transposed in the strict upper triangle (X[r][c], r > c, kept at
+// L[c][r]) with X's diagonal in dinv.  XcT holds inv(L_cb)^T of the 16 x 16
+// diagonal block being processed, dense (zeros included).
 struct DiagSmem {
-  double L[NB][NB + 1];  // the block on entry (lower part; identity past the matrix end), L on exit
-  double S[NB][5];
-  double rowb4[4][NB];
+  double L[NB][NB + 1];
+  double XcT[16][17];
+  double dinv[NB];
 };
 
+// LDS written by some lanes of a wavefront and then read by other lanes of
+// the same wavefront (the wavefront's LDS operations complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Forces v to be computed at this point of the program.
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+// Lane-dependent index whose comparisons the compiler must not hoist out of
+// the enclosing loop (each hoisted comparison pins a 64-bit lane mask).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Factor the 64 x 64 diagonal block held in sm.L (rows/columns >= nb are
-// identity), write L over A's block at (k0, k0) and inv(L) to Linv.  256
-// threads in a 16 x 16 grid, each holding a 4 x 4 register tile (rows 4ty..,
-// columns 4tx..).  The factorization walks 4-column strips: the strip is
-// factored by one wavefront (lane = row, pivots and multipliers exchanged by
-// shuffles), then every thread applies the rank-4 update to its tile.  The
-// inverse X = L^{-1} proceeds by 4-row blocks in the same way.
+// identity), write L over A's block at (k0, k0), inv(L) to Linv and
+// inv(L)^T to LinvT.  256 threads; wavefront w owns block row w of the four
+// 16-row block rows.  Right-looking over 16-column blocks cb:
+//   1. wavefront cb factors the 16 x 16 diagonal block in registers (lane =
+//      row, pivots and multipliers broadcast across lanes, one rsqrt per
+//      pivot) and, interleaved, inverts it (lane = column); it then scales
+//      its block row of inv(L) by that inverse;
+//   2. every wavefront below forms its block L[w][cb] = A[w][cb] inv(L_cb)^T
+//      and updates its block row of inv(L) (product form
+//      inv(L) = L_3^{-1} L_2^{-1} L_1^{-1} L_0^{-1}, one block column per step);
+//   3. every thread applies the rank-16 update to its 4 x 4 tile (rows
+//      4ty.., columns 4tx..) of the trailing lower triangle, in LDS.
+// Two workgroup barriers per block column.
 template <class T>
 __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict__ A, int64_t lda, int64_t k0,
                                             T *__restrict__ Linv, T *__restrict__ LinvT, int32_t *flag,
                                             int64_t *aux) {
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  double a[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int r = 4 * ty + i, m = 4 * tx + j;
-      a[i][j] = (m <= r) ? sm.L[r][m] : 0.0;
-    }
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ty = tid >> 4, tx = tid & 15;
   bool bad = false;
 #pragma unroll 1
-  for (int cb = 0; cb < 16; cb++) {
-    if (tx == cb) {
+  for (int cb = 0; cb < 4; cb++) {
+    const int c0 = 16 * cb;
+    // the trailing updates of the previous step to this wavefront's block
+    // row (the only rows it reads before the next barrier) are in LDS
+    wave_lds_sync();
+    if (wv == cb) {
+      const int r = opaque(lane & 15);  // lanes 16..63 repeat lanes 0..15
+      // Lanes 0..15 (v = row r of the block -> row r of L) factor; lanes
+      // 16..31 (v = column r of the identity -> column r of inv(L_cb))
+      // run the same instruction stream, which is forward substitution for
+      // them: both updates read v[k] -= v[j] L[k][j].  The strict upper part
+      // of a factor row starts at zero and only ever holds values that no
+      // lower entry depends on.  At pivot j the factor lanes store L[r][j] to
+      // its place in LDS and every lane reads the multipliers L[k][j], k > j,
+      // back as broadcasts; lane j + 1 forms the next pivot from its own
+      // registers (its multiplier is its own L[j+1][j]), off the LDS path.
+      const bool frow = lane < 16;
+      double v[16];
+#pragma unroll
+      for (int k = 0; k < 16; k++) {
+        const double a = sm.L[c0 + r][c0 + k];
+        v[k] = frow ? a : ((k == r) ? 1.0 : 0.0);
+      }
+      double piv = read_lane(v[0], 0);
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        if (!(piv > 0.0)) {
+          bad = true;
+          piv = 1.0;
+        }
+        const double rs = rsqrt(piv);
+        v[j] *= rs;  // L[r][j] below the pivot, sqrt(piv) at it; inv(L)[j][r] on the other lanes
+        if (j + 1 < 16) piv = read_lane(fma(-v[j], v[j], v[j + 1]), j + 1);
+        if (frow) sm.L[c0 + r][c0 + j] = v[j];
+        wave_lds_sync();
+#pragma unroll
+        for (int k = j + 1; k < 16; k++) pin(v[k]);  // the previous pivot's updates are done
+#pragma unroll
+        for (int k = j + 1; k < 16; k++) v[k] = fma(-v[j], sm.L[c0 + k][c0 + j], v[k]);
+      }
+      if (lane >= 16 && lane < 32) {
+        double dg = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+          if (k > r) sm.L[c0 + r][c0 + k] = v[k];  // column r of inv(L) transposed; L is in place
+          sm.XcT[r][k] = v[k];
+          dg = (k == r) ? v[k] : dg;
+        }
+        sm.dinv[c0 + r] = dg;
+      }
+      wave_lds_sync();
+      // block row cb of inv(L): X[cb][K] = inv(L_cb) * (accumulated X[cb][K]), K < cb
+      const int c = lane & 15, rg = lane >> 4;
+      for (int K = 0; K < cb; K++) {
+        double nx[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k = 0; k < 16; k++) {
+          const double xo = sm.L[16 * K + c][c0 + k];
+#pragma unroll
+          for (int q = 0; q < 4; q++) nx[q] = fma(sm.XcT[k][4 * rg + q], xo, nx[q]);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 4; q++) sm.L[16 * K + c][c0 + 4 * rg + q] = nx[q];
+        wave_lds_sync();
+      }
+    }
+    __syncthreads();
+    if (wv > cb) {
+      const int rb = 16 * wv, r = lane >> 2, cg = lane & 3;
+      // L[wv][cb] = A[wv][cb] inv(L_cb)^T  (lane: row r, columns 4cg..4cg+3;
+      // row values streamed from LDS, a few k at a time, to bound live registers)
+      double lo[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int k = 0; k < 16; k++) {
+        const double av = sm.L[rb + r][c0 + k];
+#pragma unroll
+        for (int q = 0; q < 4; q++) lo[q] = fma(av, sm.XcT[k][4 * cg + q], lo[q]);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; q++) sm.L[rb + r][c0 + 4 * cg + q] = lo[q];
+      wave_lds_sync();
+      // block row wv of inv(L): X[wv][K] -= L[wv][cb] X[cb][K] (K < cb), X[wv][cb] = -L[wv][cb] inv(L_cb)
+      for (int K = 0; K <= cb; K++) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (K < cb) {
+#pragma unroll 4
+          for (int k = 0; k < 16; k++) {
+            const double lv = sm.L[rb + r][c0 + k];
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[q] = fma(lv, sm.L[16 * K + 4 * cg + q][c0 + k], acc[q]);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; q++) sm.L[16 * K + 4 * cg + q][rb + r] -= acc[q];
+        } else {
+#pragma unroll 4
+          for (int k = 0; k < 16; k++) {
+            const double lv = sm.L[rb + r][c0 + k];
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[q] = fma(lv, sm.XcT[4 * cg + q][k], acc[q]);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; q++) sm.L[16 * K + 4 * cg + q][rb + r] = -acc[q];
+        }
+      }
+    }
+    __syncthreads();
+    // trailing lower triangle, in place: 4 x 4 tile (rows 4ty.., columns 4tx..)
+    // -= L[rows][cb] L[columns][cb]^T (upper halves of diagonal tiles untouched)
+    if ((tx >> 2) > cb && ty >= tx) {
+      double t[4][4];
 #pragma unroll
       for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) sm.S[4 * ty + i][j] = a[i][j];
-    }
-    __syncthreads();
-    if (tid < 64) {
-      const int r = tid;
-      double s4[4];
-#pragma unroll
-      for (int j = 0; j < 4; j++) s4[j] = sm.S[r][j];
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int c = 4 * cb + j;
-        const double piv = __shfl(s4[j], c, 64);
-        const bool ok = piv > 0.0;
-        if (r == c && !ok) bad = true;
-        const double d = sqrt(ok ? piv : 1.0);
-        if (r == c) s4[j] = d;
-        else if (r > c) s4[j] = s4[j] / d;
-#pragma unroll
-        for (int jj = j + 1; jj < 4; jj++) {
-          const double lc = __shfl(s4[j], 4 * cb + jj, 64);
-          if (r >= 4 * cb + jj) s4[jj] = fma(-s4[j], lc, s4[jj]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; j++) sm.S[r][j] = s4[j];
-    }
-    __syncthreads();
-    if (tx == cb) {
-      if (ty >= cb) {
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) a[i][j] = sm.S[4 * ty + i][j];
-      }
-    } else if (tx > cb && ty >= tx) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
+        for (int j = 0; j < 4; j++) t[i][j] = 0.0;
+#pragma unroll 4
+      for (int k = 0; k < 16; k++) {
         double lr[4], lm[4];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-          lr[i] = sm.S[4 * ty + i][k];
-          lm[i] = sm.S[4 * tx + i][k];
+          lr[i] = sm.L[4 * ty + i][c0 + k];
+          lm[i] = sm.L[4 * tx + i][c0 + k];
         }
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-          for (int j = 0; j < 4; j++)
-            if (ty != tx || j <= i) a[i][j] = fma(-lr[i], lm[j], a[i][j]);  // skip a diagonal tile's upper part
+          for (int j = 0; j < 4; j++) t[i][j] = fma(lr[i], lm[j], t[i][j]);
       }
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          if (ty != tx || j <= i) sm.L[4 * ty + i][4 * tx + j] -= t[i][j];
     }
-    __syncthreads();
   }
   if (bad) {
     set_flag(flag, FPDE_ENOTSPD);
     atomicCAS((unsigned long long *)aux, ~0ull, (unsigned long long)k0);
   }
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int r = 4 * ty + i, m = 4 * tx + j;
-      const double v = (m <= r) ? a[i][j] : 0.0;
-      sm.L[r][m] = v;
-      if (r < nb && m < nb && m <= r) A[(k0 + r) * lda + k0 + m] = (T)v;
-    }
-  // inverse: X = I, then blocks of 4 rows: the owners of rows 4cb..4cb+3
-  // finish them with the 4 x 4 diagonal block of L (inside one thread's
-  // tile), publish them, and the rows below subtract L[r, block] X[block, :]
-  double x[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) x[i][j] = (4 * ty + i == 4 * tx + j) ? 1.0 : 0.0;
-  __syncthreads();
-#pragma unroll 1
-  for (int cb = 0; cb < 16; cb++) {
-    if (ty == cb && tx <= cb) {  // X is lower triangular: columns beyond stay 0
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int c = 4 * cb + i;
-#pragma unroll
-        for (int k = 0; k < i; k++) {
-          const double l = sm.L[c][4 * cb + k];
-#pragma unroll
-          for (int j = 0; j < 4; j++) x[i][j] = fma(-l, x[k][j], x[i][j]);
-        }
-        const double dinv = 1.0 / sm.L[c][c];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          x[i][j] = x[i][j] * dinv;
-          sm.rowb4[i][4 * tx + j] = x[i][j];
-        }
-      }
-    }
-    __syncthreads();
-    if (ty > cb && tx <= cb) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        double xr[4], l[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) xr[j] = sm.rowb4[k][4 * tx + j];
-#pragma unroll
-        for (int i = 0; i < 4; i++) l[i] = sm.L[4 * ty + i][4 * cb + k];
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) x[i][j] = fma(-l[i], xr[j], x[i][j]);
-      }
-    }
-    __syncthreads();
+  // L to A (lower part inside the matrix), X row-major to Linv, X^T to LinvT
+#pragma unroll 4
+  for (int it = 0; it < 16; it++) {
+    const int idx = tid + 256 * it, r = idx >> 6, m = idx & 63;
+    const double lrm = sm.L[r][m], lmr = sm.L[m][r], dr = sm.dinv[r];
+    if (r < nb && m < nb && m <= r) A[(k0 + r) * lda + k0 + m] = (T)lrm;
+    Linv[idx] = (T)((m < r) ? lmr : ((m == r) ? dr : 0.0));   // X[r][m]
+    LinvT[idx] = (T)((r < m) ? lrm : ((m == r) ? dr : 0.0));  // X[m][r]
   }
-#pragma unroll
-  for (int i = 0; i < 4; i++)
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      Linv[(4 * ty + i) * NB + 4 * tx + j] = (T)x[i][j];
-      LinvT[(4 * tx + j) * NB + 4 * ty + i] = (T)x[i][j];
-    }
 }
 
 // Factor the diagonal block at (k0, k0) on its own (the first panel).
@@ -209,10 +263,17 @@ __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t l
                                                     int64_t *aux) {
   __shared__ DiagSmem sm;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx >> 6, m = idx & 63;
+  T av[16];  // all loads first (indices clamped into the block), then the selects
+#pragma unroll
+  for (int it = 0; it < 16; it++) {
+    const int idx = threadIdx.x + 256 * it, r = idx >> 6, m = idx & 63;
+    av[it] = A[(k0 + (r < nb ? r : nb - 1)) * lda + k0 + (m < nb ? m : nb - 1)];
+  }
+#pragma unroll
+  for (int it = 0; it < 16; it++) {
+    const int idx = threadIdx.x + 256 * it, r = idx >> 6, m = idx & 63;
     double v;
-    if (r < nb && m < nb) v = (m <= r) ? (double)A[(k0 + r) * lda + k0 + m] : 0.0;
+    if (r < nb && m < nb) v = (m <= r) ? (double)av[it] : 0.0;
     else v = (r == m) ? 1.0 : 0.0;
     sm.L[r][m] = v;
   }
@@ -241,23 +302,44 @@ __global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t l
 
 // 64 x 64 tile product acc = P Q^T over a 64-deep inner dimension, P and Q
 // given as row pointers with leading dimensions; rows past `prow`/`qrow`
-// read as zero.  256 threads, 4 x 4 outputs each (rows ty + 16a, cols tx + 16b).
+// (>= 1) read as zero.  256 threads, 4 x 4 outputs each (rows ty + 16a,
+// cols tx + 16b).  The two 32-deep chunks are staged through LDS; the second
+// chunk's global loads are issued before the first chunk's arithmetic, and
+// every load reads a valid address (rows clamped, then zeroed), so a
+// thread's loads are all in flight together.
+template <class T>
+__device__ __forceinline__ void stage_load(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
+                                           int64_t ldq, int qrow, int kk, int lr, int lc, T (&pr)[8], T (&qr)[8]) {
+#pragma unroll
+  for (int it = 0; it < 8; it++) {
+    const int rr = lr + 8 * it;
+    pr[it] = P[(int64_t)(rr < prow ? rr : prow - 1) * ldp + kk + lc];
+    qr[it] = Q[(int64_t)(rr < qrow ? rr : qrow - 1) * ldq + kk + lc];
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
                                         int64_t ldq, int qrow, T (*sP)[33], T (*sQ)[33], T acc[4][4]) {
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
+  const int lc = tid & 31, lr = tid >> 5;  // this thread stages rows lr + 8 it, column lc of a chunk
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = (T)0;
+  T pr[8], qr[8];
+  stage_load<T>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
+#pragma unroll
   for (int kk = 0; kk < NB; kk += 32) {
-    for (int idx = tid; idx < 64 * 32; idx += 256) {
-      const int rr = idx >> 5, c = idx & 31;
-      sP[rr][c] = (rr < prow) ? P[rr * ldp + kk + c] : (T)0;
-      sQ[rr][c] = (rr < qrow) ? Q[rr * ldq + kk + c] : (T)0;
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+      const int rr = lr + 8 * it;
+      sP[rr][lc] = rr < prow ? pr[it] : (T)0;
+      sQ[rr][lc] = rr < qrow ? qr[it] : (T)0;
     }
     __syncthreads();
+    if (kk + 32 < NB) stage_load<T>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
 #pragma unroll 4
     for (int k = 0; k < 32; k++) {
       T av[4], bv[4];
@@ -322,6 +404,16 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
   T acc[4][4];
   tile_nt<T>(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sm.g.sP, sm.g.sQ, acc);
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  // this thread's 16 entries of C, read before any is used (indices clamped
+  // into the matrix so the loads need no guard)
+  T cv[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int64_t r = ri + ty + 16 * a, c = cj + tx + 16 * b;
+      cv[a][b] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
+    }
   if (x == 0) {
     const int nb = prow;
 #pragma unroll
@@ -330,7 +422,7 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
       for (int b = 0; b < 4; b++) {
         const int r = ty + 16 * a, c = tx + 16 * b;
         double v;
-        if (r < nb && c < nb) v = (c <= r) ? (double)A[(ri + r) * lda + ri + c] - (double)acc[a][b] : 0.0;
+        if (r < nb && c < nb) v = (c <= r) ? (double)cv[a][b] - (double)acc[a][b] : 0.0;
         else v = (r == c) ? 1.0 : 0.0;
         sm.d.L[r][c] = v;
       }
@@ -341,12 +433,10 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
 #pragma unroll
   for (int a = 0; a < 4; a++) {
     const int64_t r = ri + ty + 16 * a;
-    if (r >= n) continue;
 #pragma unroll
     for (int b = 0; b < 4; b++) {
       const int64_t c = cj + tx + 16 * b;
-      if (c >= n || c > r) continue;
-      A[r * lda + c] -= acc[a][b];
+      if (r < n && c < n && c <= r) A[r * lda + c] = cv[a][b] - acc[a][b];
     }
   }
 }
@@ -401,11 +491,6 @@ __device__ __forceinline__ double wave_sum16(const double (&a)[16]) {
   return e;
 }
 
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
 
 // forward: x_b = inv(L_bb) (y_b - sum_{c<b} L_bc x_c).  Wave w owns rows
 // 16w..16w+15 of the block row; lane = column within block c.
