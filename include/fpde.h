@@ -234,7 +234,11 @@ int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
  *   out[0] half-rays (6 G), out[1] derivative-vector entries over all
  *   half-rays, out[2] sum over (g, i) of |L_gi| |R_gi| (entry pairs the
  *   accumulation multiplies), out[3] largest number of entries of one
- *   half-ray.  host, 4 int64.  Synchronises `stream`.
+ *   half-ray, out[4] tubes (groups of chords of one axis through one cell of
+ *   the orthogonal plane, Sec. 2.3), out[5] sum over tubes of the number of
+ *   nodes the tube's chords touch, out[6] the largest such number, out[7]
+ *   bytes of the per-tube block scratch the accumulation uses.
+ *   host, 8 int64.  Synchronises `stream`.
  */
 int fpde_plan_info(fpde_mesh *m, int quad_points, int64_t *out, void *stream);
 

@@ -169,9 +169,11 @@ class Mesh:
         _check(_lib().fpde_plan(self._h, quad_points, max_steps, _stream(stream)), "fpde_plan")
 
     def plan_info(self, quad_points: int, stream=None) -> dict:
-        out = np.zeros(4, dtype=np.int64)
+        out = np.zeros(8, dtype=np.int64)
         _check(_lib().fpde_plan_info(self._h, quad_points, _np(out), _stream(stream)), "fpde_plan_info")
-        return {"half_rays": int(out[0]), "entries": int(out[1]), "pairs": int(out[2]), "max_entries": int(out[3])}
+        return {"half_rays": int(out[0]), "entries": int(out[1]), "pairs": int(out[2]), "max_entries": int(out[3]),
+                "tubes": int(out[4]), "tube_nodes": int(out[5]), "max_tube_nodes": int(out[6]),
+                "block_bytes": int(out[7])}
 
     def timing(self, enable: bool):
         _check(_lib().fpde_timing(self._h, 1 if enable else 0), "fpde_timing")

@@ -1,16 +1,12 @@
-// Accumulation of the dense stiffness matrix, load vector, matrix-free
-// product and adjoint sums (Sec. 2.1: K = sum_E K_E with element quadrature).
+// Load vector, matrix-free product and adjoint sums (Sec. 2.1: K = sum_E K_E
+// with element quadrature); the dense accumulation of K itself is in the
+// tube pass (one block per group of parallel chords).
 //
 //   K_jk = sum_i K_i c_alpha sum_g w_g [R_gi(j) L_gi(k) + L_gi(j) R_gi(k)]
 //
-// Row-owner form: row j gathers every derivative-vector entry that sits on
-// node j (the node -> entry transpose built once per mesh and rule) and adds
-// W * value * (the partner half-ray's whole vector) into an FP64 row held in
-// LDS; the finished row is written to HBM once, coalesced.  Each entry of K
-// is therefore written exactly once and no global atomics are used.  The
-// template of Sec. 2.3 (the 0/1 pattern of K) appears here as the partner
-// lists themselves: only node pairs that share a Gauss-point line are ever
-// touched.
+// The matrix-free product y = K x takes the dots of every half-ray vector
+// with x and then, row by row, gathers W * value * (partner's dot) over the
+// node -> entry transpose built once per mesh and rule.
 #include <cmath>
 
 #include "fpde_internal.h"
@@ -30,110 +26,6 @@ struct ContractArgs {
   double KC0, KC1, KC2;   // K_i c_alpha
   __device__ __forceinline__ double KC(int i) const { return i == 0 ? KC0 : (i == 1 ? KC1 : KC2); }
 };
-
-// One workgroup (4 wavefronts) per row j.  A wavefront takes 64 incidences
-// of the row at a time: each lane loads one incidence's flattened record and
-// forms its coefficient W value_e; then the two half-wavefronts walk two
-// partner vectors at once, 32 consecutive entries per step (coalesced loads),
-// adding coef * value into the LDS row.  Within one instruction the lanes of
-// a half-wavefront hit distinct columns.
-template <class TO>
-__global__ void __launch_bounds__(256) k_contract_rows(ContractArgs c, TO *__restrict__ A) {
-  extern __shared__ double acc[];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int half = lane >> 5, sub = lane & 31;
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous range of (Morton-ordered) rows so that rows sharing partner
-  // vectors share that XCD's L2.
-  const int64_t per_xcd = (c.ndof + 7) / 8;
-  const int64_t slots = 8 * per_xcd;
-  for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
-    const int64_t row = (b % 8) * per_xcd + b / 8;
-    if (row >= c.ndof) continue;
-    const int64_t p0 = c.row_off[row], p1 = c.row_off[row + 1];
-    for (int64_t c0 = 0; c0 < c.ndof; c0 += c.chunk) {
-      const int64_t cw = (c.ndof - c0) < c.chunk ? (c.ndof - c0) : c.chunk;
-      for (int64_t j = tid; j < cw; j += blockDim.x) acc[j] = 0.0;
-      __syncthreads();
-      for (int64_t pb = p0 + 64 * wave; pb < p1; pb += 256) {
-        const int64_t p = pb + lane;
-        int po = 0, pl = 0;
-        double coef = 0.0;
-        if (p < p1) {
-          const int4 mt = c.meta[p];
-          po = mt.y;
-          pl = mt.z >> 2;
-          coef = c.w[p] * c.KC(mt.z & 3) * c.ent_val[mt.x];
-        }
-        const int nv = (int)((p1 - pb) < 64 ? (p1 - pb) : 64);
-        // Software pipeline over groups of four incidence pairs (half-wave h
-        // takes incidences t + 2u + h, u = 0..3): the first 32 entries of the
-        // next group are loaded before the current group's LDS adds, so eight
-        // partner vectors are in flight per wavefront.  Every lane joins each
-        // shuffle (a lane masked off by a condition would not deliver its
-        // value to the lanes reading from it).
-        int spo[4], spl[4], dq[4];
-        double scf[4], vq[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const int src = 2 * u + half;
-          spo[u] = __shfl(po, src & 63, 64);
-          const int l = __shfl(pl, src & 63, 64);
-          scf[u] = __shfl(coef, src & 63, 64);
-          spl[u] = src < nv ? l : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-          dq[u] = sub < spl[u] ? c.ent_dof[spo[u] + sub] : 0;
-          vq[u] = sub < spl[u] ? c.ent_val[spo[u] + sub] : 0.0;
-        }
-        for (int t = 0; t < nv; t += 8) {
-          int npo[4], npl[4], ndq[4];
-          double ncf[4], nvq[4];
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            const int src = t + 8 + 2 * u + half;
-            npo[u] = __shfl(po, src & 63, 64);
-            const int l = __shfl(pl, src & 63, 64);
-            ncf[u] = __shfl(coef, src & 63, 64);
-            npl[u] = src < nv ? l : 0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            ndq[u] = sub < npl[u] ? c.ent_dof[npo[u] + sub] : 0;
-            nvq[u] = sub < npl[u] ? c.ent_val[npo[u] + sub] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            if (sub < spl[u]) {
-              const int64_t d = (int64_t)dq[u] - c0;
-              if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf[u] * vq[u]);
-            }
-            for (int k = sub + 32; k < spl[u]; k += 32) {  // long partner vectors
-              const int dk = c.ent_dof[spo[u] + k];
-              const double vk = c.ent_val[spo[u] + k];
-              const int64_t d = (int64_t)dk - c0;
-              if ((uint64_t)d < (uint64_t)cw) atomicAdd(&acc[d], scf[u] * vk);
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            spo[u] = npo[u];
-            spl[u] = npl[u];
-            scf[u] = ncf[u];
-            dq[u] = ndq[u];
-            vq[u] = nvq[u];
-          }
-        }
-      }
-      __syncthreads();
-      TO *out = A + row * c.lda + c0;
-      for (int64_t j = tid; j < cw; j += blockDim.x) out[j] = (TO)acc[j];
-      __syncthreads();
-    }
-  }
-}
 
 struct LoadArgs {
   const int32_t *vert_of_dof, *vt_off, *vt_tet, *tet;
@@ -266,22 +158,6 @@ static ContractArgs contract_args(fpde_mesh *m, const Plan &P, const fpde_params
   return c;
 }
 
-int launch_contract(fpde_mesh *m, const Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
-  ContractArgs c = contract_args(m, P, p, lda);
-  if (m->ndof == 0) return FPDE_OK;
-  const int64_t slots = 8 * ((m->ndof + 7) / 8);  // multiple of 8 keeps each slot on one XCD
-  const unsigned grid = (unsigned)(slots < 65536 ? slots : 65536);
-  const size_t lds = sizeof(double) * (size_t)c.chunk;
-  const long t = timer_begin(m, s);
-  if (p->precision == FPDE_MIXED)
-    k_contract_rows<float><<<grid, 256, lds, s>>>(c, (float *)A);
-  else
-    k_contract_rows<double><<<grid, 256, lds, s>>>(c, (double *)A);
-  timer_end(m, FPDE_STAGE_CONTRACT, t, s);
-  FPDE_HIP(hipGetLastError());
-  return FPDE_OK;
-}
-
 int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_gauss, hipStream_t s) {
   if (m->ndof == 0) return FPDE_OK;
   LoadArgs a{};
@@ -342,7 +218,7 @@ extern "C" int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_
   Plan *P = nullptr;
   FPDE_TRY(plan_for(m, p->quad_points, p->max_steps, s, &P));
   FPDE_TRY(ensure_values(m, P, p->alpha, s));
-  FPDE_TRY(launch_contract(m, *P, p, A, lda, s));
+  FPDE_TRY(launch_contract_tubes(m, *P, p, A, lda, s));
   if (b) FPDE_TRY(launch_load(m, p, b, f_gauss, s));
   int f = take_flag(m, s);
   if (f != 0) {

@@ -36,6 +36,25 @@ int quad_rule(int nq, QuadRule *out);  // FPDE_OK or FPDE_EINVAL
 // offset of the nq-point table inside fpde_mesh::rules
 inline int rule_offset(int nq) { return nq == 4 ? 0 : 4 * 5; }
 
+// Tubes of the accumulation: pairs (g, i) grouped by axis i and the cell of
+// x_g in the plane orthogonal to e_i; U_T = the tube's nodes (sorted).
+struct TubePlan {
+  double cell = 0.0;              // cell edge
+  int64_t n_tubes = 0, n_u = 0, n_items = 0, blk_n = 0, max_u = 0;
+  int32_t *pair_sorted = nullptr; // 3 G pair ids i * G + g, tube by tube
+  int4 *pm = nullptr;             // per sorted pair {l first entry, r first entry, |l|, |r| | axis << 30}
+  double *pw = nullptr;           // per sorted pair: w_g
+  int64_t *tube_off = nullptr;    // n_tubes + 1 into the sorted pairs
+  int64_t *u_off = nullptr;       // n_tubes + 1 into tube_u
+  int32_t *tube_u = nullptr;      // n_u: U_T, increasing
+  int32_t *ent_slot = nullptr;    // n_ent: position of the entry's node in its tube's U_T
+  int64_t *row_off = nullptr;     // n_dof + 1 into row_ts
+  int2 *row_ts = nullptr;         // n_u: (tube, slot) places of each node, grouped by node
+  int4 *items = nullptr;          // pass-1 work: {tube, first block row, rows, |U_T|}
+  int64_t *blk_off = nullptr;     // n_tubes + 1: offsets (doubles) of the |U_T|^2 blocks
+  double *blk = nullptr;          // blk_n doubles of block scratch, allocated on first use
+};
+
 // Symbolic phase of one rule: derivative-vector sizes and the row transpose.
 // Half-ray index (direction-major): h = dir * G + g, dir = 2 i + side.
 struct Plan {
@@ -58,6 +77,7 @@ struct Plan {
   double *adj = nullptr;      // 4 n_half scratch for the adjoint dots
   int64_t pairs = 0;          // sum over (g, i) of |L| |R|
   int64_t max_ent = 0;        // largest entry count of one half-ray
+  TubePlan tubes;
 };
 
 // HIP events around stage launches on the caller's stream (fpde_timing).
@@ -144,6 +164,10 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out);
 int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s);
 int check_params(const fpde_mesh *m, const fpde_params *p);
 void free_plan(Plan &P);
+// tube plan of a rule whose entries exist (cell edge = kappa x mean element edge)
+int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s);
+void free_tubes(TubePlan &tp);
+int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s);
 
 // Stage timing: t = timer_begin(m, s); ...launches...; timer_end(m, stage, t, s)
 long timer_begin(fpde_mesh *m, hipStream_t s);

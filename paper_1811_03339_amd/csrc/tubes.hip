@@ -1,0 +1,679 @@
+// Accumulation of the dense stiffness matrix by tubes (Sec. 2.1 assembly,
+// Sec. 2.3 sparsity).
+//
+// Every Gauss point g and axis i contribute the rank-2 update
+//   A += w_g K_i c_alpha (l r^T + r l^T)
+// where l and r are the derivative vectors of the two half-rays of the
+// chord through x_g parallel to e_i.  Chords of nearby Gauss points run
+// through nearly the same elements, so the pairs (g, i) are grouped into
+// tubes: axis i and the square cell of the plane orthogonal to e_i that
+// holds x_g.  A tube's chords touch a small node set U_T (the union of its
+// half-rays' entries), and its whole contribution is a dense |U_T| x |U_T|
+// block.
+//
+//   plan (once per mesh and rule, independent of alpha and K):
+//     tubes, the sorted node list U_T of each tube, for every entry its slot
+//     (position of its node in U_T), and for every row the (tube, slot)
+//     places where that node appears;
+//   pass 1: one workgroup per (tube, band of block rows) reads the tube's
+//     entries once and adds every product l_p r_q into an LDS band of the
+//     block; the band goes to a scratch block in HBM;
+//   pass 2: one workgroup per row of A sums that row's slices of the tube
+//     blocks into an LDS row and writes the row once.
+// Each entry is read once per band of its tube (not once per node of its
+// partner half-ray), and A is written once, without global atomics.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "fpde_internal.h"
+
+namespace fpde {
+
+namespace {
+
+constexpr int kHash = 8192;         // LDS hash slots per tube (int32 keys)
+constexpr int kMaxU = kHash / 2;    // largest node set a tube may have
+constexpr int kBandDoubles = 20160;  // LDS doubles of one pass-1 band (157.5 KB: one band for |U_T| <= 141)
+
+// row stride of a band in LDS: odd, so the rows of one column fall in distinct bank pairs
+__host__ __device__ inline int band_stride(int U) { return U | 1; }
+
+inline unsigned nblocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Pair id P = i * G + g.  Key = tube cell of x_g in the plane orthogonal to
+// e_i; x_g summed in the walk's order ((0 + b0 v0) + b1 v1) + ...
+__global__ void k_pair_keys(const int32_t *__restrict__ tet, const double *__restrict__ xyz,
+                            const double *__restrict__ qbary, int nq, int64_t G, double lo0, double lo1, double lo2,
+                            double inv_c, int ncell, uint32_t *__restrict__ key, int32_t *__restrict__ val) {
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= 3 * G) return;
+  const int i = (int)(P / G);
+  const int64_t g = P - (int64_t)i * G;
+  const int64_t t = g / nq;
+  const int q = (int)(g - t * nq);
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int m = 0; m < 4; m++) {
+    const double b = qbary[4 * q + m];
+    const double *v = xyz + 3 * (int64_t)tet[4 * t + m];
+    for (int d = 0; d < 3; d++) x[d] = x[d] + b * v[d];
+  }
+  const double lo[3] = {lo0, lo1, lo2};
+  const int a1 = (i + 1) % 3, a2 = (i + 2) % 3;
+  int c1 = (int)floor((x[a1] - lo[a1]) * inv_c), c2 = (int)floor((x[a2] - lo[a2]) * inv_c);
+  c1 = c1 < 0 ? 0 : (c1 >= ncell ? ncell - 1 : c1);
+  c2 = c2 < 0 ? 0 : (c2 >= ncell ? ncell - 1 : c2);
+  key[P] = ((uint32_t)i * (uint32_t)ncell + (uint32_t)c1) * (uint32_t)ncell + (uint32_t)c2;
+  val[P] = (int32_t)P;
+}
+
+__global__ void k_heads(const uint32_t *__restrict__ key, int64_t n, int32_t *__restrict__ head) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) head[k] = (k == 0 || key[k] != key[k - 1]) ? 1 : 0;
+}
+
+// tube_off[T] = first sorted position of tube T; tube_off[n_tubes] = n
+__global__ void k_tube_off(const int32_t *__restrict__ head, const int32_t *__restrict__ tid, int64_t n,
+                           int64_t *__restrict__ tube_off) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && head[k]) tube_off[tid[k]] = k;
+  if (k == n - 1) tube_off[tid[k] + head[k]] = n;
+}
+
+// per sorted pair: {l first entry, r first entry, |l|, |r| | axis << 30} and w_g
+__global__ void k_pair_meta(const int32_t *__restrict__ pair_sorted, int64_t n, int64_t G, int nq,
+                            const int64_t *__restrict__ off, const double *__restrict__ qw,
+                            const double *__restrict__ vol, int4 *__restrict__ pm, double *__restrict__ pw) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t P = pair_sorted[k];
+  const int i = (int)(P / G);
+  const int64_t g = P - (int64_t)i * G;
+  const int64_t hl = (int64_t)(2 * i) * G + g, hr = hl + G;
+  int4 m;
+  m.x = (int)off[hl];
+  m.y = (int)off[hr];
+  m.z = (int)(off[hl + 1] - off[hl]);
+  m.w = (int)(off[hr + 1] - off[hr]) | (i << 30);
+  pm[k] = m;
+  const int64_t t = g / nq;
+  pw[k] = qw[g - t * nq] * vol[t];
+}
+
+__device__ __forceinline__ unsigned hash_slot(int32_t d) { return ((uint32_t)d * 2654435761u) >> (32 - 13); }
+
+// insert every node of the tube's entries into the LDS hash; returns through
+// `cnt` the number of distinct nodes (kMaxU + 1 on overflow)
+__device__ void tube_insert(int32_t *hk, int *cnt, const int4 *__restrict__ pm, int64_t k0, int64_t k1,
+                            const int32_t *__restrict__ ent_dof) {
+  for (int j = threadIdx.x; j < kHash; j += blockDim.x) hk[j] = -1;
+  if (threadIdx.x == 0) *cnt = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t k = k0 + wave; k < k1; k += nw) {
+    const int4 m = pm[k];
+    const int nl = m.z, nr = m.w & 0x3fffffff;
+    for (int e = lane; e < nl + nr; e += 64) {
+      const int32_t d = ent_dof[e < nl ? m.x + e : m.y + (e - nl)];
+      unsigned h = hash_slot(d);
+      for (int probe = 0; probe < kHash; probe++) {
+        const int32_t old = atomicCAS(&hk[h], -1, d);
+        if (old == -1) {
+          atomicAdd(cnt, 1);
+          break;
+        }
+        if (old == d) break;
+        h = (h + 1) & (kHash - 1);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_tube_count(const int64_t *__restrict__ tube_off, const int4 *__restrict__ pm,
+                                                    const int32_t *__restrict__ ent_dof, int64_t *__restrict__ u_cnt,
+                                                    int32_t *flag) {
+  __shared__ int32_t hk[kHash];
+  __shared__ int cnt;
+  const int64_t T = blockIdx.x;
+  tube_insert(hk, &cnt, pm, tube_off[T], tube_off[T + 1], ent_dof);
+  if (threadIdx.x == 0) {
+    u_cnt[T] = cnt;
+    if (cnt > kMaxU) set_flag(flag, FPDE_EUNSUPPORTED);
+  }
+}
+
+// U_T sorted, the slot of every entry, and per-row counts of (tube, slot) places
+__global__ void __launch_bounds__(256) k_tube_fill(const int64_t *__restrict__ tube_off, const int4 *__restrict__ pm,
+                                                   const int32_t *__restrict__ ent_dof,
+                                                   const int64_t *__restrict__ u_off, int32_t *__restrict__ tube_u,
+                                                   int32_t *__restrict__ ent_slot, int64_t *__restrict__ row_cnt) {
+  __shared__ int32_t hk[kHash];
+  __shared__ int32_t su[kMaxU];
+  __shared__ int cnt, cnt2;
+  const int64_t T = blockIdx.x;
+  const int64_t k0 = tube_off[T], k1 = tube_off[T + 1];
+  tube_insert(hk, &cnt, pm, k0, k1, ent_dof);
+  const int U = cnt;
+  int P2 = 1;
+  while (P2 < U) P2 <<= 1;
+  if (threadIdx.x == 0) cnt2 = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < kHash; j += blockDim.x)
+    if (hk[j] >= 0) su[atomicAdd(&cnt2, 1)] = hk[j];
+  __syncthreads();
+  for (int j = U + threadIdx.x; j < P2; j += blockDim.x) su[j] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort of su[0, P2)
+  for (int size = 2; size <= P2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int j = threadIdx.x; j < P2; j += blockDim.x) {
+        const int o = j ^ stride;
+        if (o > j) {
+          const bool up = (j & size) == 0;
+          const int32_t x = su[j], y = su[o];
+          if ((x > y) == up) {
+            su[j] = y;
+            su[o] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const int64_t ub = u_off[T];
+  for (int j = threadIdx.x; j < U; j += blockDim.x) {
+    tube_u[ub + j] = su[j];
+    atomicAdd((unsigned long long *)&row_cnt[su[j]], 1ull);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t k = k0 + wave; k < k1; k += nw) {
+    const int4 m = pm[k];
+    const int nl = m.z, nr = m.w & 0x3fffffff;
+    for (int e = lane; e < nl + nr; e += 64) {
+      const int64_t ei = e < nl ? m.x + e : m.y + (e - nl);
+      const int32_t d = ent_dof[ei];
+      int lo = 0, hi = U - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (su[mid] < d) lo = mid + 1;
+        else hi = mid;
+      }
+      ent_slot[ei] = lo;
+    }
+  }
+}
+
+__global__ void k_row_places(const int64_t *__restrict__ u_off, int64_t n_tubes, const int32_t *__restrict__ tube_u,
+                             int64_t *__restrict__ cursor, int2 *__restrict__ row_ts) {
+  const int64_t T = blockIdx.x;
+  if (T >= n_tubes) return;
+  const int64_t u0 = u_off[T], U = u_off[T + 1] - u0;
+  for (int64_t s = threadIdx.x; s < U; s += blockDim.x) {
+    const int32_t d = tube_u[u0 + s];
+    const unsigned long long pos = atomicAdd((unsigned long long *)&cursor[d], 1ull);
+    row_ts[pos] = make_int2((int)T, (int)s);
+  }
+}
+
+// pass-1 work items {tube, first block row, rows}
+__global__ void k_bands(const int64_t *__restrict__ u_off, int64_t n_tubes, const int64_t *__restrict__ band_off,
+                        int4 *__restrict__ items) {
+  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= n_tubes) return;
+  const int U = (int)(u_off[T + 1] - u_off[T]);
+  const int Up = band_stride(U);
+  const int R = U > 0 ? (kBandDoubles / Up < U ? kBandDoubles / Up : U) : 1;
+  int64_t w = band_off[T];
+  for (int r0 = 0; r0 < U; r0 += R) items[w++] = make_int4((int)T, r0, (U - r0) < R ? (U - r0) : R, U);
+}
+
+__global__ void k_band_count(const int64_t *__restrict__ u_off, int64_t n_tubes, int64_t *__restrict__ nb,
+                             int64_t *__restrict__ usq) {
+  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= n_tubes) return;
+  const int64_t U = u_off[T + 1] - u_off[T];
+  const int64_t Up = band_stride((int)U);
+  const int64_t R = U > 0 ? (kBandDoubles / Up < U ? kBandDoubles / Up : U) : 1;
+  nb[T] = U > 0 ? (U + R - 1) / R : 0;
+  usq[T] = U * U;
+}
+
+struct AccumArgs {
+  const int64_t *tube_off;
+  const int4 *pm;
+  const double *pw;
+  const int4 *items;
+  const int32_t *ent_slot;
+  const double *ent_val;
+  const int64_t *blk_off;
+  double *blk;
+  double KC0, KC1, KC2;
+};
+
+__device__ __forceinline__ double read_lane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// A pair held in registers: entry `lane` and `lane + 64` of l and of r.
+struct PairRegs {
+  int4 m;
+  double w;
+  int ls[2], rs[2];
+  double lv[2], rv[2];
+};
+
+constexpr int kRegEntries = 128;  // entries per half-ray the register path holds
+
+__device__ __forceinline__ int pair_nl(const int4 &m) { return m.z; }
+__device__ __forceinline__ int pair_nr(const int4 &m) { return m.w & 0x3fffffff; }
+
+__device__ __forceinline__ void load_entries(PairRegs &p, const int32_t *__restrict__ slot,
+                                             const double *__restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  const int nl = pair_nl(p.m), nr = pair_nr(p.m);
+  // indices clamped to a valid entry (the pair's first, or entry 0 for an
+  // empty side, whose offset may equal the entry count) so every load is in
+  // bounds; lanes past the end are masked by the counts when used
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int kl = 64 * h + lane;
+    const int il = nl > 0 ? p.m.x + (kl < nl ? kl : 0) : 0;
+    const int ir = nr > 0 ? p.m.y + (kl < nr ? kl : 0) : 0;
+    p.ls[h] = slot[il];
+    p.lv[h] = val[il];
+    p.rs[h] = slot[ir];
+    p.rv[h] = val[ir];
+  }
+}
+
+// Row-side entries one per lane (in-band ones active); the column side is
+// swept one entry at a time, broadcast with readlane:
+//   acc[s_row - r0][s_col] += v_row (w v_col).
+// One LDS update per column touches one column of distinct rows: with an
+// odd row stride these land in distinct bank pairs.
+// Forces v to be computed at this point with the current (full) lane mask.
+__device__ __forceinline__ void in_all_lanes(int &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void in_all_lanes(double &v) { asm volatile("" : "+v"(v)); }
+
+// cv_reg already carries the pair weight; ncol is wave-uniform.  The column
+// registers are read with readlane from lanes that may be masked off below:
+// they are materialised in every lane before the branch (otherwise the
+// compiler may sink their loads into it, leaving inactive lanes stale).
+__device__ __forceinline__ void sweep_cols(double *acc, int rowbase, double xv, bool xok, int cs_reg,
+                                           double cv_reg, int ncol) {
+  in_all_lanes(cs_reg);
+  in_all_lanes(cv_reg);
+  if (xok) {
+#pragma unroll 4
+    for (int j = 0; j < ncol; j++) {
+      const int cs = __builtin_amdgcn_readlane(cs_reg, j);
+      const double cv = read_lane_f64(cv_reg, j);
+      atomicAdd(&acc[rowbase + cs], xv * cv);
+    }
+  }
+}
+
+// both roles of one pair from registers (|l|, |r| <= kRegEntries)
+__device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, int R, const PairRegs &p) {
+  const int lane = threadIdx.x & 63;
+  // the pair is the wave's: its counts are uniform (scalar loop bounds)
+  const int nl = __builtin_amdgcn_readfirstlane(pair_nl(p.m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(p.m));
+  // column-side values scaled by the pair weight once
+  const double lw0 = p.lv[0] * p.w, lw1 = p.lv[1] * p.w, rw0 = p.rv[0] * p.w, rw1 = p.rv[1] * p.w;
+#pragma unroll
+  for (int role = 0; role < 2; role++) {
+    const int nrow = role ? nr : nl, ncol = role ? nl : nr;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const int xs = role ? p.rs[h] : p.ls[h];
+      const double xv = role ? p.rv[h] : p.lv[h];
+      const bool xok = 64 * h + lane < nrow && xs >= r0 && xs < r0 + R;
+      if (__ballot(xok) == 0) continue;
+      const int rowbase = (xs - r0) * Up;
+      sweep_cols(acc, rowbase, xv, xok, role ? p.ls[0] : p.rs[0], role ? lw0 : rw0, ncol < 64 ? ncol : 64);
+      if (ncol > 64) sweep_cols(acc, rowbase, xv, xok, role ? p.ls[1] : p.rs[1], role ? lw1 : rw1, ncol - 64);
+    }
+  }
+}
+
+// the same from memory, for pairs with a longer half-ray
+__device__ void pair_products_mem(double *acc, int Up, int r0, int R, const int4 m, double w,
+                                  const int32_t *__restrict__ slot, const double *__restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  const int nl = __builtin_amdgcn_readfirstlane(pair_nl(m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(m));
+  for (int role = 0; role < 2; role++) {
+    const int nrow = role ? nr : nl, ncol = role ? nl : nr;
+    const int erow = role ? m.y : m.x, ecol = role ? m.x : m.y;
+    for (int j0 = 0; j0 < nrow; j0 += 64) {
+      const int ex = erow + (j0 + lane < nrow ? j0 + lane : j0);
+      const int xs = slot[ex];
+      const double xv = val[ex];
+      const bool xok = j0 + lane < nrow && xs >= r0 && xs < r0 + R;
+      if (__ballot(xok) == 0) continue;
+      const int rowbase = (xs - r0) * Up;
+      for (int c0 = 0; c0 < ncol; c0 += 64) {
+        const int ec = ecol + (c0 + lane < ncol ? c0 + lane : c0);
+        const int cn = ncol - c0 < 64 ? ncol - c0 : 64;
+        sweep_cols(acc, rowbase, xv, xok, slot[ec], val[ec] * w, cn);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
+  extern __shared__ double acc[];
+  const int4 it = a.items[blockIdx.x];
+  const int64_t T = it.x;
+  const int r0 = it.y, R = it.z, U = it.w, Up = band_stride(U);
+  for (int j = threadIdx.x; j < R * Up; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  // wave-uniform (readfirstlane), so the pair loop, its metadata and the
+  // column sweeps are scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int64_t k0 = a.tube_off[T], k1 = a.tube_off[T + 1];
+  auto meta = [&](int64_t k, PairRegs &p) {
+    const int64_t kk = k < k1 ? k : k0;
+    p.m = a.pm[kk];
+    p.w = a.pw[kk];
+  };
+  // K_i c_alpha in registers (selected, not indexed, so no memory access sits
+  // behind the pipelined loads)
+  const double kc0 = a.KC0, kc1 = a.KC1, kc2 = a.KC2;
+  auto weight = [kc0, kc1, kc2](const PairRegs &p) {
+    const int axis = (int)((unsigned)p.m.w >> 30);
+    return p.w * (axis == 0 ? kc0 : (axis == 1 ? kc1 : kc2));
+  };
+  // register path, software-pipelined: pair k in registers, the entries of
+  // pair k + nw in flight, the metadata of pair k + 2 nw in flight (issued
+  // first, so each wait leaves the newer loads outstanding)
+  int64_t k = k0 + wave;
+  bool long_pairs = false;
+  if (k < k1) {
+    PairRegs cur, nxt, far;
+    meta(k, cur);
+    load_entries(cur, a.ent_slot, a.ent_val);
+    meta(k + nw, nxt);
+    while (k < k1) {
+      meta(k + 2 * nw, far);
+      load_entries(nxt, a.ent_slot, a.ent_val);
+      PairRegs p = cur;
+      p.w = weight(cur);
+      if (pair_nl(p.m) <= kRegEntries && pair_nr(p.m) <= kRegEntries) pair_products_reg(acc, Up, r0, R, p);
+      else long_pairs = true;
+      cur = nxt;
+      nxt = far;
+      k += nw;
+    }
+  }
+  // pairs with a half-ray longer than the register path holds
+  if (__ballot(long_pairs)) {
+    for (k = k0 + wave; k < k1; k += nw) {
+      PairRegs p;
+      meta(k, p);
+      if (pair_nl(p.m) > kRegEntries || pair_nr(p.m) > kRegEntries)
+        pair_products_mem(acc, Up, r0, R, p.m, weight(p), a.ent_slot, a.ent_val);
+    }
+  }
+  __syncthreads();
+  double *out = a.blk + a.blk_off[T] + (int64_t)r0 * U;
+  for (int j = threadIdx.x; j < R * U; j += blockDim.x) {
+    const int i = j / U, t = j - i * U;
+    out[j] = acc[i * Up + t];
+  }
+}
+
+struct GatherArgs {
+  const int64_t *row_off;
+  const int2 *row_ts;
+  const int64_t *u_off;
+  const int32_t *tube_u;
+  const int64_t *blk_off;
+  const double *blk;
+  int64_t ndof, lda;
+  int chunk;
+};
+
+// A[p, :] = sum over the (tube, slot) places of node p of that slot's row of
+// the tube block, scattered through U_T; rows dealt XCD by XCD in contiguous
+// ranges (workgroups go round-robin to the 8 XCDs).
+template <class TO>
+__global__ void __launch_bounds__(256) k_tube_gather(GatherArgs a, TO *__restrict__ A) {
+  extern __shared__ double racc[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t per_xcd = (a.ndof + 7) / 8;
+  const int64_t slots = 8 * per_xcd;
+  for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
+    const int64_t row = (b % 8) * per_xcd + b / 8;
+    if (row >= a.ndof) continue;
+    const int64_t p0 = a.row_off[row], p1 = a.row_off[row + 1];
+    for (int64_t c0 = 0; c0 < a.ndof; c0 += a.chunk) {
+      const int64_t cw = (a.ndof - c0) < a.chunk ? (a.ndof - c0) : a.chunk;
+      for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) racc[j] = 0.0;
+      __syncthreads();
+      for (int64_t p = p0 + wave; p < p1; p += 4) {
+        const int2 ts = a.row_ts[p];
+        const int64_t u0 = a.u_off[ts.x], U = a.u_off[ts.x + 1] - u0;
+        const double *brow = a.blk + a.blk_off[ts.x] + (int64_t)ts.y * U;
+        for (int64_t t = lane; t < U; t += 64) {
+          const int64_t d = (int64_t)a.tube_u[u0 + t] - c0;
+          const double v = brow[t];
+          if ((uint64_t)d < (uint64_t)cw) atomicAdd(&racc[d], v);
+        }
+      }
+      __syncthreads();
+      TO *out = A + row * a.lda + c0;
+      for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) out[j] = (TO)racc[j];
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace
+
+void free_tubes(TubePlan &tp) {
+  dfree(tp.pair_sorted); dfree(tp.pm); dfree(tp.pw); dfree(tp.tube_off); dfree(tp.u_off); dfree(tp.tube_u); dfree(tp.ent_slot);
+  dfree(tp.row_off); dfree(tp.row_ts); dfree(tp.items); dfree(tp.blk_off); dfree(tp.blk);
+  tp = TubePlan();
+}
+
+int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s) {
+  TubePlan &tp = P.tubes;
+  free_tubes(tp);
+  if (m->ndof == 0 || P.G == 0) return FPDE_OK;
+  const int64_t n = 3 * P.G;
+  if (n >= (int64_t(1) << 31)) return FPDE_EUNSUPPORTED;
+  // cell size from the mean element size: edge of the regular tet of mean volume
+  std::vector<double> xyz(3 * m->nv), vol(m->nt);
+  FPDE_HIP(hipMemcpyAsync(xyz.data(), m->xyz, sizeof(double) * 3 * m->nv, hipMemcpyDeviceToHost, s));
+  FPDE_HIP(hipMemcpyAsync(vol.data(), m->vol, sizeof(double) * m->nt, hipMemcpyDeviceToHost, s));
+  FPDE_HIP(hipStreamSynchronize(s));
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, V = 0.0;
+  for (int64_t v = 0; v < m->nv; v++)
+    for (int d = 0; d < 3; d++) {
+      lo[d] = std::min(lo[d], xyz[3 * v + d]);
+      hi[d] = std::max(hi[d], xyz[3 * v + d]);
+    }
+  for (double x : vol) V += x;
+  const double h = std::cbrt(6.0 * std::sqrt(2.0) * V / (double)m->nt);
+  const double c = kappa * h;
+  double ext = 0.0;
+  for (int d = 0; d < 3; d++) ext = std::max(ext, hi[d] - lo[d]);
+  const int ncell = std::max(1, (int)std::ceil(ext / c) + 1);
+  if ((double)3 * ncell * ncell >= 4294967295.0) return FPDE_EUNSUPPORTED;
+  tp.cell = c;
+
+  uint32_t *key = nullptr, *key2 = nullptr;
+  int32_t *val = nullptr, *head = nullptr, *tid = nullptr;
+  int64_t *u_cnt = nullptr, *row_cnt = nullptr, *cursor = nullptr, *nb = nullptr, *usq = nullptr,
+          *band_off = nullptr;
+  void *tmp = nullptr;
+  size_t tmp_bytes = 0;
+  auto cleanup = [&]() {
+    dfree(key); dfree(key2); dfree(val); dfree(head); dfree(tid);
+    dfree(u_cnt); dfree(row_cnt); dfree(cursor); dfree(nb); dfree(usq); dfree(band_off);
+    if (tmp) (void)hipFree(tmp);
+    tmp = nullptr;
+  };
+  auto fail = [&](int code) {
+    cleanup();
+    free_tubes(tp);
+    return code;
+  };
+  auto scratch = [&](size_t need) -> int {
+    if (need <= tmp_bytes) return FPDE_OK;
+    if (tmp) (void)hipFree(tmp);
+    tmp = nullptr;
+    tmp_bytes = 0;
+    if (hipMalloc(&tmp, need) != hipSuccess) return FPDE_ENOMEM;
+    tmp_bytes = need;
+    return FPDE_OK;
+  };
+#define TRY_T(x)                          \
+  do {                                    \
+    int st_ = (x);                        \
+    if (st_ != FPDE_OK) return fail(st_); \
+  } while (0)
+#define HIP_T(x)                                     \
+  do {                                               \
+    if ((x) != hipSuccess) return fail(FPDE_EHIP);   \
+  } while (0)
+  int st;
+  TRY_T(dalloc(&key, n));
+  TRY_T(dalloc(&key2, n));
+  TRY_T(dalloc(&val, n));
+  TRY_T(dalloc(&tp.pair_sorted, n));
+  const double *qtab = m->rules + rule_offset(P.nq);
+  k_pair_keys<<<nblocks(n), 256, 0, s>>>(m->tet, m->xyz, qtab, P.nq, P.G, lo[0], lo[1], lo[2], 1.0 / c, ncell, key,
+                                         val);
+  size_t need = 0;
+  const int end_bit = 32;
+  HIP_T(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key, key2, val, tp.pair_sorted, (int)n, 0, end_bit, s));
+  TRY_T(scratch(need));
+  HIP_T(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key2, val, tp.pair_sorted, (int)n, 0, end_bit, s));
+  TRY_T(dalloc(&head, n));
+  TRY_T(dalloc(&tid, n));
+  k_heads<<<nblocks(n), 256, 0, s>>>(key2, n, head);
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(nullptr, need, head, tid, (int)n, s));
+  TRY_T(scratch(need));
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, head, tid, (int)n, s));
+  int32_t last_tid = 0, last_head = 0;
+  HIP_T(hipMemcpyAsync(&last_tid, tid + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_T(hipMemcpyAsync(&last_head, head + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_T(hipStreamSynchronize(s));
+  tp.n_tubes = (int64_t)last_tid + last_head;
+  const int64_t nT = tp.n_tubes;
+  TRY_T(dalloc(&tp.tube_off, nT + 1));
+  k_tube_off<<<nblocks(n), 256, 0, s>>>(head, tid, n, tp.tube_off);
+  TRY_T(dalloc(&tp.pm, n));
+  TRY_T(dalloc(&tp.pw, n));
+  k_pair_meta<<<nblocks(n), 256, 0, s>>>(tp.pair_sorted, n, P.G, P.nq, P.off, qtab + 4 * P.nq, m->vol, tp.pm, tp.pw);
+  dfree(key); dfree(key2); dfree(val); dfree(head); dfree(tid);
+
+  // node sets
+  TRY_T(dalloc(&u_cnt, nT + 1));
+  TRY_T(dalloc(&tp.u_off, nT + 1));
+  HIP_T(hipMemsetAsync(u_cnt, 0, sizeof(int64_t) * (nT + 1), s));
+  k_tube_count<<<(unsigned)nT, 256, 0, s>>>(tp.tube_off, tp.pm, P.ent_dof, u_cnt, m->flag);
+  int f = take_flag(m, s);
+  if (f != 0) return fail(f < 0 ? f : FPDE_EHIP);
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(nullptr, need, u_cnt, tp.u_off, (int)(nT + 1), s));
+  TRY_T(scratch(need));
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, u_cnt, tp.u_off, (int)(nT + 1), s));
+  HIP_T(hipMemcpyAsync(&tp.n_u, tp.u_off + nT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_T(hipStreamSynchronize(s));
+  TRY_T(dalloc(&tp.tube_u, tp.n_u));
+  TRY_T(dalloc(&tp.ent_slot, P.n_ent));
+  TRY_T(dalloc(&row_cnt, m->ndof + 1));
+  HIP_T(hipMemsetAsync(row_cnt, 0, sizeof(int64_t) * (m->ndof + 1), s));
+  k_tube_fill<<<(unsigned)nT, 256, 0, s>>>(tp.tube_off, tp.pm, P.ent_dof, tp.u_off, tp.tube_u, tp.ent_slot, row_cnt);
+  TRY_T(dalloc(&tp.row_off, m->ndof + 1));
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(nullptr, need, row_cnt, tp.row_off, (int)(m->ndof + 1), s));
+  TRY_T(scratch(need));
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, row_cnt, tp.row_off, (int)(m->ndof + 1), s));
+  TRY_T(dalloc(&cursor, m->ndof + 1));
+  HIP_T(hipMemcpyAsync(cursor, tp.row_off, sizeof(int64_t) * (m->ndof + 1), hipMemcpyDeviceToDevice, s));
+  TRY_T(dalloc(&tp.row_ts, tp.n_u));
+  k_row_places<<<(unsigned)nT, 256, 0, s>>>(tp.u_off, nT, tp.tube_u, cursor, tp.row_ts);
+
+  // pass-1 bands and block offsets
+  TRY_T(dalloc(&nb, nT + 1));
+  TRY_T(dalloc(&usq, nT + 1));
+  TRY_T(dalloc(&band_off, nT + 1));
+  TRY_T(dalloc(&tp.blk_off, nT + 1));
+  HIP_T(hipMemsetAsync(nb, 0, sizeof(int64_t) * (nT + 1), s));
+  HIP_T(hipMemsetAsync(usq, 0, sizeof(int64_t) * (nT + 1), s));
+  k_band_count<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, nb, usq);
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(nullptr, need, nb, band_off, (int)(nT + 1), s));
+  TRY_T(scratch(need));
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, nb, band_off, (int)(nT + 1), s));
+  HIP_T(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, usq, tp.blk_off, (int)(nT + 1), s));
+  HIP_T(hipMemcpyAsync(&tp.n_items, band_off + nT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_T(hipMemcpyAsync(&tp.blk_n, tp.blk_off + nT, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_T(hipStreamSynchronize(s));
+  TRY_T(dalloc(&tp.items, tp.n_items));
+  k_bands<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, band_off, tp.items);
+  // size statistics
+  {
+    std::vector<int64_t> uo(nT + 1);
+    HIP_T(hipMemcpyAsync(uo.data(), tp.u_off, sizeof(int64_t) * (nT + 1), hipMemcpyDeviceToHost, s));
+    HIP_T(hipStreamSynchronize(s));
+    tp.max_u = 0;
+    for (int64_t T = 0; T < nT; T++) tp.max_u = std::max<int64_t>(tp.max_u, uo[T + 1] - uo[T]);
+  }
+  HIP_T(hipGetLastError());
+  f = take_flag(m, s);
+  if (f != 0) return fail(f < 0 ? f : FPDE_EHIP);
+  cleanup();
+  return FPDE_OK;
+#undef TRY_T
+#undef HIP_T
+}
+
+int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
+  TubePlan &tp = P.tubes;
+  if (m->ndof == 0) return FPDE_OK;
+  if (!tp.blk) {
+    FPDE_TRY(dalloc(&tp.blk, tp.blk_n > 0 ? tp.blk_n : 1));
+  }
+  Order o = order_scalars(p->alpha);
+  AccumArgs a{};
+  a.tube_off = tp.tube_off;
+  a.pm = tp.pm;
+  a.pw = tp.pw;
+  a.items = tp.items;
+  a.ent_slot = tp.ent_slot;
+  a.ent_val = P.ent_val;
+  a.blk_off = tp.blk_off;
+  a.blk = tp.blk;
+  a.KC0 = p->K[0] * o.c_alpha;
+  a.KC1 = p->K[1] * o.c_alpha;
+  a.KC2 = p->K[2] * o.c_alpha;
+  GatherArgs gch{};
+  gch.row_off = tp.row_off;
+  gch.row_ts = tp.row_ts;
+  gch.u_off = tp.u_off;
+  gch.tube_u = tp.tube_u;
+  gch.blk_off = tp.blk_off;
+  gch.blk = tp.blk;
+  gch.ndof = m->ndof;
+  gch.lda = lda;
+  gch.chunk = (int)(m->ndof < 8192 ? m->ndof : 8192);
+  const int64_t slots = 8 * ((m->ndof + 7) / 8);
+  const unsigned grid = (unsigned)(slots < 65536 ? slots : 65536);
+  const long t = timer_begin(m, s);
+  if (tp.n_items > 0)
+    k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
+  if (p->precision == FPDE_MIXED)
+    k_tube_gather<float><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (float *)A);
+  else
+    k_tube_gather<double><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (double *)A);
+  timer_end(m, FPDE_STAGE_CONTRACT, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+}  // namespace fpde

@@ -413,8 +413,12 @@ static void launch_walk(const WalkArgs &a, hipStream_t s) {
 void free_plan(Plan &P) {
   dfree(P.off); dfree(P.ent_dof); dfree(P.ent_ray); dfree(P.ent_val); dfree(P.row_off); dfree(P.inc);
   dfree(P.adj); dfree(P.inc_meta); dfree(P.inc_w);
+  free_tubes(P.tubes);
   P = Plan();
 }
+
+// tube cell edge of the accumulation, in mean element edges
+constexpr double kTubeCell = 1.0;
 
 static int build_plan(fpde_mesh *m, Plan &P, int nq, int max_steps, hipStream_t s) {
   QuadRule rule;
@@ -505,6 +509,7 @@ static int build_plan(fpde_mesh *m, Plan &P, int nq, int max_steps, hipStream_t 
         P.max_ent = std::max(P.max_ent, std::max(nl, nr));
       }
   }
+  if ((st = build_tubes(m, P, kTubeCell, s)) != FPDE_OK) return fail(st);
   P.val_alpha = -1.0;
   return FPDE_OK;
 }
@@ -642,5 +647,9 @@ extern "C" int fpde_plan_info(fpde_mesh *m, int quad_points, int64_t *out, void 
   out[1] = P->n_ent;
   out[2] = P->pairs;
   out[3] = P->max_ent;
+  out[4] = P->tubes.n_tubes;
+  out[5] = P->tubes.n_u;
+  out[6] = P->tubes.max_u;
+  out[7] = P->tubes.blk_n * (int64_t)sizeof(double);
   return FPDE_OK;
 }
