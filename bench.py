@@ -39,8 +39,15 @@ RULES = (4, 11)
 KCOEF = (1.0, 0.5, 2.0)
 HBM_PEAK = 8.0e12        # B/s
 FP64_PEAK = 78.6e12      # FLOP/s, vector and matrix
-PMC_FILE = os.path.join(ROOT, "profiles", "contract_rows_sphere20k_pmc.txt")
-CONTRACT_SRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc", "assemble.hip")
+CSRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc")
+# HBM counter summaries (profiles/): unit -> (file, source its kernels are built from)
+PMC = {
+    "factorization": (os.path.join(ROOT, "profiles", "potrf_sphere20k_pmc.txt"),
+                      os.path.join(CSRC, "solve.hip")),
+    "k_tube_accum": (os.path.join(ROOT, "profiles", "tube_accum_sphere20k_pmc.txt"),
+                     os.path.join(CSRC, "tubes.hip")),
+}
+NB = 64  # panel width of the blocked Cholesky
 
 
 def log(*a):
@@ -51,22 +58,36 @@ def src_sha1(path):
     return hashlib.sha1(open(path, "rb").read()).hexdigest()
 
 
-def read_traffic():
-    """HBM bytes per contraction launch from the committed PMC summary, or
-    None when it is missing or was taken on another version of the kernel."""
-    if not os.path.exists(PMC_FILE):
+def read_traffic(kernel):
+    """HBM bytes per unit (launch, or factorization) from the committed PMC
+    summary, or None when it is missing or was taken on another version of
+    the source."""
+    path, src = PMC[kernel]
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(PMC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha1") != src_sha1(CONTRACT_SRC):
+    if kv.get("source_sha1") != src_sha1(src):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_unit"])
     except (KeyError, ValueError):
         return None
+
+
+def syrk_flops(n):
+    """FP64 flops of the trailing updates of one factorization (lower
+    triangle of C -= X X^T, inner dimension NB, per panel) and their count."""
+    tot, launches = 0, 0
+    for k0 in range(0, n, NB):
+        rest = n - k0 - NB
+        if rest > 0:
+            tot += rest * (rest + 1) // 2 * NB * 2
+            launches += 1
+    return tot, launches
 
 
 def cpu_baseline(mesh_np):
@@ -167,34 +188,45 @@ def main():
     value = rays_per_step * args.steps / (total_ms / 1e3)
     log(f"[bench] {ms_per_step:.2f} ms/step, {value:.3e} paths/s, stages {stages}")
 
-    # roofline of the dominant single-kernel stage
-    single = {k: stages[k] for k in ("walk", "contract", "load")}
-    dom = max(single, key=lambda k: single[k][0])
-    dom_ms, dom_launches = single[dom]
-    per_pass = {}
-    for nq in RULES:
-        I = info[nq]
-        per_pass[nq] = {
-            "bytes": n * n * 8 + I["entries"] * 12,      # write K once, read every entry once
-            "flops": 4 * I["pairs"],                      # both outer products, multiply + add
-        }
+    # Roofline of the dominant unit: one dense factorization (k_potrf_diag
+    # once, then k_panel + k_syrk per 64-column panel; about 40% of the step),
+    # timed with one event pair per factorization on the launch stream.
+    # Algorithmic work n^3 / 3 FP64 flops, on the vector units (no MFMA in
+    # FP64 here): peak 78.6 TFLOP/s.
+    passes = len(RULES) * len(ALPHAS)
+    factorizations = stages["potrf"][1]
     roofline = None
-    if dom == "contract" and dom_launches > 0:
-        launches_per_rule = dom_launches / len(RULES)
-        alg_bytes = sum(per_pass[nq]["bytes"] for nq in RULES) * launches_per_rule
-        alg_flops = sum(per_pass[nq]["flops"] for nq in RULES) * launches_per_rule
-        t_s = dom_ms / 1e3
-        if alg_bytes / HBM_PEAK >= alg_flops / FP64_PEAK:
-            ach, peak, unit, bound = alg_bytes / t_s / 1e9, HBM_PEAK / 1e9, "GB/s", "hbm"
-        else:
-            ach, peak, unit, bound = alg_flops / t_s / 1e12, FP64_PEAK / 1e12, "TFLOP/s", "alu"
-        tr = read_traffic()
-        roofline = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-                    "traffic": tr, "kernel": "k_contract_rows<double>",
-                    "avg_launch_ms": dom_ms / dom_launches}
-    elif dom_launches > 0:
-        roofline = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
-                    "traffic": None, "kernel": dom, "avg_launch_ms": dom_ms / dom_launches}
+    if factorizations:
+        avg_s = stages["potrf"][0] / factorizations / 1e3
+        fl = n ** 3 / 3.0
+        ach = fl / avg_s / 1e12
+        roofline = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                    "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
+                    "kernel": f"factorization: k_potrf_diag<double> + {syrk_flops(n)[1]} x (k_panel<double> + "
+                              f"k_syrk<double>)",
+                    "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (vector FMA)"}
+    # every stage against its own bound (algorithmic work / measured time)
+    stage_roof = {}
+    if factorizations:
+        t = stages["potrf"][0] / factorizations / 1e3
+        fl = n ** 3 / 3.0
+        stage_roof["potrf"] = {"flops_per_factorization": fl, "TFLOP/s": fl / t / 1e12,
+                               "frac_fp64": fl / t / FP64_PEAK}
+    if stages["trsv"][1]:
+        t = stages["trsv"][0] / stages["trsv"][1] / 1e3
+        by = n * n * 8.0  # the lower triangle read once forward, once backward
+        stage_roof["trsv"] = {"bytes_per_solve": by, "GB/s": by / t / 1e9, "frac_hbm": by / t / HBM_PEAK}
+    if stages["contract"][1]:
+        t = stages["contract"][0] / stages["contract"][1] / 1e3
+        by = n * n * 8.0 + sum(12.0 * info[nq]["entries"] for nq in RULES) / len(RULES)
+        stage_roof["contract"] = {"algorithmic_bytes": by, "GB/s": by / t / 1e9, "frac_hbm": by / t / HBM_PEAK,
+                                  "note": "K written once + every derivative entry read once"}
+    if stages["accum"][1]:
+        t = stages["accum"][0] / stages["accum"][1] / 1e3
+        fl = sum(4 * info[nq]["pairs"] for nq in RULES) / len(RULES)
+        stage_roof["accum"] = {"flops_per_launch": fl, "TFLOP/s": fl / t / 1e12, "frac_fp64": fl / t / FP64_PEAK}
+    if stages["walk"][1]:
+        stage_roof["walk"] = {"paths_per_s": rays_per_step * args.steps / (stages["walk"][0] / 1e3)}
 
     # mixed-precision arm at alpha = 1.5, 11-point rule
     mixed = None
@@ -246,7 +278,6 @@ def main():
     if cpu:
         log(f"[bench] cpu oracle {cpu}")
 
-    passes = len(RULES) * len(ALPHAS)
     out = {
         "metric": METRIC,
         "value": value,
@@ -277,6 +308,7 @@ def main():
         "template_plan_ms": plan_ms,
         "plan": {str(k): v for k, v in info.items()},
         "roofline": roofline,
+        "stage_rooflines": stage_roof,
         "mixed": mixed,
         "cpu_baseline": cpu,
     }

@@ -207,9 +207,10 @@ int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const doub
 /*
  * Stage timing with HIP events recorded on the caller's stream around each
  * stage launch (no extra synchronisation while recording).
- * Stages: walk + closed-form evaluation, accumulation kernel, load vector,
- * Cholesky factorisation (all panels), triangular solves, matrix-free
- * product, symbolic plan, adjoint re-walk.
+ * Stages: walk + closed-form evaluation, accumulation (both tube passes),
+ * load vector, Cholesky factorisation (all panels), triangular solves,
+ * matrix-free product, symbolic plan, adjoint re-walk, and the tube
+ * products pass timed again on its own inside CONTRACT.
  *   fpde_timing(m, 1) clears the totals and starts recording; (m, 0) stops.
  *   fpde_stage_times waits for the recorded events, then writes per stage
  *   the summed milliseconds (host, FPDE_NSTAGES doubles) and the number of
@@ -224,7 +225,8 @@ enum {
   FPDE_STAGE_APPLY = 5,
   FPDE_STAGE_PLAN = 6,
   FPDE_STAGE_ADJOINT = 7,
-  FPDE_NSTAGES = 8
+  FPDE_STAGE_ACCUM = 8,
+  FPDE_NSTAGES = 9
 };
 int fpde_timing(fpde_mesh *m, int enable);
 int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);

@@ -34,7 +34,7 @@ EXPORTS = [
     "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
 ]
 
-STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint"]
+STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum"]
 
 
 class FpdeError(RuntimeError):

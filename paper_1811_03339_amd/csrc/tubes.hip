@@ -665,8 +665,10 @@ int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, 
   const int64_t slots = 8 * ((m->ndof + 7) / 8);
   const unsigned grid = (unsigned)(slots < 65536 ? slots : 65536);
   const long t = timer_begin(m, s);
+  const long ta = timer_begin(m, s);
   if (tp.n_items > 0)
     k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
+  timer_end(m, FPDE_STAGE_ACCUM, ta, s);
   if (p->precision == FPDE_MIXED)
     k_tube_gather<float><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (float *)A);
   else
