@@ -177,6 +177,50 @@ class OracleMesh:
             raise OracleError(st)
         return x, w
 
+    # template (Sec. 2.3) ---------------------------------------------------
+    def patch_boxes(self):
+        """Axis-aligned bounding box of the element patch omega_j (the union of
+        the elements containing node z_j, Sec. 2.3) of every interior node:
+        (lo, hi), each (ndof, 3), by min / max over the patch's vertices."""
+        dof = self.dof
+        lo = np.full((self.ndof, 3), np.inf)
+        hi = np.full((self.ndof, 3), -np.inf)
+        pts = self.xyz[self.tet]
+        elo, ehi = pts.min(axis=1), pts.max(axis=1)
+        for m in range(4):
+            d = dof[self.tet[:, m]]
+            ok = d >= 0
+            np.minimum.at(lo, d[ok], elo[ok])
+            np.maximum.at(hi, d[ok], ehi[ok])
+        return lo, hi
+
+    def template(self) -> np.ndarray:
+        """The template T of Sec. 2.3 as a dense boolean matrix.
+
+        T_jk is set when, for some axis i, the patch boxes of j and k overlap
+        (closed intervals) in both coordinates other than i: only then can a
+        line parallel to e_i meet both supports.  When it is clear for every
+        i, every chord misses one of the two supports and K_jk = 0, so T is a
+        superset of the nonzero pattern of K.  (The printed criterion, one
+        overlap test in the coordinate i itself, is garbled; this is the
+        reading used.)"""
+        lo, hi = self.patch_boxes()
+        ov = (lo[:, None, :] <= hi[None, :, :]) & (lo[None, :, :] <= hi[:, None, :])
+        T = np.zeros((self.ndof, self.ndof), dtype=bool)
+        for i in range(3):
+            T |= ov[:, :, (i + 1) % 3] & ov[:, :, (i + 2) % 3]
+        return T
+
+    def template_tiles(self, tile: int) -> np.ndarray:
+        """T at tile granularity: (nt, nt) uint8, 1 when any (j, k) of the tile is set."""
+        T = self.template()
+        nt = -(-self.ndof // tile)
+        out = np.zeros((nt, nt), dtype=np.uint8)
+        for P in range(nt):
+            for Q in range(nt):
+                out[P, Q] = T[P * tile:(P + 1) * tile, Q * tile:(Q + 1) * tile].any()
+        return out
+
     # paths ---------------------------------------------------------------
     def paths(self, nq: int, h0: int = 0, count: int | None = None, lists: bool = False):
         """Half-ray h = g*6 + 2*i + side: (length, FNV-1a hash[, ids, r_end])."""
