@@ -232,6 +232,20 @@ int fpde_timing(fpde_mesh *m, int enable);
 int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
 
 /*
+ * The template T of Sec. 2.3 (Table 1): T_jk = 1 when, for some axis i, the
+ * axis-aligned boxes of the element patches of nodes j and k overlap (closed
+ * intervals) in both coordinates other than i -- the only case in which a
+ * line parallel to e_i meets both supports, so T contains the nonzero
+ * pattern of K.  The patch boxes are computed once per mesh and kept.
+ *   tile  : tile edge in unknowns, 1..256.
+ *   tiles : host, nt x nt uint8 row-major, nt = ceil(n_dof / tile): 1 when
+ *           any (j, k) of the tile has T_jk = 1.
+ *   nnz   : host int64, the number of (j, k) with T_jk = 1.
+ * Synchronises `stream`.  FPDE_EINVAL for a tile outside 1..256.
+ */
+int fpde_template(fpde_mesh *m, int tile, uint8_t *tiles, int64_t *nnz, void *stream);
+
+/*
  * Sizes of the symbolic plan of a rule (built on demand; see fpde_plan):
  *   out[0] half-rays (6 G), out[1] derivative-vector entries over all
  *   half-rays, out[2] sum over (g, i) of |L_gi| |R_gi| (entry pairs the

@@ -32,6 +32,7 @@ EXPORTS = [
     "fpde_status_string", "fpde_mesh_create", "fpde_mesh_destroy", "fpde_mesh_info", "fpde_dof_map",
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
     "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
+    "fpde_template",
 ]
 
 STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum"]
@@ -89,6 +90,7 @@ def _lib():
     L.fpde_timing.argtypes = [P, i32]
     L.fpde_stage_times.argtypes = [P, P, P]
     L.fpde_plan_info.argtypes = [P, i32, P, P]
+    L.fpde_template.argtypes = [P, i32, P, P, P]
     for name in EXPORTS:
         getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
             None if name == "fpde_mesh_destroy" else ctypes.c_int)
@@ -174,6 +176,14 @@ class Mesh:
         return {"half_rays": int(out[0]), "entries": int(out[1]), "pairs": int(out[2]), "max_entries": int(out[3]),
                 "tubes": int(out[4]), "tube_nodes": int(out[5]), "max_tube_nodes": int(out[6]),
                 "block_bytes": int(out[7])}
+
+    def template(self, tile: int = 64, stream=None):
+        """Template of Sec. 2.3 at tile granularity: (tiles uint8 (nt, nt), nnz)."""
+        nt = -(-self.n_dof // tile) if (self.n_dof and tile >= 1) else 0  # the library rejects bad tiles
+        tiles = np.zeros((nt, nt), dtype=np.uint8)
+        nnz = np.zeros(1, dtype=np.int64)
+        _check(_lib().fpde_template(self._h, tile, _np(tiles), _np(nnz), _stream(stream)), "fpde_template")
+        return tiles, int(nnz[0])
 
     def timing(self, enable: bool):
         _check(_lib().fpde_timing(self._h, 1 if enable else 0), "fpde_timing")

@@ -107,6 +107,7 @@ struct fpde_mesh {
   int32_t *vert_of_dof = nullptr; // ndof
   double *rules = nullptr;        // device quadrature tables: [4-point | 11-point],
                                   // each nq*4 barycentric coordinates then nq weights
+  double *pbox = nullptr;         // ndof x 6: box of each node's element patch (lo xyz, hi xyz)
   int32_t *flag = nullptr;        // device status word (0 = ok)
   int64_t *flag_aux = nullptr;    // device: failing column / ray
   fpde::Plan plan[2];             // rules with 4 and 11 points
@@ -168,6 +169,8 @@ void free_plan(Plan &P);
 int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s);
 void free_tubes(TubePlan &tp);
 int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s);
+// patch boxes of the template (built once per mesh)
+int ensure_patch_boxes(fpde_mesh *m, hipStream_t s);
 
 // Stage timing: t = timer_begin(m, s); ...launches...; timer_end(m, stage, t, s)
 long timer_begin(fpde_mesh *m, hipStream_t s);

@@ -432,6 +432,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   if (m->linv) (void)hipFree(m->linv);
   dfree(m->tsync);
+  dfree(m->pbox);
   delete m;
 }
 

@@ -189,6 +189,38 @@ def test_adjoint_matches_oracle_and_finite_differences(name):
     assert abs(a_t.grad.item() - fd) <= 1e-6 * abs(fd)
 
 
+@pytest.mark.parametrize("name,tile", [("cube_n8", 64), ("cube_n8", 7), ("sphere_small", 64), ("sphere20k", 64),
+                                       ("sphere20k", 256)])
+def test_template_matches_oracle(name, tile):
+    if name == "cube_n8":
+        m = kuhn_cube(8)
+        om, gm = oracle.OracleMesh(m.xyz, m.tet), F.Mesh(m.xyz, m.tet)
+    else:
+        m, om, gm = mesh_pair(name)
+    tiles, nnz = gm.template(tile)
+    T = om.template()
+    assert nnz == int(T.sum())
+    assert np.array_equal(tiles, om.template_tiles(tile))
+
+
+def test_template_covers_assembled_pattern():
+    m, om, gm = mesh_pair("sphere20k")
+    n, tile = gm.n_dof, 64
+    tiles, nnz = gm.template(tile)
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    gm.assemble(F.params(1.4, (1.0, 2.0, 0.5), quad_points=11), A, None)
+    nt = tiles.shape[0]
+    pad = torch.zeros((nt * tile, nt * tile), dtype=torch.float64, device="cuda")
+    pad[:n, :n] = A.abs()
+    occupied = (pad.reshape(nt, tile, nt, tile).amax(dim=(1, 3)) > 0).cpu().numpy()
+    assert not (occupied & (tiles == 0)).any()
+    assert tiles.mean() < 1.0 and nnz < n * n
+    with pytest.raises(F.FpdeError):
+        gm.template(0)
+    with pytest.raises(F.FpdeError):
+        gm.template(257)
+
+
 def test_error_paths_forced_from_host():
     m, om, gm = mesh_pair("sphere_small")
     A = F.new_matrix(gm)
