@@ -155,6 +155,11 @@ def main():
     plan_ms = 1e3 * (time.perf_counter() - t)
     n = gm.n_dof
     log(f"[bench] n_dof {n}, mesh set-up {setup_ms:.1f} ms, plans {plan_ms:.1f} ms, {info}")
+    t = time.perf_counter()
+    tiles, t_nnz = gm.template(64)
+    template = {"tile": 64, "tiles_set": float(tiles.mean()), "pair_density": t_nnz / float(n * n),
+                "ms": 1e3 * (time.perf_counter() - t)}
+    log(f"[bench] template {template}")
 
     A = torch.empty((n, n), dtype=torch.float64, device=dev)
     b = torch.empty(n, dtype=torch.float64, device=dev)
@@ -306,6 +311,7 @@ def main():
                                   if stages["walk"][0] > 0 else None),
         "setup_ms": setup_ms,
         "template_plan_ms": plan_ms,
+        "template": template,
         "plan": {str(k): v for k, v in info.items()},
         "roofline": roofline,
         "stage_rooflines": stage_roof,
