@@ -29,7 +29,7 @@ import dataclasses
 import numpy as np
 
 __all__ = [
-    "Mesh", "kuhn_cube", "hull_mesh", "radius_ratio", "workload_mesh",
+    "Mesh", "kuhn_cube", "hull_mesh", "radius_ratio", "workload_mesh", "fibonacci_sphere",
     "WORKLOADS",
 ]
 
@@ -229,6 +229,17 @@ def sphere_points(n: int, seed: int) -> np.ndarray:
     return p / np.linalg.norm(p, axis=1, keepdims=True)
 
 
+def fibonacci_sphere(n: int, radius: float = 1.0) -> np.ndarray:
+    """n points on the sphere of the given radius along the golden-angle
+    spiral (equal-area latitude bands): a quasi-uniform, deterministic hull
+    whose facets shrink evenly as n grows, for mesh-refinement families."""
+    k = np.arange(n, dtype=np.float64) + 0.5
+    z = 1.0 - 2.0 * k / n
+    phi = np.pi * (1.0 + 5.0 ** 0.5) * k
+    s = np.sqrt(1.0 - z * z)
+    return radius * np.stack([s * np.cos(phi), s * np.sin(phi), z], axis=1)
+
+
 def ellipsoid_points(n: int, axes, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     p = rng.normal(size=(n, 3))
@@ -252,6 +263,13 @@ WORKLOADS = {
     # hull of 2000 points in the ellipsoid (1, 0.7, 0.4), ~400k tets / ~70k nodes
     "ellipsoid400k": dict(kind="ellipsoid", n_points=2000, axes=(1.0, 0.7, 0.4),
                           spacing=0.0246, seed=5),
+    # the ball |x| < 0.5 of the divergence-form problem (Sec. 3): a
+    # refinement family whose largest element diameter matches the h column
+    # of Table 3 (0.270, 0.139, 0.0757) and the mesh of Fig. 3 (0.0894)
+    "ball_h270": dict(kind="ball", radius=0.5, n_surface=122, spacing=0.14021, seed=21),
+    "ball_h139": dict(kind="ball", radius=0.5, n_surface=469, spacing=0.07152, seed=22),
+    "ball_h089": dict(kind="ball", radius=0.5, n_surface=1215, spacing=0.04445, seed=23),
+    "ball_h076": dict(kind="ball", radius=0.5, n_surface=1628, spacing=0.03840, seed=24),
     # small hull meshes for tests
     "sphere_tiny": dict(kind="sphere", n_surface=40, spacing=0.45, seed=11),
     "sphere_small": dict(kind="sphere", n_surface=100, spacing=0.22, seed=12),
@@ -266,6 +284,9 @@ def workload_mesh(name: str, **overrides) -> Mesh:
         m = kuhn_cube(spec["n"])
     elif kind == "sphere":
         pts = sphere_points(spec["n_surface"], spec["seed"])
+        m = hull_mesh(pts, spec["spacing"], spec["seed"], name=name)
+    elif kind == "ball":
+        pts = fibonacci_sphere(spec["n_surface"], spec["radius"])
         m = hull_mesh(pts, spec["spacing"], spec["seed"], name=name)
     elif kind == "ellipsoid":
         pts = ellipsoid_points(spec["n_points"], spec["axes"], spec["seed"])

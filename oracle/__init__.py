@@ -20,6 +20,12 @@ Splitting each one-sided operator into two of order gamma = alpha/2 gives
 
 which is symmetric positive definite and equals sum_i K_i (d_i u, d_i v) at
 alpha = 2.
+
+Also the divergence-form two-sided problem of Sec. 3 (eq. equ:sfde2) on the
+ball |x| < r: order-beta_i one-sided derivatives with coefficients
+p_i = cos x_i, q_i = 1 - cos x_i on the trial side, the classical derivative
+on the test side (a non-symmetric matrix, solved by LAPACK LU), and the
+closed-form source of its exact solution u = (|x|^2 - r^2)^2.
 """
 from __future__ import annotations
 
@@ -75,6 +81,7 @@ def _load():
     L.orc_exit_pattern.argtypes = [P, i64, P, i32, i32, P, P]
     L.orc_ray_values.argtypes = [P, i32, i64, i32, i32, dbl, dbl, dbl, dbl, i32, i32, P, P]
     L.orc_assemble.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P]
+    L.orc_assemble_div.argtypes = [P, i32, P, P, P, i32, P]
     L.orc_apply.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, P]
     L.orc_adjoint_sums.argtypes = [P, i32, dbl, dbl, dbl, i32, P, P, P, P]
     L.orc_load.argtypes = [P, i32, P, P]
@@ -287,6 +294,27 @@ class OracleMesh:
             raise OracleError(st, "assemble")
         return A
 
+    def assemble_div(self, nq: int, beta, pq=None) -> np.ndarray:
+        """Non-symmetric matrix of the divergence-form problem of Sec. 3:
+        K_jk = a(psi_k, psi_j) with trial derivatives of order beta_i along
+        e_i and the classical d_i psi_j of the own element on the test side.
+        pq: (6, G) with p_i(x_g) in rows 0..2 and q_i(x_g) in rows 3..5;
+        default the coefficients of Sec. 3 (div_coefficients)."""
+        beta = np.asarray(beta, dtype=np.float64)
+        if pq is None:
+            x, _ = self.gauss_points(nq)
+            pq = div_coefficients(x)
+        pq = np.ascontiguousarray(pq, dtype=np.float64)
+        if pq.shape != (6, self.n_tet * nq):
+            raise ValueError("pq must be (6, G)")
+        gm = np.ascontiguousarray(beta)
+        ig2 = np.array([rgamma_(2.0 - b) for b in beta])
+        A = np.zeros((self.ndof, self.ndof))
+        st = _lib.orc_assemble_div(self._h, nq, _p(gm), _p(ig2), _p(pq), self.cap, _p(A))
+        if st != 0:
+            raise OracleError(st, "assemble_div")
+        return A
+
     def apply(self, nq: int, alpha: float, K, x) -> np.ndarray:
         gm, ig2, _, _ = order_scalars(alpha)
         Kc = np.ascontiguousarray(K, dtype=np.float64)
@@ -393,6 +421,84 @@ def mms_source(x: np.ndarray, alpha: float, K=(1.0, 1.0, 1.0)) -> np.ndarray:
                 other = other * ph[d]
         f += K[i] * ca * (mms_Phi(x[:, i], alpha) + mms_Phi(1.0 - x[:, i], alpha)) * other
     return f
+
+
+# --------------------------------------------------------------------------
+# The divergence-form problem of Sec. 3 on the ball |x| < r
+# --------------------------------------------------------------------------
+def rgamma_(z: float) -> float:
+    from scipy.special import rgamma
+    return float(rgamma(z))
+
+
+def div_coefficients(x: np.ndarray) -> np.ndarray:
+    """p_i = cos x_i, q_i = 1 - cos x_i at the points x (G, 3) (Sec. 3), as
+    the (6, G) array the assembly takes."""
+    c = np.cos(x.T)
+    return np.ascontiguousarray(np.concatenate([c, 1.0 - c]))
+
+
+def ball_exact(x: np.ndarray, r: float = 0.5) -> np.ndarray:
+    """u = (|x|^2 - r^2)^2 inside the ball, 0 outside (Sec. 3)."""
+    s = np.sum(x * x, axis=1) - r * r
+    return np.where(s < 0.0, s * s, 0.0)
+
+
+def _chord_Phi(s, c, beta, deriv: bool):
+    """On the chord of half-length c the exact solution is, in the distance s
+    from either end, s^2 (s - 2c)^2 = s^4 - 4 c s^3 + 4 c^2 s^2; its order-beta
+    Riemann-Liouville derivative from that end (term by term,
+    D^beta s^n = Gamma(n+1)/Gamma(n+1-beta) s^(n-beta)) and, with deriv,
+    the s-derivative of that."""
+    g = rgamma_
+    if deriv:
+        return (8.0 * c * c * g(2.0 - beta) * s ** (1.0 - beta)
+                - 24.0 * c * g(3.0 - beta) * s ** (2.0 - beta)
+                + 24.0 * g(4.0 - beta) * s ** (3.0 - beta))
+    return (8.0 * c * c * g(3.0 - beta) * s ** (2.0 - beta)
+            - 24.0 * c * g(4.0 - beta) * s ** (3.0 - beta)
+            + 24.0 * g(5.0 - beta) * s ** (4.0 - beta))
+
+
+def ball_flux(x: np.ndarray, beta, r: float = 0.5, i: int = 0):
+    """(D_L^{beta_i} u, D_R^{beta_i} u) along e_i at x for the exact solution:
+    the chord through x is |y_i| <= c with c^2 = r^2 - sum_{m != i} x_m^2."""
+    c2 = r * r - (np.sum(x * x, axis=1) - x[:, i] ** 2)
+    c = np.sqrt(np.maximum(c2, 0.0))
+    xi = np.maximum(x[:, i] + c, 0.0)
+    eta = np.maximum(c - x[:, i], 0.0)
+    b = float(beta[i])
+    return _chord_Phi(xi, c, b, False), _chord_Phi(eta, c, b, False)
+
+
+def ball_source(x: np.ndarray, beta, r: float = 0.5) -> np.ndarray:
+    """f = sum_i D_i (p_i D_L^{beta_i} u - q_i D_R^{beta_i} u) for the exact
+    solution and the coefficients of Sec. 3, by the product rule:
+    D_i [cos x_i Phi(xi)] - D_i [(1 - cos x_i) Phi(eta)] with xi = x_i + c and
+    eta = c - x_i the distances to the chord ends (d eta / d x_i = -1)."""
+    f = np.zeros(x.shape[0])
+    for i in range(3):
+        c2 = r * r - (np.sum(x * x, axis=1) - x[:, i] ** 2)
+        c = np.sqrt(np.maximum(c2, 0.0))
+        xi = np.maximum(x[:, i] + c, 0.0)
+        eta = np.maximum(c - x[:, i], 0.0)
+        b = float(beta[i])
+        s, co = np.sin(x[:, i]), np.cos(x[:, i])
+        f += (-s * _chord_Phi(xi, c, b, False) + co * _chord_Phi(xi, c, b, True)
+              - s * _chord_Phi(eta, c, b, False) + (1.0 - co) * _chord_Phi(eta, c, b, True))
+    return f
+
+
+def solve_div(mesh: OracleMesh, nq: int, beta, r: float = 0.5, f_gauss=None):
+    """K, b and u = K^{-1} b for the problem of Sec. 3 (LAPACK LU with partial
+    pivoting; K is not symmetric).  f defaults to the exact solution's source."""
+    from scipy.linalg import lu_factor, lu_solve
+    K = mesh.assemble_div(nq, beta)
+    if f_gauss is None:
+        x, _ = mesh.gauss_points(nq)
+        f_gauss = ball_source(x, beta, r)
+    b = mesh.load(nq, f_gauss)
+    return K, b, lu_solve(lu_factor(K), b)
 
 
 def solve_problem(mesh: OracleMesh, nq: int, alpha: float, K=(1.0, 1.0, 1.0), f_gauss=None):

@@ -27,7 +27,11 @@
  *     into (D_L^gamma u, D_R^gamma v) + (D_R^gamma u, D_L^gamma v)
  *     (form 1 of eq. equ:varsss with alpha = beta = gamma);
  *   - the load vector, a matrix-free product with K and the sums needed for
- *     the adjoint derivatives with respect to the order and the coefficients.
+ *     the adjoint derivatives with respect to the order and the coefficients;
+ *   - the non-symmetric matrix of the divergence-form two-sided problem of
+ *     Sec. 3 (eq. equ:sfde2): order-beta_i trial derivatives along e_i with
+ *     variable coefficients p_i, q_i, against the classical derivative of the
+ *     test function on the Gauss point's own element.
  *
  * Readings where the paper is silent (each one is stated where it is used):
  *   - zero component of a volume coordinate: |k| <= 1e-12 max(1, |b~|, |r d~|),
@@ -630,6 +634,55 @@ int orc_assemble(const orc_mesh *m, int nq, double gamma, double inv_g2, double 
         for (int b = 0; b < nl; b++) A[Ri[a] * n + Li[b]] += W * (Rv[a] * Lv[b]);
       for (int a = 0; a < nl; a++)
         for (int b = 0; b < nr; b++) A[Li[a] * n + Ri[b]] += W * (Lv[a] * Rv[b]);
+    }
+  }
+  free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Divergence-form two-sided problem (Sec. 3, eq. equ:sfde2):               */
+/*   sum_i D_i (p_i D_L^{beta_i} u - q_i D_R^{beta_i} u) = f,                */
+/* whose variational form, after one classical integration by parts on the  */
+/* test side, is a(u, v) = -sum_i [(p_i D_L u, D_i v) - (q_i D_R u, D_i v)].  */
+/* With u = psi_k (trial) and v = psi_j (test) and the element quadrature of */
+/* Sec. 2.1 this is                                                           */
+/*   K_jk = -sum_i sum_g w_g d_i psi_j(x_g) [p_i L_gi(k) - q_i R_gi(k)]        */
+/* where L_gi, R_gi are the order-beta_i vectors of the walked half-rays and  */
+/* d_i psi_j(x_g) is the constant slope of psi_j on the Gauss point's own     */
+/* element (zero for the other nodes).  pq holds p_i(x_g) at [i G + g] and    */
+/* q_i(x_g) at [(3 + i) G + g].  A is ndof x ndof row-major (row = test),     */
+/* zeroed by the caller.                                                      */
+/* ------------------------------------------------------------------------ */
+int orc_assemble_div(const orc_mesh *m, int nq, const double *gamma /* 3 */, const double *inv_g2 /* 3 */,
+                     const double *pq, int cap, double *A) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  orc_order ord[3];
+  for (int i = 0; i < 3; i++) orc_fill_order(&ord[i], gamma[i], inv_g2[i], 0.0, 0.0);
+  orc_work *w = orc_work_new(m->nv);
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int32_t *Li = (int32_t *)malloc(sizeof(int32_t) * 4 * cap), *Ri = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+  double *Lv = (double *)malloc(sizeof(double) * 4 * cap), *Rv = (double *)malloc(sizeof(double) * 4 * cap);
+  int64_t n = m->ndof, G = m->nt * nq;
+  int st = ORC_OK;
+  for (int64_t g = 0; g < G && st == ORC_OK; g++) {
+    int64_t t = g / nq;
+    double wg = wq[g % nq] * m->vol[t];
+    for (int i = 0; i < 3; i++) {
+      int nl = orc_ray_vector(m, nq, bary, g, i, 0, &ord[i], 0, cap, w, Li, Lv, tb, rb);
+      if (nl < 0) { st = nl; break; }
+      int nr = orc_ray_vector(m, nq, bary, g, i, 1, &ord[i], 0, cap, w, Ri, Rv, tb, rb);
+      if (nr < 0) { st = nr; break; }
+      double p = pq[(int64_t)i * G + g], q = pq[(int64_t)(3 + i) * G + g];
+      for (int jl = 0; jl < 4; jl++) {
+        int32_t j = m->dof[m->tet[4 * t + jl]];
+        if (j < 0) continue;
+        double dpsi = orc_slope(m, t, jl, i);
+        for (int b = 0; b < nl; b++) A[j * n + Li[b]] += -(wg * dpsi * p) * Lv[b];
+        for (int b = 0; b < nr; b++) A[j * n + Ri[b]] += (wg * dpsi * q) * Rv[b];
+      }
     }
   }
   free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);

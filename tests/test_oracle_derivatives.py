@@ -32,7 +32,7 @@ def chord(hull, u0, d):
 
 
 @pytest.mark.parametrize("name", ["cube3", "sphere_small"])
-@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.9])
+@pytest.mark.parametrize("alpha", [0.8, 1.2, 1.5, 1.9])
 def test_linear_function_reproduced(name, alpha):
     m = kuhn_cube(3) if name == "cube3" else workload_mesh(name)
     om = oracle.OracleMesh(m.xyz, m.tet)
@@ -141,7 +141,7 @@ def literal_derivative(pieces, node, gamma, dps=40):
     return float(-mp.diff(F, mp.mpf(0)))
 
 
-@pytest.mark.parametrize("alpha", [1.3, 1.7])
+@pytest.mark.parametrize("alpha", [0.6, 1.3, 1.7])
 def test_literal_definition_on_tiny_mesh(alpha):
     m = kuhn_cube(2)
     om = oracle.OracleMesh(m.xyz, m.tet)
