@@ -32,7 +32,9 @@
  *     enqueued on it; calls that must report a device-side status or a size
  *     synchronise it once before returning (stated per call).
  *   - Matrices are dense, row-major with leading dimension lda >= n_dof.
- *     The stiffness matrix is symmetric, so row/column order is immaterial.
+ *     The Riesz stiffness matrix is symmetric, so row/column order is
+ *     immaterial there; the Sec. 3 matrix (below) has the test function as
+ *     its row.
  *   - One handle must not be used by two host threads at once.
  */
 #ifndef FPDE_H
@@ -57,11 +59,12 @@ typedef enum {
   FPDE_ENOCONV = -8,           /* iterative refinement missed its tolerance */
   FPDE_EHIP = -9,              /* a HIP runtime call failed */
   FPDE_ENOMEM = -10,           /* device allocation failed */
-  FPDE_EUNSUPPORTED = -11      /* valid but not implemented combination */
+  FPDE_EUNSUPPORTED = -11,     /* valid but not implemented combination */
+  FPDE_ESINGULAR = -12         /* LU without pivoting met a zero or non-finite pivot */
 } fpde_status;
 
 enum { FPDE_FP64 = 0, FPDE_MIXED = 1 };
-enum { FPDE_SRC_ONE = 0, FPDE_SRC_USER = 1, FPDE_SRC_CUBE_MMS = 2 };
+enum { FPDE_SRC_ONE = 0, FPDE_SRC_USER = 1, FPDE_SRC_CUBE_MMS = 2, FPDE_SRC_BALL_MMS = 3 };
 
 typedef struct {
   double alpha;     /* Riesz order, 1 < alpha <= 2 */
@@ -209,8 +212,9 @@ int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const doub
  * stage launch (no extra synchronisation while recording).
  * Stages: walk + closed-form evaluation, accumulation (both tube passes),
  * load vector, Cholesky factorisation (all panels), triangular solves,
- * matrix-free product, symbolic plan, adjoint re-walk, and the tube
- * products pass timed again on its own inside CONTRACT.
+ * matrix-free product, symbolic plan, adjoint re-walk, the tube products
+ * pass timed again on its own inside CONTRACT, and for the problem of
+ * Sec. 3 its LU factorisation and its accumulation.
  *   fpde_timing(m, 1) clears the totals and starts recording; (m, 0) stops.
  *   fpde_stage_times waits for the recorded events, then writes per stage
  *   the summed milliseconds (host, FPDE_NSTAGES doubles) and the number of
@@ -226,7 +230,9 @@ enum {
   FPDE_STAGE_PLAN = 6,
   FPDE_STAGE_ADJOINT = 7,
   FPDE_STAGE_ACCUM = 8,
-  FPDE_NSTAGES = 9
+  FPDE_STAGE_LU = 9,    /* LU factorisation of the Sec. 3 matrix (all panels) */
+  FPDE_STAGE_DIV = 10,  /* accumulation of the Sec. 3 matrix */
+  FPDE_NSTAGES = 11
 };
 int fpde_timing(fpde_mesh *m, int enable);
 int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
@@ -257,6 +263,71 @@ int fpde_template(fpde_mesh *m, int tile, uint8_t *tiles, int64_t *nnz, void *st
  *   host, 8 int64.  Synchronises `stream`.
  */
 int fpde_plan_info(fpde_mesh *m, int quad_points, int64_t *out, void *stream);
+
+/*
+ * ---- The divergence-form two-sided problem of Sec. 3 (eq. equ:sfde2) ----
+ *
+ *   sum_i D_i (p_i D_L^{beta_i} u - q_i D_R^{beta_i} u) = f,  u = 0 outside,
+ *
+ * 0 < beta_i <= 1, on the same convex meshes.  Its weak form (one classical
+ * integration by parts on the test side) is
+ *   a(u, v) = -sum_i [(p_i D_L^{beta_i} u, D_i v) - (q_i D_R^{beta_i} u, D_i v)],
+ * so with the element quadrature of Sec. 2.1
+ *   K_jk = -sum_i sum_g w_g (d_i psi_j)(x_g) [p_i(x_g) L_gi(k) - q_i(x_g) R_gi(k)],
+ * L_gi / R_gi the order-beta_i derivative vectors of the half-rays along e_i
+ * (the walk of Sec. 2.2) and d_i psi_j the slope of psi_j on the Gauss
+ * point's own element.  K is not symmetric: row j is the test function.
+ */
+enum { FPDE_COEF_SEC3 = 0, FPDE_COEF_USER = 1 };
+
+typedef struct {
+  double beta[3];   /* orders beta_1..beta_3, each in (0, 1] */
+  int quad_points;  /* element rule: 4 or 11 points */
+  int coef;         /* FPDE_COEF_SEC3: p_i = cos x_i, q_i = 1 - cos x_i (Sec. 3);
+                       FPDE_COEF_USER: p_i, q_i given at the Gauss points */
+  int source;       /* FPDE_SRC_ONE, FPDE_SRC_USER, or FPDE_SRC_BALL_MMS: the
+                       source of u = (|x|^2 - r^2)^2 on the ball |x| < radius
+                       with the coefficients of Sec. 3 (its closed form along
+                       each chord) */
+  double radius;    /* FPDE_SRC_BALL_MMS: r > 0 */
+  int max_steps;    /* cap on elements per half-ray, 0 = 4096 */
+} fpde_div_params;
+
+/*
+ * Assembly of K (above) and b_j = sum_g w_g f(x_g) psi_j(x_g).
+ *   pq: dev, 6 G FP64 for FPDE_COEF_USER (G = n_tet * quad_points Gauss
+ *       points, index element * quad_points + q): p_i(x_g) at [i G + g],
+ *       q_i(x_g) at [(3 + i) G + g]; else ignored (may be NULL).
+ *   A:  dev, n_dof x lda FP64; every entry of the leading n_dof x n_dof block
+ *       is written.
+ *   b:  dev, n_dof FP64, or NULL.  f_gauss: dev, G FP64 for FPDE_SRC_USER.
+ * Shares the symbolic plan (fpde_plan) with the Riesz problem; the entry
+ * values are recomputed only for the axes whose order changed.
+ * Synchronises `stream`.
+ * Errors: FPDE_EINVAL, FPDE_EALPHA (beta_i outside (0, 1]), FPDE_EPATH,
+ * FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_div_assemble(fpde_mesh *m, const fpde_div_params *p, const double *pq, double *A, int64_t lda,
+                      double *b, const double *f_gauss, void *stream);
+
+/*
+ * LU factorisation without pivoting of the n_dof x n_dof matrix in A
+ * (dev, FP64, lda >= n_dof), in place: A = L U with L unit lower (strict
+ * lower triangle of A) and U upper (upper triangle with the diagonal).
+ * Meant for the Sec. 3 matrix, whose symmetric part is definite (the form is
+ * coercive), so every leading block is nonsingular.  A zero or non-finite
+ * pivot gives FPDE_ESINGULAR and, if failed_pivot (host) is not NULL, the
+ * first column of the 64-wide block where it occurred.  Synchronises
+ * `stream`.  Errors: FPDE_EINVAL, FPDE_ESINGULAR, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t *failed_pivot, void *stream);
+
+/*
+ * u = U^{-1} L^{-1} b with the factor from fpde_lu_factor.
+ *   LU: dev, n_dof x lda FP64 (unchanged); b, u: dev, n_dof FP64 (may alias).
+ * Synchronises `stream`.  Errors: FPDE_EINVAL, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_lu_solve(fpde_mesh *m, const double *LU, int64_t lda, const double *b, double *u, void *stream);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,7 @@ def _load():
     L.orc_ray_values.argtypes = [P, i32, i64, i32, i32, dbl, dbl, dbl, dbl, i32, i32, P, P]
     L.orc_assemble.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P]
     L.orc_assemble_div.argtypes = [P, i32, P, P, P, i32, P]
+    L.orc_assemble_div_rows.argtypes = [P, i32, P, P, P, i32, i64, P, P]
     L.orc_apply.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, P]
     L.orc_adjoint_sums.argtypes = [P, i32, dbl, dbl, dbl, i32, P, P, P, P]
     L.orc_load.argtypes = [P, i32, P, P]
@@ -294,12 +295,13 @@ class OracleMesh:
             raise OracleError(st, "assemble")
         return A
 
-    def assemble_div(self, nq: int, beta, pq=None) -> np.ndarray:
+    def assemble_div(self, nq: int, beta, pq=None, rows=None) -> np.ndarray:
         """Non-symmetric matrix of the divergence-form problem of Sec. 3:
         K_jk = a(psi_k, psi_j) with trial derivatives of order beta_i along
         e_i and the classical d_i psi_j of the own element on the test side.
         pq: (6, G) with p_i(x_g) in rows 0..2 and q_i(x_g) in rows 3..5;
-        default the coefficients of Sec. 3 (div_coefficients)."""
+        default the coefficients of Sec. 3 (div_coefficients).  rows: only
+        these rows (len(rows) x ndof), else the whole matrix."""
         beta = np.asarray(beta, dtype=np.float64)
         if pq is None:
             x, _ = self.gauss_points(nq)
@@ -309,8 +311,14 @@ class OracleMesh:
             raise ValueError("pq must be (6, G)")
         gm = np.ascontiguousarray(beta)
         ig2 = np.array([rgamma_(2.0 - b) for b in beta])
-        A = np.zeros((self.ndof, self.ndof))
-        st = _lib.orc_assemble_div(self._h, nq, _p(gm), _p(ig2), _p(pq), self.cap, _p(A))
+        if rows is None:
+            A = np.zeros((self.ndof, self.ndof))
+            st = _lib.orc_assemble_div(self._h, nq, _p(gm), _p(ig2), _p(pq), self.cap, _p(A))
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            A = np.zeros((len(rows), self.ndof))
+            st = _lib.orc_assemble_div_rows(self._h, nq, _p(gm), _p(ig2), _p(pq), self.cap, len(rows),
+                                            _p(rows), _p(A))
         if st != 0:
             raise OracleError(st, "assemble_div")
         return A

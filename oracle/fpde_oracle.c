@@ -654,8 +654,11 @@ int orc_assemble(const orc_mesh *m, int nq, double gamma, double inv_g2, double 
 /* q_i(x_g) at [(3 + i) G + g].  A is ndof x ndof row-major (row = test),     */
 /* zeroed by the caller.                                                      */
 /* ------------------------------------------------------------------------ */
-int orc_assemble_div(const orc_mesh *m, int nq, const double *gamma /* 3 */, const double *inv_g2 /* 3 */,
-                     const double *pq, int cap, double *A) {
+/* rows: NULL for the whole matrix (A is ndof x ndof), or the list of nrows
+   rows to keep (A is nrows x ndof, row r of A = row rows[r] of K; each
+   listed row at most once). */
+static int orc_div_sums(const orc_mesh *m, int nq, const double *gamma, const double *inv_g2,
+                        const double *pq, int cap, const int64_t *slot, double *A) {
   double bary[44], wq[11];
   if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
   orc_order ord[3];
@@ -669,6 +672,14 @@ int orc_assemble_div(const orc_mesh *m, int nq, const double *gamma /* 3 */, con
   int st = ORC_OK;
   for (int64_t g = 0; g < G && st == ORC_OK; g++) {
     int64_t t = g / nq;
+    if (slot) {  /* skip Gauss points whose element has no kept row */
+      int any = 0;
+      for (int jl = 0; jl < 4; jl++) {
+        int32_t j = m->dof[m->tet[4 * t + jl]];
+        if (j >= 0 && slot[j] >= 0) any = 1;
+      }
+      if (!any) continue;
+    }
     double wg = wq[g % nq] * m->vol[t];
     for (int i = 0; i < 3; i++) {
       int nl = orc_ray_vector(m, nq, bary, g, i, 0, &ord[i], 0, cap, w, Li, Lv, tb, rb);
@@ -679,13 +690,35 @@ int orc_assemble_div(const orc_mesh *m, int nq, const double *gamma /* 3 */, con
       for (int jl = 0; jl < 4; jl++) {
         int32_t j = m->dof[m->tet[4 * t + jl]];
         if (j < 0) continue;
+        int64_t row = slot ? slot[j] : j;
+        if (row < 0) continue;
         double dpsi = orc_slope(m, t, jl, i);
-        for (int b = 0; b < nl; b++) A[j * n + Li[b]] += -(wg * dpsi * p) * Lv[b];
-        for (int b = 0; b < nr; b++) A[j * n + Ri[b]] += (wg * dpsi * q) * Rv[b];
+        for (int b = 0; b < nl; b++) A[row * n + Li[b]] += -(wg * dpsi * p) * Lv[b];
+        for (int b = 0; b < nr; b++) A[row * n + Ri[b]] += (wg * dpsi * q) * Rv[b];
       }
     }
   }
   free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);
+  return st;
+}
+
+int orc_assemble_div(const orc_mesh *m, int nq, const double *gamma /* 3 */, const double *inv_g2 /* 3 */,
+                     const double *pq, int cap, double *A) {
+  return orc_div_sums(m, nq, gamma, inv_g2, pq, cap, NULL, A);
+}
+
+/* Rows rows[0..nrows) of the same matrix (A: nrows x ndof, zeroed by the
+   caller), for checks at sizes where the whole matrix is too large. */
+int orc_assemble_div_rows(const orc_mesh *m, int nq, const double *gamma, const double *inv_g2,
+                          const double *pq, int cap, int64_t nrows, const int64_t *rows, double *A) {
+  int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (m->ndof > 0 ? m->ndof : 1));
+  for (int64_t j = 0; j < m->ndof; j++) slot[j] = -1;
+  for (int64_t r = 0; r < nrows; r++) {
+    if (rows[r] < 0 || rows[r] >= m->ndof || slot[rows[r]] >= 0) { free(slot); return ORC_EINVAL; }
+    slot[rows[r]] = r;
+  }
+  int st = orc_div_sums(m, nq, gamma, inv_g2, pq, cap, slot, A);
+  free(slot);
   return st;
 }
 

@@ -4,8 +4,9 @@ Methods for Fractional PDEs in Three Dimensions").
 
 Thin ctypes binding of ``libfpde.so`` (C ABI declared in ``include/fpde.h``):
 argument marshalling only.  Every step (mesh set-up, path walk, closed-form
-derivatives, accumulation, load vector, Cholesky, refinement, adjoint) runs in
-the library's HIP kernels; PyTorch supplies device memory and the stream.
+derivatives, accumulation, load vector, Cholesky, refinement, adjoint, and for
+the divergence-form problem of Sec. 3 its accumulation and LU) runs in the
+library's HIP kernels; PyTorch supplies device memory and the stream.
 If the library is missing, every call raises: there is no fallback.
 """
 from __future__ import annotations
@@ -20,22 +21,23 @@ LIB_PATH = _HERE / "libfpde.so"
 
 FPDE_OK = 0
 FPDE_FP64, FPDE_MIXED = 0, 1
-FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS = 0, 1, 2
+FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS, FPDE_SRC_BALL_MMS = 0, 1, 2, 3
+FPDE_COEF_SEC3, FPDE_COEF_USER = 0, 1
 
 STATUS = {
     0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EMESH_NONMANIFOLD", -3: "FPDE_EMESH_DEGENERATE",
     -5: "FPDE_EPATH", -6: "FPDE_EALPHA", -7: "FPDE_ENOTSPD", -8: "FPDE_ENOCONV", -9: "FPDE_EHIP",
-    -10: "FPDE_ENOMEM", -11: "FPDE_EUNSUPPORTED",
+    -10: "FPDE_ENOMEM", -11: "FPDE_EUNSUPPORTED", -12: "FPDE_ESINGULAR",
 }
 
 EXPORTS = [
     "fpde_status_string", "fpde_mesh_create", "fpde_mesh_destroy", "fpde_mesh_info", "fpde_dof_map",
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
     "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
-    "fpde_template",
+    "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve",
 ]
 
-STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum"]
+STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div"]
 
 
 class FpdeError(RuntimeError):
@@ -54,6 +56,11 @@ class fpde_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("K", ctypes.c_double * 3), ("quad_points", ctypes.c_int),
                 ("precision", ctypes.c_int), ("source", ctypes.c_int), ("max_steps", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int)]
+
+
+class fpde_div_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double * 3), ("quad_points", ctypes.c_int), ("coef", ctypes.c_int),
+                ("source", ctypes.c_int), ("radius", ctypes.c_double), ("max_steps", ctypes.c_int)]
 
 
 class fpde_solve_info(ctypes.Structure):
@@ -91,6 +98,9 @@ def _lib():
     L.fpde_stage_times.argtypes = [P, P, P]
     L.fpde_plan_info.argtypes = [P, i32, P, P]
     L.fpde_template.argtypes = [P, i32, P, P, P]
+    L.fpde_div_assemble.argtypes = [P, P, P, P, i64, P, P, P]
+    L.fpde_lu_factor.argtypes = [P, P, i64, P, P]
+    L.fpde_lu_solve.argtypes = [P, P, i64, P, P, P]
     for name in EXPORTS:
         getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
             None if name == "fpde_mesh_destroy" else ctypes.c_int)
@@ -132,6 +142,20 @@ def params(alpha: float, K=(1.0, 1.0, 1.0), quad_points: int = 4, precision: int
     p.max_steps = int(max_steps)
     p.ir_tol = float(ir_tol)
     p.ir_max_iter = int(ir_max_iter)
+    return p
+
+
+def div_params(beta, quad_points: int = 4, coef: int = FPDE_COEF_SEC3, source: int = FPDE_SRC_ONE,
+               radius: float = 0.5, max_steps: int = 0):
+    """Parameters of the divergence-form problem of Sec. 3."""
+    p = fpde_div_params()
+    for i in range(3):
+        p.beta[i] = float(beta[i])
+    p.quad_points = int(quad_points)
+    p.coef = int(coef)
+    p.source = int(source)
+    p.radius = float(radius)
+    p.max_steps = int(max_steps)
     return p
 
 
@@ -242,6 +266,26 @@ class Mesh:
                "fpde_solve_factored")
         return out if info else None
 
+    # the divergence-form problem of Sec. 3 -------------------------------
+    def div_assemble(self, p, A, b=None, pq=None, f_gauss=None, stream=None):
+        _check(_lib().fpde_div_assemble(self._h, ctypes.byref(p), _ptr(pq), _ptr(A), A.stride(0), _ptr(b),
+                                        _ptr(f_gauss), _stream(stream)), "fpde_div_assemble")
+
+    def lu_factor(self, A, stream=None) -> int:
+        """In-place LU without pivoting; returns -1 (FpdeError on failure,
+        with .failed_pivot set to the failing block's first column)."""
+        piv = ctypes.c_int64(-1)
+        st = _lib().fpde_lu_factor(self._h, _ptr(A), A.stride(0), ctypes.byref(piv), _stream(stream))
+        if st != FPDE_OK:
+            e = FpdeError(st, "fpde_lu_factor")
+            e.failed_pivot = piv.value
+            raise e
+        return piv.value
+
+    def lu_solve(self, LU, b, u, stream=None):
+        _check(_lib().fpde_lu_solve(self._h, _ptr(LU), LU.stride(0), _ptr(b), _ptr(u), _stream(stream)),
+               "fpde_lu_solve")
+
     def adjoint(self, p, u, lam, stream=None):
         ga = ctypes.c_double()
         gk = (ctypes.c_double * 3)()
@@ -268,8 +312,21 @@ def solve_problem(mesh: Mesh, p, f_gauss=None, stream=None, info: bool = True):
     return u, A, out
 
 
+def solve_div_problem(mesh: Mesh, p, pq=None, f_gauss=None, stream=None):
+    """Assemble the Sec. 3 system and solve it by LU: returns (u, LU, b)."""
+    import torch
+    A = new_matrix(mesh, FPDE_FP64)
+    b = torch.empty(max(mesh.n_dof, 1), dtype=torch.float64, device="cuda")
+    mesh.div_assemble(p, A, b, pq, f_gauss, stream)
+    mesh.lu_factor(A, stream)
+    u = torch.empty_like(b)
+    mesh.lu_solve(A, b, u, stream)
+    return u, A, b
+
+
 from .autograd import FracSolve  # noqa: E402
 
-__all__ = ["Mesh", "params", "solve_problem", "new_matrix", "FracSolve", "FpdeError", "fpde_params",
-           "fpde_solve_info", "FPDE_FP64", "FPDE_MIXED", "FPDE_SRC_ONE", "FPDE_SRC_USER", "FPDE_SRC_CUBE_MMS",
-           "EXPORTS", "LIB_PATH"]
+__all__ = ["Mesh", "params", "div_params", "solve_problem", "solve_div_problem", "new_matrix", "FracSolve",
+           "FpdeError", "fpde_params", "fpde_div_params", "fpde_solve_info", "FPDE_FP64", "FPDE_MIXED",
+           "FPDE_SRC_ONE", "FPDE_SRC_USER", "FPDE_SRC_CUBE_MMS", "FPDE_SRC_BALL_MMS", "FPDE_COEF_SEC3",
+           "FPDE_COEF_USER", "EXPORTS", "LIB_PATH"]

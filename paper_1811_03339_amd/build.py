@@ -14,7 +14,8 @@ HERE = Path(__file__).resolve().parent
 ROOT = HERE.parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libfpde.so"
-SOURCES = ["mesh.hip", "walk.hip", "template.hip", "assemble.hip", "tubes.hip", "solve.hip"]
+SOURCES = ["mesh.hip", "walk.hip", "template.hip", "assemble.hip", "tubes.hip", "solve.hip", "lu.hip",
+           "divform.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -222,7 +222,7 @@ extern "C" int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_
   if (b) FPDE_TRY(launch_load(m, p, b, f_gauss, s));
   int f = take_flag(m, s);
   if (f != 0) {
-    P->val_alpha = -1.0;
+    invalidate_values(P);
     return f < 0 ? f : FPDE_EHIP;
   }
   return FPDE_OK;

@@ -1,0 +1,249 @@
+// Dense 64-wide building blocks shared by the Cholesky (SPD) and LU
+// (non-symmetric) factorizations and their triangular solves: the tile
+// product staged through LDS, wavefront helpers, and the block-row
+// triangular solve with ticket ordering and per-block flags.
+#pragma once
+
+#include "fpde_internal.h"
+
+namespace fpde {
+
+constexpr int NB = 64;
+
+// LDS written by some lanes of a wavefront and then read by other lanes of
+// the same wavefront (the wavefront's LDS operations complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Forces v to be computed at this point of the program.
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+// Lane-dependent index whose comparisons the compiler must not hoist out of
+// the enclosing loop (each hoisted comparison pins a 64-bit lane mask).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// 64 x 64 tile product acc = P Q^T over a 64-deep inner dimension, P and Q
+// given as row pointers with leading dimensions; rows past `prow`/`qrow`
+// (>= 1) read as zero.  256 threads, 4 x 4 outputs each (rows ty + 16a,
+// cols tx + 16b).  The two 32-deep chunks are staged through LDS; the second
+// chunk's global loads are issued before the first chunk's arithmetic, and
+// every load reads a valid address (rows clamped, then zeroed), so a
+// thread's loads are all in flight together.
+template <class T>
+__device__ __forceinline__ void stage_load(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
+                                           int64_t ldq, int qrow, int kk, int lr, int lc, T (&pr)[8], T (&qr)[8]) {
+#pragma unroll
+  for (int it = 0; it < 8; it++) {
+    const int rr = lr + 8 * it;
+    pr[it] = P[(int64_t)(rr < prow ? rr : prow - 1) * ldp + kk + lc];
+    qr[it] = Q[(int64_t)(rr < qrow ? rr : qrow - 1) * ldq + kk + lc];
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
+                                        int64_t ldq, int qrow, T (*sP)[33], T (*sQ)[33], T acc[4][4]) {
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const int lc = tid & 31, lr = tid >> 5;  // this thread stages rows lr + 8 it, column lc of a chunk
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = (T)0;
+  T pr[8], qr[8];
+  stage_load<T>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 32) {
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+      const int rr = lr + 8 * it;
+      sP[rr][lc] = rr < prow ? pr[it] : (T)0;
+      sQ[rr][lc] = rr < qrow ? qr[it] : (T)0;
+    }
+    __syncthreads();
+    if (kk + 32 < NB) stage_load<T>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
+#pragma unroll 4
+    for (int k = 0; k < 32; k++) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; a++) av[a] = sP[ty + 16 * a][k];
+#pragma unroll
+      for (int b = 0; b < 4; b++) bv[b] = sQ[tx + 16 * b][k];
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int64_t kSpinLimit = int64_t(1) << 22;
+
+// Whole-wave poll of the flags of blocks c, c + dir, ..., (count <= 64 of
+// them).  Returns how many leading ones carry `epoch` (>= 1), or 0 after
+// kSpinLimit polls without flag c.
+__device__ __forceinline__ int poll_run(const int *flags, int c, int dir, int count, int epoch) {
+  const int lane = threadIdx.x & 63;
+  const int k = lane < count ? lane : count - 1;
+  for (int64_t it = 0; it <= kSpinLimit; it++) {
+    const int v = __hip_atomic_load(&flags[c + dir * k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long pub = __ballot(v == epoch);
+    if (pub & 1ull) {
+      const unsigned long long gap = ~pub;
+      const int run = gap ? __ffsll((long long)gap) - 1 : 64;
+      return run < count ? run : count;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return 0;
+}
+
+// Sixteen per-lane values a[q] -> sum over the wave's 64 lanes of a[q], left
+// in every lane with (lane >> 2) & 15 == q (butterfly that halves the
+// vector at each exchange: 8 + 4 + 2 + 1 + 1 + 1 shuffles).
+__device__ __forceinline__ double wave_sum16(const double (&a)[16]) {
+  const int lane = threadIdx.x & 63;
+  double b[8], c[4], d[2];
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 8; k++) b[k] = (h5 ? a[k + 8] : a[k]) + __shfl_xor(h5 ? a[k] : a[k + 8], 32, 64);
+#pragma unroll
+  for (int k = 0; k < 4; k++) c[k] = (h4 ? b[k + 4] : b[k]) + __shfl_xor(h4 ? b[k] : b[k + 4], 16, 64);
+#pragma unroll
+  for (int k = 0; k < 2; k++) d[k] = (h3 ? c[k + 2] : c[k]) + __shfl_xor(h3 ? c[k] : c[k + 2], 8, 64);
+  double e = (h2 ? d[1] : d[0]) + __shfl_xor(h2 ? d[0] : d[1], 4, 64);
+  e += __shfl_xor(e, 2, 64);
+  e += __shfl_xor(e, 1, 64);
+  return e;
+}
+
+// Block-row triangular solve in one launch:
+//   x_b = D_b^{-1} (y_b - sum_{c in S(b)} A_bc x_c),
+// S(b) = {c < b} (UP = false, block rows handed out top to bottom) or
+// {c > b} (UP = true, bottom to top); DinvT holds (D_b^{-1})^T, 64 x 64
+// row-major per block.  Used for L (Cholesky forward; LU forward with the
+// unit lower factor) and U (LU backward), all read by block rows, so the
+// loads of A are whole 64-wide row segments.  Each workgroup takes the next
+// block row from an atomic ticket, so it only waits for block rows whose
+// tickets were taken before its own by workgroups that are already running.
+// Wave w owns rows 16w..16w+15 of the block row; lane = column within
+// block c.
+template <class T, bool UP>
+__global__ void __launch_bounds__(256) k_trsv_rows(const T *__restrict__ A, int64_t lda, int64_t n, int nblk,
+                                                   const T *__restrict__ DinvT, const double *__restrict__ y,
+                                                   double *__restrict__ x, int *flags, int *ticket, int epoch,
+                                                   int32_t *err) {
+  __shared__ int sb, ok;
+  __shared__ double rhs[NB];
+  __shared__ double red[4][NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    sb = atomicAdd(ticket, 1);
+    ok = 1;
+  }
+  __syncthreads();
+  if (sb >= nblk) return;
+  const int b = UP ? nblk - 1 - sb : sb;
+  const int nc = UP ? nblk - 1 - b : b;  // blocks of S(b)
+  const int c_first = UP ? nblk - 1 : 0, step = UP ? -1 : 1;
+  const int64_t r0 = (int64_t)b * NB;
+  const int nb = (int)((n - r0) < NB ? (n - r0) : NB);
+  // D_b^{-1}[lane][16w + q], read before any wait
+  double li[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) li[q] = (double)DinvT[(int64_t)b * NB * NB + (int64_t)(16 * w + q) * NB + lane];
+  int64_t roff[16];  // rows past the matrix end repeat the last row; their sums are dropped
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    const int r = 16 * w + q;
+    roff[q] = (r0 + (r < nb ? r : nb - 1)) * lda;
+  }
+  // column of block c read by this lane (only the last block can be
+  // partial: its missing columns load a valid entry and multiply zero)
+  auto col_of = [&](int c) {
+    const int64_t cc = (int64_t)c * NB + lane;
+    return cc < n ? cc : n - 1;
+  };
+  double part[16];
+  T cur[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    part[q] = 0.0;
+    cur[q] = (T)0;
+  }
+  if (nc > 0) {
+    const int64_t cc = col_of(c_first);
+#pragma unroll
+    for (int q = 0; q < 16; q++) cur[q] = A[roff[q] + cc];
+  }
+  bool good = true;
+  int ready = 0;  // the first `ready` blocks of S(b), in visiting order, are published
+  for (int it = 0; it < nc; it++) {
+    const int c = c_first + step * it;
+    if (it >= ready) {
+      const int k = poll_run(flags, c, step, (nc - it) < 64 ? (nc - it) : 64, epoch);
+      if (k == 0) {
+        good = false;
+        break;
+      }
+      ready = it + k;
+    }
+    const int64_t cc = (int64_t)c * NB + lane;
+    const double xv = cc < n ? x[cc] : 0.0;
+    const int64_t cn = col_of(it + 1 < nc ? c + step : c);
+    T nxt[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) nxt[q] = A[roff[q] + cn];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      part[q] = fma((double)cur[q], xv, part[q]);
+      cur[q] = nxt[q];
+    }
+  }
+  if (!good && lane == 0) ok = 0;
+  const double sum = wave_sum16(part);
+  if ((lane & 3) == 0) {
+    const int r = 16 * w + (lane >> 2);
+    rhs[r] = (r < nb) ? y[r0 + r] - sum : 0.0;
+  }
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; q++) s = fma(li[q], rhs[16 * w + q], s);
+  red[w][lane] = s;
+  __syncthreads();
+  if (tid < NB) {
+    if (tid < nb) x[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    // the writers make their stores visible device-wide before the flag goes up
+    __threadfence();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ok) set_flag(err, FPDE_EHIP);
+  }
+}
+
+// Host helpers (solve.hip).
+// Device buffer of `sets` x ceil(n / 64) inverses of 64 x 64 diagonal blocks
+// (elements of `elem` bytes), kept in the mesh handle and grown on demand.
+int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out);
+// Per-block flags (two sets of nblk) and two tickets for the solves.
+int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s);
+// p[0..n) = 0 with a kernel (no memset node when a caller captures a graph).
+int zero_ints(int *p, int n, hipStream_t s);
+
+}  // namespace fpde

@@ -66,8 +66,8 @@ struct Plan {
   int64_t *off = nullptr;     // n_half + 1: entries of half-ray h
   int32_t *ent_dof = nullptr; // n_ent
   int32_t *ent_ray = nullptr; // n_ent: owning half-ray
-  double *ent_val = nullptr;  // n_ent: values for `val_alpha`
-  double val_alpha = -1.0;    // order the values were computed for
+  double *ent_val = nullptr;  // n_ent: values, half-rays along e_i at order val_gamma[i]
+  double val_gamma[3] = {-1.0, -1.0, -1.0};  // per axis; -1 = not computed
   int64_t *row_off = nullptr; // n_dof + 1
   int64_t *inc = nullptr;     // n_ent: entry ids grouped by their dof
   // per incidence (row order): {entry id, partner offset, partner length << 2 | axis,
@@ -162,7 +162,11 @@ __device__ inline void set_flag(int32_t *flag, int code) { atomicCAS(flag, 0, co
 int take_flag(fpde_mesh *m, hipStream_t s, int64_t *aux = nullptr);
 
 int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out);
+// entry values at order gamma = alpha/2 on every axis
 int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s);
+// entry values at order gamma[i] along e_i (recomputes only the axes that changed)
+int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s);
+inline void invalidate_values(Plan *P) { P->val_gamma[0] = P->val_gamma[1] = P->val_gamma[2] = -1.0; }
 int check_params(const fpde_mesh *m, const fpde_params *p);
 void free_plan(Plan &P);
 // tube plan of a rule whose entries exist (cell edge = kappa x mean element edge)
@@ -184,5 +188,7 @@ struct Order {
   double c_alpha, dc_alpha;
 };
 Order order_scalars(double alpha);
+// the same scalars for a one-sided order gamma in (0, 1] (alpha = 2 gamma)
+inline Order gamma_scalars(double gamma) { return order_scalars(2.0 * gamma); }
 
 }  // namespace fpde

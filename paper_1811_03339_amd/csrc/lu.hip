@@ -1,0 +1,373 @@
+// Dense LU factorization without pivoting, A = L U (L unit lower, U upper,
+// both kept in A), and the solve A u = b, for the non-symmetric matrix of
+// the divergence-form two-sided problem (Sec. 3).  Its bilinear form is
+// coercive (the symmetric part of -A is positive definite), so every leading
+// block is nonsingular and no row exchange is needed; a zero or non-finite
+// pivot is reported, not worked around.
+//
+// Blocked right-looking, panel width NB = 64, three launches per panel k:
+//   diag   : one workgroup factors A_kk = L_kk U_kk in registers and forms
+//            inv(L_kk) (the same row operations applied to I) and inv(U_kk);
+//   panels : L_ik = A_ik inv(U_kk) for every 64-row strip below and
+//            U_kj = inv(L_kk) A_kj for every 64-column strip to the right,
+//            each a 64 x 64 x 64 tile product (no sequential dependency);
+//   update : C_ij -= L_ik U_kj over the whole trailing square, one workgroup
+//            per 64 x 64 output tile.
+// The solve runs the block-row triangular solves of dense.h forward with L
+// (inv(L_bb) per block) and backward with U (inv(U_bb)).
+#include <cmath>
+
+#include "dense.h"
+
+namespace fpde {
+
+namespace {
+
+struct LuSmem {
+  double row[2][2][NB];  // [buffer][factor | inverse][column]: the pivot row
+  double col[2][NB];     // [buffer][row]: the pivot column
+};
+
+// Thread t owns row r = t >> 2 of the 64 x 64 block and the 16 columns
+// c = (t & 3) + 4 k.  FACTOR: a holds the block and becomes L (strict lower,
+// multipliers) + U (upper); otherwise a holds an existing factor.  On exit
+// y = inv(L) and z = inv(U) in the same layout.  Rows/columns past nb are
+// identity.  Returns false when a pivot was zero or not finite (FACTOR).
+template <bool FACTOR>
+__device__ __forceinline__ bool lu_block(LuSmem &sm, double (&a)[16], double (&y)[16], double (&z)[16]) {
+  const int tid = threadIdx.x, r = tid >> 2, cls = tid & 3;
+  bool good = true;
+#pragma unroll
+  for (int k = 0; k < 16; k++) y[k] = (cls + 4 * k == r) ? 1.0 : 0.0;
+  // forward: eliminate column j from the rows below it; the same row
+  // operations turn I into inv(L).  Row j and column j are final when step j
+  // starts; the two buffers alternate, so one barrier per step suffices.
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int j = 4 * k + c, buf = j & 1;
+      if (r == j) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+          sm.row[buf][0][cls + 4 * kk] = a[kk];
+          sm.row[buf][1][cls + 4 * kk] = y[kk];
+        }
+      }
+      if (cls == c) sm.col[buf][r] = a[k];
+      __syncthreads();
+      if (r > j) {
+        double l = sm.col[buf][r];
+        if (FACTOR) l = l / sm.row[buf][0][j];
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+          // column cls + 4 kk against j = 4 k + c
+          const bool right = kk > k || (kk == k && cls > c);
+          if (FACTOR && right) a[kk] = fma(-l, sm.row[buf][0][cls + 4 * kk], a[kk]);
+          if (!right) y[kk] = fma(-l, sm.row[buf][1][cls + 4 * kk], y[kk]);
+        }
+        if (FACTOR && cls == c) a[k] = l;
+      }
+    }
+  }
+  // every pivot, the last row's included, is a diagonal entry of U
+  if (FACTOR) {
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+      if (cls + 4 * k == r && !(fabs(a[k]) > 0.0 && isfinite(a[k]))) good = false;
+  }
+  // backward: Z = inv(U) from the right.  At step j row j of Z is final up
+  // to its scaling by 1 / U_jj; rows above subtract U_rj / U_jj times it,
+  // row j then scales itself.  The buffers keep alternating across the turn
+  // from j = 63 forward to j = 63 backward (buffer (j & 1) ^ 1 here).
+#pragma unroll
+  for (int k = 0; k < 16; k++) z[k] = (cls + 4 * k == r) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 15; k >= 0; k--) {
+#pragma unroll
+    for (int c = 3; c >= 0; c--) {
+      const int j = 4 * k + c, buf = (j & 1) ^ 1;
+      if (r == j) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) sm.row[buf][1][cls + 4 * kk] = z[kk];
+      }
+      if (cls == c) sm.col[buf][r] = a[k];
+      __syncthreads();
+      const double d = sm.col[buf][j];
+      if (r < j) {
+        const double f = sm.col[buf][r] / d;
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+          const bool left = kk < k || (kk == k && cls < c);
+          if (!left) z[kk] = fma(-f, sm.row[buf][1][cls + 4 * kk], z[kk]);
+        }
+      } else if (r == j) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) z[kk] = z[kk] / d;
+      }
+    }
+  }
+  return good;
+}
+
+// FACTOR: one workgroup factors the diagonal block b = kfac / 64 and writes
+// L / U over it; otherwise one workgroup per block b = blockIdx.x reads the
+// existing factor.  Either way it writes inv(L_bb) (row-major), its
+// transpose, and inv(U_bb)^T for block b.
+template <bool FACTOR>
+__global__ void __launch_bounds__(256) k_lu_diag(double *__restrict__ A, int64_t lda, int64_t n, int64_t kfac,
+                                                 double *__restrict__ Linv, double *__restrict__ LinvT,
+                                                 double *__restrict__ UinvT, int32_t *flag, int64_t *aux) {
+  __shared__ LuSmem sm;
+  const int64_t b = FACTOR ? kfac / NB : (int64_t)blockIdx.x;
+  const int64_t k0 = b * NB;
+  const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
+  const int tid = threadIdx.x, r = tid >> 2, cls = tid & 3;
+  double a[16], y[16], z[16];
+  const int rr = r < nb ? r : nb - 1;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int c = cls + 4 * k;
+    a[k] = A[(k0 + rr) * lda + k0 + (c < nb ? c : nb - 1)];
+  }
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int c = cls + 4 * k;
+    if (r >= nb || c >= nb) a[k] = (r == c) ? 1.0 : 0.0;
+  }
+  const bool good = lu_block<FACTOR>(sm, a, y, z);
+  if (FACTOR && !good) {
+    set_flag(flag, FPDE_ESINGULAR);
+    atomicCAS((unsigned long long *)aux, ~0ull, (unsigned long long)k0);
+  }
+  const int64_t o = b * NB * NB;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int c = cls + 4 * k;
+    if (FACTOR && r < nb && c < nb) A[(k0 + r) * lda + k0 + c] = a[k];
+    Linv[o + r * NB + c] = y[k];
+    LinvT[o + c * NB + r] = y[k];
+    UinvT[o + c * NB + r] = z[k];
+  }
+}
+
+// acc = P Q over a 64-deep inner dimension: P is 64 x 64 (rows past `prow`
+// read as zero), Q is 64 x 64 row-major by inner index (columns past `qcol`
+// read as zero).  256 threads, 4 x 4 outputs each (rows ty + 16a, columns
+// tx + 16b), two 32-deep chunks staged through LDS as in tile_nt (Q
+// transposed on the way in), every load at a valid address.
+__device__ __forceinline__ void tile_nn(const double *__restrict__ P, int64_t ldp, int prow,
+                                        const double *__restrict__ Q, int64_t ldq, int qcol, double (*sP)[33],
+                                        double (*sQ)[33], double acc[4][4]) {
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const int lc = tid & 31, lr = tid >> 5;  // P: rows lr + 8 it, column lc of a chunk
+  const int qc = tid & 63, qr = tid >> 6;  // Q: column qc, inner rows qr + 4 it of a chunk
+  const int qcc = qc < qcol ? qc : qcol - 1;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = 0.0;
+  double pr[8], qv[8];
+  auto load = [&](int kk) {
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+      const int rr = lr + 8 * it;
+      pr[it] = P[(int64_t)(rr < prow ? rr : prow - 1) * ldp + kk + lc];
+      qv[it] = Q[(int64_t)(kk + qr + 4 * it) * ldq + qcc];
+    }
+  };
+  load(0);
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 32) {
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+      const int rr = lr + 8 * it;
+      sP[rr][lc] = rr < prow ? pr[it] : 0.0;
+      sQ[qc][qr + 4 * it] = qc < qcol ? qv[it] : 0.0;
+    }
+    __syncthreads();
+    if (kk + 32 < NB) load(kk + 32);
+#pragma unroll 4
+    for (int k = 0; k < 32; k++) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; a++) av[a] = sP[ty + 16 * a][k];
+#pragma unroll
+      for (int b = 0; b < 4; b++) bv[b] = sQ[tx + 16 * b][k];
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+}
+
+// Workgroups [0, ns): L strips (rows k1 + 64 x, columns of panel k);
+// [ns, 2 ns): U strips (rows of panel k, columns k1 + 64 (x - ns)).
+__global__ void __launch_bounds__(256) k_lu_panels(double *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
+                                                   int ns, const double *__restrict__ Linv_k,
+                                                   const double *__restrict__ UinvT_k) {
+  __shared__ double sP[64][33], sQ[64][33];
+  const int64_t k1 = k0 + NB;
+  const int x = blockIdx.x;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double acc[4][4];
+  if (x < ns) {
+    const int64_t r0 = k1 + 64 * (int64_t)x;
+    const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
+    tile_nt<double>(A + r0 * lda + k0, lda, rows, UinvT_k, NB, NB, sP, sQ, acc);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int rr = ty + 16 * a;
+      if (rr >= rows) continue;
+#pragma unroll
+      for (int b = 0; b < 4; b++) A[(r0 + rr) * lda + k0 + tx + 16 * b] = acc[a][b];
+    }
+  } else {
+    const int64_t c0 = k1 + 64 * (int64_t)(x - ns);
+    const int cols = (int)((n - c0) < 64 ? (n - c0) : 64);
+    tile_nn(Linv_k, NB, NB, A + k0 * lda + c0, lda, cols, sP, sQ, acc);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int rr = ty + 16 * a;
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int cc = tx + 16 * b;
+        if (cc < cols) A[(k0 + rr) * lda + c0 + cc] = acc[a][b];
+      }
+    }
+  }
+}
+
+// C_IJ -= L_Ik U_kJ over the trailing square from k1 = k0 + NB (T x T tiles)
+__global__ void __launch_bounds__(256) k_lu_update(double *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
+                                                   int T) {
+  __shared__ double sP[64][33], sQ[64][33];
+  const int64_t k1 = k0 + NB;
+  const int64_t x = blockIdx.x;
+  const int64_t I = x / T, J = x - I * T;
+  const int64_t ri = k1 + 64 * I, cj = k1 + 64 * J;
+  const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
+  const int qcol = (int)((n - cj) < 64 ? (n - cj) : 64);
+  double acc[4][4];
+  tile_nn(A + ri * lda + k0, lda, prow, A + k0 * lda + cj, lda, qcol, sP, sQ, acc);
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  double cv[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int64_t r = ri + ty + 16 * a, c = cj + tx + 16 * b;
+      cv[a][b] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
+    }
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    const int64_t r = ri + ty + 16 * a;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int64_t c = cj + tx + 16 * b;
+      if (r < n && c < n) A[r * lda + c] = cv[a][b] - acc[a][b];
+    }
+  }
+}
+
+inline unsigned blocks_of(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+__global__ void k_copy_f64(const double *__restrict__ a, double *__restrict__ b, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) b[k] = a[k];
+}
+
+}  // namespace
+
+// the three inverse sets of the LU blocks inside the mesh's buffer
+static int lu_inverses(fpde_mesh *m, int64_t n, double **Linv, double **LinvT, double **UinvT) {
+  void *lv = nullptr;
+  FPDE_TRY(ensure_linv(m, n, sizeof(double), 3, &lv));
+  const int64_t per = ((n + NB - 1) / NB) * NB * NB;
+  *Linv = (double *)lv;
+  *LinvT = *Linv + per;
+  *UinvT = *LinvT + per;
+  return FPDE_OK;
+}
+
+int lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t n, hipStream_t s) {
+  double *Linv, *LinvT, *UinvT;
+  FPDE_TRY(lu_inverses(m, n, &Linv, &LinvT, &UinvT));
+  const long t = timer_begin(m, s);
+  for (int64_t k0 = 0; k0 < n; k0 += NB) {
+    const int64_t o = (k0 / NB) * NB * NB;  // block k0 / 64 of each inverse set
+    // the kernel indexes the sets by its block itself: base pointers here
+    k_lu_diag<true><<<1, 256, 0, s>>>(A, lda, n, k0, Linv, LinvT, UinvT, m->flag, m->flag_aux);
+    const int64_t rest = n - k0 - NB;
+    if (rest > 0) {
+      const int ns = (int)((rest + 63) / 64);
+      k_lu_panels<<<2 * ns, 256, 0, s>>>(A, lda, n, k0, ns, Linv + o, UinvT + o);
+      k_lu_update<<<(unsigned)((int64_t)ns * ns), 256, 0, s>>>(A, lda, n, k0, ns);
+    }
+  }
+  timer_end(m, FPDE_STAGE_LU, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+// u = U^{-1} L^{-1} b from an existing factor; the inverses of its diagonal
+// blocks are formed first (one workgroup per block).
+int lu_solve(fpde_mesh *m, const double *LU, int64_t lda, int64_t n, const double *b, double *u, double *xs,
+             hipStream_t s) {
+  if (n == 0) return FPDE_OK;
+  double *Linv, *LinvT, *UinvT;
+  FPDE_TRY(lu_inverses(m, n, &Linv, &LinvT, &UinvT));
+  const int nblk = (int)((n + NB - 1) / NB);
+  FPDE_TRY(ensure_trsv_sync(m, nblk, s));
+  const int epoch = ++m->tsync_epoch;
+  int *fflags = m->tsync, *bflags = m->tsync + nblk, *tickets = m->tsync + 2 * nblk;
+  const long t = timer_begin(m, s);
+  k_lu_diag<false><<<nblk, 256, 0, s>>>(const_cast<double *>(LU), lda, n, 0, Linv, LinvT, UinvT, m->flag,
+                                        m->flag_aux);
+  if (u != b) k_copy_f64<<<blocks_of(n), 256, 0, s>>>(b, u, n);
+  FPDE_TRY(zero_ints(tickets, 2, s));
+  k_trsv_rows<double, false><<<nblk, 256, 0, s>>>(LU, lda, n, nblk, LinvT, u, xs, fflags, tickets, epoch, m->flag);
+  k_trsv_rows<double, true><<<nblk, 256, 0, s>>>(LU, lda, n, nblk, UinvT, xs, u, bflags, tickets + 1, epoch,
+                                                 m->flag);
+  timer_end(m, FPDE_STAGE_TRSV, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+}  // namespace fpde
+
+using namespace fpde;
+
+extern "C" int fpde_lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t *failed_pivot, void *stream) {
+  if (!m || !A || lda < m->ndof) return FPDE_EINVAL;
+  if (failed_pivot) *failed_pivot = -1;
+  hipStream_t s = S(stream);
+  const int64_t n = m->ndof;
+  if (n == 0) return FPDE_OK;
+  FPDE_TRY(lu_factor(m, A, lda, n, s));
+  int64_t col = -1;
+  const int f = take_flag(m, s, &col);
+  if (f != 0) {
+    if (failed_pivot) *failed_pivot = col;
+    return f < 0 ? f : FPDE_EHIP;
+  }
+  return FPDE_OK;
+}
+
+extern "C" int fpde_lu_solve(fpde_mesh *m, const double *LU, int64_t lda, const double *b, double *u,
+                             void *stream) {
+  if (!m || !LU || !b || !u || lda < m->ndof) return FPDE_EINVAL;
+  hipStream_t s = S(stream);
+  const int64_t n = m->ndof;
+  if (n == 0) return FPDE_OK;
+  double *xs = nullptr;
+  FPDE_TRY(dalloc(&xs, (size_t)n));
+  int st = lu_solve(m, LU, lda, n, b, u, xs, s);
+  const int f = take_flag(m, s);
+  dfree(xs);
+  if (st != FPDE_OK) return st;
+  return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
+}

@@ -278,6 +278,7 @@ extern "C" const char *fpde_status_string(int s) {
     case FPDE_EHIP: return "HIP runtime error";
     case FPDE_ENOMEM: return "device allocation failed";
     case FPDE_EUNSUPPORTED: return "unsupported combination";
+    case FPDE_ESINGULAR: return "LU without pivoting met a zero or non-finite pivot";
     default: return "unknown status";
   }
 }

@@ -19,15 +19,13 @@
 #include <cmath>
 #include <vector>
 
-#include "fpde_internal.h"
+#include "dense.h"
 
 namespace fpde {
 
 int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
                   hipStream_t s);
 int apply_scratch(fpde_mesh *m, Plan *P, double **d);
-
-constexpr int NB = 64;
 
 // inverse of the lower-triangular L held in LDS (rows >= nb are identity);
 // lane j builds column j of inv(L) in X by forward substitution (L reads
@@ -58,30 +56,6 @@ struct DiagSmem {
   double XcT[16][17];
   double dinv[NB];
 };
-
-// LDS written by some lanes of a wavefront and then read by other lanes of
-// the same wavefront (the wavefront's LDS operations complete in order).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
-// Forces v to be computed at this point of the program.
-__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
-
-// Lane-dependent index whose comparisons the compiler must not hoist out of
-// the enclosing loop (each hoisted comparison pins a 64-bit lane mask).
-__device__ __forceinline__ int opaque(int v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
 
 // Factor the 64 x 64 diagonal block held in sm.L (rows/columns >= nb are
 // identity), write L over A's block at (k0, k0), inv(L) to Linv and
@@ -300,62 +274,6 @@ __global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t l
   tri_inverse_to<T>(Lsh, X, Linv + (int64_t)blockIdx.x * NB * NB, LinvT + (int64_t)blockIdx.x * NB * NB);
 }
 
-// 64 x 64 tile product acc = P Q^T over a 64-deep inner dimension, P and Q
-// given as row pointers with leading dimensions; rows past `prow`/`qrow`
-// (>= 1) read as zero.  256 threads, 4 x 4 outputs each (rows ty + 16a,
-// cols tx + 16b).  The two 32-deep chunks are staged through LDS; the second
-// chunk's global loads are issued before the first chunk's arithmetic, and
-// every load reads a valid address (rows clamped, then zeroed), so a
-// thread's loads are all in flight together.
-template <class T>
-__device__ __forceinline__ void stage_load(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
-                                           int64_t ldq, int qrow, int kk, int lr, int lc, T (&pr)[8], T (&qr)[8]) {
-#pragma unroll
-  for (int it = 0; it < 8; it++) {
-    const int rr = lr + 8 * it;
-    pr[it] = P[(int64_t)(rr < prow ? rr : prow - 1) * ldp + kk + lc];
-    qr[it] = Q[(int64_t)(rr < qrow ? rr : qrow - 1) * ldq + kk + lc];
-  }
-}
-
-template <class T>
-__device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
-                                        int64_t ldq, int qrow, T (*sP)[33], T (*sQ)[33], T acc[4][4]) {
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
-  const int lc = tid & 31, lr = tid >> 5;  // this thread stages rows lr + 8 it, column lc of a chunk
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) acc[a][b] = (T)0;
-  T pr[8], qr[8];
-  stage_load<T>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
-#pragma unroll
-  for (int kk = 0; kk < NB; kk += 32) {
-#pragma unroll
-    for (int it = 0; it < 8; it++) {
-      const int rr = lr + 8 * it;
-      sP[rr][lc] = rr < prow ? pr[it] : (T)0;
-      sQ[rr][lc] = rr < qrow ? qr[it] : (T)0;
-    }
-    __syncthreads();
-    if (kk + 32 < NB) stage_load<T>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
-#pragma unroll 4
-    for (int k = 0; k < 32; k++) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; a++) av[a] = sP[ty + 16 * a][k];
-#pragma unroll
-      for (int b = 0; b < 4; b++) bv[b] = sQ[tx + 16 * b][k];
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-    }
-    __syncthreads();
-  }
-}
-
 // panel: rows [k0+NB+64 b, +64) of columns [k0, k0+NB) become B inv(L_kk)^T
 template <class T>
 __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
@@ -451,134 +369,6 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
 // Every wave polls the flags it needs by itself (acquire loads, up to 64
 // flags per poll), so the loop over earlier blocks has no barrier; a poll
 // that exceeds kSpinLimit marks the call failed and every wave still exits.
-constexpr int64_t kSpinLimit = int64_t(1) << 22;
-
-// Whole-wave poll of the flags of blocks c, c + dir, ..., (count <= 64 of
-// them).  Returns how many leading ones carry `epoch` (>= 1), or 0 after
-// kSpinLimit polls without flag c.
-__device__ __forceinline__ int poll_run(const int *flags, int c, int dir, int count, int epoch) {
-  const int lane = threadIdx.x & 63;
-  const int k = lane < count ? lane : count - 1;
-  for (int64_t it = 0; it <= kSpinLimit; it++) {
-    const int v = __hip_atomic_load(&flags[c + dir * k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long pub = __ballot(v == epoch);
-    if (pub & 1ull) {
-      const unsigned long long gap = ~pub;
-      const int run = gap ? __ffsll((long long)gap) - 1 : 64;
-      return run < count ? run : count;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  return 0;
-}
-
-// Sixteen per-lane values a[q] -> sum over the wave's 64 lanes of a[q], left
-// in every lane with (lane >> 2) & 15 == q (butterfly that halves the
-// vector at each exchange: 8 + 4 + 2 + 1 + 1 + 1 shuffles).
-__device__ __forceinline__ double wave_sum16(const double (&a)[16]) {
-  const int lane = threadIdx.x & 63;
-  double b[8], c[4], d[2];
-  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
-#pragma unroll
-  for (int k = 0; k < 8; k++) b[k] = (h5 ? a[k + 8] : a[k]) + __shfl_xor(h5 ? a[k] : a[k + 8], 32, 64);
-#pragma unroll
-  for (int k = 0; k < 4; k++) c[k] = (h4 ? b[k + 4] : b[k]) + __shfl_xor(h4 ? b[k] : b[k + 4], 16, 64);
-#pragma unroll
-  for (int k = 0; k < 2; k++) d[k] = (h3 ? c[k + 2] : c[k]) + __shfl_xor(h3 ? c[k] : c[k + 2], 8, 64);
-  double e = (h2 ? d[1] : d[0]) + __shfl_xor(h2 ? d[0] : d[1], 4, 64);
-  e += __shfl_xor(e, 2, 64);
-  e += __shfl_xor(e, 1, 64);
-  return e;
-}
-
-
-// forward: x_b = inv(L_bb) (y_b - sum_{c<b} L_bc x_c).  Wave w owns rows
-// 16w..16w+15 of the block row; lane = column within block c.
-template <class T>
-__global__ void __launch_bounds__(256) k_trsv_fwd(const T *__restrict__ L, int64_t lda, int64_t n, int nblk,
-                                                  const T *__restrict__ LinvT, const double *__restrict__ y,
-                                                  double *__restrict__ x, int *flags, int *ticket, int epoch,
-                                                  int32_t *err) {
-  __shared__ int sb, ok;
-  __shared__ double rhs[NB];
-  __shared__ double red[4][NB];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) {
-    sb = atomicAdd(ticket, 1);
-    ok = 1;
-  }
-  __syncthreads();
-  const int b = sb;
-  if (b >= nblk) return;
-  const int64_t r0 = (int64_t)b * NB;
-  const int nb = (int)((n - r0) < NB ? (n - r0) : NB);
-  // inv(L_bb)[lane][16w + q], read before any wait
-  double li[16];
-#pragma unroll
-  for (int q = 0; q < 16; q++) li[q] = (double)LinvT[(int64_t)b * NB * NB + (int64_t)(16 * w + q) * NB + lane];
-  int64_t roff[16];  // rows past the matrix end repeat the last row; their sums are dropped
-#pragma unroll
-  for (int q = 0; q < 16; q++) {
-    const int r = 16 * w + q;
-    roff[q] = (r0 + (r < nb ? r : nb - 1)) * lda + lane;
-  }
-  double part[16];
-  T cur[16];
-#pragma unroll
-  for (int q = 0; q < 16; q++) {
-    part[q] = 0.0;
-    cur[q] = (T)0;
-  }
-  if (b > 0) {  // column block 0 exists left of this block row
-#pragma unroll
-    for (int q = 0; q < 16; q++) cur[q] = L[roff[q]];
-  }
-  bool good = true;
-  int ready = 0;  // blocks [0, ready) known to be published
-  for (int c = 0; c < b; c++) {
-    if (c >= ready) {
-      const int k = poll_run(flags, c, 1, (b - c) < 64 ? (b - c) : 64, epoch);
-      if (k == 0) {
-        good = false;
-        break;
-      }
-      ready = c + k;
-    }
-    const double xv = x[(int64_t)c * NB + lane];
-    const int64_t cn = (int64_t)((c + 1 < b) ? c + 1 : c) * NB;
-    T nxt[16];
-#pragma unroll
-    for (int q = 0; q < 16; q++) nxt[q] = L[roff[q] + cn];
-#pragma unroll
-    for (int q = 0; q < 16; q++) {
-      part[q] = fma((double)cur[q], xv, part[q]);
-      cur[q] = nxt[q];
-    }
-  }
-  if (!good && lane == 0) ok = 0;
-  const double sum = wave_sum16(part);
-  if ((lane & 3) == 0) {
-    const int r = 16 * w + (lane >> 2);
-    rhs[r] = (r < nb) ? y[r0 + r] - sum : 0.0;
-  }
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < 16; q++) s = fma(li[q], rhs[16 * w + q], s);
-  red[w][lane] = s;
-  __syncthreads();
-  if (tid < NB) {
-    if (tid < nb) x[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-    // the writers make their stores visible device-wide before the flag goes up
-    __threadfence();
-  }
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) set_flag(err, FPDE_EHIP);
-  }
-}
-
 // backward: u_b = inv(L_bb)^T (x_b - sum_{c>b} L_cb^T u_c).  Lane = row of
 // the result block (column r0 + lane of L); wave w owns rows 16w..16w+15 of
 // block c.
@@ -701,10 +491,8 @@ __global__ void __launch_bounds__(256) k_sumsq(const double *__restrict__ x, int
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-// device buffer for the inverses of the diagonal blocks (bytes, reused)
-static int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, void **out) {
-  // inverses of the diagonal blocks, then their transposes
-  const size_t need = 2 * (size_t)((n + NB - 1) / NB) * NB * NB * elem;
+int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
+  const size_t need = (size_t)sets * (size_t)((n + NB - 1) / NB) * NB * NB * elem;
   if (m->linv_bytes < need) {
     if (m->linv) (void)hipFree(m->linv);
     m->linv = nullptr;
@@ -719,7 +507,7 @@ static int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, void **out) {
 template <class T>
 static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
   void *lv = nullptr;
-  FPDE_TRY(ensure_linv(m, n, sizeof(T), &lv));
+  FPDE_TRY(ensure_linv(m, n, sizeof(T), 2, &lv));  // inverses, then their transposes
   T *Linv = (T *)lv;
   const long t = timer_begin(m, s);
   // the first diagonal block on its own; every later one is factored by the
@@ -745,7 +533,14 @@ static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
 // y (n) holds the right-hand side on entry and the solution on exit;
 // x (n) is scratch.  Two launches (forward, backward), each preceded by a
 // reset of its ticket counter.
-static int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s) {
+int zero_ints(int *p, int n, hipStream_t s) {
+  if (n <= 0) return FPDE_OK;
+  k_zero_i32<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s) {
   if (m->tsync_n < nblk) {
     dfree(m->tsync);
     m->tsync_n = 0;
@@ -768,7 +563,7 @@ static int trsv_pair(const T *L, int64_t lda, int64_t n, const T *Linv, double *
   const T *LinvT = Linv + (size_t)nblk * NB * NB;
   const long t = timer_begin(m, s);
   k_zero_i32<<<1, 64, 0, s>>>(tickets, 2);
-  k_trsv_fwd<T><<<nblk, 256, 0, s>>>(L, lda, n, nblk, LinvT, y, x, fflags, tickets, epoch, m->flag);
+  k_trsv_rows<T, false><<<nblk, 256, 0, s>>>(L, lda, n, nblk, LinvT, y, x, fflags, tickets, epoch, m->flag);
   k_trsv_bwd<T><<<nblk, 256, 0, s>>>(L, lda, n, nblk, Linv, x, y, bflags, tickets + 1, epoch, m->flag);
   timer_end(m, FPDE_STAGE_TRSV, t, s);
   FPDE_HIP(hipGetLastError());
@@ -897,7 +692,7 @@ extern "C" int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const voi
   if (n == 0) return solve_with_factor(m, p, L, lda, nullptr, b, u, info, s);
   void *lv = nullptr;
   const size_t elem = p->precision == FPDE_MIXED ? sizeof(float) : sizeof(double);
-  FPDE_TRY(ensure_linv(m, n, elem, &lv));
+  FPDE_TRY(ensure_linv(m, n, elem, 2, &lv));
   const unsigned nbk = (unsigned)((n + NB - 1) / NB);
   if (p->precision == FPDE_MIXED)
     k_trinv<float><<<nbk, 64, 0, s>>>((const float *)L, lda, n, (float *)lv, (float *)lv + (size_t)nbk * NB * NB);

@@ -510,7 +510,7 @@ static int build_plan(fpde_mesh *m, Plan &P, int nq, int max_steps, hipStream_t 
       }
   }
   if ((st = build_tubes(m, P, kTubeCell, s)) != FPDE_OK) return fail(st);
-  P.val_alpha = -1.0;
+  invalidate_values(&P);
   return FPDE_OK;
 }
 
@@ -530,25 +530,37 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out) {
   return FPDE_OK;
 }
 
-// Fills the plan's entry values for order alpha (walk + closed-form eval).
-int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s) {
-  if (P->val_alpha == alpha) return FPDE_OK;
+// Fills the plan's entry values (walk + closed-form eval), one launch per
+// axis whose order changed: the half-rays along e_i are dir = 2i, 2i + 1,
+// i.e. the contiguous range [2 i G, (2 i + 2) G).
+int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s) {
   QuadRule rule;
   FPDE_TRY(quad_rule(P->nq, &rule));
-  Order o = order_scalars(alpha);
-  WalkArgs a = base_args(m, *P, rule);
-  a.h0 = 0;
-  a.n = P->n_half;
-  a.e = o.e;
-  a.inv_g2 = o.inv_g2;
-  a.off = P->off;
-  a.ent_val = P->ent_val;
   const long t = timer_begin(m, s);
-  launch_walk<W_VALUES>(a, s);
+  for (int i = 0; i < 3; i++) {
+    if (P->val_gamma[i] == gamma[i]) continue;
+    Order o = gamma_scalars(gamma[i]);
+    WalkArgs a = base_args(m, *P, rule);
+    a.h0 = (int64_t)(2 * i) * P->G;
+    a.n = 2 * P->G;
+    a.e = o.e;
+    a.inv_g2 = o.inv_g2;
+    a.off = P->off;
+    a.ent_val = P->ent_val;
+    launch_walk<W_VALUES>(a, s);
+    P->val_gamma[i] = gamma[i];
+  }
   timer_end(m, FPDE_STAGE_WALK, t, s);
-  FPDE_HIP(hipGetLastError());
-  P->val_alpha = alpha;
+  if (hipGetLastError() != hipSuccess) {
+    invalidate_values(P);
+    return FPDE_EHIP;
+  }
   return FPDE_OK;
+}
+
+int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s) {
+  const double g[3] = {0.5 * alpha, 0.5 * alpha, 0.5 * alpha};
+  return ensure_values_axes(m, P, g, s);
 }
 
 // Adjoint dots per half-ray (re-walks every path): value.u, value.lam,

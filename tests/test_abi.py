@@ -68,3 +68,17 @@ def test_params_layout_matches_header():
     assert ctypes.sizeof(F.fpde_params) == 8 + 24 + 16 + 8 + 8
     assert F.fpde_params.ir_tol.offset == 48
     assert ctypes.sizeof(F.fpde_solve_info) == 24
+
+
+def test_div_params_layout_matches_header():
+    # double beta[3]; int quad_points, coef, source; double radius; int max_steps
+    assert F.fpde_div_params.radius.offset == 40
+    assert ctypes.sizeof(F.fpde_div_params) == 56
+
+
+def test_div_and_lu_calls_reject_bad_arguments_without_device():
+    L = F._lib()
+    p = F.div_params((0.8, 0.8, 0.8))
+    assert L.fpde_div_assemble(None, ctypes.byref(p), None, None, 0, None, None, None) == -1
+    assert L.fpde_lu_factor(None, None, 0, None, None) == -1
+    assert L.fpde_lu_solve(None, None, 0, None, None, None) == -1
