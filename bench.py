@@ -16,7 +16,9 @@ value = Gauss-point paths per second over the timed steps (6 half-rays per
 Gauss point, summed over the six passes, divided by the step time).
 The single JSON line on stdout also carries the per-stage times, the
 roofline of the dominant kernel (measured with HIP events inside the library
-on the launch stream), the mixed-precision arm and the CPU oracle baseline.
+on the launch stream), the mixed-precision arm, the divergence-form problem
+of Sec. 3 on the finest mesh of Table 3 (assembly + LU + solve, with the LU
+against its FP64 roofline) and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -90,6 +92,71 @@ def syrk_flops(n):
     return tot, launches
 
 
+SEC3_WORKLOAD = "ball_h076"
+SEC3_BETAS = ((0.6, 0.7, 0.8), (0.8, 0.8, 0.8))
+SEC3_R = 0.5
+
+
+def bench_sec3(F, torch, dev, reps=4):
+    """The divergence-form problem of Sec. 3 on the finest mesh of Table 3
+    (ball |x| < 0.5, largest element diameter 0.0757): per pass the Sec. 3
+    assembly (walk values at the pass's orders, row accumulation, closed-form
+    source), the LU factorization and the two triangular solves.  Passes
+    alternate the two order sets of Table 3, so the walk re-evaluates the
+    axes whose order changed."""
+    import numpy as np
+    from fpde_inputs import workload_mesh
+    mesh = workload_mesh(SEC3_WORKLOAD)
+    g3 = F.Mesh(mesh.xyz, mesh.tet)
+    g3.plan(4)
+    n = g3.n_dof
+    A = torch.empty((n, n), dtype=torch.float64, device=dev)
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def one(beta):
+        p = F.div_params(beta, 4, source=F.FPDE_SRC_BALL_MMS, radius=SEC3_R)
+        g3.div_assemble(p, A, b)
+        g3.lu_factor(A)
+        g3.lu_solve(A, b, u)
+
+    one(SEC3_BETAS[1])  # warm-up
+    torch.cuda.synchronize()
+    g3.timing(True)
+    ts = []
+    for k in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        one(SEC3_BETAS[k % 2])
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    g3.timing(False)
+    st = g3.stage_times()
+    # nodal error against the exact solution of the last pass's orders
+    dof = g3.dof_map()
+    x = mesh.xyz[dof >= 0]
+    exact = (np.sum(x * x, axis=1) - SEC3_R ** 2) ** 2
+    uh = u.cpu().numpy()[dof[dof >= 0]]
+    lu_t = st["lu"][0] / max(st["lu"][1], 1) / 1e3
+    fl = 2.0 * n ** 3 / 3.0
+    out = {
+        "workload": f"{SEC3_WORKLOAD}: ball |x| < 0.5, {g3.n_tet} tets, {mesh.n_vert} nodes ({n} interior), "
+                    f"largest element diameter 0.0757 (Table 3), 4-point rule, p_i = cos x_i, "
+                    f"q_i = 1 - cos x_i, beta alternating {list(SEC3_BETAS)}",
+        "n_dof": n,
+        "pass_ms": sorted(ts)[len(ts) // 2],
+        "stages_ms_per_pass": {k: v[0] / reps for k, v in st.items() if v[1] > 0},
+        "lu": {"bound": "alu", "flops_per_factorization": fl, "ms": lu_t * 1e3,
+               "achieved": fl / lu_t / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+               "frac": fl / lu_t / FP64_PEAK},
+        "max_nodal_error": float(np.abs(uh - exact).max()),
+    }
+    g3.close()
+    return out
+
+
 def cpu_baseline(mesh_np):
     """The oracle, unchanged, single-threaded, on one full step."""
     from threadpoolctl import threadpool_limits
@@ -118,6 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision arm")
+    ap.add_argument("--no-sec3", action="store_true", help="skip the Sec. 3 divergence-form problem")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -270,6 +338,11 @@ def main():
                  "final_rel_residual": inf.final_rel_residual}
         log(f"[bench] mixed {mixed}")
 
+    sec3 = None
+    if not args.no_sec3:
+        sec3 = bench_sec3(F, torch, dev)
+        log(f"[bench] sec3 {sec3}")
+
     if args.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -316,6 +389,7 @@ def main():
         "roofline": roofline,
         "stage_rooflines": stage_roof,
         "mixed": mixed,
+        "sec3": sec3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -16,8 +16,11 @@
 // scaled by -w_g sigma_ji p_i and +w_g sigma_ji q_i.
 //
 //   k_div_rows  one workgroup per (row, column chunk): the chunk of the row
-//               lives in LDS, each thread takes (element, point, axis)
-//               items of the row's patch and adds its two vectors with LDS
+//               lives in LDS.  The row's (element, Gauss point, axis) items
+//               are set up one per thread (coefficients, vector extents) into
+//               LDS, then groups of 16 lanes sweep the items' vectors, each
+//               group reading 16 consecutive entries of a vector per load
+//               (a few cache lines per instruction), and add them with LDS
 //               atomics; the chunk is then written to K once.
 //   k_div_load  b_j = sum_g w_g f(x_g) psi_j(x_g), f = 1, user values, or
 //               the closed-form source of u = (|x|^2 - r^2)^2 on the ball.
@@ -62,55 +65,107 @@ __device__ __forceinline__ double gauss_coord(const DivArgs &a, int64_t t, int q
   return acc;
 }
 
-__device__ __forceinline__ void add_ray(double *row, int64_t c0, int cw, const int64_t *__restrict__ off,
-                                        const int32_t *__restrict__ dof, const double *__restrict__ val,
-                                        int64_t h, double coef) {
-  const int64_t e1 = off[h + 1];
-  for (int64_t e = off[h]; e < e1; e++) {
-    const int64_t k = (int64_t)dof[e] - c0;
-    if ((uint64_t)k < (uint64_t)cw) atomicAdd(&row[k], coef * val[e]);
-  }
+// One (element, Gauss point, axis) item of a row: its two derivative
+// vectors (first entry and length) and their scale factors.
+struct DivItem {
+  int32_t l0, nl, r0, nr;
+  double cl, cr;
+};
+constexpr int kItemBatch = 512;
+
+// entry k of a vector [e0, e0 + n), clamped into it; an empty vector reads
+// entry 0 of the plan (the value is discarded by the caller)
+__device__ __forceinline__ int64_t clamp_entry(int32_t e0, int32_t n, int k) {
+  return n > 0 ? (int64_t)e0 + (k < n ? k : n - 1) : 0;
 }
 
 __global__ void __launch_bounds__(256) k_div_rows(DivArgs a, double *__restrict__ A) {
   __shared__ double row[kDivChunk];
+  __shared__ DivItem its[kItemBatch];
+  const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
   const int64_t j = blockIdx.x;
   const int64_t c0 = (int64_t)blockIdx.y * a.chunk;
   const int cw = (int)((a.ndof - c0) < a.chunk ? (a.ndof - c0) : a.chunk);
-  for (int k = threadIdx.x; k < cw; k += blockDim.x) row[k] = 0.0;
-  __syncthreads();
+  for (int k = tid; k < cw; k += blockDim.x) row[k] = 0.0;
   const int32_t v = a.vert_of_dof[j];
   const int32_t p0 = a.vt_off[v];
   const int per = 3 * a.nq;
   const int items = (a.vt_off[v + 1] - p0) * per;
   const double *wq = a.qtab + 4 * a.nq;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int pt = it / per, rem = it - pt * per;
-    const int q = rem / 3, i = rem - 3 * q;
-    const int64_t t = a.vt_tet[p0 + pt];
-    const TetRec &R = a.rec[t];
-    int jl = 0;
+  for (int i0 = 0; i0 < items; i0 += kItemBatch) {
+    const int nb = (items - i0) < kItemBatch ? (items - i0) : kItemBatch;
+    // phase A: one thread per item
+    for (int k = tid; k < nb; k += blockDim.x) {
+      const int it = i0 + k;
+      const int pt = it / per, rem = it - pt * per;
+      const int q = rem / 3, i = rem - 3 * q;
+      const int64_t t = a.vt_tet[p0 + pt];
+      const TetRec &R = a.rec[t];
+      int jl = 0;
 #pragma unroll
-    for (int m = 1; m < 4; m++)
-      if (R.dof[m] == (int32_t)j) jl = m;
-    const double sigma = vslope(R, jl, i);
-    const int64_t g = t * a.nq + q;
-    const double wg = wq[q] * a.vol[t];
-    double p, qc;
-    if (a.pq) {
-      p = a.pq[(int64_t)i * a.G + g];
-      qc = a.pq[(int64_t)(3 + i) * a.G + g];
-    } else {
-      p = cos(gauss_coord(a, t, q, i));
-      qc = 1.0 - p;
+      for (int m = 1; m < 4; m++)
+        if (R.dof[m] == (int32_t)j) jl = m;
+      const double sigma = vslope(R, jl, i);
+      const int64_t g = t * a.nq + q;
+      const double wg = wq[q] * a.vol[t];
+      double p, qc;
+      if (a.pq) {
+        p = a.pq[(int64_t)i * a.G + g];
+        qc = a.pq[(int64_t)(3 + i) * a.G + g];
+      } else {
+        p = cos(gauss_coord(a, t, q, i));
+        qc = 1.0 - p;
+      }
+      const int64_t hl = (int64_t)(2 * i) * a.G + g, hr = hl + a.G;
+      const int64_t l0 = a.off[hl], l1 = a.off[hl + 1], r0 = a.off[hr], r1 = a.off[hr + 1];
+      DivItem d;
+      d.l0 = (int32_t)l0;
+      d.nl = (int32_t)(l1 - l0);
+      d.r0 = (int32_t)r0;
+      d.nr = (int32_t)(r1 - r0);
+      d.cl = -(wg * sigma * p);
+      d.cr = wg * sigma * qc;
+      its[k] = d;
     }
-    const int64_t hl = (int64_t)(2 * i) * a.G + g;
-    add_ray(row, c0, cw, a.off, a.ent_dof, a.ent_val, hl, -(wg * sigma * p));
-    add_ray(row, c0, cw, a.off, a.ent_dof, a.ent_val, hl + a.G, wg * sigma * qc);
+    __syncthreads();
+    // phase B: a group of 16 lanes sweeps two items' four vectors, 16
+    // consecutive entries of each per round (loads first, then the adds)
+    for (int k = grp; k < nb; k += 32) {
+      const DivItem P = its[k];
+      DivItem Q = P;
+      if (k + 16 < nb) {
+        Q = its[k + 16];
+      } else {
+        Q.nl = 0;
+        Q.nr = 0;
+      }
+      int nmax = P.nl > P.nr ? P.nl : P.nr;
+      nmax = Q.nl > nmax ? Q.nl : nmax;
+      nmax = Q.nr > nmax ? Q.nr : nmax;
+      for (int b = 0; b < nmax; b += 16) {
+        const int kk = b + gl;
+        const int64_t e[4] = {clamp_entry(P.l0, P.nl, kk), clamp_entry(P.r0, P.nr, kk),
+                              clamp_entry(Q.l0, Q.nl, kk), clamp_entry(Q.r0, Q.nr, kk)};
+        int32_t d[4];
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          d[u] = a.ent_dof[e[u]];
+          x[u] = a.ent_val[e[u]];
+        }
+        const int32_t n[4] = {P.nl, P.nr, Q.nl, Q.nr};
+        const double cf[4] = {P.cl, P.cr, Q.cl, Q.cr};
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int64_t col = (int64_t)d[u] - c0;
+          if (kk < n[u] && (uint64_t)col < (uint64_t)cw) atomicAdd(&row[col], cf[u] * x[u]);
+        }
+      }
+    }
+    __syncthreads();  // the batch's items are done before the next batch overwrites them
   }
-  __syncthreads();
   double *out = A + j * a.lda + c0;
-  for (int k = threadIdx.x; k < cw; k += blockDim.x) out[k] = row[k];
+  for (int k = tid; k < cw; k += blockDim.x) out[k] = row[k];
 }
 
 // Closed-form source of the exact solution u = (|x|^2 - r^2)^2 with

@@ -28,84 +28,108 @@ struct LuSmem {
   double col[2][NB];     // [buffer][row]: the pivot column
 };
 
-// Thread t owns row r = t >> 2 of the 64 x 64 block and the 16 columns
-// c = (t & 3) + 4 k.  FACTOR: a holds the block and becomes L (strict lower,
-// multipliers) + U (upper); otherwise a holds an existing factor.  On exit
-// y = inv(L) and z = inv(U) in the same layout.  Rows/columns past nb are
-// identity.  Returns false when a pivot was zero or not finite (FACTOR).
+// Thread t owns row r = t >> 2 of the 64 x 64 block and 16 of its columns
+// (the four threads of a row are neighbouring lanes of one wavefront).
+// FACTOR: a holds the block and becomes L (strict lower, multipliers) + U
+// (upper); otherwise a holds an existing factor.  On exit y = inv(L) and
+// z = inv(U) in the same layout.  Rows/columns past nb are identity.
+// Returns false when a pivot was zero or not finite (FACTOR).
+//
+// One pass over the pivots j = 0..63, one barrier each.  Row j and column j
+// of the partly eliminated block are final when step j starts; they are
+// published to LDS (two alternating buffers, so the next step's writes
+// cannot overtake this step's reads), then
+//   rows r > j:  l = A_rj / U_jj, A_rc -= l U_jc (c > j), A_rj = l, and the
+//                same row operation on Y (Y = I at the start, inv(L) at the
+//                end: inv(L) is the product of the elimination steps);
+//   rows r <= j: column j of W = inv(U) from W U = I,
+//                W_rj = (delta_rj - sum_{k<j} W_rk U_kj) / U_jj, whose
+//                column of U is the published column j and whose W_rk were
+//                formed at the earlier steps (a 4-lane sum over the row's
+//                threads).
+// The pivots run in 16 blocks of 4 (a runtime loop over the blocks, the 4
+// steps of a block unrolled), so the code stays small.  To keep register
+// indices static, the three arrays rotate by one slot after each block: in
+// block kb, slot s of a thread with t & 3 = cl holds column
+// cl + 4 ((s + kb) mod 16), so the block's own columns are in slot 0.  The
+// LDS row buffer is kept in slot order; the column buffer (indexed by row)
+// in the same rotated order, row r at (r & 3) + 4 ((r / 4 - kb) mod 16).
 template <bool FACTOR>
 __device__ __forceinline__ bool lu_block(LuSmem &sm, double (&a)[16], double (&y)[16], double (&z)[16]) {
   const int tid = threadIdx.x, r = tid >> 2, cls = tid & 3;
-  bool good = true;
-#pragma unroll
-  for (int k = 0; k < 16; k++) y[k] = (cls + 4 * k == r) ? 1.0 : 0.0;
-  // forward: eliminate column j from the rows below it; the same row
-  // operations turn I into inv(L).  Row j and column j are final when step j
-  // starts; the two buffers alternate, so one barrier per step suffices.
 #pragma unroll
   for (int k = 0; k < 16; k++) {
+    y[k] = (cls + 4 * k == r) ? 1.0 : 0.0;
+    z[k] = 0.0;
+  }
+#pragma unroll 1
+  for (int kb = 0; kb < 16; kb++) {
+    const int own = (r & 3) + 4 * (((r >> 2) - kb) & 15);  // this row's slot in the column buffer
+    const int live = 15 - kb;  // slots 1..live hold columns right of the block
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-      const int j = 4 * k + c, buf = j & 1;
+      const int j = 4 * kb + c, buf = c & 1;
       if (r == j) {
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++) {
-          sm.row[buf][0][cls + 4 * kk] = a[kk];
-          sm.row[buf][1][cls + 4 * kk] = y[kk];
+        for (int s = 0; s < 16; s++) {
+          sm.row[buf][0][cls + 4 * s] = a[s];
+          sm.row[buf][1][cls + 4 * s] = y[s];
         }
       }
-      if (cls == c) sm.col[buf][r] = a[k];
+      if (cls == c) sm.col[buf][own] = a[0];
       __syncthreads();
-      if (r > j) {
-        double l = sm.col[buf][r];
-        if (FACTOR) l = l / sm.row[buf][0][j];
+      // everything this step reads from LDS, loaded before any use
+      double ra[16], ry[16], rc[16];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++) {
-          // column cls + 4 kk against j = 4 k + c
-          const bool right = kk > k || (kk == k && cls > c);
-          if (FACTOR && right) a[kk] = fma(-l, sm.row[buf][0][cls + 4 * kk], a[kk]);
-          if (!right) y[kk] = fma(-l, sm.row[buf][1][cls + 4 * kk], y[kk]);
-        }
-        if (FACTOR && cls == c) a[k] = l;
+      for (int s = 0; s < 16; s++) {
+        ra[s] = sm.row[buf][0][cls + 4 * s];
+        ry[s] = sm.row[buf][1][cls + 4 * s];
+        rc[s] = sm.col[buf][cls + 4 * s];
       }
+      const double piv = sm.row[buf][0][c];  // U_jj: column j is slot 0 of lane class c
+      const double cown = sm.col[buf][own];
+      const double rp = 1.0 / piv;
+      // column j of inv(U): sum over the columns left of j (inactive slots
+      // contribute an exact zero)
+      double part = 0.0;
+#pragma unroll
+      for (int s = 0; s < 16; s++) {
+        const bool left = s == 0 ? cls < c : s > live;
+        part = fma(left ? z[s] : 0.0, rc[s], part);
+      }
+      part += __shfl_xor(part, 1, 64);
+      part += __shfl_xor(part, 2, 64);
+      if (cls == c && r <= j) z[0] = ((r == j ? 1.0 : 0.0) - part) * rp;
+      // elimination below the pivot: multipliers are zero where a slot does
+      // not take part, which leaves it unchanged
+      const double l = r > j ? (FACTOR ? cown * rp : cown) : 0.0;
+#pragma unroll
+      for (int s = 0; s < 16; s++) {
+        const bool right = s == 0 ? cls > c : s <= live;
+        if (FACTOR) a[s] = fma(right ? -l : 0.0, ra[s], a[s]);
+        y[s] = fma(right ? 0.0 : -l, ry[s], y[s]);
+      }
+      if (FACTOR && cls == c && r > j) a[0] = l;
     }
+    // rotate: slot s takes slot s + 1, slot 15 takes slot 0
+    const double a0 = a[0], y0 = y[0], z0 = z[0];
+#pragma unroll
+    for (int s = 0; s < 15; s++) {
+      a[s] = a[s + 1];
+      y[s] = y[s + 1];
+      z[s] = z[s + 1];
+    }
+    a[15] = a0;
+    y[15] = y0;
+    z[15] = z0;
   }
-  // every pivot, the last row's included, is a diagonal entry of U
+  // after 16 rotations every slot is back at column cls + 4 s; every pivot,
+  // the last row's included, is a diagonal entry of U
+  bool good = true;
   if (FACTOR) {
 #pragma unroll
     for (int k = 0; k < 16; k++)
       if (cls + 4 * k == r && !(fabs(a[k]) > 0.0 && isfinite(a[k]))) good = false;
-  }
-  // backward: Z = inv(U) from the right.  At step j row j of Z is final up
-  // to its scaling by 1 / U_jj; rows above subtract U_rj / U_jj times it,
-  // row j then scales itself.  The buffers keep alternating across the turn
-  // from j = 63 forward to j = 63 backward (buffer (j & 1) ^ 1 here).
-#pragma unroll
-  for (int k = 0; k < 16; k++) z[k] = (cls + 4 * k == r) ? 1.0 : 0.0;
-#pragma unroll
-  for (int k = 15; k >= 0; k--) {
-#pragma unroll
-    for (int c = 3; c >= 0; c--) {
-      const int j = 4 * k + c, buf = (j & 1) ^ 1;
-      if (r == j) {
-#pragma unroll
-        for (int kk = 0; kk < 16; kk++) sm.row[buf][1][cls + 4 * kk] = z[kk];
-      }
-      if (cls == c) sm.col[buf][r] = a[k];
-      __syncthreads();
-      const double d = sm.col[buf][j];
-      if (r < j) {
-        const double f = sm.col[buf][r] / d;
-#pragma unroll
-        for (int kk = 0; kk < 16; kk++) {
-          const bool left = kk < k || (kk == k && cls < c);
-          if (!left) z[kk] = fma(-f, sm.row[buf][1][cls + 4 * kk], z[kk]);
-        }
-      } else if (r == j) {
-#pragma unroll
-        for (int kk = 0; kk < 16; kk++) z[kk] = z[kk] / d;
-      }
-    }
   }
   return good;
 }

@@ -12,6 +12,12 @@
   alpha = 1.3): mixed precision with an FP32 matrix of ~18 GB; sampled paths
   and derivative vectors against the oracle, K x (FP32, dense) against the
   FP64 matrix-free product, refinement to 1e-8.
+* ball_h076 (the finest mesh of Table 3, ~8.2k unknowns), the divergence-form
+  problem of Sec. 3 at beta = (0.6, 0.7, 0.8): the whole matrix, the load
+  vector and the LU solution against the oracle (LAPACK LU).
+* sphere150k, Sec. 3 at beta = (0.8, 0.8, 0.8) with the 11-point rule: ~25k
+  unknowns, so every row is accumulated in four column chunks; 16 sampled
+  rows (first, last, random) against the oracle's rows.
 """
 import gc
 import time
@@ -182,5 +188,51 @@ def test_ellipsoid400k_mixed():
     stages = {k: round(v[0], 1) for k, v in gm.stage_times().items() if v[1]}
     log(f"[ellipsoid400k] stage ms {stages}")
     del A32, gm
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_ball_h076_sec3_whole_system():
+    m = workload_mesh("ball_h076")
+    log(f"[ball_h076] {m.n_vert} vertices, {m.n_tet} elements")
+    om = oracle.OracleMesh(m.xyz, m.tet)
+    gm = F.Mesh(m.xyz, m.tet)
+    n, nq, beta = gm.n_dof, 4, (0.6, 0.7, 0.8)
+    p = F.div_params(beta, nq, source=F.FPDE_SRC_BALL_MMS, radius=0.5)
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    _, t_asm = timed(lambda: gm.div_assemble(p, A, b))
+    Ko = om.assemble_div(nq, beta)
+    assert rel(A.cpu().numpy(), Ko) <= 1e-11
+    x, _ = om.gauss_points(nq)
+    bo = om.load(nq, oracle.ball_source(x, beta, 0.5))
+    assert rel(b.cpu().numpy(), bo) <= 1e-11
+    _, t_lu = timed(lambda: gm.lu_factor(A))
+    u = torch.empty_like(b)
+    _, t_sol = timed(lambda: gm.lu_solve(A, b, u))
+    from scipy.linalg import lu_factor, lu_solve
+    uo = lu_solve(lu_factor(Ko), bo)
+    assert rel(u.cpu().numpy(), uo) <= 1e-9
+    log(f"[ball_h076] n={n} assemble {t_asm:.3f}s LU {t_lu:.3f}s solve {t_sol:.4f}s")
+    del A, gm
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_sphere150k_sec3_chunked_rows():
+    m = workload_mesh("sphere150k")
+    om = oracle.OracleMesh(m.xyz, m.tet)
+    gm = F.Mesh(m.xyz, m.tet)
+    n, nq, beta = gm.n_dof, 11, (0.8, 0.8, 0.8)
+    assert n > 3 * 8192
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    _, t_asm = timed(lambda: gm.div_assemble(F.div_params(beta, nq), A))
+    rng = np.random.default_rng(1500)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.integers(1, n - 1, size=14)]))
+    Ko = om.assemble_div(nq, beta, rows=rows)
+    Kg = A[torch.tensor(rows, device="cuda")].cpu().numpy()
+    assert rel(Kg, Ko) <= 1e-11
+    log(f"[sphere150k sec3] n={n} assemble {t_asm:.3f}s, {len(rows)} rows match")
+    del A, gm
     gc.collect()
     torch.cuda.empty_cache()
