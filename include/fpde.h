@@ -213,8 +213,9 @@ int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const doub
  * Stages: walk + closed-form evaluation, accumulation (both tube passes),
  * load vector, Cholesky factorisation (all panels), triangular solves,
  * matrix-free product, symbolic plan, adjoint re-walk, the tube products
- * pass timed again on its own inside CONTRACT, and for the problem of
- * Sec. 3 its LU factorisation and its accumulation.
+ * pass timed again on its own inside CONTRACT, for the problem of Sec. 3
+ * its LU factorisation and its accumulation, and the sparse products and
+ * conjugate-gradient solves.
  *   fpde_timing(m, 1) clears the totals and starts recording; (m, 0) stops.
  *   fpde_stage_times waits for the recorded events, then writes per stage
  *   the summed milliseconds (host, FPDE_NSTAGES doubles) and the number of
@@ -232,7 +233,9 @@ enum {
   FPDE_STAGE_ACCUM = 8,
   FPDE_STAGE_LU = 9,    /* LU factorisation of the Sec. 3 matrix (all panels) */
   FPDE_STAGE_DIV = 10,  /* accumulation of the Sec. 3 matrix */
-  FPDE_NSTAGES = 11
+  FPDE_STAGE_SPMV = 11, /* CSR products (fpde_csr_apply and inside fpde_cg_solve) */
+  FPDE_STAGE_CG = 12,   /* a whole conjugate-gradient solve */
+  FPDE_NSTAGES = 13
 };
 int fpde_timing(fpde_mesh *m, int enable);
 int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
@@ -263,6 +266,54 @@ int fpde_template(fpde_mesh *m, int tile, uint8_t *tiles, int64_t *nnz, void *st
  *   host, 8 int64.  Synchronises `stream`.
  */
 int fpde_plan_info(fpde_mesh *m, int quad_points, int64_t *out, void *stream);
+
+/*
+ * ---- Sparse storage on the template (Sec. 2.3, Table 1) and a Krylov solve ----
+ *
+ * K stored as CSR on the template T (the pattern of fpde_template, at node
+ * granularity): rows are unknowns, columns increasing, the diagonal always
+ * present.  T contains the nonzero pattern of K, so nothing is dropped.
+ */
+
+/*
+ * The template as CSR.  row_ptr: dev, n_dof + 1 int64 (always written);
+ * nnz: host int64 (always written).  col: dev, capacity int32, written when
+ * not NULL (call once with col = NULL to learn nnz).  O(n_dof^2) box tests,
+ * once per mesh.  Synchronises `stream`.
+ * Errors: FPDE_EINVAL (capacity < nnz), FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_template_csr(fpde_mesh *m, int64_t *row_ptr, int32_t *col, int64_t capacity, int64_t *nnz,
+                      void *stream);
+
+/*
+ * Assembly of K (the same sums as fpde_assemble) into val (dev, nnz FP64)
+ * on the pattern row_ptr / col from fpde_template_csr, and of b (dev, n_dof,
+ * may be NULL).  FPDE_FP64 only.  Synchronises `stream`.
+ * Errors: FPDE_EINVAL, FPDE_EALPHA, FPDE_EUNSUPPORTED (mixed), FPDE_EPATH,
+ * FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_assemble_csr(fpde_mesh *m, const fpde_params *p, const int64_t *row_ptr, const int32_t *col,
+                      double *val, double *b, const double *f_gauss, void *stream);
+
+/* y = K x for the CSR matrix (all dev, FP64).  Does not synchronise. */
+int fpde_csr_apply(fpde_mesh *m, const int64_t *row_ptr, const int32_t *col, const double *val,
+                   const double *x, double *y, void *stream);
+
+/*
+ * K u = b by conjugate gradients with the Jacobi preconditioner (K is
+ * symmetric positive definite), from u = 0, until ||b - K u|| / ||b|| <= tol
+ * in the recurrence; info->final_rel_residual is then recomputed from
+ * b - K u.  The operator is the CSR matrix when row_ptr is not NULL, else the
+ * matrix-free product of fpde_apply (no N^2 storage at all).
+ *   b, u: dev, n_dof FP64, distinct.  tol: 0 = 1e-10.  max_iter: 0 = 10000.
+ *   info: host, may be NULL (ir_iters = CG iterations).
+ * Synchronises `stream` every iteration.
+ * Errors: FPDE_EINVAL, FPDE_EALPHA, FPDE_ENOTSPD (a diagonal entry or p.Kp
+ * <= 0), FPDE_ENOCONV (max_iter reached), FPDE_EPATH, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_cg_solve(fpde_mesh *m, const fpde_params *p, const int64_t *row_ptr, const int32_t *col,
+                  const double *val, const double *b, double *u, double tol, int max_iter,
+                  fpde_solve_info *info, void *stream);
 
 /*
  * ---- The divergence-form two-sided problem of Sec. 3 (eq. equ:sfde2) ----

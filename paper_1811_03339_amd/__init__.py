@@ -34,10 +34,12 @@ EXPORTS = [
     "fpde_status_string", "fpde_mesh_create", "fpde_mesh_destroy", "fpde_mesh_info", "fpde_dof_map",
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
     "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
-    "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve",
+    "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve", "fpde_template_csr",
+    "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve",
 ]
 
-STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div"]
+STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div", "spmv",
+          "cg"]
 
 
 class FpdeError(RuntimeError):
@@ -101,6 +103,10 @@ def _lib():
     L.fpde_div_assemble.argtypes = [P, P, P, P, i64, P, P, P]
     L.fpde_lu_factor.argtypes = [P, P, i64, P, P]
     L.fpde_lu_solve.argtypes = [P, P, i64, P, P, P]
+    L.fpde_template_csr.argtypes = [P, P, P, i64, P, P]
+    L.fpde_assemble_csr.argtypes = [P, P, P, P, P, P, P, P]
+    L.fpde_csr_apply.argtypes = [P, P, P, P, P, P, P]
+    L.fpde_cg_solve.argtypes = [P, P, P, P, P, P, P, dbl, i32, P, P]
     for name in EXPORTS:
         getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
             None if name == "fpde_mesh_destroy" else ctypes.c_int)
@@ -265,6 +271,38 @@ class Mesh:
                                           ctypes.byref(out) if info else None, _stream(stream)),
                "fpde_solve_factored")
         return out if info else None
+
+    # sparse storage on the template, conjugate gradients ------------------
+    def template_csr(self, stream=None):
+        """The template of Sec. 2.3 as CSR: (row_ptr int64, col int32), device tensors."""
+        import torch
+        L = _lib()
+        rp = torch.empty(self.n_dof + 1, dtype=torch.int64, device="cuda")
+        nnz = ctypes.c_int64()
+        _check(L.fpde_template_csr(self._h, _ptr(rp), None, 0, ctypes.byref(nnz), _stream(stream)),
+               "fpde_template_csr")
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        _check(L.fpde_template_csr(self._h, _ptr(rp), _ptr(col), nnz.value, ctypes.byref(nnz), _stream(stream)),
+               "fpde_template_csr")
+        return rp, col[:nnz.value]
+
+    def assemble_csr(self, p, row_ptr, col, val, b=None, f_gauss=None, stream=None):
+        _check(_lib().fpde_assemble_csr(self._h, ctypes.byref(p), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(b),
+                                        _ptr(f_gauss), _stream(stream)), "fpde_assemble_csr")
+
+    def csr_apply(self, row_ptr, col, val, x, y, stream=None):
+        _check(_lib().fpde_csr_apply(self._h, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
+                                     _stream(stream)), "fpde_csr_apply")
+
+    def cg_solve(self, p, b, u, csr=None, tol: float = 1e-10, max_iter: int = 0, stream=None):
+        """CG with the Jacobi preconditioner; csr = (row_ptr, col, val) or None
+        for the matrix-free operator.  Returns fpde_solve_info."""
+        out = fpde_solve_info()
+        rp, ci, va = csr if csr is not None else (None, None, None)
+        _check(_lib().fpde_cg_solve(self._h, ctypes.byref(p), _ptr(rp), _ptr(ci), _ptr(va), _ptr(b), _ptr(u),
+                                    float(tol), int(max_iter), ctypes.byref(out), _stream(stream)),
+               "fpde_cg_solve")
+        return out
 
     # the divergence-form problem of Sec. 3 -------------------------------
     def div_assemble(self, p, A, b=None, pq=None, f_gauss=None, stream=None):

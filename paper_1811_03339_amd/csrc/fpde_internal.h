@@ -117,6 +117,8 @@ struct fpde_mesh {
   int64_t red_n = 0;
   void *linv = nullptr;           // inverses of the factor's 64 x 64 diagonal blocks (+ transposes)
   size_t linv_bytes = 0;
+  double *cg = nullptr;           // conjugate-gradient vectors and partial sums
+  int64_t cg_n = 0;
   int *tsync = nullptr;           // triangular solves: per-block flags (2 nblk) and 2 tickets
   int tsync_n = 0;
   int tsync_epoch = 0;
@@ -173,6 +175,15 @@ void free_plan(Plan &P);
 int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s);
 void free_tubes(TubePlan &tp);
 int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s);
+// the same sums kept at the columns of a CSR pattern (FP64)
+int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const int64_t *row_ptr,
+                              const int32_t *col, double *val, hipStream_t s);
+// matrix-free y = K x and its scratch (assemble.hip)
+int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
+                  hipStream_t s);
+int apply_scratch(fpde_mesh *m, Plan *P, double **d);
+// load vector b for the Riesz problem (assemble.hip)
+int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_gauss, hipStream_t s);
 // patch boxes of the template (built once per mesh)
 int ensure_patch_boxes(fpde_mesh *m, hipStream_t s);
 

@@ -434,6 +434,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   if (m->linv) (void)hipFree(m->linv);
   dfree(m->tsync);
   dfree(m->pbox);
+  dfree(m->cg);
   delete m;
 }
 

@@ -437,36 +437,72 @@ struct GatherArgs {
   int chunk;
 };
 
-// A[p, :] = sum over the (tube, slot) places of node p of that slot's row of
-// the tube block, scattered through U_T; rows dealt XCD by XCD in contiguous
-// ranges (workgroups go round-robin to the 8 XCDs).
+// Row `row`, columns [c0, c0 + cw), of K into the LDS chunk racc: the sum
+// over the (tube, slot) places of the node of that slot's row of the tube
+// block, scattered through U_T (one wavefront per place).  Ends with the
+// chunk complete and visible to the whole workgroup.
+__device__ __forceinline__ void gather_row_chunk(const GatherArgs &a, int64_t row, int64_t c0, int64_t cw,
+                                                 double *racc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p0 = a.row_off[row], p1 = a.row_off[row + 1];
+  for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) racc[j] = 0.0;
+  __syncthreads();
+  for (int64_t p = p0 + wave; p < p1; p += 4) {
+    const int2 ts = a.row_ts[p];
+    const int64_t u0 = a.u_off[ts.x], U = a.u_off[ts.x + 1] - u0;
+    const double *brow = a.blk + a.blk_off[ts.x] + (int64_t)ts.y * U;
+    for (int64_t t = lane; t < U; t += 64) {
+      const int64_t d = (int64_t)a.tube_u[u0 + t] - c0;
+      const double v = brow[t];
+      if ((uint64_t)d < (uint64_t)cw) atomicAdd(&racc[d], v);
+    }
+  }
+  __syncthreads();
+}
+
+// row of the dealt slot b: rows dealt XCD by XCD in contiguous ranges
+// (workgroups go round-robin to the 8 XCDs)
+__device__ __forceinline__ int64_t dealt_row(int64_t b, int64_t ndof) {
+  const int64_t per_xcd = (ndof + 7) / 8;
+  return (b % 8) * per_xcd + b / 8;
+}
+
+// A[p, :] = row p of K, written densely, once.
 template <class TO>
 __global__ void __launch_bounds__(256) k_tube_gather(GatherArgs a, TO *__restrict__ A) {
   extern __shared__ double racc[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t per_xcd = (a.ndof + 7) / 8;
-  const int64_t slots = 8 * per_xcd;
+  const int64_t slots = 8 * ((a.ndof + 7) / 8);
   for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
-    const int64_t row = (b % 8) * per_xcd + b / 8;
+    const int64_t row = dealt_row(b, a.ndof);
     if (row >= a.ndof) continue;
-    const int64_t p0 = a.row_off[row], p1 = a.row_off[row + 1];
     for (int64_t c0 = 0; c0 < a.ndof; c0 += a.chunk) {
       const int64_t cw = (a.ndof - c0) < a.chunk ? (a.ndof - c0) : a.chunk;
-      for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) racc[j] = 0.0;
-      __syncthreads();
-      for (int64_t p = p0 + wave; p < p1; p += 4) {
-        const int2 ts = a.row_ts[p];
-        const int64_t u0 = a.u_off[ts.x], U = a.u_off[ts.x + 1] - u0;
-        const double *brow = a.blk + a.blk_off[ts.x] + (int64_t)ts.y * U;
-        for (int64_t t = lane; t < U; t += 64) {
-          const int64_t d = (int64_t)a.tube_u[u0 + t] - c0;
-          const double v = brow[t];
-          if ((uint64_t)d < (uint64_t)cw) atomicAdd(&racc[d], v);
-        }
-      }
-      __syncthreads();
+      gather_row_chunk(a, row, c0, cw, racc);
       TO *out = A + row * a.lda + c0;
       for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) out[j] = (TO)racc[j];
+      __syncthreads();
+    }
+  }
+}
+
+// The same rows, kept only at the columns of a CSR pattern (sorted columns
+// per row): val[q] = K[row, col[q]] for q in [row_ptr[row], row_ptr[row+1]).
+__global__ void __launch_bounds__(256) k_tube_gather_csr(GatherArgs a, const int64_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         double *__restrict__ val) {
+  extern __shared__ double racc[];
+  const int64_t slots = 8 * ((a.ndof + 7) / 8);
+  for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
+    const int64_t row = dealt_row(b, a.ndof);
+    if (row >= a.ndof) continue;
+    const int64_t q0 = row_ptr[row], q1 = row_ptr[row + 1];
+    for (int64_t c0 = 0; c0 < a.ndof; c0 += a.chunk) {
+      const int64_t cw = (a.ndof - c0) < a.chunk ? (a.ndof - c0) : a.chunk;
+      gather_row_chunk(a, row, c0, cw, racc);
+      for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        const int64_t d = (int64_t)col[q] - c0;
+        if ((uint64_t)d < (uint64_t)cw) val[q] = racc[d];
+      }
       __syncthreads();
     }
   }
@@ -633,9 +669,9 @@ int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s) {
 #undef HIP_T
 }
 
-int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
+// Pass 1 (the tube blocks) for order p->alpha and coefficients p->K.
+static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, hipStream_t s) {
   TubePlan &tp = P.tubes;
-  if (m->ndof == 0) return FPDE_OK;
   if (!tp.blk) {
     FPDE_TRY(dalloc(&tp.blk, tp.blk_n > 0 ? tp.blk_n : 1));
   }
@@ -652,6 +688,15 @@ int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, 
   a.KC0 = p->K[0] * o.c_alpha;
   a.KC1 = p->K[1] * o.c_alpha;
   a.KC2 = p->K[2] * o.c_alpha;
+  const long ta = timer_begin(m, s);
+  if (tp.n_items > 0)
+    k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
+  timer_end(m, FPDE_STAGE_ACCUM, ta, s);
+  return FPDE_OK;
+}
+
+static GatherArgs gather_args(fpde_mesh *m, Plan &P, int64_t lda) {
+  TubePlan &tp = P.tubes;
   GatherArgs gch{};
   gch.row_off = tp.row_off;
   gch.row_ts = tp.row_ts;
@@ -662,17 +707,36 @@ int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, 
   gch.ndof = m->ndof;
   gch.lda = lda;
   gch.chunk = (int)(m->ndof < 8192 ? m->ndof : 8192);
-  const int64_t slots = 8 * ((m->ndof + 7) / 8);
-  const unsigned grid = (unsigned)(slots < 65536 ? slots : 65536);
+  return gch;
+}
+
+static unsigned gather_grid(int64_t ndof) {
+  const int64_t slots = 8 * ((ndof + 7) / 8);
+  return (unsigned)(slots < 65536 ? slots : 65536);
+}
+
+int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
+  if (m->ndof == 0) return FPDE_OK;
   const long t = timer_begin(m, s);
-  const long ta = timer_begin(m, s);
-  if (tp.n_items > 0)
-    k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
-  timer_end(m, FPDE_STAGE_ACCUM, ta, s);
+  FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
+  GatherArgs gch = gather_args(m, P, lda);
+  const unsigned grid = gather_grid(m->ndof);
   if (p->precision == FPDE_MIXED)
     k_tube_gather<float><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (float *)A);
   else
     k_tube_gather<double><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (double *)A);
+  timer_end(m, FPDE_STAGE_CONTRACT, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const int64_t *row_ptr,
+                              const int32_t *col, double *val, hipStream_t s) {
+  if (m->ndof == 0) return FPDE_OK;
+  const long t = timer_begin(m, s);
+  FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
+  GatherArgs gch = gather_args(m, P, 0);
+  k_tube_gather_csr<<<gather_grid(m->ndof), 256, sizeof(double) * gch.chunk, s>>>(gch, row_ptr, col, val);
   timer_end(m, FPDE_STAGE_CONTRACT, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
