@@ -16,8 +16,9 @@ value = Gauss-point paths per second over the timed steps (6 half-rays per
 Gauss point, summed over the six passes, divided by the step time).
 The single JSON line on stdout also carries the per-stage times, the
 roofline of the dominant kernel (measured with HIP events inside the library
-on the launch stream), the mixed-precision arm, the divergence-form problem
-of Sec. 3 on the finest mesh of Table 3 (assembly + LU + solve, with the LU
+on the launch stream), the mixed-precision arm, K on the template of Sec. 2.3
+as CSR with conjugate gradients (CSR and matrix-free), the divergence-form
+problem of Sec. 3 on the finest mesh of Table 3 (assembly + LU + solve, with the LU
 against its FP64 roofline) and the CPU oracle baseline.
 """
 from __future__ import annotations
@@ -157,6 +158,52 @@ def bench_sec3(F, torch, dev, reps=4):
     return out
 
 
+def bench_sparse(F, torch, gm, reps=3):
+    """K on the template of Sec. 2.3 as CSR, on the bench mesh: the pattern
+    (once per mesh), the CSR assembly, the CSR product against its HBM
+    roofline, and conjugate gradients on the CSR matrix and matrix-free,
+    compared with the dense FP64 Cholesky solution."""
+    n = gm.n_dof
+    p = F.params(1.5, KCOEF, quad_points=4)
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), r
+
+    t_tpl, (rp, col) = timed(lambda: gm.template_csr())
+    nnz = col.numel()
+    val = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    t_asm = sorted(timed(lambda: gm.assemble_csr(p, rp, col, val, b))[0] for _ in range(reps))[reps // 2]
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    gm.csr_apply(rp, col, val, x, y)
+    k = 50
+    t_mv = timed(lambda: [gm.csr_apply(rp, col, val, x, y) for _ in range(k)])[0] / k
+    by = nnz * 12.0 + (n + 1) * 8.0 + 2.0 * n * 8.0
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ud = torch.empty_like(b)
+    gm.assemble(p, A, b)
+    gm.solve(p, A, b, ud, info=False)
+    del A
+    out = {"workload": f"{WORKLOAD}, alpha = 1.5, 4-point rule", "template_ms": t_tpl, "nnz": nnz,
+           "density": nnz / float(n * n), "csr_bytes": nnz * 12 + (n + 1) * 8, "dense_bytes": n * n * 8,
+           "csr_assembly_ms": t_asm,
+           "spmv": {"ms": t_mv, "bound": "hbm", "algorithmic_bytes": by, "achieved": by / (t_mv / 1e3) / 1e9,
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": by / (t_mv / 1e3) / HBM_PEAK}}
+    for name, csr in (("cg_csr", (rp, col, val)), ("cg_matrix_free", None)):
+        u = torch.empty_like(b)
+        t, info = timed(lambda: gm.cg_solve(p, b, u, csr=csr, tol=1e-10))
+        out[name] = {"ms": t, "iterations": info.ir_iters, "rel_residual": info.final_rel_residual,
+                     "rel_diff_vs_cholesky": float((u - ud).abs().max() / ud.abs().max())}
+    return out
+
+
 def cpu_baseline(mesh_np):
     """The oracle, unchanged, single-threaded, on one full step."""
     from threadpoolctl import threadpool_limits
@@ -186,6 +233,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision arm")
     ap.add_argument("--no-sec3", action="store_true", help="skip the Sec. 3 divergence-form problem")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the template-CSR / CG section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -338,6 +386,11 @@ def main():
                  "final_rel_residual": inf.final_rel_residual}
         log(f"[bench] mixed {mixed}")
 
+    sparse = None
+    if not args.no_sparse:
+        sparse = bench_sparse(F, torch, gm)
+        log(f"[bench] sparse {sparse}")
+
     sec3 = None
     if not args.no_sec3:
         sec3 = bench_sec3(F, torch, dev)
@@ -389,6 +442,7 @@ def main():
         "roofline": roofline,
         "stage_rooflines": stage_roof,
         "mixed": mixed,
+        "sparse": sparse,
         "sec3": sec3,
         "cpu_baseline": cpu,
     }

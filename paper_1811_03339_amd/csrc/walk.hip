@@ -48,7 +48,8 @@ struct WalkArgs {
   int cap;         // max elements per half-ray
   int nq;
   const double *qbary;  // device: nq x 4 barycentric coordinates of the rule
-  double e, inv_g2, half_psi0;  // 1 - gamma, 1/Gamma(2-gamma), psi(2-gamma)/2
+  // per axis: 1 - gamma_i, 1/Gamma(2 - gamma_i); psi(2 - gamma)/2 (one order)
+  double e[3], inv_g2[3], half_psi0;
   // W_COUNT
   int32_t *cnt;    // n: entries per half-ray
   int32_t *len;    // n or null: elements per path
@@ -239,12 +240,14 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
         }
       }
       if (MODE == W_VALUES || MODE == W_ADJ) {
-        const double P_hi = powr(o.r_max, a.e);
-        double dP = a.inv_g2 * (P_hi - P_lo);
+        const double ei = i == 0 ? a.e[0] : (i == 1 ? a.e[1] : a.e[2]);
+        const double gi = i == 0 ? a.inv_g2[0] : (i == 1 ? a.inv_g2[1] : a.inv_g2[2]);
+        const double P_hi = powr(o.r_max, ei);
+        double dP = gi * (P_hi - P_lo);
         double dQ = 0.0;
         if (MODE == W_ADJ) {
-          const double Q_hi = lnpowr(o.r_max, a.e);
-          dQ = a.inv_g2 * (a.half_psi0 * (P_hi - P_lo) - 0.5 * (Q_hi - Q_lo));
+          const double Q_hi = lnpowr(o.r_max, ei);
+          dQ = gi * (a.half_psi0 * (P_hi - P_lo) - 0.5 * (Q_hi - Q_lo));
           Q_lo = Q_hi;
         }
         P_lo = P_hi;
@@ -530,31 +533,38 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out) {
   return FPDE_OK;
 }
 
-// Fills the plan's entry values (walk + closed-form eval), one launch per
-// axis whose order changed: the half-rays along e_i are dir = 2i, 2i + 1,
-// i.e. the contiguous range [2 i G, (2 i + 2) G).
+// Fills the plan's entry values (walk + closed-form eval) for the axes whose
+// order changed, in one launch over the contiguous range of half-rays that
+// covers them (the half-rays along e_i are dir = 2i, 2i + 1, i.e.
+// [2 i G, (2 i + 2) G)); each thread takes its axis's order.
 int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s) {
+  int i0 = 3, i1 = -1;
+  for (int i = 0; i < 3; i++)
+    if (P->val_gamma[i] != gamma[i]) {
+      i0 = i < i0 ? i : i0;
+      i1 = i;
+    }
+  if (i1 < 0) return FPDE_OK;
   QuadRule rule;
   FPDE_TRY(quad_rule(P->nq, &rule));
-  const long t = timer_begin(m, s);
+  WalkArgs a = base_args(m, *P, rule);
   for (int i = 0; i < 3; i++) {
-    if (P->val_gamma[i] == gamma[i]) continue;
-    Order o = gamma_scalars(gamma[i]);
-    WalkArgs a = base_args(m, *P, rule);
-    a.h0 = (int64_t)(2 * i) * P->G;
-    a.n = 2 * P->G;
-    a.e = o.e;
-    a.inv_g2 = o.inv_g2;
-    a.off = P->off;
-    a.ent_val = P->ent_val;
-    launch_walk<W_VALUES>(a, s);
-    P->val_gamma[i] = gamma[i];
+    const Order o = gamma_scalars(gamma[i]);
+    a.e[i] = o.e;
+    a.inv_g2[i] = o.inv_g2;
   }
+  a.h0 = (int64_t)(2 * i0) * P->G;
+  a.n = (int64_t)(2 * (i1 - i0 + 1)) * P->G;
+  a.off = P->off;
+  a.ent_val = P->ent_val;
+  const long t = timer_begin(m, s);
+  launch_walk<W_VALUES>(a, s);
   timer_end(m, FPDE_STAGE_WALK, t, s);
   if (hipGetLastError() != hipSuccess) {
     invalidate_values(P);
     return FPDE_EHIP;
   }
+  for (int i = i0; i <= i1; i++) P->val_gamma[i] = gamma[i];
   return FPDE_OK;
 }
 
@@ -573,8 +583,10 @@ int walk_adjoint(fpde_mesh *m, Plan *P, double alpha, const double *u, const dou
   WalkArgs a = base_args(m, *P, rule);
   a.h0 = 0;
   a.n = P->n_half;
-  a.e = o.e;
-  a.inv_g2 = o.inv_g2;
+  for (int i = 0; i < 3; i++) {
+    a.e[i] = o.e;
+    a.inv_g2[i] = o.inv_g2;
+  }
   a.half_psi0 = o.half_psi0;
   a.u = u;
   a.lam = lam;

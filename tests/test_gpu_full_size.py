@@ -3,7 +3,9 @@
 * sphere150k (~152k elements, ~25k unknowns, 11-point rule, alpha = 1.7):
   sampled paths bit-exact, sampled derivative vectors, K x against the
   oracle's matrix-free product, FP64 and mixed solutions (mixed within 1e-6
-  of FP64 after refinement to 1e-8).
+  of FP64 after refinement to 1e-8); K on the template as CSR (its product
+  equal to the matrix-free one), CG on it and matrix-free within 1e-7 of
+  the FP64 Cholesky solution.
 * ball40k (~42k elements, ~6.6k unknowns, 4-point rule): adjoint gradients of
   ||u - u_obs||^2 at alpha = 1.4, K = (1,1,1) against the oracle's adjoint and
   central differences (h = 1e-6); u_obs from alpha = 1.6, K = (1.2, 0.8, 1.0)
@@ -11,7 +13,8 @@
 * ellipsoid400k (~400k elements, ~67k unknowns, 11-point rule,
   alpha = 1.3): mixed precision with an FP32 matrix of ~18 GB; sampled paths
   and derivative vectors against the oracle, K x (FP32, dense) against the
-  FP64 matrix-free product, refinement to 1e-8.
+  FP64 matrix-free product, refinement to 1e-8; the same system by
+  matrix-free CG (no dense matrix) within 1e-6 of the refined solution.
 * ball_h076 (the finest mesh of Table 3, ~8.2k unknowns), the divergence-form
   problem of Sec. 3 at beta = (0.6, 0.7, 0.8): the whole matrix, the load
   vector and the LU solution against the oracle (LAPACK LU).
@@ -107,7 +110,29 @@ def test_sphere150k_fp64_and_mixed():
     assert err <= 1e-6
     log(f"[sphere150k] mixed assemble {t_asm32:.3f}s solve {t_sol32:.3f}s ir_iters {info32.ir_iters} "
         f"rel err vs FP64 {err:.2e} speedup {(t_asm + t_sol) / (t_asm32 + t_sol32):.2f}x")
-    del A32, gm
+    del A32
+    gc.collect()
+    torch.cuda.empty_cache()
+    # sparse storage on the template and CG, against the dense FP64 solution
+    (rp, col), t_tpl = timed(lambda: gm.template_csr())
+    val = torch.empty(col.numel(), dtype=torch.float64, device="cuda")
+    _, t_csr = timed(lambda: gm.assemble_csr(p64, rp, col, val, b))
+    xs = torch.tensor(rng.normal(size=n), device="cuda")
+    ys = torch.empty_like(xs)
+    gm.csr_apply(rp, col, val, xs, ys)
+    ym = torch.empty_like(xs)
+    gm.apply(p64, xs, ym)
+    assert float((ys - ym).abs().max() / ym.abs().max()) <= 1e-10
+    for csr in ((rp, col, val), None):
+        ucg = torch.empty_like(b)
+        infocg, t_cg = timed(lambda: gm.cg_solve(p64, b, ucg, csr=csr, tol=1e-10))
+        err = float((ucg - u64).abs().max() / u64.abs().max())
+        assert infocg.final_rel_residual <= 1e-9 and err <= 1e-7
+        log(f"[sphere150k] CG ({'CSR' if csr else 'matrix-free'}) {t_cg:.3f}s, {infocg.ir_iters} iterations, "
+            f"{err:.1e} from FP64 Cholesky")
+    log(f"[sphere150k] template CSR {t_tpl:.3f}s nnz {col.numel()} ({col.numel() / n / n:.3f} of N^2, "
+        f"{col.numel() * 12 / 2**30:.2f} GiB), CSR assembly {t_csr:.3f}s")
+    del gm
     gc.collect()
     torch.cuda.empty_cache()
 
@@ -187,7 +212,19 @@ def test_ellipsoid400k_mixed():
         f"solve {t_sol:.2f}s, ir_iters {info32.ir_iters}, residual {info32.final_rel_residual:.2e}")
     stages = {k: round(v[0], 1) for k, v in gm.stage_times().items() if v[1]}
     log(f"[ellipsoid400k] stage ms {stages}")
-    del A32, gm
+    del A32
+    gc.collect()
+    torch.cuda.empty_cache()
+    # the same system by matrix-free CG: no N^2 storage at all
+    p64 = F.params(alpha, K, quad_points=nq)
+    ucg = torch.empty_like(b)
+    infocg, t_cg = timed(lambda: gm.cg_solve(p64, b, ucg, tol=1e-10))
+    assert infocg.final_rel_residual <= 1e-9
+    err = float((ucg - u).abs().max() / u.abs().max())
+    assert err <= 1e-6
+    log(f"[ellipsoid400k] matrix-free CG {t_cg:.2f}s, {infocg.ir_iters} iterations, residual "
+        f"{infocg.final_rel_residual:.2e}, {err:.1e} from the refined dense solution")
+    del gm
     gc.collect()
     torch.cuda.empty_cache()
 
