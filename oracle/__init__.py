@@ -83,6 +83,7 @@ def _load():
     L.orc_assemble.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P]
     L.orc_assemble_div.argtypes = [P, i32, P, P, P, i32, P]
     L.orc_assemble_div_rows.argtypes = [P, i32, P, P, P, i32, i64, P, P]
+    L.orc_assemble_form.argtypes = [P, i32, P, P, P, P, P, i32, P]
     L.orc_apply.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, P]
     L.orc_adjoint_sums.argtypes = [P, i32, dbl, dbl, dbl, i32, P, P, P, P]
     L.orc_load.argtypes = [P, i32, P, P]
@@ -321,6 +322,30 @@ class OracleMesh:
                                             _p(rows), _p(A))
         if st != 0:
             raise OracleError(st, "assemble_div")
+        return A
+
+    def assemble_form(self, nq: int, alpha, beta, coef) -> np.ndarray:
+        """The uniform form of Sec. 1 (eq. equ:varsss), test operator on the
+        side opposite to the trial one:
+        K_kl = sum_i sum_g w_g [cl_i D_L^{alpha_i} psi_l D_R^{beta_i} psi_k
+                                + cr_i D_R^{alpha_i} psi_l D_L^{beta_i} psi_k](x_g),
+        orders in [0, 1] per axis; coef: (6, G) with cl_i in rows 0..2 and
+        cr_i in rows 3..5, or 6 constants."""
+        G = self.n_tet * nq
+        coef = np.asarray(coef, dtype=np.float64)
+        if coef.shape == (6,):
+            coef = np.repeat(coef[:, None], G, axis=1)
+        coef = np.ascontiguousarray(coef)
+        if coef.shape != (6, G):
+            raise ValueError("coef must be (6,) or (6, G)")
+        ga = np.ascontiguousarray(alpha, dtype=np.float64)
+        gb = np.ascontiguousarray(beta, dtype=np.float64)
+        iga = np.array([rgamma_(2.0 - a) for a in ga])
+        igb = np.array([rgamma_(2.0 - b) for b in gb])
+        A = np.zeros((self.ndof, self.ndof))
+        st = _lib.orc_assemble_form(self._h, nq, _p(ga), _p(iga), _p(gb), _p(igb), _p(coef), self.cap, _p(A))
+        if st != 0:
+            raise OracleError(st, "assemble_form")
         return A
 
     def apply(self, nq: int, alpha: float, K, x) -> np.ndarray:

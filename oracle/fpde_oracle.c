@@ -31,7 +31,10 @@
  *   - the non-symmetric matrix of the divergence-form two-sided problem of
  *     Sec. 3 (eq. equ:sfde2): order-beta_i trial derivatives along e_i with
  *     variable coefficients p_i, q_i, against the classical derivative of the
- *     test function on the Gauss point's own element.
+ *     test function on the Gauss point's own element;
+ *   - the general uniform form (c D^alpha u, D^beta v) of Sec. 1 with the
+ *     test operator on the opposite side, per-axis orders in [0, 1] and a
+ *     coefficient per side.
  *
  * Readings where the paper is silent (each one is stated where it is used):
  *   - zero component of a volume coordinate: |k| <= 1e-12 max(1, |b~|, |r d~|),
@@ -719,6 +722,60 @@ int orc_assemble_div_rows(const orc_mesh *m, int nq, const double *gamma, const 
   }
   int st = orc_div_sums(m, nq, gamma, inv_g2, pq, cap, slot, A);
   free(slot);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The uniform form of Sec. 1 (eq. equ:varsss) with its element quadrature  */
+/* (Sec. 2.1, (K_E)_kl): per axis i a trial order alpha_i and a test order  */
+/* beta_i in [0, 1], the test operator on the side opposite to the trial     */
+/* one, and a coefficient per side:                                          */
+/*   K_kl = sum_i sum_g w_g [cl_i(x_g) D_L^{a_i} psi_l(x_g) D_R^{b_i} psi_k(x_g) */
+/*                         + cr_i(x_g) D_R^{a_i} psi_l(x_g) D_L^{b_i} psi_k(x_g)] */
+/* (row k = test function).  coef holds cl_i(x_g) at [i G + g] and cr_i(x_g) */
+/* at [(3 + i) G + g].  A is ndof x ndof row-major, zeroed by the caller.    */
+/* ------------------------------------------------------------------------ */
+int orc_assemble_form(const orc_mesh *m, int nq, const double *ga /* 3 */, const double *iga /* 3 */,
+                      const double *gb /* 3 */, const double *igb /* 3 */, const double *coef, int cap,
+                      double *A) {
+  double bary[44], wq[11];
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  orc_order oa[3], ob[3];
+  for (int i = 0; i < 3; i++) {
+    orc_fill_order(&oa[i], ga[i], iga[i], 0.0, 0.0);
+    orc_fill_order(&ob[i], gb[i], igb[i], 0.0, 0.0);
+  }
+  orc_work *w = orc_work_new(m->nv);
+  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+  double *rb = (double *)malloc(sizeof(double) * cap);
+  int32_t *id[4];
+  double *v[4];
+  for (int k = 0; k < 4; k++) {
+    id[k] = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+    v[k] = (double *)malloc(sizeof(double) * 4 * cap);
+  }
+  int64_t n = m->ndof, G = m->nt * nq;
+  int st = ORC_OK;
+  for (int64_t g = 0; g < G && st == ORC_OK; g++) {
+    double wg = wq[g % nq] * m->vol[g / nq];
+    for (int i = 0; i < 3; i++) {
+      /* 0: D_L^a, 1: D_R^a (trial); 2: D_L^b, 3: D_R^b (test) */
+      int cnt[4];
+      for (int k = 0; k < 4; k++) {
+        cnt[k] = orc_ray_vector(m, nq, bary, g, i, k & 1, k < 2 ? &oa[i] : &ob[i], 0, cap, w, id[k], v[k], tb, rb);
+        if (cnt[k] < 0) { st = cnt[k]; break; }
+      }
+      if (st != ORC_OK) break;
+      double cl = coef[(int64_t)i * G + g], cr = coef[(int64_t)(3 + i) * G + g];
+      for (int a = 0; a < cnt[3]; a++)
+        for (int b = 0; b < cnt[0]; b++) A[id[3][a] * n + id[0][b]] += (wg * cl) * (v[3][a] * v[0][b]);
+      for (int a = 0; a < cnt[2]; a++)
+        for (int b = 0; b < cnt[1]; b++) A[id[2][a] * n + id[1][b]] += (wg * cr) * (v[2][a] * v[1][b]);
+    }
+  }
+  free(tb); free(rb);
+  for (int k = 0; k < 4; k++) { free(id[k]); free(v[k]); }
+  orc_work_free(w);
   return st;
 }
 
