@@ -235,7 +235,8 @@ enum {
   FPDE_STAGE_DIV = 10,  /* accumulation of the Sec. 3 matrix */
   FPDE_STAGE_SPMV = 11, /* CSR products (fpde_csr_apply and inside fpde_cg_solve) */
   FPDE_STAGE_CG = 12,   /* a whole conjugate-gradient solve */
-  FPDE_NSTAGES = 13
+  FPDE_STAGE_FORM = 13, /* accumulation of a general uniform form (fpde_form_assemble) */
+  FPDE_NSTAGES = 14
 };
 int fpde_timing(fpde_mesh *m, int enable);
 int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
@@ -329,7 +330,7 @@ int fpde_cg_solve(fpde_mesh *m, const fpde_params *p, const int64_t *row_ptr, co
  * (the walk of Sec. 2.2) and d_i psi_j the slope of psi_j on the Gauss
  * point's own element.  K is not symmetric: row j is the test function.
  */
-enum { FPDE_COEF_SEC3 = 0, FPDE_COEF_USER = 1 };
+enum { FPDE_COEF_SEC3 = 0, FPDE_COEF_USER = 1, FPDE_COEF_CONST = 2 };
 
 typedef struct {
   double beta[3];   /* orders beta_1..beta_3, each in (0, 1] */
@@ -379,6 +380,43 @@ int fpde_lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t *failed_pivot, 
  * Synchronises `stream`.  Errors: FPDE_EINVAL, FPDE_ENOMEM, FPDE_EHIP.
  */
 int fpde_lu_solve(fpde_mesh *m, const double *LU, int64_t lda, const double *b, double *u, void *stream);
+
+/*
+ * ---- The general uniform form of Sec. 1 (eq. equ:varsss) ----
+ *
+ *   K_kl = sum_i sum_g w_g [cl_i(x_g) D_L^{alpha_i} psi_l(x_g) D_R^{beta_i} psi_k(x_g)
+ *                         + cr_i(x_g) D_R^{alpha_i} psi_l(x_g) D_L^{beta_i} psi_k(x_g)]
+ *
+ * (c D^alpha u, D^beta v) with the test operator on the side opposite to the
+ * trial one, per axis, with the element quadrature of Sec. 2.1; row k is the
+ * test function.  Orders in [0, 1]: 0 is the identity, 1 the classical
+ * derivative (D_L^1 = d/dx_i, D_R^1 = -d/dx_i), so the three operator forms
+ * of Sec. 1 and the problems of fpde_assemble (alpha_i = beta_i = alpha/2,
+ * cl = cr = K_i c_alpha) and fpde_div_assemble (beta_i = 1, cl = p_i,
+ * cr = q_i) are instances.
+ */
+typedef struct {
+  double alpha[3];  /* trial orders, each in [0, 1] */
+  double beta[3];   /* test orders, each in [0, 1] */
+  int quad_points;  /* 4 or 11 */
+  int coef;         /* FPDE_COEF_CONST: cl, cr below; FPDE_COEF_USER: at the Gauss points */
+  double cl[3];     /* FPDE_COEF_CONST: coefficient of the (D_L^alpha u, D_R^beta v) term per axis */
+  double cr[3];     /* FPDE_COEF_CONST: coefficient of the (D_R^alpha u, D_L^beta v) term per axis */
+  int max_steps;    /* cap on elements per half-ray, 0 = 4096 */
+} fpde_form_params;
+
+/*
+ * Assembly of K (above) into A (dev, n_dof x lda FP64; the leading
+ * n_dof x n_dof block is written).  coef: dev, 6 G FP64 for
+ * FPDE_COEF_USER (cl_i(x_g) at [i G + g], cr_i(x_g) at [(3 + i) G + g],
+ * g = element * quad_points + q), else ignored.  Every half-ray is evaluated
+ * at the trial and at the test orders (two value sets in the plan, each
+ * recomputed only for the axes whose order changed).  Synchronises `stream`.
+ * Errors: FPDE_EINVAL, FPDE_EALPHA (an order outside [0, 1]), FPDE_EPATH,
+ * FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_form_assemble(fpde_mesh *m, const fpde_form_params *p, const double *coef, double *A, int64_t lda,
+                       void *stream);
 
 #ifdef __cplusplus
 }

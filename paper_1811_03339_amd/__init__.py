@@ -22,7 +22,7 @@ LIB_PATH = _HERE / "libfpde.so"
 FPDE_OK = 0
 FPDE_FP64, FPDE_MIXED = 0, 1
 FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS, FPDE_SRC_BALL_MMS = 0, 1, 2, 3
-FPDE_COEF_SEC3, FPDE_COEF_USER = 0, 1
+FPDE_COEF_SEC3, FPDE_COEF_USER, FPDE_COEF_CONST = 0, 1, 2
 
 STATUS = {
     0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EMESH_NONMANIFOLD", -3: "FPDE_EMESH_DEGENERATE",
@@ -35,11 +35,11 @@ EXPORTS = [
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
     "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
     "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve", "fpde_template_csr",
-    "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve",
+    "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble",
 ]
 
 STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div", "spmv",
-          "cg"]
+          "cg", "form"]
 
 
 class FpdeError(RuntimeError):
@@ -63,6 +63,12 @@ class fpde_params(ctypes.Structure):
 class fpde_div_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double * 3), ("quad_points", ctypes.c_int), ("coef", ctypes.c_int),
                 ("source", ctypes.c_int), ("radius", ctypes.c_double), ("max_steps", ctypes.c_int)]
+
+
+class fpde_form_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double * 3), ("beta", ctypes.c_double * 3), ("quad_points", ctypes.c_int),
+                ("coef", ctypes.c_int), ("cl", ctypes.c_double * 3), ("cr", ctypes.c_double * 3),
+                ("max_steps", ctypes.c_int)]
 
 
 class fpde_solve_info(ctypes.Structure):
@@ -107,6 +113,7 @@ def _lib():
     L.fpde_assemble_csr.argtypes = [P, P, P, P, P, P, P, P]
     L.fpde_csr_apply.argtypes = [P, P, P, P, P, P, P]
     L.fpde_cg_solve.argtypes = [P, P, P, P, P, P, P, dbl, i32, P, P]
+    L.fpde_form_assemble.argtypes = [P, P, P, P, i64, P]
     for name in EXPORTS:
         getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
             None if name == "fpde_mesh_destroy" else ctypes.c_int)
@@ -161,6 +168,21 @@ def div_params(beta, quad_points: int = 4, coef: int = FPDE_COEF_SEC3, source: i
     p.coef = int(coef)
     p.source = int(source)
     p.radius = float(radius)
+    p.max_steps = int(max_steps)
+    return p
+
+
+def form_params(alpha, beta, cl=(1.0, 1.0, 1.0), cr=(1.0, 1.0, 1.0), quad_points: int = 4,
+                coef: int = FPDE_COEF_CONST, max_steps: int = 0):
+    """Parameters of the general uniform form (c D^alpha u, D^beta v)."""
+    p = fpde_form_params()
+    for i in range(3):
+        p.alpha[i] = float(alpha[i])
+        p.beta[i] = float(beta[i])
+        p.cl[i] = float(cl[i])
+        p.cr[i] = float(cr[i])
+    p.quad_points = int(quad_points)
+    p.coef = int(coef)
     p.max_steps = int(max_steps)
     return p
 
@@ -304,6 +326,11 @@ class Mesh:
                "fpde_cg_solve")
         return out
 
+    # the general uniform form --------------------------------------------
+    def form_assemble(self, p, A, coef=None, stream=None):
+        _check(_lib().fpde_form_assemble(self._h, ctypes.byref(p), _ptr(coef), _ptr(A), A.stride(0),
+                                         _stream(stream)), "fpde_form_assemble")
+
     # the divergence-form problem of Sec. 3 -------------------------------
     def div_assemble(self, p, A, b=None, pq=None, f_gauss=None, stream=None):
         _check(_lib().fpde_div_assemble(self._h, ctypes.byref(p), _ptr(pq), _ptr(A), A.stride(0), _ptr(b),
@@ -367,4 +394,4 @@ from .autograd import FracSolve  # noqa: E402
 __all__ = ["Mesh", "params", "div_params", "solve_problem", "solve_div_problem", "new_matrix", "FracSolve",
            "FpdeError", "fpde_params", "fpde_div_params", "fpde_solve_info", "FPDE_FP64", "FPDE_MIXED",
            "FPDE_SRC_ONE", "FPDE_SRC_USER", "FPDE_SRC_CUBE_MMS", "FPDE_SRC_BALL_MMS", "FPDE_COEF_SEC3",
-           "FPDE_COEF_USER", "EXPORTS", "LIB_PATH"]
+           "FPDE_COEF_USER", "FPDE_COEF_CONST", "form_params", "fpde_form_params", "EXPORTS", "LIB_PATH"]

@@ -68,6 +68,8 @@ struct Plan {
   int32_t *ent_ray = nullptr; // n_ent: owning half-ray
   double *ent_val = nullptr;  // n_ent: values, half-rays along e_i at order val_gamma[i]
   double val_gamma[3] = {-1.0, -1.0, -1.0};  // per axis; -1 = not computed
+  double *ent_val2 = nullptr;  // n_ent: a second set of values (allocated on first use)
+  double val_gamma2[3] = {-1.0, -1.0, -1.0};
   int64_t *row_off = nullptr; // n_dof + 1
   int64_t *inc = nullptr;     // n_ent: entry ids grouped by their dof
   // per incidence (row order): {entry id, partner offset, partner length << 2 | axis,
@@ -166,9 +168,12 @@ int take_flag(fpde_mesh *m, hipStream_t s, int64_t *aux = nullptr);
 int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out);
 // entry values at order gamma = alpha/2 on every axis
 int ensure_values(fpde_mesh *m, Plan *P, double alpha, hipStream_t s);
-// entry values at order gamma[i] along e_i (recomputes only the axes that changed)
-int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s);
-inline void invalidate_values(Plan *P) { P->val_gamma[0] = P->val_gamma[1] = P->val_gamma[2] = -1.0; }
+// entry values at order gamma[i] along e_i (recomputes only the axes that
+// changed); slot 0 = ent_val, slot 1 = ent_val2
+int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s, int slot = 0);
+inline void invalidate_values(Plan *P) {
+  for (int i = 0; i < 3; i++) P->val_gamma[i] = P->val_gamma2[i] = -1.0;
+}
 int check_params(const fpde_mesh *m, const fpde_params *p);
 void free_plan(Plan &P);
 // tube plan of a rule whose entries exist (cell edge = kappa x mean element edge)

@@ -414,7 +414,7 @@ static void launch_walk(const WalkArgs &a, hipStream_t s) {
 }
 
 void free_plan(Plan &P) {
-  dfree(P.off); dfree(P.ent_dof); dfree(P.ent_ray); dfree(P.ent_val); dfree(P.row_off); dfree(P.inc);
+  dfree(P.off); dfree(P.ent_dof); dfree(P.ent_ray); dfree(P.ent_val); dfree(P.ent_val2); dfree(P.row_off); dfree(P.inc);
   dfree(P.adj); dfree(P.inc_meta); dfree(P.inc_w);
   free_tubes(P.tubes);
   P = Plan();
@@ -537,10 +537,13 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out) {
 // order changed, in one launch over the contiguous range of half-rays that
 // covers them (the half-rays along e_i are dir = 2i, 2i + 1, i.e.
 // [2 i G, (2 i + 2) G)); each thread takes its axis's order.
-int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s) {
+int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t s, int slot) {
+  double *cache = slot == 0 ? P->val_gamma : P->val_gamma2;
+  if (slot == 1 && !P->ent_val2) FPDE_TRY(dalloc(&P->ent_val2, P->n_ent));
+  double *dest = slot == 0 ? P->ent_val : P->ent_val2;
   int i0 = 3, i1 = -1;
   for (int i = 0; i < 3; i++)
-    if (P->val_gamma[i] != gamma[i]) {
+    if (cache[i] != gamma[i]) {
       i0 = i < i0 ? i : i0;
       i1 = i;
     }
@@ -556,7 +559,7 @@ int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t
   a.h0 = (int64_t)(2 * i0) * P->G;
   a.n = (int64_t)(2 * (i1 - i0 + 1)) * P->G;
   a.off = P->off;
-  a.ent_val = P->ent_val;
+  a.ent_val = dest;
   const long t = timer_begin(m, s);
   launch_walk<W_VALUES>(a, s);
   timer_end(m, FPDE_STAGE_WALK, t, s);
@@ -564,7 +567,7 @@ int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t
     invalidate_values(P);
     return FPDE_EHIP;
   }
-  for (int i = i0; i <= i1; i++) P->val_gamma[i] = gamma[i];
+  for (int i = i0; i <= i1; i++) cache[i] = gamma[i];
   return FPDE_OK;
 }
 
