@@ -17,7 +17,8 @@ Gauss point, summed over the six passes, divided by the step time).
 The single JSON line on stdout also carries the per-stage times, the
 roofline of the dominant kernel (measured with HIP events inside the library
 on the launch stream), the mixed-precision arm, K on the template of Sec. 2.3
-as CSR with conjugate gradients (CSR and matrix-free), the divergence-form
+as CSR with conjugate gradients (CSR and matrix-free), the general uniform
+form (c D^alpha u, D^beta v) with per-axis orders, the divergence-form
 problem of Sec. 3 on the finest mesh of Table 3 (assembly + LU + solve, with the LU
 against its FP64 roofline) and the CPU oracle baseline.
 """
@@ -43,12 +44,12 @@ KCOEF = (1.0, 0.5, 2.0)
 HBM_PEAK = 8.0e12        # B/s
 FP64_PEAK = 78.6e12      # FLOP/s, vector and matrix
 CSRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc")
-# HBM counter summaries (profiles/): unit -> (file, source its kernels are built from)
+# HBM counter summaries (profiles/): unit -> (file, sources its kernels are built from)
 PMC = {
     "factorization": (os.path.join(ROOT, "profiles", "potrf_sphere20k_pmc.txt"),
-                      os.path.join(CSRC, "solve.hip")),
+                      [os.path.join(CSRC, "solve.hip"), os.path.join(CSRC, "dense.h")]),
     "k_tube_accum": (os.path.join(ROOT, "profiles", "tube_accum_sphere20k_pmc.txt"),
-                     os.path.join(CSRC, "tubes.hip")),
+                     [os.path.join(CSRC, "tubes.hip")]),
 }
 NB = 64  # panel width of the blocked Cholesky
 
@@ -57,8 +58,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def src_sha1(path):
-    return hashlib.sha1(open(path, "rb").read()).hexdigest()
+def src_sha1(paths):
+    h = hashlib.sha1()
+    for path in paths:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def read_traffic(kernel):
@@ -204,6 +208,45 @@ def bench_sparse(F, torch, gm, reps=3):
     return out
 
 
+FORM_ALPHA = (0.3, 0.8, 0.55)
+FORM_BETA = (0.9, 0.4, 0.7)
+
+
+def bench_form(F, torch, gm, info4, reps=3):
+    """The general uniform form (c D^alpha u, D^beta v) with per-axis orders
+    on the bench mesh (4-point rule): the non-symmetric row-gather assembly,
+    both value sets re-walked every pass (the orders alternate)."""
+    n = gm.n_dof
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    gm.timing(True)
+    ts = []
+    for k in range(reps):
+        a, b = (FORM_ALPHA, FORM_BETA) if k % 2 == 0 else (FORM_BETA, FORM_ALPHA)
+        p = F.form_params(a, b, (1.0, 0.5, 2.0), (0.7, 1.5, 0.3), 4)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gm.form_assemble(p, A)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    gm.timing(False)
+    st = gm.stage_times()
+    t_rows = st["form"][0] / max(st["form"][1], 1) / 1e3
+    ent, pairs = info4["entries"], info4["pairs"]
+    # algorithmic bytes: each entry's node and two values read once, K written once
+    alg = 16.0 * ent + 8.0 * n * n
+    # what the row gather reads: every incidence's partner vector (node + value)
+    gathered = 24.0 * pairs + 32.0 * ent + 8.0 * n * n
+    return {"workload": f"{WORKLOAD}, 4-point rule, alpha {list(FORM_ALPHA)}, beta {list(FORM_BETA)} "
+                        f"(alternating), constant coefficients",
+            "pass_ms": sorted(ts)[len(ts) // 2],
+            "stages_ms_per_pass": {k: v[0] / reps for k, v in st.items() if v[1] > 0},
+            "rows": {"bound": "hbm", "ms": t_rows * 1e3, "algorithmic_bytes": alg,
+                     "achieved": alg / t_rows / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": alg / t_rows / HBM_PEAK, "gathered_bytes": gathered}}
+
+
 def cpu_baseline(mesh_np):
     """The oracle, unchanged, single-threaded, on one full step."""
     from threadpoolctl import threadpool_limits
@@ -234,6 +277,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision arm")
     ap.add_argument("--no-sec3", action="store_true", help="skip the Sec. 3 divergence-form problem")
     ap.add_argument("--no-sparse", action="store_true", help="skip the template-CSR / CG section")
+    ap.add_argument("--no-form", action="store_true", help="skip the general-form section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -391,6 +435,11 @@ def main():
         sparse = bench_sparse(F, torch, gm)
         log(f"[bench] sparse {sparse}")
 
+    form = None
+    if not args.no_form:
+        form = bench_form(F, torch, gm, info[4])
+        log(f"[bench] form {form}")
+
     sec3 = None
     if not args.no_sec3:
         sec3 = bench_sec3(F, torch, dev)
@@ -443,6 +492,7 @@ def main():
         "stage_rooflines": stage_roof,
         "mixed": mixed,
         "sparse": sparse,
+        "form": form,
         "sec3": sec3,
         "cpu_baseline": cpu,
     }
