@@ -3,7 +3,9 @@
 Holds none of the method's arithmetic; see ``meshes`` for the generators.
 """
 from .meshes import (Mesh, kuhn_cube, hull_mesh, radius_ratio, workload_mesh,
-                     WORKLOADS, sphere_points, ellipsoid_points, morton_renumber)
+                     WORKLOADS, sphere_points, ellipsoid_points, morton_renumber,
+                     kuhn_square, polygon_mesh, circle_points, fibonacci_sphere)
 
 __all__ = ["Mesh", "kuhn_cube", "hull_mesh", "radius_ratio", "workload_mesh",
-           "WORKLOADS", "sphere_points", "ellipsoid_points", "morton_renumber"]
+           "WORKLOADS", "sphere_points", "ellipsoid_points", "morton_renumber",
+           "kuhn_square", "polygon_mesh", "circle_points", "fibonacci_sphere"]

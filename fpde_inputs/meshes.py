@@ -30,6 +30,7 @@ import numpy as np
 
 __all__ = [
     "Mesh", "kuhn_cube", "hull_mesh", "radius_ratio", "workload_mesh", "fibonacci_sphere",
+    "kuhn_square", "polygon_mesh", "circle_points",
     "WORKLOADS",
 ]
 
@@ -120,6 +121,63 @@ def kuhn_cube(n: int, lo: float = 0.0, hi: float = 1.0, morton: bool = False) ->
 # --------------------------------------------------------------------------
 # Quality measure (input statistics only)
 # --------------------------------------------------------------------------
+def kuhn_square(n: int, lo: float = 0.0, hi: float = 1.0) -> Mesh:
+    """The unit square cut into n x n sub-squares, each split into two
+    triangles along its (0,0)-(1,1) diagonal (a two-dimensional input: xyz
+    has two columns, tet holds triangles)."""
+    t = np.linspace(lo, hi, n + 1)
+    X, Y = np.meshgrid(t, t, indexing="ij")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    vid = lambda i, j: i * (n + 1) + j  # noqa: E731
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            tris.append((a, b, c))
+            tris.append((a, c, d))
+    return Mesh(xy, np.array(tris, dtype=np.int32), name=f"square{n}")
+
+
+def polygon_mesh(hull_points: np.ndarray, spacing: float, seed: int, jitter: float = 0.1,
+                 name: str = "polygon") -> Mesh:
+    """Delaunay triangulation of conv(hull_points) (2-D) with a jittered
+    triangular lattice of interior points kept at least half a spacing
+    inside every edge; vertices and triangles in Morton order of their
+    positions / centroids."""
+    from scipy.spatial import ConvexHull, Delaunay
+    rng = np.random.default_rng(seed)
+    h = ConvexHull(hull_points)
+    bpts = hull_points[h.vertices]
+    eq = h.equations
+    lo, hi = bpts.min(0), bpts.max(0)
+    xs = np.arange(lo[0], hi[0] + spacing, spacing)
+    ys = np.arange(lo[1], hi[1] + spacing, spacing * np.sqrt(3) / 2)
+    G = np.array([(x + (0.5 * spacing if k % 2 else 0.0), y) for k, y in enumerate(ys) for x in xs])
+    G = G + rng.uniform(-jitter * spacing, jitter * spacing, size=G.shape)
+    inside = (G @ eq[:, :2].T + eq[:, 2]).max(axis=1) <= -0.5 * spacing
+    P = np.concatenate([bpts, G[inside]])
+    tri = Delaunay(P).simplices.astype(np.int64)
+    p = P[tri]
+    area2 = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+    tri = tri[np.abs(area2) > 1e-12 * spacing ** 2]
+    keys = _morton_keys(np.concatenate([P, np.zeros((len(P), 1))], axis=1),
+                        np.append(lo, 0.0), np.append(hi, 1.0))
+    order = np.argsort(keys, kind="stable")
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    P = P[order]
+    tri = inv[tri]
+    c = P[tri].mean(axis=1)
+    tkeys = _morton_keys(np.concatenate([c, np.zeros((len(c), 1))], axis=1), np.append(lo, 0.0), np.append(hi, 1.0))
+    tri = tri[np.argsort(tkeys, kind="stable")]
+    return Mesh(P, tri.astype(np.int32), name=name)
+
+
+def circle_points(n: int, radius: float = 1.0) -> np.ndarray:
+    k = np.arange(n) * 2.0 * np.pi / n
+    return radius * np.stack([np.cos(k), np.sin(k)], axis=1)
+
+
 def radius_ratio(xyz: np.ndarray, tet: np.ndarray) -> np.ndarray:
     """rho = 3 r_in / R_circ per tetrahedron (1 for the regular one)."""
     p = xyz[tet]
@@ -270,6 +328,10 @@ WORKLOADS = {
     "ball_h139": dict(kind="ball", radius=0.5, n_surface=469, spacing=0.07152, seed=22),
     "ball_h089": dict(kind="ball", radius=0.5, n_surface=1215, spacing=0.04445, seed=23),
     "ball_h076": dict(kind="ball", radius=0.5, n_surface=1628, spacing=0.03840, seed=24),
+    # two dimensions: the unit disk as a 64-gon filled with a jittered
+    # triangular lattice (~4.5k nodes) and a small one for tests
+    "disk4k": dict(kind="disk", n_boundary=160, spacing=0.028, seed=31),
+    "disk_small": dict(kind="disk", n_boundary=24, spacing=0.2, seed=32),
     # small hull meshes for tests
     "sphere_tiny": dict(kind="sphere", n_surface=40, spacing=0.45, seed=11),
     "sphere_small": dict(kind="sphere", n_surface=100, spacing=0.22, seed=12),
@@ -285,6 +347,8 @@ def workload_mesh(name: str, **overrides) -> Mesh:
     elif kind == "sphere":
         pts = sphere_points(spec["n_surface"], spec["seed"])
         m = hull_mesh(pts, spec["spacing"], spec["seed"], name=name)
+    elif kind == "disk":
+        m = polygon_mesh(circle_points(spec["n_boundary"]), spec["spacing"], spec["seed"], name=name)
     elif kind == "ball":
         pts = fibonacci_sphere(spec["n_surface"], spec["radius"])
         m = hull_mesh(pts, spec["spacing"], spec["seed"], name=name)

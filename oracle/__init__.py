@@ -39,6 +39,7 @@ import numpy as np
 
 _HERE = Path(__file__).resolve().parent
 _SRC = _HERE / "fpde_oracle.c"
+_SRC2 = _HERE / "fpde_oracle2d.c"
 _LIB = _HERE / "_fpde_oracle.so"
 
 ORC_EPATH = -5
@@ -47,10 +48,10 @@ DEFAULT_CAP = 4096
 
 def build(force: bool = True) -> Path:
     """Compile the C oracle with gcc (plain FP64, no FMA contraction)."""
-    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+    if force or _stale():
         tmp = _LIB.with_suffix(".so.tmp")
         subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                        "-fPIC", "-shared", "-o", str(tmp), str(_SRC), "-lm"], check=True)
+                        "-fPIC", "-shared", "-o", str(tmp), str(_SRC), str(_SRC2), "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,11 +59,18 @@ def build(force: bool = True) -> Path:
 _lib = None
 
 
+def _stale() -> bool:
+    if not _LIB.exists():
+        return True
+    t = _LIB.stat().st_mtime
+    return t < _SRC.stat().st_mtime or t < _SRC2.stat().st_mtime
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+    if _stale():
         build(force=True)
     L = ctypes.CDLL(str(_LIB))
     P = ctypes.c_void_p
@@ -84,6 +92,23 @@ def _load():
     L.orc_assemble_div.argtypes = [P, i32, P, P, P, i32, P]
     L.orc_assemble_div_rows.argtypes = [P, i32, P, P, P, i32, i64, P, P]
     L.orc_assemble_form.argtypes = [P, i32, P, P, P, P, P, i32, P]
+    # two dimensions
+    L.o2_mesh_create.restype = P
+    L.o2_mesh_create.argtypes = [P, i64, P, i64, P]
+    L.o2_mesh_free.argtypes = [P]
+    L.o2_mesh_ndof.restype = i64
+    L.o2_mesh_ndof.argtypes = [P]
+    L.o2_mesh_dof.argtypes = [P, P]
+    L.o2_mesh_nbr.argtypes = [P, P]
+    L.o2_mesh_affine.argtypes = [P, P, P]
+    L.o2_quadrature.argtypes = [i32, P, P]
+    L.o2_gauss_points.argtypes = [P, i32, P, P]
+    L.o2_paths.argtypes = [P, i32, i64, i64, i32, P, P, P, P]
+    L.o2_walk_from.argtypes = [P, i64, P, i32, i32, i32, P, P, P]
+    L.o2_ray_values.argtypes = [P, i32, i64, i32, i32, dbl, dbl, dbl, i32, i32, P, P]
+    L.o2_assemble.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P]
+    L.o2_load.argtypes = [P, i32, P, P]
+    L.o2_exhaustive.argtypes = [P, P, P, P, P]
     L.orc_apply.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, P]
     L.orc_adjoint_sums.argtypes = [P, i32, dbl, dbl, dbl, i32, P, P, P, P]
     L.orc_load.argtypes = [P, i32, P, P]
@@ -390,6 +415,146 @@ class OracleMesh:
         dK = -ca * S
         da = -float(np.sum(K * (dca * S + ca * T)))
         return da, dK
+
+
+# --------------------------------------------------------------------------
+# The two-dimensional variant (n = 2): triangles, paths along +-e_1, +-e_2
+# --------------------------------------------------------------------------
+def quadrature2d(nq: int):
+    L = _load()
+    bary = np.empty(3 * nq)
+    w = np.empty(nq)
+    if L.o2_quadrature(nq, _p(bary), _p(w)) != 0:
+        raise OracleError(-1, "quadrature2d")
+    return bary.reshape(nq, 3), w
+
+
+class OracleMesh2D:
+    def __init__(self, xy, tri, cap: int = DEFAULT_CAP):
+        L = _load()
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.cap = int(cap)
+        st = ctypes.c_int(0)
+        h = L.o2_mesh_create(_p(self.xy), self.xy.shape[0], _p(self.tri), self.tri.shape[0], ctypes.byref(st))
+        if not h:
+            raise OracleError(st.value, "mesh2d")
+        self._h = ctypes.c_void_p(h)
+        self.n_vert = self.xy.shape[0]
+        self.n_tri = self.tri.shape[0]
+        self.ndof = int(L.o2_mesh_ndof(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.o2_mesh_free(self._h)
+            self._h = None
+
+    @property
+    def dof(self) -> np.ndarray:
+        out = np.empty(self.n_vert, dtype=np.int32)
+        _lib.o2_mesh_dof(self._h, _p(out))
+        return out
+
+    @property
+    def nbr(self) -> np.ndarray:
+        out = np.empty((self.n_tri, 3), dtype=np.int32)
+        _lib.o2_mesh_nbr(self._h, _p(out))
+        return out
+
+    def affine(self):
+        M = np.empty((self.n_tri, 2, 2))
+        area = np.empty(self.n_tri)
+        _lib.o2_mesh_affine(self._h, _p(M), _p(area))
+        return M, area
+
+    def gauss_points(self, nq: int):
+        G = self.n_tri * nq
+        x = np.empty((G, 2))
+        w = np.empty(G)
+        if _lib.o2_gauss_points(self._h, nq, _p(x), _p(w)) != 0:
+            raise OracleError(-1, "gauss2d")
+        return x, w
+
+    def paths(self, nq: int, h0: int = 0, count: int | None = None, lists: bool = False):
+        """Half-ray h = g*4 + 2*i + side: (length, FNV-1a hash[, ids, r_end])."""
+        if count is None:
+            count = self.n_tri * nq * 4 - h0
+        ln = np.zeros(count, dtype=np.int32)
+        hs = np.zeros(count, dtype=np.uint64)
+        ids = np.full((count, self.cap), -1, dtype=np.int32) if lists else None
+        rend = np.zeros((count, self.cap)) if lists else None
+        st = _lib.o2_paths(self._h, nq, h0, count, self.cap, _p(ln), _p(hs),
+                           _p(ids) if lists else None, _p(rend) if lists else None)
+        if st != 0:
+            raise OracleError(st, "paths2d")
+        return (ln, hs, ids, rend) if lists else (ln, hs)
+
+    def walk(self, t0: int, u0, i: int, s: int):
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        ids = np.empty(self.cap, dtype=np.int32)
+        rend = np.empty(self.cap)
+        n = ctypes.c_int(0)
+        st = _lib.o2_walk_from(self._h, t0, _p(u0), i, s, self.cap, _p(ids), _p(rend), ctypes.byref(n))
+        if st != 0:
+            raise OracleError(st, "walk2d")
+        return ids[: n.value].copy(), rend[: n.value].copy()
+
+    def exhaustive(self, u0, d):
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        lo = np.empty(self.n_tri)
+        hi = np.empty(self.n_tri)
+        _lib.o2_exhaustive(self._h, _p(u0), _p(d), _p(lo), _p(hi))
+        return lo, hi
+
+    def ray_values(self, nq: int, g: int, i: int, side: int, alpha: float, mode: int = 0):
+        gm, ig2, ig1, _ = order_scalars(alpha)
+        ids = np.empty(3 * self.cap, dtype=np.int32)
+        vals = np.empty(3 * self.cap)
+        n = _lib.o2_ray_values(self._h, nq, g, i, side, gm, ig2, ig1, mode, self.cap, _p(ids), _p(vals))
+        if n < 0:
+            raise OracleError(n, "ray2d")
+        return ids[:n].copy(), vals[:n].copy()
+
+    def assemble(self, nq: int, alpha: float, K=(1.0, 1.0)) -> np.ndarray:
+        gm, ig2, _, _ = order_scalars(alpha)
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        A = np.zeros((self.ndof, self.ndof))
+        st = _lib.o2_assemble(self._h, nq, gm, ig2, c_alpha(alpha), _p(Kc), self.cap, _p(A))
+        if st != 0:
+            raise OracleError(st, "assemble2d")
+        return A
+
+    def load(self, nq: int, f_gauss=None) -> np.ndarray:
+        b = np.zeros(self.ndof)
+        f = None if f_gauss is None else np.ascontiguousarray(f_gauss, dtype=np.float64)
+        if _lib.o2_load(self._h, nq, _p(f) if f is not None else None, _p(b)) != 0:
+            raise OracleError(-1, "load2d")
+        return b
+
+
+def mms_exact2d(x: np.ndarray) -> np.ndarray:
+    return mms_phi(x[:, 0]) * mms_phi(x[:, 1])
+
+
+def mms_source2d(x: np.ndarray, alpha: float, K=(1.0, 1.0)) -> np.ndarray:
+    """Source of u = phi(x) phi(y) on the unit square for the Riesz problem:
+    f = sum_i K_i c_alpha [Phi(x_i) + Phi(1 - x_i)] phi(x_other)."""
+    ca = c_alpha(alpha)
+    ph = [mms_phi(x[:, 0]), mms_phi(x[:, 1])]
+    return sum(K[i] * ca * (mms_Phi(x[:, i], alpha) + mms_Phi(1.0 - x[:, i], alpha)) * ph[1 - i]
+               for i in range(2))
+
+
+def l2_error2d(mesh: OracleMesh2D, u_dof: np.ndarray, exact, nq: int = 7) -> float:
+    bary, _ = quadrature2d(nq)
+    x, w = mesh.gauss_points(nq)
+    dof = mesh.dof
+    full = np.zeros(mesh.n_vert)
+    full[dof >= 0] = u_dof[dof[dof >= 0]]
+    uh = np.einsum("qj,tj->tq", bary, full[mesh.tri]).reshape(-1)
+    e = exact(x) - uh
+    return math.sqrt(float(np.sum(w * e * e)))
 
 
 # --------------------------------------------------------------------------
