@@ -64,7 +64,7 @@ typedef enum {
 } fpde_status;
 
 enum { FPDE_FP64 = 0, FPDE_MIXED = 1 };
-enum { FPDE_SRC_ONE = 0, FPDE_SRC_USER = 1, FPDE_SRC_CUBE_MMS = 2, FPDE_SRC_BALL_MMS = 3 };
+enum { FPDE_SRC_ONE = 0, FPDE_SRC_USER = 1, FPDE_SRC_CUBE_MMS = 2, FPDE_SRC_BALL_MMS = 3, FPDE_SRC_SQUARE_MMS = 4 };
 
 typedef struct {
   double alpha;     /* Riesz order, 1 < alpha <= 2 */
@@ -417,6 +417,77 @@ typedef struct {
  */
 int fpde_form_assemble(fpde_mesh *m, const fpde_form_params *p, const double *coef, double *A, int64_t lda,
                        void *stream);
+
+/*
+ * ---- The two-dimensional variant (n = 2; Sec. 1 with n = 2, Fig. 1a) ----
+ *
+ * P1 elements on a convex triangulated polygon, paths along +-e_1, +-e_2
+ * (the walk of Sec. 2.2 with three area coordinates: an edge go-out leads
+ * to the triangle across it, a vertex go-out to the smallest-id triangle
+ * around the vertex in which the ray advances), the split Riesz stiffness
+ *   K_jk = c_alpha sum_{i=1,2} K_i sum_g w_g [L_gi(k) R_gi(j) + R_gi(k) L_gi(j)],
+ * the load vector and the dense FP64 Cholesky solve.  Element rules: 3
+ * points (degree 2) and 7 points (degree 5, Radon).  Unknowns are the
+ * vertices on no boundary edge, by increasing vertex id.  Conventions as for
+ * the 3-D calls.
+ */
+typedef struct fpde_mesh2d fpde_mesh2d; /* opaque, library-owned */
+
+typedef struct {
+  double alpha;     /* Riesz order, 1 < alpha <= 2 */
+  double K[2];      /* K_1, K_2 > 0 */
+  int quad_points;  /* 3 or 7 */
+  int source;       /* FPDE_SRC_ONE, FPDE_SRC_USER, or FPDE_SRC_SQUARE_MMS: the
+                       manufactured source of u = phi(x) phi(y),
+                       phi(s) = s^2 (1 - s)^2, on the unit square */
+  int max_steps;    /* cap on elements per half-ray, 0 = 4096 */
+} fpde_params2d;
+
+/*
+ * xy: host, n_vert x 2 FP64; tri: host, n_tri x 3 int32 (any orientation).
+ * Builds on the device: A^{-1} and area per triangle, edge adjacency (edge f
+ * opposite local vertex f), boundary, numbering, vertex -> triangle lists.
+ * Synchronises `stream`.  Errors: FPDE_EINVAL, FPDE_EMESH_NONMANIFOLD,
+ * FPDE_EMESH_DEGENERATE, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_mesh2d_create(const double *xy, int64_t n_vert, const int32_t *tri, int64_t n_tri, void *stream,
+                       fpde_mesh2d **out);
+void fpde_mesh2d_destroy(fpde_mesh2d *m);
+int fpde_mesh2d_info(const fpde_mesh2d *m, int64_t *n_dof, int64_t *n_boundary_edges, int64_t *n_tri);
+/* host, n_vert int32: unknown of each vertex, -1 on the boundary */
+int fpde_dof_map2d(const fpde_mesh2d *m, int32_t *dof);
+
+/*
+ * Paths of the half-rays (g, dir) for Gauss points g in [g0, g0 + count),
+ * dir = 2 i + side (i = 0, 1; side 0: -e_i, side 1: +e_i); g lies in
+ * triangle g / quad_points.  Outputs as fpde_paths (len, FNV-1a hash of the
+ * triangle ids, optional ids and break points).  Synchronises `stream`.
+ */
+int fpde_paths2d(fpde_mesh2d *m, int quad_points, int dir, int64_t g0, int64_t count, int max_steps,
+                 int32_t *len, uint64_t *hash, int32_t *ids, double *rend, void *stream);
+
+/*
+ * K (dev, n_dof x lda FP64, leading block written) and b (dev, n_dof, may be
+ * NULL); f_gauss: dev, n_tri * quad_points for FPDE_SRC_USER.  The symbolic
+ * plan (paths, entry counts, node -> entry transpose) is built on first use
+ * per rule.  Synchronises `stream`.
+ * Errors: FPDE_EINVAL, FPDE_EALPHA, FPDE_EPATH, FPDE_ENOMEM, FPDE_EHIP.
+ */
+int fpde_assemble2d(fpde_mesh2d *m, const fpde_params2d *p, double *A, int64_t lda, double *b,
+                    const double *f_gauss, void *stream);
+
+/*
+ * K u = b by the FP64 Cholesky of the 3-D path; A is overwritten by its
+ * factor.  b, u: dev (may alias).  failed_pivot: host, may be NULL.
+ * Synchronises `stream`.  Errors: FPDE_EINVAL, FPDE_ENOTSPD, FPDE_ENOMEM,
+ * FPDE_EHIP.
+ */
+int fpde_solve2d(fpde_mesh2d *m, double *A, int64_t lda, const double *b, double *u, int64_t *failed_pivot,
+                 void *stream);
+
+/* stage timing of a 2-D handle (as fpde_timing / fpde_stage_times) */
+int fpde_timing2d(fpde_mesh2d *m, int enable);
+int fpde_stage_times2d(fpde_mesh2d *m, double *ms, int64_t *count);
 
 #ifdef __cplusplus
 }

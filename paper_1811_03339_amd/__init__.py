@@ -21,7 +21,7 @@ LIB_PATH = _HERE / "libfpde.so"
 
 FPDE_OK = 0
 FPDE_FP64, FPDE_MIXED = 0, 1
-FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS, FPDE_SRC_BALL_MMS = 0, 1, 2, 3
+FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS, FPDE_SRC_BALL_MMS, FPDE_SRC_SQUARE_MMS = 0, 1, 2, 3, 4
 FPDE_COEF_SEC3, FPDE_COEF_USER, FPDE_COEF_CONST = 0, 1, 2
 
 STATUS = {
@@ -35,7 +35,9 @@ EXPORTS = [
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
     "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
     "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve", "fpde_template_csr",
-    "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble",
+    "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble", "fpde_mesh2d_create",
+    "fpde_mesh2d_destroy", "fpde_mesh2d_info", "fpde_dof_map2d", "fpde_paths2d", "fpde_assemble2d",
+    "fpde_solve2d", "fpde_timing2d", "fpde_stage_times2d",
 ]
 
 STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div", "spmv",
@@ -69,6 +71,11 @@ class fpde_form_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double * 3), ("beta", ctypes.c_double * 3), ("quad_points", ctypes.c_int),
                 ("coef", ctypes.c_int), ("cl", ctypes.c_double * 3), ("cr", ctypes.c_double * 3),
                 ("max_steps", ctypes.c_int)]
+
+
+class fpde_params2d(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("K", ctypes.c_double * 2), ("quad_points", ctypes.c_int),
+                ("source", ctypes.c_int), ("max_steps", ctypes.c_int)]
 
 
 class fpde_solve_info(ctypes.Structure):
@@ -114,9 +121,18 @@ def _lib():
     L.fpde_csr_apply.argtypes = [P, P, P, P, P, P, P]
     L.fpde_cg_solve.argtypes = [P, P, P, P, P, P, P, dbl, i32, P, P]
     L.fpde_form_assemble.argtypes = [P, P, P, P, i64, P]
+    L.fpde_mesh2d_create.argtypes = [P, i64, P, i64, P, ctypes.POINTER(P)]
+    L.fpde_mesh2d_destroy.argtypes = [P]
+    L.fpde_mesh2d_info.argtypes = [P, P, P, P]
+    L.fpde_dof_map2d.argtypes = [P, P]
+    L.fpde_paths2d.argtypes = [P, i32, i32, i64, i64, i32, P, P, P, P, P]
+    L.fpde_assemble2d.argtypes = [P, P, P, i64, P, P, P]
+    L.fpde_solve2d.argtypes = [P, P, i64, P, P, P, P]
+    L.fpde_timing2d.argtypes = [P, i32]
+    L.fpde_stage_times2d.argtypes = [P, P, P]
     for name in EXPORTS:
         getattr(L, name).restype = L.fpde_status_string.restype if name == "fpde_status_string" else (
-            None if name == "fpde_mesh_destroy" else ctypes.c_int)
+            None if name in ("fpde_mesh_destroy", "fpde_mesh2d_destroy") else ctypes.c_int)
     _L = L
     return L
 
@@ -359,6 +375,78 @@ class Mesh:
         return ga.value, np.array(list(gk))
 
 
+def params2d(alpha: float, K=(1.0, 1.0), quad_points: int = 3, source: int = FPDE_SRC_ONE, max_steps: int = 0):
+    p = fpde_params2d()
+    p.alpha = float(alpha)
+    p.K[0], p.K[1] = float(K[0]), float(K[1])
+    p.quad_points = int(quad_points)
+    p.source = int(source)
+    p.max_steps = int(max_steps)
+    return p
+
+
+class Mesh2D:
+    """Device-resident two-dimensional mesh handle (fpde_mesh2d_*)."""
+
+    def __init__(self, xy, tri, stream=None):
+        L = _lib()
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(L.fpde_mesh2d_create(_np(self.xy), self.xy.shape[0], _np(self.tri), self.tri.shape[0],
+                                    _stream(stream), ctypes.byref(h)), "fpde_mesh2d_create")
+        self._h = h
+        nd, nb, nt = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.fpde_mesh2d_info(h, ctypes.byref(nd), ctypes.byref(nb), ctypes.byref(nt)), "fpde_mesh2d_info")
+        self.n_dof, self.n_boundary_edges, self.n_tri = nd.value, nb.value, nt.value
+        self.n_vert = self.xy.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().fpde_mesh2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def dof_map(self) -> np.ndarray:
+        out = np.empty(self.n_vert, dtype=np.int32)
+        _check(_lib().fpde_dof_map2d(self._h, _np(out)), "fpde_dof_map2d")
+        return out
+
+    def paths(self, quad_points: int, dir: int, g0: int, count: int, max_steps: int = 4096, lists: bool = False,
+              stream=None):
+        import torch
+        ln = torch.empty(count, dtype=torch.int32, device="cuda")
+        hs = torch.empty(count, dtype=torch.int64, device="cuda")
+        ids = torch.empty((count, max_steps), dtype=torch.int32, device="cuda") if lists else None
+        rend = torch.empty((count, max_steps), dtype=torch.float64, device="cuda") if lists else None
+        _check(_lib().fpde_paths2d(self._h, quad_points, dir, g0, count, max_steps, _ptr(ln), _ptr(hs), _ptr(ids),
+                                   _ptr(rend), _stream(stream)), "fpde_paths2d")
+        return ln, hs, ids, rend
+
+    def assemble(self, p, A, b=None, f_gauss=None, stream=None):
+        _check(_lib().fpde_assemble2d(self._h, ctypes.byref(p), _ptr(A), A.stride(0), _ptr(b), _ptr(f_gauss),
+                                      _stream(stream)), "fpde_assemble2d")
+
+    def solve(self, A, b, u, stream=None):
+        piv = ctypes.c_int64(-1)
+        _check(_lib().fpde_solve2d(self._h, _ptr(A), A.stride(0), _ptr(b), _ptr(u), ctypes.byref(piv),
+                                   _stream(stream)), "fpde_solve2d")
+
+    def timing(self, enable: bool):
+        _check(_lib().fpde_timing2d(self._h, 1 if enable else 0), "fpde_timing2d")
+
+    def stage_times(self) -> dict:
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), dtype=np.int64)
+        _check(_lib().fpde_stage_times2d(self._h, _np(ms), _np(cnt)), "fpde_stage_times2d")
+        return {s: (float(ms[k]), int(cnt[k])) for k, s in enumerate(STAGES)}
+
+
 def new_matrix(mesh: Mesh, precision: int = FPDE_FP64):
     import torch
     dt = torch.float64 if precision == FPDE_FP64 else torch.float32
@@ -394,4 +482,5 @@ from .autograd import FracSolve  # noqa: E402
 __all__ = ["Mesh", "params", "div_params", "solve_problem", "solve_div_problem", "new_matrix", "FracSolve",
            "FpdeError", "fpde_params", "fpde_div_params", "fpde_solve_info", "FPDE_FP64", "FPDE_MIXED",
            "FPDE_SRC_ONE", "FPDE_SRC_USER", "FPDE_SRC_CUBE_MMS", "FPDE_SRC_BALL_MMS", "FPDE_COEF_SEC3",
-           "FPDE_COEF_USER", "FPDE_COEF_CONST", "form_params", "fpde_form_params", "EXPORTS", "LIB_PATH"]
+           "FPDE_COEF_USER", "FPDE_COEF_CONST", "form_params", "fpde_form_params", "Mesh2D", "params2d",
+           "fpde_params2d", "FPDE_SRC_SQUARE_MMS", "EXPORTS", "LIB_PATH"]

@@ -15,7 +15,7 @@ ROOT = HERE.parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libfpde.so"
 SOURCES = ["mesh.hip", "walk.hip", "template.hip", "assemble.hip", "tubes.hip", "solve.hip", "lu.hip",
-           "divform.hip", "sparse.hip", "forms.hip"]
+           "divform.hip", "sparse.hip", "forms.hip", "plane.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -189,6 +189,11 @@ int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, 
 int apply_scratch(fpde_mesh *m, Plan *P, double **d);
 // load vector b for the Riesz problem (assemble.hip)
 int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_gauss, hipStream_t s);
+// dense SPD solve with a workspace handle (solve.hip); a workspace handle
+// holding only flags, timers and solve scratch for n unknowns (mesh.hip)
+int dense_spd_solve(fpde_mesh *ws, double *A, int64_t lda, int64_t n, const double *b, double *u,
+                    int64_t *failed, hipStream_t s);
+int workspace_new(int64_t ndof, fpde_mesh **out);
 // patch boxes of the template (built once per mesh)
 int ensure_patch_boxes(fpde_mesh *m, hipStream_t s);
 

@@ -402,6 +402,30 @@ static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, hipSt
 #undef STEPH
 }
 
+namespace fpde {
+
+int workspace_new(int64_t ndof, fpde_mesh **out) {
+  *out = nullptr;
+  fpde_mesh *m = new fpde_mesh();
+  m->ndof = ndof;
+  if (hipGetDevice(&m->device) != hipSuccess || dalloc(&m->flag, 1) != FPDE_OK ||
+      dalloc(&m->flag_aux, 1) != FPDE_OK) {
+    fpde_mesh_destroy(m);
+    return FPDE_ENOMEM;
+  }
+  const int32_t z = 0;
+  const int64_t mz = -1;
+  if (hipMemcpy(m->flag, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->flag_aux, &mz, sizeof(mz), hipMemcpyHostToDevice) != hipSuccess) {
+    fpde_mesh_destroy(m);
+    return FPDE_EHIP;
+  }
+  *out = m;
+  return FPDE_OK;
+}
+
+}  // namespace fpde
+
 extern "C" int fpde_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tet, int64_t n_tet,
                                 void *stream, fpde_mesh **out) {
   if (!out) return FPDE_EINVAL;

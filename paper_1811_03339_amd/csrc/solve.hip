@@ -656,6 +656,27 @@ static int solve_with_factor(fpde_mesh *m, const fpde_params *p, const void *L, 
   return rel <= tol ? FPDE_OK : FPDE_ENOCONV;
 }
 
+// Dense SPD solve for a matrix that is not the Riesz matrix of a 3-D mesh
+// (the two-dimensional variant): ws is a workspace handle (flags, timers,
+// scratch) with ws->ndof = n.  A is overwritten by its Cholesky factor.
+int dense_spd_solve(fpde_mesh *ws, double *A, int64_t lda, int64_t n, const double *b, double *u,
+                    int64_t *failed, hipStream_t s) {
+  if (failed) *failed = -1;
+  if (n == 0) return FPDE_OK;
+  FPDE_TRY(potrf<double>(A, lda, n, ws, s));
+  int64_t col = -1;
+  int f = take_flag(ws, s, &col);
+  if (f != 0) {
+    if (failed) *failed = col;
+    return f < 0 ? f : FPDE_EHIP;
+  }
+  FPDE_TRY(ensure_vec(ws));
+  if (u != b) FPDE_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  FPDE_TRY(trsv_pair<double>(A, lda, n, (const double *)ws->linv, u, ws->vec + 3 * n, ws, s));
+  f = take_flag(ws, s);
+  return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
+}
+
 }  // namespace fpde
 
 using namespace fpde;

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 def declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fpde_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fpde_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported():
@@ -82,3 +82,18 @@ def test_div_and_lu_calls_reject_bad_arguments_without_device():
     assert L.fpde_div_assemble(None, ctypes.byref(p), None, None, 0, None, None, None) == -1
     assert L.fpde_lu_factor(None, None, 0, None, None) == -1
     assert L.fpde_lu_solve(None, None, 0, None, None, None) == -1
+
+
+def test_params2d_layout_and_null_handles():
+    # double alpha; double K[2]; int quad_points, source, max_steps
+    assert F.fpde_params2d.quad_points.offset == 24
+    assert ctypes.sizeof(F.fpde_params2d) == 40
+    L = F._lib()
+    p = F.params2d(1.5)
+    assert L.fpde_assemble2d(None, ctypes.byref(p), None, 0, None, None, None) == -1
+    assert L.fpde_mesh2d_info(None, None, None, None) == -1
+    h = ctypes.c_void_p()
+    xy = np.zeros((3, 2))
+    tri = np.array([[0, 1, 5]], dtype=np.int32)
+    assert L.fpde_mesh2d_create(xy.ctypes.data_as(ctypes.c_void_p), 3, tri.ctypes.data_as(ctypes.c_void_p), 1,
+                                None, ctypes.byref(h)) == -1
