@@ -18,7 +18,8 @@ The single JSON line on stdout also carries the per-stage times, the
 roofline of the dominant kernel (measured with HIP events inside the library
 on the launch stream), the mixed-precision arm, K on the template of Sec. 2.3
 as CSR with conjugate gradients (CSR and matrix-free), the general uniform
-form (c D^alpha u, D^beta v) with per-axis orders, the divergence-form
+form (c D^alpha u, D^beta v) with per-axis orders, the two-dimensional
+variant on a disk, the divergence-form
 problem of Sec. 3 on the finest mesh of Table 3 (assembly + LU + solve, with the LU
 against its FP64 roofline) and the CPU oracle baseline.
 """
@@ -247,6 +248,50 @@ def bench_form(F, torch, gm, info4, reps=3):
                      "frac": alg / t_rows / HBM_PEAK, "gathered_bytes": gathered}}
 
 
+PLANE_WORKLOAD = "disk4k"
+
+
+def bench_plane(F, torch, reps=3):
+    """The two-dimensional variant on the disk (4654 nodes), 7-point rule:
+    per pass the walk at the pass's order, the row accumulation, the load
+    vector and the dense Cholesky solve (orders alternate so every pass
+    re-walks)."""
+    from fpde_inputs import workload_mesh
+    mesh = workload_mesh(PLANE_WORKLOAD)
+    g2 = F.Mesh2D(mesh.xyz, mesh.tet)
+    n = g2.n_dof
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    u = torch.empty_like(b)
+
+    def one(alpha):
+        g2.assemble(F.params2d(alpha, (1.0, 0.5), 7), A, b)
+        g2.solve(A, b, u)
+
+    one(1.8)  # plan + warm-up
+    torch.cuda.synchronize()
+    g2.timing(True)
+    ts = []
+    for k in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        one(1.3 if k % 2 == 0 else 1.6)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    g2.timing(False)
+    st = g2.stage_times()
+    t = sorted(ts)[len(ts) // 2]
+    rays = 4 * g2.n_tri * 7
+    out = {"workload": f"{PLANE_WORKLOAD}: unit disk (160-gon) + jittered triangular lattice, {g2.n_tri} triangles, "
+                       f"{mesh.n_vert} nodes ({n} interior), 7-point rule, K = (1, 0.5), alpha alternating 1.3 / 1.6",
+           "n_dof": n, "pass_ms": t, "paths_per_s": rays / (t / 1e3),
+           "stages_ms_per_pass": {k: v[0] / reps for k, v in st.items() if v[1] > 0}}
+    g2.close()
+    return out
+
+
 def cpu_baseline(mesh_np):
     """The oracle, unchanged, single-threaded, on one full step."""
     from threadpoolctl import threadpool_limits
@@ -278,6 +323,7 @@ def main():
     ap.add_argument("--no-sec3", action="store_true", help="skip the Sec. 3 divergence-form problem")
     ap.add_argument("--no-sparse", action="store_true", help="skip the template-CSR / CG section")
     ap.add_argument("--no-form", action="store_true", help="skip the general-form section")
+    ap.add_argument("--no-plane", action="store_true", help="skip the two-dimensional section")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -440,6 +486,11 @@ def main():
         form = bench_form(F, torch, gm, info[4])
         log(f"[bench] form {form}")
 
+    plane = None
+    if not args.no_plane:
+        plane = bench_plane(F, torch)
+        log(f"[bench] plane {plane}")
+
     sec3 = None
     if not args.no_sec3:
         sec3 = bench_sec3(F, torch, dev)
@@ -493,6 +544,7 @@ def main():
         "mixed": mixed,
         "sparse": sparse,
         "form": form,
+        "plane": plane,
         "sec3": sec3,
         "cpu_baseline": cpu,
     }
