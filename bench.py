@@ -367,17 +367,25 @@ def main():
                 "ms": 1e3 * (time.perf_counter() - t)}
     log(f"[bench] template {template}")
 
-    A = torch.empty((n, n), dtype=torch.float64, device=dev)
-    b = torch.empty(n, dtype=torch.float64, device=dev)
-    u = torch.empty(n, dtype=torch.float64, device=dev)
+    cases = [(nq, a) for nq in RULES for a in ALPHAS]
+    A = torch.empty((len(cases), n, n), dtype=torch.float64, device=dev)
+    b = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
+    u = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
     rays_per_step = sum(6 * gm.n_tet * nq for nq in RULES) * len(ALPHAS)
 
     def step():
-        for nq in RULES:
-            for a in ALPHAS:
-                p = F.params(a, KCOEF, quad_points=nq)
-                gm.assemble(p, A, b)
-                gm.solve(p, A, b, u, info=False)
+        # the step's systems are assembled one after another (each fills the
+        # device), then factored and solved together: their Cholesky and
+        # triangular-solve chains, latency-bound one by one, run side by side
+        for z, (nq, a) in enumerate(cases):
+            gm.assemble(F.params(a, KCOEF, quad_points=nq), A[z], b[z])
+        gm.solve_batch(A, b, u)
+
+    def step_sequential():
+        for z, (nq, a) in enumerate(cases):
+            p = F.params(a, KCOEF, quad_points=nq)
+            gm.assemble(p, A[z], b[z])
+            gm.solve(p, A[z], b[z], u[z], info=False)
 
     for _ in range(args.warmup):
         step()
@@ -399,22 +407,37 @@ def main():
     value = rays_per_step * args.steps / (total_ms / 1e3)
     log(f"[bench] {ms_per_step:.2f} ms/step, {value:.3e} paths/s, stages {stages}")
 
-    # Roofline of the dominant unit: one dense factorization (k_potrf_diag
-    # once, then k_panel + k_syrk per 64-column panel; about 40% of the step),
-    # timed with one event pair per factorization on the launch stream.
-    # Algorithmic work n^3 / 3 FP64 flops, on the vector units (no MFMA in
-    # FP64 here): peak 78.6 TFLOP/s.
-    passes = len(RULES) * len(ALPHAS)
+    # the same systems one at a time (assemble, factor, solve per system), one
+    # step, outside the timed region: the per-system latency beside the
+    # batched throughput
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    step_sequential()
+    e1.record()
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    log(f"[bench] one step with the systems solved one at a time: {seq_ms:.2f} ms")
+
+    # Roofline of the dominant unit: one batched dense factorization of the
+    # step's systems (k_potrf_diag once, then k_panel + k_syrk per 64-column
+    # panel, grid.y = system), timed with one event pair per call on the
+    # launch stream (the stage count is in systems).  Algorithmic work
+    # systems x n^3 / 3 FP64 flops, on the vector units (no MFMA in FP64
+    # here): peak 78.6 TFLOP/s.
+    passes = len(cases)
     factorizations = stages["potrf"][1]
     roofline = None
     if factorizations:
-        avg_s = stages["potrf"][0] / factorizations / 1e3
-        fl = n ** 3 / 3.0
+        calls = factorizations / passes
+        avg_s = stages["potrf"][0] / calls / 1e3
+        fl = passes * n ** 3 / 3.0
         ach = fl / avg_s / 1e12
         roofline = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
                     "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
-                    "kernel": f"factorization: k_potrf_diag<double> + {syrk_flops(n)[1]} x (k_panel<double> + "
-                              f"k_syrk<double>)",
+                    "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double> + "
+                              f"{syrk_flops(n)[1]} x (k_panel<double> + k_syrk<double>), grid.y = system",
                     "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (vector FMA)"}
     # every stage against its own bound (algorithmic work / measured time)
     stage_roof = {}
@@ -445,7 +468,8 @@ def main():
         p64 = F.params(1.5, KCOEF, quad_points=11)
         pmx = F.params(1.5, KCOEF, quad_points=11, precision=F.FPDE_MIXED, ir_tol=1e-8)
         A32 = torch.empty((n, n), dtype=torch.float32, device=dev)
-        u32 = torch.empty_like(u)
+        A0, b0, u0 = A[0], b[0], u[0]
+        u32 = torch.empty_like(u0)
 
         def timed(fn, reps=3):
             ts = []
@@ -460,16 +484,16 @@ def main():
             return sorted(ts)[len(ts) // 2], r
 
         def run64():
-            gm.assemble(p64, A, b)
-            gm.solve(p64, A, b, u, info=False)
+            gm.assemble(p64, A0, b0)
+            gm.solve(p64, A0, b0, u0, info=False)
 
         def runmx():
-            gm.assemble(pmx, A32, b)
-            return gm.solve(pmx, A32, b, u32)
+            gm.assemble(pmx, A32, b0)
+            return gm.solve(pmx, A32, b0, u32)
 
         t64, _ = timed(run64)
         tmx, inf = timed(runmx)
-        err = float((u32 - u).abs().max() / u.abs().max())
+        err = float((u32 - u0).abs().max() / u0.abs().max())
         mixed = {"workload": "alpha=1.5, 11-point rule", "fp64_assembly_solve_s": t64 / 1e3,
                  "mixed_assembly_solve_s": tmx / 1e3, "speedup_vs_fp64": t64 / tmx,
                  "rel_err_vs_fp64": err, "ir_iters": inf.ir_iters,
@@ -526,12 +550,14 @@ def main():
             "workload": f"{WORKLOAD}: hull of 400 seeded points on the unit sphere + BCC lattice, "
                         f"{gm.n_tet} tets, {mesh.n_vert} nodes ({n} interior); alpha {list(ALPHAS)}, "
                         f"K={list(KCOEF)}, rules {list(RULES)}; FP64 assembly + dense Cholesky; "
-                        f"{passes} assembly+solve passes per step",
+                        f"{passes} systems per step, assembled one by one, factored and solved as one batch",
             "n_nodes": mesh.n_vert, "n_dof": n, "n_tet": gm.n_tet,
             "gauss_points": {str(nq): gm.n_tet * nq for nq in RULES},
             "parallelism": "single GPU",
         },
         "assembly_solve_s_per_pass": ms_per_step / passes / 1e3,
+        "sequential_ms_per_step": seq_ms,
+        "sequential_assembly_solve_s_per_system": seq_ms / passes / 1e3,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0},
         "walk_eval_paths_per_s": (rays_per_step * args.steps / (stages["walk"][0] / 1e3)
                                   if stages["walk"][0] > 0 else None),

@@ -194,6 +194,28 @@ int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const void *L, int64
                         const double *b, double *u, fpde_solve_info *info, void *stream);
 
 /*
+ * FP64 dense solves of `count` independent systems K_z u_z = b_z, z < count
+ * (the "Solve linear equations" stage, Table 4, for several alpha or rules at
+ * once), with one launch sequence: the systems' Cholesky factorizations and
+ * triangular solves run side by side on the device.
+ *   A: dev FP64, count matrices of n_dof x n_dof (row-major, leading
+ *      dimension lda >= n_dof), matrix z at A + z stride_A
+ *      (stride_A >= n_dof lda when count > 1); each is overwritten by its
+ *      Cholesky factor L_z (lower triangle), exactly as fpde_solve does.
+ *   b, u: dev FP64, vector z at b + z stride_v and u + z stride_v
+ *      (stride_v >= n_dof when count > 1); u may alias b.
+ *   count: 1..16.  failed_pivot: host, count entries, may be NULL; entry z
+ *      is the first column of the block where K_z was found not positive
+ *      definite, else -1.
+ * Synchronises `stream`.  The mesh handle's scratch is shared, so calls on
+ * one handle must not overlap.
+ * Errors: FPDE_EINVAL, FPDE_ENOTSPD (no solution written), FPDE_ENOMEM,
+ * FPDE_EHIP.
+ */
+int fpde_solve_batch(fpde_mesh *m, int count, double *A, int64_t lda, int64_t stride_A, const double *b,
+                     double *u, int64_t stride_v, int64_t *failed_pivot, void *stream);
+
+/*
  * Adjoint sums for the gradient of a loss J(u) through assembly and solve
  * (u = K^{-1} b, b independent of alpha and K): with lam = K^{-1} dJ/du,
  *   dJ/dK_i   = -c_alpha S_i

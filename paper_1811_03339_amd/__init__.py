@@ -37,7 +37,7 @@ EXPORTS = [
     "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve", "fpde_template_csr",
     "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble", "fpde_mesh2d_create",
     "fpde_mesh2d_destroy", "fpde_mesh2d_info", "fpde_dof_map2d", "fpde_paths2d", "fpde_assemble2d",
-    "fpde_solve2d", "fpde_timing2d", "fpde_stage_times2d",
+    "fpde_solve2d", "fpde_timing2d", "fpde_stage_times2d", "fpde_solve_batch",
 ]
 
 STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div", "spmv",
@@ -108,6 +108,7 @@ def _lib():
     L.fpde_apply.argtypes = [P, P, P, P, P]
     L.fpde_solve.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_solve_factored.argtypes = [P, P, P, i64, P, P, P, P]
+    L.fpde_solve_batch.argtypes = [P, i32, P, i64, i64, P, P, i64, P, P]
     L.fpde_adjoint.argtypes = [P, P, P, P, P, P, P]
     L.fpde_timing.argtypes = [P, i32]
     L.fpde_stage_times.argtypes = [P, P, P]
@@ -302,6 +303,21 @@ class Mesh:
         _check(_lib().fpde_solve(self._h, ctypes.byref(p), _ptr(A), A.stride(0), _ptr(b), _ptr(u),
                                  ctypes.byref(out) if info else None, _stream(stream)), "fpde_solve")
         return out if info else None
+
+    def solve_batch(self, A, b, u, stream=None):
+        """FP64 Cholesky solves of A[z] u[z] = b[z] for every z < A.shape[0]
+        (1..16) in one launch sequence; A (count, n, n) is overwritten by the
+        factors.  Raises FpdeError with .failed_pivot (per system) on failure."""
+        count = A.shape[0]
+        if A.stride(2) != 1 or b.stride(-1) != 1 or u.stride(-1) != 1 or u.stride(0) != b.stride(0):
+            raise ValueError("solve_batch: rows of A and the vectors must be contiguous, b and u alike strided")
+        piv = (ctypes.c_int64 * max(count, 1))()
+        st = _lib().fpde_solve_batch(self._h, count, _ptr(A), A.stride(1), A.stride(0), _ptr(b), _ptr(u),
+                                     b.stride(0), piv, _stream(stream))
+        if st != FPDE_OK:
+            e = FpdeError(st, "fpde_solve_batch")
+            e.failed_pivot = [piv[z] for z in range(count)]
+            raise e
 
     def solve_factored(self, p, L, b, u, stream=None, info: bool = True):
         out = fpde_solve_info()

@@ -90,6 +90,15 @@ __device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, in
   }
 }
 
+// Element strides between the systems of a strided batch (grid.y = system):
+// matrix, diagonal-block inverses, vectors, per-block flags, tickets.  All
+// zero for a single system.
+struct BatchStrides {
+  int64_t a = 0, l = 0, v = 0, x = 0;  // v: right-hand side / solution, x: intermediate vector
+  int f = 0, t = 0;
+};
+constexpr int kMaxBatch = 16;
+
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
 
 // Whole-wave poll of the flags of blocks c, c + dir, ..., (count <= 64 of
@@ -145,11 +154,20 @@ template <class T, bool UP>
 __global__ void __launch_bounds__(256) k_trsv_rows(const T *__restrict__ A, int64_t lda, int64_t n, int nblk,
                                                    const T *__restrict__ DinvT, const double *__restrict__ y,
                                                    double *__restrict__ x, int *flags, int *ticket, int epoch,
-                                                   int32_t *err) {
+                                                   int32_t *err, BatchStrides bs) {
   __shared__ int sb, ok;
   __shared__ double rhs[NB];
   __shared__ double red[4][NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  {
+    const int64_t z = blockIdx.y;  // system z of a strided batch (its own tickets and flags)
+    A += z * bs.a;
+    DinvT += z * bs.l;
+    y += z * bs.v;
+    x += z * bs.x;
+    flags += z * bs.f;
+    ticket += z * bs.t;
+  }
   if (tid == 0) {
     sb = atomicAdd(ticket, 1);
     ok = 1;
@@ -242,7 +260,8 @@ __global__ void __launch_bounds__(256) k_trsv_rows(const T *__restrict__ A, int6
 // (elements of `elem` bytes), kept in the mesh handle and grown on demand.
 int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out);
 // Per-block flags (two sets of nblk) and two tickets for the solves.
-int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s);
+// per-system flags (2 nblk each) then tickets (2 each) for `count` systems
+int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s, int count = 1);
 // p[0..n) = 0 with a kernel (no memset node when a caller captures a graph).
 int zero_ints(int *p, int n, hipStream_t s);
 

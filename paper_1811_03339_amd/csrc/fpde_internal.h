@@ -90,6 +90,7 @@ struct StageTimer {
   struct Mark {
     int stage;
     size_t a, b;
+    int weight;  // units the interval covers (systems of a batch)
   };
   std::vector<Mark> marks;
 };
@@ -121,8 +122,11 @@ struct fpde_mesh {
   size_t linv_bytes = 0;
   double *cg = nullptr;           // conjugate-gradient vectors and partial sums
   int64_t cg_n = 0;
-  int *tsync = nullptr;           // triangular solves: per-block flags (2 nblk) and 2 tickets
-  int tsync_n = 0;
+  int *tsync = nullptr;           // triangular solves: per-system block flags (2 nblk) and tickets (2)
+  int tsync_n = 0;                // ints allocated
+  int64_t *batch_aux = nullptr;   // device, kMaxBatch: failing column per system of a batched factorization
+  double *bvec = nullptr;         // device: intermediate vectors of a batched solve
+  int64_t bvec_n = 0;
   int tsync_epoch = 0;
   fpde::StageTimer timer;
 };
@@ -199,7 +203,7 @@ int ensure_patch_boxes(fpde_mesh *m, hipStream_t s);
 
 // Stage timing: t = timer_begin(m, s); ...launches...; timer_end(m, stage, t, s)
 long timer_begin(fpde_mesh *m, hipStream_t s);
-void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s);
+void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s, int weight = 1);
 
 // host-side order scalars
 struct Order {

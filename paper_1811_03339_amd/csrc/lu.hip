@@ -353,9 +353,10 @@ int lu_solve(fpde_mesh *m, const double *LU, int64_t lda, int64_t n, const doubl
                                         m->flag_aux);
   if (u != b) k_copy_f64<<<blocks_of(n), 256, 0, s>>>(b, u, n);
   FPDE_TRY(zero_ints(tickets, 2, s));
-  k_trsv_rows<double, false><<<nblk, 256, 0, s>>>(LU, lda, n, nblk, LinvT, u, xs, fflags, tickets, epoch, m->flag);
+  k_trsv_rows<double, false><<<nblk, 256, 0, s>>>(LU, lda, n, nblk, LinvT, u, xs, fflags, tickets, epoch, m->flag,
+                                                  BatchStrides{});
   k_trsv_rows<double, true><<<nblk, 256, 0, s>>>(LU, lda, n, nblk, UinvT, xs, u, bflags, tickets + 1, epoch,
-                                                 m->flag);
+                                                 m->flag, BatchStrides{});
   timer_end(m, FPDE_STAGE_TRSV, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;

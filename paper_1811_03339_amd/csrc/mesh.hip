@@ -457,6 +457,8 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   if (m->linv) (void)hipFree(m->linv);
   dfree(m->tsync);
+  dfree(m->batch_aux);
+  dfree(m->bvec);
   dfree(m->pbox);
   dfree(m->cg);
   delete m;
@@ -491,7 +493,7 @@ long timer_begin(fpde_mesh *m, hipStream_t s) {
   return (long)i;
 }
 
-void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s) {
+void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s, int weight) {
   StageTimer &T = m->timer;
   if (t < 0 || !T.on) return;
   if (T.used >= T.pool.size()) {
@@ -501,7 +503,7 @@ void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s) {
   }
   const size_t i = T.used++;
   if (hipEventRecord(T.pool[i], s) != hipSuccess) return;
-  T.marks.push_back({stage, (size_t)t, i});
+  T.marks.push_back({stage, (size_t)t, i, weight});
 }
 
 }  // namespace fpde
@@ -526,7 +528,7 @@ extern "C" int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count) {
     float e = 0.f;
     FPDE_HIP(hipEventElapsedTime(&e, m->timer.pool[mk.a], m->timer.pool[mk.b]));
     t[mk.stage] += (double)e;
-    c[mk.stage] += 1;
+    c[mk.stage] += mk.weight;
   }
   for (int k = 0; k < FPDE_NSTAGES; k++) {
     if (ms) ms[k] = t[k];

@@ -234,8 +234,12 @@ __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict_
 template <class T>
 __global__ void __launch_bounds__(256) k_potrf_diag(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                                     T *__restrict__ Linv, T *__restrict__ LinvT, int32_t *flag,
-                                                    int64_t *aux) {
+                                                    int64_t *aux, int64_t sA, int64_t sL) {
   __shared__ DiagSmem sm;
+  A += (int64_t)blockIdx.y * sA;  // matrix blockIdx.y of a strided batch
+  Linv += (int64_t)blockIdx.y * sL;
+  LinvT += (int64_t)blockIdx.y * sL;
+  aux += blockIdx.y;
   const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
   T av[16];  // all loads first (indices clamped into the block), then the selects
 #pragma unroll
@@ -277,8 +281,10 @@ __global__ void __launch_bounds__(64) k_trinv(const T *__restrict__ A, int64_t l
 // panel: rows [k0+NB+64 b, +64) of columns [k0, k0+NB) become B inv(L_kk)^T
 template <class T>
 __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                               const T *__restrict__ Linv) {
+                                               const T *__restrict__ Linv, int64_t sA, int64_t sL) {
   __shared__ T sP[64][33], sQ[64][33];
+  A += (int64_t)blockIdx.y * sA;
+  Linv += (int64_t)blockIdx.y * sL;
   const int64_t r0 = k0 + NB + 64 * (int64_t)blockIdx.x;
   const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
   T acc[4][4];
@@ -302,7 +308,11 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
 template <class T>
 __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                               T *__restrict__ Linv_next, T *__restrict__ LinvT_next, int32_t *flag,
-                                              int64_t *aux) {
+                                              int64_t *aux, int64_t sA, int64_t sL) {
+  A += (int64_t)blockIdx.y * sA;
+  Linv_next += (int64_t)blockIdx.y * sL;
+  LinvT_next += (int64_t)blockIdx.y * sL;
+  aux += blockIdx.y;
   struct Gemm {
     T sP[64][33], sQ[64][33];
   };
@@ -376,11 +386,20 @@ template <class T>
 __global__ void __launch_bounds__(256) k_trsv_bwd(const T *__restrict__ L, int64_t lda, int64_t n, int nblk,
                                                   const T *__restrict__ Linv, const double *__restrict__ x,
                                                   double *__restrict__ u, int *flags, int *ticket, int epoch,
-                                                  int32_t *err) {
+                                                  int32_t *err, BatchStrides bs) {
   __shared__ int sb, ok;
   __shared__ double rhs[NB];
   __shared__ double red[4][NB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  {
+    const int64_t z = blockIdx.y;
+    L += z * bs.a;
+    Linv += z * bs.l;
+    x += z * bs.x;
+    u += z * bs.v;
+    flags += z * bs.f;
+    ticket += z * bs.t;
+  }
   if (tid == 0) {
     sb = atomicAdd(ticket, 1);
     ok = 1;
@@ -461,6 +480,18 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const T *__restrict__ L, int64
   }
 }
 
+__global__ void k_fill_i64(int64_t *p, int n, int64_t v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// u + z sv = b + z sv for the systems z = blockIdx.y of a batch
+__global__ void k_copy_strided(const double *__restrict__ b, double *__restrict__ u, int64_t n, int64_t sv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = (int64_t)blockIdx.y * sv;
+  if (k < n) u[o + k] = b[o + k];
+}
+
 __global__ void k_zero_i32(int *p, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0;
@@ -504,30 +535,41 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
   return FPDE_OK;
 }
 
+// Factor `count` matrices of a strided batch (A + z sA, z < count) with one
+// launch sequence: grid.y is the system, so the diagonal-block chains of the
+// systems run side by side.  Linv holds 2 nblk inverse blocks per system
+// (inverses, then transposes) at stride sL; aux[z] receives system z's
+// failing column.
 template <class T>
-static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
-  void *lv = nullptr;
-  FPDE_TRY(ensure_linv(m, n, sizeof(T), 2, &lv));  // inverses, then their transposes
-  T *Linv = (T *)lv;
+static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
+                       fpde_mesh *m, hipStream_t s) {
   const long t = timer_begin(m, s);
   // the first diagonal block on its own; every later one is factored by the
   // workgroup of tile (0, 0) inside the preceding trailing update
-  T *LinvT = Linv + ((n + NB - 1) / NB) * NB * NB;
-  k_potrf_diag<T><<<1, 256, 0, s>>>(A, lda, n, 0, Linv, LinvT, m->flag, m->flag_aux);
+  const int64_t nbk = (n + NB - 1) / NB;
+  T *LinvT = Linv + nbk * NB * NB;
+  const unsigned z = (unsigned)count;
+  k_potrf_diag<T><<<dim3(1, z), 256, 0, s>>>(A, lda, n, 0, Linv, LinvT, m->flag, aux, sA, sL);
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     T *Lk = Linv + (k0 / NB) * NB * NB;
     const int64_t rest = n - k0 - NB;
     if (rest > 0) {
-      k_panel<T><<<nblk(rest, 64), 256, 0, s>>>(A, lda, n, k0, Lk);
+      k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, k0, Lk, sA, sL);
       const int64_t Tn = (rest + 63) / 64;
-      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2), 256, 0, s>>>(A, lda, n, k0, Lk + NB * NB,
-                                                                LinvT + (k0 / NB + 1) * NB * NB, m->flag,
-                                                                m->flag_aux);
+      k_syrk<T><<<dim3((unsigned)(Tn * (Tn + 1) / 2), z), 256, 0, s>>>(
+          A, lda, n, k0, Lk + NB * NB, LinvT + (k0 / NB + 1) * NB * NB, m->flag, aux, sA, sL);
     }
   }
-  timer_end(m, FPDE_STAGE_POTRF, t, s);
+  timer_end(m, FPDE_STAGE_POTRF, t, s, count);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
+}
+
+template <class T>
+static int potrf(T *A, int64_t lda, int64_t n, fpde_mesh *m, hipStream_t s) {
+  void *lv = nullptr;
+  FPDE_TRY(ensure_linv(m, n, sizeof(T), 2, &lv));  // inverses, then their transposes
+  return potrf_batch<T>(A, lda, 0, n, 1, (T *)lv, 0, m->flag_aux, m, s);
 }
 
 // y (n) holds the right-hand side on entry and the solution on exit;
@@ -540,34 +582,51 @@ int zero_ints(int *p, int n, hipStream_t s) {
   return FPDE_OK;
 }
 
-int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s) {
-  if (m->tsync_n < nblk) {
+int ensure_trsv_sync(fpde_mesh *m, int nblk, hipStream_t s, int count) {
+  const int cnt = count * (2 * nblk + 2);
+  if (m->tsync_n < cnt) {
     dfree(m->tsync);
     m->tsync_n = 0;
-    const int cnt = 2 * nblk + 2;
     FPDE_TRY(dalloc(&m->tsync, (size_t)cnt));
     k_zero_i32<<<(cnt + 255) / 256, 256, 0, s>>>(m->tsync, cnt);
-    m->tsync_n = nblk;
-    m->tsync_epoch = 0;
+    m->tsync_n = cnt;
+    m->tsync_epoch = 0;  // every flag is below the next epoch
   }
+  return FPDE_OK;
+}
+
+// Forward and backward solves of `count` systems (strided batch, grid.y =
+// system): y + z sv holds system z's right-hand side on entry and its
+// solution on exit; x + z sx is scratch.
+template <class T>
+static int trsv_batch(const T *L, int64_t lda, int64_t sA, int64_t n, int count, const T *Linv, int64_t sL,
+                      double *y, int64_t sv, double *x, int64_t sx, fpde_mesh *m, hipStream_t s) {
+  const int nblk = (int)((n + NB - 1) / NB);
+  FPDE_TRY(ensure_trsv_sync(m, nblk, s, count));
+  const int epoch = ++m->tsync_epoch;
+  int *fflags = m->tsync, *bflags = m->tsync + nblk, *tickets = m->tsync + (int64_t)count * 2 * nblk;
+  const T *LinvT = Linv + (size_t)nblk * NB * NB;
+  BatchStrides bs;
+  bs.a = sA;
+  bs.l = sL;
+  bs.v = sv;
+  bs.x = sx;
+  bs.f = 2 * nblk;
+  bs.t = 2;
+  const dim3 grid((unsigned)nblk, (unsigned)count);
+  const long t = timer_begin(m, s);
+  k_zero_i32<<<1, 64, 0, s>>>(tickets, 2 * count);
+  k_trsv_rows<T, false><<<grid, 256, 0, s>>>(L, lda, n, nblk, LinvT, y, x, fflags, tickets, epoch, m->flag, bs);
+  k_trsv_bwd<T><<<grid, 256, 0, s>>>(L, lda, n, nblk, Linv, x, y, bflags, tickets + 1, epoch, m->flag, bs);
+  timer_end(m, FPDE_STAGE_TRSV, t, s, count);
+  FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }
 
 template <class T>
 static int trsv_pair(const T *L, int64_t lda, int64_t n, const T *Linv, double *y, double *x, fpde_mesh *m,
                      hipStream_t s) {
-  const int nblk = (int)((n + NB - 1) / NB);
-  FPDE_TRY(ensure_trsv_sync(m, nblk, s));
-  const int epoch = ++m->tsync_epoch;
-  int *fflags = m->tsync, *bflags = m->tsync + nblk, *tickets = m->tsync + 2 * nblk;
-  const T *LinvT = Linv + (size_t)nblk * NB * NB;
-  const long t = timer_begin(m, s);
-  k_zero_i32<<<1, 64, 0, s>>>(tickets, 2);
-  k_trsv_rows<T, false><<<nblk, 256, 0, s>>>(L, lda, n, nblk, LinvT, y, x, fflags, tickets, epoch, m->flag);
-  k_trsv_bwd<T><<<nblk, 256, 0, s>>>(L, lda, n, nblk, Linv, x, y, bflags, tickets + 1, epoch, m->flag);
-  timer_end(m, FPDE_STAGE_TRSV, t, s);
-  FPDE_HIP(hipGetLastError());
-  return FPDE_OK;
+  return trsv_batch<T>(L, lda, 0, n, 1, Linv, 0, y, 0, x, 0, m, s);
 }
 
 static int ensure_vec(fpde_mesh *m) {
@@ -722,4 +781,45 @@ extern "C" int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const voi
                                         (double *)lv + (size_t)nbk * NB * NB);
   FPDE_HIP(hipGetLastError());
   return solve_with_factor(m, p, L, lda, lv, b, u, info, s);
+}
+
+extern "C" int fpde_solve_batch(fpde_mesh *m, int count, double *A, int64_t lda, int64_t stride_A, const double *b,
+                                double *u, int64_t stride_v, int64_t *failed_pivot, void *stream) {
+  if (!m || count < 1 || count > kMaxBatch) return FPDE_EINVAL;
+  const int64_t n = m->ndof;
+  if (!A || !b || !u || lda < n) return FPDE_EINVAL;
+  if (count > 1 && (stride_A < n * lda || stride_v < n)) return FPDE_EINVAL;
+  if (failed_pivot)
+    for (int z = 0; z < count; z++) failed_pivot[z] = -1;
+  if (n == 0) return FPDE_OK;
+  const int64_t sA = count > 1 ? stride_A : 0, sv = count > 1 ? stride_v : 0;
+  hipStream_t s = S(stream);
+  if (!m->batch_aux) FPDE_TRY(dalloc(&m->batch_aux, (size_t)kMaxBatch));
+  if (m->bvec_n < (int64_t)count * n) {
+    dfree(m->bvec);
+    m->bvec_n = 0;
+    FPDE_TRY(dalloc(&m->bvec, (size_t)count * (size_t)n));
+    m->bvec_n = (int64_t)count * n;
+  }
+  const int64_t nbk = (n + NB - 1) / NB, sL = 2 * nbk * NB * NB;
+  void *lv = nullptr;
+  FPDE_TRY(ensure_linv(m, n, sizeof(double), 2 * count, &lv));
+  k_fill_i64<<<1, 64, 0, s>>>(m->batch_aux, count, -1);
+  FPDE_TRY(potrf_batch<double>(A, lda, sA, n, count, (double *)lv, sL, m->batch_aux, m, s));
+  int f = take_flag(m, s);
+  if (f != 0) {
+    int64_t col[kMaxBatch];
+    FPDE_HIP(hipMemcpyAsync(col, m->batch_aux, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+    FPDE_HIP(hipStreamSynchronize(s));
+    if (failed_pivot)
+      for (int z = 0; z < count; z++) failed_pivot[z] = col[z];
+    return f < 0 ? f : FPDE_EHIP;
+  }
+  if (u != b) {
+    k_copy_strided<<<dim3(nblk(n), (unsigned)count), 256, 0, s>>>(b, u, n, sv);
+    FPDE_HIP(hipGetLastError());
+  }
+  FPDE_TRY(trsv_batch<double>(A, lda, sA, n, count, (const double *)lv, sL, u, sv, m->bvec, n, m, s));
+  f = take_flag(m, s);
+  return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
 }
