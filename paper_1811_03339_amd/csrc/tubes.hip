@@ -17,7 +17,10 @@
 //     places where that node appears;
 //   pass 1: one workgroup per (tube, band of block rows) reads the tube's
 //     entries once and adds every product l_p r_q into an LDS band of the
-//     block; the band goes to a scratch block in HBM;
+//     block; the band goes to a scratch block in HBM.  The block is
+//     symmetric, B = S + S^T with S = sum w l r^T, so a tube whose packed
+//     upper triangle fits in LDS (|U_T| <= 200) is one band that adds each
+//     product of S once, at (min, max), and expands the triangle as it writes;
 //   pass 2: one workgroup per row of A sums that row's slices of the tube
 //     blocks into an LDS row and writes the row once.
 // Each entry is read once per band of its tube (not once per node of its
@@ -36,10 +39,23 @@ namespace {
 
 constexpr int kHash = 8192;         // LDS hash slots per tube (int32 keys)
 constexpr int kMaxU = kHash / 2;    // largest node set a tube may have
-constexpr int kBandDoubles = 20160;  // LDS doubles of one pass-1 band (157.5 KB: one band for |U_T| <= 141)
+constexpr int kBandDoubles = 20160;  // LDS doubles of one pass-1 band (157.5 KB: the packed triangle of |U_T| <= 200)
 
 // row stride of a band in LDS: odd, so the rows of one column fall in distinct bank pairs
 __host__ __device__ inline int band_stride(int U) { return U | 1; }
+
+// A tube whose packed upper triangle fits in LDS is one band (its whole
+// block); a larger one is cut into bands of full rows.
+__host__ __device__ inline int band_rows(int U) {
+  if (U <= 0) return 1;
+  if ((int64_t)U * (U + 1) / 2 <= kBandDoubles) return U;
+  const int R = kBandDoubles / band_stride(U);
+  return R < U ? R : U;
+}
+
+// position of (lo, hi), lo <= hi, in the row-packed upper triangle of a
+// U x U block: tri_base(lo, U) + hi
+__host__ __device__ inline int tri_base(int lo, int U) { return lo * (2 * U - lo + 1) / 2 - lo; }
 
 inline unsigned nblocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
@@ -223,8 +239,7 @@ __global__ void k_bands(const int64_t *__restrict__ u_off, int64_t n_tubes, cons
   const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (T >= n_tubes) return;
   const int U = (int)(u_off[T + 1] - u_off[T]);
-  const int Up = band_stride(U);
-  const int R = U > 0 ? (kBandDoubles / Up < U ? kBandDoubles / Up : U) : 1;
+  const int R = band_rows(U);
   int64_t w = band_off[T];
   for (int r0 = 0; r0 < U; r0 += R) items[w++] = make_int4((int)T, r0, (U - r0) < R ? (U - r0) : R, U);
 }
@@ -234,8 +249,7 @@ __global__ void k_band_count(const int64_t *__restrict__ u_off, int64_t n_tubes,
   const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (T >= n_tubes) return;
   const int64_t U = u_off[T + 1] - u_off[T];
-  const int64_t Up = band_stride((int)U);
-  const int64_t R = U > 0 ? (kBandDoubles / Up < U ? kBandDoubles / Up : U) : 1;
+  const int64_t R = band_rows((int)U);
   nb[T] = U > 0 ? (U + R - 1) / R : 0;
   usq[T] = U * U;
 }
@@ -303,7 +317,12 @@ __device__ __forceinline__ void in_all_lanes(double &v) { asm volatile("" : "+v"
 // registers are read with readlane from lanes that may be masked off below:
 // they are materialised in every lane before the branch (otherwise the
 // compiler may sink their loads into it, leaving inactive lanes stale).
-__device__ __forceinline__ void sweep_cols(double *acc, int rowbase, double xv, bool xok, int cs_reg,
+// TRI = false: square band, acc[rowbase + cs] with rowbase = (xs - r0) Up.
+// TRI = true: the tube's whole block as a packed upper triangle; the
+// product of row slot xs and column slot cs goes to (min, max), with
+// bx = tri_base(xs, U).
+template <bool TRI>
+__device__ __forceinline__ void sweep_cols(double *acc, int rowbase, int xs, int U, double xv, bool xok, int cs_reg,
                                            double cv_reg, int ncol) {
   in_all_lanes(cs_reg);
   in_all_lanes(cv_reg);
@@ -312,20 +331,27 @@ __device__ __forceinline__ void sweep_cols(double *acc, int rowbase, double xv, 
     for (int j = 0; j < ncol; j++) {
       const int cs = __builtin_amdgcn_readlane(cs_reg, j);
       const double cv = read_lane_f64(cv_reg, j);
-      atomicAdd(&acc[rowbase + cs], xv * cv);
+      int idx;
+      if (TRI) idx = xs <= cs ? rowbase + cs : tri_base(cs, U) + xs;
+      else idx = rowbase + cs;
+      atomicAdd(&acc[idx], xv * cv);
     }
   }
 }
 
-// both roles of one pair from registers (|l|, |r| <= kRegEntries)
-__device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, int R, const PairRegs &p) {
+// one pair from registers (|l|, |r| <= kRegEntries).  Square band: role 0
+// adds l (w r)^T, role 1 adds r (w l)^T to the rows in the band.  Packed
+// triangle (the whole block): role 0 only, each product at (min, max),
+// which sums both roles (B = S + S^T, diagonal doubled when written).
+template <bool TRI>
+__device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, int R, int U, const PairRegs &p) {
   const int lane = threadIdx.x & 63;
   // the pair is the wave's: its counts are uniform (scalar loop bounds)
   const int nl = __builtin_amdgcn_readfirstlane(pair_nl(p.m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(p.m));
   // column-side values scaled by the pair weight once
   const double lw0 = p.lv[0] * p.w, lw1 = p.lv[1] * p.w, rw0 = p.rv[0] * p.w, rw1 = p.rv[1] * p.w;
 #pragma unroll
-  for (int role = 0; role < 2; role++) {
+  for (int role = 0; role < (TRI ? 1 : 2); role++) {
     const int nrow = role ? nr : nl, ncol = role ? nl : nr;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
@@ -333,19 +359,22 @@ __device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, i
       const double xv = role ? p.rv[h] : p.lv[h];
       const bool xok = 64 * h + lane < nrow && xs >= r0 && xs < r0 + R;
       if (__ballot(xok) == 0) continue;
-      const int rowbase = (xs - r0) * Up;
-      sweep_cols(acc, rowbase, xv, xok, role ? p.ls[0] : p.rs[0], role ? lw0 : rw0, ncol < 64 ? ncol : 64);
-      if (ncol > 64) sweep_cols(acc, rowbase, xv, xok, role ? p.ls[1] : p.rs[1], role ? lw1 : rw1, ncol - 64);
+      const int rowbase = TRI ? tri_base(xs, U) : (xs - r0) * Up;
+      sweep_cols<TRI>(acc, rowbase, xs, U, xv, xok, role ? p.ls[0] : p.rs[0], role ? lw0 : rw0,
+                      ncol < 64 ? ncol : 64);
+      if (ncol > 64)
+        sweep_cols<TRI>(acc, rowbase, xs, U, xv, xok, role ? p.ls[1] : p.rs[1], role ? lw1 : rw1, ncol - 64);
     }
   }
 }
 
 // the same from memory, for pairs with a longer half-ray
-__device__ void pair_products_mem(double *acc, int Up, int r0, int R, const int4 m, double w,
+template <bool TRI>
+__device__ void pair_products_mem(double *acc, int Up, int r0, int R, int U, const int4 m, double w,
                                   const int32_t *__restrict__ slot, const double *__restrict__ val) {
   const int lane = threadIdx.x & 63;
   const int nl = __builtin_amdgcn_readfirstlane(pair_nl(m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(m));
-  for (int role = 0; role < 2; role++) {
+  for (int role = 0; role < (TRI ? 1 : 2); role++) {
     const int nrow = role ? nr : nl, ncol = role ? nl : nr;
     const int erow = role ? m.y : m.x, ecol = role ? m.x : m.y;
     for (int j0 = 0; j0 < nrow; j0 += 64) {
@@ -354,11 +383,11 @@ __device__ void pair_products_mem(double *acc, int Up, int r0, int R, const int4
       const double xv = val[ex];
       const bool xok = j0 + lane < nrow && xs >= r0 && xs < r0 + R;
       if (__ballot(xok) == 0) continue;
-      const int rowbase = (xs - r0) * Up;
+      const int rowbase = TRI ? tri_base(xs, U) : (xs - r0) * Up;
       for (int c0 = 0; c0 < ncol; c0 += 64) {
         const int ec = ecol + (c0 + lane < ncol ? c0 + lane : c0);
         const int cn = ncol - c0 < 64 ? ncol - c0 : 64;
-        sweep_cols(acc, rowbase, xv, xok, slot[ec], val[ec] * w, cn);
+        sweep_cols<TRI>(acc, rowbase, xs, U, xv, xok, slot[ec], val[ec] * w, cn);
       }
     }
   }
@@ -369,7 +398,13 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
   const int4 it = a.items[blockIdx.x];
   const int64_t T = it.x;
   const int r0 = it.y, R = it.z, U = it.w, Up = band_stride(U);
-  for (int j = threadIdx.x; j < R * Up; j += blockDim.x) acc[j] = 0.0;
+  // B = S + S^T with S = sum_p w_p l_p r_p^T.  A tube that is one band
+  // (band_rows) keeps its block as a packed upper triangle and adds each
+  // product of S once, at (min, max): half the LDS updates of the two
+  // products; a band of a larger block takes both products into full rows.
+  const bool tri = (R == U);
+  const int nacc = tri ? U * (U + 1) / 2 : R * Up;
+  for (int j = threadIdx.x; j < nacc; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   // wave-uniform (readfirstlane), so the pair loop, its metadata and the
   // column sweeps are scalar
@@ -402,8 +437,12 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
       load_entries(nxt, a.ent_slot, a.ent_val);
       PairRegs p = cur;
       p.w = weight(cur);
-      if (pair_nl(p.m) <= kRegEntries && pair_nr(p.m) <= kRegEntries) pair_products_reg(acc, Up, r0, R, p);
-      else long_pairs = true;
+      if (pair_nl(p.m) <= kRegEntries && pair_nr(p.m) <= kRegEntries) {
+        if (tri) pair_products_reg<true>(acc, Up, r0, R, U, p);
+        else pair_products_reg<false>(acc, Up, r0, R, U, p);
+      } else {
+        long_pairs = true;
+      }
       cur = nxt;
       nxt = far;
       k += nw;
@@ -415,14 +454,24 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
       PairRegs p;
       meta(k, p);
       if (pair_nl(p.m) > kRegEntries || pair_nr(p.m) > kRegEntries)
-        pair_products_mem(acc, Up, r0, R, p.m, weight(p), a.ent_slot, a.ent_val);
+        if (tri) pair_products_mem<true>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
+        else pair_products_mem<false>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
     }
   }
   __syncthreads();
   double *out = a.blk + a.blk_off[T] + (int64_t)r0 * U;
-  for (int j = threadIdx.x; j < R * U; j += blockDim.x) {
-    const int i = j / U, t = j - i * U;
-    out[j] = acc[i * Up + t];
+  if (tri) {
+    for (int j = threadIdx.x; j < U * U; j += blockDim.x) {
+      const int i = j / U, t = j - i * U;
+      const int lo = i < t ? i : t, hi = i < t ? t : i;
+      const double v = acc[tri_base(lo, U) + hi];
+      out[j] = i == t ? v + v : v;
+    }
+  } else {
+    for (int j = threadIdx.x; j < R * U; j += blockDim.x) {
+      const int i = j / U, t = j - i * U;
+      out[j] = acc[i * Up + t];
+    }
   }
 }
 
