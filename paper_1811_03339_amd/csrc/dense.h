@@ -90,6 +90,97 @@ __device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, in
   }
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// The same 64 x 64 product on the matrix cores, FP64: wavefront w owns the
+// 32 x 32 quarter (w >> 1, w & 1) as four 16 x 16 tiles, each accumulated
+// by v_mfma_f64_16x16x4f64 over 4-deep slices of the inner dimension
+// (A operand: lane l holds P[row l & 15][k + (l >> 4)]; B operand:
+// Q[column l & 15][k + (l >> 4)]).  Result: out[(2 a + b) 4 + i] is tile
+// (a, b) of the quarter at row 4 i + (l >> 4), column l & 15.
+__device__ __forceinline__ void tile_nt_mfma(const double *__restrict__ P, int64_t ldp, int prow,
+                                             const double *__restrict__ Q, int64_t ldq, int qrow, double (*sP)[33],
+                                             double (*sQ)[33], double out[16]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lc = tid & 31, lr = tid >> 5;
+  const int rm = 32 * (w >> 1) + (lane & 15), cm = 32 * (w & 1) + (lane & 15), kq = lane >> 4;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double pr[8], qr[8];
+  stage_load<double>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 32) {
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+      const int rr = lr + 8 * it;
+      sP[rr][lc] = rr < prow ? pr[it] : 0.0;
+      sQ[rr][lc] = rr < qrow ? qr[it] : 0.0;
+    }
+    __syncthreads();
+    if (kk + 32 < NB) stage_load<double>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
+#pragma unroll
+    for (int k4 = 0; k4 < 32; k4 += 4) {
+      const double a0 = sP[rm][k4 + kq], a1 = sP[rm + 16][k4 + kq];
+      const double b0 = sQ[cm][k4 + kq], b1 = sQ[cm + 16][k4 + kq];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) out[(2 * a + b) * 4 + i] = acc[a][b][i];
+}
+
+// 64 x 64 tile product for the factorization kernels: FP64 on the matrix
+// cores, FP32 on the vector units.  Value q of the 16 a thread holds sits at
+// tile row frag_row<T>(q), column frag_col<T>(q).
+__device__ __forceinline__ void tile_product(const double *__restrict__ P, int64_t ldp, int prow,
+                                             const double *__restrict__ Q, int64_t ldq, int qrow, double (*sP)[33],
+                                             double (*sQ)[33], double out[16]) {
+  tile_nt_mfma(P, ldp, prow, Q, ldq, qrow, sP, sQ, out);
+}
+
+__device__ __forceinline__ void tile_product(const float *__restrict__ P, int64_t ldp, int prow,
+                                             const float *__restrict__ Q, int64_t ldq, int qrow, float (*sP)[33],
+                                             float (*sQ)[33], float out[16]) {
+  float acc[4][4];
+  tile_nt<float>(P, ldp, prow, Q, ldq, qrow, sP, sQ, acc);
+#pragma unroll
+  for (int q = 0; q < 16; q++) out[q] = acc[q >> 2][q & 3];
+}
+
+template <class T>
+__device__ __forceinline__ int frag_row(int q);
+template <class T>
+__device__ __forceinline__ int frag_col(int q);
+template <>
+__device__ __forceinline__ int frag_row<double>(int q) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return 32 * (w >> 1) + 16 * (q >> 3) + 4 * (q & 3) + (lane >> 4);
+}
+template <>
+__device__ __forceinline__ int frag_col<double>(int q) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return 32 * (w & 1) + 16 * ((q >> 2) & 1) + (lane & 15);
+}
+template <>
+__device__ __forceinline__ int frag_row<float>(int q) {
+  return (threadIdx.x >> 4) + 16 * (q >> 2);
+}
+template <>
+__device__ __forceinline__ int frag_col<float>(int q) {
+  return (threadIdx.x & 15) + 16 * (q & 3);
+}
+
 // Element strides between the systems of a strided batch (grid.y = system):
 // matrix, diagonal-block inverses, vectors, per-block flags, tickets.  All
 // zero for a single system.

@@ -287,15 +287,12 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
   Linv += (int64_t)blockIdx.y * sL;
   const int64_t r0 = k0 + NB + 64 * (int64_t)blockIdx.x;
   const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
-  T acc[4][4];
-  tile_nt<T>(A + r0 * lda + k0, lda, rows, Linv, NB, NB, sP, sQ, acc);
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  T out[16];
+  tile_product(A + r0 * lda + k0, lda, rows, Linv, NB, NB, sP, sQ, out);
 #pragma unroll
-  for (int a = 0; a < 4; a++) {
-    const int rr = ty + 16 * a;
-    if (rr >= rows) continue;
-#pragma unroll
-    for (int b = 0; b < 4; b++) A[(r0 + rr) * lda + k0 + tx + 16 * b] = acc[a][b];
+  for (int q = 0; q < 16; q++) {
+    const int rr = frag_row<T>(q);
+    if (rr < rows) A[(r0 + rr) * lda + k0 + frag_col<T>(q)] = out[q];
   }
 }
 
@@ -308,11 +305,15 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
 template <class T>
 __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                               T *__restrict__ Linv_next, T *__restrict__ LinvT_next, int32_t *flag,
-                                              int64_t *aux, int64_t sA, int64_t sL) {
-  A += (int64_t)blockIdx.y * sA;
-  Linv_next += (int64_t)blockIdx.y * sL;
-  LinvT_next += (int64_t)blockIdx.y * sL;
-  aux += blockIdx.y;
+                                              int64_t *aux, int64_t sA, int64_t sL, int nz) {
+  // block b = tile * nz + system: the tiles (0, 0) of all systems, which
+  // carry the next diagonal factorizations, are dispatched first
+  const int64_t z = (int64_t)blockIdx.x % nz;
+  const int64_t x = (int64_t)blockIdx.x / nz;
+  A += z * sA;
+  Linv_next += z * sL;
+  LinvT_next += z * sL;
+  aux += z;
   struct Gemm {
     T sP[64][33], sQ[64][33];
   };
@@ -320,7 +321,6 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
     Gemm g;
     DiagSmem d;
   } sm;
-  const int64_t x = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= x) I++;
   while (I * (I + 1) / 2 > x) I--;
@@ -329,43 +329,34 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
   const int64_t ri = base + 64 * I, cj = base + 64 * J;
   const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
   const int qrow = (int)((n - cj) < 64 ? (n - cj) : 64);
-  T acc[4][4];
-  tile_nt<T>(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sm.g.sP, sm.g.sQ, acc);
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  T out[16];
+  tile_product(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sm.g.sP, sm.g.sQ, out);
   // this thread's 16 entries of C, read before any is used (indices clamped
   // into the matrix so the loads need no guard)
-  T cv[4][4];
+  T cv[16];
 #pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int64_t r = ri + ty + 16 * a, c = cj + tx + 16 * b;
-      cv[a][b] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
-    }
+  for (int q = 0; q < 16; q++) {
+    const int64_t r = ri + frag_row<T>(q), c = cj + frag_col<T>(q);
+    cv[q] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
+  }
   if (x == 0) {
     const int nb = prow;
 #pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const int r = ty + 16 * a, c = tx + 16 * b;
-        double v;
-        if (r < nb && c < nb) v = (c <= r) ? (double)cv[a][b] - (double)acc[a][b] : 0.0;
-        else v = (r == c) ? 1.0 : 0.0;
-        sm.d.L[r][c] = v;
-      }
+    for (int q = 0; q < 16; q++) {
+      const int r = frag_row<T>(q), c = frag_col<T>(q);
+      double v;
+      if (r < nb && c < nb) v = (c <= r) ? (double)cv[q] - (double)out[q] : 0.0;
+      else v = (r == c) ? 1.0 : 0.0;
+      sm.d.L[r][c] = v;
+    }
     __syncthreads();
     diag_factor<T>(sm.d, nb, A, lda, ri, Linv_next, LinvT_next, flag, aux);
     return;
   }
 #pragma unroll
-  for (int a = 0; a < 4; a++) {
-    const int64_t r = ri + ty + 16 * a;
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int64_t c = cj + tx + 16 * b;
-      if (r < n && c < n && c <= r) A[r * lda + c] = cv[a][b] - acc[a][b];
-    }
+  for (int q = 0; q < 16; q++) {
+    const int64_t r = ri + frag_row<T>(q), c = cj + frag_col<T>(q);
+    if (r < n && c < n && c <= r) A[r * lda + c] = cv[q] - out[q];
   }
 }
 
@@ -556,8 +547,8 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
     if (rest > 0) {
       k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, k0, Lk, sA, sL);
       const int64_t Tn = (rest + 63) / 64;
-      k_syrk<T><<<dim3((unsigned)(Tn * (Tn + 1) / 2), z), 256, 0, s>>>(
-          A, lda, n, k0, Lk + NB * NB, LinvT + (k0 / NB + 1) * NB * NB, m->flag, aux, sA, sL);
+      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2 * count), 256, 0, s>>>(
+          A, lda, n, k0, Lk + NB * NB, LinvT + (k0 / NB + 1) * NB * NB, m->flag, aux, sA, sL, count);
     }
   }
   timer_end(m, FPDE_STAGE_POTRF, t, s, count);
