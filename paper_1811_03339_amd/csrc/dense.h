@@ -92,6 +92,31 @@ __device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, in
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// acc += sP[rows][0..32) sQ[columns][0..32)^T for this wavefront's 32 x 32
+// quarter (rows rm, rm + 16, columns cm, cm + 16 of the lane's 16-groups;
+// kq = lane >> 4 picks the slice row of the 4-deep operands)
+__device__ __forceinline__ void mfma_chunk(const double (*sP)[33], const double (*sQ)[33], int rm, int cm, int kq,
+                                           f64x4 acc[2][2]) {
+#pragma unroll
+  for (int k4 = 0; k4 < 32; k4 += 4) {
+    const double a0 = sP[rm][k4 + kq], a1 = sP[rm + 16][k4 + kq];
+    const double b0 = sQ[cm][k4 + kq], b1 = sQ[cm + 16][k4 + kq];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void mfma_out(const f64x4 acc[2][2], double out[16]) {
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) out[(2 * a + b) * 4 + i] = acc[a][b][i];
+}
+
 // The same 64 x 64 product on the matrix cores, FP64: wavefront w owns the
 // 32 x 32 quarter (w >> 1, w & 1) as four 16 x 16 tiles, each accumulated
 // by v_mfma_f64_16x16x4f64 over 4-deep slices of the inner dimension
@@ -121,23 +146,10 @@ __device__ __forceinline__ void tile_nt_mfma(const double *__restrict__ P, int64
     }
     __syncthreads();
     if (kk + 32 < NB) stage_load<double>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
-#pragma unroll
-    for (int k4 = 0; k4 < 32; k4 += 4) {
-      const double a0 = sP[rm][k4 + kq], a1 = sP[rm + 16][k4 + kq];
-      const double b0 = sQ[cm][k4 + kq], b1 = sQ[cm + 16][k4 + kq];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
+    mfma_chunk(sP, sQ, rm, cm, kq, acc);
     __syncthreads();
   }
-#pragma unroll
-  for (int a = 0; a < 2; a++)
-#pragma unroll
-    for (int b = 0; b < 2; b++)
-#pragma unroll
-      for (int i = 0; i < 4; i++) out[(2 * a + b) * 4 + i] = acc[a][b][i];
+  mfma_out(acc, out);
 }
 
 // 64 x 64 tile product for the factorization kernels: FP64 on the matrix

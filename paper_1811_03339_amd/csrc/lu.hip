@@ -175,23 +175,25 @@ __global__ void __launch_bounds__(256) k_lu_diag(double *__restrict__ A, int64_t
   }
 }
 
-// acc = P Q over a 64-deep inner dimension: P is 64 x 64 (rows past `prow`
+// out = P Q over a 64-deep inner dimension: P is 64 x 64 (rows past `prow`
 // read as zero), Q is 64 x 64 row-major by inner index (columns past `qcol`
-// read as zero).  256 threads, 4 x 4 outputs each (rows ty + 16a, columns
-// tx + 16b), two 32-deep chunks staged through LDS as in tile_nt (Q
-// transposed on the way in), every load at a valid address.
+// read as zero).  Two 32-deep chunks staged through LDS as in tile_nt (Q
+// transposed on the way in, every load at a valid address), multiplied on
+// the matrix cores; value q of a thread's 16 sits at (frag_row<double>(q),
+// frag_col<double>(q)).
 __device__ __forceinline__ void tile_nn(const double *__restrict__ P, int64_t ldp, int prow,
                                         const double *__restrict__ Q, int64_t ldq, int qcol, double (*sP)[33],
-                                        double (*sQ)[33], double acc[4][4]) {
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
+                                        double (*sQ)[33], double out[16]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lc = tid & 31, lr = tid >> 5;  // P: rows lr + 8 it, column lc of a chunk
   const int qc = tid & 63, qr = tid >> 6;  // Q: column qc, inner rows qr + 4 it of a chunk
   const int qcc = qc < qcol ? qc : qcol - 1;
+  const int rm = 32 * (w >> 1) + (lane & 15), cm = 32 * (w & 1) + (lane & 15), kq = lane >> 4;
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) acc[a][b] = 0.0;
+    for (int b = 0; b < 2; b++) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   double pr[8], qv[8];
   auto load = [&](int kk) {
 #pragma unroll
@@ -212,20 +214,10 @@ __device__ __forceinline__ void tile_nn(const double *__restrict__ P, int64_t ld
     }
     __syncthreads();
     if (kk + 32 < NB) load(kk + 32);
-#pragma unroll 4
-    for (int k = 0; k < 32; k++) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; a++) av[a] = sP[ty + 16 * a][k];
-#pragma unroll
-      for (int b = 0; b < 4; b++) bv[b] = sQ[tx + 16 * b][k];
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-    }
+    mfma_chunk(sP, sQ, rm, cm, kq, acc);
     __syncthreads();
   }
+  mfma_out(acc, out);
 }
 
 // Workgroups [0, ns): L strips (rows k1 + 64 x, columns of panel k);
@@ -236,64 +228,103 @@ __global__ void __launch_bounds__(256) k_lu_panels(double *__restrict__ A, int64
   __shared__ double sP[64][33], sQ[64][33];
   const int64_t k1 = k0 + NB;
   const int x = blockIdx.x;
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double acc[4][4];
+  double out[16];
   if (x < ns) {
     const int64_t r0 = k1 + 64 * (int64_t)x;
     const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
-    tile_nt<double>(A + r0 * lda + k0, lda, rows, UinvT_k, NB, NB, sP, sQ, acc);
+    tile_product(A + r0 * lda + k0, lda, rows, UinvT_k, NB, NB, sP, sQ, out);
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int rr = ty + 16 * a;
-      if (rr >= rows) continue;
-#pragma unroll
-      for (int b = 0; b < 4; b++) A[(r0 + rr) * lda + k0 + tx + 16 * b] = acc[a][b];
+    for (int q = 0; q < 16; q++) {
+      const int rr = frag_row<double>(q);
+      if (rr < rows) A[(r0 + rr) * lda + k0 + frag_col<double>(q)] = out[q];
     }
   } else {
     const int64_t c0 = k1 + 64 * (int64_t)(x - ns);
     const int cols = (int)((n - c0) < 64 ? (n - c0) : 64);
-    tile_nn(Linv_k, NB, NB, A + k0 * lda + c0, lda, cols, sP, sQ, acc);
+    tile_nn(Linv_k, NB, NB, A + k0 * lda + c0, lda, cols, sP, sQ, out);
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int rr = ty + 16 * a;
-#pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const int cc = tx + 16 * b;
-        if (cc < cols) A[(k0 + rr) * lda + c0 + cc] = acc[a][b];
-      }
+    for (int q = 0; q < 16; q++) {
+      const int cc = frag_col<double>(q);
+      if (cc < cols) A[(k0 + frag_row<double>(q)) * lda + c0 + cc] = out[q];
     }
   }
 }
 
-// C_IJ -= L_Ik U_kJ over the trailing square from k1 = k0 + NB (T x T tiles)
+// Diagonal block at (k0, k0) from registers a (thread t: row t >> 2,
+// columns (t & 3) + 4 k; rows/columns past nb identity): factor it, write
+// L + U over A's block and inv(L), inv(L)^T, inv(U)^T of block k0 / 64.
+__device__ __forceinline__ void lu_diag_from(LuSmem &sm, double (&a)[16], int nb, double *__restrict__ A, int64_t lda,
+                                             int64_t k0, double *__restrict__ Linv, double *__restrict__ LinvT,
+                                             double *__restrict__ UinvT, int32_t *flag, int64_t *aux) {
+  const int tid = threadIdx.x, r = tid >> 2, cls = tid & 3;
+  double y[16], z[16];
+  const bool good = lu_block<true>(sm, a, y, z);
+  if (!good) {
+    set_flag(flag, FPDE_ESINGULAR);
+    atomicCAS((unsigned long long *)aux, ~0ull, (unsigned long long)k0);
+  }
+  const int64_t o = (k0 / NB) * NB * NB;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int c = cls + 4 * k;
+    if (r < nb && c < nb) A[(k0 + r) * lda + k0 + c] = a[k];
+    Linv[o + r * NB + c] = y[k];
+    LinvT[o + c * NB + r] = y[k];
+    UinvT[o + c * NB + r] = z[k];
+  }
+}
+
+// C_IJ -= L_Ik U_kJ over the trailing square from k1 = k0 + NB (T x T
+// tiles).  The workgroup of tile (0, 0) -- the next diagonal block -- then
+// factors that block at once (lu_diag_from), so the next step's diagonal
+// factorization runs beside the rest of this update.
 __global__ void __launch_bounds__(256) k_lu_update(double *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                   int T) {
-  __shared__ double sP[64][33], sQ[64][33];
+                                                   int T, double *__restrict__ Linv, double *__restrict__ LinvT,
+                                                   double *__restrict__ UinvT, int32_t *flag, int64_t *aux) {
+  struct Gemm {
+    double sP[64][33], sQ[64][33];
+  };
+  struct Diag {
+    double blk[64][65];
+    LuSmem lu;
+  };
+  __shared__ union {
+    Gemm g;
+    Diag d;
+  } sm;
   const int64_t k1 = k0 + NB;
   const int64_t x = blockIdx.x;
   const int64_t I = x / T, J = x - I * T;
   const int64_t ri = k1 + 64 * I, cj = k1 + 64 * J;
   const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
   const int qcol = (int)((n - cj) < 64 ? (n - cj) : 64);
-  double acc[4][4];
-  tile_nn(A + ri * lda + k0, lda, prow, A + k0 * lda + cj, lda, qcol, sP, sQ, acc);
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double cv[4][4];
+  double out[16];
+  tile_nn(A + ri * lda + k0, lda, prow, A + k0 * lda + cj, lda, qcol, sm.g.sP, sm.g.sQ, out);
+  double cv[16];
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+  for (int q = 0; q < 16; q++) {
+    const int64_t r = ri + frag_row<double>(q), c = cj + frag_col<double>(q);
+    cv[q] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
+  }
+  if (x == 0) {
+    const int nb = prow;
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int64_t r = ri + ty + 16 * a, c = cj + tx + 16 * b;
-      cv[a][b] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
+    for (int q = 0; q < 16; q++) sm.d.blk[frag_row<double>(q)][frag_col<double>(q)] = cv[q] - out[q];
+    __syncthreads();
+    const int tid = threadIdx.x, r = tid >> 2, cls = tid & 3;
+    double a[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const int c = cls + 4 * k;
+      a[k] = (r < nb && c < nb) ? sm.d.blk[r][c] : ((r == c) ? 1.0 : 0.0);
     }
+    lu_diag_from(sm.d.lu, a, nb, A, lda, k1, Linv, LinvT, UinvT, flag, aux);
+    return;
+  }
 #pragma unroll
-  for (int a = 0; a < 4; a++) {
-    const int64_t r = ri + ty + 16 * a;
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int64_t c = cj + tx + 16 * b;
-      if (r < n && c < n) A[r * lda + c] = cv[a][b] - acc[a][b];
-    }
+  for (int q = 0; q < 16; q++) {
+    const int64_t r = ri + frag_row<double>(q), c = cj + frag_col<double>(q);
+    if (r < n && c < n) A[r * lda + c] = cv[q] - out[q];
   }
 }
 
@@ -323,13 +354,16 @@ int lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t n, hipStream_t s) {
   const long t = timer_begin(m, s);
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     const int64_t o = (k0 / NB) * NB * NB;  // block k0 / 64 of each inverse set
-    // the kernel indexes the sets by its block itself: base pointers here
-    k_lu_diag<true><<<1, 256, 0, s>>>(A, lda, n, k0, Linv, LinvT, UinvT, m->flag, m->flag_aux);
+    // the first diagonal block on its own (the kernel indexes the sets by its
+    // block itself: base pointers); every later one is factored by tile
+    // (0, 0) of the preceding update
+    if (k0 == 0) k_lu_diag<true><<<1, 256, 0, s>>>(A, lda, n, k0, Linv, LinvT, UinvT, m->flag, m->flag_aux);
     const int64_t rest = n - k0 - NB;
     if (rest > 0) {
       const int ns = (int)((rest + 63) / 64);
       k_lu_panels<<<2 * ns, 256, 0, s>>>(A, lda, n, k0, ns, Linv + o, UinvT + o);
-      k_lu_update<<<(unsigned)((int64_t)ns * ns), 256, 0, s>>>(A, lda, n, k0, ns);
+      k_lu_update<<<(unsigned)((int64_t)ns * ns), 256, 0, s>>>(A, lda, n, k0, ns, Linv, LinvT, UinvT, m->flag,
+                                                                m->flag_aux);
     }
   }
   timer_end(m, FPDE_STAGE_LU, t, s);
