@@ -130,8 +130,12 @@ __device__ __forceinline__ double slope(const TetRec &R, int j, int i) {
 __device__ __forceinline__ double powr(double r, double e) { return r > 0.0 ? pow(r, e) : 0.0; }
 __device__ __forceinline__ double lnpowr(double r, double e) { return r > 0.0 ? log(r) * pow(r, e) : 0.0; }
 
+// The walk is a chain of dependent element-record loads per thread; the
+// value pass is asked for 4 wavefronts per SIMD (at most 128 VGPRs) so more
+// chains are in flight.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == W_VALUES ? 4 : 1)))
+k_walk(WalkArgs a) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.n) return;
   const int64_t h = a.h0 + k;
