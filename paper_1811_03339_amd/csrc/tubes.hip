@@ -18,9 +18,10 @@
 //   pass 1: one workgroup per (tube, band of block rows) reads the tube's
 //     entries once and adds every product l_p r_q into an LDS band of the
 //     block; the band goes to a scratch block in HBM.  The block is
-//     symmetric, B = S + S^T with S = sum w l r^T, so a tube whose packed
-//     upper triangle fits in LDS (|U_T| <= 200) is one band that adds each
-//     product of S once, at (min, max), and expands the triangle as it writes;
+//     symmetric, B = S + S^T with S = sum w l r^T, so a tube that fits in
+//     LDS whole (the square for |U_T| <= 141, else the packed upper
+//     triangle for |U_T| <= 200) is one band that adds each product of S
+//     once, at (min, max), and expands it as it writes;
 //   pass 2: one workgroup per row of A sums that row's slices of the tube
 //     blocks into an LDS row and writes the row once.
 // Each entry is read once per band of its tube (not once per node of its
@@ -317,13 +318,21 @@ __device__ __forceinline__ void in_all_lanes(double &v) { asm volatile("" : "+v"
 // registers are read with readlane from lanes that may be masked off below:
 // they are materialised in every lane before the branch (otherwise the
 // compiler may sink their loads into it, leaving inactive lanes stale).
-// TRI = false: square band, acc[rowbase + cs] with rowbase = (xs - r0) Up.
-// TRI = true: the tube's whole block as a packed upper triangle; the
-// product of row slot xs and column slot cs goes to (min, max), with
-// bx = tri_base(xs, U).
-template <bool TRI>
-__device__ __forceinline__ void sweep_cols(double *acc, int rowbase, int xs, int U, double xv, bool xok, int cs_reg,
-                                           double cv_reg, int ncol) {
+// Layouts of a pass-1 band in LDS:
+//   kBand2: rows [r0, r0 + R) of the block, row stride Up; both products of
+//           every pair (acc[rowbase + cs], rowbase = (xs - r0) Up);
+//   kSquare1: the whole block, row stride Up, each product once at
+//           (min, max) (lo Up + hi);
+//   kTri1: the whole block as a row-packed upper triangle, each product once
+//           at tri_base(lo, U) + hi (rowbase = tri_base(xs, U)).
+// With the odd stride, the rows of one column sweep fall in distinct bank
+// pairs in kBand2 and kSquare1 (stride Up when xs < cs, consecutive when
+// xs > cs).
+enum BandLayout { kBand2 = 0, kSquare1 = 1, kTri1 = 2 };
+
+template <int LAYOUT>
+__device__ __forceinline__ void sweep_cols(double *acc, int rowbase, int xs, int U, int Up, double xv, bool xok,
+                                           int cs_reg, double cv_reg, int ncol) {
   in_all_lanes(cs_reg);
   in_all_lanes(cv_reg);
   if (xok) {
@@ -332,18 +341,19 @@ __device__ __forceinline__ void sweep_cols(double *acc, int rowbase, int xs, int
       const int cs = __builtin_amdgcn_readlane(cs_reg, j);
       const double cv = read_lane_f64(cv_reg, j);
       int idx;
-      if (TRI) idx = xs <= cs ? rowbase + cs : tri_base(cs, U) + xs;
+      if (LAYOUT == kTri1) idx = xs <= cs ? rowbase + cs : tri_base(cs, U) + xs;
+      else if (LAYOUT == kSquare1) idx = xs <= cs ? rowbase + cs : cs * Up + xs;
       else idx = rowbase + cs;
       atomicAdd(&acc[idx], xv * cv);
     }
   }
 }
 
-// one pair from registers (|l|, |r| <= kRegEntries).  Square band: role 0
-// adds l (w r)^T, role 1 adds r (w l)^T to the rows in the band.  Packed
-// triangle (the whole block): role 0 only, each product at (min, max),
-// which sums both roles (B = S + S^T, diagonal doubled when written).
-template <bool TRI>
+// one pair from registers (|l|, |r| <= kRegEntries).  kBand2: role 0 adds
+// l (w r)^T, role 1 adds r (w l)^T to the rows in the band.  kSquare1,
+// kTri1 (the whole block): role 0 only, each product at (min, max), which
+// sums both roles (B = S + S^T, diagonal doubled when written).
+template <int LAYOUT>
 __device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, int R, int U, const PairRegs &p) {
   const int lane = threadIdx.x & 63;
   // the pair is the wave's: its counts are uniform (scalar loop bounds)
@@ -351,7 +361,7 @@ __device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, i
   // column-side values scaled by the pair weight once
   const double lw0 = p.lv[0] * p.w, lw1 = p.lv[1] * p.w, rw0 = p.rv[0] * p.w, rw1 = p.rv[1] * p.w;
 #pragma unroll
-  for (int role = 0; role < (TRI ? 1 : 2); role++) {
+  for (int role = 0; role < (LAYOUT == kBand2 ? 2 : 1); role++) {
     const int nrow = role ? nr : nl, ncol = role ? nl : nr;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
@@ -359,22 +369,23 @@ __device__ __forceinline__ void pair_products_reg(double *acc, int Up, int r0, i
       const double xv = role ? p.rv[h] : p.lv[h];
       const bool xok = 64 * h + lane < nrow && xs >= r0 && xs < r0 + R;
       if (__ballot(xok) == 0) continue;
-      const int rowbase = TRI ? tri_base(xs, U) : (xs - r0) * Up;
-      sweep_cols<TRI>(acc, rowbase, xs, U, xv, xok, role ? p.ls[0] : p.rs[0], role ? lw0 : rw0,
-                      ncol < 64 ? ncol : 64);
+      const int rowbase = LAYOUT == kTri1 ? tri_base(xs, U) : (xs - r0) * Up;
+      sweep_cols<LAYOUT>(acc, rowbase, xs, U, Up, xv, xok, role ? p.ls[0] : p.rs[0], role ? lw0 : rw0,
+                         ncol < 64 ? ncol : 64);
       if (ncol > 64)
-        sweep_cols<TRI>(acc, rowbase, xs, U, xv, xok, role ? p.ls[1] : p.rs[1], role ? lw1 : rw1, ncol - 64);
+        sweep_cols<LAYOUT>(acc, rowbase, xs, U, Up, xv, xok, role ? p.ls[1] : p.rs[1], role ? lw1 : rw1,
+                           ncol - 64);
     }
   }
 }
 
 // the same from memory, for pairs with a longer half-ray
-template <bool TRI>
+template <int LAYOUT>
 __device__ void pair_products_mem(double *acc, int Up, int r0, int R, int U, const int4 m, double w,
                                   const int32_t *__restrict__ slot, const double *__restrict__ val) {
   const int lane = threadIdx.x & 63;
   const int nl = __builtin_amdgcn_readfirstlane(pair_nl(m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(m));
-  for (int role = 0; role < (TRI ? 1 : 2); role++) {
+  for (int role = 0; role < (LAYOUT == kBand2 ? 2 : 1); role++) {
     const int nrow = role ? nr : nl, ncol = role ? nl : nr;
     const int erow = role ? m.y : m.x, ecol = role ? m.x : m.y;
     for (int j0 = 0; j0 < nrow; j0 += 64) {
@@ -383,11 +394,11 @@ __device__ void pair_products_mem(double *acc, int Up, int r0, int R, int U, con
       const double xv = val[ex];
       const bool xok = j0 + lane < nrow && xs >= r0 && xs < r0 + R;
       if (__ballot(xok) == 0) continue;
-      const int rowbase = TRI ? tri_base(xs, U) : (xs - r0) * Up;
+      const int rowbase = LAYOUT == kTri1 ? tri_base(xs, U) : (xs - r0) * Up;
       for (int c0 = 0; c0 < ncol; c0 += 64) {
         const int ec = ecol + (c0 + lane < ncol ? c0 + lane : c0);
         const int cn = ncol - c0 < 64 ? ncol - c0 : 64;
-        sweep_cols<TRI>(acc, rowbase, xs, U, xv, xok, slot[ec], val[ec] * w, cn);
+        sweep_cols<LAYOUT>(acc, rowbase, xs, U, Up, xv, xok, slot[ec], val[ec] * w, cn);
       }
     }
   }
@@ -399,11 +410,12 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
   const int64_t T = it.x;
   const int r0 = it.y, R = it.z, U = it.w, Up = band_stride(U);
   // B = S + S^T with S = sum_p w_p l_p r_p^T.  A tube that is one band
-  // (band_rows) keeps its block as a packed upper triangle and adds each
-  // product of S once, at (min, max): half the LDS updates of the two
-  // products; a band of a larger block takes both products into full rows.
-  const bool tri = (R == U);
-  const int nacc = tri ? U * (U + 1) / 2 : R * Up;
+  // (band_rows) adds each product of S once, at (min, max): half the LDS
+  // updates of the two products, in the full square when it fits (bank
+  // conflict free), else in the packed upper triangle; a band of a larger
+  // block takes both products into full rows.
+  const int layout = R != U ? kBand2 : (U * Up <= kBandDoubles ? kSquare1 : kTri1);
+  const int nacc = layout == kTri1 ? U * (U + 1) / 2 : R * Up;
   for (int j = threadIdx.x; j < nacc; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   // wave-uniform (readfirstlane), so the pair loop, its metadata and the
@@ -438,8 +450,9 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
       PairRegs p = cur;
       p.w = weight(cur);
       if (pair_nl(p.m) <= kRegEntries && pair_nr(p.m) <= kRegEntries) {
-        if (tri) pair_products_reg<true>(acc, Up, r0, R, U, p);
-        else pair_products_reg<false>(acc, Up, r0, R, U, p);
+        if (layout == kSquare1) pair_products_reg<kSquare1>(acc, Up, r0, R, U, p);
+        else if (layout == kTri1) pair_products_reg<kTri1>(acc, Up, r0, R, U, p);
+        else pair_products_reg<kBand2>(acc, Up, r0, R, U, p);
       } else {
         long_pairs = true;
       }
@@ -454,17 +467,18 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
       PairRegs p;
       meta(k, p);
       if (pair_nl(p.m) > kRegEntries || pair_nr(p.m) > kRegEntries)
-        if (tri) pair_products_mem<true>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
-        else pair_products_mem<false>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
+        if (layout == kSquare1) pair_products_mem<kSquare1>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
+        else if (layout == kTri1) pair_products_mem<kTri1>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
+        else pair_products_mem<kBand2>(acc, Up, r0, R, U, p.m, weight(p), a.ent_slot, a.ent_val);
     }
   }
   __syncthreads();
   double *out = a.blk + a.blk_off[T] + (int64_t)r0 * U;
-  if (tri) {
+  if (layout != kBand2) {
     for (int j = threadIdx.x; j < U * U; j += blockDim.x) {
       const int i = j / U, t = j - i * U;
       const int lo = i < t ? i : t, hi = i < t ? t : i;
-      const double v = acc[tri_base(lo, U) + hi];
+      const double v = acc[(layout == kTri1 ? tri_base(lo, U) : lo * Up) + hi];
       out[j] = i == t ? v + v : v;
     }
   } else {
