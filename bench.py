@@ -324,6 +324,8 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the template-CSR / CG section")
     ap.add_argument("--no-form", action="store_true", help="skip the general-form section")
     ap.add_argument("--no-plane", action="store_true", help="skip the two-dimensional section")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the one-step comparison that solves the systems one at a time")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -410,35 +412,52 @@ def main():
     # the same systems one at a time (assemble, factor, solve per system), one
     # step, outside the timed region: the per-system latency beside the
     # batched throughput
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    step_sequential()
-    e1.record()
-    torch.cuda.synchronize()
-    seq_ms = e0.elapsed_time(e1)
-    log(f"[bench] one step with the systems solved one at a time: {seq_ms:.2f} ms")
+    seq_ms = None
+    if not args.no_sequential:
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step_sequential()
+        e1.record()
+        torch.cuda.synchronize()
+        seq_ms = e0.elapsed_time(e1)
+        log(f"[bench] one step with the systems solved one at a time: {seq_ms:.2f} ms")
 
-    # Roofline of the dominant unit: one batched dense factorization of the
-    # step's systems (k_potrf_diag once, then k_panel + k_syrk per 64-column
-    # panel, grid.y = system), timed with one event pair per call on the
-    # launch stream (the stage count is in systems).  Algorithmic work
-    # systems x n^3 / 3 FP64 flops, on the vector units (no MFMA in FP64
-    # here): peak 78.6 TFLOP/s.
+    # Roofline of the dominant kernel of the step, by time per step: either
+    # the batched dense factorization (one unit = k_potrf_diag once, then
+    # k_panel + k_syrk per 64-column panel over all systems, timed with one
+    # event pair per call on the launch stream; algorithmic work
+    # systems x n^3 / 3 FP64 flops, on the matrix cores: FP64 peak
+    # 78.6 TFLOP/s) or the tube accumulation (one unit = one k_tube_accum
+    # launch, one per system; algorithmic work one multiply-add per entry
+    # product of S = sum w l r^T, B = S + S^T, i.e. 2 flops x pairs, on the
+    # vector ALUs with LDS atomics: FP64 peak 78.6 TFLOP/s).
     passes = len(cases)
     factorizations = stages["potrf"][1]
-    roofline = None
+    cand = []
     if factorizations:
         calls = factorizations / passes
         avg_s = stages["potrf"][0] / calls / 1e3
         fl = passes * n ** 3 / 3.0
         ach = fl / avg_s / 1e12
-        roofline = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-                    "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
-                    "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double> + "
-                              f"{syrk_flops(n)[1]} x (k_panel<double> + k_syrk<double>), grid.y = system",
-                    "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (vector FMA)"}
+        cand.append((stages["potrf"][0], {
+            "bound": "mfma", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
+            "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double> + "
+                      f"{syrk_flops(n)[1]} x (k_panel<double> + k_syrk<double>)",
+            "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (v_mfma_f64_16x16x4f64 tiles)"}))
+    if stages["accum"][1]:
+        avg_s = stages["accum"][0] / stages["accum"][1] / 1e3
+        fl = sum(2 * info[nq]["pairs"] for nq in RULES) / len(RULES)  # launches alternate the rules evenly
+        ach = fl / avg_s / 1e12
+        cand.append((stages["accum"][0], {
+            "bound": "alu", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("k_tube_accum"),
+            "kernel": "k_tube_accum (tube blocks, one launch per system)",
+            "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (vector FMA, LDS atomics)"}))
+    roofline = max(cand, key=lambda c: c[0])[1] if cand else None
+    other_roofline = min(cand, key=lambda c: c[0])[1] if len(cand) > 1 else None
     # every stage against its own bound (algorithmic work / measured time)
     stage_roof = {}
     if factorizations:
@@ -457,8 +476,9 @@ def main():
                                   "note": "K written once + every derivative entry read once"}
     if stages["accum"][1]:
         t = stages["accum"][0] / stages["accum"][1] / 1e3
-        fl = sum(4 * info[nq]["pairs"] for nq in RULES) / len(RULES)
-        stage_roof["accum"] = {"flops_per_launch": fl, "TFLOP/s": fl / t / 1e12, "frac_fp64": fl / t / FP64_PEAK}
+        fl = sum(2 * info[nq]["pairs"] for nq in RULES) / len(RULES)
+        stage_roof["accum"] = {"flops_per_launch": fl, "TFLOP/s": fl / t / 1e12, "frac_fp64": fl / t / FP64_PEAK,
+                               "note": "one multiply-add per entry product of S (B = S + S^T)"}
     if stages["walk"][1]:
         stage_roof["walk"] = {"paths_per_s": rays_per_step * args.steps / (stages["walk"][0] / 1e3)}
 
@@ -557,7 +577,7 @@ def main():
         },
         "assembly_solve_s_per_pass": ms_per_step / passes / 1e3,
         "sequential_ms_per_step": seq_ms,
-        "sequential_assembly_solve_s_per_system": seq_ms / passes / 1e3,
+        "sequential_assembly_solve_s_per_system": seq_ms / passes / 1e3 if seq_ms else None,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0},
         "walk_eval_paths_per_s": (rays_per_step * args.steps / (stages["walk"][0] / 1e3)
                                   if stages["walk"][0] > 0 else None),
@@ -566,6 +586,7 @@ def main():
         "template": template,
         "plan": {str(k): v for k, v in info.items()},
         "roofline": roofline,
+        "roofline_other": other_roofline,
         "stage_rooflines": stage_roof,
         "mixed": mixed,
         "sparse": sparse,
