@@ -206,14 +206,17 @@ constexpr int64_t kSpinLimit = int64_t(1) << 22;
 
 // Whole-wave poll of the flags of blocks c, c + dir, ..., (count <= 64 of
 // them).  Returns how many leading ones carry `epoch` (>= 1), or 0 after
-// kSpinLimit polls without flag c.
+// kSpinLimit polls without flag c.  The polls are relaxed device-scope loads
+// (no cache invalidation per poll); one acquire fence after the flags are
+// seen orders the reads of the published blocks after them.
 __device__ __forceinline__ int poll_run(const int *flags, int c, int dir, int count, int epoch) {
   const int lane = threadIdx.x & 63;
   const int k = lane < count ? lane : count - 1;
   for (int64_t it = 0; it <= kSpinLimit; it++) {
-    const int v = __hip_atomic_load(&flags[c + dir * k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const int v = __hip_atomic_load(&flags[c + dir * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long pub = __ballot(v == epoch);
     if (pub & 1ull) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const unsigned long long gap = ~pub;
       const int run = gap ? __ffsll((long long)gap) - 1 : 64;
       return run < count ? run : count;
