@@ -285,7 +285,9 @@ __device__ __forceinline__ double slope2(const TriRec &R, int j, int i) {
   return -(mcol2(R, 0, i) + mcol2(R, 1, i));
 }
 
-__device__ __forceinline__ double powr2(double r, double e) { return r > 0.0 ? pow(r, e) : 0.0; }
+// r^e for r > 0 as exp(e ln r) (e in (0, 1], r a chord length): a few ulp
+// from the correctly rounded power; the values need 1e-10, not bit equality
+__device__ __forceinline__ double powr2(double r, double e) { return r > 0.0 ? exp(e * log(r)) : 0.0; }
 
 template <int MODE>
 __global__ void __launch_bounds__(256) k2_walk(Walk2Args a) {

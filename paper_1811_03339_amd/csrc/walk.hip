@@ -127,8 +127,16 @@ __device__ __forceinline__ double slope(const TetRec &R, int j, int i) {
   return -((Mcol(R, 0, i) + Mcol(R, 1, i)) + Mcol(R, 2, i));
 }
 
-__device__ __forceinline__ double powr(double r, double e) { return r > 0.0 ? pow(r, e) : 0.0; }
-__device__ __forceinline__ double lnpowr(double r, double e) { return r > 0.0 ? log(r) * pow(r, e) : 0.0; }
+// r^e for r > 0 as exp(e ln r): the exponent e = 1 - gamma lies in (0, 1]
+// and r is a chord length (well inside (0, 1e3)), so |e ln r| is small and
+// the result is within a few ulp of the correctly rounded power -- the
+// values need 1e-10, not bit equality (only the element ids are bit-exact)
+__device__ __forceinline__ double powr(double r, double e) { return r > 0.0 ? exp(e * log(r)) : 0.0; }
+__device__ __forceinline__ double lnpowr(double r, double e) {
+  if (!(r > 0.0)) return 0.0;
+  const double l = log(r);
+  return l * exp(e * l);
+}
 
 // The walk is a chain of dependent element-record loads per thread; the
 // value pass is asked for 4 wavefronts per SIMD (at most 128 VGPRs) so more
