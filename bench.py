@@ -103,6 +103,77 @@ SEC3_BETAS = ((0.6, 0.7, 0.8), (0.8, 0.8, 0.8))
 SEC3_R = 0.5
 
 
+MIXED_LARGE = "sphere150k"
+
+
+def bench_mixed_large(F, torch, dev, reps=3):
+    """FP64 against the mixed arm where the factorization dominates: the
+    convex-hull mesh of 400 sphere points with ~150k elements (~25k
+    unknowns), 11-point rule, K = (1, 1, 1), alpha alternating 1.70 / 1.69
+    so that every pass re-walks.  Per pass and arm: assembly + solve (FP64:
+    FP64 matrix, Cholesky, two triangular solves; mixed: FP32 matrix, FP32
+    Cholesky, refinement with FP64 matrix-free residuals to 1e-8).  Median of
+    `reps` passes after one warm-up pass of each arm."""
+    from fpde_inputs import workload_mesh
+    mesh = workload_mesh(MIXED_LARGE)
+    g = F.Mesh(mesh.xyz, mesh.tet)
+    nq, K = 11, (1.0, 1.0, 1.0)
+    g.plan(nq)
+    n = g.n_dof
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    u64 = torch.empty_like(b)
+    u32 = torch.empty_like(b)
+    alphas = (1.70, 1.69)
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), r
+
+    def arm(precision, A, u):
+        ts, info = [], None
+        g.timing(True)
+        for k in range(reps + 1):
+            a = alphas[k % 2]
+            p = F.params(a, K, quad_points=nq, precision=precision, ir_tol=1e-8)
+
+            def run():
+                g.assemble(p, A, b)
+                return g.solve(p, A, b, u, info=(precision == F.FPDE_MIXED))
+            t, info = timed(run)
+            if k > 0:
+                ts.append(t)
+        g.timing(False)
+        st = g.stage_times()
+        return sorted(ts)[len(ts) // 2], info, st
+
+    A = torch.empty((n, n), dtype=torch.float64, device=dev)
+    t64, _, st64 = arm(F.FPDE_FP64, A, u64)
+    del A
+    torch.cuda.empty_cache()
+    A32 = torch.empty((n, n), dtype=torch.float32, device=dev)
+    tmx, info, stmx = arm(F.FPDE_MIXED, A32, u32)
+    del A32
+    torch.cuda.empty_cache()
+    err = float((u32 - u64).abs().max() / u64.abs().max())  # both at the last alpha of the sequence
+    fl = n ** 3 / 3.0
+
+    def tf(st):
+        return fl / (st["potrf"][0] / st["potrf"][1] / 1e3) / 1e12 if st["potrf"][1] else None
+    return {"workload": f"{MIXED_LARGE}: hull of 400 seeded points on the unit sphere + BCC lattice, {g.n_tet} "
+                        f"tets, {n} unknowns, 11-point rule, K = (1, 1, 1), alpha alternating 1.70 / 1.69",
+            "n_dof": n, "fp64_assembly_solve_s": t64 / 1e3, "mixed_assembly_solve_s": tmx / 1e3,
+            "speedup_vs_fp64": t64 / tmx, "rel_err_vs_fp64": err, "ir_iters": info.ir_iters,
+            "final_rel_residual": info.final_rel_residual,
+            "factorization_TFLOP_s": {"fp64": tf(st64), "fp32": tf(stmx)},
+            "factorization_ms": {"fp64": st64["potrf"][0] / max(st64["potrf"][1], 1),
+                                 "fp32": stmx["potrf"][0] / max(stmx["potrf"][1], 1)}}
+
+
 def bench_sec3(F, torch, dev, reps=4):
     """The divergence-form problem of Sec. 3 on the finest mesh of Table 3
     (ball |x| < 0.5, largest element diameter 0.0757): per pass the Sec. 3
@@ -324,6 +395,8 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the template-CSR / CG section")
     ap.add_argument("--no-form", action="store_true", help="skip the general-form section")
     ap.add_argument("--no-plane", action="store_true", help="skip the two-dimensional section")
+    ap.add_argument("--no-mixed-large", action="store_true",
+                    help="skip FP64 vs mixed at the 25k-unknown mesh")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-step comparison that solves the systems one at a time")
     ap.add_argument("--copy-calib", action="store_true",
@@ -535,6 +608,11 @@ def main():
         plane = bench_plane(F, torch)
         log(f"[bench] plane {plane}")
 
+    mixed_large = None
+    if not args.no_mixed_large:
+        mixed_large = bench_mixed_large(F, torch, dev)
+        log(f"[bench] mixed_large {mixed_large}")
+
     sec3 = None
     if not args.no_sec3:
         sec3 = bench_sec3(F, torch, dev)
@@ -589,6 +667,7 @@ def main():
         "roofline_other": other_roofline,
         "stage_rooflines": stage_roof,
         "mixed": mixed,
+        "mixed_large": mixed_large,
         "sparse": sparse,
         "form": form,
         "plane": plane,

@@ -34,13 +34,13 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-// 64 x 64 tile product acc = P Q^T over a 64-deep inner dimension, P and Q
-// given as row pointers with leading dimensions; rows past `prow`/`qrow`
-// (>= 1) read as zero.  256 threads, 4 x 4 outputs each (rows ty + 16a,
-// cols tx + 16b).  The two 32-deep chunks are staged through LDS; the second
-// chunk's global loads are issued before the first chunk's arithmetic, and
-// every load reads a valid address (rows clamped, then zeroed), so a
-// thread's loads are all in flight together.
+// Staging of the 64 x 64 tile products P Q^T over a 64-deep inner dimension
+// (P and Q given as row pointers with leading dimensions; rows past
+// `prow`/`qrow` (>= 1) read as zero): 256 threads load rows lr + 8 it,
+// column lc of a 32-deep chunk.  The second chunk's global loads are issued
+// before the first chunk's arithmetic, and every load reads a valid address
+// (rows clamped, then zeroed), so a thread's loads are all in flight
+// together.
 template <class T>
 __device__ __forceinline__ void stage_load(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
                                            int64_t ldq, int qrow, int kk, int lr, int lc, T (&pr)[8], T (&qr)[8]) {
@@ -52,43 +52,6 @@ __device__ __forceinline__ void stage_load(const T *__restrict__ P, int64_t ldp,
   }
 }
 
-template <class T>
-__device__ __forceinline__ void tile_nt(const T *__restrict__ P, int64_t ldp, int prow, const T *__restrict__ Q,
-                                        int64_t ldq, int qrow, T (*sP)[33], T (*sQ)[33], T acc[4][4]) {
-  const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
-  const int lc = tid & 31, lr = tid >> 5;  // this thread stages rows lr + 8 it, column lc of a chunk
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) acc[a][b] = (T)0;
-  T pr[8], qr[8];
-  stage_load<T>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
-#pragma unroll
-  for (int kk = 0; kk < NB; kk += 32) {
-#pragma unroll
-    for (int it = 0; it < 8; it++) {
-      const int rr = lr + 8 * it;
-      sP[rr][lc] = rr < prow ? pr[it] : (T)0;
-      sQ[rr][lc] = rr < qrow ? qr[it] : (T)0;
-    }
-    __syncthreads();
-    if (kk + 32 < NB) stage_load<T>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
-#pragma unroll 4
-    for (int k = 0; k < 32; k++) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; a++) av[a] = sP[ty + 16 * a][k];
-#pragma unroll
-      for (int b = 0; b < 4; b++) bv[b] = sQ[tx + 16 * b][k];
-#pragma unroll
-      for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-    }
-    __syncthreads();
-  }
-}
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -152,22 +115,60 @@ __device__ __forceinline__ void tile_nt_mfma(const double *__restrict__ P, int64
   mfma_out(acc, out);
 }
 
-// 64 x 64 tile product for the factorization kernels: FP64 on the matrix
-// cores, FP32 on the vector units.  Value q of the 16 a thread holds sits at
-// tile row frag_row<T>(q), column frag_col<T>(q).
+// 64 x 64 tile product for the factorization kernels, on the matrix cores
+// in FP64 and in FP32.  Value q of the 16 a thread holds sits at tile row
+// frag_row<T>(q), column frag_col<T>(q).
 __device__ __forceinline__ void tile_product(const double *__restrict__ P, int64_t ldp, int prow,
                                              const double *__restrict__ Q, int64_t ldq, int qrow, double (*sP)[33],
                                              double (*sQ)[33], double out[16]) {
   tile_nt_mfma(P, ldp, prow, Q, ldq, qrow, sP, sQ, out);
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 on the matrix cores (v_mfma_f32_16x16x4f32), same quarters and
+// operand layout as the FP64 product; this instruction's result is blocked:
+// lane l holds rows 4 (l >> 4) + i, column l & 15 of each 16 x 16 tile.
 __device__ __forceinline__ void tile_product(const float *__restrict__ P, int64_t ldp, int prow,
                                              const float *__restrict__ Q, int64_t ldq, int qrow, float (*sP)[33],
                                              float (*sQ)[33], float out[16]) {
-  float acc[4][4];
-  tile_nt<float>(P, ldp, prow, Q, ldq, qrow, sP, sQ, acc);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lc = tid & 31, lr = tid >> 5;
+  const int rm = 32 * (w >> 1) + (lane & 15), cm = 32 * (w & 1) + (lane & 15), kq = lane >> 4;
+  f32x4 acc[2][2];
 #pragma unroll
-  for (int q = 0; q < 16; q++) out[q] = acc[q >> 2][q & 3];
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float pr[8], qr[8];
+  stage_load<float>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 32) {
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+      const int rr = lr + 8 * it;
+      sP[rr][lc] = rr < prow ? pr[it] : 0.f;
+      sQ[rr][lc] = rr < qrow ? qr[it] : 0.f;
+    }
+    __syncthreads();
+    if (kk + 32 < NB) stage_load<float>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
+#pragma unroll
+    for (int k4 = 0; k4 < 32; k4 += 4) {
+      const float a0 = sP[rm][k4 + kq], a1 = sP[rm + 16][k4 + kq];
+      const float b0 = sQ[cm][k4 + kq], b1 = sQ[cm + 16][k4 + kq];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) out[(2 * a + b) * 4 + i] = acc[a][b][i];
 }
 
 template <class T>
@@ -186,11 +187,13 @@ __device__ __forceinline__ int frag_col<double>(int q) {
 }
 template <>
 __device__ __forceinline__ int frag_row<float>(int q) {
-  return (threadIdx.x >> 4) + 16 * (q >> 2);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return 32 * (w >> 1) + 16 * (q >> 3) + 4 * (lane >> 4) + (q & 3);
 }
 template <>
 __device__ __forceinline__ int frag_col<float>(int q) {
-  return (threadIdx.x & 15) + 16 * (q & 3);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return 32 * (w & 1) + 16 * ((q >> 2) & 1) + (lane & 15);
 }
 
 // Element strides between the systems of a strided batch (grid.y = system):

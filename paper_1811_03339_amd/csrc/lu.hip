@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) k_lu_diag(double *__restrict__ A, int64_t
 
 // out = P Q over a 64-deep inner dimension: P is 64 x 64 (rows past `prow`
 // read as zero), Q is 64 x 64 row-major by inner index (columns past `qcol`
-// read as zero).  Two 32-deep chunks staged through LDS as in tile_nt (Q
+// read as zero).  Two 32-deep chunks staged through LDS as in tile_product (Q
 // transposed on the way in, every load at a valid address), multiplied on
 // the matrix cores; value q of a thread's 16 sits at (frag_row<double>(q),
 // frag_col<double>(q)).
