@@ -86,6 +86,7 @@ __device__ __forceinline__ void mfma_out(const f64x4 acc[2][2], double out[16]) 
 // (A operand: lane l holds P[row l & 15][k + (l >> 4)]; B operand:
 // Q[column l & 15][k + (l >> 4)]).  Result: out[(2 a + b) 4 + i] is tile
 // (a, b) of the quarter at row 4 i + (l >> 4), column l & 15.
+template <int KD = NB>
 __device__ __forceinline__ void tile_nt_mfma(const double *__restrict__ P, int64_t ldp, int prow,
                                              const double *__restrict__ Q, int64_t ldq, int qrow, double (*sP)[33],
                                              double (*sQ)[33], double out[16]) {
@@ -100,7 +101,7 @@ __device__ __forceinline__ void tile_nt_mfma(const double *__restrict__ P, int64
   double pr[8], qr[8];
   stage_load<double>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
 #pragma unroll
-  for (int kk = 0; kk < NB; kk += 32) {
+  for (int kk = 0; kk < KD; kk += 32) {
 #pragma unroll
     for (int it = 0; it < 8; it++) {
       const int rr = lr + 8 * it;
@@ -108,20 +109,21 @@ __device__ __forceinline__ void tile_nt_mfma(const double *__restrict__ P, int64
       sQ[rr][lc] = rr < qrow ? qr[it] : 0.0;
     }
     __syncthreads();
-    if (kk + 32 < NB) stage_load<double>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
+    if (kk + 32 < KD) stage_load<double>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
     mfma_chunk(sP, sQ, rm, cm, kq, acc);
     __syncthreads();
   }
   mfma_out(acc, out);
 }
 
-// 64 x 64 tile product for the factorization kernels, on the matrix cores
-// in FP64 and in FP32.  Value q of the 16 a thread holds sits at tile row
+// 64 x 64 tile product over a KD-deep inner dimension (a multiple of 32)
+// for the factorization kernels, on the matrix cores in FP64 and in FP32.  Value q of the 16 a thread holds sits at tile row
 // frag_row<T>(q), column frag_col<T>(q).
+template <int KD = NB>
 __device__ __forceinline__ void tile_product(const double *__restrict__ P, int64_t ldp, int prow,
                                              const double *__restrict__ Q, int64_t ldq, int qrow, double (*sP)[33],
                                              double (*sQ)[33], double out[16]) {
-  tile_nt_mfma(P, ldp, prow, Q, ldq, qrow, sP, sQ, out);
+  tile_nt_mfma<KD>(P, ldp, prow, Q, ldq, qrow, sP, sQ, out);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -129,6 +131,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // FP32 on the matrix cores (v_mfma_f32_16x16x4f32), same quarters and
 // operand layout as the FP64 product; this instruction's result is blocked:
 // lane l holds rows 4 (l >> 4) + i, column l & 15 of each 16 x 16 tile.
+template <int KD = NB>
 __device__ __forceinline__ void tile_product(const float *__restrict__ P, int64_t ldp, int prow,
                                              const float *__restrict__ Q, int64_t ldq, int qrow, float (*sP)[33],
                                              float (*sQ)[33], float out[16]) {
@@ -143,7 +146,7 @@ __device__ __forceinline__ void tile_product(const float *__restrict__ P, int64_
   float pr[8], qr[8];
   stage_load<float>(P, ldp, prow, Q, ldq, qrow, 0, lr, lc, pr, qr);
 #pragma unroll
-  for (int kk = 0; kk < NB; kk += 32) {
+  for (int kk = 0; kk < KD; kk += 32) {
 #pragma unroll
     for (int it = 0; it < 8; it++) {
       const int rr = lr + 8 * it;
@@ -151,7 +154,7 @@ __device__ __forceinline__ void tile_product(const float *__restrict__ P, int64_
       sQ[rr][lc] = rr < qrow ? qr[it] : 0.f;
     }
     __syncthreads();
-    if (kk + 32 < NB) stage_load<float>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
+    if (kk + 32 < KD) stage_load<float>(P, ldp, prow, Q, ldq, qrow, kk + 32, lr, lc, pr, qr);
 #pragma unroll
     for (int k4 = 0; k4 < 32; k4 += 4) {
       const float a0 = sP[rm][k4 + kq], a1 = sP[rm + 16][k4 + kq];

@@ -297,15 +297,16 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
 }
 
 // trailing update C[I,J] -= X_I X_J^T over lower tiles I >= J of the matrix
-// starting at row/column k1 = k0 + NB; X = columns [k0, k0+NB).  The
-// workgroup of tile (0, 0) -- the next diagonal block -- keeps its updated
-// tile in LDS and factors it at once (diag_factor), so the next panel's
-// diagonal factorization runs beside the rest of this update instead of
-// after it.
-template <class T>
+// starting at row/column k1 = k0 + KD; X = columns [k0, k0 + KD) (one panel,
+// KD = 64, or two consecutive panels, KD = 128).  colonly: only the tiles
+// (I, 0), the block column at k1.  The workgroup of tile (0, 0) -- the next
+// diagonal block -- keeps its updated tile in LDS and factors it at once
+// (diag_factor), so the next panel's diagonal factorization runs beside the
+// rest of this update instead of after it.
+template <class T, int KD>
 __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                               T *__restrict__ Linv_next, T *__restrict__ LinvT_next, int32_t *flag,
-                                              int64_t *aux, int64_t sA, int64_t sL, int nz) {
+                                              int64_t *aux, int64_t sA, int64_t sL, int nz, int colonly) {
   // block b = tile * nz + system: the tiles (0, 0) of all systems, which
   // carry the next diagonal factorizations, are dispatched first
   const int64_t z = (int64_t)blockIdx.x % nz;
@@ -321,16 +322,19 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
     Gemm g;
     DiagSmem d;
   } sm;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= x) I++;
-  while (I * (I + 1) / 2 > x) I--;
-  const int64_t J = x - I * (I + 1) / 2;
-  const int64_t base = k0 + NB;
+  int64_t I = x, J = 0;
+  if (!colonly) {
+    I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= x) I++;
+    while (I * (I + 1) / 2 > x) I--;
+    J = x - I * (I + 1) / 2;
+  }
+  const int64_t base = k0 + KD;
   const int64_t ri = base + 64 * I, cj = base + 64 * J;
   const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
   const int qrow = (int)((n - cj) < 64 ? (n - cj) : 64);
   T out[16];
-  tile_product(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sm.g.sP, sm.g.sQ, out);
+  tile_product<KD>(A + ri * lda + k0, lda, prow, A + cj * lda + k0, lda, qrow, sm.g.sP, sm.g.sQ, out);
   // this thread's 16 entries of C, read before any is used (indices clamped
   // into the matrix so the loads need no guard)
   T cv[16];
@@ -541,15 +545,28 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
   T *LinvT = Linv + nbk * NB * NB;
   const unsigned z = (unsigned)count;
   k_potrf_diag<T><<<dim3(1, z), 256, 0, s>>>(A, lda, n, 0, Linv, LinvT, m->flag, aux, sA, sL);
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    T *Lk = Linv + (k0 / NB) * NB * NB;
+  // panels in pairs: panel k0; the block column at k1 = k0 + 64 updated by
+  // it alone (its tile (0, 0) factors diagonal block k1); panel k1; then the
+  // trailing matrix from k1 + 64 updated once by both panels (128 columns):
+  // the trailing matrix is read and written once per two panels
+  for (int64_t k0 = 0; k0 < n; k0 += 2 * NB) {
     const int64_t rest = n - k0 - NB;
-    if (rest > 0) {
-      k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, k0, Lk, sA, sL);
-      const int64_t Tn = (rest + 63) / 64;
-      k_syrk<T><<<(unsigned)(Tn * (Tn + 1) / 2 * count), 256, 0, s>>>(
-          A, lda, n, k0, Lk + NB * NB, LinvT + (k0 / NB + 1) * NB * NB, m->flag, aux, sA, sL, count);
+    if (rest <= 0) break;
+    T *Lk = Linv + (k0 / NB) * NB * NB;
+    k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, k0, Lk, sA, sL);
+    const int64_t Tn = (rest + 63) / 64;
+    T *Lk1 = Lk + NB * NB, *LkT1 = LinvT + (k0 / NB + 1) * NB * NB;
+    if (rest <= NB) {  // one block column left
+      k_syrk<T, NB><<<(unsigned)(Tn * (Tn + 1) / 2 * count), 256, 0, s>>>(A, lda, n, k0, Lk1, LkT1, m->flag,
+                                                                              aux, sA, sL, count, 0);
+      break;
     }
+    k_syrk<T, NB><<<(unsigned)(Tn * count), 256, 0, s>>>(A, lda, n, k0, Lk1, LkT1, m->flag, aux, sA, sL, count, 1);
+    const int64_t k1 = k0 + NB, rest1 = rest - NB;
+    k_panel<T><<<dim3(nblk(rest1, 64), z), 256, 0, s>>>(A, lda, n, k1, Lk1, sA, sL);
+    const int64_t T1 = (rest1 + 63) / 64;
+    k_syrk<T, 2 * NB><<<(unsigned)(T1 * (T1 + 1) / 2 * count), 256, 0, s>>>(
+        A, lda, n, k0, Lk1 + NB * NB, LkT1 + NB * NB, m->flag, aux, sA, sL, count, 0);
   }
   timer_end(m, FPDE_STAGE_POTRF, t, s, count);
   FPDE_HIP(hipGetLastError());
