@@ -171,7 +171,9 @@ def bench_mixed_large(F, torch, dev, reps=3):
             "final_rel_residual": info.final_rel_residual,
             "factorization_TFLOP_s": {"fp64": tf(st64), "fp32": tf(stmx)},
             "factorization_ms": {"fp64": st64["potrf"][0] / max(st64["potrf"][1], 1),
-                                 "fp32": stmx["potrf"][0] / max(stmx["potrf"][1], 1)}}
+                                 "fp32": stmx["potrf"][0] / max(stmx["potrf"][1], 1)},
+            "stages_ms_per_pass": {"fp64": {k: v[0] / (reps + 1) for k, v in st64.items() if v[1] > 0},
+                                   "mixed": {k: v[0] / (reps + 1) for k, v in stmx.items() if v[1] > 0}}}
 
 
 def bench_sec3(F, torch, dev, reps=4):

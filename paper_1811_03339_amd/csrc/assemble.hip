@@ -19,6 +19,7 @@ struct ContractArgs {
   const int64_t *row_off;
   const int4 *meta;       // per incidence: entry, partner offset, partner length << 2 | axis, partner
   const double *w;        // per incidence: Gauss weight w_g
+  const double *wv;       // per incidence: w_g times its entry's value (matrix-free product)
   const int32_t *ent_dof;
   const double *ent_val;
   int64_t ndof, lda;
@@ -100,6 +101,14 @@ __global__ void __launch_bounds__(256) k_ray_dot(const int64_t *__restrict__ off
   if (gl == 0) d[h] = s;
 }
 
+// wv[p] = w_g value_e for incidence p (entry e = meta[p].x): the entry
+// values in the node -> entry order, so the product streams them
+__global__ void k_inc_wv(const int4 *__restrict__ meta, const double *__restrict__ w,
+                         const double *__restrict__ ent_val, int64_t n, double *__restrict__ wv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) wv[p] = w[p] * ent_val[meta[p].x];
+}
+
 // y_j = sum over entries e on node j of W(h_e) value_e d[partner(h_e)];
 // one wavefront per row, lanes stride over the row's entries
 __global__ void __launch_bounds__(256) k_apply_rows(ContractArgs c, const double *__restrict__ d,
@@ -110,7 +119,7 @@ __global__ void __launch_bounds__(256) k_apply_rows(ContractArgs c, const double
   double s = 0.0;
   for (int64_t p = c.row_off[j] + lane; p < c.row_off[j + 1]; p += 64) {
     const int4 mt = c.meta[p];
-    s += c.w[p] * c.KC(mt.z & 3) * c.ent_val[mt.x] * d[mt.w];
+    s += c.wv[p] * c.KC(mt.z & 3) * d[mt.w];
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) y[j] = s;
@@ -194,8 +203,14 @@ int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_g
 // y = K x from the stored derivative vectors (plan + values for p->alpha)
 int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
                   hipStream_t s) {
+  if (!P->inc_wv) FPDE_TRY(dalloc(&P->inc_wv, P->n_ent > 0 ? P->n_ent : 1));
   ContractArgs c = contract_args(m, *P, p, 0);
+  c.wv = P->inc_wv;
   const long t = timer_begin(m, s);
+  if (P->inc_wv_version != P->values_version) {
+    if (P->n_ent > 0) k_inc_wv<<<nblk(P->n_ent), 256, 0, s>>>(P->inc_meta, P->inc_w, P->ent_val, P->n_ent, P->inc_wv);
+    P->inc_wv_version = P->values_version;
+  }
   k_ray_dot<<<nblk(16 * P->n_half), 256, 0, s>>>(P->off, P->ent_dof, P->ent_val, x, P->n_half, dscratch);
   k_apply_rows<<<nblk(m->ndof, 4), 256, 0, s>>>(c, dscratch, y);
   timer_end(m, FPDE_STAGE_APPLY, t, s);

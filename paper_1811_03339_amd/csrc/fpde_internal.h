@@ -76,6 +76,10 @@ struct Plan {
   // partner half-ray} and the quadrature weight w_g of its Gauss point
   int4 *inc_meta = nullptr;
   double *inc_w = nullptr;
+  // per incidence: w_g times its entry's value (first value set), built by
+  // the matrix-free product when the values changed since (versions)
+  double *inc_wv = nullptr;
+  int64_t values_version = 0, inc_wv_version = -1;
   double *adj = nullptr;      // 4 n_half scratch for the adjoint dots
   int64_t pairs = 0;          // sum over (g, i) of |L| |R|
   int64_t max_ent = 0;        // largest entry count of one half-ray

@@ -427,7 +427,7 @@ static void launch_walk(const WalkArgs &a, hipStream_t s) {
 
 void free_plan(Plan &P) {
   dfree(P.off); dfree(P.ent_dof); dfree(P.ent_ray); dfree(P.ent_val); dfree(P.ent_val2); dfree(P.row_off); dfree(P.inc);
-  dfree(P.adj); dfree(P.inc_meta); dfree(P.inc_w);
+  dfree(P.adj); dfree(P.inc_meta); dfree(P.inc_w); dfree(P.inc_wv);
   free_tubes(P.tubes);
   P = Plan();
 }
@@ -580,6 +580,7 @@ int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t
     return FPDE_EHIP;
   }
   for (int i = i0; i <= i1; i++) cache[i] = gamma[i];
+  if (slot == 0) P->values_version++;
   return FPDE_OK;
 }
 
