@@ -227,7 +227,7 @@ def bench_sec3(F, torch, dev, reps=4):
         "n_dof": n,
         "pass_ms": sorted(ts)[len(ts) // 2],
         "stages_ms_per_pass": {k: v[0] / reps for k, v in st.items() if v[1] > 0},
-        "lu": {"bound": "alu", "flops_per_factorization": fl, "ms": lu_t * 1e3,
+        "lu": {"bound": "mfma", "flops_per_factorization": fl, "ms": lu_t * 1e3,
                "achieved": fl / lu_t / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
                "frac": fl / lu_t / FP64_PEAK},
         "max_nodal_error": float(np.abs(uh - exact).max()),

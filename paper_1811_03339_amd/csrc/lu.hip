@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(256) k_lu_diag(double *__restrict__ A, int64_t
 // transposed on the way in, every load at a valid address), multiplied on
 // the matrix cores; value q of a thread's 16 sits at (frag_row<double>(q),
 // frag_col<double>(q)).
+template <int KD = NB>
 __device__ __forceinline__ void tile_nn(const double *__restrict__ P, int64_t ldp, int prow,
                                         const double *__restrict__ Q, int64_t ldq, int qcol, double (*sP)[33],
                                         double (*sQ)[33], double out[16]) {
@@ -205,7 +206,7 @@ __device__ __forceinline__ void tile_nn(const double *__restrict__ P, int64_t ld
   };
   load(0);
 #pragma unroll
-  for (int kk = 0; kk < NB; kk += 32) {
+  for (int kk = 0; kk < KD; kk += 32) {
 #pragma unroll
     for (int it = 0; it < 8; it++) {
       const int rr = lr + 8 * it;
@@ -213,7 +214,7 @@ __device__ __forceinline__ void tile_nn(const double *__restrict__ P, int64_t ld
       sQ[qc][qr + 4 * it] = qc < qcol ? qv[it] : 0.0;
     }
     __syncthreads();
-    if (kk + 32 < NB) load(kk + 32);
+    if (kk + 32 < KD) load(kk + 32);
     mfma_chunk(sP, sQ, rm, cm, kq, acc);
     __syncthreads();
   }
@@ -274,13 +275,18 @@ __device__ __forceinline__ void lu_diag_from(LuSmem &sm, double (&a)[16], int nb
   }
 }
 
-// C_IJ -= L_Ik U_kJ over the trailing square from k1 = k0 + NB (T x T
-// tiles).  The workgroup of tile (0, 0) -- the next diagonal block -- then
-// factors that block at once (lu_diag_from), so the next step's diagonal
+// C_IJ -= L_I,K U_K,J over the trailing square from k1 = k0 + KD (T x T
+// tiles), K = columns of L / rows of U [k0, k0 + KD): one panel (KD = 64) or
+// two consecutive panels (KD = 128).  cross: only the block column and the
+// block row at k1 (tiles (x, 0), x < T, then (0, x - T + 1): 2T - 1 tiles).
+// The workgroup of tile (0, 0) -- the next diagonal block -- then factors
+// that block at once (lu_diag_from), so the next step's diagonal
 // factorization runs beside the rest of this update.
+template <int KD>
 __global__ void __launch_bounds__(256) k_lu_update(double *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                                    int T, double *__restrict__ Linv, double *__restrict__ LinvT,
-                                                   double *__restrict__ UinvT, int32_t *flag, int64_t *aux) {
+                                                   double *__restrict__ UinvT, int32_t *flag, int64_t *aux,
+                                                   int cross) {
   struct Gemm {
     double sP[64][33], sQ[64][33];
   };
@@ -292,14 +298,21 @@ __global__ void __launch_bounds__(256) k_lu_update(double *__restrict__ A, int64
     Gemm g;
     Diag d;
   } sm;
-  const int64_t k1 = k0 + NB;
+  const int64_t k1 = k0 + KD;
   const int64_t x = blockIdx.x;
-  const int64_t I = x / T, J = x - I * T;
+  int64_t I, J;
+  if (cross) {
+    I = x < T ? x : 0;
+    J = x < T ? 0 : x - T + 1;
+  } else {
+    I = x / T;
+    J = x - I * T;
+  }
   const int64_t ri = k1 + 64 * I, cj = k1 + 64 * J;
   const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
   const int qcol = (int)((n - cj) < 64 ? (n - cj) : 64);
   double out[16];
-  tile_nn(A + ri * lda + k0, lda, prow, A + k0 * lda + cj, lda, qcol, sm.g.sP, sm.g.sQ, out);
+  tile_nn<KD>(A + ri * lda + k0, lda, prow, A + k0 * lda + cj, lda, qcol, sm.g.sP, sm.g.sQ, out);
   double cv[16];
 #pragma unroll
   for (int q = 0; q < 16; q++) {
@@ -352,19 +365,32 @@ int lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t n, hipStream_t s) {
   double *Linv, *LinvT, *UinvT;
   FPDE_TRY(lu_inverses(m, n, &Linv, &LinvT, &UinvT));
   const long t = timer_begin(m, s);
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    const int64_t o = (k0 / NB) * NB * NB;  // block k0 / 64 of each inverse set
+  for (int64_t k0 = 0; k0 < n; k0 += 2 * NB) {
     // the first diagonal block on its own (the kernel indexes the sets by its
     // block itself: base pointers); every later one is factored by tile
-    // (0, 0) of the preceding update
+    // (0, 0) of the preceding update.  Panels in pairs: panel k0, the cross
+    // at k1 = k0 + 64 (its block column and block row) updated by it alone,
+    // panel k1, then the trailing square from k1 + 64 updated once by both
+    // (128 columns of L, 128 rows of U): the trailing square is read and
+    // written once per two panels.
     if (k0 == 0) k_lu_diag<true><<<1, 256, 0, s>>>(A, lda, n, k0, Linv, LinvT, UinvT, m->flag, m->flag_aux);
     const int64_t rest = n - k0 - NB;
-    if (rest > 0) {
-      const int ns = (int)((rest + 63) / 64);
-      k_lu_panels<<<2 * ns, 256, 0, s>>>(A, lda, n, k0, ns, Linv + o, UinvT + o);
-      k_lu_update<<<(unsigned)((int64_t)ns * ns), 256, 0, s>>>(A, lda, n, k0, ns, Linv, LinvT, UinvT, m->flag,
-                                                                m->flag_aux);
+    if (rest <= 0) break;
+    const int64_t o = (k0 / NB) * NB * NB;  // block k0 / 64 of each inverse set
+    const int ns = (int)((rest + 63) / 64);
+    k_lu_panels<<<2 * ns, 256, 0, s>>>(A, lda, n, k0, ns, Linv + o, UinvT + o);
+    if (rest <= NB) {  // one block left
+      k_lu_update<NB><<<(unsigned)((int64_t)ns * ns), 256, 0, s>>>(A, lda, n, k0, ns, Linv, LinvT, UinvT, m->flag,
+                                                                    m->flag_aux, 0);
+      break;
     }
+    k_lu_update<NB><<<(unsigned)(2 * ns - 1), 256, 0, s>>>(A, lda, n, k0, ns, Linv, LinvT, UinvT, m->flag,
+                                                            m->flag_aux, 1);
+    const int64_t k1 = k0 + NB, rest1 = rest - NB, o1 = o + NB * NB;
+    const int ns1 = (int)((rest1 + 63) / 64);
+    k_lu_panels<<<2 * ns1, 256, 0, s>>>(A, lda, n, k1, ns1, Linv + o1, UinvT + o1);
+    k_lu_update<2 * NB><<<(unsigned)((int64_t)ns1 * ns1), 256, 0, s>>>(A, lda, n, k0, ns1, Linv, LinvT, UinvT,
+                                                                        m->flag, m->flag_aux, 0);
   }
   timer_end(m, FPDE_STAGE_LU, t, s);
   FPDE_HIP(hipGetLastError());
