@@ -52,7 +52,6 @@ PMC = {
     "k_tube_accum": (os.path.join(ROOT, "profiles", "tube_accum_sphere20k_pmc.txt"),
                      [os.path.join(CSRC, "tubes.hip")]),
 }
-NB = 64  # panel width of the blocked Cholesky
 
 
 def log(*a):
@@ -84,18 +83,6 @@ def read_traffic(kernel):
         return float(kv["hbm_bytes_per_unit"])
     except (KeyError, ValueError):
         return None
-
-
-def syrk_flops(n):
-    """FP64 flops of the trailing updates of one factorization (lower
-    triangle of C -= X X^T, inner dimension NB, per panel) and their count."""
-    tot, launches = 0, 0
-    for k0 in range(0, n, NB):
-        rest = n - k0 - NB
-        if rest > 0:
-            tot += rest * (rest + 1) // 2 * NB * 2
-            launches += 1
-    return tot, launches
 
 
 SEC3_WORKLOAD = "ball_h076"
@@ -500,8 +487,9 @@ def main():
         log(f"[bench] one step with the systems solved one at a time: {seq_ms:.2f} ms")
 
     # Roofline of the dominant kernel of the step, by time per step: either
-    # the batched dense factorization (one unit = k_potrf_diag once, then
-    # k_panel + k_syrk per 64-column panel over all systems, timed with one
+    # the batched dense factorization (one unit = k_potrf_diag once, then per
+    # pair of 64-column panels two k_panel and two k_syrk launches over all
+    # systems, timed with one
     # event pair per call on the launch stream; algorithmic work
     # systems x n^3 / 3 FP64 flops, on the matrix cores: FP64 peak
     # 78.6 TFLOP/s) or the tube accumulation (one unit = one k_tube_accum
@@ -519,8 +507,9 @@ def main():
         cand.append((stages["potrf"][0], {
             "bound": "mfma", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
-            "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double> + "
-                      f"{syrk_flops(n)[1]} x (k_panel<double> + k_syrk<double>)",
+            "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double>, then per pair of "
+                      f"64-column panels k_panel, k_syrk<double, 64> (block column), k_panel, "
+                      f"k_syrk<double, 128> (trailing matrix)",
             "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (v_mfma_f64_16x16x4f64 tiles)"}))
     if stages["accum"][1]:
         avg_s = stages["accum"][0] / stages["accum"][1] / 1e3
