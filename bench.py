@@ -437,12 +437,14 @@ def main():
     u = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
     rays_per_step = sum(6 * gm.n_tet * nq for nq in RULES) * len(ALPHAS)
 
+    step_params = [F.params(a, KCOEF, quad_points=nq) for nq, a in cases]
+
     def step():
         # the step's systems are assembled one after another (each fills the
-        # device), then factored and solved together: their Cholesky and
-        # triangular-solve chains, latency-bound one by one, run side by side
-        for z, (nq, a) in enumerate(cases):
-            gm.assemble(F.params(a, KCOEF, quad_points=nq), A[z], b[z])
+        # device; one status check for all), then factored and solved
+        # together: their Cholesky and triangular-solve chains, latency-bound
+        # one by one, run side by side
+        gm.assemble_batch(step_params, A, b)
         gm.solve_batch(A, b, u)
 
     def step_sequential():

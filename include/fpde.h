@@ -165,6 +165,21 @@ int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_t lda, doub
                   const double *f_gauss, void *stream);
 
 /*
+ * fpde_assemble for `count` systems (1..16) of one mesh with one status
+ * check at the end: system z (parameters p[z], host array; every p[z] of
+ * one precision, no FPDE_SRC_USER) goes to A + z stride_A (elements of that
+ * precision, stride_A >= n_dof lda when count > 1) and, when b is not NULL,
+ * its load vector to b + z stride_b (stride_b >= n_dof).  The systems'
+ * kernels are enqueued back to back; the caller of a batch solve
+ * (fpde_solve_batch) assembles with this and synchronises twice per batch
+ * instead of once per system.
+ * Synchronises `stream`.  Errors: as fpde_assemble; on a walk failure
+ * every touched value set is invalidated and no system is to be used.
+ */
+int fpde_assemble_batch(fpde_mesh *m, int count, const fpde_params *p, void *A, int64_t lda, int64_t stride_A,
+                        double *b, int64_t stride_b, void *stream);
+
+/*
  * Matrix-free product y = K x in FP64 (the sums of fpde_assemble, never
  * forming K): the residual of the refinement in FPDE_MIXED.
  *   x, y: dev, n_dof FP64.  Synchronises `stream`.

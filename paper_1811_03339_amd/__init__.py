@@ -37,7 +37,7 @@ EXPORTS = [
     "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve", "fpde_template_csr",
     "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble", "fpde_mesh2d_create",
     "fpde_mesh2d_destroy", "fpde_mesh2d_info", "fpde_dof_map2d", "fpde_paths2d", "fpde_assemble2d",
-    "fpde_solve2d", "fpde_timing2d", "fpde_stage_times2d", "fpde_solve_batch",
+    "fpde_solve2d", "fpde_timing2d", "fpde_stage_times2d", "fpde_solve_batch", "fpde_assemble_batch",
 ]
 
 STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div", "spmv",
@@ -109,6 +109,7 @@ def _lib():
     L.fpde_solve.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_solve_factored.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_solve_batch.argtypes = [P, i32, P, i64, i64, P, P, i64, P, P]
+    L.fpde_assemble_batch.argtypes = [P, i32, P, P, i64, i64, P, i64, P]
     L.fpde_adjoint.argtypes = [P, P, P, P, P, P, P]
     L.fpde_timing.argtypes = [P, i32]
     L.fpde_stage_times.argtypes = [P, P, P]
@@ -303,6 +304,17 @@ class Mesh:
         _check(_lib().fpde_solve(self._h, ctypes.byref(p), _ptr(A), A.stride(0), _ptr(b), _ptr(u),
                                  ctypes.byref(out) if info else None, _stream(stream)), "fpde_solve")
         return out if info else None
+
+    def assemble_batch(self, params_list, A, b=None, stream=None):
+        """fpde_assemble for the systems params_list[z] into A[z] (and b[z]),
+        one status check at the end."""
+        count = len(params_list)
+        if A.shape[0] != count or A.stride(2) != 1 or (b is not None and (b.shape[0] != count or b.stride(1) != 1)):
+            raise ValueError("assemble_batch: A (count, n, n) and b (count, n) with contiguous rows")
+        arr = (fpde_params * count)(*params_list)
+        _check(_lib().fpde_assemble_batch(self._h, count, arr, _ptr(A), A.stride(1), A.stride(0), _ptr(b),
+                                          b.stride(0) if b is not None else 0, _stream(stream)),
+               "fpde_assemble_batch")
 
     def solve_batch(self, A, b, u, stream=None):
         """FP64 Cholesky solves of A[z] u[z] = b[z] for every z < A.shape[0]

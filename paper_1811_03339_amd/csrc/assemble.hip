@@ -248,6 +248,36 @@ extern "C" int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_
   return FPDE_OK;
 }
 
+extern "C" int fpde_assemble_batch(fpde_mesh *m, int count, const fpde_params *p, void *A, int64_t lda,
+                                   int64_t stride_A, double *b, int64_t stride_b, void *stream) {
+  if (!m || !p || count < 1 || count > 16 || !A || lda < m->ndof) return FPDE_EINVAL;
+  for (int z = 0; z < count; z++) {
+    FPDE_TRY(check_params(m, &p[z]));
+    if (p[z].source == FPDE_SRC_USER || p[z].precision != p[0].precision) return FPDE_EINVAL;
+  }
+  if (count > 1 && (stride_A < m->ndof * lda || (b && stride_b < m->ndof))) return FPDE_EINVAL;
+  hipStream_t s = S(stream);
+  const size_t elem = p[0].precision == FPDE_MIXED ? sizeof(float) : sizeof(double);
+  Plan *used[16] = {};
+  for (int z = 0; z < count; z++) {
+    Plan *P = nullptr;
+    FPDE_TRY(plan_for(m, p[z].quad_points, p[z].max_steps, s, &P));
+    used[z] = P;
+    // every system's kernels are enqueued behind the previous one's on the
+    // stream; a walk failure is reported (and every touched value set
+    // invalidated) once, at the end
+    FPDE_TRY(ensure_values(m, P, p[z].alpha, s));
+    FPDE_TRY(launch_contract_tubes(m, *P, &p[z], (char *)A + (size_t)z * (size_t)stride_A * elem, lda, s));
+    if (b) FPDE_TRY(launch_load(m, &p[z], b + (size_t)z * (size_t)stride_b, nullptr, s));
+  }
+  int f = take_flag(m, s);
+  if (f != 0) {
+    for (int z = 0; z < count; z++) invalidate_values(used[z]);
+    return f < 0 ? f : FPDE_EHIP;
+  }
+  return FPDE_OK;
+}
+
 extern "C" int fpde_apply(fpde_mesh *m, const fpde_params *p, const double *x, double *y, void *stream) {
   FPDE_TRY(check_params(m, p));
   if (!x || !y) return FPDE_EINVAL;

@@ -112,3 +112,37 @@ def test_batch_rejects():
         assert st == -1, (count, sa, sv)
     st = lib.fpde_solve_batch(h, 2, None, n, n * n, F._ptr(b), F._ptr(b), n, None, s)
     assert st == -1
+
+
+@pytest.mark.parametrize("name", ["cube8", "sphere20k"])
+def test_assemble_batch_equals_single(name):
+    """fpde_assemble_batch gives each system the matrix and load of fpde_assemble
+    (to the rounding of the LDS accumulation order)."""
+    print(f"[case] assemble_batch {name}", flush=True)
+    m, om, gm = mesh_pair(name)
+    cases = [(1.2, 4), (1.5, 11), (1.8, 4), (1.3, 11)]
+    ps = [F.params(a, (1.0, 0.5, 2.0), quad_points=nq) for a, nq in cases]
+    n = gm.n_dof
+    A = torch.empty((len(cases), n, n), dtype=torch.float64, device="cuda")
+    b = torch.empty((len(cases), n), dtype=torch.float64, device="cuda")
+    gm.assemble_batch(ps, A, b)
+    A1, b1 = systems(gm, cases)
+    torch.cuda.synchronize()
+    for z in range(len(cases)):
+        assert rel(A[z].cpu().numpy(), A1[z].cpu().numpy()) <= 1e-13, z
+        assert rel(b[z].cpu().numpy(), b1[z].cpu().numpy()) <= 1e-14, z
+
+
+def test_assemble_batch_rejects():
+    m, om, gm = mesh_pair("cube3")
+    n = gm.n_dof
+    lib = F._lib()
+    A = torch.empty((2, n, n), dtype=torch.float64, device="cuda")
+    h, s = gm._h, F._stream()
+    mixed = (F.fpde_params * 2)(F.params(1.5), F.params(1.5, precision=F.FPDE_MIXED))
+    assert lib.fpde_assemble_batch(h, 2, mixed, F._ptr(A), n, n * n, None, 0, s) == -1
+    user = (F.fpde_params * 1)(F.params(1.5, source=F.FPDE_SRC_USER))
+    assert lib.fpde_assemble_batch(h, 1, user, F._ptr(A), n, n * n, None, 0, s) == -1
+    ok = (F.fpde_params * 2)(F.params(1.5), F.params(1.6))
+    assert lib.fpde_assemble_batch(h, 0, ok, F._ptr(A), n, n * n, None, 0, s) == -1
+    assert lib.fpde_assemble_batch(h, 2, ok, F._ptr(A), n, n * n - 1, None, 0, s) == -1
