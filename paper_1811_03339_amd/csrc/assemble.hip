@@ -259,18 +259,48 @@ extern "C" int fpde_assemble_batch(fpde_mesh *m, int count, const fpde_params *p
   hipStream_t s = S(stream);
   const size_t elem = p[0].precision == FPDE_MIXED ? sizeof(float) : sizeof(double);
   Plan *used[16] = {};
-  for (int z = 0; z < count; z++) {
-    Plan *P = nullptr;
-    FPDE_TRY(plan_for(m, p[z].quad_points, p[z].max_steps, s, &P));
-    used[z] = P;
-    // every system's kernels are enqueued behind the previous one's on the
-    // stream; a walk failure is reported (and every touched value set
-    // invalidated) once, at the end
-    FPDE_TRY(ensure_values(m, P, p[z].alpha, s));
+  for (int z = 0; z < count; z++) FPDE_TRY(plan_for(m, p[z].quad_points, p[z].max_steps, s, &used[z]));
+  // The walks run on a second stream: the walk of a system overlaps the
+  // accumulation of the previous one when that one belongs to the other
+  // rule (another plan, another value buffer).  Systems are taken with the
+  // rules alternating; a walk waits for the caller's earlier work and for
+  // the last accumulation that read its plan's values, an accumulation for
+  // its walk (events; the values are re-walked only when the orders
+  // changed, as in fpde_assemble).
+  if (!m->side && hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess) m->side = nullptr;
+  for (int k = 0; k < 2 * count + 1 && m->side; k++)
+    if (!m->bev[k] && hipEventCreateWithFlags(&m->bev[k], hipEventDisableTiming) != hipSuccess) return FPDE_EHIP;
+  int order[16], no = 0;
+  {
+    int q4[16], q11[16], n4 = 0, n11 = 0;
+    for (int z = 0; z < count; z++) (used[z] == used[0] ? q4[n4++] : q11[n11++]) = z;
+    for (int k = 0; k < n4 || k < n11; k++) {
+      if (k < n4) order[no++] = q4[k];
+      if (k < n11) order[no++] = q11[k];
+    }
+  }
+  hipStream_t w = m->side ? m->side : s;
+  if (m->side) {
+    FPDE_HIP(hipEventRecord(m->bev[2 * count], s));
+    FPDE_HIP(hipStreamWaitEvent(w, m->bev[2 * count], 0));
+  }
+  int last_acc[2] = {-1, -1};  // per plan: the last system whose accumulation was enqueued
+  for (int k = 0; k < count; k++) {
+    const int z = order[k];
+    Plan *P = used[z];
+    const int pl = P == used[0] ? 0 : 1;
+    if (m->side && last_acc[pl] >= 0) FPDE_HIP(hipStreamWaitEvent(w, m->bev[2 * last_acc[pl] + 1], 0));
+    FPDE_TRY(ensure_values(m, P, p[z].alpha, w));
+    if (m->side) {
+      FPDE_HIP(hipEventRecord(m->bev[2 * z], w));
+      FPDE_HIP(hipStreamWaitEvent(s, m->bev[2 * z], 0));
+    }
     FPDE_TRY(launch_contract_tubes(m, *P, &p[z], (char *)A + (size_t)z * (size_t)stride_A * elem, lda, s));
     if (b) FPDE_TRY(launch_load(m, &p[z], b + (size_t)z * (size_t)stride_b, nullptr, s));
+    if (m->side) FPDE_HIP(hipEventRecord(m->bev[2 * z + 1], s));
+    last_acc[pl] = z;
   }
-  int f = take_flag(m, s);
+  int f = take_flag(m, s);  // every walk is ordered before an accumulation on s
   if (f != 0) {
     for (int z = 0; z < count; z++) invalidate_values(used[z]);
     return f < 0 ? f : FPDE_EHIP;

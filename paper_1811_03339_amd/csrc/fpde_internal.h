@@ -133,6 +133,10 @@ struct fpde_mesh {
   int64_t bvec_n = 0;
   int tsync_epoch = 0;
   fpde::StageTimer timer;
+  // batched assembly: a second stream for the walks and events ordering it
+  // against the caller's stream (created on first use)
+  hipStream_t side = nullptr;
+  hipEvent_t bev[33] = {};
 };
 
 namespace fpde {

@@ -455,6 +455,9 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   dfree(m->dof); dfree(m->vert_of_dof); dfree(m->rules); dfree(m->flag); dfree(m->flag_aux); dfree(m->vec); dfree(m->red);
   for (auto &P : m->plan) free_plan(P);
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : m->bev)
+    if (e) (void)hipEventDestroy(e);
+  if (m->side) (void)hipStreamDestroy(m->side);
   if (m->linv) (void)hipFree(m->linv);
   dfree(m->tsync);
   dfree(m->batch_aux);
