@@ -441,9 +441,10 @@ def main():
 
     def step():
         # the step's systems are assembled one after another (each fills the
-        # device; one status check for all), then factored and solved
-        # together: their Cholesky and triangular-solve chains, latency-bound
-        # one by one, run side by side
+        # device; one status check for all, each walk beside the previous
+        # system's accumulation), then factored and solved together: their
+        # Cholesky and triangular-solve chains, latency-bound one by one, run
+        # side by side
         gm.assemble_batch(step_params, A, b)
         gm.solve_batch(A, b, u)
 
@@ -641,7 +642,8 @@ def main():
             "workload": f"{WORKLOAD}: hull of 400 seeded points on the unit sphere + BCC lattice, "
                         f"{gm.n_tet} tets, {mesh.n_vert} nodes ({n} interior); alpha {list(ALPHAS)}, "
                         f"K={list(KCOEF)}, rules {list(RULES)}; FP64 assembly + dense Cholesky; "
-                        f"{passes} systems per step, assembled one by one, factored and solved as one batch",
+                        f"{passes} systems per step, assembled as one batch (walks beside the accumulations), "
+                        f"factored and solved as one batch",
             "n_nodes": mesh.n_vert, "n_dof": n, "n_tet": gm.n_tet,
             "gauss_points": {str(nq): gm.n_tet * nq for nq in RULES},
             "parallelism": "single GPU",
