@@ -146,3 +146,28 @@ def test_assemble_batch_rejects():
     ok = (F.fpde_params * 2)(F.params(1.5), F.params(1.6))
     assert lib.fpde_assemble_batch(h, 0, ok, F._ptr(A), n, n * n, None, 0, s) == -1
     assert lib.fpde_assemble_batch(h, 2, ok, F._ptr(A), n, n * n - 1, None, 0, s) == -1
+
+
+def test_assemble_batch_fp32_and_single_rule():
+    """FP32 matrices (the mixed arm) and a batch whose systems all use one rule
+    (every walk waits for the previous accumulation of the same plan)."""
+    m, om, gm = mesh_pair("sphere_small")
+    n = gm.n_dof
+    cases = [(1.2, 11), (1.5, 11), (1.8, 11)]
+    ps = [F.params(a, (1.0, 0.5, 2.0), quad_points=nq, precision=F.FPDE_MIXED) for a, nq in cases]
+    A = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+    b = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    gm.assemble_batch(ps, A, b)
+    for z, p in enumerate(ps):
+        A1 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        b1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        gm.assemble(p, A1, b1)
+        torch.cuda.synchronize()
+        assert rel(A[z].cpu().numpy(), A1.cpu().numpy()) <= 1e-6, z
+        assert rel(b[z].cpu().numpy(), b1.cpu().numpy()) <= 1e-14, z
+    ps64 = [F.params(a, (1.0, 0.5, 2.0), quad_points=nq) for a, nq in cases]
+    A64 = torch.empty((3, n, n), dtype=torch.float64, device="cuda")
+    gm.assemble_batch(ps64, A64, None)
+    torch.cuda.synchronize()
+    for z, (a, nq) in enumerate(cases):
+        assert rel(A64[z].cpu().numpy(), om.assemble(nq, a, (1.0, 0.5, 2.0))) <= 1e-10, z
