@@ -172,7 +172,11 @@ int fpde_assemble(fpde_mesh *m, const fpde_params *p, void *A, int64_t lda, doub
  * its load vector to b + z stride_b (stride_b >= n_dof).  The systems'
  * kernels are enqueued back to back; the caller of a batch solve
  * (fpde_solve_batch) assembles with this and synchronises twice per batch
- * instead of once per system.
+ * instead of once per system.  The walks (derivative values) run on a
+ * second stream owned by the mesh handle, each beside the previous
+ * system's accumulation when that one uses the other quadrature rule;
+ * events order them after the work already on `stream` and before the
+ * accumulations on `stream`, so on return all of it is complete.
  * Synchronises `stream`.  Errors: as fpde_assemble; on a walk failure
  * every touched value set is invalidated and no system is to be used.
  */
