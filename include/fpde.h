@@ -228,7 +228,7 @@ int fpde_solve_factored(fpde_mesh *m, const fpde_params *p, const void *L, int64
  *      definite, else -1.
  * Synchronises `stream`.  The mesh handle's scratch is shared, so calls on
  * one handle must not overlap.
- * Errors: FPDE_EINVAL, FPDE_ENOTSPD (no solution written), FPDE_ENOMEM,
+ * Errors: FPDE_EINVAL, FPDE_ENOTSPD (u then holds no solution), FPDE_ENOMEM,
  * FPDE_EHIP.
  */
 int fpde_solve_batch(fpde_mesh *m, int count, double *A, int64_t lda, int64_t stride_A, const double *b,

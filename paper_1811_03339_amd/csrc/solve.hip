@@ -814,20 +814,21 @@ extern "C" int fpde_solve_batch(fpde_mesh *m, int count, double *A, int64_t lda,
   FPDE_TRY(ensure_linv(m, n, sizeof(double), 2 * count, &lv));
   k_fill_i64<<<1, 64, 0, s>>>(m->batch_aux, count, -1);
   FPDE_TRY(potrf_batch<double>(A, lda, sA, n, count, (double *)lv, sL, m->batch_aux, m, s));
-  int f = take_flag(m, s);
-  if (f != 0) {
-    int64_t col[kMaxBatch];
-    FPDE_HIP(hipMemcpyAsync(col, m->batch_aux, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
-    FPDE_HIP(hipStreamSynchronize(s));
-    if (failed_pivot)
-      for (int z = 0; z < count; z++) failed_pivot[z] = col[z];
-    return f < 0 ? f : FPDE_EHIP;
-  }
+  // the solves follow at once: they finish whatever the factor holds (every
+  // block flag is published, every wait bounded), and one status check at
+  // the end covers both; a failed factorization reports no solution
   if (u != b) {
     k_copy_strided<<<dim3(nblk(n), (unsigned)count), 256, 0, s>>>(b, u, n, sv);
     FPDE_HIP(hipGetLastError());
   }
   FPDE_TRY(trsv_batch<double>(A, lda, sA, n, count, (const double *)lv, sL, u, sv, m->bvec, n, m, s));
-  f = take_flag(m, s);
+  int f = take_flag(m, s);
+  if (f == FPDE_ENOTSPD) {
+    int64_t col[kMaxBatch];
+    FPDE_HIP(hipMemcpyAsync(col, m->batch_aux, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
+    FPDE_HIP(hipStreamSynchronize(s));
+    if (failed_pivot)
+      for (int z = 0; z < count; z++) failed_pivot[z] = col[z];
+  }
   return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
 }
