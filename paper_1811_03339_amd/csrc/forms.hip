@@ -11,7 +11,10 @@
 // (b = 1, cl = p_i, cr = q_i) are instances.
 //
 // The walk evaluates every half-ray twice: at the trial orders into the
-// plan's first value set and at the test orders into its second.  Row k
+// plan's first value set and at the test orders into its second.  With
+// constant coefficients the products are accumulated by tubes (the two
+// products of every pair into a tube block, then the row pass of the
+// Riesz matrix); with coefficients per Gauss point, row k
 // then collects, over the incidences of node k (entry e of half-ray h in the
 // plan's node -> entry transpose, partner half-ray h' on the other side of
 // the same (g, i)), the partner's trial vector scaled by w_g c val_b(e), with
@@ -158,7 +161,12 @@ extern "C" int fpde_form_assemble(fpde_mesh *m, const fpde_form_params *p, const
   a.chunk = (int)(m->ndof < kFormChunk ? m->ndof : kFormChunk);
   const unsigned nchunk = (unsigned)((m->ndof + a.chunk - 1) / a.chunk);
   const long t = timer_begin(m, s);
-  k_form_rows<<<dim3((unsigned)m->ndof, nchunk), 256, 0, s>>>(a, A);
+  if (p->coef == FPDE_COEF_CONST) {
+    // constant coefficients: the pairs' products by tubes, then the row pass
+    FPDE_TRY(launch_form_tubes(m, *P, p->cl, p->cr, A, lda, s));
+  } else {
+    k_form_rows<<<dim3((unsigned)m->ndof, nchunk), 256, 0, s>>>(a, A);
+  }
   timer_end(m, FPDE_STAGE_FORM, t, s);
   FPDE_HIP(hipGetLastError());
   const int f = take_flag(m, s);

@@ -193,6 +193,9 @@ int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s);
 void free_tubes(TubePlan &tp);
 int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s);
 // the same sums kept at the columns of a CSR pattern (FP64)
+// general form with constant coefficients from the plan's two value sets
+int launch_form_tubes(fpde_mesh *m, Plan &P, const double cl[3], const double cr[3], double *A, int64_t lda,
+                      hipStream_t s);
 int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const int64_t *row_ptr,
                               const int32_t *col, double *val, hipStream_t s);
 // matrix-free y = K x and its scratch (assemble.hip)

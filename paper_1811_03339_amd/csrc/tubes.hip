@@ -265,6 +265,9 @@ struct AccumArgs {
   const int64_t *blk_off;
   double *blk;
   double KC0, KC1, KC2;
+  // general form (k_tube_form): test-order values and constant coefficients
+  const double *val_b;
+  double cl[3], cr[3];
 };
 
 __device__ __forceinline__ double read_lane_f64(double v, int l) {
@@ -486,6 +489,109 @@ __global__ void __launch_bounds__(1024) k_tube_accum(AccumArgs a) {
       const int i = j / U, t = j - i * U;
       out[j] = acc[i * Up + t];
     }
+  }
+}
+
+// General form with constant coefficients (Sec. 1, the test operator on
+// the side opposite to the trial one): per pair, with l / r the left / right
+// half-rays, the trial values at orders alpha (a.ent_val) and the test
+// values at orders beta (a.val_b),
+//   B[k][l] += w cl_i r_beta[k] l_alpha[l] + w cr_i l_beta[k] r_alpha[l]
+// (rows: test node, columns: trial node).  Not symmetric, so both products
+// of every pair go into full rows; an item is processed in row bands that
+// fit the square layout, the pairs re-read per band.
+__device__ void form_products_mem(double *acc, int Up, int rb, int Rb, const int4 m, double wl, double wr,
+                                  const int32_t *__restrict__ slot, const double *__restrict__ va,
+                                  const double *__restrict__ vb) {
+  const int lane = threadIdx.x & 63;
+  const int nl = __builtin_amdgcn_readfirstlane(pair_nl(m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(m));
+  for (int role = 0; role < 2; role++) {
+    // role 0: rows r (beta), columns l (alpha, w cl); role 1: rows l, columns r (w cr)
+    const int nrow = role ? nl : nr, ncol = role ? nr : nl;
+    const int erow = role ? m.x : m.y, ecol = role ? m.y : m.x;
+    const double w = role ? wr : wl;
+    for (int j0 = 0; j0 < nrow; j0 += 64) {
+      const int ex = erow + (j0 + lane < nrow ? j0 + lane : j0);
+      const int xs = slot[ex];
+      const double xv = vb[ex];
+      const bool xok = j0 + lane < nrow && xs >= rb && xs < rb + Rb;
+      if (__ballot(xok) == 0) continue;
+      for (int c0 = 0; c0 < ncol; c0 += 64) {
+        const int ec = ecol + (c0 + lane < ncol ? c0 + lane : c0);
+        const int cn = ncol - c0 < 64 ? ncol - c0 : 64;
+        sweep_cols<kBand2>(acc, (xs - rb) * Up, xs, 0, Up, xv, xok, slot[ec], va[ec] * w, cn);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_tube_form(AccumArgs a) {
+  extern __shared__ double acc[];
+  const int4 it = a.items[blockIdx.x];
+  const int64_t T = it.x;
+  const int r0 = it.y, R = it.z, U = it.w, Up = band_stride(U);
+  const int Rsq = kBandDoubles / Up;  // rows of one square band (>= 39 for |U_T| <= 512)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t k0 = a.tube_off[T], k1 = a.tube_off[T + 1];
+  for (int rb = r0; rb < r0 + R; rb += Rsq) {
+    const int Rb = (r0 + R - rb) < Rsq ? (r0 + R - rb) : Rsq;
+    for (int j = threadIdx.x; j < Rb * Up; j += blockDim.x) acc[j] = 0.0;
+    __syncthreads();
+    for (int64_t k = k0 + wave; k < k1; k += nw) {
+      PairRegs p;
+      p.m = a.pm[k];
+      p.w = a.pw[k];
+      const int axis = (int)((unsigned)p.m.w >> 30);
+      const double wl = p.w * (axis == 0 ? a.cl[0] : (axis == 1 ? a.cl[1] : a.cl[2]));
+      const double wr = p.w * (axis == 0 ? a.cr[0] : (axis == 1 ? a.cr[1] : a.cr[2]));
+      const int nl = __builtin_amdgcn_readfirstlane(pair_nl(p.m)), nr = __builtin_amdgcn_readfirstlane(pair_nr(p.m));
+      if (nl > kRegEntries || nr > kRegEntries) {
+        form_products_mem(acc, Up, rb, Rb, p.m, wl, wr, a.ent_slot, a.ent_val, a.val_b);
+        continue;
+      }
+      // entries `lane` and `lane + 64` of both sides, both value sets
+      // (indices clamped to a valid entry; lanes past the end are masked)
+      int ls[2], rs[2];
+      double la[2], ra[2], lb[2], rbv[2];
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int kl = 64 * h + lane;
+        const int il = nl > 0 ? p.m.x + (kl < nl ? kl : 0) : 0;
+        const int ir = nr > 0 ? p.m.y + (kl < nr ? kl : 0) : 0;
+        ls[h] = a.ent_slot[il];
+        rs[h] = a.ent_slot[ir];
+        la[h] = a.ent_val[il];
+        ra[h] = a.ent_val[ir];
+        lb[h] = a.val_b[il];
+        rbv[h] = a.val_b[ir];
+      }
+#pragma unroll
+      for (int role = 0; role < 2; role++) {
+        const int nrow = role ? nl : nr, ncol = role ? nr : nl;
+        const double w = role ? wr : wl;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int xs = role ? ls[h] : rs[h];
+          const double xv = role ? lb[h] : rbv[h];
+          const bool xok = 64 * h + lane < nrow && xs >= rb && xs < rb + Rb;
+          if (__ballot(xok) == 0) continue;
+          const int rowbase = (xs - rb) * Up;
+          sweep_cols<kBand2>(acc, rowbase, xs, 0, Up, xv, xok, role ? rs[0] : ls[0], (role ? ra[0] : la[0]) * w,
+                             ncol < 64 ? ncol : 64);
+          if (ncol > 64)
+            sweep_cols<kBand2>(acc, rowbase, xs, 0, Up, xv, xok, role ? rs[1] : ls[1], (role ? ra[1] : la[1]) * w,
+                               ncol - 64);
+        }
+      }
+    }
+    __syncthreads();
+    double *out = a.blk + a.blk_off[T] + (int64_t)rb * U;
+    for (int j = threadIdx.x; j < Rb * U; j += blockDim.x) {
+      const int i = j / U, t = j - i * U;
+      out[j] = acc[i * Up + t];
+    }
+    __syncthreads();  // the band is written before the next one is cleared
   }
 }
 
@@ -789,6 +895,35 @@ int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, 
   else
     k_tube_gather<double><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (double *)A);
   timer_end(m, FPDE_STAGE_CONTRACT, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
+// General form with constant coefficients: blocks by k_tube_form from the
+// plan's two value sets (trial orders in ent_val, test orders in ent_val2),
+// then the same row pass as the Riesz matrix.
+int launch_form_tubes(fpde_mesh *m, Plan &P, const double cl[3], const double cr[3], double *A, int64_t lda,
+                      hipStream_t s) {
+  if (m->ndof == 0) return FPDE_OK;
+  TubePlan &tp = P.tubes;
+  if (!tp.blk) FPDE_TRY(dalloc(&tp.blk, tp.blk_n > 0 ? tp.blk_n : 1));
+  AccumArgs a{};
+  a.tube_off = tp.tube_off;
+  a.pm = tp.pm;
+  a.pw = tp.pw;
+  a.items = tp.items;
+  a.ent_slot = tp.ent_slot;
+  a.ent_val = P.ent_val;
+  a.val_b = P.ent_val2;
+  a.blk_off = tp.blk_off;
+  a.blk = tp.blk;
+  for (int i = 0; i < 3; i++) {
+    a.cl[i] = cl[i];
+    a.cr[i] = cr[i];
+  }
+  if (tp.n_items > 0) k_tube_form<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
+  GatherArgs gch = gather_args(m, P, lda);
+  k_tube_gather<double><<<gather_grid(m->ndof), 256, sizeof(double) * gch.chunk, s>>>(gch, A);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
 }
