@@ -92,6 +92,7 @@ def _load():
     L.orc_assemble_div.argtypes = [P, i32, P, P, P, i32, P]
     L.orc_assemble_div_rows.argtypes = [P, i32, P, P, P, i32, i64, P, P]
     L.orc_assemble_form.argtypes = [P, i32, P, P, P, P, P, i32, P]
+    L.orc_assemble_form_rows.argtypes = [P, i32, P, P, P, P, P, i32, i64, P, P]
     # two dimensions
     L.o2_mesh_create.restype = P
     L.o2_mesh_create.argtypes = [P, i64, P, i64, P]
@@ -349,13 +350,14 @@ class OracleMesh:
             raise OracleError(st, "assemble_div")
         return A
 
-    def assemble_form(self, nq: int, alpha, beta, coef) -> np.ndarray:
+    def assemble_form(self, nq: int, alpha, beta, coef, rows=None) -> np.ndarray:
         """The uniform form of Sec. 1 (eq. equ:varsss), test operator on the
         side opposite to the trial one:
         K_kl = sum_i sum_g w_g [cl_i D_L^{alpha_i} psi_l D_R^{beta_i} psi_k
                                 + cr_i D_R^{alpha_i} psi_l D_L^{beta_i} psi_k](x_g),
         orders in [0, 1] per axis; coef: (6, G) with cl_i in rows 0..2 and
-        cr_i in rows 3..5, or 6 constants."""
+        cr_i in rows 3..5, or 6 constants.  rows: only these rows
+        (len(rows) x ndof), else the whole matrix."""
         G = self.n_tet * nq
         coef = np.asarray(coef, dtype=np.float64)
         if coef.shape == (6,):
@@ -367,8 +369,14 @@ class OracleMesh:
         gb = np.ascontiguousarray(beta, dtype=np.float64)
         iga = np.array([rgamma_(2.0 - a) for a in ga])
         igb = np.array([rgamma_(2.0 - b) for b in gb])
-        A = np.zeros((self.ndof, self.ndof))
-        st = _lib.orc_assemble_form(self._h, nq, _p(ga), _p(iga), _p(gb), _p(igb), _p(coef), self.cap, _p(A))
+        if rows is None:
+            A = np.zeros((self.ndof, self.ndof))
+            st = _lib.orc_assemble_form(self._h, nq, _p(ga), _p(iga), _p(gb), _p(igb), _p(coef), self.cap, _p(A))
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            A = np.zeros((len(rows), self.ndof))
+            st = _lib.orc_assemble_form_rows(self._h, nq, _p(ga), _p(iga), _p(gb), _p(igb), _p(coef), self.cap,
+                                             len(rows), _p(rows), _p(A))
         if st != 0:
             raise OracleError(st, "assemble_form")
         return A

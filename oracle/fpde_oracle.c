@@ -735,9 +735,10 @@ int orc_assemble_div_rows(const orc_mesh *m, int nq, const double *gamma, const 
 /* (row k = test function).  coef holds cl_i(x_g) at [i G + g] and cr_i(x_g) */
 /* at [(3 + i) G + g].  A is ndof x ndof row-major, zeroed by the caller.    */
 /* ------------------------------------------------------------------------ */
-int orc_assemble_form(const orc_mesh *m, int nq, const double *ga /* 3 */, const double *iga /* 3 */,
-                      const double *gb /* 3 */, const double *igb /* 3 */, const double *coef, int cap,
-                      double *A) {
+/* slot: NULL for the whole matrix, else slot[k] = the row of A that keeps
+   row k of K, or -1 (A is then nrows x ndof). */
+static int orc_form_sums(const orc_mesh *m, int nq, const double *ga, const double *iga, const double *gb,
+                         const double *igb, const double *coef, int cap, const int64_t *slot, double *A) {
   double bary[44], wq[11];
   if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
   orc_order oa[3], ob[3];
@@ -759,23 +760,62 @@ int orc_assemble_form(const orc_mesh *m, int nq, const double *ga /* 3 */, const
   for (int64_t g = 0; g < G && st == ORC_OK; g++) {
     double wg = wq[g % nq] * m->vol[g / nq];
     for (int i = 0; i < 3; i++) {
-      /* 0: D_L^a, 1: D_R^a (trial); 2: D_L^b, 3: D_R^b (test) */
+      /* 0: D_L^a, 1: D_R^a (trial); 2: D_L^b, 3: D_R^b (test).  The test
+         vectors are walked first: with a row list, a point whose test
+         vectors touch no kept row adds nothing. */
       int cnt[4];
-      for (int k = 0; k < 4; k++) {
+      for (int k = 3; k >= 0; k--) {
+        if (k == 1 && slot) {
+          int any = 0;
+          for (int a = 0; a < cnt[3] && !any; a++) any = slot[id[3][a]] >= 0;
+          for (int a = 0; a < cnt[2] && !any; a++) any = slot[id[2][a]] >= 0;
+          if (!any) break;
+        }
         cnt[k] = orc_ray_vector(m, nq, bary, g, i, k & 1, k < 2 ? &oa[i] : &ob[i], 0, cap, w, id[k], v[k], tb, rb);
         if (cnt[k] < 0) { st = cnt[k]; break; }
+        if (k == 0) {
+          double cl = coef[(int64_t)i * G + g], cr = coef[(int64_t)(3 + i) * G + g];
+          for (int a = 0; a < cnt[3]; a++) {
+            int64_t row = slot ? slot[id[3][a]] : id[3][a];
+            if (row < 0) continue;
+            for (int b = 0; b < cnt[0]; b++) A[row * n + id[0][b]] += (wg * cl) * (v[3][a] * v[0][b]);
+          }
+          for (int a = 0; a < cnt[2]; a++) {
+            int64_t row = slot ? slot[id[2][a]] : id[2][a];
+            if (row < 0) continue;
+            for (int b = 0; b < cnt[1]; b++) A[row * n + id[1][b]] += (wg * cr) * (v[2][a] * v[1][b]);
+          }
+        }
       }
       if (st != ORC_OK) break;
-      double cl = coef[(int64_t)i * G + g], cr = coef[(int64_t)(3 + i) * G + g];
-      for (int a = 0; a < cnt[3]; a++)
-        for (int b = 0; b < cnt[0]; b++) A[id[3][a] * n + id[0][b]] += (wg * cl) * (v[3][a] * v[0][b]);
-      for (int a = 0; a < cnt[2]; a++)
-        for (int b = 0; b < cnt[1]; b++) A[id[2][a] * n + id[1][b]] += (wg * cr) * (v[2][a] * v[1][b]);
     }
   }
   free(tb); free(rb);
   for (int k = 0; k < 4; k++) { free(id[k]); free(v[k]); }
   orc_work_free(w);
+  return st;
+}
+
+int orc_assemble_form(const orc_mesh *m, int nq, const double *ga /* 3 */, const double *iga /* 3 */,
+                      const double *gb /* 3 */, const double *igb /* 3 */, const double *coef, int cap,
+                      double *A) {
+  return orc_form_sums(m, nq, ga, iga, gb, igb, coef, cap, NULL, A);
+}
+
+/* Rows rows[0..nrows) of the same matrix (A: nrows x ndof, zeroed by the
+   caller, each row listed at most once), for checks at sizes where the
+   whole matrix is too large. */
+int orc_assemble_form_rows(const orc_mesh *m, int nq, const double *ga, const double *iga, const double *gb,
+                           const double *igb, const double *coef, int cap, int64_t nrows, const int64_t *rows,
+                           double *A) {
+  int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (m->ndof > 0 ? m->ndof : 1));
+  for (int64_t j = 0; j < m->ndof; j++) slot[j] = -1;
+  for (int64_t r = 0; r < nrows; r++) {
+    if (rows[r] < 0 || rows[r] >= m->ndof || slot[rows[r]] >= 0) { free(slot); return ORC_EINVAL; }
+    slot[rows[r]] = r;
+  }
+  int st = orc_form_sums(m, nq, ga, iga, gb, igb, coef, cap, slot, A);
+  free(slot);
   return st;
 }
 

@@ -101,3 +101,19 @@ def test_riesz_and_sec3_are_instances():
     B1 = om.assemble_div(4, beta)
     B2 = om.assemble_form(4, beta, (1.0, 1.0, 1.0), oracle.div_coefficients(x))
     assert np.abs(B1 - B2).max() <= 1e-14 * np.abs(B1).max()
+
+
+def test_rows_variant_keeps_the_listed_rows():
+    # the row list only selects which rows are kept: every kept row equals
+    # the whole matrix's, in any order, including the first and last rows
+    m = workload_mesh("sphere_small")
+    om = oracle.OracleMesh(m.xyz, m.tet)
+    a, b = (0.3, 0.8, 0.55), (0.9, 0.4, 0.7)
+    coef = (1.0, 0.5, 2.0, 0.7, 1.5, 0.3)
+    K = om.assemble_form(4, a, b, coef)
+    n = K.shape[0]
+    rows = np.array([n - 1, 0, 17, n // 2, 5])
+    R = om.assemble_form(4, a, b, coef, rows=rows)
+    assert np.array_equal(R, K[rows])
+    with pytest.raises(oracle.OracleError):
+        om.assemble_form(4, a, b, coef, rows=np.array([3, 3]))
