@@ -41,6 +41,7 @@ METRIC = "assembly+solve s & Gauss-pt paths/s at N nodes, FP64 vs mixed @1e-6 re
 WORKLOAD = "sphere20k"
 ALPHAS = (1.2, 1.5, 1.8)
 RULES = (4, 11)
+BREAKDOWN_STEPS = 5  # steps with every stage timed, after the timed steps
 KCOEF = (1.0, 0.5, 2.0)
 HBM_PEAK = 8.0e12        # B/s
 FP64_PEAK = 78.6e12      # FLOP/s, vector and matrix
@@ -457,7 +458,9 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    gm.timing(True)
+    # inside the timed steps only the two roofline candidates carry stage
+    # events (each timed stage costs two event records per launch)
+    gm.timing(True, stages=["accum", "potrf"])
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -469,10 +472,19 @@ def main():
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     gm.timing(False)
-    stages = gm.stage_times()
+    live = gm.stage_times()  # accumulation and factorization over the timed steps
     ms_per_step = total_ms / args.steps
     value = rays_per_step * args.steps / (total_ms / 1e3)
-    log(f"[bench] {ms_per_step:.2f} ms/step, {value:.3e} paths/s, stages {stages}")
+    log(f"[bench] {ms_per_step:.2f} ms/step, {value:.3e} paths/s, timed-step stages {live}")
+    # the per-stage breakdown from further steps with every stage timed
+    # (outside the timed region)
+    gm.timing(True)
+    for _ in range(BREAKDOWN_STEPS):
+        step()
+    torch.cuda.synchronize()
+    gm.timing(False)
+    stages = gm.stage_times()
+    log(f"[bench] stage breakdown over {BREAKDOWN_STEPS} steps: {stages}")
 
     # the same systems one at a time (assemble, factor, solve per system), one
     # step, outside the timed region: the per-system latency beside the
@@ -500,25 +512,25 @@ def main():
     # product of S = sum w l r^T, B = S + S^T, i.e. 2 flops x pairs, on the
     # vector ALUs with LDS atomics: FP64 peak 78.6 TFLOP/s).
     passes = len(cases)
-    factorizations = stages["potrf"][1]
+    factorizations = live["potrf"][1]
     cand = []
     if factorizations:
         calls = factorizations / passes
-        avg_s = stages["potrf"][0] / calls / 1e3
+        avg_s = live["potrf"][0] / calls / 1e3
         fl = passes * n ** 3 / 3.0
         ach = fl / avg_s / 1e12
-        cand.append((stages["potrf"][0], {
+        cand.append((live["potrf"][0], {
             "bound": "mfma", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
             "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double>, then per pair of "
                       f"64-column panels k_panel, k_syrk<double, 64> (block column), k_panel, "
                       f"k_syrk<double, 128> (trailing matrix)",
             "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (v_mfma_f64_16x16x4f64 tiles)"}))
-    if stages["accum"][1]:
-        avg_s = stages["accum"][0] / stages["accum"][1] / 1e3
+    if live["accum"][1]:
+        avg_s = live["accum"][0] / live["accum"][1] / 1e3
         fl = sum(2 * info[nq]["pairs"] for nq in RULES) / len(RULES)  # launches alternate the rules evenly
         ach = fl / avg_s / 1e12
-        cand.append((stages["accum"][0], {
+        cand.append((live["accum"][0], {
             "bound": "alu", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("k_tube_accum"),
             "kernel": "k_tube_accum (tube blocks, one launch per system)",
@@ -527,8 +539,8 @@ def main():
     other_roofline = min(cand, key=lambda c: c[0])[1] if len(cand) > 1 else None
     # every stage against its own bound (algorithmic work / measured time)
     stage_roof = {}
-    if factorizations:
-        t = stages["potrf"][0] / factorizations / 1e3
+    if stages["potrf"][1]:
+        t = stages["potrf"][0] / stages["potrf"][1] / 1e3
         fl = n ** 3 / 3.0
         stage_roof["potrf"] = {"flops_per_factorization": fl, "TFLOP/s": fl / t / 1e12,
                                "frac_fp64": fl / t / FP64_PEAK}
@@ -547,7 +559,7 @@ def main():
         stage_roof["accum"] = {"flops_per_launch": fl, "TFLOP/s": fl / t / 1e12, "frac_fp64": fl / t / FP64_PEAK,
                                "note": "one multiply-add per entry product of S (B = S + S^T)"}
     if stages["walk"][1]:
-        stage_roof["walk"] = {"paths_per_s": rays_per_step * args.steps / (stages["walk"][0] / 1e3)}
+        stage_roof["walk"] = {"paths_per_s": rays_per_step * BREAKDOWN_STEPS / (stages["walk"][0] / 1e3)}
 
     # mixed-precision arm at alpha = 1.5, 11-point rule
     mixed = None
@@ -651,8 +663,11 @@ def main():
         "assembly_solve_s_per_pass": ms_per_step / passes / 1e3,
         "sequential_ms_per_step": seq_ms,
         "sequential_assembly_solve_s_per_system": seq_ms / passes / 1e3 if seq_ms else None,
-        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0},
-        "walk_eval_paths_per_s": (rays_per_step * args.steps / (stages["walk"][0] / 1e3)
+        "stages_ms_per_step": {k: v[0] / BREAKDOWN_STEPS for k, v in stages.items() if v[1] > 0},
+        "stages_note": (f"launch times per stage from {BREAKDOWN_STEPS} further steps with every stage timed; "
+                        f"inside the timed steps only the accumulation and the factorization carry events "
+                        f"(the roofline's launch durations)"),
+        "walk_eval_paths_per_s": (rays_per_step * BREAKDOWN_STEPS / (stages["walk"][0] / 1e3)
                                   if stages["walk"][0] > 0 else None),
         "setup_ms": setup_ms,
         "template_plan_ms": plan_ms,

@@ -258,6 +258,10 @@ int fpde_adjoint(fpde_mesh *m, const fpde_params *p, const double *u, const doub
  * its LU factorisation and its accumulation, and the sparse products and
  * conjugate-gradient solves.
  *   fpde_timing(m, 1) clears the totals and starts recording; (m, 0) stops.
+ *   fpde_timing_stages(m, mask) does the same for the stages whose bit
+ *   (1u << FPDE_STAGE_x) is set in mask only (mask 0 stops; fpde_timing(m, 1)
+ *   is mask ~0u).  Every timed stage costs two event records per interval on
+ *   the stream, so a throughput measurement times only what it reports.
  *   fpde_stage_times waits for the recorded events, then writes per stage
  *   the summed milliseconds (host, FPDE_NSTAGES doubles) and the number of
  *   timed intervals (host, FPDE_NSTAGES int64; either pointer may be NULL).
@@ -280,6 +284,7 @@ enum {
   FPDE_NSTAGES = 14
 };
 int fpde_timing(fpde_mesh *m, int enable);
+int fpde_timing_stages(fpde_mesh *m, unsigned mask);
 int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count);
 
 /*

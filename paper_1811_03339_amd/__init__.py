@@ -33,7 +33,7 @@ STATUS = {
 EXPORTS = [
     "fpde_status_string", "fpde_mesh_create", "fpde_mesh_destroy", "fpde_mesh_info", "fpde_dof_map",
     "fpde_plan", "fpde_paths", "fpde_ray_values", "fpde_assemble", "fpde_apply", "fpde_solve",
-    "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_stage_times", "fpde_plan_info",
+    "fpde_solve_factored", "fpde_adjoint", "fpde_timing", "fpde_timing_stages", "fpde_stage_times", "fpde_plan_info",
     "fpde_template", "fpde_div_assemble", "fpde_lu_factor", "fpde_lu_solve", "fpde_template_csr",
     "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble", "fpde_mesh2d_create",
     "fpde_mesh2d_destroy", "fpde_mesh2d_info", "fpde_dof_map2d", "fpde_paths2d", "fpde_assemble2d",
@@ -112,6 +112,7 @@ def _lib():
     L.fpde_assemble_batch.argtypes = [P, i32, P, P, i64, i64, P, i64, P]
     L.fpde_adjoint.argtypes = [P, P, P, P, P, P, P]
     L.fpde_timing.argtypes = [P, i32]
+    L.fpde_timing_stages.argtypes = [P, ctypes.c_uint]
     L.fpde_stage_times.argtypes = [P, P, P]
     L.fpde_plan_info.argtypes = [P, i32, P, P]
     L.fpde_template.argtypes = [P, i32, P, P, P]
@@ -255,8 +256,18 @@ class Mesh:
         _check(_lib().fpde_template(self._h, tile, _np(tiles), _np(nnz), _stream(stream)), "fpde_template")
         return tiles, int(nnz[0])
 
-    def timing(self, enable: bool):
-        _check(_lib().fpde_timing(self._h, 1 if enable else 0), "fpde_timing")
+    def timing(self, enable: bool, stages=None):
+        """Start (clearing the totals) or stop stage timing; stages: names
+        from STAGES to time only those (default: every stage)."""
+        if not enable:
+            _check(_lib().fpde_timing_stages(self._h, 0), "fpde_timing_stages")
+        elif stages is None:
+            _check(_lib().fpde_timing(self._h, 1), "fpde_timing")
+        else:
+            mask = 0
+            for name in stages:
+                mask |= 1 << STAGES.index(name)
+            _check(_lib().fpde_timing_stages(self._h, mask), "fpde_timing_stages")
 
     def stage_times(self) -> dict:
         ms = np.zeros(len(STAGES))

@@ -193,7 +193,7 @@ int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_g
   a.rg3 = 1.0 / std::tgamma(3.0 - p->alpha);
   a.rg4 = 1.0 / std::tgamma(4.0 - p->alpha);
   a.rg5 = 1.0 / std::tgamma(5.0 - p->alpha);
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_LOAD);
   k_load<<<nblk(m->ndof), 256, 0, s>>>(a, b);
   timer_end(m, FPDE_STAGE_LOAD, t, s);
   FPDE_HIP(hipGetLastError());
@@ -206,7 +206,7 @@ int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, 
   if (!P->inc_wv) FPDE_TRY(dalloc(&P->inc_wv, P->n_ent > 0 ? P->n_ent : 1));
   ContractArgs c = contract_args(m, *P, p, 0);
   c.wv = P->inc_wv;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_APPLY);
   if (P->inc_wv_version != P->values_version) {
     if (P->n_ent > 0) k_inc_wv<<<nblk(P->n_ent), 256, 0, s>>>(P->inc_meta, P->inc_w, P->ent_val, P->n_ent, P->inc_wv);
     P->inc_wv_version = P->values_version;

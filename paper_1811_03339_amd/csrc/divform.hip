@@ -304,7 +304,7 @@ extern "C" int fpde_div_assemble(fpde_mesh *m, const fpde_div_params *p, const d
   a.pq = p->coef == FPDE_COEF_USER ? pq : nullptr;
   a.chunk = (int)(m->ndof < kDivChunk ? m->ndof : kDivChunk);
   const unsigned nchunk = (unsigned)((m->ndof + a.chunk - 1) / a.chunk);
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_DIV);
   k_div_rows<<<dim3((unsigned)m->ndof, nchunk), 256, 0, s>>>(a, A);
   timer_end(m, FPDE_STAGE_DIV, t, s);
   FPDE_HIP(hipGetLastError());
@@ -326,7 +326,7 @@ extern "C" int fpde_div_assemble(fpde_mesh *m, const fpde_div_params *p, const d
       l.ball.beta[i] = p->beta[i];
       for (int k = 0; k < 4; k++) l.ball.rg[i][k] = 1.0 / std::tgamma((double)(k + 2) - p->beta[i]);
     }
-    const long t2 = timer_begin(m, s);
+    const long t2 = timer_begin(m, s, FPDE_STAGE_LOAD);
     k_div_load<<<blocks_of(m->ndof), 256, 0, s>>>(l, b);
     timer_end(m, FPDE_STAGE_LOAD, t2, s);
     FPDE_HIP(hipGetLastError());

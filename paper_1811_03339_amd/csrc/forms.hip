@@ -160,7 +160,7 @@ extern "C" int fpde_form_assemble(fpde_mesh *m, const fpde_form_params *p, const
   a.lda = lda;
   a.chunk = (int)(m->ndof < kFormChunk ? m->ndof : kFormChunk);
   const unsigned nchunk = (unsigned)((m->ndof + a.chunk - 1) / a.chunk);
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_FORM);
   if (p->coef == FPDE_COEF_CONST) {
     // constant coefficients: the pairs' products by tubes, then the row pass
     FPDE_TRY(launch_form_tubes(m, *P, p->cl, p->cr, A, lda, s));

@@ -89,6 +89,7 @@ struct Plan {
 // HIP events around stage launches on the caller's stream (fpde_timing).
 struct StageTimer {
   bool on = false;
+  unsigned mask = ~0u;  // stages recorded while on (bit 1 << stage)
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Mark {
@@ -212,8 +213,10 @@ int workspace_new(int64_t ndof, fpde_mesh **out);
 // patch boxes of the template (built once per mesh)
 int ensure_patch_boxes(fpde_mesh *m, hipStream_t s);
 
-// Stage timing: t = timer_begin(m, s); ...launches...; timer_end(m, stage, t, s)
-long timer_begin(fpde_mesh *m, hipStream_t s);
+// Stage timing: t = timer_begin(m, s, stage); ...launches...;
+// timer_end(m, stage, t, s).  Records nothing (t = -1) unless timing is on
+// for that stage.
+long timer_begin(fpde_mesh *m, hipStream_t s, int stage);
 void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s, int weight = 1);
 
 // host-side order scalars

@@ -364,7 +364,7 @@ static int lu_inverses(fpde_mesh *m, int64_t n, double **Linv, double **LinvT, d
 int lu_factor(fpde_mesh *m, double *A, int64_t lda, int64_t n, hipStream_t s) {
   double *Linv, *LinvT, *UinvT;
   FPDE_TRY(lu_inverses(m, n, &Linv, &LinvT, &UinvT));
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_LU);
   for (int64_t k0 = 0; k0 < n; k0 += 2 * NB) {
     // the first diagonal block on its own (the kernel indexes the sets by its
     // block itself: base pointers); every later one is factored by tile
@@ -408,7 +408,7 @@ int lu_solve(fpde_mesh *m, const double *LU, int64_t lda, int64_t n, const doubl
   FPDE_TRY(ensure_trsv_sync(m, nblk, s));
   const int epoch = ++m->tsync_epoch;
   int *fflags = m->tsync, *bflags = m->tsync + nblk, *tickets = m->tsync + 2 * nblk;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_TRSV);
   k_lu_diag<false><<<nblk, 256, 0, s>>>(const_cast<double *>(LU), lda, n, 0, Linv, LinvT, UinvT, m->flag,
                                         m->flag_aux);
   if (u != b) k_copy_f64<<<blocks_of(n), 256, 0, s>>>(b, u, n);

@@ -483,12 +483,17 @@ extern "C" int fpde_dof_map(const fpde_mesh *m, int32_t *dof) {
 
 namespace fpde {
 
-long timer_begin(fpde_mesh *m, hipStream_t s) {
+// Stage timers only take timestamps: their records need no system-scope
+// cache writeback (the times are read after the caller has synchronised),
+// which would otherwise cost every recorded stage a flush.
+constexpr unsigned kTimerEventFlags = hipEventDisableSystemFence;
+
+long timer_begin(fpde_mesh *m, hipStream_t s, int stage) {
   StageTimer &T = m->timer;
-  if (!T.on) return -1;
+  if (!T.on || !((T.mask >> stage) & 1u)) return -1;
   if (T.used >= T.pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&e, kTimerEventFlags) != hipSuccess) return -1;
     T.pool.push_back(e);
   }
   const size_t i = T.used++;
@@ -501,7 +506,7 @@ void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s, int weight) {
   if (t < 0 || !T.on) return;
   if (T.used >= T.pool.size()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&e, kTimerEventFlags) != hipSuccess) return;
     T.pool.push_back(e);
   }
   const size_t i = T.used++;
@@ -511,16 +516,19 @@ void timer_end(fpde_mesh *m, int stage, long t, hipStream_t s, int weight) {
 
 }  // namespace fpde
 
-extern "C" int fpde_timing(fpde_mesh *m, int enable) {
+extern "C" int fpde_timing_stages(fpde_mesh *m, unsigned mask) {
   if (!m) return FPDE_EINVAL;
-  if (enable) {
+  if (mask) {
     FPDE_HIP(hipDeviceSynchronize());
     m->timer.used = 0;
     m->timer.marks.clear();
   }
-  m->timer.on = enable != 0;
+  m->timer.on = mask != 0;
+  m->timer.mask = mask;
   return FPDE_OK;
 }
+
+extern "C" int fpde_timing(fpde_mesh *m, int enable) { return fpde_timing_stages(m, enable ? ~0u : 0u); }
 
 extern "C" int fpde_stage_times(fpde_mesh *m, double *ms, int64_t *count) {
   if (!m) return FPDE_EINVAL;

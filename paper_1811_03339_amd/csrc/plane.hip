@@ -697,7 +697,7 @@ static int plan2_for(fpde_mesh2d *m, int nq, int max_steps, hipStream_t s, Plan2
     return FPDE_OK;
   }
   free_plan2(P);
-  const long t = timer_begin(m->ws, s);
+  const long t = timer_begin(m->ws, s, FPDE_STAGE_PLAN);
   FPDE_TRY(build_plan2(m, P, nq, max_steps, s));
   timer_end(m->ws, FPDE_STAGE_PLAN, t, s);
   *out = &P;
@@ -815,7 +815,7 @@ static int ensure_values2(fpde_mesh2d *m, Plan2 *P, double alpha, hipStream_t s)
   a.inv_g2 = o.inv_g2;
   a.off = P->off;
   a.ent_val = P->ent_val;
-  const long t = timer_begin(m->ws, s);
+  const long t = timer_begin(m->ws, s, FPDE_STAGE_WALK);
   launch_walk2<W2_VALUES>(a, s);
   timer_end(m->ws, FPDE_STAGE_WALK, t, s);
   FPDE_HIP(hipGetLastError());
@@ -928,7 +928,7 @@ extern "C" int fpde_assemble2d(fpde_mesh2d *m, const fpde_params2d *p, double *A
   a.KC0 = p->K[0] * o.c_alpha;
   a.KC1 = p->K[1] * o.c_alpha;
   const unsigned nchunk = (unsigned)((m->ndof + a.chunk - 1) / a.chunk);
-  const long t = timer_begin(m->ws, s);
+  const long t = timer_begin(m->ws, s, FPDE_STAGE_CONTRACT);
   k2_rows<<<dim3((unsigned)m->ndof, nchunk), 256, 0, s>>>(a, A);
   timer_end(m->ws, FPDE_STAGE_CONTRACT, t, s);
   FPDE_HIP(hipGetLastError());
@@ -952,7 +952,7 @@ extern "C" int fpde_assemble2d(fpde_mesh2d *m, const fpde_params2d *p, double *A
     l.rg3 = 1.0 / std::tgamma(3.0 - p->alpha);
     l.rg4 = 1.0 / std::tgamma(4.0 - p->alpha);
     l.rg5 = 1.0 / std::tgamma(5.0 - p->alpha);
-    const long t2 = timer_begin(m->ws, s);
+    const long t2 = timer_begin(m->ws, s, FPDE_STAGE_LOAD);
     k2_load<<<nblk2(m->ndof), 256, 0, s>>>(l, b);
     timer_end(m->ws, FPDE_STAGE_LOAD, t2, s);
     FPDE_HIP(hipGetLastError());

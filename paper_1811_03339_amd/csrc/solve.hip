@@ -538,7 +538,7 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
 template <class T>
 static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
                        fpde_mesh *m, hipStream_t s) {
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_POTRF);
   // the first diagonal block on its own; every later one is factored by the
   // workgroup of tile (0, 0) inside the preceding trailing update
   const int64_t nbk = (n + NB - 1) / NB;
@@ -622,7 +622,7 @@ static int trsv_batch(const T *L, int64_t lda, int64_t sA, int64_t n, int count,
   bs.f = 2 * nblk;
   bs.t = 2;
   const dim3 grid((unsigned)nblk, (unsigned)count);
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_TRSV);
   k_zero_i32<<<1, 64, 0, s>>>(tickets, 2 * count);
   k_trsv_rows<T, false><<<grid, 256, 0, s>>>(L, lda, n, nblk, LinvT, y, x, fflags, tickets, epoch, m->flag, bs);
   k_trsv_bwd<T><<<grid, 256, 0, s>>>(L, lda, n, nblk, Linv, x, y, bflags, tickets + 1, epoch, m->flag, bs);

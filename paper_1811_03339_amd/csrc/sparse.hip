@@ -273,7 +273,7 @@ extern "C" int fpde_template_csr(fpde_mesh *m, int64_t *row_ptr, int32_t *col, i
   int64_t *cnt = nullptr;
   FPDE_TRY(dalloc(&cnt, (size_t)(n + 1)));
   int st = FPDE_OK;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_PLAN);
   k_tpl_count<<<(unsigned)n, 256, 0, s>>>(m->pbox, n, cnt);
   if (hipGetLastError() != hipSuccess) st = FPDE_EHIP;
   // row_ptr = exclusive prefix of the counts (host: N + 1 values)
@@ -332,7 +332,7 @@ extern "C" int fpde_csr_apply(fpde_mesh *m, const int64_t *row_ptr, const int32_
   if (!m || !row_ptr || !col || !val || !x || !y) return FPDE_EINVAL;
   if (m->ndof == 0) return FPDE_OK;
   hipStream_t s = S(stream);
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_SPMV);
   k_csr_apply<<<blocks_of(m->ndof, 4), 256, 0, s>>>(row_ptr, col, val, x, m->ndof, y);
   timer_end(m, FPDE_STAGE_SPMV, t, s);
   FPDE_HIP(hipGetLastError());
@@ -368,14 +368,14 @@ extern "C" int fpde_cg_solve(fpde_mesh *m, const fpde_params *p, const int64_t *
   }
   auto op = [&](const double *x, double *y) -> int {
     if (csr) {
-      const long t = timer_begin(m, s);
+      const long t = timer_begin(m, s, FPDE_STAGE_SPMV);
       k_csr_apply<<<blocks_of(n, 4), 256, 0, s>>>(row_ptr, col, val, x, n, y);
       timer_end(m, FPDE_STAGE_SPMV, t, s);
       return hipGetLastError() == hipSuccess ? FPDE_OK : FPDE_EHIP;
     }
     return apply_matfree(m, P, p, x, y, dsc, s);
   };
-  const long t_all = timer_begin(m, s);
+  const long t_all = timer_begin(m, s, FPDE_STAGE_CG);
   // diagonal of K for the Jacobi preconditioner
   if (csr) {
     k_csr_diag<<<blocks_of(n), 256, 0, s>>>(row_ptr, col, val, n, w.d);

@@ -116,7 +116,7 @@ extern "C" int fpde_template(fpde_mesh *m, int tile, uint8_t *tiles, int64_t *nn
   int st = FPDE_OK;
   unsigned long long hn = 0;
   if (hipMemsetAsync(dn, 0, sizeof(*dn), s) != hipSuccess) st = FPDE_EHIP;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_PLAN);
   if (st == FPDE_OK) k_template_tiles<<<(unsigned)(nt * nt), 256, 0, s>>>(m->pbox, m->ndof, tile, nt, dt, dn);
   timer_end(m, FPDE_STAGE_PLAN, t, s);
   if (st == FPDE_OK && hipGetLastError() != hipSuccess) st = FPDE_EHIP;

@@ -857,7 +857,7 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
   a.KC0 = p->K[0] * o.c_alpha;
   a.KC1 = p->K[1] * o.c_alpha;
   a.KC2 = p->K[2] * o.c_alpha;
-  const long ta = timer_begin(m, s);
+  const long ta = timer_begin(m, s, FPDE_STAGE_ACCUM);
   if (tp.n_items > 0)
     k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
   timer_end(m, FPDE_STAGE_ACCUM, ta, s);
@@ -886,7 +886,7 @@ static unsigned gather_grid(int64_t ndof) {
 
 int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
   if (m->ndof == 0) return FPDE_OK;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_CONTRACT);
   FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
   GatherArgs gch = gather_args(m, P, lda);
   const unsigned grid = gather_grid(m->ndof);
@@ -931,7 +931,7 @@ int launch_form_tubes(fpde_mesh *m, Plan &P, const double cl[3], const double cr
 int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const int64_t *row_ptr,
                               const int32_t *col, double *val, hipStream_t s) {
   if (m->ndof == 0) return FPDE_OK;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_CONTRACT);
   FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
   GatherArgs gch = gather_args(m, P, 0);
   k_tube_gather_csr<<<gather_grid(m->ndof), 256, sizeof(double) * gch.chunk, s>>>(gch, row_ptr, col, val);

@@ -538,7 +538,7 @@ int plan_for(fpde_mesh *m, int nq, int max_steps, hipStream_t s, Plan **out) {
     return FPDE_OK;
   }
   free_plan(P);
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_PLAN);
   FPDE_TRY(build_plan(m, P, nq, max_steps, s));
   timer_end(m, FPDE_STAGE_PLAN, t, s);
   *out = &P;
@@ -572,7 +572,7 @@ int ensure_values_axes(fpde_mesh *m, Plan *P, const double gamma[3], hipStream_t
   a.n = (int64_t)(2 * (i1 - i0 + 1)) * P->G;
   a.off = P->off;
   a.ent_val = dest;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_WALK);
   launch_walk<W_VALUES>(a, s);
   timer_end(m, FPDE_STAGE_WALK, t, s);
   if (hipGetLastError() != hipSuccess) {
@@ -607,7 +607,7 @@ int walk_adjoint(fpde_mesh *m, Plan *P, double alpha, const double *u, const dou
   a.u = u;
   a.lam = lam;
   a.adj = P->adj;
-  const long t = timer_begin(m, s);
+  const long t = timer_begin(m, s, FPDE_STAGE_ADJOINT);
   launch_walk<W_ADJ>(a, s);
   timer_end(m, FPDE_STAGE_ADJOINT, t, s);
   FPDE_HIP(hipGetLastError());
