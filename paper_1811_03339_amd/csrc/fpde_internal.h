@@ -118,6 +118,8 @@ struct fpde_mesh {
   double *pbox = nullptr;         // ndof x 6: box of each node's element patch (lo xyz, hi xyz)
   int32_t *flag = nullptr;        // device status word (0 = ok)
   int64_t *flag_aux = nullptr;    // device: failing column / ray
+  int64_t *flag_blk = nullptr;    // device block holding both: {flag (low word), flag_aux}
+  int64_t *hflag = nullptr;       // pinned host copy of flag_blk (one transfer per status check)
   fpde::Plan plan[2];             // rules with 4 and 11 points
   // solve scratch
   double *vec = nullptr;          // 4 ndof FP64

@@ -96,12 +96,26 @@ int check_params(const fpde_mesh *m, const fpde_params *p) {
   return FPDE_OK;
 }
 
+// The status word and the failure detail share one 16-byte device block,
+// read back with one transfer into pinned host memory.
+static int alloc_flags(fpde_mesh *m) {
+  FPDE_TRY(dalloc(&m->flag_blk, 2));
+  m->flag = reinterpret_cast<int32_t *>(m->flag_blk);
+  m->flag_aux = m->flag_blk + 1;
+  if (hipHostMalloc((void **)&m->hflag, 2 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    m->hflag = nullptr;
+    return FPDE_ENOMEM;
+  }
+  return FPDE_OK;
+}
+
 int take_flag(fpde_mesh *m, hipStream_t s, int64_t *aux) {
   int32_t f = 0;
   int64_t a = -1;
-  FPDE_HIP(hipMemcpyAsync(&f, m->flag, sizeof(f), hipMemcpyDeviceToHost, s));
-  FPDE_HIP(hipMemcpyAsync(&a, m->flag_aux, sizeof(a), hipMemcpyDeviceToHost, s));
+  FPDE_HIP(hipMemcpyAsync(m->hflag, m->flag_blk, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   FPDE_HIP(hipStreamSynchronize(s));
+  std::memcpy(&f, m->hflag, sizeof(f));
+  a = m->hflag[1];
   if (f != 0) {
     int32_t z = 0;
     int64_t mz = -1;
@@ -293,8 +307,7 @@ static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, hipSt
   FPDE_TRY(dalloc(&m->vt_off, nv + 1));
   FPDE_TRY(dalloc(&m->vt_tet, nf));
   FPDE_TRY(dalloc(&m->dof, nv));
-  FPDE_TRY(dalloc(&m->flag, 1));
-  FPDE_TRY(dalloc(&m->flag_aux, 1));
+  FPDE_TRY(alloc_flags(m));
   {
     double tab[4 * 5 + 11 * 5];
     for (int nq : {4, 11}) {
@@ -408,8 +421,7 @@ int workspace_new(int64_t ndof, fpde_mesh **out) {
   *out = nullptr;
   fpde_mesh *m = new fpde_mesh();
   m->ndof = ndof;
-  if (hipGetDevice(&m->device) != hipSuccess || dalloc(&m->flag, 1) != FPDE_OK ||
-      dalloc(&m->flag_aux, 1) != FPDE_OK) {
+  if (hipGetDevice(&m->device) != hipSuccess || alloc_flags(m) != FPDE_OK) {
     fpde_mesh_destroy(m);
     return FPDE_ENOMEM;
   }
@@ -452,7 +464,8 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   if (!m) return;
   (void)hipDeviceSynchronize();
   dfree(m->xyz); dfree(m->tet); dfree(m->rec); dfree(m->vol); dfree(m->vt_off); dfree(m->vt_tet);
-  dfree(m->dof); dfree(m->vert_of_dof); dfree(m->rules); dfree(m->flag); dfree(m->flag_aux); dfree(m->vec); dfree(m->red);
+  dfree(m->dof); dfree(m->vert_of_dof); dfree(m->rules); dfree(m->flag_blk);
+  if (m->hflag) (void)hipHostFree(m->hflag); dfree(m->vec); dfree(m->red);
   for (auto &P : m->plan) free_plan(P);
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : m->bev)
