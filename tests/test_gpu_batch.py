@@ -171,3 +171,28 @@ def test_assemble_batch_fp32_and_single_rule():
     torch.cuda.synchronize()
     for z, (a, nq) in enumerate(cases):
         assert rel(A64[z].cpu().numpy(), om.assemble(nq, a, (1.0, 0.5, 2.0))) <= 1e-10, z
+
+
+def test_timing_chosen_stages_only():
+    # fpde_timing_stages: only the chosen stages record intervals (the batch
+    # assembly's accumulations here); stopping keeps what was recorded
+    m, om, gm = mesh_pair("cube4")
+    n = gm.n_dof
+    cases = [(4, 1.3), (11, 1.6), (4, 1.7)]
+    params = [F.params(a, (1.0, 0.5, 2.0), quad_points=nq) for nq, a in cases]
+    A = torch.empty((len(cases), n, n), dtype=torch.float64, device="cuda")
+    b = torch.empty((len(cases), n), dtype=torch.float64, device="cuda")
+    print("[case] timing accum only, cube4", flush=True)
+    gm.timing(True, stages=["accum"])
+    gm.assemble_batch(params, A, b)
+    torch.cuda.synchronize()
+    gm.timing(False)
+    st = gm.stage_times()
+    assert st["accum"][1] == len(cases) and st["accum"][0] > 0.0
+    assert all(c == 0 for k, (t, c) in st.items() if k != "accum")
+    gm.timing(True)
+    gm.assemble_batch(params, A, b)
+    torch.cuda.synchronize()
+    gm.timing(False)
+    st = gm.stage_times()
+    assert st["accum"][1] == len(cases) and st["walk"][1] >= 1 and st["contract"][1] == len(cases)
