@@ -44,45 +44,52 @@ __device__ inline double mms_Phi(double s, const LoadArgs &a) {
          24.0 * pow(s, 4.0 - a.alpha) * a.rg5;
 }
 
-// b_j = sum over elements E containing node j, points q: w_q |E| f(x_q) lambda_j(x_q)
-__global__ void k_load(LoadArgs a, double *__restrict__ b) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.ndof) return;
+// b_j = sum over elements E containing node j, points q: w_q |E| f(x_q) lambda_j(x_q).
+// One wavefront per node: its lanes take the node's (element, point) pairs,
+// then a butterfly sum in a fixed order (one node's few hundred terms would
+// otherwise be a serial loop for a handful of workgroups).
+__global__ void __launch_bounds__(256) k_load(LoadArgs a, double *__restrict__ b) {
+  const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (j >= a.ndof) return;  // whole wavefronts
   const int32_t v = a.vert_of_dof[j];
+  const int32_t p0 = a.vt_off[v];
+  const int items = (a.vt_off[v + 1] - p0) * a.nq;
   double sum = 0.0;
-  for (int32_t p = a.vt_off[v]; p < a.vt_off[v + 1]; p++) {
-    const int64_t t = a.vt_tet[p];
+  for (int k = lane; k < items; k += 64) {
+    const int pi = k / a.nq, q = k - pi * a.nq;
+    const int64_t t = a.vt_tet[p0 + pi];
     int jl = 0;
     int32_t vv[4];
     for (int m = 0; m < 4; m++) {
       vv[m] = a.tet[4 * t + m];
       if (vv[m] == v) jl = m;
     }
-    for (int q = 0; q < a.nq; q++) {
-      double f = 1.0;
-      if (a.src == FPDE_SRC_USER) {
-        f = a.f_gauss[t * a.nq + q];
-      } else if (a.src == FPDE_SRC_CUBE_MMS) {
-        double x[3];
-        for (int d = 0; d < 3; d++) {
-          double s = 0.0;
-          for (int m = 0; m < 4; m++) s = s + a.qtab[4 * q + m] * a.xyz[3 * (int64_t)vv[m] + d];
-          x[d] = s;
-        }
-        const double ph[3] = {mms_phi(x[0]), mms_phi(x[1]), mms_phi(x[2])};
-        f = 0.0;
-        for (int i = 0; i < 3; i++) {
-          double other = 1.0;
-          for (int d = 0; d < 3; d++)
-            if (d != i) other *= ph[d];
-          f += a.K[i] * a.c_alpha * (mms_Phi(x[i], a) + mms_Phi(1.0 - x[i], a)) * other;
-        }
+    double f = 1.0;
+    if (a.src == FPDE_SRC_USER) {
+      f = a.f_gauss[t * a.nq + q];
+    } else if (a.src == FPDE_SRC_CUBE_MMS) {
+      double x[3];
+      for (int d = 0; d < 3; d++) {
+        double s = 0.0;
+        for (int m = 0; m < 4; m++) s = s + a.qtab[4 * q + m] * a.xyz[3 * (int64_t)vv[m] + d];
+        x[d] = s;
       }
-      const double wg = a.qtab[4 * a.nq + q] * a.vol[t];
-      sum += wg * f * a.qtab[4 * q + jl];
+      const double ph[3] = {mms_phi(x[0]), mms_phi(x[1]), mms_phi(x[2])};
+      f = 0.0;
+      for (int i = 0; i < 3; i++) {
+        double other = 1.0;
+        for (int d = 0; d < 3; d++)
+          if (d != i) other *= ph[d];
+        f += a.K[i] * a.c_alpha * (mms_Phi(x[i], a) + mms_Phi(1.0 - x[i], a)) * other;
+      }
     }
+    const double wg = a.qtab[4 * a.nq + q] * a.vol[t];
+    sum += wg * f * a.qtab[4 * q + jl];
   }
-  b[j] = sum;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if (lane == 0) b[j] = sum;
 }
 
 // d[h] = sum over entries of half-ray h of value * x[dof]; 16 lanes per
@@ -194,7 +201,7 @@ int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_g
   a.rg4 = 1.0 / std::tgamma(4.0 - p->alpha);
   a.rg5 = 1.0 / std::tgamma(5.0 - p->alpha);
   const long t = timer_begin(m, s, FPDE_STAGE_LOAD);
-  k_load<<<nblk(m->ndof), 256, 0, s>>>(a, b);
+  k_load<<<nblk(m->ndof * 64), 256, 0, s>>>(a, b);
   timer_end(m, FPDE_STAGE_LOAD, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
