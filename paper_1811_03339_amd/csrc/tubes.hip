@@ -606,24 +606,42 @@ struct GatherArgs {
   int chunk;
 };
 
+__device__ __forceinline__ int64_t lane64(int64_t v, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Row `row`, columns [c0, c0 + cw), of K into the LDS chunk racc: the sum
 // over the (tube, slot) places of the node of that slot's row of the tube
-// block, scattered through U_T (one wavefront per place).  Ends with the
-// chunk complete and visible to the whole workgroup.
+// block, scattered through U_T (one wavefront per place).  The places'
+// metadata (tube, slot, node-set offset and size, block offset) is loaded
+// 64 places at a time, one per lane, and broadcast from there, so each
+// place costs one round of dependent loads instead of three.  Ends with
+// the chunk complete and visible to the whole workgroup.
 __device__ __forceinline__ void gather_row_chunk(const GatherArgs &a, int64_t row, int64_t c0, int64_t cw,
                                                  double *racc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t p0 = a.row_off[row], p1 = a.row_off[row + 1];
+  const int64_t p0 = a.row_off[row], np = a.row_off[row + 1] - p0;
   for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) racc[j] = 0.0;
   __syncthreads();
-  for (int64_t p = p0 + wave; p < p1; p += 4) {
-    const int2 ts = a.row_ts[p];
-    const int64_t u0 = a.u_off[ts.x], U = a.u_off[ts.x + 1] - u0;
-    const double *brow = a.blk + a.blk_off[ts.x] + (int64_t)ts.y * U;
-    for (int64_t t = lane; t < U; t += 64) {
-      const int64_t d = (int64_t)a.tube_u[u0 + t] - c0;
-      const double v = brow[t];
-      if ((uint64_t)d < (uint64_t)cw) atomicAdd(&racc[d], v);
+  for (int64_t pb = 0; pb < np; pb += 64) {
+    int64_t u0 = 0, U = 0, brow0 = 0;
+    if (pb + lane < np) {
+      const int2 ts = a.row_ts[p0 + pb + lane];
+      u0 = a.u_off[ts.x];
+      U = a.u_off[ts.x + 1] - u0;
+      brow0 = a.blk_off[ts.x] + (int64_t)ts.y * U;
+    }
+    const int cnt = (int)((np - pb) < 64 ? (np - pb) : 64);
+    for (int k = wave; k < cnt; k += 4) {
+      const int64_t uk = lane64(u0, k), Uk = lane64(U, k);
+      const double *brow = a.blk + lane64(brow0, k);
+      for (int64_t t = lane; t < Uk; t += 64) {
+        const int64_t d = (int64_t)a.tube_u[uk + t] - c0;
+        const double v = brow[t];
+        if ((uint64_t)d < (uint64_t)cw) atomicAdd(&racc[d], v);
+      }
     }
   }
   __syncthreads();
