@@ -355,11 +355,10 @@ __global__ void __launch_bounds__(256) k_trsv_rows(const T *__restrict__ A, int6
   for (int q = 0; q < 16; q++) s = fma(li[q], rhs[16 * w + q], s);
   red[w][lane] = s;
   __syncthreads();
-  if (tid < NB) {
-    if (tid < nb) x[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-    // the writers make their stores visible device-wide before the flag goes up
-    __threadfence();
-  }
+  // the block of x is written by wavefront 0; after the barrier (which waits
+  // for those stores) lane 0 of the same wavefront publishes it with a
+  // device-scope release store, which makes them visible device-wide
+  if (tid < nb) x[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
   __syncthreads();
   if (tid == 0) {
     __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

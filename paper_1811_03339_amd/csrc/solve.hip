@@ -464,10 +464,9 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const T *__restrict__ L, int64
   __syncthreads();  // red is reused
   red[w][lane] = s;
   __syncthreads();
-  if (tid < NB) {
-    if (tid < nb) u[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-    __threadfence();
-  }
+  // written by wavefront 0, published by its lane 0 after the barrier (as
+  // in the forward solve)
+  if (tid < nb) u[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
   __syncthreads();
   if (tid == 0) {
     __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
