@@ -276,7 +276,7 @@ extern "C" int fpde_assemble_batch(fpde_mesh *m, int count, const fpde_params *p
   // changed, as in fpde_assemble).
   if (!m->side && hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess) m->side = nullptr;
   for (int k = 0; k < 2 * count + 1 && m->side; k++)
-    if (!m->bev[k] && hipEventCreateWithFlags(&m->bev[k], hipEventDisableTiming) != hipSuccess) return FPDE_EHIP;
+    if (!m->bev[k] && hipEventCreateWithFlags(&m->bev[k], hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) return FPDE_EHIP;
   int order[16], no = 0;
   {
     int q4[16], q11[16], n4 = 0, n11 = 0;
