@@ -14,9 +14,11 @@ mesh and rule) happen before the timed region and are reported apart.
 
 value = Gauss-point paths per second over the timed steps (6 half-rays per
 Gauss point, summed over the six passes, divided by the step time).
-The single JSON line on stdout also carries the per-stage times, the
-roofline of the dominant kernel (measured with HIP events inside the library
-on the launch stream), the mixed-precision arm, K on the template of Sec. 2.3
+The single JSON line on stdout also carries the per-stage times (from a few
+further steps with every stage timed), the roofline of the dominant kernel
+(its launch durations measured over the timed steps with HIP events inside
+the library on the launch stream; only the two candidate stages carry
+events there), the mixed-precision arm, K on the template of Sec. 2.3
 as CSR with conjugate gradients (CSR and matrix-free), the general uniform
 form (c D^alpha u, D^beta v) with per-axis orders, the two-dimensional
 variant on a disk, the divergence-form
