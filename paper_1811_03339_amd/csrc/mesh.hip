@@ -465,7 +465,8 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   (void)hipDeviceSynchronize();
   dfree(m->xyz); dfree(m->tet); dfree(m->rec); dfree(m->vol); dfree(m->vt_off); dfree(m->vt_tet);
   dfree(m->dof); dfree(m->vert_of_dof); dfree(m->rules); dfree(m->flag_blk);
-  if (m->hflag) (void)hipHostFree(m->hflag); dfree(m->vec); dfree(m->red);
+  if (m->hflag) (void)hipHostFree(m->hflag);
+  dfree(m->vec); dfree(m->red);
   for (auto &P : m->plan) free_plan(P);
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : m->bev)
