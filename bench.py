@@ -395,7 +395,7 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the build is single-GPU)",
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the library runs on one GPU)",
               file=sys.stderr)
         sys.exit(2)
 
