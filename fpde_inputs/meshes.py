@@ -29,7 +29,7 @@ import dataclasses
 import numpy as np
 
 __all__ = [
-    "Mesh", "kuhn_cube", "hull_mesh", "radius_ratio", "workload_mesh", "fibonacci_sphere",
+    "Mesh", "kuhn_cube", "notched_cube", "hull_mesh", "radius_ratio", "workload_mesh", "fibonacci_sphere",
     "kuhn_square", "polygon_mesh", "circle_points",
     "WORKLOADS",
 ]
@@ -116,6 +116,22 @@ def kuhn_cube(n: int, lo: float = 0.0, hi: float = 1.0, morton: bool = False) ->
     if morton:
         xyz, tet = morton_renumber(xyz, tet)
     return Mesh(xyz, tet, name=f"kuhn_cube_{n}", info={"n": n})
+
+
+def notched_cube(n: int) -> Mesh:
+    """A non-convex input: the Kuhn cube of ``kuhn_cube(n)`` (n even) with the
+    sub-cubes of the quarter x > 1/2, y > 1/2 removed (an L-shaped prism).
+    Vertices no longer used by any tetrahedron are dropped."""
+    if n < 2 or n % 2:
+        raise ValueError("notched_cube needs an even n >= 2")
+    c = kuhn_cube(n)
+    cen = c.xyz[c.tet].mean(axis=1)
+    keep = ~((cen[:, 0] > 0.5) & (cen[:, 1] > 0.5))
+    tet = c.tet[keep]
+    used = np.unique(tet)
+    remap = np.full(c.n_vert, -1, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    return Mesh(c.xyz[used].copy(), remap[tet].astype(np.int32), name=f"notched_cube_{n}", info={"n": n})
 
 
 # --------------------------------------------------------------------------

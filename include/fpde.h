@@ -53,6 +53,7 @@ typedef enum {
   FPDE_EINVAL = -1,            /* bad argument (null pointer, size, lda, rule) */
   FPDE_EMESH_NONMANIFOLD = -2, /* a face shared by more than two elements */
   FPDE_EMESH_DEGENERATE = -3,  /* zero-volume element or repeated vertex */
+  FPDE_EMESH_NONCONVEX = -4,   /* a vertex lies outside the plane of a boundary face */
   FPDE_EPATH = -5,             /* a walk found no continuation or exceeded max_steps */
   FPDE_EALPHA = -6,            /* alpha outside (1, 2] or K_i <= 0 */
   FPDE_ENOTSPD = -7,           /* Cholesky met a pivot <= 0 */
@@ -96,9 +97,14 @@ const char *fpde_status_string(int status);
  * Copies both to the current HIP device, then builds on the device: per
  * element A^{-1} (A = (v1-v0, v2-v0, v3-v0)) and |E|, the neighbour across
  * each face (face f opposite local vertex f), boundary faces and nodes, the
- * interior numbering and vertex -> element lists.  Synchronises `stream`.
+ * interior numbering and vertex -> element lists.  The domain must be
+ * convex (the chord bounds a_i(x), b_i(x) of Sec. 1 eq. (1) are the two ends
+ * of one chord only then): every vertex used by an element must lie on the
+ * inner side of the plane of every boundary face, within 1e-12 times the
+ * diagonal of the vertices' bounding box, else FPDE_EMESH_NONCONVEX.
+ * Synchronises `stream`.
  * Errors: FPDE_EINVAL (sizes, ids out of range), FPDE_EMESH_NONMANIFOLD,
- * FPDE_EMESH_DEGENERATE, FPDE_ENOMEM, FPDE_EHIP.
+ * FPDE_EMESH_DEGENERATE, FPDE_EMESH_NONCONVEX, FPDE_ENOMEM, FPDE_EHIP.
  */
 int fpde_mesh_create(const double *xyz, int64_t n_vert, const int32_t *tet, int64_t n_tet,
                      void *stream, fpde_mesh **out);

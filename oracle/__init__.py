@@ -50,7 +50,7 @@ def build(force: bool = True) -> Path:
     """Compile the C oracle with gcc (plain FP64, no FMA contraction)."""
     if force or _stale():
         tmp = _LIB.with_suffix(".so.tmp")
-        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                         "-fPIC", "-shared", "-o", str(tmp), str(_SRC), str(_SRC2), "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -111,6 +111,16 @@ def _load():
     L.o2_load.argtypes = [P, i32, P, P]
     L.o2_exhaustive.argtypes = [P, P, P, P, P]
     L.orc_apply.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, P]
+    L.orc_apply_range.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P, i64, i64, P]
+    L.orc_operator_create.restype = P
+    L.orc_operator_create.argtypes = [P, i32, dbl, dbl, dbl, P, i32, P]
+    L.orc_operator_free.argtypes = [P]
+    L.orc_operator_apply.argtypes = [P, P, P]
+    L.orc_operator_diagonal.argtypes = [P, P]
+    L.orc_operator_entries.restype = i64
+    L.orc_operator_entries.argtypes = [P]
+    L.orc_set_threads.argtypes = [i32]
+    L.orc_set_threads.restype = i32
     L.orc_adjoint_sums.argtypes = [P, i32, dbl, dbl, dbl, i32, P, P, P, P]
     L.orc_load.argtypes = [P, i32, P, P]
     L.orc_exhaustive.argtypes = [P, P, P, P, P]
@@ -391,6 +401,18 @@ class OracleMesh:
             raise OracleError(st, "apply")
         return y
 
+    def apply_range(self, nq: int, alpha: float, K, x, g0: int, g1: int) -> np.ndarray:
+        """The part of K x summed over the Gauss points g0 <= g < g1 only."""
+        gm, ig2, _, _ = order_scalars(alpha)
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.ndof)
+        st = _lib.orc_apply_range(self._h, nq, gm, ig2, c_alpha(alpha), _p(Kc), self.cap, _p(x), int(g0), int(g1),
+                                  _p(y))
+        if st != 0:
+            raise OracleError(st, "apply_range")
+        return y
+
     def load(self, nq: int, f_gauss=None) -> np.ndarray:
         b = np.zeros(self.ndof)
         f = None if f_gauss is None else np.ascontiguousarray(f_gauss, dtype=np.float64)
@@ -533,6 +555,18 @@ class OracleMesh2D:
             raise OracleError(st, "assemble2d")
         return A
 
+    def apply_range(self, nq: int, alpha: float, K, x, g0: int, g1: int) -> np.ndarray:
+        """The part of K x summed over the Gauss points g0 <= g < g1 only."""
+        gm, ig2, _, _ = order_scalars(alpha)
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.ndof)
+        st = _lib.orc_apply_range(self._h, nq, gm, ig2, c_alpha(alpha), _p(Kc), self.cap, _p(x), int(g0), int(g1),
+                                  _p(y))
+        if st != 0:
+            raise OracleError(st, "apply_range")
+        return y
+
     def load(self, nq: int, f_gauss=None) -> np.ndarray:
         b = np.zeros(self.ndof)
         f = None if f_gauss is None else np.ascontiguousarray(f_gauss, dtype=np.float64)
@@ -565,31 +599,74 @@ def l2_error2d(mesh: OracleMesh2D, u_dof: np.ndarray, exact, nq: int = 7) -> flo
     return math.sqrt(float(np.sum(w * e * e)))
 
 
+class OracleOperator:
+    """The stiffness matrix of OracleMesh.apply as an operator whose
+    derivative vectors are walked once and kept (host memory: 12 bytes per
+    entry), for repeated products (conjugate gradients at large N)."""
+
+    def __init__(self, mesh: OracleMesh, nq: int, alpha: float, K=(1.0, 1.0, 1.0)):
+        gm, ig2, _, _ = order_scalars(alpha)
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        st = ctypes.c_int(0)
+        h = _lib.orc_operator_create(mesh._h, nq, gm, ig2, c_alpha(alpha), _p(Kc), mesh.cap, ctypes.byref(st))
+        if not h:
+            raise OracleError(st.value, "operator")
+        self._h = ctypes.c_void_p(h)
+        self.n = mesh.ndof
+        self.entries = int(_lib.orc_operator_entries(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_operator_free(self._h)
+            self._h = None
+
+    def apply(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.n)
+        _lib.orc_operator_apply(self._h, _p(x), _p(y))
+        return y
+
+    def diagonal(self) -> np.ndarray:
+        d = np.zeros(self.n)
+        _lib.orc_operator_diagonal(self._h, _p(d))
+        return d
+
+
 # --------------------------------------------------------------------------
 # Solves (textbook routines)
 # --------------------------------------------------------------------------
+def set_threads(n: int = 0) -> int:
+    """OpenMP threads of the oracle's parallel loops (the matrix-free
+    product, the row-restricted forms); n <= 0 only reports the count."""
+    return int(_load().orc_set_threads(int(n)))
+
+
 def solve_spd(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     """LAPACK Cholesky (dpotrf/dpotrs via SciPy)."""
     from scipy.linalg import cho_factor, cho_solve
     return cho_solve(cho_factor(A, lower=True), b)
 
 
-def cg(apply, b: np.ndarray, tol: float = 1e-13, maxiter: int = 10000):
-    """Plain conjugate gradients on a symmetric positive definite operator."""
+def cg(apply, b: np.ndarray, tol: float = 1e-13, maxiter: int = 10000, dinv=None):
+    """Conjugate gradients on a symmetric positive definite operator, stopped
+    at ||r|| <= tol ||b||; with dinv (the inverse of K's diagonal) the Jacobi
+    preconditioned variant (the textbook recurrences with z = dinv r)."""
     x = np.zeros_like(b)
     r = b.copy()
-    p = r.copy()
-    rr = float(r @ r)
+    z = r if dinv is None else dinv * r
+    p = z.copy()
+    rz = float(r @ z)
     bn = math.sqrt(float(b @ b))
     it = 0
-    while math.sqrt(rr) > tol * bn and it < maxiter:
+    while math.sqrt(float(r @ r)) > tol * bn and it < maxiter:
         q = apply(p)
-        a = rr / float(p @ q)
+        a = rz / float(p @ q)
         x += a * p
         r -= a * q
-        rr2 = float(r @ r)
-        p = r + (rr2 / rr) * p
-        rr = rr2
+        z = r if dinv is None else dinv * r
+        rz2 = float(r @ z)
+        p = z + (rz2 / rz) * p
+        rz = rz2
         it += 1
     return x, it
 

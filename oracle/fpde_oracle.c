@@ -8,7 +8,10 @@
  * benchmark's CPU-baseline leg may load this file.  It shares no code with the
  * GPU library and is deliberately slow and literal: straight loops, a fixed
  * iteration order, FP64 throughout, no FMA contraction (built with
- * -ffp-contract=off).
+ * -ffp-contract=off).  The matrix-free products and the row-restricted form
+ * split the Gauss points into one fixed block per OpenMP thread, each summed
+ * into its own copy of the result; the copies are added in thread order, so
+ * the thread count changes results only by rounding.
  *
  * What it computes (all citations are to the paper):
  *   - chord bounds a_i(x), b_i(x) of the convex domain along e_i (Sec. 1,
@@ -26,8 +29,10 @@
  *     the global dense matrix K = sum_E K_E, here for the Riesz operator split
  *     into (D_L^gamma u, D_R^gamma v) + (D_R^gamma u, D_L^gamma v)
  *     (form 1 of eq. equ:varsss with alpha = beta = gamma);
- *   - the load vector, a matrix-free product with K and the sums needed for
- *     the adjoint derivatives with respect to the order and the coefficients;
+ *   - the load vector, a matrix-free product with K (walking every path, or
+ *     from the derivative vectors walked once and kept) and the sums needed
+ *     for the adjoint derivatives with respect to the order and the
+ *     coefficients;
  *   - the non-symmetric matrix of the divergence-form two-sided problem of
  *     Sec. 3 (eq. equ:sfde2): order-beta_i trial derivatives along e_i with
  *     variable coefficients p_i, q_i, against the classical derivative of the
@@ -47,6 +52,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_EPS_BARY 1e-12   /* zero test on a volume coordinate */
 #define ORC_EPS_ADV 1e-12    /* relative advance required past an edge/vertex */
@@ -56,6 +64,7 @@ enum {
   ORC_EINVAL = -1,
   ORC_ENONMANIFOLD = -2,
   ORC_EDEGENERATE = -3,
+  ORC_ENONCONVEX = -4,
   ORC_EPATH = -5,
   ORC_ENOMEM = -10
 };
@@ -238,7 +247,46 @@ orc_mesh *orc_mesh_create(const double *xyz, int64_t nv, const int32_t *tet, int
   }
   m->ndof = 0;
   for (int64_t v = 0; v < nv; v++) m->dof[v] = (used[v] && !bnd[v]) ? (int32_t)(m->ndof++) : -1;
-  free(bnd); free(used);
+  free(bnd);
+
+  /* The chord bounds a_i(x), b_i(x) of Sec. 1 eq. (1) assume a convex domain.
+     A polyhedron is convex exactly when each of its vertices lies on the
+     inner side of the plane of each boundary face (each face plane supports
+     it).  Tolerance: 1e-12 of the diagonal of the vertices' bounding box. */
+  double lo[3], hi[3], diag = 0.0;
+  for (int d = 0; d < 3; d++) lo[d] = hi[d] = xyz[d];
+  for (int64_t v = 0; v < nv; v++) {
+    for (int d = 0; d < 3; d++) {
+      if (xyz[3 * v + d] < lo[d]) lo[d] = xyz[3 * v + d];
+      if (xyz[3 * v + d] > hi[d]) hi[d] = xyz[3 * v + d];
+    }
+  }
+  for (int d = 0; d < 3; d++) diag += (hi[d] - lo[d]) * (hi[d] - lo[d]);
+  const double tol = 1e-12 * sqrt(diag);
+  for (int64_t t = 0; t < nt; t++) {
+    for (int f = 0; f < 4; f++) {
+      if (m->nbr[4 * t + f] >= 0) continue;
+      const double *p[3];
+      int k = 0;
+      for (int j = 0; j < 4; j++) if (j != f) p[k++] = xyz + 3 * (int64_t)tet[4 * t + j];
+      const double *q = xyz + 3 * (int64_t)tet[4 * t + f];
+      double a[3], b[3];
+      for (int d = 0; d < 3; d++) { a[d] = p[1][d] - p[0][d]; b[d] = p[2][d] - p[0][d]; }
+      double n[3] = {orc_cross_x(a, b), orc_cross_y(a, b), orc_cross_z(a, b)};
+      double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int d = 0; d < 3; d++) n[d] /= len;
+      /* outward: away from the element's own opposite vertex */
+      if (n[0] * (q[0] - p[0][0]) + n[1] * (q[1] - p[0][1]) + n[2] * (q[2] - p[0][2]) > 0.0)
+        for (int d = 0; d < 3; d++) n[d] = -n[d];
+      for (int64_t v = 0; v < nv; v++) {
+        if (!used[v]) continue;
+        const double *x = xyz + 3 * v;
+        double dist = n[0] * (x[0] - p[0][0]) + n[1] * (x[1] - p[0][1]) + n[2] * (x[2] - p[0][2]);
+        if (dist > tol) { free(used); *status = ORC_ENONCONVEX; orc_mesh_free(m); return NULL; }
+      }
+    }
+  }
+  free(used);
 
   /* vertex -> element lists, ascending element id */
   for (int64_t k = 0; k < 4 * nt; k++) m->vt_off[tet[k] + 1]++;
@@ -738,7 +786,8 @@ int orc_assemble_div_rows(const orc_mesh *m, int nq, const double *gamma, const 
 /* slot: NULL for the whole matrix, else slot[k] = the row of A that keeps
    row k of K, or -1 (A is then nrows x ndof). */
 static int orc_form_sums(const orc_mesh *m, int nq, const double *ga, const double *iga, const double *gb,
-                         const double *igb, const double *coef, int cap, const int64_t *slot, double *A) {
+                         const double *igb, const double *coef, int cap, const int64_t *slot, int64_t nrows,
+                         double *A) {
   double bary[44], wq[11];
   if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
   orc_order oa[3], ob[3];
@@ -746,60 +795,90 @@ static int orc_form_sums(const orc_mesh *m, int nq, const double *ga, const doub
     orc_fill_order(&oa[i], ga[i], iga[i], 0.0, 0.0);
     orc_fill_order(&ob[i], gb[i], igb[i], 0.0, 0.0);
   }
-  orc_work *w = orc_work_new(m->nv);
-  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
-  double *rb = (double *)malloc(sizeof(double) * cap);
-  int32_t *id[4];
-  double *v[4];
-  for (int k = 0; k < 4; k++) {
-    id[k] = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
-    v[k] = (double *)malloc(sizeof(double) * 4 * cap);
-  }
   int64_t n = m->ndof, G = m->nt * nq;
+  /* With a row list each OpenMP thread adds its block of Gauss points into
+     its own copy of the rows, and the copies are added in thread order; the
+     whole matrix is summed by one thread. */
+  int nth = 1;
+#ifdef _OPENMP
+  if (slot) nth = omp_get_max_threads();
+#endif
+  const size_t asz = slot ? (size_t)nrows * (size_t)n : 0;
+  double *At = (slot && nth > 1) ? (double *)calloc((size_t)nth * (asz > 0 ? asz : 1), sizeof(double)) : NULL;
   int st = ORC_OK;
-  for (int64_t g = 0; g < G && st == ORC_OK; g++) {
-    double wg = wq[g % nq] * m->vol[g / nq];
-    for (int i = 0; i < 3; i++) {
-      /* 0: D_L^a, 1: D_R^a (trial); 2: D_L^b, 3: D_R^b (test).  The test
-         vectors are walked first: with a row list, a point whose test
-         vectors touch no kept row adds nothing. */
-      int cnt[4];
-      for (int k = 3; k >= 0; k--) {
-        if (k == 1 && slot) {
-          int any = 0;
-          for (int a = 0; a < cnt[3] && !any; a++) any = slot[id[3][a]] >= 0;
-          for (int a = 0; a < cnt[2] && !any; a++) any = slot[id[2][a]] >= 0;
-          if (!any) break;
-        }
-        cnt[k] = orc_ray_vector(m, nq, bary, g, i, k & 1, k < 2 ? &oa[i] : &ob[i], 0, cap, w, id[k], v[k], tb, rb);
-        if (cnt[k] < 0) { st = cnt[k]; break; }
-        if (k == 0) {
-          double cl = coef[(int64_t)i * G + g], cr = coef[(int64_t)(3 + i) * G + g];
-          for (int a = 0; a < cnt[3]; a++) {
-            int64_t row = slot ? slot[id[3][a]] : id[3][a];
-            if (row < 0) continue;
-            for (int b = 0; b < cnt[0]; b++) A[row * n + id[0][b]] += (wg * cl) * (v[3][a] * v[0][b]);
-          }
-          for (int a = 0; a < cnt[2]; a++) {
-            int64_t row = slot ? slot[id[2][a]] : id[2][a];
-            if (row < 0) continue;
-            for (int b = 0; b < cnt[1]; b++) A[row * n + id[1][b]] += (wg * cr) * (v[2][a] * v[1][b]);
-          }
-        }
-      }
-      if (st != ORC_OK) break;
+#pragma omp parallel num_threads(nth)
+  {
+    int me = 0;
+#ifdef _OPENMP
+    me = omp_get_thread_num();
+#endif
+    double *Al = At ? At + (size_t)me * (asz > 0 ? asz : 1) : A;
+    orc_work *w = orc_work_new(m->nv);
+    int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+    double *rb = (double *)malloc(sizeof(double) * cap);
+    int32_t *id[4];
+    double *v[4];
+    for (int k = 0; k < 4; k++) {
+      id[k] = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+      v[k] = (double *)malloc(sizeof(double) * 4 * cap);
     }
+    int my_st = ORC_OK;
+#pragma omp for schedule(static)
+    for (int64_t g = 0; g < G; g++) {
+      if (my_st != ORC_OK) continue;
+      double wg = wq[g % nq] * m->vol[g / nq];
+      for (int i = 0; i < 3; i++) {
+        /* 0: D_L^a, 1: D_R^a (trial); 2: D_L^b, 3: D_R^b (test).  The test
+           vectors are walked first: with a row list, a point whose test
+           vectors touch no kept row adds nothing. */
+        int cnt[4];
+        for (int k = 3; k >= 0; k--) {
+          if (k == 1 && slot) {
+            int any = 0;
+            for (int a = 0; a < cnt[3] && !any; a++) any = slot[id[3][a]] >= 0;
+            for (int a = 0; a < cnt[2] && !any; a++) any = slot[id[2][a]] >= 0;
+            if (!any) break;
+          }
+          cnt[k] = orc_ray_vector(m, nq, bary, g, i, k & 1, k < 2 ? &oa[i] : &ob[i], 0, cap, w, id[k], v[k], tb, rb);
+          if (cnt[k] < 0) { my_st = cnt[k]; break; }
+          if (k == 0) {
+            double cl = coef[(int64_t)i * G + g], cr = coef[(int64_t)(3 + i) * G + g];
+            for (int a = 0; a < cnt[3]; a++) {
+              int64_t row = slot ? slot[id[3][a]] : id[3][a];
+              if (row < 0) continue;
+              for (int b = 0; b < cnt[0]; b++) Al[row * n + id[0][b]] += (wg * cl) * (v[3][a] * v[0][b]);
+            }
+            for (int a = 0; a < cnt[2]; a++) {
+              int64_t row = slot ? slot[id[2][a]] : id[2][a];
+              if (row < 0) continue;
+              for (int b = 0; b < cnt[1]; b++) Al[row * n + id[1][b]] += (wg * cr) * (v[2][a] * v[1][b]);
+            }
+          }
+        }
+        if (my_st != ORC_OK) break;
+      }
+    }
+#pragma omp critical
+    if (my_st != ORC_OK && st == ORC_OK) st = my_st;
+    free(tb); free(rb);
+    for (int k = 0; k < 4; k++) { free(id[k]); free(v[k]); }
+    orc_work_free(w);
   }
-  free(tb); free(rb);
-  for (int k = 0; k < 4; k++) { free(id[k]); free(v[k]); }
-  orc_work_free(w);
+  if (At) {
+    for (size_t e = 0; e < asz; e++) {
+      double acc = 0.0;
+      for (int t = 0; t < nth; t++) acc += At[(size_t)t * asz + e];
+      A[e] += acc;
+    }
+    free(At);
+  }
   return st;
 }
 
 int orc_assemble_form(const orc_mesh *m, int nq, const double *ga /* 3 */, const double *iga /* 3 */,
                       const double *gb /* 3 */, const double *igb /* 3 */, const double *coef, int cap,
                       double *A) {
-  return orc_form_sums(m, nq, ga, iga, gb, igb, coef, cap, NULL, A);
+  return orc_form_sums(m, nq, ga, iga, gb, igb, coef, cap, NULL, 0, A);
 }
 
 /* Rows rows[0..nrows) of the same matrix (A: nrows x ndof, zeroed by the
@@ -814,42 +893,257 @@ int orc_assemble_form_rows(const orc_mesh *m, int nq, const double *ga, const do
     if (rows[r] < 0 || rows[r] >= m->ndof || slot[rows[r]] >= 0) { free(slot); return ORC_EINVAL; }
     slot[rows[r]] = r;
   }
-  int st = orc_form_sums(m, nq, ga, iga, gb, igb, coef, cap, slot, A);
+  int st = orc_form_sums(m, nq, ga, iga, gb, igb, coef, cap, slot, nrows, A);
   free(slot);
   return st;
 }
 
-/* Matrix-free product y = K x (same sums as orc_assemble, never forming K). */
-int orc_apply(const orc_mesh *m, int nq, double gamma, double inv_g2, double c_alpha,
-              const double *Kc, int cap, const double *x, double *y) {
+/* Matrix-free product y = K x (same sums as orc_assemble, never forming K),
+   restricted to the Gauss points g in [g0, g1): the whole product for
+   g0 = 0, g1 = G.  Each OpenMP thread walks a fixed block of Gauss points and
+   sums into its own copy of y; the copies are added in thread order. */
+int orc_apply_range(const orc_mesh *m, int nq, double gamma, double inv_g2, double c_alpha,
+                    const double *Kc, int cap, const double *x, int64_t g0, int64_t g1, double *y) {
   double bary[44], wq[11];
   if (orc_quadrature(nq, bary, wq) != ORC_OK) return ORC_EINVAL;
+  if (g0 < 0 || g1 > m->nt * nq || g0 > g1) return ORC_EINVAL;
   orc_order ord;
   orc_fill_order(&ord, gamma, inv_g2, 0.0, 0.0);
-  orc_work *w = orc_work_new(m->nv);
-  int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
-  double *rb = (double *)malloc(sizeof(double) * cap);
-  int32_t *Li = (int32_t *)malloc(sizeof(int32_t) * 4 * cap), *Ri = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
-  double *Lv = (double *)malloc(sizeof(double) * 4 * cap), *Rv = (double *)malloc(sizeof(double) * 4 * cap);
-  for (int64_t j = 0; j < m->ndof; j++) y[j] = 0.0;
+  const int64_t n = m->ndof;
+  int nth = 1;
+#ifdef _OPENMP
+  nth = omp_get_max_threads();
+#endif
+  double *yt = (double *)calloc((size_t)nth * (size_t)(n > 0 ? n : 1), sizeof(double));
   int st = ORC_OK;
-  for (int64_t g = 0; g < m->nt * nq && st == ORC_OK; g++) {
-    double wg = wq[g % nq] * m->vol[g / nq];
-    for (int i = 0; i < 3; i++) {
-      int nl = orc_ray_vector(m, nq, bary, g, i, 0, &ord, 0, cap, w, Li, Lv, tb, rb);
-      if (nl < 0) { st = nl; break; }
-      int nr = orc_ray_vector(m, nq, bary, g, i, 1, &ord, 0, cap, w, Ri, Rv, tb, rb);
-      if (nr < 0) { st = nr; break; }
-      double W = wg * Kc[i] * c_alpha;
-      double lx = 0.0, rx = 0.0;
-      for (int b = 0; b < nl; b++) lx += Lv[b] * x[Li[b]];
-      for (int b = 0; b < nr; b++) rx += Rv[b] * x[Ri[b]];
-      for (int a = 0; a < nr; a++) y[Ri[a]] += W * (Rv[a] * lx);
-      for (int a = 0; a < nl; a++) y[Li[a]] += W * (Lv[a] * rx);
+#pragma omp parallel num_threads(nth)
+  {
+    int me = 0;
+#ifdef _OPENMP
+    me = omp_get_thread_num();
+#endif
+    double *yl = yt + (size_t)me * (size_t)(n > 0 ? n : 1);
+    orc_work *w = orc_work_new(m->nv);
+    int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+    double *rb = (double *)malloc(sizeof(double) * cap);
+    int32_t *Li = (int32_t *)malloc(sizeof(int32_t) * 4 * cap), *Ri = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+    double *Lv = (double *)malloc(sizeof(double) * 4 * cap), *Rv = (double *)malloc(sizeof(double) * 4 * cap);
+    int my_st = ORC_OK;
+#pragma omp for schedule(static)
+    for (int64_t g = g0; g < g1; g++) {
+      if (my_st != ORC_OK) continue;
+      double wg = wq[g % nq] * m->vol[g / nq];
+      for (int i = 0; i < 3; i++) {
+        int nl = orc_ray_vector(m, nq, bary, g, i, 0, &ord, 0, cap, w, Li, Lv, tb, rb);
+        if (nl < 0) { my_st = nl; break; }
+        int nr = orc_ray_vector(m, nq, bary, g, i, 1, &ord, 0, cap, w, Ri, Rv, tb, rb);
+        if (nr < 0) { my_st = nr; break; }
+        double W = wg * Kc[i] * c_alpha;
+        double lx = 0.0, rx = 0.0;
+        for (int b = 0; b < nl; b++) lx += Lv[b] * x[Li[b]];
+        for (int b = 0; b < nr; b++) rx += Rv[b] * x[Ri[b]];
+        for (int a = 0; a < nr; a++) yl[Ri[a]] += W * (Rv[a] * lx);
+        for (int a = 0; a < nl; a++) yl[Li[a]] += W * (Lv[a] * rx);
+      }
+    }
+#pragma omp critical
+    if (my_st != ORC_OK && st == ORC_OK) st = my_st;
+    free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);
+  }
+  for (int64_t j = 0; j < n; j++) {
+    double acc = 0.0;
+    for (int t = 0; t < nth; t++) acc += yt[(size_t)t * (size_t)n + j];
+    y[j] = acc;
+  }
+  free(yt);
+  return st;
+}
+
+int orc_apply(const orc_mesh *m, int nq, double gamma, double inv_g2, double c_alpha,
+              const double *Kc, int cap, const double *x, double *y) {
+  return orc_apply_range(m, nq, gamma, inv_g2, c_alpha, Kc, cap, x, 0, m->nt * nq, y);
+}
+
+/* The same operator with its derivative vectors kept: every half-ray is
+   walked once (orc_ray_vector, as above) and its sparse vector stored, so
+   repeated products (conjugate gradients at sizes where the dense matrix is
+   out of reach) cost two passes over the stored entries each.  The Gauss
+   points are cut into one contiguous chunk per OpenMP thread at creation;
+   chunk c holds, per point g and axis i, the weight W = w_g K_i c_alpha and
+   the entries of L (side 0) then R (side 1). */
+typedef struct {
+  int64_t g0, g1, n_ent, cap_ent;
+  int32_t *cnt;  /* (g1 - g0) * 6: entries of (g, i, side) at [6 (g - g0) + 2 i + side] */
+  double *W;     /* (g1 - g0) * 3 */
+  int32_t *id;
+  double *val;
+} orc_op_chunk;
+
+typedef struct {
+  int64_t n, nchunk;
+  orc_op_chunk *c;
+} orc_operator;
+
+void orc_operator_free(orc_operator *op) {
+  if (!op) return;
+  for (int64_t k = 0; k < op->nchunk; k++) {
+    free(op->c[k].cnt); free(op->c[k].W); free(op->c[k].id); free(op->c[k].val);
+  }
+  free(op->c);
+  free(op);
+}
+
+orc_operator *orc_operator_create(const orc_mesh *m, int nq, double gamma, double inv_g2, double c_alpha,
+                                  const double *Kc, int cap, int *status) {
+  double bary[44], wq[11];
+  *status = ORC_OK;
+  if (orc_quadrature(nq, bary, wq) != ORC_OK) { *status = ORC_EINVAL; return NULL; }
+  orc_order ord;
+  orc_fill_order(&ord, gamma, inv_g2, 0.0, 0.0);
+  const int64_t G = m->nt * nq;
+  int nth = 1;
+#ifdef _OPENMP
+  nth = omp_get_max_threads();
+#endif
+  orc_operator *op = (orc_operator *)calloc(1, sizeof(orc_operator));
+  op->n = m->ndof;
+  op->nchunk = nth;
+  op->c = (orc_op_chunk *)calloc((size_t)nth, sizeof(orc_op_chunk));
+  int st = ORC_OK;
+#pragma omp parallel num_threads(nth)
+  {
+    int me = 0;
+#ifdef _OPENMP
+    me = omp_get_thread_num();
+#endif
+    orc_op_chunk *c = &op->c[me];
+    c->g0 = G * me / nth;
+    c->g1 = G * (me + 1) / nth;
+    const int64_t ng = c->g1 - c->g0;
+    c->cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(6 * ng + 1));
+    c->W = (double *)malloc(sizeof(double) * (size_t)(3 * ng + 1));
+    c->cap_ent = 64 * ng + 1024;
+    c->id = (int32_t *)malloc(sizeof(int32_t) * (size_t)c->cap_ent);
+    c->val = (double *)malloc(sizeof(double) * (size_t)c->cap_ent);
+    orc_work *w = orc_work_new(m->nv);
+    int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+    double *rb = (double *)malloc(sizeof(double) * cap);
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * 4 * cap);
+    double *vals = (double *)malloc(sizeof(double) * 4 * cap);
+    int my_st = ORC_OK;
+    for (int64_t g = c->g0; g < c->g1 && my_st == ORC_OK; g++) {
+      double wg = wq[g % nq] * m->vol[g / nq];
+      for (int i = 0; i < 3 && my_st == ORC_OK; i++) {
+        c->W[3 * (g - c->g0) + i] = wg * Kc[i] * c_alpha;
+        for (int side = 0; side < 2; side++) {
+          int nn = orc_ray_vector(m, nq, bary, g, i, side, &ord, 0, cap, w, ids, vals, tb, rb);
+          if (nn < 0) { my_st = nn; break; }
+          if (c->n_ent + nn > c->cap_ent) {
+            c->cap_ent = 2 * (c->n_ent + nn);
+            c->id = (int32_t *)realloc(c->id, sizeof(int32_t) * (size_t)c->cap_ent);
+            c->val = (double *)realloc(c->val, sizeof(double) * (size_t)c->cap_ent);
+          }
+          memcpy(c->id + c->n_ent, ids, sizeof(int32_t) * nn);
+          memcpy(c->val + c->n_ent, vals, sizeof(double) * nn);
+          c->n_ent += nn;
+          c->cnt[6 * (g - c->g0) + 2 * i + side] = nn;
+        }
+      }
+    }
+#pragma omp critical
+    if (my_st != ORC_OK && st == ORC_OK) st = my_st;
+    free(tb); free(rb); free(ids); free(vals); orc_work_free(w);
+  }
+  if (st != ORC_OK) { orc_operator_free(op); *status = st; return NULL; }
+  return op;
+}
+
+int64_t orc_operator_entries(const orc_operator *op) {
+  int64_t t = 0;
+  for (int64_t k = 0; k < op->nchunk; k++) t += op->c[k].n_ent;
+  return t;
+}
+
+/* y = K x from the stored vectors: per (g, i), y += W [R (L.x) + L (R.x)].
+   Chunk k adds into its own copy of y; the copies are added in chunk order. */
+void orc_operator_apply(const orc_operator *op, const double *x, double *y) {
+  const int64_t n = op->n > 0 ? op->n : 1;
+  double *yt = (double *)calloc((size_t)op->nchunk * (size_t)n, sizeof(double));
+#pragma omp parallel for schedule(static, 1)
+  for (int64_t k = 0; k < op->nchunk; k++) {
+    const orc_op_chunk *c = &op->c[k];
+    double *yl = yt + (size_t)k * (size_t)n;
+    int64_t e = 0;
+    for (int64_t g = c->g0; g < c->g1; g++) {
+      for (int i = 0; i < 3; i++) {
+        const int64_t q = 6 * (g - c->g0) + 2 * i;
+        const int nl = c->cnt[q], nr = c->cnt[q + 1];
+        const int32_t *Li = c->id + e, *Ri = c->id + e + nl;
+        const double *Lv = c->val + e, *Rv = c->val + e + nl;
+        double lx = 0.0, rx = 0.0;
+        for (int b = 0; b < nl; b++) lx += Lv[b] * x[Li[b]];
+        for (int b = 0; b < nr; b++) rx += Rv[b] * x[Ri[b]];
+        const double W = c->W[3 * (g - c->g0) + i];
+        for (int a = 0; a < nr; a++) yl[Ri[a]] += W * (Rv[a] * lx);
+        for (int a = 0; a < nl; a++) yl[Li[a]] += W * (Lv[a] * rx);
+        e += nl + nr;
+      }
     }
   }
-  free(tb); free(rb); free(Li); free(Ri); free(Lv); free(Rv); orc_work_free(w);
-  return st;
+  for (int64_t j = 0; j < op->n; j++) {
+    double acc = 0.0;
+    for (int64_t k = 0; k < op->nchunk; k++) acc += yt[(size_t)k * (size_t)n + j];
+    y[j] = acc;
+  }
+  free(yt);
+}
+
+/* Diagonal of K from the stored vectors: K_jj = sum over (g, i) of
+   2 W L(j) R(j) (the ids of each vector are ascending, so a merge finds the
+   nodes on both sides). */
+void orc_operator_diagonal(const orc_operator *op, double *d) {
+  const int64_t n = op->n > 0 ? op->n : 1;
+  double *dt = (double *)calloc((size_t)op->nchunk * (size_t)n, sizeof(double));
+#pragma omp parallel for schedule(static, 1)
+  for (int64_t k = 0; k < op->nchunk; k++) {
+    const orc_op_chunk *c = &op->c[k];
+    double *dl = dt + (size_t)k * (size_t)n;
+    int64_t e = 0;
+    for (int64_t g = c->g0; g < c->g1; g++) {
+      for (int i = 0; i < 3; i++) {
+        const int64_t q = 6 * (g - c->g0) + 2 * i;
+        const int nl = c->cnt[q], nr = c->cnt[q + 1];
+        const int32_t *Li = c->id + e, *Ri = c->id + e + nl;
+        const double *Lv = c->val + e, *Rv = c->val + e + nl;
+        const double W = c->W[3 * (g - c->g0) + i];
+        int a = 0, b = 0;
+        while (a < nl && b < nr) {
+          if (Li[a] < Ri[b]) a++;
+          else if (Ri[b] < Li[a]) b++;
+          else { dl[Li[a]] += 2.0 * W * (Lv[a] * Rv[b]); a++; b++; }
+        }
+        e += nl + nr;
+      }
+    }
+  }
+  for (int64_t j = 0; j < op->n; j++) {
+    double acc = 0.0;
+    for (int64_t k = 0; k < op->nchunk; k++) acc += dt[(size_t)k * (size_t)n + j];
+    d[j] = acc;
+  }
+  free(dt);
+}
+
+/* OpenMP threads of the parallel oracle loops (0 or less: leave unchanged);
+   returns the number now in use. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* Sums for the adjoint (lambda = K^{-1} dJ/du, K symmetric):

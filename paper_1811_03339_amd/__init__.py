@@ -25,7 +25,7 @@ FPDE_SRC_ONE, FPDE_SRC_USER, FPDE_SRC_CUBE_MMS, FPDE_SRC_BALL_MMS, FPDE_SRC_SQUA
 FPDE_COEF_SEC3, FPDE_COEF_USER, FPDE_COEF_CONST = 0, 1, 2
 
 STATUS = {
-    0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EMESH_NONMANIFOLD", -3: "FPDE_EMESH_DEGENERATE",
+    0: "FPDE_OK", -1: "FPDE_EINVAL", -2: "FPDE_EMESH_NONMANIFOLD", -3: "FPDE_EMESH_DEGENERATE", -4: "FPDE_EMESH_NONCONVEX",
     -5: "FPDE_EPATH", -6: "FPDE_EALPHA", -7: "FPDE_ENOTSPD", -8: "FPDE_ENOCONV", -9: "FPDE_EHIP",
     -10: "FPDE_ENOMEM", -11: "FPDE_EUNSUPPORTED", -12: "FPDE_ESINGULAR",
 }

@@ -4,6 +4,11 @@ forward(alpha, K) -> u = K(alpha, K)^{-1} b on the device (fpde_assemble +
 fpde_solve).  backward(gbar) -> lam = K^{-1} gbar with the stored factor
 (K is symmetric; fpde_solve_factored), then the adjoint kernel re-walks every
 path and returns dJ/dalpha and dJ/dK (fpde_adjoint).
+
+The adjoint sums hold for a load vector that does not depend on alpha or K
+(f = 1 or source values given at the Gauss points).  The manufactured source
+of the unit cube is a function of both, so it is refused here rather than
+differentiated only through the matrix.
 """
 from __future__ import annotations
 
@@ -13,7 +18,10 @@ import torch
 class FracSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, alpha, K, mesh, quad_points=4, precision=0, source=0, f_gauss=None):
-        from . import params, solve_problem
+        from . import FPDE_SRC_ONE, FPDE_SRC_USER, params, solve_problem
+        if source not in (FPDE_SRC_ONE, FPDE_SRC_USER):
+            raise ValueError("FracSolve: the load vector must not depend on alpha or K "
+                             "(FPDE_SRC_ONE or FPDE_SRC_USER)")
         a = float(alpha.detach().cpu())
         k = [float(v) for v in K.detach().cpu()]
         p = params(a, k, quad_points=quad_points, precision=precision, source=source)

@@ -7,6 +7,7 @@
 // that contain a given m-face (found through vertex -> element lists).
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -224,6 +225,81 @@ __global__ void k_boundary(const int32_t *__restrict__ tet, const int32_t *__res
   }
 }
 
+// Convexity of the domain (the chord bounds a_i(x), b_i(x) of Sec. 1 eq. (1)
+// assume a convex domain).  A polyhedron is convex exactly when every one of
+// its vertices lies on the inner side of the plane of every boundary face.
+// Plane of boundary face f of element t: unit normal pointing away from the
+// element's opposite vertex f, offset n . p0.
+__global__ void k_bface_planes(const double *__restrict__ xyz, const int32_t *__restrict__ tet,
+                               const int32_t *__restrict__ nbr4, int64_t nt, double4 *__restrict__ planes,
+                               unsigned long long *__restrict__ count) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 4 * nt || nbr4[k] >= 0) return;
+  const int64_t t = k >> 2;
+  const int f = (int)(k & 3);
+  double p[3][3];
+  int n = 0;
+  for (int j = 0; j < 4; j++) {
+    if (j == f) continue;
+    for (int d = 0; d < 3; d++) p[n][d] = xyz[3 * (int64_t)tet[4 * t + j] + d];
+    n++;
+  }
+  const double *q = xyz + 3 * (int64_t)tet[4 * t + f];
+  double a[3], b[3];
+  for (int d = 0; d < 3; d++) {
+    a[d] = p[1][d] - p[0][d];
+    b[d] = p[2][d] - p[0][d];
+  }
+  double nx = a[1] * b[2] - a[2] * b[1];
+  double ny = a[2] * b[0] - a[0] * b[2];
+  double nz = a[0] * b[1] - a[1] * b[0];
+  const double len = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= len;
+  ny /= len;
+  nz /= len;
+  if (nx * (q[0] - p[0][0]) + ny * (q[1] - p[0][1]) + nz * (q[2] - p[0][2]) > 0.0) {
+    nx = -nx;
+    ny = -ny;
+    nz = -nz;
+  }
+  const unsigned long long slot = atomicAdd(count, 1ull);
+  planes[slot] = make_double4(nx, ny, nz, nx * p[0][0] + ny * p[0][1] + nz * p[0][2]);
+}
+
+// every used vertex against every boundary plane, planes staged through LDS
+// 256 at a time; a vertex more than tol outside a plane marks the mesh
+// non-convex (aux = that vertex)
+__global__ void __launch_bounds__(256) k_convex(const double *__restrict__ xyz, const int32_t *__restrict__ used,
+                                                int64_t nv, const double4 *__restrict__ planes,
+                                                const unsigned long long *__restrict__ count, double tol,
+                                                int32_t *flag, int64_t *flag_aux) {
+  __shared__ double4 pl[256];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = v < nv && used[v];
+  double x = 0.0, y = 0.0, z = 0.0;
+  if (live) {
+    x = xyz[3 * v];
+    y = xyz[3 * v + 1];
+    z = xyz[3 * v + 2];
+  }
+  const int64_t nb = (int64_t)*count;
+  bool out = false;
+  for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+    __syncthreads();
+    if (c0 + threadIdx.x < nb) pl[threadIdx.x] = planes[c0 + threadIdx.x];
+    __syncthreads();
+    const int cn = (int)(nb - c0 < 256 ? nb - c0 : 256);
+    for (int c = 0; c < cn; c++) {
+      const double4 P = pl[c];
+      out |= (P.x * x + P.y * y + P.z * z) - P.w > tol;
+    }
+  }
+  if (live && out) {
+    set_flag(flag, FPDE_EMESH_NONCONVEX);
+    atomicCAS((unsigned long long *)flag_aux, ~0ull, (unsigned long long)v);
+  }
+}
+
 __global__ void k_isdof(const int32_t *__restrict__ used, const int32_t *__restrict__ bnd, int64_t nv,
                         int32_t *__restrict__ isdof) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -285,6 +361,7 @@ extern "C" const char *fpde_status_string(int s) {
     case FPDE_EINVAL: return "invalid argument";
     case FPDE_EMESH_NONMANIFOLD: return "non-manifold mesh: a face is shared by more than two elements";
     case FPDE_EMESH_DEGENERATE: return "degenerate element (zero volume or repeated vertex)";
+    case FPDE_EMESH_NONCONVEX: return "non-convex domain: a vertex lies outside the plane of a boundary face";
     case FPDE_EPATH: return "integration path: no continuation found or max_steps exceeded";
     case FPDE_EALPHA: return "alpha outside (1, 2] or a coefficient K_i <= 0";
     case FPDE_ENOTSPD: return "Cholesky pivot <= 0: matrix not positive definite";
@@ -297,7 +374,7 @@ extern "C" const char *fpde_status_string(int s) {
   }
 }
 
-static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, hipStream_t s) {
+static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, double convex_tol, hipStream_t s) {
   const int64_t nv = m->nv, nt = m->nt, nf = 4 * nt;
   FPDE_HIP(hipGetDevice(&m->device));
   FPDE_TRY(dalloc(&m->xyz, 3 * nv));
@@ -334,13 +411,15 @@ static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, hipSt
   int32_t *val = nullptr, *val2 = nullptr, *nbr4 = nullptr;
   int32_t *used = nullptr, *bnd = nullptr, *isdof = nullptr, *scan = nullptr, *cnt = nullptr;
   uint32_t *vkey = nullptr, *vkey2 = nullptr;
-  unsigned long long *nbf = nullptr;
+  unsigned long long *nbf = nullptr, *nplanes = nullptr;
+  double4 *planes = nullptr;
   void *tmp = nullptr;
   size_t tmp_bytes = 0;
   int st = FPDE_OK;
   auto cleanup = [&]() {
     dfree(key); dfree(key2); dfree(val); dfree(val2); dfree(nbr4); dfree(used); dfree(bnd);
-    dfree(isdof); dfree(scan); dfree(cnt); dfree(vkey); dfree(vkey2); dfree(nbf);
+    dfree(isdof); dfree(scan); dfree(cnt); dfree(vkey); dfree(vkey2); dfree(nbf); dfree(nplanes);
+    dfree(planes);
     if (tmp) (void)hipFree(tmp);
   };
 #define STEP(x)                \
@@ -365,6 +444,7 @@ static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, hipSt
   STEP(dalloc(&vkey, nf));
   STEP(dalloc(&vkey2, nf));
   STEP(dalloc(&nbf, 1));
+  STEP(dalloc(&nplanes, 1));
 
   k_face_keys<<<nblk(nf), 256, 0, s>>>(m->tet, nt, key, val);
   int end_bit = 42 + bits_for((uint64_t)nv);
@@ -395,6 +475,11 @@ static int mesh_build(fpde_mesh *m, const double *xyz, const int32_t *tet, hipSt
   STEPH(hipStreamSynchronize(s));
   m->ndof = ndof;
   m->nbf = (int64_t)nbf_h;
+  // the domain must be convex: every vertex inside every boundary-face plane
+  STEP(dalloc(&planes, nbf_h > 0 ? nbf_h : 1));
+  STEPH(hipMemsetAsync(nplanes, 0, sizeof(unsigned long long), s));
+  k_bface_planes<<<nblk(nf), 256, 0, s>>>(m->xyz, m->tet, nbr4, nt, planes, nplanes);
+  k_convex<<<nblk(nv), 256, 0, s>>>(m->xyz, used, nv, planes, nplanes, convex_tol, m->flag, m->flag_aux);
   STEP(dalloc(&m->vert_of_dof, ndof > 0 ? ndof : 1));
   k_dof<<<nblk(nv), 256, 0, s>>>(isdof, scan, nv, m->dof, m->vert_of_dof);
   k_finalize<<<nblk(nt), 256, 0, s>>>(m->tet, nbr4, m->dof, nt, m->rec);
@@ -448,10 +533,22 @@ extern "C" int fpde_mesh_create(const double *xyz, int64_t n_vert, const int32_t
     if (tet[k] < 0 || tet[k] >= n_vert) return FPDE_EINVAL;
   for (int64_t k = 0; k < 3 * n_vert; k++)
     if (!std::isfinite(xyz[k])) return FPDE_EINVAL;
+  // convexity tolerance: 1e-12 of the diagonal of the vertices' bounding box
+  // (an upper bound of the domain's diameter)
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; d++) lo[d] = hi[d] = xyz[d];
+  for (int64_t v = 1; v < n_vert; v++)
+    for (int d = 0; d < 3; d++) {
+      lo[d] = std::min(lo[d], xyz[3 * v + d]);
+      hi[d] = std::max(hi[d], xyz[3 * v + d]);
+    }
+  double diag = 0.0;
+  for (int d = 0; d < 3; d++) diag += (hi[d] - lo[d]) * (hi[d] - lo[d]);
+  diag = std::sqrt(diag);
   fpde_mesh *m = new fpde_mesh();
   m->nv = n_vert;
   m->nt = n_tet;
-  int st = mesh_build(m, xyz, tet, S(stream));
+  int st = mesh_build(m, xyz, tet, 1e-12 * diag, S(stream));
   if (st != FPDE_OK) {
     fpde_mesh_destroy(m);
     return st;

@@ -97,3 +97,12 @@ def test_params2d_layout_and_null_handles():
     tri = np.array([[0, 1, 5]], dtype=np.int32)
     assert L.fpde_mesh2d_create(xy.ctypes.data_as(ctypes.c_void_p), 3, tri.ctypes.data_as(ctypes.c_void_p), 1,
                                 None, ctypes.byref(h)) == -1
+
+
+def test_fracsolve_refuses_sources_that_depend_on_alpha_or_K():
+    import torch
+    a = torch.tensor(1.5, dtype=torch.float64, requires_grad=True)
+    k = torch.ones(3, dtype=torch.float64, requires_grad=True)
+    # rejected before any device work (the mesh is never touched)
+    with pytest.raises(ValueError):
+        F.FracSolve.apply(a, k, None, 4, F.FPDE_FP64, F.FPDE_SRC_CUBE_MMS)

@@ -1,20 +1,26 @@
 """Full-size cases on the GPU, checked on outputs the oracle can afford.
 
 * sphere150k (~152k elements, ~25k unknowns, 11-point rule, alpha = 1.7):
-  sampled paths bit-exact, sampled derivative vectors, K x against the
-  oracle's matrix-free product, FP64 and mixed solutions (mixed within 1e-6
-  of FP64 after refinement to 1e-8); K on the template as CSR (its product
-  equal to the matrix-free one), CG on it and matrix-free within 1e-7 of
-  the FP64 Cholesky solution.
+  sampled paths bit-exact, sampled derivative vectors, 24 sampled rows of
+  the FP64 and of the FP32 stiffness matrix against the oracle's rows (its
+  tubes of more than 200 nodes take the banded accumulation), K x against
+  the oracle's matrix-free product, the FP64 and the refined mixed solution
+  against the oracle's solution (Jacobi-preconditioned CG on the oracle's
+  operator to 1e-14); K on the template as CSR (its product equal to the
+  matrix-free one), CG on it and matrix-free within 1e-7 of the FP64
+  Cholesky solution.
 * ball40k (~42k elements, ~6.6k unknowns, 4-point rule): adjoint gradients of
   ||u - u_obs||^2 at alpha = 1.4, K = (1,1,1) against the oracle's adjoint and
   central differences (h = 1e-6); u_obs from alpha = 1.6, K = (1.2, 0.8, 1.0)
   plus N(0, 1e-3^2) noise (seed 40).
 * ellipsoid400k (~400k elements, ~67k unknowns, 11-point rule,
   alpha = 1.3): mixed precision with an FP32 matrix of ~18 GB; sampled paths
-  and derivative vectors against the oracle, K x (FP32, dense) against the
-  FP64 matrix-free product, refinement to 1e-8; the same system by
-  matrix-free CG (no dense matrix) within 1e-6 of the refined solution.
+  and derivative vectors, 16 sampled rows of the FP32 matrix, the load
+  vector, the dense FP32 product K x and the GPU's FP64 matrix-free product
+  against the oracle (its matrix-free product on the same vector), and the
+  refined solution's residual measured with the oracle's product; the same
+  system by matrix-free CG (no dense matrix) within 1e-6 of the refined
+  solution.
 * ball_h076 (the finest mesh of Table 3, ~8.2k unknowns), the divergence-form
   problem of Sec. 3 at beta = (0.6, 0.7, 0.8): the whole matrix, the load
   vector and the LU solution against the oracle (LAPACK LU).
@@ -71,6 +77,24 @@ def sampled_paths_and_values(om, gm, nq, alpha, G, rng, n_ranges=2, span=200, n_
                 assert abs(got[int(a)] - v) <= 1e-10 * scale
 
 
+def sample_rows(n, rng, count):
+    return np.unique(np.concatenate([[0, n - 1], rng.integers(1, n - 1, size=count - 2)]))
+
+
+def riesz_rows(om, nq, alpha, K, rows):
+    """Rows of the Riesz stiffness matrix from the oracle: the uniform form
+    with trial and test orders alpha/2 on every axis and both coefficients
+    c_alpha K_i (the instance pinned on the CPU)."""
+    g = alpha / 2.0
+    ca = oracle.c_alpha(alpha)
+    coef = [ca * K[i] for i in range(3)] * 2
+    return om.assemble_form(nq, (g, g, g), (g, g, g), coef, rows=rows)
+
+
+def gpu_rows(A, rows):
+    return A[torch.tensor(rows, device=A.device)].double().cpu().numpy()
+
+
 def timed(fn):
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -90,18 +114,32 @@ def test_sphere150k_fp64_and_mixed():
     log("[sphere150k] sampled paths and derivative vectors match")
     p64 = F.params(alpha, K, quad_points=nq)
     _, t_plan = timed(lambda: gm.plan(nq))
+    info_plan = gm.plan_info(nq)
+    assert info_plan["max_tube_nodes"] > 200  # the banded layout is reached
     A = torch.empty((n, n), dtype=torch.float64, device="cuda")
     b = torch.empty(n, dtype=torch.float64, device="cuda")
     _, t_asm = timed(lambda: gm.assemble(p64, A, b))
+    rows = sample_rows(n, rng, 24)
+    Ko = riesz_rows(om, nq, alpha, K, rows)
+    assert rel(gpu_rows(A, rows), Ko) <= 1e-10
+    log(f"[sphere150k] {len(rows)} rows of K equal the oracle's (tubes up to {info_plan['max_tube_nodes']} nodes)")
     x = torch.tensor(rng.normal(size=n), device="cuda")
     Ax = (A @ x).cpu().numpy()
     y_o = om.apply(nq, alpha, K, x.cpu().numpy())
     assert rel(Ax, y_o) <= 1e-10
-    assert rel(b.cpu().numpy(), om.load(nq)) <= 1e-10
+    b_o = om.load(nq)
+    assert rel(b.cpu().numpy(), b_o) <= 1e-10
     u64 = torch.empty_like(b)
     info, t_sol = timed(lambda: gm.solve(p64, A, b, u64))
     assert info.final_rel_residual <= 1e-12
     log(f"[sphere150k] n={n} plan {t_plan:.2f}s FP64 assemble {t_asm:.3f}s solve {t_sol:.3f}s")
+    # the oracle's solution: Jacobi-preconditioned CG on its operator
+    op = oracle.OracleOperator(om, nq, alpha, K)
+    u_o, it_o = oracle.cg(op.apply, b_o, tol=1e-14, dinv=1.0 / op.diagonal())
+    del op
+    err64 = rel(u64.cpu().numpy(), u_o)
+    assert err64 <= 1e-10
+    log(f"[sphere150k] FP64 solution {err64:.1e} from the oracle's ({it_o} CG iterations)")
     del A
     gc.collect()
     torch.cuda.empty_cache()
@@ -109,12 +147,13 @@ def test_sphere150k_fp64_and_mixed():
     A32 = torch.empty((n, n), dtype=torch.float32, device="cuda")
     u32 = torch.empty_like(b)
     _, t_asm32 = timed(lambda: gm.assemble(pmx, A32, b))
+    assert rel(gpu_rows(A32, rows), Ko) <= 1e-6
     info32, t_sol32 = timed(lambda: gm.solve(pmx, A32, b, u32))
     assert info32.final_rel_residual <= 1e-8
-    err = float((u32 - u64).abs().max() / u64.abs().max())
+    err = rel(u32.cpu().numpy(), u_o)
     assert err <= 1e-6
     log(f"[sphere150k] mixed assemble {t_asm32:.3f}s solve {t_sol32:.3f}s ir_iters {info32.ir_iters} "
-        f"rel err vs FP64 {err:.2e} speedup {(t_asm + t_sol) / (t_asm32 + t_sol32):.2f}x")
+        f"rel err vs the oracle {err:.2e} speedup {(t_asm + t_sol) / (t_asm32 + t_sol32):.2f}x")
     del A32
     gc.collect()
     torch.cuda.empty_cache()
@@ -205,14 +244,32 @@ def test_ellipsoid400k_mixed():
     b = torch.empty(n, dtype=torch.float64, device="cuda")
     gm.timing(True)
     _, t_asm = timed(lambda: gm.assemble(pmx, A32, b))
+    # against the oracle: sampled rows of the FP32 matrix, the load vector,
+    # K x from the dense FP32 matrix (accumulated in FP64) and the GPU's
+    # FP64 matrix-free product, both on the same vector as the oracle's
+    rows = sample_rows(n, rng, 16)
+    Ko = riesz_rows(om, nq, alpha, K, rows)
+    assert rel(gpu_rows(A32, rows), Ko) <= 1e-6
+    log(f"[ellipsoid400k] {len(rows)} rows of the FP32 matrix match the oracle's")
+    assert rel(b.cpu().numpy(), om.load(nq)) <= 1e-10
     x = torch.tensor(rng.normal(size=n), device="cuda")
-    Ax32 = (A32 @ x.float()).double()
+    Ax32 = torch.empty_like(x)
+    for r0 in range(0, n, 4096):
+        Ax32[r0:r0 + 4096] = A32[r0:r0 + 4096].double() @ x
     y = torch.empty_like(x)
     gm.apply(pmx, x, y)
-    assert float((Ax32 - y).abs().max() / y.abs().max()) <= 1e-5
+    y_o = om.apply(nq, alpha, K, x.cpu().numpy())
+    assert rel(Ax32.cpu().numpy(), y_o) <= 1e-6
+    assert rel(y.cpu().numpy(), y_o) <= 1e-10
+    log("[ellipsoid400k] K x (dense FP32 and matrix-free FP64) matches the oracle's product")
     u = torch.empty_like(b)
     info32, t_sol = timed(lambda: gm.solve(pmx, A32, b, u))
     assert info32.final_rel_residual <= 1e-8
+    # the refined solution's residual with the oracle's own product
+    r_o = om.load(nq) - om.apply(nq, alpha, K, u.cpu().numpy())
+    res_o = float(np.linalg.norm(r_o) / np.linalg.norm(om.load(nq)))
+    assert res_o <= 1e-8
+    log(f"[ellipsoid400k] refined solution: residual {res_o:.2e} with the oracle's product")
     log(f"[ellipsoid400k] n={n} FP32 matrix {n * n * 4 / 2**30:.1f} GiB, assemble {t_asm:.2f}s, "
         f"solve {t_sol:.2f}s, ir_iters {info32.ir_iters}, residual {info32.final_rel_residual:.2e}")
     stages = {k: round(v[0], 1) for k, v in gm.stage_times().items() if v[1]}

@@ -102,6 +102,7 @@ CASES = [
     ("sphere_small", 1.2, (1.0, 0.5, 2.0), 11, "one"),
     ("sphere_small", 1.8, (1.0, 0.5, 2.0), 4, "one"),
     ("sphere20k", 1.5, (1.0, 0.5, 2.0), 4, "one"),
+    ("sphere20k", 1.8, (1.0, 0.5, 2.0), 11, "one"),
 ]
 
 
@@ -260,3 +261,52 @@ def test_mesh_errors():
     with pytest.raises(F.FpdeError) as e:
         F.Mesh(flat, np.array([[0, 1, 2, 3]], dtype=np.int32))
     assert e.value.status == -3
+
+
+def test_nonconvex_meshes_are_rejected():
+    """The chord bounds of Sec. 1 eq. (1) need a convex domain: the L-shaped
+    prism and a cube with a 1e-9 bump or dent in one face are refused with
+    FPDE_EMESH_NONCONVEX (as by the oracle); a 1e-15 move is inside the
+    tolerance and accepted."""
+    from fpde_inputs import notched_cube
+    m = notched_cube(4)
+    print(f"[nonconvex] notched cube {m.n_tet} elements", flush=True)
+    with pytest.raises(F.FpdeError) as e:
+        F.Mesh(m.xyz, m.tet)
+    assert e.value.status == -4
+    c = kuhn_cube(4)
+    v = int(np.flatnonzero(np.all(np.abs(c.xyz - [0.5, 0.5, 1.0]) < 1e-14, axis=1))[0])
+    for dz, ok in ((1e-9, False), (-1e-9, False), (1e-15, True), (-1e-15, True)):
+        xyz = c.xyz.copy()
+        xyz[v, 2] += dz
+        if ok:
+            assert F.Mesh(xyz, c.tet).n_dof == 27
+        else:
+            with pytest.raises(F.FpdeError) as e:
+                F.Mesh(xyz, c.tet)
+            assert e.value.status == -4
+    # a handle made afterwards works
+    assert F.Mesh(c.xyz, c.tet).n_dof == 27
+
+
+def test_refinement_that_misses_its_tolerance_reports_enoconv():
+    """FPDE_ENOCONV with the sweep count and residual filled in: one sweep
+    cannot reach a relative residual of 1e-30."""
+    import ctypes
+    m, om, gm = mesh_pair("sphere_small")
+    print("[enoconv] sphere_small mixed, ir_max_iter = 1", flush=True)
+    p = F.params(1.5, quad_points=4, precision=F.FPDE_MIXED, ir_tol=1e-30, ir_max_iter=1)
+    A = F.new_matrix(gm, F.FPDE_MIXED)
+    b = torch.empty(gm.n_dof, dtype=torch.float64, device="cuda")
+    gm.assemble(p, A, b)
+    u = torch.empty_like(b)
+    info = F.fpde_solve_info()
+    st = F._lib().fpde_solve(gm._h, ctypes.byref(p), F._ptr(A), A.stride(0), F._ptr(b), F._ptr(u),
+                             ctypes.byref(info), F._stream())
+    assert st == -8
+    assert info.ir_iters == 1
+    assert 0.0 < info.final_rel_residual < 1e-6
+    # the same factor refined to a reachable tolerance converges
+    p2 = F.params(1.5, quad_points=4, precision=F.FPDE_MIXED, ir_tol=1e-8)
+    info2 = gm.solve_factored(p2, A, b, u)
+    assert info2.final_rel_residual <= 1e-8

@@ -113,7 +113,16 @@ def test_rows_variant_keeps_the_listed_rows():
     K = om.assemble_form(4, a, b, coef)
     n = K.shape[0]
     rows = np.array([n - 1, 0, 17, n // 2, 5])
-    R = om.assemble_form(4, a, b, coef, rows=rows)
+    # one thread sums in the whole matrix's order: the same bits
+    before = oracle.set_threads()
+    try:
+        oracle.set_threads(1)
+        R = om.assemble_form(4, a, b, coef, rows=rows)
+    finally:
+        oracle.set_threads(before)
     assert np.array_equal(R, K[rows])
+    # several threads add their Gauss points' parts in thread order
+    R = om.assemble_form(4, a, b, coef, rows=rows)
+    assert np.abs(R - K[rows]).max() <= 1e-14 * np.abs(K).max()
     with pytest.raises(oracle.OracleError):
         om.assemble_form(4, a, b, coef, rows=np.array([3, 3]))
