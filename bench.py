@@ -1,29 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the fractional FEM hot path on one MI355X.
 
-Workload (synthetic, seeded): the convex hull of 400 random points on the
-unit sphere filled with a jittered body-centred-cubic lattice (19 689
-elements, 3 472 nodes, 3 072 interior unknowns), Riesz orders
-alpha in {1.2, 1.5, 1.8}, K = (1, 0.5, 2), the 4- and 11-point element rules.
+Headline workload (synthetic, seeded): the convex hull of 2000 random points
+in the ellipsoid with semi-axes (1, 0.7, 0.4), filled with a jittered
+body-centred-cubic lattice (~400k elements, ~67k nodes), Riesz order
+alpha = 1.3 (the timed passes alternate 1.30 / 1.31 so every pass walks its
+paths again instead of reusing the previous pass's derivative values),
+K = (1, 1, 1), the 11-point element rule.
 
-One step = for each rule and each alpha: assemble (path walk + closed-form
-derivatives, accumulation of the dense FP64 stiffness matrix, load vector)
-and solve (dense FP64 Cholesky + triangular solves) -- six assembly+solve
-passes.  The mesh set-up and the symbolic plan (the template, built once per
-mesh and rule) happen before the timed region and are reported apart.
+One step = one mixed-precision assembly + solve pass on that mesh: path walk
+and closed-form derivatives (FP64), accumulation of the dense stiffness
+matrix stored in FP32 (~18 GB), load vector, FP32 Cholesky, then refinement
+with FP64 residuals from the matrix-free product until ||b - K u|| / ||b||
+<= 1e-8.  Inputs are resident on the device when the timed region starts;
+the mesh set-up and the symbolic plan (built once per mesh and rule) happen
+before it and are reported apart.
 
-value = Gauss-point paths per second over the timed steps (6 half-rays per
-Gauss point, summed over the six passes, divided by the step time).
-The single JSON line on stdout also carries the per-stage times (from a few
-further steps with every stage timed), the roofline of the dominant kernel
-(its launch durations measured over the timed steps with HIP events inside
-the library on the launch stream; only the two candidate stages carry
-events there), the mixed-precision arm, K on the template of Sec. 2.3
-as CSR with conjugate gradients (CSR and matrix-free), the general uniform
-form (c D^alpha u, D^beta v) with per-axis orders, the two-dimensional
-variant on a disk, the divergence-form
-problem of Sec. 3 on the finest mesh of Table 3 (assembly + LU + solve, with the LU
-against its FP64 roofline) and the CPU oracle baseline.
+value = Gauss-point paths per second of the whole step (6 half-rays per
+Gauss point divided by the step time).  Beside it on the single JSON line:
+assembly+solve seconds per step, paths/s of walk+eval alone, the FP64 arm on
+the same mesh (FP64 matrix, ~36 GB, FP64 Cholesky) with the mixed/FP64
+speedup and the distance between the two solutions, the per-stage times, the
+roofline of the step's dominant kernel (launch durations measured over the
+timed steps with HIP events inside the library on the launch stream), and
+the CPU oracle on a bounded sample of the same workload.  Secondary sections
+(not the headline): FP64 vs mixed on the ~150k-element sphere hull, the
+adjoint gradient on the ~40k-element ball, the six-system batch on the
+~20k-element sphere hull, sparse template storage with CG, the general
+uniform form, the two-dimensional variant and the divergence-form problem of
+Sec. 3.
 """
 from __future__ import annotations
 
@@ -40,13 +45,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "assembly+solve s & Gauss-pt paths/s at N nodes, FP64 vs mixed @1e-6 rel err"
-WORKLOAD = "sphere20k"
+WORKLOAD = "ellipsoid400k"
+HEAD_ALPHAS = (1.30, 1.31)
+HEAD_NQ = 11
+HEAD_K = (1.0, 1.0, 1.0)
+C2_WORKLOAD = "sphere20k"
 ALPHAS = (1.2, 1.5, 1.8)
 RULES = (4, 11)
 BREAKDOWN_STEPS = 5  # steps with every stage timed, after the timed steps
 KCOEF = (1.0, 0.5, 2.0)
 HBM_PEAK = 8.0e12        # B/s
 FP64_PEAK = 78.6e12      # FLOP/s, vector and matrix
+FP32_PEAK = 157.3e12     # FLOP/s, matrix cores
+FP16_PEAK = 2.5e15       # FLOP/s, dense matrix cores
 CSRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc")
 # HBM counter summaries (profiles/): unit -> (file, sources its kernels are built from)
 PMC = {
@@ -259,7 +270,7 @@ def bench_sparse(F, torch, gm, reps=3):
     gm.assemble(p, A, b)
     gm.solve(p, A, b, ud, info=False)
     del A
-    out = {"workload": f"{WORKLOAD}, alpha = 1.5, 4-point rule", "template_ms": t_tpl, "nnz": nnz,
+    out = {"workload": f"{C2_WORKLOAD}, alpha = 1.5, 4-point rule", "template_ms": t_tpl, "nnz": nnz,
            "density": nnz / float(n * n), "csr_bytes": nnz * 12 + (n + 1) * 8, "dense_bytes": n * n * 8,
            "csr_assembly_ms": t_asm,
            "spmv": {"ms": t_mv, "bound": "hbm", "algorithmic_bytes": by, "achieved": by / (t_mv / 1e3) / 1e9,
@@ -301,7 +312,7 @@ def bench_form(F, torch, gm, info4, reps=3):
     # algorithmic work: per entry product of a pair two products (trial x
     # test scaled by cl, test x trial scaled by cr), a multiply-add each
     fl = 4.0 * info4["pairs"]
-    return {"workload": f"{WORKLOAD}, 4-point rule, alpha {list(FORM_ALPHA)}, beta {list(FORM_BETA)} "
+    return {"workload": f"{C2_WORKLOAD}, 4-point rule, alpha {list(FORM_ALPHA)}, beta {list(FORM_BETA)} "
                         f"(alternating), constant coefficients",
             "pass_ms": sorted(ts)[len(ts) // 2],
             "stages_ms_per_pass": {k: v[0] / reps for k, v in st.items() if v[1] > 0},
@@ -355,42 +366,215 @@ def bench_plane(F, torch, reps=3):
     return out
 
 
-def cpu_baseline(mesh_np):
-    """The oracle, unchanged, single-threaded, on one full step."""
-    from threadpoolctl import threadpool_limits
+ADJ_WORKLOAD = "ball40k"
+
+
+def bench_adjoint(F, torch, dev):
+    """Adjoint gradients on the unit-ball hull (~42k elements): loss
+    J = ||u_h - u_obs||^2 at alpha = 1.4, K = (1, 1, 1) (4-point rule), u_obs
+    from alpha = 1.6, K = (1.2, 0.8, 1.0) plus N(0, 1e-3^2) noise (seed 40).
+    One forward (assembly + FP64 solve) and backward (adjoint solve with the
+    stored factor + the adjoint kernel re-walking every path), timed, and the
+    gradient against central differences with h = 1e-6."""
+    import numpy as np
+    from fpde_inputs import workload_mesh
+    mesh = workload_mesh(ADJ_WORKLOAD)
+    g = F.Mesh(mesh.xyz, mesh.tet)
+    nq = 4
+    g.plan(nq)
+    rng = np.random.default_rng(40)
+    u_obs, _, _ = F.solve_problem(g, F.params(1.6, (1.2, 0.8, 1.0), quad_points=nq), info=False)
+    obs = u_obs + 1e-3 * torch.tensor(rng.normal(size=g.n_dof), device=dev)
+    alpha, K = 1.4, np.array([1.0, 1.0, 1.0])
+
+    def fwd_bwd():
+        a_t = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+        k_t = torch.tensor(K, dtype=torch.float64, requires_grad=True)
+        u = F.FracSolve.apply(a_t, k_t, g, nq)
+        J = torch.sum((u - obs) ** 2)
+        J.backward()
+        return a_t.grad.item(), k_t.grad.numpy().copy()
+
+    fwd_bwd()  # warm-up (values, factor scratch)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ga, gk = fwd_bwd()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+
+    def loss(a, k):
+        uu, _, _ = F.solve_problem(g, F.params(a, k, quad_points=nq), info=False)
+        return float(torch.sum((uu - obs) ** 2))
+
+    h = 1e-6
+    fd_a = (loss(alpha + h, K) - loss(alpha - h, K)) / (2 * h)
+    fd_k = []
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fd_k.append((loss(alpha, K + e) - loss(alpha, K - e)) / (2 * h))
+    fd_k = np.array(fd_k)
+    out = {"workload": f"{ADJ_WORKLOAD}: hull of 800 seeded points on the unit sphere + BCC lattice, {g.n_tet} tets, "
+                       f"{mesh.n_vert} nodes ({g.n_dof} interior), 4-point rule, alpha = 1.4, K = (1, 1, 1)",
+           "forward_backward_s": sorted(ts)[1], "dJ_dalpha": ga, "dJ_dK": gk.tolist(),
+           "fd_dalpha": fd_a, "fd_dK": fd_k.tolist(),
+           "rel_err_dalpha_vs_fd": abs(ga - fd_a) / abs(fd_a),
+           "rel_err_dK_vs_fd": float(np.abs(gk - fd_k).max() / np.abs(fd_k).max()),
+           "fd_step": h}
+    g.close()
+    return out
+
+
+def bench_c2(F, torch, dev, steps=20, warmup=2):
+    """The six-system batch on the ~20k-element sphere hull (3 alphas x 2
+    rules, K = (1, 0.5, 2)): per step the six systems are assembled as one
+    batch (walks beside the accumulations) and factored and solved as one
+    batch.  Also the mixed arm at this size (alpha alternating so that every
+    pass walks again), the template CSR / CG and the general-form sections."""
+    from fpde_inputs import workload_mesh
+    mesh = workload_mesh(C2_WORKLOAD)
+    gm = F.Mesh(mesh.xyz, mesh.tet)
+    info = {}
+    for nq in RULES:
+        gm.plan(nq)
+        info[nq] = gm.plan_info(nq)
+    n = gm.n_dof
+    cases = [(nq, a) for nq in RULES for a in ALPHAS]
+    A = torch.empty((len(cases), n, n), dtype=torch.float64, device=dev)
+    b = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
+    u = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
+    rays_per_step = sum(6 * gm.n_tet * nq for nq in RULES) * len(ALPHAS)
+    step_params = [F.params(a, KCOEF, quad_points=nq) for nq, a in cases]
+
+    def step():
+        gm.assemble_batch(step_params, A, b)
+        gm.solve_batch(A, b, u)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    gm.timing(True)
+    for _ in range(BREAKDOWN_STEPS):
+        step()
+    torch.cuda.synchronize()
+    gm.timing(False)
+    st = gm.stage_times()
+    out = {"workload": f"{C2_WORKLOAD}: hull of 400 seeded points on the unit sphere + BCC lattice, {gm.n_tet} tets, "
+                       f"{mesh.n_vert} nodes ({n} interior); alpha {list(ALPHAS)}, K={list(KCOEF)}, rules "
+                       f"{list(RULES)}; six FP64 systems per step, assembled and solved as batches",
+           "n_dof": n, "ms_per_step": ms, "paths_per_s": rays_per_step / (ms / 1e3),
+           "stages_ms_per_step": {k: v[0] / BREAKDOWN_STEPS for k, v in st.items() if v[1] > 0},
+           "tube_accum": None}
+    if st["accum"][1]:
+        t = st["accum"][0] / st["accum"][1] / 1e3
+        fl = sum(4 * info[nq]["pairs"] for nq in RULES) / len(RULES)
+        out["tube_accum"] = {"bound": "alu", "ms_per_launch": t * 1e3, "flops_per_launch": fl,
+                             "achieved": fl / t / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                             "frac": fl / t / FP64_PEAK,
+                             "note": "4 |L| |R| flops per (g, i): both products W (R L^T + L R^T)"}
+    # mixed arm at this size, alpha alternating so every pass walks again
+    p64s = [F.params(a, KCOEF, quad_points=11) for a in (1.5, 1.51)]
+    pmxs = [F.params(a, KCOEF, quad_points=11, precision=F.FPDE_MIXED, ir_tol=1e-8) for a in (1.5, 1.51)]
+    A32 = torch.empty((n, n), dtype=torch.float32, device=dev)
+    u32 = torch.empty_like(u[0])
+
+    def timed(fn, reps=4):
+        ts, r = [], None
+        for k in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = fn(k)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2], r
+
+    def run64(k):
+        p = p64s[k % 2]
+        gm.assemble(p, A[0], b[0])
+        gm.solve(p, A[0], b[0], u[0], info=False)
+
+    def runmx(k):
+        p = pmxs[k % 2]
+        gm.assemble(p, A32, b[0])
+        return gm.solve(p, A32, b[0], u32)
+
+    t64, _ = timed(run64)
+    tmx, inf = timed(runmx)
+    err = float((u32 - u[0]).abs().max() / u[0].abs().max())  # both at alpha = 1.51
+    out["mixed"] = {"workload": "alpha alternating 1.50 / 1.51, 11-point rule", "fp64_assembly_solve_s": t64 / 1e3,
+                    "mixed_assembly_solve_s": tmx / 1e3, "speedup_vs_fp64": t64 / tmx, "rel_err_vs_fp64": err,
+                    "ir_iters": inf.ir_iters, "final_rel_residual": inf.final_rel_residual}
+    del A32, A
+    torch.cuda.empty_cache()
+    out["sparse"] = bench_sparse(F, torch, gm)
+    out["form"] = bench_form(F, torch, gm, info[4])
+    gm.close()
+    return out
+
+
+def cpu_baseline(om, alpha, K, nq, G, budget_s=10.0):
+    """The oracle as it stands on a bounded sample of the headline workload:
+    its matrix-free product (walk, closed-form derivatives and the sums of
+    Sec. 2.1 for every half-ray of the sampled Gauss points) restricted to a
+    contiguous range of Gauss points sized for about `budget_s` seconds, at
+    one thread and at every host thread.  Gauss-point paths per second."""
+    import numpy as np
 
     import oracle
-    with threadpool_limits(limits=1):
-        om = oracle.OracleMesh(mesh_np.xyz, mesh_np.tet)
-        rays = 0
-        t0 = time.perf_counter()
-        for nq in RULES:
-            for a in ALPHAS:
-                A = om.assemble(nq, a, KCOEF)
-                b = om.load(nq)
-                oracle.solve_spd(A, b)
-                rays += 6 * om.n_tet * nq
-        dt = time.perf_counter() - t0
-    return {"value": rays / dt, "unit": "Gauss-pt paths/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full step ({len(RULES)} rules x {len(ALPHAS)} alphas): dense assembly + load + "
-                      f"LAPACK Cholesky, FP64, 1 thread, {dt:.1f} s"}
+    x = np.random.default_rng(0).normal(size=om.ndof)
+    before = oracle.set_threads()
+    out = {}
+    try:
+        for th in (1, before):
+            oracle.set_threads(th)
+            cal = 2000 * th
+            t0 = time.perf_counter()
+            om.apply_range(nq, alpha, K, x, 0, cal)
+            dt = time.perf_counter() - t0
+            cnt = int(min(G, max(cal, cal * budget_s / max(dt, 1e-3))))
+            g0 = (G - cnt) // 2
+            t0 = time.perf_counter()
+            om.apply_range(nq, alpha, K, x, g0, g0 + cnt)
+            dt = time.perf_counter() - t0
+            out[th] = (6 * cnt / dt, cnt, dt)
+    finally:
+        oracle.set_threads(before)
+    v1, c1, d1 = out[1]
+    vn, cn, dn = out[before]
+    return {"value": vn, "unit": "Gauss-pt paths/s", "cores": before, "kind": "oracle",
+            "sample": f"{WORKLOAD}, alpha {alpha}, {nq}-point rule: the oracle's matrix-free product (walk + "
+                      f"closed-form derivatives + the sums of K x, FP64) over {cn} contiguous Gauss points "
+                      f"({6 * cn} half-rays) of {G} in {dn:.1f} s on {before} threads; one thread: {c1} points "
+                      f"in {d1:.1f} s",
+            "single_thread_value": v1}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision arm")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 arm of the headline workload")
+    ap.add_argument("--no-sections", action="store_true", help="only the headline workload")
     ap.add_argument("--no-sec3", action="store_true", help="skip the Sec. 3 divergence-form problem")
-    ap.add_argument("--no-sparse", action="store_true", help="skip the template-CSR / CG section")
-    ap.add_argument("--no-form", action="store_true", help="skip the general-form section")
+    ap.add_argument("--no-c2", action="store_true", help="skip the six-system batch section (and sparse, form)")
     ap.add_argument("--no-plane", action="store_true", help="skip the two-dimensional section")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint section")
     ap.add_argument("--no-mixed-large", action="store_true",
                     help="skip FP64 vs mixed at the 25k-unknown mesh")
-    ap.add_argument("--no-sequential", action="store_true",
-                    help="skip the one-step comparison that solves the systems one at a time")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -420,45 +604,29 @@ def main():
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t)
     t = time.perf_counter()
-    info = {}
-    for nq in RULES:
-        gm.plan(nq)
-        info[nq] = gm.plan_info(nq)
+    gm.plan(HEAD_NQ)
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t)
+    info = gm.plan_info(HEAD_NQ)
     n = gm.n_dof
-    log(f"[bench] n_dof {n}, mesh set-up {setup_ms:.1f} ms, plans {plan_ms:.1f} ms, {info}")
-    t = time.perf_counter()
-    tiles, t_nnz = gm.template(64)
-    template = {"tile": 64, "tiles_set": float(tiles.mean()), "pair_density": t_nnz / float(n * n),
-                "ms": 1e3 * (time.perf_counter() - t)}
-    log(f"[bench] template {template}")
+    G = gm.n_tet * HEAD_NQ
+    rays = 6 * G
+    log(f"[bench] n_dof {n}, mesh set-up {setup_ms:.1f} ms, plan {plan_ms:.1f} ms, {info}")
 
-    cases = [(nq, a) for nq in RULES for a in ALPHAS]
-    A = torch.empty((len(cases), n, n), dtype=torch.float64, device=dev)
-    b = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
-    u = torch.empty((len(cases), n), dtype=torch.float64, device=dev)
-    rays_per_step = sum(6 * gm.n_tet * nq for nq in RULES) * len(ALPHAS)
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    u = torch.empty_like(b)
+    A32 = torch.empty((n, n), dtype=torch.float32, device=dev)
+    pm = [F.params(a, HEAD_K, quad_points=HEAD_NQ, precision=F.FPDE_MIXED, ir_tol=1e-8) for a in HEAD_ALPHAS]
+    last = {}
 
-    step_params = [F.params(a, KCOEF, quad_points=nq) for nq, a in cases]
+    def step(k):
+        p = pm[k % 2]
+        gm.assemble(p, A32, b)
+        last["info"] = gm.solve(p, A32, b, u)
+        last["alpha"] = p.alpha
 
-    def step():
-        # the step's systems are assembled one after another (each fills the
-        # device; one status check for all, each walk beside the previous
-        # system's accumulation), then factored and solved together: their
-        # Cholesky and triangular-solve chains, latency-bound one by one, run
-        # side by side
-        gm.assemble_batch(step_params, A, b)
-        gm.solve_batch(A, b, u)
-
-    def step_sequential():
-        for z, (nq, a) in enumerate(cases):
-            p = F.params(a, KCOEF, quad_points=nq)
-            gm.assemble(p, A[z], b[z])
-            gm.solve(p, A[z], b[z], u[z], info=False)
-
-    for _ in range(args.warmup):
-        step()
+    for k in range(args.warmup):
+        step(k + 1)  # ends on the alpha the first timed step does not use
     torch.cuda.synchronize()
     # inside the timed steps only the two roofline candidates carry stage
     # events (each timed stage costs two event records per launch)
@@ -468,163 +636,126 @@ def main():
     torch.cuda.synchronize()
     ev0.record()
     for k in range(args.steps):
-        step()
-        log(f"[bench] step {k + 1}/{args.steps} done")
+        step(k)
+        log(f"[bench] step {k + 1}/{args.steps} done (ir_iters {last['info'].ir_iters}, residual "
+            f"{last['info'].final_rel_residual:.2e})")
     ev1.record()
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     gm.timing(False)
-    live = gm.stage_times()  # accumulation and factorization over the timed steps
+    live = gm.stage_times()
     ms_per_step = total_ms / args.steps
-    value = rays_per_step * args.steps / (total_ms / 1e3)
-    log(f"[bench] {ms_per_step:.2f} ms/step, {value:.3e} paths/s, timed-step stages {live}")
-    # the per-stage breakdown from further steps with every stage timed
-    # (outside the timed region)
+    value = rays * args.steps / (total_ms / 1e3)
+    log(f"[bench] {ms_per_step:.1f} ms/step, {value:.3e} paths/s, timed-step stages {live}")
+    mixed_info = last["info"]
+    # per-stage breakdown from one further step with every stage timed
     gm.timing(True)
-    for _ in range(BREAKDOWN_STEPS):
-        step()
+    step(args.steps)
     torch.cuda.synchronize()
     gm.timing(False)
     stages = gm.stage_times()
-    log(f"[bench] stage breakdown over {BREAKDOWN_STEPS} steps: {stages}")
+    log(f"[bench] stage breakdown (one step): {stages}")
+    walk_ms = stages["walk"][0]
+    u_mixed = u.clone()
+    alpha_mixed = last["alpha"]
 
-    # the same systems one at a time (assemble, factor, solve per system), one
-    # step, outside the timed region: the per-system latency beside the
-    # batched throughput
-    seq_ms = None
-    if not args.no_sequential:
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        step_sequential()
-        e1.record()
-        torch.cuda.synchronize()
-        seq_ms = e0.elapsed_time(e1)
-        log(f"[bench] one step with the systems solved one at a time: {seq_ms:.2f} ms")
-
-    # Roofline of the dominant kernel of the step, by time per step: either
-    # the batched dense factorization (one unit = k_potrf_diag once, then per
-    # pair of 64-column panels two k_panel and two k_syrk launches over all
-    # systems, timed with one
-    # event pair per call on the launch stream; algorithmic work
-    # systems x n^3 / 3 FP64 flops, on the matrix cores: FP64 peak
-    # 78.6 TFLOP/s) or the tube accumulation (one unit = one k_tube_accum
-    # launch, one per system; algorithmic work one multiply-add per entry
-    # product of S = sum w l r^T, B = S + S^T, i.e. 2 flops x pairs, on the
-    # vector ALUs with LDS atomics: FP64 peak 78.6 TFLOP/s).
-    passes = len(cases)
-    factorizations = live["potrf"][1]
+    # roofline of the step's dominant kernel, by time per step: the FP32
+    # factorization (one unit = one factorization of the n x n matrix:
+    # n^3 / 3 algorithmic flops) or the tube accumulation (one unit = one
+    # k_tube_accum launch: 4 |L| |R| flops per (g, i))
     cand = []
-    if factorizations:
-        calls = factorizations / passes
-        avg_s = live["potrf"][0] / calls / 1e3
-        fl = passes * n ** 3 / 3.0
-        ach = fl / avg_s / 1e12
+    if live["potrf"][1]:
+        t_f = live["potrf"][0] / live["potrf"][1] / 1e3
+        fl = n ** 3 / 3.0
         cand.append((live["potrf"][0], {
-            "bound": "mfma", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("factorization"),
-            "kernel": f"batched factorization of {passes} systems: k_potrf_diag<double>, then per pair of "
-                      f"64-column panels k_panel, k_syrk<double, 64> (block column), k_panel, "
-                      f"k_syrk<double, 128> (trailing matrix)",
-            "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (v_mfma_f64_16x16x4f64 tiles)"}))
+            "bound": "mfma", "achieved": fl / t_f / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": fl / t_f / FP32_PEAK, "traffic": read_traffic("factorization_fp32_c5") if "factorization_fp32_c5" in PMC else None,
+            "kernel": "FP32 Cholesky of the n x n matrix: k_potrf_diag<float>, then per pair of 64-column "
+                      "panels k_panel, k_syrk<float, 64> (block column), k_panel, k_syrk<float, 128>",
+            "avg_launch_ms": t_f * 1e3, "flops_per_unit": fl, "dtype": "f32 (v_mfma_f32_16x16x4f32 tiles)"}))
     if live["accum"][1]:
-        avg_s = live["accum"][0] / live["accum"][1] / 1e3
-        fl = sum(2 * info[nq]["pairs"] for nq in RULES) / len(RULES)  # launches alternate the rules evenly
-        ach = fl / avg_s / 1e12
+        t_a = live["accum"][0] / live["accum"][1] / 1e3
+        fl = 4.0 * info["pairs"]
         cand.append((live["accum"][0], {
-            "bound": "alu", "achieved": ach, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": ach / (FP64_PEAK / 1e12), "traffic": read_traffic("k_tube_accum"),
-            "kernel": "k_tube_accum (tube blocks, one launch per system)",
-            "avg_launch_ms": avg_s * 1e3, "flops_per_unit": fl, "dtype": "f64 (vector FMA, LDS atomics)"}))
+            "bound": "alu", "achieved": fl / t_a / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": fl / t_a / FP64_PEAK, "traffic": None,
+            "kernel": "k_tube_accum (tube blocks, one launch per assembly)", "avg_launch_ms": t_a * 1e3,
+            "flops_per_unit": fl, "dtype": "f64 (vector FMA, LDS atomics)"}))
     roofline = max(cand, key=lambda c: c[0])[1] if cand else None
     other_roofline = min(cand, key=lambda c: c[0])[1] if len(cand) > 1 else None
-    # every stage against its own bound (algorithmic work / measured time)
-    stage_roof = {}
-    if stages["potrf"][1]:
-        t = stages["potrf"][0] / stages["potrf"][1] / 1e3
-        fl = n ** 3 / 3.0
-        stage_roof["potrf"] = {"flops_per_factorization": fl, "TFLOP/s": fl / t / 1e12,
-                               "frac_fp64": fl / t / FP64_PEAK}
-    if stages["trsv"][1]:
-        t = stages["trsv"][0] / stages["trsv"][1] / 1e3
-        by = n * n * 8.0  # the lower triangle read once forward, once backward
-        stage_roof["trsv"] = {"bytes_per_solve": by, "GB/s": by / t / 1e9, "frac_hbm": by / t / HBM_PEAK}
-    if stages["contract"][1]:
-        t = stages["contract"][0] / stages["contract"][1] / 1e3
-        by = n * n * 8.0 + sum(12.0 * info[nq]["entries"] for nq in RULES) / len(RULES)
-        stage_roof["contract"] = {"algorithmic_bytes": by, "GB/s": by / t / 1e9, "frac_hbm": by / t / HBM_PEAK,
-                                  "note": "K written once + every derivative entry read once"}
-    if stages["accum"][1]:
-        t = stages["accum"][0] / stages["accum"][1] / 1e3
-        fl = sum(2 * info[nq]["pairs"] for nq in RULES) / len(RULES)
-        stage_roof["accum"] = {"flops_per_launch": fl, "TFLOP/s": fl / t / 1e12, "frac_fp64": fl / t / FP64_PEAK,
-                               "note": "one multiply-add per entry product of S (B = S + S^T)"}
-    if stages["walk"][1]:
-        stage_roof["walk"] = {"paths_per_s": rays_per_step * BREAKDOWN_STEPS / (stages["walk"][0] / 1e3)}
 
-    # mixed-precision arm at alpha = 1.5, 11-point rule
-    mixed = None
-    if not args.no_mixed:
-        p64 = F.params(1.5, KCOEF, quad_points=11)
-        pmx = F.params(1.5, KCOEF, quad_points=11, precision=F.FPDE_MIXED, ir_tol=1e-8)
-        A32 = torch.empty((n, n), dtype=torch.float32, device=dev)
-        A0, b0, u0 = A[0], b[0], u[0]
-        u32 = torch.empty_like(u0)
-
-        def timed(fn, reps=3):
-            ts = []
-            for _ in range(reps):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                r = fn()
-                e1.record()
-                torch.cuda.synchronize()
+    # the FP64 arm on the same mesh: FP64 matrix (n^2 x 8 bytes), FP64
+    # Cholesky, two triangular solves; alpha alternating as above
+    fp64 = None
+    if not args.no_fp64:
+        del A32
+        torch.cuda.empty_cache()
+        A64 = torch.empty((n, n), dtype=torch.float64, device=dev)
+        u64 = torch.empty_like(b)
+        p64 = [F.params(a, HEAD_K, quad_points=HEAD_NQ) for a in HEAD_ALPHAS]
+        ts = []
+        gm.timing(True)
+        # pass 0 (untimed) warms the FP64 scratch; the timed passes 1 and 2
+        # each take the alpha the previous pass did not (so both walk), and
+        # the last is the mixed solution's
+        mi = HEAD_ALPHAS.index(alpha_mixed)
+        seq = [p64[mi], p64[1 - mi], p64[mi]]
+        for k in range(3):
+            p = seq[k]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            gm.assemble(p, A64, b)
+            gm.solve(p, A64, b, u64, info=False)
+            e1.record()
+            torch.cuda.synchronize()
+            if k > 0:
                 ts.append(e0.elapsed_time(e1))
-            return sorted(ts)[len(ts) // 2], r
+            log(f"[bench] FP64 pass {k} {e0.elapsed_time(e1):.1f} ms")
+        gm.timing(False)
+        st64 = gm.stage_times()
+        assert abs(p.alpha - alpha_mixed) < 1e-15  # the last FP64 pass solved the mixed solution's alpha
+        t64 = sum(ts) / len(ts)
+        err = float((u_mixed - u64).abs().max() / u64.abs().max())
+        potrf64 = st64["potrf"][0] / max(st64["potrf"][1], 1) / 1e3
+        fp64 = {"assembly_solve_s": t64 / 1e3, "speedup_mixed_vs_fp64": t64 / ms_per_step,
+                "mixed_rel_err_vs_fp64": err, "alpha_compared": alpha_mixed,
+                "matrix_bytes": n * n * 8,
+                "stages_ms_per_pass": {k: v[0] / 3 for k, v in st64.items() if v[1] > 0},
+                "factorization": {"bound": "mfma", "ms": potrf64 * 1e3,
+                                  "achieved": n ** 3 / 3.0 / potrf64 / 1e12, "peak": FP64_PEAK / 1e12,
+                                  "unit": "TFLOP/s", "frac": n ** 3 / 3.0 / potrf64 / FP64_PEAK}}
+        log(f"[bench] FP64 arm {fp64}")
+        del A64
+        torch.cuda.empty_cache()
 
-        def run64():
-            gm.assemble(p64, A0, b0)
-            gm.solve(p64, A0, b0, u0, info=False)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        om = oracle.OracleMesh(mesh.xyz, mesh.tet)
+        cpu = cpu_baseline(om, HEAD_ALPHAS[0], HEAD_K, HEAD_NQ, G)
+        log(f"[bench] cpu oracle {cpu}")
+        del om
+    gm.close()
+    torch.cuda.empty_cache()
 
-        def runmx():
-            gm.assemble(pmx, A32, b0)
-            return gm.solve(pmx, A32, b0, u32)
-
-        t64, _ = timed(run64)
-        tmx, inf = timed(runmx)
-        err = float((u32 - u0).abs().max() / u0.abs().max())
-        mixed = {"workload": "alpha=1.5, 11-point rule", "fp64_assembly_solve_s": t64 / 1e3,
-                 "mixed_assembly_solve_s": tmx / 1e3, "speedup_vs_fp64": t64 / tmx,
-                 "rel_err_vs_fp64": err, "ir_iters": inf.ir_iters,
-                 "final_rel_residual": inf.final_rel_residual}
-        log(f"[bench] mixed {mixed}")
-
-    sparse = None
-    if not args.no_sparse:
-        sparse = bench_sparse(F, torch, gm)
-        log(f"[bench] sparse {sparse}")
-
-    form = None
-    if not args.no_form:
-        form = bench_form(F, torch, gm, info[4])
-        log(f"[bench] form {form}")
-
-    plane = None
-    if not args.no_plane:
-        plane = bench_plane(F, torch)
-        log(f"[bench] plane {plane}")
-
-    mixed_large = None
-    if not args.no_mixed_large:
-        mixed_large = bench_mixed_large(F, torch, dev)
-        log(f"[bench] mixed_large {mixed_large}")
-
-    sec3 = None
-    if not args.no_sec3:
-        sec3 = bench_sec3(F, torch, dev)
-        log(f"[bench] sec3 {sec3}")
+    sections = {}
+    if not args.no_sections:
+        if not args.no_mixed_large:
+            sections["sphere150k_fp64_vs_mixed"] = bench_mixed_large(F, torch, dev)
+            log(f"[bench] sphere150k {sections['sphere150k_fp64_vs_mixed']}")
+        if not args.no_adjoint:
+            sections["ball40k_adjoint"] = bench_adjoint(F, torch, dev)
+            log(f"[bench] adjoint {sections['ball40k_adjoint']}")
+        if not args.no_c2:
+            sections["sphere20k_batch"] = bench_c2(F, torch, dev)
+            log(f"[bench] sphere20k {sections['sphere20k_batch']}")
+        if not args.no_plane:
+            sections["plane"] = bench_plane(F, torch)
+            log(f"[bench] plane {sections['plane']}")
+        if not args.no_sec3:
+            sections["sec3"] = bench_sec3(F, torch, dev)
+            log(f"[bench] sec3 {sections['sec3']}")
 
     if args.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -634,10 +765,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("[bench] copy calibration: 1 GiB device-to-device copy done")
-
-    cpu = None if args.no_cpu else cpu_baseline(mesh)
-    if cpu:
-        log(f"[bench] cpu oracle {cpu}")
 
     out = {
         "metric": METRIC,
@@ -650,40 +777,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 paths/derivatives/residuals, f32 matrix and factor",
         "data": "synthetic",
         "config": {
-            "workload": f"{WORKLOAD}: hull of 400 seeded points on the unit sphere + BCC lattice, "
-                        f"{gm.n_tet} tets, {mesh.n_vert} nodes ({n} interior); alpha {list(ALPHAS)}, "
-                        f"K={list(KCOEF)}, rules {list(RULES)}; FP64 assembly + dense Cholesky; "
-                        f"{passes} systems per step, assembled as one batch (walks beside the accumulations), "
-                        f"factored and solved as one batch",
-            "n_nodes": mesh.n_vert, "n_dof": n, "n_tet": gm.n_tet,
-            "gauss_points": {str(nq): gm.n_tet * nq for nq in RULES},
+            "workload": f"{WORKLOAD}: hull of 2000 seeded points in the ellipsoid (1, 0.7, 0.4) + BCC lattice, "
+                        f"{gm.n_tet} tets, {mesh.n_vert} nodes ({n} interior); alpha {HEAD_ALPHAS[0]} "
+                        f"(timed passes alternate {list(HEAD_ALPHAS)}), K={list(HEAD_K)}, {HEAD_NQ}-point rule; "
+                        f"mixed precision: FP32 dense matrix + FP32 Cholesky + FP64 matrix-free refinement to 1e-8",
+            "n_nodes": mesh.n_vert, "n_dof": n, "n_tet": gm.n_tet, "gauss_points": G,
             "parallelism": "single GPU",
         },
-        "assembly_solve_s_per_pass": ms_per_step / passes / 1e3,
-        "sequential_ms_per_step": seq_ms,
-        "sequential_assembly_solve_s_per_system": seq_ms / passes / 1e3 if seq_ms else None,
-        "stages_ms_per_step": {k: v[0] / BREAKDOWN_STEPS for k, v in stages.items() if v[1] > 0},
-        "stages_note": (f"launch times per stage from {BREAKDOWN_STEPS} further steps with every stage timed; "
-                        f"inside the timed steps only the accumulation and the factorization carry events "
-                        f"(the roofline's launch durations)"),
-        "walk_eval_paths_per_s": (rays_per_step * BREAKDOWN_STEPS / (stages["walk"][0] / 1e3)
-                                  if stages["walk"][0] > 0 else None),
+        "assembly_solve_s": ms_per_step / 1e3,
+        "walk_eval_paths_per_s": rays / (walk_ms / 1e3) if walk_ms > 0 else None,
+        "mixed": {"ir_iters": mixed_info.ir_iters, "final_rel_residual": mixed_info.final_rel_residual,
+                  "matrix_bytes": n * n * 4},
+        "fp64": fp64,
+        "stages_ms_per_step": {k: v[0] for k, v in stages.items() if v[1] > 0},
+        "stages_note": ("launch times per stage from one further step with every stage timed; inside the timed "
+                        "steps only the accumulation and the factorization carry events (the roofline's launch "
+                        "durations)"),
         "setup_ms": setup_ms,
-        "template_plan_ms": plan_ms,
-        "template": template,
-        "plan": {str(k): v for k, v in info.items()},
+        "plan_ms": plan_ms,
+        "mesh_generation_s": gen_s,
+        "end_to_end_first_pass_s": (setup_ms + plan_ms) / 1e3 + ms_per_step / 1e3,
+        "plan": info,
         "roofline": roofline,
         "roofline_other": other_roofline,
-        "stage_rooflines": stage_roof,
-        "mixed": mixed,
-        "mixed_large": mixed_large,
-        "sparse": sparse,
-        "form": form,
-        "plane": plane,
-        "sec3": sec3,
+        "sections": sections,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -132,6 +132,8 @@ struct fpde_mesh {
   int *tsync = nullptr;           // triangular solves: per-system block flags (2 nblk) and tickets (2)
   int tsync_n = 0;                // ints allocated
   int64_t *batch_aux = nullptr;   // device, kMaxBatch: failing column per system of a batched factorization
+  int *escale = nullptr;          // device: per-row exponents of the split-FP16 trailing updates
+  int64_t escale_n = 0;
   double *bvec = nullptr;         // device: intermediate vectors of a batched solve
   int64_t bvec_n = 0;
   int tsync_epoch = 0;

@@ -572,6 +572,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   if (m->linv) (void)hipFree(m->linv);
   dfree(m->tsync);
   dfree(m->batch_aux);
+  dfree(m->escale);
   dfree(m->bvec);
   dfree(m->pbox);
   dfree(m->cg);

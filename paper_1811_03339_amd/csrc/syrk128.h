@@ -1,0 +1,345 @@
+// Trailing update of the blocked Cholesky on 128 x 128 output tiles:
+//   C[I, J] -= X_I X_J^T  over the lower tiles I >= J of the trailing matrix,
+// X = the KD = 128 columns of the two panels just factored.  One workgroup
+// (256 threads, four wavefronts in a 2 x 2 arrangement, 64 x 64 each) per
+// output tile reads and writes its tile of C once and streams X_I and X_J
+// through LDS in chunks of the inner dimension, double-buffered: a 128-wide
+// tile halves the reads of X per output entry compared with 64-wide tiles.
+//
+// Two arithmetic forms:
+//  * FP64 storage: v_mfma_f64_16x16x4f64 tiles (a wavefront's 64 x 64 as
+//    4 x 4 accumulators of 16 x 16), 16-deep chunks.
+//  * FP32 storage (the factor of the mixed-precision solve): split FP16 on
+//    the FP16 matrix cores, 32-deep chunks.  Row r of X is scaled by a power
+//    of two 2^-e_r (e_r from the row's largest magnitude over the KD
+//    columns, computed by k_row_scale before the update) so that its largest
+//    entry lies in [2^13, 2^14), then split as x = hi + lo with hi = fp16(x)
+//    and lo = fp16(x - hi) (22 significant bits).  The product accumulates
+//    hi hi^T + hi lo^T + lo hi^T in FP32 with v_mfma_f32_16x16x32_f16 (the
+//    dropped lo lo^T term is below 2^-22 of each product) and the update is
+//    C -= 2^(e_r + e_c) acc.  Entries far below their row's largest lose
+//    relative precision in lo, but their absolute error stays below 2^-24
+//    of that largest entry: the FP32 rounding of the stored factor.
+//
+// The workgroup of tile (0, 0) keeps the top-left 64 x 64 quadrant of its
+// updated tile -- the next diagonal block -- and factors it at once
+// (diag_factor), as the 64-wide trailing update does.
+#pragma once
+
+#include <type_traits>
+
+#include "chol_diag.h"
+#include "dense.h"
+
+namespace fpde {
+
+constexpr int T128 = 128;
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// exponent e_r of each row r in [r0, n) of the KD columns at k0:
+// max_k |A[r][k0 + k]| * 2^-e_r in [2^13, 2^14), e_r within [-110, 110]
+// (0 for an all-zero row).  One wavefront per row; batch z = blockIdx.y
+// (rows of system z at A + z sA, exponents at escale + z se).
+template <int KD>
+__global__ void __launch_bounds__(256) k_row_scale(const float *__restrict__ A, int64_t lda, int64_t n, int64_t r0,
+                                                   int64_t k0, int *__restrict__ escale, int64_t sA, int64_t se) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = r0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  A += (int64_t)blockIdx.y * sA;
+  escale += (int64_t)blockIdx.y * se;
+  if (r >= n) return;
+  float mx = 0.f;
+#pragma unroll
+  for (int k = lane; k < KD; k += 64) mx = fmaxf(mx, fabsf(A[r * lda + k0 + k]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) {
+    int e = mx > 0.f ? ilogbf(mx) - 13 : 0;
+    escale[r] = e < -110 ? -110 : (e > 110 ? 110 : e);
+  }
+}
+
+// Split FP16 chunks: [buffer][hi, lo][row][k], 32 halfs per row.  The four
+// 16-byte groups of a row (k 8q..8q+7, q < 4) sit at group q ^ ((row >> 2) & 3),
+// so the 16 lanes of one 16-row read (rows r0..r0+15, one q) hit 16 distinct
+// 16-byte slots of a 256-byte bank window.
+constexpr int KC16 = 32;
+struct Split16Smem {
+  _Float16 a[2][2][T128][KC16];
+  _Float16 b[2][2][T128][KC16];
+};
+__device__ __forceinline__ int swz(int row, int q) { return 8 * (q ^ ((row >> 2) & 3)); }
+
+// FP64 chunks: [buffer][row][k], padded to an odd number of doubles per row
+constexpr int KC64 = 16;
+struct F64Smem {
+  double a[2][T128][KC64 + 1];
+  double b[2][T128][KC64 + 1];
+};
+
+template <class T>
+struct Syrk128Smem;
+template <>
+struct Syrk128Smem<float> {
+  union {
+    Split16Smem g;
+    DiagSmem d;
+  };
+};
+template <>
+struct Syrk128Smem<double> {
+  union {
+    F64Smem g;
+    DiagSmem d;
+  };
+};
+
+// Global loads of one CW-deep chunk: thread t reads CW / 2 consecutive
+// values of row t >> 1 (columns (CW / 2)(t & 1)..) of X_I and of X_J; rows at
+// or past the matrix end read a valid row and are zeroed when stored.
+template <class T, int CW>
+__device__ __forceinline__ void chunk_load(const T *__restrict__ P, const T *__restrict__ Q, int64_t lda, int prow,
+                                          int qrow, int kk, T (&pv)[CW / 2], T (&qv)[CW / 2]) {
+  const int t = threadIdx.x, rr = t >> 1, c0 = kk + (CW / 2) * (t & 1);
+  const T *pp = P + (int64_t)(rr < prow ? rr : prow - 1) * lda + c0;
+  const T *qq = Q + (int64_t)(rr < qrow ? rr : qrow - 1) * lda + c0;
+#pragma unroll
+  for (int j = 0; j < CW / 2; j++) {
+    pv[j] = pp[j];
+    qv[j] = qq[j];
+  }
+}
+
+// scaled split of this thread's 16 FP32 values (row rr, k groups 2h, 2h + 1)
+// into the hi and lo planes of one operand buffer
+__device__ __forceinline__ void split_store(const float (&v)[16], float s, bool live, int rr, int h,
+                                            _Float16 (*hi)[KC16], _Float16 (*lo)[KC16]) {
+#pragma unroll
+  for (int g = 0; g < 2; g++) {
+    half8 hv, lv;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const float x = live ? v[8 * g + j] * s : 0.f;
+      const _Float16 a = (_Float16)x;
+      hv[j] = a;
+      lv[j] = (_Float16)(x - (float)a);
+    }
+    const int o = swz(rr, 2 * h + g);
+    *(half8 *)&hi[rr][o] = hv;
+    *(half8 *)&lo[rr][o] = lv;
+  }
+}
+
+// acc[a][b] (wavefront tile rows 16 a.., columns 16 b..) = X_I X_J^T over KD
+// columns, split FP16.  Result layout: lane l holds rows 4 (l >> 4) + i,
+// column l & 15 of each 16 x 16 tile.
+template <int KD>
+__device__ __forceinline__ void product_split16(const float *__restrict__ P, const float *__restrict__ Q,
+                                                int64_t lda, int prow, int qrow, float sp, float sq, Split16Smem &sm,
+                                                f32x4v (&acc)[4][4]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  const int rr = t >> 1, h = t & 1;
+  const bool plive = rr < prow, qlive = rr < qrow;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  float pv[16], qv[16];
+  chunk_load<float, KC16>(P, Q, lda, prow, qrow, 0, pv, qv);
+  split_store(pv, sp, plive, rr, h, sm.a[0][0], sm.a[0][1]);
+  split_store(qv, sq, qlive, rr, h, sm.b[0][0], sm.b[0][1]);
+  __syncthreads();
+  const int q = lane >> 4;
+#pragma unroll 1
+  for (int kk = 0; kk < KD; kk += KC16) {
+    const int buf = (kk / KC16) & 1;
+    const bool more = kk + KC16 < KD;
+    if (more) chunk_load<float, KC16>(P, Q, lda, prow, qrow, kk + KC16, pv, qv);
+    half8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int x = 0; x < 4; x++) {
+      const int ar = 64 * wr + 16 * x + (lane & 15), br = 64 * wc + 16 * x + (lane & 15);
+      ah[x] = *(const half8 *)&sm.a[buf][0][ar][swz(ar, q)];
+      al[x] = *(const half8 *)&sm.a[buf][1][ar][swz(ar, q)];
+      bh[x] = *(const half8 *)&sm.b[buf][0][br][swz(br, q)];
+      bl[x] = *(const half8 *)&sm.b[buf][1][br][swz(br, q)];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], acc[a][b], 0, 0, 0);
+      }
+    if (more) {
+      split_store(pv, sp, plive, rr, h, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
+      split_store(qv, sq, qlive, rr, h, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
+    }
+    __syncthreads();
+  }
+}
+
+// The same product in FP64 on v_mfma_f64_16x16x4f64.  Result layout: lane l
+// holds rows 4 i + (l >> 4), column l & 15 of each 16 x 16 tile.
+template <int KD>
+__device__ __forceinline__ void product_f64(const double *__restrict__ P, const double *__restrict__ Q, int64_t lda,
+                                            int prow, int qrow, F64Smem &sm, f64x4 (&acc)[4][4]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  const int rr = t >> 1, kc = (KC64 / 2) * (t & 1);
+  const bool plive = rr < prow, qlive = rr < qrow;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double pv[KC64 / 2], qv[KC64 / 2];
+  chunk_load<double, KC64>(P, Q, lda, prow, qrow, 0, pv, qv);
+#pragma unroll
+  for (int j = 0; j < KC64 / 2; j++) {
+    sm.a[0][rr][kc + j] = plive ? pv[j] : 0.0;
+    sm.b[0][rr][kc + j] = qlive ? qv[j] : 0.0;
+  }
+  __syncthreads();
+  const int kq = lane >> 4;
+#pragma unroll 1
+  for (int kk = 0; kk < KD; kk += KC64) {
+    const int buf = (kk / KC64) & 1;
+    const bool more = kk + KC64 < KD;
+    if (more) chunk_load<double, KC64>(P, Q, lda, prow, qrow, kk + KC64, pv, qv);
+#pragma unroll
+    for (int k4 = 0; k4 < KC64; k4 += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int x = 0; x < 4; x++) {
+        av[x] = sm.a[buf][64 * wr + 16 * x + (lane & 15)][k4 + kq];
+        bv[x] = sm.b[buf][64 * wc + 16 * x + (lane & 15)][k4 + kq];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < KC64 / 2; j++) {
+        sm.a[buf ^ 1][rr][kc + j] = plive ? pv[j] : 0.0;
+        sm.b[buf ^ 1][rr][kc + j] = qlive ? qv[j] : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Trailing update over the lower 128 x 128 tiles of the matrix from
+// row/column base = k0 + KD, with X = columns [k0, k0 + KD); the workgroup
+// of tile (0, 0) factors the 64 x 64 diagonal block at base.  Block b =
+// tile * nz + system (the tiles (0, 0) of all systems first).  escale:
+// per-row exponents (FP32 only), system z at escale + z se.
+template <class T, int KD>
+__global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
+                                                 T *__restrict__ Linv_next, T *__restrict__ LinvT_next,
+                                                 int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
+                                                 const int *__restrict__ escale, int64_t se, int nz) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  const int64_t z = (int64_t)blockIdx.x % nz;
+  const int64_t x = (int64_t)blockIdx.x / nz;
+  A += z * sA;
+  Linv_next += z * sL;
+  LinvT_next += z * sL;
+  aux += z;
+  __shared__ Syrk128Smem<T> sm;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= x) I++;
+  while (I * (I + 1) / 2 > x) I--;
+  const int64_t J = x - I * (I + 1) / 2;
+  const int64_t base = k0 + KD;
+  const int64_t ri = base + T128 * I, cj = base + T128 * J;
+  const int prow = (int)((n - ri) < T128 ? (n - ri) : T128);
+  const int qrow = (int)((n - cj) < T128 ? (n - cj) : T128);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  // the product: val(a, b, i) at tile row frow(a, i), column fcol(b)
+  using Acc = std::conditional_t<F32, f32x4v, f64x4>;
+  Acc acc[4][4];
+  int ec[4] = {0, 0, 0, 0}, er[4][4] = {};
+  if constexpr (F32) {
+    const int *es = escale + z * se;
+    const int rr = t >> 1;
+    const float sp = ldexpf(1.f, -es[ri + (rr < prow ? rr : prow - 1)]);
+    const float sq = ldexpf(1.f, -es[cj + (rr < qrow ? rr : qrow - 1)]);
+    product_split16<KD>(A + ri * lda + k0, A + cj * lda + k0, lda, prow, qrow, sp, sq, sm.g, acc);
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int c = 64 * wc + 16 * b + (lane & 15);
+      ec[b] = es[cj + (c < qrow ? c : qrow - 1)];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = 64 * wr + 16 * a + 4 * (lane >> 4) + i;
+        er[a][i] = es[ri + (r < prow ? r : prow - 1)];
+      }
+  } else {
+    product_f64<KD>(A + ri * lda + k0, A + cj * lda + k0, lda, prow, qrow, sm.g, acc);
+  }
+  auto frow = [&](int a, int i) {
+    return F32 ? 64 * wr + 16 * a + 4 * (lane >> 4) + i : 64 * wr + 16 * a + 4 * i + (lane >> 4);
+  };
+  auto fcol = [&](int b) { return 64 * wc + 16 * b + (lane & 15); };
+  auto val = [&](int a, int b, int i) -> T {
+    if constexpr (F32) return ldexpf(acc[a][b][i], er[a][i] + ec[b]);
+    else return acc[a][b][i];
+  };
+  const bool keep = x == 0 && w == 0;  // the next diagonal block, factored below
+  if (!keep) {
+    // one block row of 16 at a time: its 16 entries of C loaded first
+    // (indices clamped into the matrix), then updated and stored
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      T cv[4][4];
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int64_t r = ri + frow(a, i), c = cj + fcol(b);
+          cv[b][i] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
+        }
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int64_t r = ri + frow(a, i), c = cj + fcol(b);
+          if (r < n && c < n && c <= r) A[r * lda + c] = cv[b][i] - val(a, b, i);
+        }
+    }
+  }
+  if (x != 0) return;
+  // tile (0, 0): wavefront 0 holds the next 64 x 64 diagonal block; stage
+  // it in LDS (lower part; identity past the matrix end) and factor it
+  __syncthreads();  // the product's LDS is free
+  const int nb = prow < NB ? prow : NB;
+  if (keep) {
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int r = frow(a, i), c = fcol(b);
+          double v;
+          if (r < nb && c < nb) {
+            const T cold = A[(ri + r) * lda + cj + c];
+            v = (c <= r) ? (double)(cold - val(a, b, i)) : 0.0;
+          } else {
+            v = (r == c) ? 1.0 : 0.0;
+          }
+          sm.d.L[r][c] = v;
+        }
+  }
+  __syncthreads();
+  diag_factor<T>(sm.d, nb, A, lda, ri, Linv_next, LinvT_next, flag, aux);
+}
+
+}  // namespace fpde

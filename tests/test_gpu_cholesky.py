@@ -1,7 +1,9 @@
 """The dense Cholesky solve (Table 4's solve stage) on its own, through the
 C ABI, at sizes that take every branch of the blocked factorization: one
 partial block, exactly one block, a pair of 64-column panels followed by a
-single last panel, pairs that end exactly at N, and a partial last block.
+single last panel, pairs that end exactly at N, a partial last block, and
+trailing matrices of one and of several 128 x 128 update tiles, full and
+partial (N = 1000, 1728).
 
 The matrices are seeded random SPD matrices (any SPD matrix of the mesh's
 size is a valid input); the factor must equal LAPACK's Cholesky factor and
@@ -18,7 +20,7 @@ from fpde_inputs import kuhn_cube
 pytestmark = pytest.mark.gpu
 
 # unit cube with k^3 sub-cubes: (k - 1)^3 unknowns
-SIZES = {2: 1, 3: 8, 5: 64, 6: 125, 7: 216, 8: 343, 9: 512, 10: 729}
+SIZES = {2: 1, 3: 8, 5: 64, 6: 125, 7: 216, 8: 343, 9: 512, 10: 729, 11: 1000, 13: 1728}
 _MESHES = {}
 
 
@@ -55,7 +57,7 @@ def test_factor_and_solve_match_lapack(k):
     assert rel(u.cpu().numpy(), np.linalg.solve(S, rhs)) <= 1e-10
 
 
-@pytest.mark.parametrize("k", [3, 6, 7, 9, 10])
+@pytest.mark.parametrize("k", [3, 6, 7, 9, 10, 11])
 def test_batch_matches_lapack(k):
     gm = mesh(k)
     n = gm.n_dof
