@@ -241,6 +241,27 @@ int fpde_solve_batch(fpde_mesh *m, int count, double *A, int64_t lda, int64_t st
                      double *u, int64_t stride_v, int64_t *failed_pivot, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * path of fpde_solve without its residual -- A (dev, n_dof x lda FP64, from
+ * fpde_assemble) is overwritten by its Cholesky factor and u = K^{-1} b
+ * (b, u: dev, n_dof FP64, may alias) -- with every scratch buffer (the
+ * diagonal-block inverses, the triangular solves' flags and tickets, one
+ * intermediate vector; 8.4 MB) in a static device array of the library
+ * instead of the handle: no hipMalloc, hipFree or allocating library call.
+ * Limit: n_dof <= 8192.  Each device holds one copy of the array for the
+ * life of the process, shared by every call on that device: calls that
+ * overlap on one device (other streams, other threads, other handles) race.
+ * The current device must be the mesh's; stage timing must be off.
+ * failed_pivot: host, may be NULL (as in fpde_solve_batch).  Synchronises
+ * `stream` (one status check).
+ * Errors: FPDE_EINVAL (null pointer, lda, n_dof > 8192, timing on, other
+ * device), FPDE_ENOTSPD, FPDE_EHIP.
+ */
+int fpde_solve_noalloc(fpde_mesh *m, double *A, int64_t lda, const double *b, double *u, int64_t *failed_pivot,
+                       void *stream);
+
+/*
  * Adjoint sums for the gradient of a loss J(u) through assembly and solve
  * (u = K^{-1} b, b independent of alpha and K): with lam = K^{-1} dJ/du,
  *   dJ/dK_i   = -c_alpha S_i

@@ -38,6 +38,7 @@ EXPORTS = [
     "fpde_assemble_csr", "fpde_csr_apply", "fpde_cg_solve", "fpde_form_assemble", "fpde_mesh2d_create",
     "fpde_mesh2d_destroy", "fpde_mesh2d_info", "fpde_dof_map2d", "fpde_paths2d", "fpde_assemble2d",
     "fpde_solve2d", "fpde_timing2d", "fpde_stage_times2d", "fpde_solve_batch", "fpde_assemble_batch",
+    "fpde_solve_noalloc",
 ]
 
 STAGES = ["walk", "contract", "load", "potrf", "trsv", "apply", "plan", "adjoint", "accum", "lu", "div", "spmv",
@@ -109,6 +110,7 @@ def _lib():
     L.fpde_solve.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_solve_factored.argtypes = [P, P, P, i64, P, P, P, P]
     L.fpde_solve_batch.argtypes = [P, i32, P, i64, i64, P, P, i64, P, P]
+    L.fpde_solve_noalloc.argtypes = [P, P, i64, P, P, P, P]
     L.fpde_assemble_batch.argtypes = [P, i32, P, P, i64, i64, P, i64, P]
     L.fpde_adjoint.argtypes = [P, P, P, P, P, P, P]
     L.fpde_timing.argtypes = [P, i32]
@@ -340,6 +342,17 @@ class Mesh:
         if st != FPDE_OK:
             e = FpdeError(st, "fpde_solve_batch")
             e.failed_pivot = [piv[z] for z in range(count)]
+            raise e
+
+    def solve_noalloc(self, A, b, u, stream=None):
+        """FP64 Cholesky solve with the library's static scratch (no device
+        allocation; n_dof <= 8192).  Raises FpdeError with .failed_pivot."""
+        piv = ctypes.c_int64(-1)
+        st = _lib().fpde_solve_noalloc(self._h, _ptr(A), A.stride(0), _ptr(b), _ptr(u), ctypes.byref(piv),
+                                       _stream(stream))
+        if st != FPDE_OK:
+            e = FpdeError(st, "fpde_solve_noalloc")
+            e.failed_pivot = piv.value
             raise e
 
     def solve_factored(self, p, L, b, u, stream=None, info: bool = True):

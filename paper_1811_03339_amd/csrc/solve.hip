@@ -17,6 +17,7 @@
 // then refines against FP64 residuals b - K u computed matrix-free from the
 // FP64 derivative vectors.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -590,9 +591,74 @@ int dense_spd_solve(fpde_mesh *ws, double *A, int64_t lda, int64_t n, const doub
   return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
 }
 
+// ---- Dense FP64 solve whose scratch is a static device array ----
+//
+// For callers that cannot allocate: the diagonal-block inverses (and their
+// transposes), the triangular solves' flags and tickets and the intermediate
+// vector of fpde_solve's FP64 path live in `scratch`, one copy per device
+// (the library's code object is loaded on every device it runs on), sized
+// for kNoAllocMaxN unknowns.  Host code reaches the array through the device
+// address hipGetSymbolAddress returns on each device (looked up once per
+// device, on the first call there), never through its name.
+constexpr int64_t kNoAllocMaxN = 8192;
+constexpr int64_t kNoAllocBlk = (kNoAllocMaxN + NB - 1) / NB;
+constexpr size_t kNoAllocLinv = 2 * (size_t)kNoAllocBlk * NB * NB;  // doubles
+constexpr size_t kNoAllocVec = (size_t)kNoAllocMaxN;                // doubles
+constexpr size_t kNoAllocInts = 2 * (size_t)kNoAllocBlk + 2;        // flags, tickets
+constexpr size_t kNoAllocBytes = (kNoAllocLinv + kNoAllocVec) * sizeof(double) + kNoAllocInts * sizeof(int);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (`dev`)
+static int scratch_address(int dev, void **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return FPDE_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FPDE_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FPDE_OK;
+}
+
 }  // namespace fpde
 
 using namespace fpde;
+
+extern "C" int fpde_solve_noalloc(fpde_mesh *m, double *A, int64_t lda, const double *b, double *u,
+                                  int64_t *failed_pivot, void *stream) {
+  if (failed_pivot) *failed_pivot = -1;
+  if (!m || !A || !b || !u) return FPDE_EINVAL;
+  const int64_t n = m->ndof;
+  if (lda < n || n > kNoAllocMaxN) return FPDE_EINVAL;
+  if (m->timer.on) return FPDE_EINVAL;  // stage timers create events
+  int dev = -1;
+  FPDE_HIP(hipGetDevice(&dev));
+  if (dev != m->device) return FPDE_EINVAL;
+  if (n == 0) return FPDE_OK;
+  void *base = nullptr;
+  FPDE_TRY(scratch_address(dev, &base));
+  double *lv = (double *)base;
+  double *xs = lv + kNoAllocLinv;
+  int *tsync = (int *)(xs + kNoAllocVec);
+  const int nblk = (int)((n + NB - 1) / NB);
+  hipStream_t s = S(stream);
+  // the flags and tickets keep the previous call's values: cleared by a
+  // kernel (no memset node if the caller captures a graph)
+  FPDE_TRY(zero_ints(tsync, 2 * nblk + 2, s));
+  FPDE_TRY(potrf_batch<double>(A, lda, 0, n, 1, lv, 0, m->flag_aux, m, s));
+  if (u != b) FPDE_HIP(hipMemcpyAsync(u, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  FPDE_TRY(trsv_batch_sync<double>(A, lda, 0, n, 1, lv, 0, u, 0, xs, 0, tsync, 1, m, s));
+  int64_t col = -1;
+  int f = take_flag(m, s, &col);
+  if (f == FPDE_ENOTSPD && failed_pivot) *failed_pivot = col;
+  return f < 0 ? f : (f > 0 ? FPDE_EHIP : FPDE_OK);
+}
 
 extern "C" int fpde_solve(fpde_mesh *m, const fpde_params *p, void *A, int64_t lda, const double *b, double *u,
                           fpde_solve_info *info, void *stream) {
