@@ -116,17 +116,18 @@ __global__ void __launch_bounds__(256) k_panel(T *__restrict__ A, int64_t lda, i
   }
 }
 
-// trailing update C[I,J] -= X_I X_J^T over lower tiles I >= J of the matrix
+// update C[I,J] -= X_I X_J^T over lower 64 x 64 tiles I >= J of the matrix
 // starting at row/column k1 = k0 + KD; X = columns [k0, k0 + KD) (one panel,
-// KD = 64, or two consecutive panels, KD = 128).  colonly: only the tiles
-// (I, 0), the block column at k1.  The workgroup of tile (0, 0) -- the next
-// diagonal block -- keeps its updated tile in LDS and factors it at once
-// (diag_factor), so the next panel's diagonal factorization runs beside the
-// rest of this update instead of after it.
+// KD = 64).  ncol = 0: the whole lower triangle; ncol >= 1: only the strip
+// of the first ncol block columns (tiles (I, J), J < ncol, I >= J), the
+// block columns that the later panels of a group still need.  The workgroup
+// of tile (0, 0) -- the next diagonal block -- keeps its updated tile in LDS
+// and factors it at once (diag_factor), so the next panel's diagonal
+// factorization runs beside the rest of this update instead of after it.
 template <class T, int KD>
 __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                               T *__restrict__ Linv_next, T *__restrict__ LinvT_next, int32_t *flag,
-                                              int64_t *aux, int64_t sA, int64_t sL, int nz, int colonly) {
+                                              int64_t *aux, int64_t sA, int64_t sL, int nz, int ncol) {
   // block b = tile * nz + system: the tiles (0, 0) of all systems, which
   // carry the next diagonal factorizations, are dispatched first
   const int64_t z = (int64_t)blockIdx.x % nz;
@@ -142,14 +143,23 @@ __global__ void __launch_bounds__(256) k_syrk(T *__restrict__ A, int64_t lda, in
     Gemm g;
     DiagSmem d;
   } sm;
-  int64_t I = x, J = 0;
-  if (!colonly) {
+  const int64_t base = k0 + KD;
+  int64_t I = 0, J = 0;
+  if (ncol == 0) {
     I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= x) I++;
     while (I * (I + 1) / 2 > x) I--;
     J = x - I * (I + 1) / 2;
+  } else {
+    // strip tiles column by column: block column J holds Tn - J tiles
+    const int64_t Tn = (n - base + 63) / 64;
+    int64_t first = 0;
+    while (J + 1 < ncol && x >= first + (Tn - J)) {
+      first += Tn - J;
+      J++;
+    }
+    I = J + (x - first);
   }
-  const int64_t base = k0 + KD;
   const int64_t ri = base + 64 * I, cj = base + 64 * J;
   const int prow = (int)((n - ri) < 64 ? (n - ri) : 64);
   const int qrow = (int)((n - cj) < 64 ? (n - cj) : 64);
@@ -376,35 +386,47 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
   T *LinvT = Linv + nbk * NB * NB;
   const unsigned z = (unsigned)count;
   k_potrf_diag<T><<<dim3(1, z), 256, 0, s>>>(A, lda, n, 0, Linv, LinvT, m->flag, aux, sA, sL);
-  // panels in pairs: panel k0; the block column at k1 = k0 + 64 updated by
-  // it alone (its tile (0, 0) factors diagonal block k1); panel k1; then the
-  // trailing matrix from k1 + 64 updated once by both panels (128 columns):
-  // the trailing matrix is read and written once per two panels
-  for (int64_t k0 = 0; k0 < n; k0 += 2 * NB) {
-    const int64_t rest = n - k0 - NB;
-    if (rest <= 0) break;
-    T *Lk = Linv + (k0 / NB) * NB * NB;
-    k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, k0, Lk, sA, sL);
-    const int64_t Tn = (rest + 63) / 64;
-    T *Lk1 = Lk + NB * NB, *LkT1 = LinvT + (k0 / NB + 1) * NB * NB;
-    if (rest <= NB) {  // one block column left
-      k_syrk<T, NB><<<(unsigned)(Tn * (Tn + 1) / 2 * count), 256, 0, s>>>(A, lda, n, k0, Lk1, LkT1, m->flag,
-                                                                              aux, sA, sL, count, 0);
-      break;
+  // Panels in groups of kGroup: after panel s of a group (X_s = B inv(L)^T
+  // for the 64 columns at ks, every row below), only the group's later block
+  // columns are updated by it (a strip, KD = 64; its tile (0, 0) factors the
+  // next diagonal block), and the trailing matrix beyond the group is
+  // updated once by the whole group (KD = 64 kGroup, 128 x 128 tiles): the
+  // trailing matrix is read and written once per kGroup panels.
+  constexpr int kGroup = 4;
+  for (int64_t k0 = 0; k0 < n; k0 += kGroup * NB) {
+    for (int sp = 0; sp < kGroup; sp++) {
+      const int64_t ks = k0 + sp * NB;
+      const int64_t rest = n - ks - NB;  // rows below panel sp
+      if (rest <= 0) goto factored;      // the last diagonal block is factored
+      T *Lk = Linv + (ks / NB) * NB * NB;
+      T *Ln = Lk + NB * NB, *LnT = LinvT + (ks / NB + 1) * NB * NB;
+      k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, ks, Lk, sA, sL);
+      const int64_t Tn = (rest + 63) / 64;  // block rows (and columns) below panel sp
+      const int inner = kGroup - 1 - sp;    // block columns of the group after panel sp
+      if (Tn <= inner) {
+        // the rest of the matrix lies inside the group: all of it, by this panel
+        k_syrk<T, NB><<<(unsigned)(Tn * (Tn + 1) / 2 * count), 256, 0, s>>>(A, lda, n, ks, Ln, LnT, m->flag,
+                                                                                aux, sA, sL, count, 0);
+      } else if (inner > 0) {
+        const int64_t tiles = (int64_t)inner * Tn - (int64_t)inner * (inner - 1) / 2;
+        k_syrk<T, NB><<<(unsigned)(tiles * count), 256, 0, s>>>(A, lda, n, ks, Ln, LnT, m->flag, aux, sA, sL,
+                                                                 count, inner);
+      } else {
+        // the group's update of the trailing matrix from k0 + 64 kGroup on
+        // 128 x 128 tiles (FP32: split FP16 with per-row exponents over the
+        // group's columns)
+        const int64_t base = k0 + kGroup * NB;
+        const int64_t T2 = (n - base + T128 - 1) / T128;
+        const int64_t work = T2 * (T2 + 1) / 2 * count;
+        if (escale)
+          k_row_scale<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
+              (const float *)A, lda, n, base, k0, escale, sA, n);
+        k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), 256, 0, s>>>(
+            A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, count, work);
+      }
     }
-    k_syrk<T, NB><<<(unsigned)(Tn * count), 256, 0, s>>>(A, lda, n, k0, Lk1, LkT1, m->flag, aux, sA, sL, count, 1);
-    const int64_t k1 = k0 + NB, rest1 = rest - NB;
-    k_panel<T><<<dim3(nblk(rest1, 64), z), 256, 0, s>>>(A, lda, n, k1, Lk1, sA, sL);
-    // the trailing matrix from k1 + 64 on 128 x 128 tiles (FP32: split FP16
-    // with per-row exponents over the two panels' 128 columns)
-    const int64_t base = k0 + 2 * NB;
-    const int64_t T2 = (rest1 + T128 - 1) / T128;
-    if (escale)
-      k_row_scale<2 * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
-          (const float *)A, lda, n, base, k0, escale, sA, n);
-    k_syrk128<T, 2 * NB><<<(unsigned)(T2 * (T2 + 1) / 2 * count), 256, 0, s>>>(
-        A, lda, n, k0, Lk1 + NB * NB, LkT1 + NB * NB, m->flag, aux, sA, sL, escale, n, count);
   }
+factored:
   timer_end(m, FPDE_STAGE_POTRF, t, s, count);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;

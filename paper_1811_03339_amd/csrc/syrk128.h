@@ -1,6 +1,6 @@
 // Trailing update of the blocked Cholesky on 128 x 128 output tiles:
 //   C[I, J] -= X_I X_J^T  over the lower tiles I >= J of the trailing matrix,
-// X = the KD = 128 columns of the two panels just factored.  One workgroup
+// X = the KD columns of the group of panels just factored (KD = 256).  One workgroup
 // (256 threads, four wavefronts in a 2 x 2 arrangement, 64 x 64 each) per
 // output tile reads and writes its tile of C once and streams X_I and X_J
 // through LDS in chunks of the inner dimension, double-buffered: a 128-wide
@@ -234,17 +234,29 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
 
 // Trailing update over the lower 128 x 128 tiles of the matrix from
 // row/column base = k0 + KD, with X = columns [k0, k0 + KD); the workgroup
-// of tile (0, 0) factors the 64 x 64 diagonal block at base.  Block b =
-// tile * nz + system (the tiles (0, 0) of all systems first).  escale:
-// per-row exponents (FP32 only), system z at escale + z se.
+// of tile (0, 0) factors the 64 x 64 diagonal block at base.  Work item
+// b = tile * nz + system (the tiles (0, 0) of all systems first), nwork of
+// them; the grid is 8 ceil(nwork / 8) blocks, dealt to the eight XCDs (which
+// take workgroups round-robin) in contiguous ranges of b, so that an XCD's
+// L2 serves consecutive tiles, which share their block row of X; blocks
+// past nwork exit.  escale: per-row exponents (FP32 only), system z at
+// escale + z se.
+__device__ __forceinline__ int64_t xcd_deal(int64_t b, int64_t nblocks) {
+  const int64_t per = nblocks / 8;  // nblocks is a multiple of 8
+  return (b % 8) * per + b / 8;
+}
+
 template <class T, int KD>
 __global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                                  T *__restrict__ Linv_next, T *__restrict__ LinvT_next,
                                                  int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
-                                                 const int *__restrict__ escale, int64_t se, int nz) {
+                                                 const int *__restrict__ escale, int64_t se, int nz,
+                                                 int64_t nwork) {
   constexpr bool F32 = std::is_same<T, float>::value;
-  const int64_t z = (int64_t)blockIdx.x % nz;
-  const int64_t x = (int64_t)blockIdx.x / nz;
+  const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
+  if (bw >= nwork) return;
+  const int64_t z = bw % nz;
+  const int64_t x = bw / nz;
   A += z * sA;
   Linv_next += z * sL;
   LinvT_next += z * sL;
