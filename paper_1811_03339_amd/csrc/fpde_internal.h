@@ -53,6 +53,12 @@ struct TubePlan {
   int4 *items = nullptr;          // pass-1 work: {tube, first block row, rows, |U_T|}
   int64_t *blk_off = nullptr;     // n_tubes + 1: offsets (doubles) of the |U_T|^2 blocks
   double *blk = nullptr;          // blk_n doubles of block scratch, allocated on first use
+  // the matrix-core contraction (mixed precision): work items {tube, region
+  // row, region column, |U_T|} over the upper 128 x 128 regions of every
+  // block, and per tube the power-of-two exponents of its two operands
+  int4 *mitems = nullptr;
+  int64_t n_mitems = 0;
+  int2 *texp = nullptr;
 };
 
 // Symbolic phase of one rule: derivative-vector sizes and the row transpose.

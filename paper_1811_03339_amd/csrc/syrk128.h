@@ -69,6 +69,7 @@ constexpr int KC16 = 32;
 struct Split16Smem {
   _Float16 a[2][2][T128][KC16];
   _Float16 b[2][2][T128][KC16];
+  float rsp[T128], rsq[T128];  // row scales 2^-e_r of X_I and X_J
 };
 __device__ __forceinline__ int swz(int row, int q) { return 8 * (q ^ ((row >> 2) & 3)); }
 
@@ -96,67 +97,91 @@ struct Syrk128Smem<double> {
   };
 };
 
-// Global loads of one CW-deep chunk: thread t reads CW / 2 consecutive
-// values of row t >> 1 (columns (CW / 2)(t & 1)..) of X_I and of X_J; rows at
-// or past the matrix end read a valid row and are zeroed when stored.
-template <class T, int CW>
-__device__ __forceinline__ void chunk_load(const T *__restrict__ P, const T *__restrict__ Q, int64_t lda, int prow,
-                                          int qrow, int kk, T (&pv)[CW / 2], T (&qv)[CW / 2]) {
-  const int t = threadIdx.x, rr = t >> 1, c0 = kk + (CW / 2) * (t & 1);
-  const T *pp = P + (int64_t)(rr < prow ? rr : prow - 1) * lda + c0;
-  const T *qq = Q + (int64_t)(rr < qrow ? rr : qrow - 1) * lda + c0;
+// Global loads of one chunk, coalesced: the sixteen lanes of a row group
+// read one 128-byte row segment.  FP32 (32 columns per chunk): thread t
+// reads columns 2 (t & 15) and 2 (t & 15) + 1 of rows (t >> 4) + 16 it,
+// it < 8; FP64 (16 columns): column t & 15 of the same rows.  Rows at or
+// past the matrix end read a valid row and are zeroed when stored.
+__device__ __forceinline__ int stage_row(int it) { return (threadIdx.x >> 4) + 16 * it; }
+
+// element offsets (row r clamped into [0, rows)) * lda + this thread's first
+// column, for the eight staged rows; they fit 32 bits (128 lda < 2^31)
+template <int CPL>
+__device__ __forceinline__ void stage_offsets(int rows, int64_t lda, int (&off)[8]) {
 #pragma unroll
-  for (int j = 0; j < CW / 2; j++) {
-    pv[j] = pp[j];
-    qv[j] = qq[j];
+  for (int it = 0; it < 8; it++) {
+    const int r = stage_row(it);
+    off[it] = (r < rows ? r : rows - 1) * (int)lda + CPL * (threadIdx.x & 15);
   }
 }
 
-// scaled split of this thread's 16 FP32 values (row rr, k groups 2h, 2h + 1)
-// into the hi and lo planes of one operand buffer
-__device__ __forceinline__ void split_store(const float (&v)[16], float s, bool live, int rr, int h,
+__device__ __forceinline__ void chunk_load(const float *__restrict__ P, const float *__restrict__ Q,
+                                          const int (&po)[8], const int (&qo)[8], float (&pv)[16],
+                                          float (&qv)[16]) {
+#pragma unroll
+  for (int it = 0; it < 8; it++) {
+    pv[2 * it] = P[po[it]];
+    pv[2 * it + 1] = P[po[it] + 1];
+    qv[2 * it] = Q[qo[it]];
+    qv[2 * it + 1] = Q[qo[it] + 1];
+  }
+}
+
+__device__ __forceinline__ void chunk_load(const double *__restrict__ P, const double *__restrict__ Q,
+                                          const int (&po)[8], const int (&qo)[8], double (&pv)[8],
+                                          double (&qv)[8]) {
+#pragma unroll
+  for (int it = 0; it < 8; it++) {
+    pv[it] = P[po[it]];
+    qv[it] = Q[qo[it]];
+  }
+}
+
+// scaled split of this thread's chunk values into the hi and lo planes of
+// one operand buffer (row scales 2^-e_r from LDS); two halfs per store
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_store(const float (&v)[16], const float *__restrict__ rs, int nrow,
                                             _Float16 (*hi)[KC16], _Float16 (*lo)[KC16]) {
+  const int c2 = 2 * (threadIdx.x & 15);
 #pragma unroll
-  for (int g = 0; g < 2; g++) {
-    half8 hv, lv;
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const float x = live ? v[8 * g + j] * s : 0.f;
-      const _Float16 a = (_Float16)x;
-      hv[j] = a;
-      lv[j] = (_Float16)(x - (float)a);
-    }
-    const int o = swz(rr, 2 * h + g);
-    *(half8 *)&hi[rr][o] = hv;
-    *(half8 *)&lo[rr][o] = lv;
+  for (int it = 0; it < 8; it++) {
+    const int r = stage_row(it);
+    const bool live = r < nrow;
+    const float s = rs[r];
+    const float x0 = live ? v[2 * it] * s : 0.f, x1 = live ? v[2 * it + 1] * s : 0.f;
+    const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
+    const int o = swz(r, c2 >> 3) + (c2 & 7);
+    *(half2v *)&hi[r][o] = half2v{h0, h1};
+    *(half2v *)&lo[r][o] = half2v{(_Float16)(x0 - (float)h0), (_Float16)(x1 - (float)h1)};
   }
 }
 
 // acc[a][b] (wavefront tile rows 16 a.., columns 16 b..) = X_I X_J^T over KD
-// columns, split FP16.  Result layout: lane l holds rows 4 (l >> 4) + i,
-// column l & 15 of each 16 x 16 tile.
+// columns, split FP16 (row scales in sm.rsp / sm.rsq).  Result layout: lane
+// l holds rows 4 (l >> 4) + i, column l & 15 of each 16 x 16 tile.
 template <int KD>
 __device__ __forceinline__ void product_split16(const float *__restrict__ P, const float *__restrict__ Q,
-                                                int64_t lda, int prow, int qrow, float sp, float sq, Split16Smem &sm,
+                                                int64_t lda, int prow, int qrow, Split16Smem &sm,
                                                 f32x4v (&acc)[4][4]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  const int rr = t >> 1, h = t & 1;
-  const bool plive = rr < prow, qlive = rr < qrow;
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  int po[8], qo[8];
+  stage_offsets<2>(prow, lda, po);
+  stage_offsets<2>(qrow, lda, qo);
   float pv[16], qv[16];
-  chunk_load<float, KC16>(P, Q, lda, prow, qrow, 0, pv, qv);
-  split_store(pv, sp, plive, rr, h, sm.a[0][0], sm.a[0][1]);
-  split_store(qv, sq, qlive, rr, h, sm.b[0][0], sm.b[0][1]);
+  chunk_load(P, Q, po, qo, pv, qv);
+  split_store(pv, sm.rsp, prow, sm.a[0][0], sm.a[0][1]);
+  split_store(qv, sm.rsq, qrow, sm.b[0][0], sm.b[0][1]);
   __syncthreads();
   const int q = lane >> 4;
 #pragma unroll 1
   for (int kk = 0; kk < KD; kk += KC16) {
     const int buf = (kk / KC16) & 1;
     const bool more = kk + KC16 < KD;
-    if (more) chunk_load<float, KC16>(P, Q, lda, prow, qrow, kk + KC16, pv, qv);
+    if (more) chunk_load(P + kk + KC16, Q + kk + KC16, po, qo, pv, qv);
     half8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
     for (int x = 0; x < 4; x++) {
@@ -175,8 +200,8 @@ __device__ __forceinline__ void product_split16(const float *__restrict__ P, con
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], acc[a][b], 0, 0, 0);
       }
     if (more) {
-      split_store(pv, sp, plive, rr, h, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
-      split_store(qv, sq, qlive, rr, h, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
+      split_store(pv, sm.rsp, prow, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
+      split_store(qv, sm.rsq, qrow, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
     }
     __syncthreads();
   }
@@ -188,18 +213,21 @@ template <int KD>
 __device__ __forceinline__ void product_f64(const double *__restrict__ P, const double *__restrict__ Q, int64_t lda,
                                             int prow, int qrow, F64Smem &sm, f64x4 (&acc)[4][4]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  const int rr = t >> 1, kc = (KC64 / 2) * (t & 1);
-  const bool plive = rr < prow, qlive = rr < qrow;
+  const int c = t & 15;
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double pv[KC64 / 2], qv[KC64 / 2];
-  chunk_load<double, KC64>(P, Q, lda, prow, qrow, 0, pv, qv);
+  int po[8], qo[8];
+  stage_offsets<1>(prow, lda, po);
+  stage_offsets<1>(qrow, lda, qo);
+  double pv[8], qv[8];
+  chunk_load(P, Q, po, qo, pv, qv);
 #pragma unroll
-  for (int j = 0; j < KC64 / 2; j++) {
-    sm.a[0][rr][kc + j] = plive ? pv[j] : 0.0;
-    sm.b[0][rr][kc + j] = qlive ? qv[j] : 0.0;
+  for (int it = 0; it < 8; it++) {
+    const int r = stage_row(it);
+    sm.a[0][r][c] = r < prow ? pv[it] : 0.0;
+    sm.b[0][r][c] = r < qrow ? qv[it] : 0.0;
   }
   __syncthreads();
   const int kq = lane >> 4;
@@ -207,7 +235,7 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
   for (int kk = 0; kk < KD; kk += KC64) {
     const int buf = (kk / KC64) & 1;
     const bool more = kk + KC64 < KD;
-    if (more) chunk_load<double, KC64>(P, Q, lda, prow, qrow, kk + KC64, pv, qv);
+    if (more) chunk_load(P + kk + KC64, Q + kk + KC64, po, qo, pv, qv);
 #pragma unroll
     for (int k4 = 0; k4 < KC64; k4 += 4) {
       double av[4], bv[4];
@@ -223,9 +251,10 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
     }
     if (more) {
 #pragma unroll
-      for (int j = 0; j < KC64 / 2; j++) {
-        sm.a[buf ^ 1][rr][kc + j] = plive ? pv[j] : 0.0;
-        sm.b[buf ^ 1][rr][kc + j] = qlive ? qv[j] : 0.0;
+      for (int it = 0; it < 8; it++) {
+        const int r = stage_row(it);
+        sm.a[buf ^ 1][r][c] = r < prow ? pv[it] : 0.0;
+        sm.b[buf ^ 1][r][c] = r < qrow ? qv[it] : 0.0;
       }
     }
     __syncthreads();
@@ -277,10 +306,10 @@ __global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda,
   int ec[4] = {0, 0, 0, 0}, er[4][4] = {};
   if constexpr (F32) {
     const int *es = escale + z * se;
-    const int rr = t >> 1;
-    const float sp = ldexpf(1.f, -es[ri + (rr < prow ? rr : prow - 1)]);
-    const float sq = ldexpf(1.f, -es[cj + (rr < qrow ? rr : qrow - 1)]);
-    product_split16<KD>(A + ri * lda + k0, A + cj * lda + k0, lda, prow, qrow, sp, sq, sm.g, acc);
+    if (t < T128) sm.g.rsp[t] = ldexpf(1.f, -es[ri + (t < prow ? t : prow - 1)]);
+    else sm.g.rsq[t - T128] = ldexpf(1.f, -es[cj + (t - T128 < qrow ? t - T128 : qrow - 1)]);
+    __syncthreads();
+    product_split16<KD>(A + ri * lda + k0, A + cj * lda + k0, lda, prow, qrow, sm.g, acc);
 #pragma unroll
     for (int b = 0; b < 4; b++) {
       const int c = 64 * wc + 16 * b + (lane & 15);

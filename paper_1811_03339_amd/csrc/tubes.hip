@@ -695,11 +695,276 @@ __global__ void __launch_bounds__(256) k_tube_gather_csr(GatherArgs a, const int
   }
 }
 
+// ---- Tube blocks on the matrix cores in split FP16 (mixed precision) ----
+//
+// The block of a tube is one product B = X Y^T with an inner dimension of
+// two columns per pair p: X_{:,2p} = W_p l_p, X_{:,2p+1} = W_p r_p,
+// Y_{:,2p} = r_p, Y_{:,2p+1} = l_p (W_p = w_g K_i c_alpha), so that
+// (X Y^T)_jk = sum_p W_p (l_j r_k + r_j l_k): the L W R^T contraction of the
+// element quadrature, symmetric.  One workgroup (four wavefronts, 64 x 64
+// each) computes a 128 x 128 region (I, J), I <= J, of B and writes it and
+// its mirror into the tube's block.  The pairs go through LDS sixteen at a
+// time (32 inner columns, one depth of v_mfma_f32_16x16x32_f16): their
+// entries are added into FP32 panels (a node may appear twice in one
+// half-ray), then split into FP16 hi + lo after scaling X and Y by the
+// tube's powers of two (largest magnitude in [2^13, 2^14)), and the region
+// accumulates hi hi + hi lo + lo hi in FP32 (22 significant bits per operand;
+// the dropped lo lo term is below 2^-22 of each product).
+constexpr int kRegion = 128;
+constexpr int kChunkPairs = 16;
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int tswz(int row, int q) { return 8 * (q ^ ((row >> 2) & 3)); }
+
+constexpr int kPanelStride = 2 * kChunkPairs + 1;  // odd: the rows of one column fall in distinct banks
+struct TubeMfmaSmem {
+  float fx[kRegion][kPanelStride];  // FP32 panels, entries added
+  float fy[kRegion][kPanelStride];
+  _Float16 hx[2][kRegion][2 * kChunkPairs];  // [hi, lo][row][inner], 16-byte groups swizzled
+  _Float16 hy[2][kRegion][2 * kChunkPairs];
+};
+
+// per tube: exponents {ex, ey} of X (weighted values) and Y (values); one
+// wavefront per tube
+__global__ void __launch_bounds__(256) k_tube_scale(const int64_t *__restrict__ tube_off, const int4 *__restrict__ pm,
+                                                    const double *__restrict__ pw, const double *__restrict__ val,
+                                                    int64_t n_tubes, double KC0, double KC1, double KC2,
+                                                    int2 *__restrict__ texp) {
+  const int lane = threadIdx.x & 63;
+  const int64_t T = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (T >= n_tubes) return;
+  double mx = 0.0, my = 0.0;
+  for (int64_t k = tube_off[T]; k < tube_off[T + 1]; k++) {
+    const int4 m = pm[k];
+    const int axis = (int)((unsigned)m.w >> 30);
+    const double w = fabs(pw[k] * (axis == 0 ? KC0 : (axis == 1 ? KC1 : KC2)));
+    const int nl = pair_nl(m), nr = pair_nr(m);
+    for (int e = lane; e < nl + nr; e += 64) {
+      const double v = fabs(val[e < nl ? m.x + e : m.y + (e - nl)]);
+      my = fmax(my, v);
+      mx = fmax(mx, w * v);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    my = fmax(my, __shfl_xor(my, o, 64));
+  }
+  if (lane == 0) {
+    auto ex = [](double v) {
+      int e = v > 0.0 ? ilogb(v) - 13 : 0;
+      return e < -120 ? -120 : (e > 120 ? 120 : e);
+    };
+    texp[T] = make_int2(ex(mx), ex(my));
+  }
+}
+
+__global__ void k_region_count(const int64_t *__restrict__ u_off, int64_t n_tubes, int64_t *__restrict__ cnt) {
+  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= n_tubes) return;
+  const int64_t U = u_off[T + 1] - u_off[T];
+  const int64_t nr = (U + kRegion - 1) / kRegion;
+  cnt[T] = nr * (nr + 1) / 2;
+}
+
+__global__ void k_region_items(const int64_t *__restrict__ u_off, int64_t n_tubes, const int64_t *__restrict__ off,
+                               int4 *__restrict__ items) {
+  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= n_tubes) return;
+  const int U = (int)(u_off[T + 1] - u_off[T]);
+  const int nr = (U + kRegion - 1) / kRegion;
+  int64_t w = off[T];
+  for (int I = 0; I < nr; I++)
+    for (int J = I; J < nr; J++) items[w++] = make_int4((int)T, I, J, U);
+}
+
+// Work item b of n_items; the grid is 8 ceil(n_items / 8) blocks dealt to
+// the eight XCDs (round-robin by block) in contiguous ranges of b, so the
+// regions of one tube, consecutive items, share an XCD's L2 for the
+// tube's entries.
+__global__ void __launch_bounds__(256) k_tube_mfma(AccumArgs a, const int4 *__restrict__ items, int64_t n_items,
+                                                   const int2 *__restrict__ texp) {
+  __shared__ TubeMfmaSmem sm;
+  const int64_t bw = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  if (bw >= n_items) return;
+  const int4 it = items[bw];
+  const int64_t T = it.x;
+  const int U = it.w, rx0 = kRegion * it.y, ry0 = kRegion * it.z;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  const int4 *__restrict__ pm = a.pm;
+  const double *__restrict__ pw = a.pw;
+  const int32_t *__restrict__ eslot = a.ent_slot;
+  const double *__restrict__ evals = a.ent_val;
+  const int64_t k0 = a.tube_off[T], k1 = a.tube_off[T + 1];
+  const int2 te = texp[T];
+  const double sx = ldexp(1.0, -te.x), sy = ldexp(1.0, -te.y);
+  const double kc0 = a.KC0, kc1 = a.KC1, kc2 = a.KC2;
+  // this thread's 16 panel values (row t >> 1, inner columns 16 (t & 1)..)
+  const int pr = t >> 1, pc = 16 * (t & 1);
+  float *fxr = &sm.fx[pr][pc], *fyr = &sm.fy[pr][pc];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    fxr[j] = 0.f;
+    fyr[j] = 0.f;
+  }
+  f32x4v acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; x++)
+#pragma unroll
+    for (int y = 0; y < 4; y++) acc[x][y] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  const int q = lane >> 4;
+  // Sixteen threads per pair (pair pl of each chunk, entries e = t & 15,
+  // + 16, ...).  Software pipeline: the metadata of chunk c + 2 and the
+  // first twelve entries per thread of chunk c + 1 are loaded while chunk c
+  // is split and multiplied.
+  const int pl = t >> 4, el = t & 15;
+  constexpr int kPre = 12;
+  int4 m_cur = make_int4(0, 0, 0, 0), m_nxt = make_int4(0, 0, 0, 0);
+  double w_cur = 0.0, w_nxt = 0.0;
+  int sl[kPre];
+  double va[kPre];
+  {
+    const int64_t kk = k0 + pl;
+    if (kk < k1) {
+      m_cur = pm[kk];
+      const int ax = (int)((unsigned)m_cur.w >> 30);
+      w_cur = pw[kk] * (ax == 0 ? kc0 : (ax == 1 ? kc1 : kc2));
+    }
+    const int64_t kn = k0 + kChunkPairs + pl;
+    if (kn < k1) {
+      m_nxt = pm[kn];
+      const int ax = (int)((unsigned)m_nxt.w >> 30);
+      w_nxt = pw[kn] * (ax == 0 ? kc0 : (ax == 1 ? kc1 : kc2));
+    }
+    const int nl = pair_nl(m_cur), ne = nl + pair_nr(m_cur);
+#pragma unroll
+    for (int j = 0; j < kPre; j++) {
+      const int e = el + 16 * j;
+      const int ec = e < ne ? e : 0;
+      const int64_t ei = ne > 0 ? (ec < nl ? (int64_t)m_cur.x + ec : (int64_t)m_cur.y + (ec - nl)) : 0;
+      sl[j] = eslot[ei];
+      va[j] = evals[ei];
+    }
+  }
+  __syncthreads();
+  for (int64_t kc = k0; kc < k1; kc += kChunkPairs) {
+    // chunk kc's entries into the FP32 panels: the prefetched ones, then
+    // any past the twelfth per thread
+    {
+      const int nl = pair_nl(m_cur), ne = nl + pair_nr(m_cur);
+#pragma unroll
+      for (int j = 0; j < kPre; j++) {
+        const int e = el + 16 * j;
+        if (e < ne) {
+          const bool isl = e < nl;
+          const int cx = 2 * pl + (isl ? 0 : 1), cy = 2 * pl + (isl ? 1 : 0);
+          if ((unsigned)(sl[j] - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[sl[j] - rx0][cx], (float)(w_cur * va[j] * sx));
+          if ((unsigned)(sl[j] - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[sl[j] - ry0][cy], (float)(va[j] * sy));
+        }
+      }
+      for (int e = el + 16 * kPre; e < ne; e += 16) {
+        const bool isl = e < nl;
+        const int64_t ei = isl ? (int64_t)m_cur.x + e : (int64_t)m_cur.y + (e - nl);
+        const int s1 = eslot[ei];
+        const double v1 = evals[ei];
+        const int cx = 2 * pl + (isl ? 0 : 1), cy = 2 * pl + (isl ? 1 : 0);
+        if ((unsigned)(s1 - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[s1 - rx0][cx], (float)(w_cur * v1 * sx));
+        if ((unsigned)(s1 - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[s1 - ry0][cy], (float)(v1 * sy));
+      }
+    }
+    __syncthreads();
+    // split into hi and lo (and clear the FP32 panels for the next chunk)
+#pragma unroll
+    for (int g = 0; g < 2; g++) {
+      half8 xh, xl, yh, yl;
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const float xv = fxr[8 * g + j], yv = fyr[8 * g + j];
+        const _Float16 xa = (_Float16)xv, ya = (_Float16)yv;
+        xh[j] = xa;
+        xl[j] = (_Float16)(xv - (float)xa);
+        yh[j] = ya;
+        yl[j] = (_Float16)(yv - (float)ya);
+        fxr[8 * g + j] = 0.f;
+        fyr[8 * g + j] = 0.f;
+      }
+      const int o = tswz(pr, (pc >> 3) + g);
+      *(half8 *)&sm.hx[0][pr][o] = xh;
+      *(half8 *)&sm.hx[1][pr][o] = xl;
+      *(half8 *)&sm.hy[0][pr][o] = yh;
+      *(half8 *)&sm.hy[1][pr][o] = yl;
+    }
+    __syncthreads();
+    // next chunk: its metadata becomes current, the one after is loaded,
+    // and its first entries are loaded during the products below
+    m_cur = m_nxt;
+    w_cur = w_nxt;
+    {
+      const int64_t kn = kc + 2 * kChunkPairs + pl;
+      m_nxt = make_int4(0, 0, 0, 0);
+      w_nxt = 0.0;
+      if (kn < k1) {
+        m_nxt = pm[kn];
+        const int ax = (int)((unsigned)m_nxt.w >> 30);
+        w_nxt = pw[kn] * (ax == 0 ? kc0 : (ax == 1 ? kc1 : kc2));
+      }
+      const int nl = pair_nl(m_cur), ne = nl + pair_nr(m_cur);
+#pragma unroll
+      for (int j = 0; j < kPre; j++) {
+        const int e = el + 16 * j;
+        const int ec = e < ne ? e : 0;
+        const int64_t ei = ne > 0 ? (ec < nl ? (int64_t)m_cur.x + ec : (int64_t)m_cur.y + (ec - nl)) : 0;
+        sl[j] = eslot[ei];
+        va[j] = evals[ei];
+      }
+    }
+    half8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int x = 0; x < 4; x++) {
+      const int ar = 64 * wr + 16 * x + (lane & 15), br = 64 * wc + 16 * x + (lane & 15);
+      ah[x] = *(const half8 *)&sm.hx[0][ar][tswz(ar, q)];
+      al[x] = *(const half8 *)&sm.hx[1][ar][tswz(ar, q)];
+      bh[x] = *(const half8 *)&sm.hy[0][br][tswz(br, q)];
+      bl[x] = *(const half8 *)&sm.hy[1][br][tswz(br, q)];
+    }
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = 0; y < 4; y++) {
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[x], bh[y], acc[x][y], 0, 0, 0);
+      }
+    // the next chunk adds into the FP32 panels (cleared above) while these
+    // operands are in registers; its split waits at the barrier after the adds
+  }
+  // region (I, J) of the block and, off the diagonal of regions, its mirror
+  double *out = a.blk + a.blk_off[T];
+  const int eu = te.x + te.y;
+#pragma unroll
+  for (int x = 0; x < 4; x++)
+#pragma unroll
+    for (int y = 0; y < 4; y++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = rx0 + 64 * wr + 16 * x + 4 * (lane >> 4) + i;
+        const int c = ry0 + 64 * wc + 16 * y + (lane & 15);
+        if (r < U && c < U) {
+          const double v = ldexp((double)acc[x][y][i], eu);
+          out[(int64_t)r * U + c] = v;
+          if (it.y != it.z) out[(int64_t)c * U + r] = v;
+        }
+      }
+}
+
 }  // namespace
 
 void free_tubes(TubePlan &tp) {
   dfree(tp.pair_sorted); dfree(tp.pm); dfree(tp.pw); dfree(tp.tube_off); dfree(tp.u_off); dfree(tp.tube_u); dfree(tp.ent_slot);
   dfree(tp.row_off); dfree(tp.row_ts); dfree(tp.items); dfree(tp.blk_off); dfree(tp.blk);
+  dfree(tp.mitems); dfree(tp.texp);
   tp = TubePlan();
 }
 
@@ -856,7 +1121,43 @@ int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s) {
 #undef HIP_T
 }
 
-// Pass 1 (the tube blocks) for order p->alpha and coefficients p->K.
+// Work items of the matrix-core contraction: the upper 128 x 128 regions of
+// every tube block.
+static int build_region_items(fpde_mesh *m, TubePlan &tp, hipStream_t s) {
+  const int64_t nT = tp.n_tubes;
+  if (nT == 0) return FPDE_OK;
+  int64_t *cnt = nullptr, *off = nullptr;
+  void *tmp = nullptr;
+  size_t need = 0;
+  int st = FPDE_OK;
+  auto done = [&](int code) {
+    dfree(cnt);
+    dfree(off);
+    if (tmp) (void)hipFree(tmp);
+    return code;
+  };
+  if ((st = dalloc(&cnt, nT + 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&off, nT + 1)) != FPDE_OK) return done(st);
+  if (hipMemsetAsync(cnt, 0, sizeof(int64_t) * (nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
+  k_region_count<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, cnt);
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, cnt, off, (int)(nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
+  if (hipMalloc(&tmp, need) != hipSuccess) return done(FPDE_ENOMEM);
+  if (hipcub::DeviceScan::ExclusiveSum(tmp, need, cnt, off, (int)(nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
+  int64_t total = 0;
+  if (hipMemcpyAsync(&total, off + nT, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(FPDE_EHIP);
+  if (total >= (int64_t(1) << 31)) return done(FPDE_EUNSUPPORTED);
+  if ((st = dalloc(&tp.mitems, total > 0 ? total : 1)) != FPDE_OK) return done(st);
+  k_region_items<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, off, tp.mitems);
+  tp.n_mitems = total;
+  if (hipGetLastError() != hipSuccess) return done(FPDE_EHIP);
+  return done(FPDE_OK);
+}
+
+// Pass 1 (the tube blocks) for order p->alpha and coefficients p->K:
+// FP64 LDS accumulation, or for the mixed-precision matrix the split-FP16
+// matrix-core contraction.
 static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, hipStream_t s) {
   TubePlan &tp = P.tubes;
   if (!tp.blk) {
@@ -875,6 +1176,20 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
   a.KC0 = p->K[0] * o.c_alpha;
   a.KC1 = p->K[1] * o.c_alpha;
   a.KC2 = p->K[2] * o.c_alpha;
+  if (p->precision == FPDE_MIXED) {
+    // split FP16 on the matrix cores: region items once per plan, exponents
+    // per assembly (they follow the values)
+    if (!tp.mitems) FPDE_TRY(build_region_items(m, tp, s));
+    if (!tp.texp) FPDE_TRY(dalloc(&tp.texp, tp.n_tubes > 0 ? tp.n_tubes : 1));
+    const long ta = timer_begin(m, s, FPDE_STAGE_ACCUM);
+    if (tp.n_tubes > 0)
+      k_tube_scale<<<nblocks(tp.n_tubes, 4), 256, 0, s>>>(tp.tube_off, tp.pm, tp.pw, P.ent_val, tp.n_tubes, a.KC0,
+                                                          a.KC1, a.KC2, tp.texp);
+    if (tp.n_mitems > 0)
+      k_tube_mfma<<<(unsigned)(8 * ((tp.n_mitems + 7) / 8)), 256, 0, s>>>(a, tp.mitems, tp.n_mitems, tp.texp);
+    timer_end(m, FPDE_STAGE_ACCUM, ta, s);
+    return FPDE_OK;
+  }
   const long ta = timer_begin(m, s, FPDE_STAGE_ACCUM);
   if (tp.n_items > 0)
     k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
