@@ -139,6 +139,7 @@ struct fpde_mesh {
   int tsync_n = 0;                // ints allocated
   int64_t *batch_aux = nullptr;   // device, kMaxBatch: failing column per system of a batched factorization
   int *escale = nullptr;          // device: per-row exponents of the split-FP16 trailing updates
+  _Float16 *xsplit = nullptr;     // device: the split rows (hi, lo) of X for those updates
   int64_t escale_n = 0;
   double *bvec = nullptr;         // device: intermediate vectors of a batched solve
   int64_t bvec_n = 0;

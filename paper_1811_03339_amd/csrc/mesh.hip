@@ -573,6 +573,7 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   dfree(m->tsync);
   dfree(m->batch_aux);
   dfree(m->escale);
+  dfree(m->xsplit);
   dfree(m->bvec);
   dfree(m->pbox);
   dfree(m->cg);

@@ -367,17 +367,24 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
 template <class T>
 static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
                        fpde_mesh *m, hipStream_t s) {
-  // FP32: per-row exponents of the split-FP16 trailing updates (count x n)
+  // FP32: per-row exponents and split rows (2 x 256 halfs) of the
+  // split-FP16 trailing updates, count x n of each
+  constexpr int kGroup = 4;
   int *escale = nullptr;
+  _Float16 *xsplit = nullptr;
+  const int64_t sx = n * 2 * kGroup * NB;
   if (std::is_same<T, float>::value) {
     const int64_t need = (int64_t)count * n;
     if (m->escale_n < need) {
       dfree(m->escale);
+      dfree(m->xsplit);
       m->escale_n = 0;
       FPDE_TRY(dalloc(&m->escale, (size_t)need));
+      FPDE_TRY(dalloc(&m->xsplit, (size_t)(count * sx)));
       m->escale_n = need;
     }
     escale = m->escale;
+    xsplit = m->xsplit;
   }
   const long t = timer_begin(m, s, FPDE_STAGE_POTRF);
   // the first diagonal block on its own; every later one is factored by the
@@ -392,7 +399,6 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
   // next diagonal block), and the trailing matrix beyond the group is
   // updated once by the whole group (KD = 64 kGroup, 128 x 128 tiles): the
   // trailing matrix is read and written once per kGroup panels.
-  constexpr int kGroup = 4;
   for (int64_t k0 = 0; k0 < n; k0 += kGroup * NB) {
     for (int sp = 0; sp < kGroup; sp++) {
       const int64_t ks = k0 + sp * NB;
@@ -419,10 +425,10 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
         const int64_t T2 = (n - base + T128 - 1) / T128;
         const int64_t work = T2 * (T2 + 1) / 2 * count;
         if (escale)
-          k_row_scale<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
-              (const float *)A, lda, n, base, k0, escale, sA, n);
+          k_row_split<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
+              (const float *)A, lda, n, base, k0, escale, xsplit, sA, n, sx);
         k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), 256, 0, s>>>(
-            A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, count, work);
+            A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
       }
     }
   }

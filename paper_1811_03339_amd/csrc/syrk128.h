@@ -38,26 +38,49 @@ constexpr int T128 = 128;
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
-// exponent e_r of each row r in [r0, n) of the KD columns at k0:
-// max_k |A[r][k0 + k]| * 2^-e_r in [2^13, 2^14), e_r within [-110, 110]
-// (0 for an all-zero row).  One wavefront per row; batch z = blockIdx.y
-// (rows of system z at A + z sA, exponents at escale + z se).
+// The group's columns of X in split FP16, once per group (every trailing
+// tile then stages them as they are): for each row r in [r0, n) of the KD
+// columns at k0, the exponent e_r with max_k |A[r][k0 + k]| 2^-e_r in
+// [2^13, 2^14) (e_r within [-110, 110], 0 for an all-zero row), and
+// x 2^-e_r = hi + lo, hi = fp16(x 2^-e_r), lo = fp16(x 2^-e_r - hi), stored
+// row-major: xs[r][0][k] = hi, xs[r][1][k] = lo (KD halfs each).  One
+// wavefront per row, KD / 64 columns per lane; batch z = blockIdx.y (rows of
+// system z at A + z sA, exponents at escale + z se, split rows at xs + z sx).
 template <int KD>
-__global__ void __launch_bounds__(256) k_row_scale(const float *__restrict__ A, int64_t lda, int64_t n, int64_t r0,
-                                                   int64_t k0, int *__restrict__ escale, int64_t sA, int64_t se) {
+__global__ void __launch_bounds__(256) k_row_split(const float *__restrict__ A, int64_t lda, int64_t n, int64_t r0,
+                                                   int64_t k0, int *__restrict__ escale, _Float16 *__restrict__ xs,
+                                                   int64_t sA, int64_t se, int64_t sx) {
+  constexpr int PL = KD / 64;  // consecutive columns per lane
   const int lane = threadIdx.x & 63;
   const int64_t r = r0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   A += (int64_t)blockIdx.y * sA;
   escale += (int64_t)blockIdx.y * se;
+  xs += (int64_t)blockIdx.y * sx;
   if (r >= n) return;
+  float v[PL];
   float mx = 0.f;
 #pragma unroll
-  for (int k = lane; k < KD; k += 64) mx = fmaxf(mx, fabsf(A[r * lda + k0 + k]));
+  for (int j = 0; j < PL; j++) {
+    v[j] = A[r * lda + k0 + PL * lane + j];
+    mx = fmaxf(mx, fabsf(v[j]));
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0) {
-    int e = mx > 0.f ? ilogbf(mx) - 13 : 0;
-    escale[r] = e < -110 ? -110 : (e > 110 ? 110 : e);
+  int e = mx > 0.f ? ilogbf(mx) - 13 : 0;
+  e = e < -110 ? -110 : (e > 110 ? 110 : e);
+  if (lane == 0) escale[r] = e;
+  _Float16 hi[PL], lo[PL];
+#pragma unroll
+  for (int j = 0; j < PL; j++) {
+    const float x = ldexpf(v[j], -e);
+    hi[j] = (_Float16)x;
+    lo[j] = (_Float16)(x - (float)hi[j]);
+  }
+  _Float16 *row = xs + r * (2 * KD);
+#pragma unroll
+  for (int j = 0; j < PL; j++) {
+    row[PL * lane + j] = hi[j];
+    row[KD + PL * lane + j] = lo[j];
   }
 }
 
@@ -69,7 +92,6 @@ constexpr int KC16 = 32;
 struct Split16Smem {
   _Float16 a[2][2][T128][KC16];
   _Float16 b[2][2][T128][KC16];
-  float rsp[T128], rsq[T128];  // row scales 2^-e_r of X_I and X_J
 };
 __device__ __forceinline__ int swz(int row, int q) { return 8 * (q ^ ((row >> 2) & 3)); }
 
@@ -115,18 +137,6 @@ __device__ __forceinline__ void stage_offsets(int rows, int64_t lda, int (&off)[
   }
 }
 
-__device__ __forceinline__ void chunk_load(const float *__restrict__ P, const float *__restrict__ Q,
-                                          const int (&po)[8], const int (&qo)[8], float (&pv)[16],
-                                          float (&qv)[16]) {
-#pragma unroll
-  for (int it = 0; it < 8; it++) {
-    pv[2 * it] = P[po[it]];
-    pv[2 * it + 1] = P[po[it] + 1];
-    qv[2 * it] = Q[qo[it]];
-    qv[2 * it + 1] = Q[qo[it] + 1];
-  }
-}
-
 __device__ __forceinline__ void chunk_load(const double *__restrict__ P, const double *__restrict__ Q,
                                           const int (&po)[8], const int (&qo)[8], double (&pv)[8],
                                           double (&qv)[8]) {
@@ -137,51 +147,65 @@ __device__ __forceinline__ void chunk_load(const double *__restrict__ P, const d
   }
 }
 
-// scaled split of this thread's chunk values into the hi and lo planes of
-// one operand buffer (row scales 2^-e_r from LDS); two halfs per store
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void split_store(const float (&v)[16], const float *__restrict__ rs, int nrow,
-                                            _Float16 (*hi)[KC16], _Float16 (*lo)[KC16]) {
-  const int c2 = 2 * (threadIdx.x & 15);
+// Staging of the split X: one chunk is, per row, 32 hi and 32 lo halfs
+// (four 16-byte groups each).  Thread t moves groups 2 (t & 1) and
+// 2 (t & 1) + 1 of both planes of row t >> 1 (rows past the tile's end read
+// the last row and are zeroed).
+struct SplitChunk {
+  half8 v[4];  // [plane][group]: hi g0, hi g1, lo g0, lo g1
+};
+
+__device__ __forceinline__ void split_load(const _Float16 *__restrict__ xrow, int kk, SplitChunk &c) {
+  const int g0 = 2 * (threadIdx.x & 1);
 #pragma unroll
-  for (int it = 0; it < 8; it++) {
-    const int r = stage_row(it);
-    const bool live = r < nrow;
-    const float s = rs[r];
-    const float x0 = live ? v[2 * it] * s : 0.f, x1 = live ? v[2 * it + 1] * s : 0.f;
-    const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
-    const int o = swz(r, c2 >> 3) + (c2 & 7);
-    *(half2v *)&hi[r][o] = half2v{h0, h1};
-    *(half2v *)&lo[r][o] = half2v{(_Float16)(x0 - (float)h0), (_Float16)(x1 - (float)h1)};
+  for (int pl = 0; pl < 2; pl++)
+#pragma unroll
+    for (int g = 0; g < 2; g++) c.v[2 * pl + g] = *(const half8 *)(xrow + pl * 256 + kk + 8 * (g0 + g));
+}
+
+__device__ __forceinline__ void split_put(const SplitChunk &c, bool live, _Float16 (*hi)[KC16],
+                                          _Float16 (*lo)[KC16]) {
+  const int r = threadIdx.x >> 1, g0 = 2 * (threadIdx.x & 1);
+  const half8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int g = 0; g < 2; g++) {
+    *(half8 *)&hi[r][swz(r, g0 + g)] = live ? c.v[g] : z;
+    *(half8 *)&lo[r][swz(r, g0 + g)] = live ? c.v[2 + g] : z;
   }
 }
 
 // acc[a][b] (wavefront tile rows 16 a.., columns 16 b..) = X_I X_J^T over KD
-// columns, split FP16 (row scales in sm.rsp / sm.rsq).  Result layout: lane
-// l holds rows 4 (l >> 4) + i, column l & 15 of each 16 x 16 tile.
+// columns, split FP16, from the split rows xi (of X_I) and xj (of X_J).
+// Result layout: lane l holds rows 4 (l >> 4) + i, column l & 15 of each
+// 16 x 16 tile.
 template <int KD>
-__device__ __forceinline__ void product_split16(const float *__restrict__ P, const float *__restrict__ Q,
-                                                int64_t lda, int prow, int qrow, Split16Smem &sm,
-                                                f32x4v (&acc)[4][4]) {
+__device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi, const _Float16 *__restrict__ xj,
+                                                int prow, int qrow, Split16Smem &sm, f32x4v (&acc)[4][4]) {
+  static_assert(KD == 256, "split rows are laid out for 256 columns");
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  const int rr = t >> 1;
+  const bool plive = rr < prow, qlive = rr < qrow;
+  const _Float16 *pr = xi + (int64_t)(plive ? rr : prow - 1) * (2 * KD);
+  const _Float16 *qr = xj + (int64_t)(qlive ? rr : qrow - 1) * (2 * KD);
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = f32x4v{0.f, 0.f, 0.f, 0.f};
-  int po[8], qo[8];
-  stage_offsets<2>(prow, lda, po);
-  stage_offsets<2>(qrow, lda, qo);
-  float pv[16], qv[16];
-  chunk_load(P, Q, po, qo, pv, qv);
-  split_store(pv, sm.rsp, prow, sm.a[0][0], sm.a[0][1]);
-  split_store(qv, sm.rsq, qrow, sm.b[0][0], sm.b[0][1]);
+  SplitChunk pc, qc;
+  split_load(pr, 0, pc);
+  split_load(qr, 0, qc);
+  split_put(pc, plive, sm.a[0][0], sm.a[0][1]);
+  split_put(qc, qlive, sm.b[0][0], sm.b[0][1]);
   __syncthreads();
   const int q = lane >> 4;
 #pragma unroll 1
   for (int kk = 0; kk < KD; kk += KC16) {
     const int buf = (kk / KC16) & 1;
     const bool more = kk + KC16 < KD;
-    if (more) chunk_load(P + kk + KC16, Q + kk + KC16, po, qo, pv, qv);
+    if (more) {
+      split_load(pr, kk + KC16, pc);
+      split_load(qr, kk + KC16, qc);
+    }
     half8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
     for (int x = 0; x < 4; x++) {
@@ -200,8 +224,8 @@ __device__ __forceinline__ void product_split16(const float *__restrict__ P, con
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], acc[a][b], 0, 0, 0);
       }
     if (more) {
-      split_store(pv, sm.rsp, prow, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
-      split_store(qv, sm.rsq, qrow, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
+      split_put(pc, plive, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
+      split_put(qc, qlive, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
     }
     __syncthreads();
   }
@@ -268,8 +292,8 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
 // them; the grid is 8 ceil(nwork / 8) blocks, dealt to the eight XCDs (which
 // take workgroups round-robin) in contiguous ranges of b, so that an XCD's
 // L2 serves consecutive tiles, which share their block row of X; blocks
-// past nwork exit.  escale: per-row exponents (FP32 only), system z at
-// escale + z se.
+// past nwork exit.  FP32 only: escale and xs, the per-row exponents and
+// split rows of X from k_row_split, system z at escale + z se and xs + z sx.
 __device__ __forceinline__ int64_t xcd_deal(int64_t b, int64_t nblocks) {
   const int64_t per = nblocks / 8;  // nblocks is a multiple of 8
   return (b % 8) * per + b / 8;
@@ -279,7 +303,8 @@ template <class T, int KD>
 __global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                                  T *__restrict__ Linv_next, T *__restrict__ LinvT_next,
                                                  int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
-                                                 const int *__restrict__ escale, int64_t se, int nz,
+                                                 const int *__restrict__ escale, int64_t se,
+                                                 const _Float16 *__restrict__ xs, int64_t sx, int nz,
                                                  int64_t nwork) {
   constexpr bool F32 = std::is_same<T, float>::value;
   const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
@@ -306,10 +331,8 @@ __global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda,
   int ec[4] = {0, 0, 0, 0}, er[4][4] = {};
   if constexpr (F32) {
     const int *es = escale + z * se;
-    if (t < T128) sm.g.rsp[t] = ldexpf(1.f, -es[ri + (t < prow ? t : prow - 1)]);
-    else sm.g.rsq[t - T128] = ldexpf(1.f, -es[cj + (t - T128 < qrow ? t - T128 : qrow - 1)]);
-    __syncthreads();
-    product_split16<KD>(A + ri * lda + k0, A + cj * lda + k0, lda, prow, qrow, sm.g, acc);
+    const _Float16 *x0 = xs + z * sx;
+    product_split16<KD>(x0 + ri * (2 * KD), x0 + cj * (2 * KD), prow, qrow, sm.g, acc);
 #pragma unroll
     for (int b = 0; b < 4; b++) {
       const int c = 64 * wc + 16 * b + (lane & 15);
@@ -334,7 +357,25 @@ __global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda,
     else return acc[a][b][i];
   };
   const bool keep = x == 0 && w == 0;  // the next diagonal block, factored below
-  if (!keep) {
+  // a tile strictly below the diagonal and inside the matrix needs neither
+  // clamped loads nor guarded stores: 32-bit offsets from this lane's first
+  // entry (128 lda < 2^31)
+  const bool interior = J < I && ri + T128 <= n && cj + T128 <= n;
+  if (interior) {
+    T *p0 = A + (ri + frow(0, 0)) * lda + cj + fcol(0);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      T cv[4][4];
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) cv[b][i] = p0[(frow(a, i) - frow(0, 0)) * (int)lda + 16 * b];
+#pragma unroll
+      for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) p0[(frow(a, i) - frow(0, 0)) * (int)lda + 16 * b] = cv[b][i] - val(a, b, i);
+    }
+  } else if (!keep) {
     // one block row of 16 at a time: its 16 entries of C loaded first
     // (indices clamped into the matrix), then updated and stored
 #pragma unroll
