@@ -55,10 +55,18 @@ struct TubePlan {
   double *blk = nullptr;          // blk_n doubles of block scratch, allocated on first use
   // the matrix-core contraction (mixed precision): work items {tube, region
   // row, region column, |U_T|} over the upper 128 x 128 regions of every
-  // block, and per tube the power-of-two exponents of its two operands
+  // block, and per tube the largest binary exponents of its two operands
   int4 *mitems = nullptr;
   int64_t n_mitems = 0;
   int2 *texp = nullptr;
+  // the entries packed contiguously in sorted-pair order (l then r of each
+  // pair): first packed entry of every pair, per packed entry its tube
+  // slot | (inner column << 16) (column 2 (pair mod 16) + side), and the
+  // values in FP32 (repacked at every assembly)
+  int64_t *pk_pair = nullptr;
+  uint32_t *pk_meta = nullptr;
+  float *pk_val = nullptr;
+  int32_t *pk_tube = nullptr;  // per sorted pair: its tube
 };
 
 // Symbolic phase of one rule: derivative-vector sizes and the row transpose.

@@ -29,6 +29,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -726,39 +727,88 @@ struct TubeMfmaSmem {
   _Float16 hy[2][kRegion][2 * kChunkPairs];
 };
 
-// per tube: exponents {ex, ey} of X (weighted values) and Y (values); one
-// wavefront per tube
-__global__ void __launch_bounds__(256) k_tube_scale(const int64_t *__restrict__ tube_off, const int4 *__restrict__ pm,
-                                                    const double *__restrict__ pw, const double *__restrict__ val,
-                                                    int64_t n_tubes, double KC0, double KC1, double KC2,
-                                                    int2 *__restrict__ texp) {
+// packed entries of every sorted pair (plan time): one wavefront per pair
+__global__ void __launch_bounds__(256) k_pack_meta(const int64_t *__restrict__ tube_off, int64_t n_tubes,
+                                                   const int4 *__restrict__ pm, const int64_t *__restrict__ pk_pair,
+                                                   int64_t n_pairs, const int32_t *__restrict__ ent_slot,
+                                                   uint32_t *__restrict__ pk_meta, int32_t *__restrict__ pk_tube) {
   const int lane = threadIdx.x & 63;
-  const int64_t T = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (T >= n_tubes) return;
-  double mx = 0.0, my = 0.0;
-  for (int64_t k = tube_off[T]; k < tube_off[T + 1]; k++) {
-    const int4 m = pm[k];
-    const int axis = (int)((unsigned)m.w >> 30);
-    const double w = fabs(pw[k] * (axis == 0 ? KC0 : (axis == 1 ? KC1 : KC2)));
-    const int nl = pair_nl(m), nr = pair_nr(m);
-    for (int e = lane; e < nl + nr; e += 64) {
-      const double v = fabs(val[e < nl ? m.x + e : m.y + (e - nl)]);
-      my = fmax(my, v);
-      mx = fmax(mx, w * v);
-    }
+  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= n_pairs) return;
+  // the pair's tube: the last T with tube_off[T] <= k
+  int64_t lo = 0, hi = n_tubes - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tube_off[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint32_t col0 = 2u * (uint32_t)((k - tube_off[lo]) % kChunkPairs);
+  if (lane == 0) pk_tube[k] = (int32_t)lo;
+  const int4 m = pm[k];
+  const int nl = pair_nl(m), ne = nl + pair_nr(m);
+  const int64_t p0 = pk_pair[k];
+  for (int e = lane; e < ne; e += 64) {
+    const bool side = e >= nl;
+    const int64_t ei = side ? (int64_t)m.y + (e - nl) : (int64_t)m.x + e;
+    pk_meta[p0 + e] = (uint32_t)ent_slot[ei] | ((col0 + (side ? 1u : 0u)) << 16);
+  }
+}
+
+__global__ void k_pair_count(const int4 *__restrict__ pm, int64_t n_pairs, int64_t *__restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_pairs) cnt[k] = pair_nl(pm[k]) + pair_nr(pm[k]);
+}
+
+__global__ void k_fill_int2(int2 *__restrict__ p, int64_t n, int2 v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// The values in pack order, FP32 (every assembly), one wavefront per pair;
+// and per tube the largest binary exponents of X (W_p |v|) and of Y (|v|):
+// texp must hold {INT_MIN, INT_MIN} per tube on entry and receives
+// atomic maxima (ilogb is monotone, so the maximum of the exponents is the
+// exponent of the maximum).
+__global__ void __launch_bounds__(256) k_pack_vals(const int4 *__restrict__ pm, const double *__restrict__ pw,
+                                                   const int64_t *__restrict__ pk_pair,
+                                                   const int32_t *__restrict__ pk_tube, int64_t n_pairs,
+                                                   const double *__restrict__ val, double KC0, double KC1, double KC2,
+                                                   float *__restrict__ pk_val, int2 *__restrict__ texp) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= n_pairs) return;
+  const int4 m = pm[k];
+  const int nl = pair_nl(m), nr = pair_nr(m);
+  float *out = pk_val + pk_pair[k];
+  float vm = 0.f;
+  for (int e = lane; e < nl; e += 64) {
+    const float v = (float)val[(int64_t)m.x + e];
+    out[e] = v;
+    vm = fmaxf(vm, fabsf(v));
+  }
+  for (int e = lane; e < nr; e += 64) {
+    const float v = (float)val[(int64_t)m.y + e];
+    out[nl + e] = v;
+    vm = fmaxf(vm, fabsf(v));
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, o, 64));
-    my = fmax(my, __shfl_xor(my, o, 64));
+  for (int o = 32; o > 0; o >>= 1) vm = fmaxf(vm, __shfl_xor(vm, o, 64));
+  if (lane == 0 && vm > 0.f) {
+    const int axis = (int)((unsigned)m.w >> 30);
+    const double w = fabs(pw[k]) * fabs(axis == 0 ? KC0 : (axis == 1 ? KC1 : KC2));
+    const double mx = w * (double)vm;
+    int *te = (int *)&texp[pk_tube[k]];
+    if (mx > 0.0) atomicMax(te, ilogb(mx));
+    atomicMax(te + 1, ilogb((double)vm));
   }
-  if (lane == 0) {
-    auto ex = [](double v) {
-      int e = v > 0.0 ? ilogb(v) - 13 : 0;
-      return e < -120 ? -120 : (e > 120 ? 120 : e);
-    };
-    texp[T] = make_int2(ex(mx), ex(my));
-  }
+}
+
+// scale exponent of an operand from its largest exponent: the largest
+// magnitude lands in [2^13, 2^14) (0 for an all-zero operand)
+__device__ __forceinline__ int tube_scale_exp(int e) {
+  if (e == INT_MIN) return 0;
+  e -= 13;
+  return e < -120 ? -120 : (e > 120 ? 120 : e);
 }
 
 __global__ void k_region_count(const int64_t *__restrict__ u_off, int64_t n_tubes, int64_t *__restrict__ cnt) {
@@ -780,27 +830,44 @@ __global__ void k_region_items(const int64_t *__restrict__ u_off, int64_t n_tube
     for (int J = I; J < nr; J++) items[w++] = make_int4((int)T, I, J, U);
 }
 
+
+struct TubeMfmaArgs {
+  const int64_t *tube_off;
+  const int4 *pm;
+  const double *pw;
+  const int64_t *pk_pair;
+  const uint32_t *pk_meta;
+  const float *pk_val;
+  const int64_t *blk_off;
+  double *blk;
+  double KC0, KC1, KC2;
+};
+
 // Work item b of n_items; the grid is 8 ceil(n_items / 8) blocks dealt to
 // the eight XCDs (round-robin by block) in contiguous ranges of b, so the
 // regions of one tube, consecutive items, share an XCD's L2 for the
-// tube's entries.
-__global__ void __launch_bounds__(256) k_tube_mfma(AccumArgs a, const int4 *__restrict__ items, int64_t n_items,
+// tube's packed entries.
+__global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *__restrict__ items, int64_t n_items,
                                                    const int2 *__restrict__ texp) {
   __shared__ TubeMfmaSmem sm;
+  __shared__ float sw[2][kChunkPairs];  // W_p 2^-ex of the chunk's pairs (double-buffered)
   const int64_t bw = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
   if (bw >= n_items) return;
   const int4 it = items[bw];
   const int64_t T = it.x;
   const int U = it.w, rx0 = kRegion * it.y, ry0 = kRegion * it.z;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  const int4 *__restrict__ pm = a.pm;
+  const int64_t *__restrict__ pk_pair = a.pk_pair;
+  const uint32_t *__restrict__ pk_meta = a.pk_meta;
+  const float *__restrict__ pk_val = a.pk_val;
   const double *__restrict__ pw = a.pw;
-  const int32_t *__restrict__ eslot = a.ent_slot;
-  const double *__restrict__ evals = a.ent_val;
   const int64_t k0 = a.tube_off[T], k1 = a.tube_off[T + 1];
-  const int2 te = texp[T];
-  const double sx = ldexp(1.0, -te.x), sy = ldexp(1.0, -te.y);
-  const double kc0 = a.KC0, kc1 = a.KC1, kc2 = a.KC2;
+  const int2 te0 = texp[T];
+  const int2 te = make_int2(tube_scale_exp(te0.x), tube_scale_exp(te0.y));
+  // the tube's pairs share one axis, so one coefficient
+  const int axis = k1 > k0 ? (int)((unsigned)a.pm[k0].w >> 30) : 0;
+  const double xsc = (axis == 0 ? a.KC0 : (axis == 1 ? a.KC1 : a.KC2)) * ldexp(1.0, -te.x);
+  const float ysc = ldexpf(1.f, -te.y);
   // this thread's 16 panel values (row t >> 1, inner columns 16 (t & 1)..)
   const int pr = t >> 1, pc = 16 * (t & 1);
   float *fxr = &sm.fx[pr][pc], *fyr = &sm.fy[pr][pc];
@@ -815,67 +882,50 @@ __global__ void __launch_bounds__(256) k_tube_mfma(AccumArgs a, const int4 *__re
 #pragma unroll
     for (int y = 0; y < 4; y++) acc[x][y] = f32x4v{0.f, 0.f, 0.f, 0.f};
   const int q = lane >> 4;
-  // Sixteen threads per pair (pair pl of each chunk, entries e = t & 15,
-  // + 16, ...).  Software pipeline: the metadata of chunk c + 2 and the
-  // first twelve entries per thread of chunk c + 1 are loaded while chunk c
-  // is split and multiplied.
-  const int pl = t >> 4, el = t & 15;
+  // A chunk's entries are one contiguous packed range [e0, e1); thread t
+  // takes e0 + t + 256 j.  Software pipeline: the first kPre of the next
+  // chunk's entries per thread are loaded while the current chunk is split
+  // and multiplied.
   constexpr int kPre = 12;
-  int4 m_cur = make_int4(0, 0, 0, 0), m_nxt = make_int4(0, 0, 0, 0);
-  double w_cur = 0.0, w_nxt = 0.0;
-  int sl[kPre];
-  double va[kPre];
-  {
-    const int64_t kk = k0 + pl;
-    if (kk < k1) {
-      m_cur = pm[kk];
-      const int ax = (int)((unsigned)m_cur.w >> 30);
-      w_cur = pw[kk] * (ax == 0 ? kc0 : (ax == 1 ? kc1 : kc2));
-    }
-    const int64_t kn = k0 + kChunkPairs + pl;
-    if (kn < k1) {
-      m_nxt = pm[kn];
-      const int ax = (int)((unsigned)m_nxt.w >> 30);
-      w_nxt = pw[kn] * (ax == 0 ? kc0 : (ax == 1 ? kc1 : kc2));
-    }
-    const int nl = pair_nl(m_cur), ne = nl + pair_nr(m_cur);
+  uint32_t pm_[kPre];
+  float pv_[kPre];
+  auto chunk_range = [&](int64_t kc, int64_t &e0, int64_t &e1) {
+    e0 = pk_pair[kc];
+    e1 = pk_pair[kc + kChunkPairs < k1 ? kc + kChunkPairs : k1];
+  };
+  int64_t e0 = 0, e1 = 0;
+  if (k1 > k0) chunk_range(k0, e0, e1);
+#pragma unroll
+  for (int j = 0; j < kPre; j++) {
+    const int64_t i = e0 + t + 256 * j;
+    const int64_t ic = i < e1 ? i : e0;
+    pm_[j] = e1 > e0 ? pk_meta[ic] : 0u;
+    pv_[j] = e1 > e0 ? pk_val[ic] : 0.f;
+  }
+  if (t < kChunkPairs) sw[0][t] = k0 + t < k1 ? (float)(pw[k0 + t] * xsc) : 0.f;
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kc = k0; kc < k1; kc += kChunkPairs) {
+    // the chunk's entries into the FP32 panels: X column c = 2 p + side
+    // takes W_p v, Y column c ^ 1 takes v (X = [W l, W r], Y = [r, l])
 #pragma unroll
     for (int j = 0; j < kPre; j++) {
-      const int e = el + 16 * j;
-      const int ec = e < ne ? e : 0;
-      const int64_t ei = ne > 0 ? (ec < nl ? (int64_t)m_cur.x + ec : (int64_t)m_cur.y + (ec - nl)) : 0;
-      sl[j] = eslot[ei];
-      va[j] = evals[ei];
+      if (e0 + t + 256 * j < e1) {
+        const int sl = (int)(pm_[j] & 0xffffu), c = (int)(pm_[j] >> 16);
+        if ((unsigned)(sl - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[sl - rx0][c], sw[buf][c >> 1] * pv_[j]);
+        if ((unsigned)(sl - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[sl - ry0][c ^ 1], pv_[j] * ysc);
+      }
     }
-  }
-  __syncthreads();
-  for (int64_t kc = k0; kc < k1; kc += kChunkPairs) {
-    // chunk kc's entries into the FP32 panels: the prefetched ones, then
-    // any past the twelfth per thread
-    {
-      const int nl = pair_nl(m_cur), ne = nl + pair_nr(m_cur);
-#pragma unroll
-      for (int j = 0; j < kPre; j++) {
-        const int e = el + 16 * j;
-        if (e < ne) {
-          const bool isl = e < nl;
-          const int cx = 2 * pl + (isl ? 0 : 1), cy = 2 * pl + (isl ? 1 : 0);
-          if ((unsigned)(sl[j] - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[sl[j] - rx0][cx], (float)(w_cur * va[j] * sx));
-          if ((unsigned)(sl[j] - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[sl[j] - ry0][cy], (float)(va[j] * sy));
-        }
-      }
-      for (int e = el + 16 * kPre; e < ne; e += 16) {
-        const bool isl = e < nl;
-        const int64_t ei = isl ? (int64_t)m_cur.x + e : (int64_t)m_cur.y + (e - nl);
-        const int s1 = eslot[ei];
-        const double v1 = evals[ei];
-        const int cx = 2 * pl + (isl ? 0 : 1), cy = 2 * pl + (isl ? 1 : 0);
-        if ((unsigned)(s1 - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[s1 - rx0][cx], (float)(w_cur * v1 * sx));
-        if ((unsigned)(s1 - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[s1 - ry0][cy], (float)(v1 * sy));
-      }
+    for (int64_t i = e0 + t + 256 * kPre; i < e1; i += 256) {
+      const uint32_t mt = pk_meta[i];
+      const float v = pk_val[i];
+      const int sl = (int)(mt & 0xffffu), c = (int)(mt >> 16);
+      if ((unsigned)(sl - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[sl - rx0][c], sw[buf][c >> 1] * v);
+      if ((unsigned)(sl - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[sl - ry0][c ^ 1], v * ysc);
     }
     __syncthreads();
-    // split into hi and lo (and clear the FP32 panels for the next chunk)
+    // split into hi and lo (and clear the FP32 panels for the next chunk);
+    // the next chunk's weights
 #pragma unroll
     for (int g = 0; g < 2; g++) {
       half8 xh, xl, yh, yl;
@@ -896,29 +946,19 @@ __global__ void __launch_bounds__(256) k_tube_mfma(AccumArgs a, const int4 *__re
       *(half8 *)&sm.hy[0][pr][o] = yh;
       *(half8 *)&sm.hy[1][pr][o] = yl;
     }
+    const int64_t kn = kc + kChunkPairs;
+    if (t < kChunkPairs) sw[buf ^ 1][t] = kn + t < k1 ? (float)(pw[kn + t] * xsc) : 0.f;
     __syncthreads();
-    // next chunk: its metadata becomes current, the one after is loaded,
-    // and its first entries are loaded during the products below
-    m_cur = m_nxt;
-    w_cur = w_nxt;
-    {
-      const int64_t kn = kc + 2 * kChunkPairs + pl;
-      m_nxt = make_int4(0, 0, 0, 0);
-      w_nxt = 0.0;
-      if (kn < k1) {
-        m_nxt = pm[kn];
-        const int ax = (int)((unsigned)m_nxt.w >> 30);
-        w_nxt = pw[kn] * (ax == 0 ? kc0 : (ax == 1 ? kc1 : kc2));
-      }
-      const int nl = pair_nl(m_cur), ne = nl + pair_nr(m_cur);
+    buf ^= 1;
+    // the next chunk's first entries, in flight during the products
+    if (kn < k1) chunk_range(kn, e0, e1);
+    else e0 = e1 = 0;
 #pragma unroll
-      for (int j = 0; j < kPre; j++) {
-        const int e = el + 16 * j;
-        const int ec = e < ne ? e : 0;
-        const int64_t ei = ne > 0 ? (ec < nl ? (int64_t)m_cur.x + ec : (int64_t)m_cur.y + (ec - nl)) : 0;
-        sl[j] = eslot[ei];
-        va[j] = evals[ei];
-      }
+    for (int j = 0; j < kPre; j++) {
+      const int64_t i = e0 + t + 256 * j;
+      const int64_t ic = i < e1 ? i : e0;
+      pm_[j] = e1 > e0 ? pk_meta[ic] : 0u;
+      pv_[j] = e1 > e0 ? pk_val[ic] : 0.f;
     }
     half8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
@@ -965,6 +1005,7 @@ void free_tubes(TubePlan &tp) {
   dfree(tp.pair_sorted); dfree(tp.pm); dfree(tp.pw); dfree(tp.tube_off); dfree(tp.u_off); dfree(tp.tube_u); dfree(tp.ent_slot);
   dfree(tp.row_off); dfree(tp.row_ts); dfree(tp.items); dfree(tp.blk_off); dfree(tp.blk);
   dfree(tp.mitems); dfree(tp.texp);
+  dfree(tp.pk_pair); dfree(tp.pk_meta); dfree(tp.pk_val); dfree(tp.pk_tube);
   tp = TubePlan();
 }
 
@@ -1121,33 +1162,58 @@ int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s) {
 #undef HIP_T
 }
 
-// Work items of the matrix-core contraction: the upper 128 x 128 regions of
-// every tube block.
-static int build_region_items(fpde_mesh *m, TubePlan &tp, hipStream_t s) {
-  const int64_t nT = tp.n_tubes;
+// Plan of the matrix-core contraction: work items over the upper 128 x 128
+// regions of every tube block, and the entries packed in sorted-pair order
+// with their tube slots and inner columns.
+static int build_mfma_plan(fpde_mesh *m, Plan &P, TubePlan &tp, hipStream_t s) {
+  const int64_t nT = tp.n_tubes, nP = 3 * P.G;
   if (nT == 0) return FPDE_OK;
-  int64_t *cnt = nullptr, *off = nullptr;
+  int64_t *cnt = nullptr, *off = nullptr, *pcnt = nullptr;
   void *tmp = nullptr;
-  size_t need = 0;
+  size_t need = 0, have = 0;
   int st = FPDE_OK;
   auto done = [&](int code) {
     dfree(cnt);
     dfree(off);
+    dfree(pcnt);
     if (tmp) (void)hipFree(tmp);
     return code;
+  };
+  auto scan = [&](const int64_t *in, int64_t *out, int64_t n) {
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, (int)n, s) != hipSuccess) return FPDE_EHIP;
+    if (need > have) {
+      if (tmp) (void)hipFree(tmp);
+      tmp = nullptr;
+      if (hipMalloc(&tmp, need) != hipSuccess) return FPDE_ENOMEM;
+      have = need;
+    }
+    return hipcub::DeviceScan::ExclusiveSum(tmp, need, in, out, (int)n, s) == hipSuccess ? FPDE_OK : FPDE_EHIP;
   };
   if ((st = dalloc(&cnt, nT + 1)) != FPDE_OK) return done(st);
   if ((st = dalloc(&off, nT + 1)) != FPDE_OK) return done(st);
   if (hipMemsetAsync(cnt, 0, sizeof(int64_t) * (nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
   k_region_count<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, cnt);
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, cnt, off, (int)(nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
-  if (hipMalloc(&tmp, need) != hipSuccess) return done(FPDE_ENOMEM);
-  if (hipcub::DeviceScan::ExclusiveSum(tmp, need, cnt, off, (int)(nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
+  if ((st = scan(cnt, off, nT + 1)) != FPDE_OK) return done(st);
   int64_t total = 0;
   if (hipMemcpyAsync(&total, off + nT, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return done(FPDE_EHIP);
   if (total >= (int64_t(1) << 31)) return done(FPDE_EUNSUPPORTED);
+  // packed entries: per pair |l| + |r|, scanned
+  if ((st = dalloc(&pcnt, nP + 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.pk_pair, nP + 1)) != FPDE_OK) return done(st);
+  if (hipMemsetAsync(pcnt, 0, sizeof(int64_t) * (nP + 1), s) != hipSuccess) return done(FPDE_EHIP);
+  k_pair_count<<<nblocks(nP), 256, 0, s>>>(tp.pm, nP, pcnt);
+  if ((st = scan(pcnt, tp.pk_pair, nP + 1)) != FPDE_OK) return done(st);
+  int64_t n_pk = 0;
+  if (hipMemcpyAsync(&n_pk, tp.pk_pair + nP, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done(FPDE_EHIP);
+  if ((st = dalloc(&tp.pk_meta, n_pk > 0 ? n_pk : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.pk_val, n_pk > 0 ? n_pk : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.pk_tube, nP > 0 ? nP : 1)) != FPDE_OK) return done(st);
+  k_pack_meta<<<nblocks(nP, 4), 256, 0, s>>>(tp.tube_off, nT, tp.pm, tp.pk_pair, nP, tp.ent_slot, tp.pk_meta,
+                                             tp.pk_tube);
   if ((st = dalloc(&tp.mitems, total > 0 ? total : 1)) != FPDE_OK) return done(st);
   k_region_items<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, off, tp.mitems);
   tp.n_mitems = total;
@@ -1176,17 +1242,25 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
   a.KC0 = p->K[0] * o.c_alpha;
   a.KC1 = p->K[1] * o.c_alpha;
   a.KC2 = p->K[2] * o.c_alpha;
-  if (p->precision == FPDE_MIXED) {
-    // split FP16 on the matrix cores: region items once per plan, exponents
-    // per assembly (they follow the values)
-    if (!tp.mitems) FPDE_TRY(build_region_items(m, tp, s));
+  // split FP16 on the matrix cores for the mixed-precision matrix (tube
+  // slots must fit the packed 16-bit field; larger tubes take the FP64 path)
+  if (p->precision == FPDE_MIXED && tp.max_u <= 0xffff) {
+    // plan once (items, packed slots and columns); values and exponents at
+    // every assembly (they follow the values)
+    if (!tp.mitems) FPDE_TRY(build_mfma_plan(m, P, tp, s));
     if (!tp.texp) FPDE_TRY(dalloc(&tp.texp, tp.n_tubes > 0 ? tp.n_tubes : 1));
+    const int64_t nP = 3 * P.G;
     const long ta = timer_begin(m, s, FPDE_STAGE_ACCUM);
-    if (tp.n_tubes > 0)
-      k_tube_scale<<<nblocks(tp.n_tubes, 4), 256, 0, s>>>(tp.tube_off, tp.pm, tp.pw, P.ent_val, tp.n_tubes, a.KC0,
-                                                          a.KC1, a.KC2, tp.texp);
-    if (tp.n_mitems > 0)
-      k_tube_mfma<<<(unsigned)(8 * ((tp.n_mitems + 7) / 8)), 256, 0, s>>>(a, tp.mitems, tp.n_mitems, tp.texp);
+    if (tp.n_tubes > 0) {
+      k_fill_int2<<<nblocks(tp.n_tubes), 256, 0, s>>>(tp.texp, tp.n_tubes, make_int2(INT_MIN, INT_MIN));
+      k_pack_vals<<<nblocks(nP, 4), 256, 0, s>>>(tp.pm, tp.pw, tp.pk_pair, tp.pk_tube, nP, P.ent_val, a.KC0, a.KC1,
+                                                 a.KC2, tp.pk_val, tp.texp);
+    }
+    if (tp.n_mitems > 0) {
+      TubeMfmaArgs ma{tp.tube_off, tp.pm, tp.pw, tp.pk_pair, tp.pk_meta, tp.pk_val, tp.blk_off, tp.blk,
+                      a.KC0, a.KC1, a.KC2};
+      k_tube_mfma<<<(unsigned)(8 * ((tp.n_mitems + 7) / 8)), 256, 0, s>>>(ma, tp.mitems, tp.n_mitems, tp.texp);
+    }
     timer_end(m, FPDE_STAGE_ACCUM, ta, s);
     return FPDE_OK;
   }
