@@ -367,9 +367,12 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
 template <class T>
 static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
                        fpde_mesh *m, hipStream_t s) {
-  // FP32: per-row exponents and split rows (2 x 256 halfs) of the
-  // split-FP16 trailing updates, count x n of each
-  constexpr int kGroup = 4;
+  // Panels per group: 8 for FP32 (the split-FP16 trailing update is bound
+  // by reading and writing the trailing matrix, so it runs once per 512
+  // columns), 4 for FP64 (bound by the FP64 matrix cores).  FP32: per-row
+  // exponents and split rows (2 x 512 halfs) of the trailing updates, count
+  // x n of each.
+  constexpr int kGroup = std::is_same<T, float>::value ? 8 : 4;
   int *escale = nullptr;
   _Float16 *xsplit = nullptr;
   const int64_t sx = n * 2 * kGroup * NB;
@@ -420,7 +423,7 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
       } else {
         // the group's update of the trailing matrix from k0 + 64 kGroup on
         // 128 x 128 tiles (FP32: split FP16 with per-row exponents over the
-        // group's columns)
+        // group's 512 columns)
         const int64_t base = k0 + kGroup * NB;
         const int64_t T2 = (n - base + T128 - 1) / T128;
         const int64_t work = T2 * (T2 + 1) / 2 * count;

@@ -1,6 +1,7 @@
 // Trailing update of the blocked Cholesky on 128 x 128 output tiles:
 //   C[I, J] -= X_I X_J^T  over the lower tiles I >= J of the trailing matrix,
-// X = the KD columns of the group of panels just factored (KD = 256).  One workgroup
+// X = the KD columns of the group of panels just factored (KD = 256 for
+// FP64 storage, 512 for FP32).  One workgroup
 // (256 threads, four wavefronts in a 2 x 2 arrangement, 64 x 64 each) per
 // output tile reads and writes its tile of C once and streams X_I and X_J
 // through LDS in chunks of the inner dimension, double-buffered: a 128-wide
@@ -12,7 +13,7 @@
 //  * FP32 storage (the factor of the mixed-precision solve): split FP16 on
 //    the FP16 matrix cores, 32-deep chunks.  Row r of X is scaled by a power
 //    of two 2^-e_r (e_r from the row's largest magnitude over the KD
-//    columns, computed by k_row_scale before the update) so that its largest
+//    columns, computed by k_row_split before the update) so that its largest
 //    entry lies in [2^13, 2^14), then split as x = hi + lo with hi = fp16(x)
 //    and lo = fp16(x - hi) (22 significant bits).  The product accumulates
 //    hi hi^T + hi lo^T + lo hi^T in FP32 with v_mfma_f32_16x16x32_f16 (the
@@ -155,12 +156,13 @@ struct SplitChunk {
   half8 v[4];  // [plane][group]: hi g0, hi g1, lo g0, lo g1
 };
 
+template <int KD>
 __device__ __forceinline__ void split_load(const _Float16 *__restrict__ xrow, int kk, SplitChunk &c) {
   const int g0 = 2 * (threadIdx.x & 1);
 #pragma unroll
   for (int pl = 0; pl < 2; pl++)
 #pragma unroll
-    for (int g = 0; g < 2; g++) c.v[2 * pl + g] = *(const half8 *)(xrow + pl * 256 + kk + 8 * (g0 + g));
+    for (int g = 0; g < 2; g++) c.v[2 * pl + g] = *(const half8 *)(xrow + pl * KD + kk + 8 * (g0 + g));
 }
 
 __device__ __forceinline__ void split_put(const SplitChunk &c, bool live, _Float16 (*hi)[KC16],
@@ -181,7 +183,7 @@ __device__ __forceinline__ void split_put(const SplitChunk &c, bool live, _Float
 template <int KD>
 __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi, const _Float16 *__restrict__ xj,
                                                 int prow, int qrow, Split16Smem &sm, f32x4v (&acc)[4][4]) {
-  static_assert(KD == 256, "split rows are laid out for 256 columns");
+  static_assert(KD % KC16 == 0, "split rows hold whole chunks");
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
   const int rr = t >> 1;
   const bool plive = rr < prow, qlive = rr < qrow;
@@ -192,8 +194,8 @@ __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi,
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = f32x4v{0.f, 0.f, 0.f, 0.f};
   SplitChunk pc, qc;
-  split_load(pr, 0, pc);
-  split_load(qr, 0, qc);
+  split_load<KD>(pr, 0, pc);
+  split_load<KD>(qr, 0, qc);
   split_put(pc, plive, sm.a[0][0], sm.a[0][1]);
   split_put(qc, qlive, sm.b[0][0], sm.b[0][1]);
   __syncthreads();
@@ -203,8 +205,8 @@ __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi,
     const int buf = (kk / KC16) & 1;
     const bool more = kk + KC16 < KD;
     if (more) {
-      split_load(pr, kk + KC16, pc);
-      split_load(qr, kk + KC16, qc);
+      split_load<KD>(pr, kk + KC16, pc);
+      split_load<KD>(qr, kk + KC16, qc);
     }
     half8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
