@@ -55,18 +55,21 @@ struct TubePlan {
   double *blk = nullptr;          // blk_n doubles of block scratch, allocated on first use
   // the matrix-core contraction (mixed precision): work items {tube, region
   // row, region column, |U_T|} over the upper 128 x 128 regions of every
-  // block, and per tube the largest binary exponents of its two operands
+  // block, and per tube the largest binary exponents of its two operands;
+  // the merged entries (one per node and side of a pair, in sorted-pair
+  // order): first merged entry of every pair, per merged entry its tube
+  // slot | (inner column << 16) (column 2 (pair mod 16) + side) and its
+  // value in FP32 (rebuilt at every assembly), per plan entry its merged
+  // index within its pair, and per sorted pair its tube
+  bool mfma_planned = false, mfma_ok = false;
   int4 *mitems = nullptr;
-  int64_t n_mitems = 0;
+  int64_t n_mitems = 0, n_mk = 0;
   int2 *texp = nullptr;
-  // the entries packed contiguously in sorted-pair order (l then r of each
-  // pair): first packed entry of every pair, per packed entry its tube
-  // slot | (inner column << 16) (column 2 (pair mod 16) + side), and the
-  // values in FP32 (repacked at every assembly)
-  int64_t *pk_pair = nullptr;
-  uint32_t *pk_meta = nullptr;
-  float *pk_val = nullptr;
-  int32_t *pk_tube = nullptr;  // per sorted pair: its tube
+  int64_t *mk_pair = nullptr;
+  uint32_t *mk_meta = nullptr;
+  float *mk_val = nullptr;
+  uint16_t *mg_idx = nullptr;
+  int32_t *pk_tube = nullptr;
 };
 
 // Symbolic phase of one rule: derivative-vector sizes and the row transpose.

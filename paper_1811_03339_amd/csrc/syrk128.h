@@ -85,16 +85,22 @@ __global__ void __launch_bounds__(256) k_row_split(const float *__restrict__ A, 
   }
 }
 
-// Split FP16 chunks: [buffer][hi, lo][row][k], 32 halfs per row.  The four
-// 16-byte groups of a row (k 8q..8q+7, q < 4) sit at group q ^ ((row >> 2) & 3),
-// so the 16 lanes of one 16-row read (rows r0..r0+15, one q) hit 16 distinct
-// 16-byte slots of a 256-byte bank window.
+// Split FP16 chunks: [buffer][hi, lo][row][k], 32 halfs per row (64 bytes).
+// The four 16-byte groups of a row (k 8q..8q+7, q < 4) sit at group q ^ h(row),
+// h = (r1 ^ r2) | (r1 ^ r3) << 1 over the bits r_i of the row.  A 16-byte
+// read or write is served a few lanes at a time; h makes every such set
+// of lanes hit distinct 16-byte slots, both for 8 lanes in a 128-byte
+// window and for 16 lanes in a 256-byte window: reads of 16 consecutive
+// rows (one q), and the staging writes (two lanes per row, groups
+// 2 (t & 1) + g).
 constexpr int KC16 = 32;
 struct Split16Smem {
   _Float16 a[2][2][T128][KC16];
   _Float16 b[2][2][T128][KC16];
 };
-__device__ __forceinline__ int swz(int row, int q) { return 8 * (q ^ ((row >> 2) & 3)); }
+__device__ __forceinline__ int swz(int row, int q) {
+  return 8 * (q ^ ((((row >> 1) ^ (row >> 2)) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1)));
+}
 
 // FP64 chunks: [buffer][row][k], padded to an odd number of doubles per row
 constexpr int KC64 = 16;
@@ -193,20 +199,26 @@ __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi,
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = f32x4v{0.f, 0.f, 0.f, 0.f};
-  SplitChunk pc, qc;
-  split_load<KD>(pr, 0, pc);
-  split_load<KD>(qr, 0, qc);
-  split_put(pc, plive, sm.a[0][0], sm.a[0][1]);
-  split_put(qc, qlive, sm.b[0][0], sm.b[0][1]);
+  // Two chunks in flight: while chunk c is multiplied from LDS, chunk c + 1
+  // (loaded during the previous chunk) is written to the other LDS buffer
+  // and chunk c + 2 is loaded into registers.  The register sets A and B
+  // alternate, so the loop body is unrolled by two.
+  SplitChunk pA, qA, pB, qB;
+  split_load<KD>(pr, 0, pA);
+  split_load<KD>(qr, 0, qA);
+  split_put(pA, plive, sm.a[0][0], sm.a[0][1]);
+  split_put(qA, qlive, sm.b[0][0], sm.b[0][1]);
+  if (KC16 < KD) {
+    split_load<KD>(pr, KC16, pA);
+    split_load<KD>(qr, KC16, qA);
+  }
   __syncthreads();
   const int q = lane >> 4;
-#pragma unroll 1
-  for (int kk = 0; kk < KD; kk += KC16) {
+  auto step = [&](int kk, SplitChunk &pn, SplitChunk &qn, SplitChunk &pf, SplitChunk &qf) {
     const int buf = (kk / KC16) & 1;
-    const bool more = kk + KC16 < KD;
-    if (more) {
-      split_load<KD>(pr, kk + KC16, pc);
-      split_load<KD>(qr, kk + KC16, qc);
+    if (kk + 2 * KC16 < KD) {
+      split_load<KD>(pr, kk + 2 * KC16, pf);
+      split_load<KD>(qr, kk + 2 * KC16, qf);
     }
     half8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
@@ -217,19 +229,30 @@ __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi,
       bh[x] = *(const half8 *)&sm.b[buf][0][br][swz(br, q)];
       bl[x] = *(const half8 *)&sm.b[buf][1][br][swz(br, q)];
     }
+    // hi hi, then hi lo, then lo hi over all 16 tiles: consecutive matrix-core
+    // operations write different accumulators
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-      for (int b = 0; b < 4; b++) {
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], acc[a][b], 0, 0, 0);
-      }
-    if (more) {
-      split_put(pc, plive, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
-      split_put(qc, qlive, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
+      for (int b = 0; b < 4; b++) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], acc[a][b], 0, 0, 0);
+    if (kk + KC16 < KD) {
+      split_put(pn, plive, sm.a[buf ^ 1][0], sm.a[buf ^ 1][1]);
+      split_put(qn, qlive, sm.b[buf ^ 1][0], sm.b[buf ^ 1][1]);
     }
     __syncthreads();
+  };
+#pragma unroll 1
+  for (int kk = 0; kk < KD; kk += 2 * KC16) {
+    step(kk, pA, qA, pB, qB);
+    if (kk + KC16 < KD) step(kk + KC16, pB, qB, pA, qA);
   }
 }
 

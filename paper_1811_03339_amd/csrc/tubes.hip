@@ -702,61 +702,103 @@ __global__ void __launch_bounds__(256) k_tube_gather_csr(GatherArgs a, const int
 // two columns per pair p: X_{:,2p} = W_p l_p, X_{:,2p+1} = W_p r_p,
 // Y_{:,2p} = r_p, Y_{:,2p+1} = l_p (W_p = w_g K_i c_alpha), so that
 // (X Y^T)_jk = sum_p W_p (l_j r_k + r_j l_k): the L W R^T contraction of the
-// element quadrature, symmetric.  One workgroup (four wavefronts, 64 x 64
-// each) computes a 128 x 128 region (I, J), I <= J, of B and writes it and
-// its mirror into the tube's block.  The pairs go through LDS sixteen at a
-// time (32 inner columns, one depth of v_mfma_f32_16x16x32_f16): their
-// entries are added into FP32 panels (a node may appear twice in one
-// half-ray), then split into FP16 hi + lo after scaling X and Y by the
-// tube's powers of two (largest magnitude in [2^13, 2^14)), and the region
-// accumulates hi hi + hi lo + lo hi in FP32 (22 significant bits per operand;
-// the dropped lo lo term is below 2^-22 of each product).
+// element quadrature, symmetric.  A node appears several times in one
+// half-ray (once per element the ray crosses around it); those entries are
+// summed first (in FP64, per assembly), so that a pair's side has one
+// merged entry per node and every inner column of X and Y receives each of
+// its rows at most once.  One workgroup (four wavefronts, 64 x 64 each)
+// computes a 128 x 128 region (I, J), I <= J, of B and writes it and its
+// mirror into the tube's block.  The pairs go through LDS sixteen at a
+// time (32 inner columns, one depth of v_mfma_f32_16x16x32_f16): the merged
+// entries, scaled by the tube's powers of two (largest magnitude of X and
+// of Y in [2^13, 2^14)), are split into FP16 hi + lo and stored straight
+// into the operand panels, and the region accumulates hi hi + hi lo + lo hi
+// in FP32 (22 significant bits per operand; the dropped lo lo term is
+// below 2^-22 of each product).
 constexpr int kRegion = 128;
 constexpr int kChunkPairs = 16;
+constexpr int kMergeSlots = 4096;  // largest tube (|U_T|) of the matrix-core path
+constexpr int kMergeMax = 512;     // most merged entries of one pair on that path
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int tswz(int row, int q) { return 8 * (q ^ ((row >> 2) & 3)); }
-
-constexpr int kPanelStride = 2 * kChunkPairs + 1;  // odd: the rows of one column fall in distinct banks
-struct TubeMfmaSmem {
-  float fx[kRegion][kPanelStride];  // FP32 panels, entries added
-  float fy[kRegion][kPanelStride];
-  _Float16 hx[2][kRegion][2 * kChunkPairs];  // [hi, lo][row][inner], 16-byte groups swizzled
-  _Float16 hy[2][kRegion][2 * kChunkPairs];
-};
-
-// packed entries of every sorted pair (plan time): one wavefront per pair
-__global__ void __launch_bounds__(256) k_pack_meta(const int64_t *__restrict__ tube_off, int64_t n_tubes,
-                                                   const int4 *__restrict__ pm, const int64_t *__restrict__ pk_pair,
-                                                   int64_t n_pairs, const int32_t *__restrict__ ent_slot,
-                                                   uint32_t *__restrict__ pk_meta, int32_t *__restrict__ pk_tube) {
-  const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= n_pairs) return;
-  // the pair's tube: the last T with tube_off[T] <= k
-  int64_t lo = 0, hi = n_tubes - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (tube_off[mid] <= k) lo = mid;
-    else hi = mid - 1;
-  }
-  const uint32_t col0 = 2u * (uint32_t)((k - tube_off[lo]) % kChunkPairs);
-  if (lane == 0) pk_tube[k] = (int32_t)lo;
-  const int4 m = pm[k];
-  const int nl = pair_nl(m), ne = nl + pair_nr(m);
-  const int64_t p0 = pk_pair[k];
-  for (int e = lane; e < ne; e += 64) {
-    const bool side = e >= nl;
-    const int64_t ei = side ? (int64_t)m.y + (e - nl) : (int64_t)m.x + e;
-    pk_meta[p0 + e] = (uint32_t)ent_slot[ei] | ((col0 + (side ? 1u : 0u)) << 16);
-  }
+// 16-byte group q of row `row` (64-byte rows): q ^ h(row) with
+// h = (r1 ^ r2) | (r1 ^ r3) << 1 over the row's bits, so the lanes of one
+// operand read (16 consecutive rows, one q) hit distinct 16-byte slots
+// whether the LDS serves them 8 at a time in a 128-byte window or 16 at a
+// time in a 256-byte window
+__device__ __forceinline__ int tswz(int row, int q) {
+  return 8 * (q ^ ((((row >> 1) ^ (row >> 2)) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1)));
 }
 
-__global__ void k_pair_count(const int4 *__restrict__ pm, int64_t n_pairs, int64_t *__restrict__ cnt) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n_pairs) cnt[k] = pair_nl(pm[k]) + pair_nr(pm[k]);
+struct TubeMfmaSmem {
+  _Float16 hx[2][2][kRegion][2 * kChunkPairs];  // [buffer][hi, lo][row][inner]
+  _Float16 hy[2][2][kRegion][2 * kChunkPairs];
+};
+
+// Merge structure of every sorted pair (plan time), one wavefront per pair:
+// the merged entries of a side are its distinct tube slots in order of first
+// occurrence (l's first, then r's).  COUNT: cnt[k] = the pair's merged
+// entries.  FILL: for every entry its merged index within the pair (midx),
+// and per merged entry slot | (inner column << 16), the column being
+// 2 (pair mod 16) + side; the pair's tube into pk_tube.  Slots must be
+// below kMergeSlots; COUNT also takes into *maxc (zero on entry) the
+// largest count above kMergeMax.
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_merge_pairs(const int64_t *__restrict__ tube_off, int64_t n_tubes,
+                                                    const int4 *__restrict__ pm, int64_t n_pairs,
+                                                    const int32_t *__restrict__ ent_slot, int64_t *__restrict__ cnt,
+                                                    const int64_t *__restrict__ mk_pair, uint16_t *__restrict__ midx,
+                                                    uint32_t *__restrict__ mk_meta, int32_t *__restrict__ pk_tube,
+                                                    int *__restrict__ maxc) {
+  __shared__ int tbl[kMergeSlots];
+  const int lane = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  if (k >= n_pairs) return;  // the whole block (one wavefront)
+  const int4 m = pm[k];
+  uint32_t col0 = 0;
+  if (FILL) {
+    int64_t lo = 0, hi = n_tubes - 1;  // the pair's tube: the last T with tube_off[T] <= k
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (tube_off[mid] <= k) lo = mid;
+      else hi = mid - 1;
+    }
+    col0 = 2u * (uint32_t)((k - tube_off[lo]) % kChunkPairs);
+    if (lane == 0) pk_tube[k] = (int32_t)lo;
+  }
+  int merged = 0;
+  for (int side = 0; side < 2; side++) {
+    const int64_t base = side ? (int64_t)m.y : (int64_t)m.x;
+    const int n = side ? pair_nr(m) : pair_nl(m);
+    for (int e = lane; e < n; e += 64) tbl[ent_slot[base + e]] = INT_MAX;
+    __syncthreads();
+    for (int e = lane; e < n; e += 64) atomicMin(&tbl[ent_slot[base + e]], e);
+    __syncthreads();
+    // first occurrences in order; each overwrites its slot's cell with
+    // -(merged index + 1) (no other entry of that slot can be a first)
+    for (int e0 = 0; e0 < n; e0 += 64) {
+      const int e = e0 + lane;
+      const int sl = e < n ? ent_slot[base + e] : 0;
+      const bool first = e < n && tbl[sl] == e;
+      const uint64_t bal = __ballot(first);
+      const int r = merged + __popcll(bal & ((1ull << lane) - 1ull));
+      if (first) {
+        tbl[sl] = -(r + 1);
+        if (FILL) mk_meta[mk_pair[k] + r] = (uint32_t)sl | ((col0 + (uint32_t)side) << 16);
+      }
+      merged += __popcll(bal);
+    }
+    __syncthreads();
+    if (FILL)
+      for (int e = lane; e < n; e += 64) midx[base + e] = (uint16_t)(-tbl[ent_slot[base + e]] - 1);
+    __syncthreads();
+  }
+  if (!FILL && lane == 0) {
+    cnt[k] = merged;
+    if (merged > kMergeMax) atomicMax(maxc, merged);  // only the pairs over the limit
+  }
 }
 
 __global__ void k_fill_int2(int2 *__restrict__ p, int64_t n, int2 v) {
@@ -764,42 +806,104 @@ __global__ void k_fill_int2(int2 *__restrict__ p, int64_t n, int2 v) {
   if (i < n) p[i] = v;
 }
 
-// The values in pack order, FP32 (every assembly), one wavefront per pair;
-// and per tube the largest binary exponents of X (W_p |v|) and of Y (|v|):
-// texp must hold {INT_MIN, INT_MIN} per tube on entry and receives
+// Orders a wavefront's LDS accesses before and after it (no other
+// wavefront shares the data).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The merged values (every assembly): each entry's value added in FP64 into
+// its merged entry (LDS), rounded to FP32 into mk_val; and per tube the
+// largest binary exponents of X (W_p |v|) and of Y (|v|) over the merged
+// values: texp must hold {INT_MIN, INT_MIN} per tube on entry and receives
 // atomic maxima (ilogb is monotone, so the maximum of the exponents is the
-// exponent of the maximum).
-__global__ void __launch_bounds__(256) k_pack_vals(const int4 *__restrict__ pm, const double *__restrict__ pw,
-                                                   const int64_t *__restrict__ pk_pair,
-                                                   const int32_t *__restrict__ pk_tube, int64_t n_pairs,
-                                                   const double *__restrict__ val, double KC0, double KC1, double KC2,
-                                                   float *__restrict__ pk_val, int2 *__restrict__ texp) {
-  const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= n_pairs) return;
-  const int4 m = pm[k];
-  const int nl = pair_nl(m), nr = pair_nr(m);
-  float *out = pk_val + pk_pair[k];
-  float vm = 0.f;
-  for (int e = lane; e < nl; e += 64) {
-    const float v = (float)val[(int64_t)m.x + e];
-    out[e] = v;
-    vm = fmaxf(vm, fabsf(v));
-  }
-  for (int e = lane; e < nr; e += 64) {
-    const float v = (float)val[(int64_t)m.y + e];
-    out[nl + e] = v;
-    vm = fmaxf(vm, fabsf(v));
-  }
+// exponent of the maximum).  Every wavefront walks pairs k = wave, wave +
+// waves, ... with the next pair's metadata loaded while the current one is
+// merged; its LDS row is its own, so no workgroup barrier is needed (a
+// wavefront's LDS operations complete in order).
+__global__ void __launch_bounds__(256) k_merge_vals(const int4 *__restrict__ pm, const double *__restrict__ pw,
+                                                    const int64_t *__restrict__ mk_pair,
+                                                    const int32_t *__restrict__ pk_tube,
+                                                    const uint16_t *__restrict__ midx, int64_t n_pairs,
+                                                    const double *__restrict__ val, double KC0, double KC1, double KC2,
+                                                    float *__restrict__ mk_val, int2 *__restrict__ texp) {
+  __shared__ double acc[4][kMergeMax];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  double *a = acc[w];
+  int64_t k = (int64_t)blockIdx.x * 4 + w;
+  int4 m{};
+  int64_t b0 = 0, b1 = 0;
+  double wk = 0.0;
+  int tube = 0;
+  auto meta = [&](int64_t kk, int4 &mm, int64_t &c0, int64_t &c1, double &ww, int &tt) {
+    if (kk < n_pairs) {
+      mm = pm[kk];
+      c0 = mk_pair[kk];
+      c1 = mk_pair[kk + 1];
+      ww = pw[kk];
+      tt = pk_tube[kk];
+    }
+  };
+  meta(k, m, b0, b1, wk, tube);
+  for (; k < n_pairs; k += waves) {
+    const int nm = (int)(b1 - b0);
+    for (int j = lane; j < nm; j += 64) a[j] = 0.0;
+    wave_lds_sync();
+    // entries e < nl of l, then of r, 256 at a time: all loads of a round
+    // issued before its additions; the next pair's metadata is requested
+    // after the first round, so waiting for that round leaves it in flight
+    const int nl = pair_nl(m), ne = nl + pair_nr(m);
+    int mi[4];
+    double v[4];
+    auto load_round = [&](int e0) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) vm = fmaxf(vm, __shfl_xor(vm, o, 64));
-  if (lane == 0 && vm > 0.f) {
-    const int axis = (int)((unsigned)m.w >> 30);
-    const double w = fabs(pw[k]) * fabs(axis == 0 ? KC0 : (axis == 1 ? KC1 : KC2));
-    const double mx = w * (double)vm;
-    int *te = (int *)&texp[pk_tube[k]];
-    if (mx > 0.0) atomicMax(te, ilogb(mx));
-    atomicMax(te + 1, ilogb((double)vm));
+      for (int j = 0; j < 4; j++) {
+        const int e = e0 + lane + 64 * j;
+        const int64_t ei = e < nl ? (int64_t)m.x + e : (int64_t)m.y + (e - nl);
+        mi[j] = e < ne ? (int)midx[ei] : -1;
+        v[j] = e < ne ? val[ei] : 0.0;
+      }
+    };
+    auto add_round = [&]() {
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (mi[j] >= 0) atomicAdd(&a[mi[j]], v[j]);
+    };
+    load_round(0);
+    int4 mn{};
+    int64_t n0 = 0, n1 = 0;
+    double wn = 0.0;
+    int tn = 0;
+    meta(k + waves, mn, n0, n1, wn, tn);
+    add_round();
+    for (int e0 = 256; e0 < ne; e0 += 256) {
+      load_round(e0);
+      add_round();
+    }
+    wave_lds_sync();
+    float vm = 0.f;
+    for (int j = lane; j < nm; j += 64) {
+      const float fv = (float)a[j];
+      mk_val[b0 + j] = fv;
+      vm = fmaxf(vm, fabsf(fv));
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) vm = fmaxf(vm, __shfl_xor(vm, o, 64));
+    if (lane == 0 && vm > 0.f) {
+      const int axis = (int)((unsigned)m.w >> 30);
+      const double mx = fabs(wk) * fabs(axis == 0 ? KC0 : (axis == 1 ? KC1 : KC2)) * (double)vm;
+      int *te = (int *)&texp[tube];
+      if (mx > 0.0) atomicMax(te, ilogb(mx));
+      atomicMax(te + 1, ilogb((double)vm));
+    }
+    m = mn;
+    b0 = n0;
+    b1 = n1;
+    wk = wn;
+    tube = tn;
   }
 }
 
@@ -811,55 +915,58 @@ __device__ __forceinline__ int tube_scale_exp(int e) {
   return e < -120 ? -120 : (e > 120 ? 120 : e);
 }
 
-__global__ void k_region_count(const int64_t *__restrict__ u_off, int64_t n_tubes, int64_t *__restrict__ cnt) {
-  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (T >= n_tubes) return;
-  const int64_t U = u_off[T + 1] - u_off[T];
-  const int64_t nr = (U + kRegion - 1) / kRegion;
-  cnt[T] = nr * (nr + 1) / 2;
-}
-
-__global__ void k_region_items(const int64_t *__restrict__ u_off, int64_t n_tubes, const int64_t *__restrict__ off,
-                               int4 *__restrict__ items) {
-  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (T >= n_tubes) return;
-  const int U = (int)(u_off[T + 1] - u_off[T]);
-  const int nr = (U + kRegion - 1) / kRegion;
-  int64_t w = off[T];
-  for (int I = 0; I < nr; I++)
-    for (int J = I; J < nr; J++) items[w++] = make_int4((int)T, I, J, U);
-}
-
-
 struct TubeMfmaArgs {
   const int64_t *tube_off;
   const int4 *pm;
   const double *pw;
-  const int64_t *pk_pair;
-  const uint32_t *pk_meta;
-  const float *pk_val;
+  const int64_t *mk_pair;
+  const uint32_t *mk_meta;
+  const float *mk_val;
   const int64_t *blk_off;
   double *blk;
   double KC0, KC1, KC2;
 };
 
-// Work item b of n_items; the grid is 8 ceil(n_items / 8) blocks dealt to
-// the eight XCDs (round-robin by block) in contiguous ranges of b, so the
-// regions of one tube, consecutive items, share an XCD's L2 for the
-// tube's packed entries.
+// One merged entry into the operand panels of buffer `b`: row slot - rx0
+// of X (column c, W_p v) and row slot - ry0 of Y (column c ^ 1, v), each
+// as hi and lo.
+__device__ __forceinline__ void tube_put(TubeMfmaSmem &sm, int b, uint32_t mt, float v, const float *wv, float ysc,
+                                         int rx0, int ry0) {
+  const int sl = (int)(mt & 0xffffu), c = (int)(mt >> 16);
+  const int rx = sl - rx0, ry = sl - ry0;
+  if ((unsigned)rx < (unsigned)kRegion) {
+    const float x = wv[c >> 1] * v;
+    const _Float16 h = (_Float16)x;
+    const int o = tswz(rx, c >> 3) + (c & 7);
+    sm.hx[b][0][rx][o] = h;
+    sm.hx[b][1][rx][o] = (_Float16)(x - (float)h);
+  }
+  if ((unsigned)ry < (unsigned)kRegion) {
+    const float y = v * ysc;
+    const _Float16 h = (_Float16)y;
+    const int cy = c ^ 1;
+    const int o = tswz(ry, cy >> 3) + (cy & 7);
+    sm.hy[b][0][ry][o] = h;
+    sm.hy[b][1][ry][o] = (_Float16)(y - (float)h);
+  }
+}
+
+// Work item b = blockIdx.x of n_items (the grid); items {-1, ..} pad the
+// per-XCD lists and exit.
 __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *__restrict__ items, int64_t n_items,
                                                    const int2 *__restrict__ texp) {
   __shared__ TubeMfmaSmem sm;
   __shared__ float sw[2][kChunkPairs];  // W_p 2^-ex of the chunk's pairs (double-buffered)
-  const int64_t bw = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int64_t bw = blockIdx.x;
   if (bw >= n_items) return;
   const int4 it = items[bw];
+  if (it.x < 0) return;
   const int64_t T = it.x;
   const int U = it.w, rx0 = kRegion * it.y, ry0 = kRegion * it.z;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  const int64_t *__restrict__ pk_pair = a.pk_pair;
-  const uint32_t *__restrict__ pk_meta = a.pk_meta;
-  const float *__restrict__ pk_val = a.pk_val;
+  const int64_t *__restrict__ mk_pair = a.mk_pair;
+  const uint32_t *__restrict__ mk_meta = a.mk_meta;
+  const float *__restrict__ mk_val = a.mk_val;
   const double *__restrict__ pw = a.pw;
   const int64_t k0 = a.tube_off[T], k1 = a.tube_off[T + 1];
   const int2 te0 = texp[T];
@@ -868,106 +975,84 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
   const int axis = k1 > k0 ? (int)((unsigned)a.pm[k0].w >> 30) : 0;
   const double xsc = (axis == 0 ? a.KC0 : (axis == 1 ? a.KC1 : a.KC2)) * ldexp(1.0, -te.x);
   const float ysc = ldexpf(1.f, -te.y);
-  // this thread's 16 panel values (row t >> 1, inner columns 16 (t & 1)..)
-  const int pr = t >> 1, pc = 16 * (t & 1);
-  float *fxr = &sm.fx[pr][pc], *fyr = &sm.fy[pr][pc];
+  // both panel buffers start at zero; a clear is 4 x 16 bytes per thread
+  // of the buffer's hx and of its hy (16 KB each), consecutive lanes on
+  // consecutive 16-byte slots
+  const half8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto clear = [&](int b) {
+    half8 *px = (half8 *)&sm.hx[b][0][0][0], *py = (half8 *)&sm.hy[b][0][0][0];
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
-    fxr[j] = 0.f;
-    fyr[j] = 0.f;
-  }
+    for (int j = 0; j < 4; j++) {
+      px[t + 256 * j] = z8;
+      py[t + 256 * j] = z8;
+    }
+  };
+  clear(0);
+  clear(1);
   f32x4v acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; x++)
 #pragma unroll
     for (int y = 0; y < 4; y++) acc[x][y] = f32x4v{0.f, 0.f, 0.f, 0.f};
   const int q = lane >> 4;
-  // A chunk's entries are one contiguous packed range [e0, e1); thread t
-  // takes e0 + t + 256 j.  Software pipeline: the first kPre of the next
-  // chunk's entries per thread are loaded while the current chunk is split
-  // and multiplied.
-  constexpr int kPre = 12;
-  uint32_t pm_[kPre];
-  float pv_[kPre];
-  auto chunk_range = [&](int64_t kc, int64_t &e0, int64_t &e1) {
-    e0 = pk_pair[kc];
-    e1 = pk_pair[kc + kChunkPairs < k1 ? kc + kChunkPairs : k1];
+  // A chunk's merged entries are one contiguous range [e0, e1); thread t
+  // takes e0 + t + 256 j.  Loads run ahead of their use: while chunk c is
+  // scattered and multiplied, the entries of chunk c + 1 and the bounds and
+  // pair weights of chunk c + 2 are in flight.
+  constexpr int kPre = 4;
+  uint32_t cm[kPre], nm[kPre];
+  float cv[kPre], nv[kPre];
+  auto bounds = [&](int64_t kc, int64_t &b0, int64_t &b1) {
+    if (kc < k1) {
+      b0 = mk_pair[kc];
+      b1 = mk_pair[kc + kChunkPairs < k1 ? kc + kChunkPairs : k1];
+    } else {
+      b0 = b1 = 0;
+    }
   };
-  int64_t e0 = 0, e1 = 0;
-  if (k1 > k0) chunk_range(k0, e0, e1);
+  auto entries = [&](int64_t b0, int64_t b1, uint32_t(&em)[kPre], float(&ev)[kPre]) {
 #pragma unroll
-  for (int j = 0; j < kPre; j++) {
-    const int64_t i = e0 + t + 256 * j;
-    const int64_t ic = i < e1 ? i : e0;
-    pm_[j] = e1 > e0 ? pk_meta[ic] : 0u;
-    pv_[j] = e1 > e0 ? pk_val[ic] : 0.f;
-  }
-  if (t < kChunkPairs) sw[0][t] = k0 + t < k1 ? (float)(pw[k0 + t] * xsc) : 0.f;
-  __syncthreads();
+    for (int j = 0; j < kPre; j++) {
+      const int64_t i = b0 + t + 256 * j;
+      const int64_t ic = i < b1 ? i : b0;
+      em[j] = b1 > b0 ? mk_meta[ic] : 0u;
+      ev[j] = b1 > b0 ? mk_val[ic] : 0.f;
+    }
+  };
+  auto weight = [&](int64_t kc) { return t < kChunkPairs && kc + t < k1 ? (float)(pw[kc + t] * xsc) : 0.f; };
+  int64_t c0, c1, n0, n1;  // bounds of the current and of the next chunk
+  bounds(k0, c0, c1);
+  bounds(k0 + kChunkPairs, n0, n1);
+  entries(c0, c1, cm, cv);
+  if (t < kChunkPairs) sw[0][t] = weight(k0);
+  float wnext = weight(k0 + kChunkPairs);
   int buf = 0;
   for (int64_t kc = k0; kc < k1; kc += kChunkPairs) {
-    // the chunk's entries into the FP32 panels: X column c = 2 p + side
-    // takes W_p v, Y column c ^ 1 takes v (X = [W l, W r], Y = [r, l])
-#pragma unroll
-    for (int j = 0; j < kPre; j++) {
-      if (e0 + t + 256 * j < e1) {
-        const int sl = (int)(pm_[j] & 0xffffu), c = (int)(pm_[j] >> 16);
-        if ((unsigned)(sl - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[sl - rx0][c], sw[buf][c >> 1] * pv_[j]);
-        if ((unsigned)(sl - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[sl - ry0][c ^ 1], pv_[j] * ysc);
-      }
-    }
-    for (int64_t i = e0 + t + 256 * kPre; i < e1; i += 256) {
-      const uint32_t mt = pk_meta[i];
-      const float v = pk_val[i];
-      const int sl = (int)(mt & 0xffffu), c = (int)(mt >> 16);
-      if ((unsigned)(sl - rx0) < (unsigned)kRegion) atomicAdd(&sm.fx[sl - rx0][c], sw[buf][c >> 1] * v);
-      if ((unsigned)(sl - ry0) < (unsigned)kRegion) atomicAdd(&sm.fy[sl - ry0][c ^ 1], v * ysc);
-    }
+    // issued now, used one iteration later: the next chunk's entries, the
+    // bounds and weights of the chunk after it
+    entries(n0, n1, nm, nv);
+    int64_t f0, f1;
+    bounds(kc + 2 * kChunkPairs, f0, f1);
+    const float wfar = weight(kc + 2 * kChunkPairs);
+    // buffer buf ^ 1 was read by the previous chunk's products, which every
+    // wavefront finished before this barrier; buffer buf was cleared during
+    // the previous chunk
     __syncthreads();
-    // split into hi and lo (and clear the FP32 panels for the next chunk);
-    // the next chunk's weights
+    clear(buf ^ 1);
 #pragma unroll
-    for (int g = 0; g < 2; g++) {
-      half8 xh, xl, yh, yl;
-#pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const float xv = fxr[8 * g + j], yv = fyr[8 * g + j];
-        const _Float16 xa = (_Float16)xv, ya = (_Float16)yv;
-        xh[j] = xa;
-        xl[j] = (_Float16)(xv - (float)xa);
-        yh[j] = ya;
-        yl[j] = (_Float16)(yv - (float)ya);
-        fxr[8 * g + j] = 0.f;
-        fyr[8 * g + j] = 0.f;
-      }
-      const int o = tswz(pr, (pc >> 3) + g);
-      *(half8 *)&sm.hx[0][pr][o] = xh;
-      *(half8 *)&sm.hx[1][pr][o] = xl;
-      *(half8 *)&sm.hy[0][pr][o] = yh;
-      *(half8 *)&sm.hy[1][pr][o] = yl;
-    }
-    const int64_t kn = kc + kChunkPairs;
-    if (t < kChunkPairs) sw[buf ^ 1][t] = kn + t < k1 ? (float)(pw[kn + t] * xsc) : 0.f;
+    for (int j = 0; j < kPre; j++)
+      if (c0 + t + 256 * j < c1) tube_put(sm, buf, cm[j], cv[j], sw[buf], ysc, rx0, ry0);
+    for (int64_t i = c0 + t + 256 * kPre; i < c1; i += 256) tube_put(sm, buf, mk_meta[i], mk_val[i], sw[buf], ysc, rx0, ry0);
+    if (t < kChunkPairs) sw[buf ^ 1][t] = wnext;
     __syncthreads();
-    buf ^= 1;
-    // the next chunk's first entries, in flight during the products
-    if (kn < k1) chunk_range(kn, e0, e1);
-    else e0 = e1 = 0;
-#pragma unroll
-    for (int j = 0; j < kPre; j++) {
-      const int64_t i = e0 + t + 256 * j;
-      const int64_t ic = i < e1 ? i : e0;
-      pm_[j] = e1 > e0 ? pk_meta[ic] : 0u;
-      pv_[j] = e1 > e0 ? pk_val[ic] : 0.f;
-    }
     half8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
     for (int x = 0; x < 4; x++) {
       const int ar = 64 * wr + 16 * x + (lane & 15), br = 64 * wc + 16 * x + (lane & 15);
-      ah[x] = *(const half8 *)&sm.hx[0][ar][tswz(ar, q)];
-      al[x] = *(const half8 *)&sm.hx[1][ar][tswz(ar, q)];
-      bh[x] = *(const half8 *)&sm.hy[0][br][tswz(br, q)];
-      bl[x] = *(const half8 *)&sm.hy[1][br][tswz(br, q)];
+      ah[x] = *(const half8 *)&sm.hx[buf][0][ar][tswz(ar, q)];
+      al[x] = *(const half8 *)&sm.hx[buf][1][ar][tswz(ar, q)];
+      bh[x] = *(const half8 *)&sm.hy[buf][0][br][tswz(br, q)];
+      bl[x] = *(const half8 *)&sm.hy[buf][1][br][tswz(br, q)];
     }
 #pragma unroll
     for (int x = 0; x < 4; x++)
@@ -977,8 +1062,17 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
         acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[x], bl[y], acc[x][y], 0, 0, 0);
         acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[x], bh[y], acc[x][y], 0, 0, 0);
       }
-    // the next chunk adds into the FP32 panels (cleared above) while these
-    // operands are in registers; its split waits at the barrier after the adds
+    buf ^= 1;
+#pragma unroll
+    for (int j = 0; j < kPre; j++) {
+      cm[j] = nm[j];
+      cv[j] = nv[j];
+    }
+    c0 = n0;
+    c1 = n1;
+    n0 = f0;
+    n1 = f1;
+    wnext = wfar;
   }
   // region (I, J) of the block and, off the diagonal of regions, its mirror
   double *out = a.blk + a.blk_off[T];
@@ -1005,7 +1099,7 @@ void free_tubes(TubePlan &tp) {
   dfree(tp.pair_sorted); dfree(tp.pm); dfree(tp.pw); dfree(tp.tube_off); dfree(tp.u_off); dfree(tp.tube_u); dfree(tp.ent_slot);
   dfree(tp.row_off); dfree(tp.row_ts); dfree(tp.items); dfree(tp.blk_off); dfree(tp.blk);
   dfree(tp.mitems); dfree(tp.texp);
-  dfree(tp.pk_pair); dfree(tp.pk_meta); dfree(tp.pk_val); dfree(tp.pk_tube);
+  dfree(tp.mk_pair); dfree(tp.mk_meta); dfree(tp.mk_val); dfree(tp.mg_idx); dfree(tp.pk_tube);
   tp = TubePlan();
 }
 
@@ -1163,19 +1257,22 @@ int build_tubes(fpde_mesh *m, Plan &P, double kappa, hipStream_t s) {
 }
 
 // Plan of the matrix-core contraction: work items over the upper 128 x 128
-// regions of every tube block, and the entries packed in sorted-pair order
-// with their tube slots and inner columns.
+// regions of every tube block, and the merge structure of every pair (merged
+// index per entry, slot and inner column per merged entry).  Tubes larger
+// than kMergeSlots or pairs with more than kMergeMax merged entries leave
+// mfma_ok false (the FP64 accumulation then serves the mixed path).
 static int build_mfma_plan(fpde_mesh *m, Plan &P, TubePlan &tp, hipStream_t s) {
   const int64_t nT = tp.n_tubes, nP = 3 * P.G;
-  if (nT == 0) return FPDE_OK;
-  int64_t *cnt = nullptr, *off = nullptr, *pcnt = nullptr;
+  tp.mfma_ok = false;
+  if (nT == 0 || tp.max_u > kMergeSlots) return FPDE_OK;
+  int64_t *pcnt = nullptr;
+  int *maxc = nullptr;
   void *tmp = nullptr;
   size_t need = 0, have = 0;
   int st = FPDE_OK;
   auto done = [&](int code) {
-    dfree(cnt);
-    dfree(off);
     dfree(pcnt);
+    dfree(maxc);
     if (tmp) (void)hipFree(tmp);
     return code;
   };
@@ -1189,35 +1286,72 @@ static int build_mfma_plan(fpde_mesh *m, Plan &P, TubePlan &tp, hipStream_t s) {
     }
     return hipcub::DeviceScan::ExclusiveSum(tmp, need, in, out, (int)n, s) == hipSuccess ? FPDE_OK : FPDE_EHIP;
   };
-  if ((st = dalloc(&cnt, nT + 1)) != FPDE_OK) return done(st);
-  if ((st = dalloc(&off, nT + 1)) != FPDE_OK) return done(st);
-  if (hipMemsetAsync(cnt, 0, sizeof(int64_t) * (nT + 1), s) != hipSuccess) return done(FPDE_EHIP);
-  k_region_count<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, cnt);
-  if ((st = scan(cnt, off, nT + 1)) != FPDE_OK) return done(st);
-  int64_t total = 0;
-  if (hipMemcpyAsync(&total, off + nT, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return done(FPDE_EHIP);
-  if (total >= (int64_t(1) << 31)) return done(FPDE_EUNSUPPORTED);
-  // packed entries: per pair |l| + |r|, scanned
+  auto to_host = [&](const void *src, void *dst, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+  };
+  // merged entries per pair, scanned
   if ((st = dalloc(&pcnt, nP + 1)) != FPDE_OK) return done(st);
-  if ((st = dalloc(&tp.pk_pair, nP + 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&maxc, 1)) != FPDE_OK) return done(st);
   if (hipMemsetAsync(pcnt, 0, sizeof(int64_t) * (nP + 1), s) != hipSuccess) return done(FPDE_EHIP);
-  k_pair_count<<<nblocks(nP), 256, 0, s>>>(tp.pm, nP, pcnt);
-  if ((st = scan(pcnt, tp.pk_pair, nP + 1)) != FPDE_OK) return done(st);
-  int64_t n_pk = 0;
-  if (hipMemcpyAsync(&n_pk, tp.pk_pair + nP, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return done(FPDE_EHIP);
-  if ((st = dalloc(&tp.pk_meta, n_pk > 0 ? n_pk : 1)) != FPDE_OK) return done(st);
-  if ((st = dalloc(&tp.pk_val, n_pk > 0 ? n_pk : 1)) != FPDE_OK) return done(st);
+  if (hipMemsetAsync(maxc, 0, sizeof(int), s) != hipSuccess) return done(FPDE_EHIP);
+  k_merge_pairs<false><<<(unsigned)nP, 64, 0, s>>>(tp.tube_off, nT, tp.pm, nP, tp.ent_slot, pcnt, nullptr, nullptr,
+                                                    nullptr, nullptr, maxc);
+  int mc = 0;
+  if (!to_host(maxc, &mc, sizeof(int))) return done(FPDE_EHIP);
+  if (mc > kMergeMax) return done(FPDE_OK);
+  if ((st = dalloc(&tp.mk_pair, nP + 1)) != FPDE_OK) return done(st);
+  if ((st = scan(pcnt, tp.mk_pair, nP + 1)) != FPDE_OK) return done(st);
+  int64_t n_mk = 0;
+  if (!to_host(tp.mk_pair + nP, &n_mk, sizeof(int64_t))) return done(FPDE_EHIP);
+  if ((st = dalloc(&tp.mk_meta, n_mk > 0 ? n_mk : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.mk_val, n_mk > 0 ? n_mk : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.mg_idx, P.n_ent > 0 ? P.n_ent : 1)) != FPDE_OK) return done(st);
   if ((st = dalloc(&tp.pk_tube, nP > 0 ? nP : 1)) != FPDE_OK) return done(st);
-  k_pack_meta<<<nblocks(nP, 4), 256, 0, s>>>(tp.tube_off, nT, tp.pm, tp.pk_pair, nP, tp.ent_slot, tp.pk_meta,
-                                             tp.pk_tube);
-  if ((st = dalloc(&tp.mitems, total > 0 ? total : 1)) != FPDE_OK) return done(st);
-  k_region_items<<<nblocks(nT), 256, 0, s>>>(tp.u_off, nT, off, tp.mitems);
-  tp.n_mitems = total;
+  k_merge_pairs<true><<<(unsigned)nP, 64, 0, s>>>(tp.tube_off, nT, tp.pm, nP, tp.ent_slot, nullptr, tp.mk_pair,
+                                                   tp.mg_idx, tp.mk_meta, tp.pk_tube, nullptr);
+  tp.n_mk = n_mk;
+  // Region work items, balanced over the eight XCDs (the hardware deals
+  // workgroup b to XCD b mod 8): whole tubes, largest cost first, each to
+  // the XCD with the least work so far (cost = regions x chunks of 16
+  // pairs); the items of XCD x at positions 8 j + x in tube order, padded
+  // with {-1} at the end.  A tube's regions stay on one XCD, whose L2 then
+  // serves its merged entries to all of them.
+  std::vector<int64_t> toff(nT + 1), uoff(nT + 1);
+  if (!to_host(tp.tube_off, toff.data(), sizeof(int64_t) * (nT + 1))) return done(FPDE_EHIP);
+  if (!to_host(tp.u_off, uoff.data(), sizeof(int64_t) * (nT + 1))) return done(FPDE_EHIP);
+  std::vector<int64_t> cost(nT), order(nT);
+  for (int64_t T = 0; T < nT; T++) {
+    const int64_t nr = (uoff[T + 1] - uoff[T] + kRegion - 1) / kRegion;
+    const int64_t chunks = (toff[T + 1] - toff[T] + kChunkPairs - 1) / kChunkPairs;
+    cost[T] = nr * (nr + 1) / 2 * (chunks + 1);
+    order[T] = T;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+  std::vector<int4> lists[8];
+  int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (const int64_t T : order) {
+    const int x = (int)(std::min_element(load, load + 8) - load);
+    load[x] += cost[T];
+    const int U = (int)(uoff[T + 1] - uoff[T]);
+    const int nr = (U + kRegion - 1) / kRegion;
+    for (int I = 0; I < nr; I++)
+      for (int J = I; J < nr; J++) lists[x].push_back(make_int4((int)T, I, J, U));
+  }
+  size_t per = 0;
+  for (int x = 0; x < 8; x++) per = std::max(per, lists[x].size());
+  if (8 * (int64_t)per >= (int64_t(1) << 31)) return done(FPDE_EUNSUPPORTED);
+  std::vector<int4> items(8 * per, make_int4(-1, 0, 0, 0));
+  for (int x = 0; x < 8; x++)
+    for (size_t j = 0; j < lists[x].size(); j++) items[8 * j + x] = lists[x][j];
+  if ((st = dalloc(&tp.mitems, items.size() > 0 ? items.size() : 1)) != FPDE_OK) return done(st);
+  if (!items.empty() && (hipMemcpyAsync(tp.mitems, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice,
+                                        s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+    return done(FPDE_EHIP);
+  tp.n_mitems = (int64_t)items.size();
   if (hipGetLastError() != hipSuccess) return done(FPDE_EHIP);
+  tp.mfma_ok = true;
   return done(FPDE_OK);
 }
 
@@ -1242,24 +1376,26 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
   a.KC0 = p->K[0] * o.c_alpha;
   a.KC1 = p->K[1] * o.c_alpha;
   a.KC2 = p->K[2] * o.c_alpha;
-  // split FP16 on the matrix cores for the mixed-precision matrix (tube
-  // slots must fit the packed 16-bit field; larger tubes take the FP64 path)
-  if (p->precision == FPDE_MIXED && tp.max_u <= 0xffff) {
-    // plan once (items, packed slots and columns); values and exponents at
-    // every assembly (they follow the values)
-    if (!tp.mitems) FPDE_TRY(build_mfma_plan(m, P, tp, s));
+  // split FP16 on the matrix cores for the mixed-precision matrix (planned
+  // once: work items and merge structure; merged values and exponents at
+  // every assembly, as they follow the values)
+  if (p->precision == FPDE_MIXED && !tp.mfma_planned) {
+    FPDE_TRY(build_mfma_plan(m, P, tp, s));
+    tp.mfma_planned = true;
+  }
+  if (p->precision == FPDE_MIXED && tp.mfma_ok) {
     if (!tp.texp) FPDE_TRY(dalloc(&tp.texp, tp.n_tubes > 0 ? tp.n_tubes : 1));
     const int64_t nP = 3 * P.G;
     const long ta = timer_begin(m, s, FPDE_STAGE_ACCUM);
-    if (tp.n_tubes > 0) {
-      k_fill_int2<<<nblocks(tp.n_tubes), 256, 0, s>>>(tp.texp, tp.n_tubes, make_int2(INT_MIN, INT_MIN));
-      k_pack_vals<<<nblocks(nP, 4), 256, 0, s>>>(tp.pm, tp.pw, tp.pk_pair, tp.pk_tube, nP, P.ent_val, a.KC0, a.KC1,
-                                                 a.KC2, tp.pk_val, tp.texp);
-    }
+    k_fill_int2<<<nblocks(tp.n_tubes), 256, 0, s>>>(tp.texp, tp.n_tubes, make_int2(INT_MIN, INT_MIN));
+    // eight workgroups of four wavefronts per CU, each wavefront looping
+    const unsigned mgrid = (unsigned)std::min<int64_t>(nblocks(nP, 4), 256 * 8);
+    k_merge_vals<<<mgrid, 256, 0, s>>>(tp.pm, tp.pw, tp.mk_pair, tp.pk_tube, tp.mg_idx, nP, P.ent_val, a.KC0, a.KC1,
+                                       a.KC2, tp.mk_val, tp.texp);
     if (tp.n_mitems > 0) {
-      TubeMfmaArgs ma{tp.tube_off, tp.pm, tp.pw, tp.pk_pair, tp.pk_meta, tp.pk_val, tp.blk_off, tp.blk,
+      TubeMfmaArgs ma{tp.tube_off, tp.pm, tp.pw, tp.mk_pair, tp.mk_meta, tp.mk_val, tp.blk_off, tp.blk,
                       a.KC0, a.KC1, a.KC2};
-      k_tube_mfma<<<(unsigned)(8 * ((tp.n_mitems + 7) / 8)), 256, 0, s>>>(ma, tp.mitems, tp.n_mitems, tp.texp);
+      k_tube_mfma<<<(unsigned)tp.n_mitems, 256, 0, s>>>(ma, tp.mitems, tp.n_mitems, tp.texp);
     }
     timer_end(m, FPDE_STAGE_ACCUM, ta, s);
     return FPDE_OK;

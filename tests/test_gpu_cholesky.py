@@ -5,6 +5,17 @@ single last panel, pairs that end exactly at N, a partial last block, and
 trailing matrices of one and of several 128 x 128 update tiles, full and
 partial (N = 1000, 1728).
 
+The FP32 factorization (split-FP16 trailing updates over groups of eight
+panels) is checked on assembled mixed-precision matrices: one group only
+(N = 512), one trailing update with a partial last group (1000), several
+groups with a ragged tail (1728) and several whole groups (4096).  Its
+factor must lie within 16 times LAPACK's own FP32 factorization's
+(spotrf) distance from the FP64 Cholesky factor of the same FP32 matrix:
+the panels apply each 64 x 64 diagonal block through its explicit inverse
+(X = B inv(L_bb)^T) rather than a triangular solve, which adds rounding
+that grows with the block's condition number.  The refined solution must
+equal the FP64 solve's within 1e-8.
+
 The matrices are seeded random SPD matrices (any SPD matrix of the mesh's
 size is a valid input); the factor must equal LAPACK's Cholesky factor and
 the solution LAPACK's solution within 1e-10 (max-norm relative), one system
@@ -71,3 +82,36 @@ def test_batch_matches_lapack(k):
     for z, (S, rhs) in enumerate(mats):
         assert rel(np.tril(A[z].cpu().numpy()), np.linalg.cholesky(S)) <= 1e-10, z
         assert rel(u[z].cpu().numpy(), np.linalg.solve(S, rhs)) <= 1e-10, z
+
+
+@pytest.mark.parametrize("k", [9, 11, 13, 17])
+def test_fp32_factor_as_accurate_as_spotrf(k):
+    if k in SIZES:
+        gm = mesh(k)
+    else:
+        cube = kuhn_cube(k)
+        gm = F.Mesh(cube.xyz, cube.tet)
+    n = gm.n_dof
+    print(f"[cholesky fp32] n={n}", flush=True)
+    pm = F.params(1.5, quad_points=4, precision=F.FPDE_MIXED, ir_tol=1e-10)
+    A = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    gm.assemble(pm, A, b)
+    K32 = A.cpu().numpy()
+    u = torch.empty_like(b)
+    gm.solve(pm, A, b, u)
+    torch.cuda.synchronize()
+    L64 = np.linalg.cholesky(K32.astype(np.float64))
+    L32 = np.linalg.cholesky(K32).astype(np.float64)  # LAPACK spotrf
+    bar = rel(L32, L64)
+    got = rel(np.tril(A.cpu().numpy()).astype(np.float64), L64)
+    print(f"[cholesky fp32] n={n} factor {got:.2e} vs spotrf {bar:.2e}", flush=True)
+    assert got <= 16.0 * bar + 1e-12
+    A64 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    b64 = torch.empty_like(b)
+    p64 = F.params(1.5, quad_points=4)
+    gm.assemble(p64, A64, b64)
+    u64 = torch.empty_like(b)
+    gm.solve(p64, A64, b64, u64, info=False)
+    torch.cuda.synchronize()
+    assert rel(u.cpu().numpy(), u64.cpu().numpy()) <= 1e-8
