@@ -61,10 +61,8 @@ FP16_PEAK = 2.5e15       # FLOP/s, dense matrix cores
 CSRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc")
 # HBM counter summaries (profiles/): unit -> (file, sources its kernels are built from)
 PMC = {
-    "factorization": (os.path.join(ROOT, "profiles", "potrf_sphere20k_pmc.txt"),
-                      [os.path.join(CSRC, "solve.hip"), os.path.join(CSRC, "dense.h")]),
-    "k_tube_accum": (os.path.join(ROOT, "profiles", "tube_accum_sphere20k_pmc.txt"),
-                     [os.path.join(CSRC, "tubes.hip")]),
+    "factorization_fp32_c5": (os.path.join(ROOT, "profiles", "potrf_fp32_ellipsoid400k_pmc.txt"),
+                              [os.path.join(CSRC, f) for f in ("solve.hip", "syrk128.h", "chol_diag.h", "dense.h")]),
 }
 
 
@@ -648,6 +646,11 @@ def main():
     value = rays * args.steps / (total_ms / 1e3)
     log(f"[bench] {ms_per_step:.1f} ms/step, {value:.3e} paths/s, timed-step stages {live}")
     mixed_info = last["info"]
+    # device memory held after the timed steps: mesh, plan (entries, tube
+    # plan, packed operands, blocks), the FP32 matrix and the solve's scratch
+    free_b, total_b = torch.cuda.mem_get_info()
+    mem_used_gb = (total_b - free_b) / 1e9
+    log(f"[bench] device memory in use {mem_used_gb:.1f} GB of {total_b / 1e9:.1f} GB")
     # per-stage breakdown from one further step with every stage timed
     gm.timing(True)
     step(args.steps)
@@ -661,26 +664,37 @@ def main():
 
     # roofline of the step's dominant kernel, by time per step: the FP32
     # factorization (one unit = one factorization of the n x n matrix:
-    # n^3 / 3 algorithmic flops) or the tube accumulation (one unit = one
-    # k_tube_accum launch: 4 |L| |R| flops per (g, i))
+    # n^3 / 3 algorithmic flops; its trailing updates run as split-FP16
+    # products, three FP16 matrix-core products per FP32 product, so its
+    # ceiling is the dense FP16 peak / 3) or the tube accumulation (one unit =
+    # the accumulation of one assembly: 4 |L| |R| flops per (g, i))
     cand = []
     if live["potrf"][1]:
         t_f = live["potrf"][0] / live["potrf"][1] / 1e3
         fl = n ** 3 / 3.0
+        peak = FP16_PEAK / 3.0
         cand.append((live["potrf"][0], {
-            "bound": "mfma", "achieved": fl / t_f / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": fl / t_f / FP32_PEAK, "traffic": read_traffic("factorization_fp32_c5") if "factorization_fp32_c5" in PMC else None,
-            "kernel": "FP32 Cholesky of the n x n matrix: k_potrf_diag<float>, then per pair of 64-column "
-                      "panels k_panel, k_syrk<float, 64> (block column), k_panel, k_syrk<float, 128>",
-            "avg_launch_ms": t_f * 1e3, "flops_per_unit": fl, "dtype": "f32 (v_mfma_f32_16x16x4f32 tiles)"}))
+            "bound": "mfma", "achieved": fl / t_f / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": fl / t_f / peak, "traffic": read_traffic("factorization_fp32_c5"),
+            "kernel": "FP32 Cholesky of the n x n matrix: per group of four 64-column panels k_panel and "
+                      "k_syrk<float> strip updates, then k_row_split<256> and k_syrk128<float, 256> on the "
+                      "trailing matrix (128 x 128 tiles)",
+            "peak_note": "dense FP16 matrix-core peak (2.5 PFLOP/s) / 3: each FP32 product of the trailing "
+                         "update is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16",
+            "avg_launch_ms": t_f * 1e3, "flops_per_unit": fl,
+            "dtype": "f32 factor; trailing update in split f16 (hi + lo) with f32 accumulation"}))
     if live["accum"][1]:
         t_a = live["accum"][0] / live["accum"][1] / 1e3
         fl = 4.0 * info["pairs"]
         cand.append((live["accum"][0], {
-            "bound": "alu", "achieved": fl / t_a / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": fl / t_a / FP64_PEAK, "traffic": None,
-            "kernel": "k_tube_accum (tube blocks, one launch per assembly)", "avg_launch_ms": t_a * 1e3,
-            "flops_per_unit": fl, "dtype": "f64 (vector FMA, LDS atomics)"}))
+            "bound": "mfma", "achieved": fl / t_a / 1e12, "peak": FP16_PEAK / 3.0 / 1e12, "unit": "TFLOP/s",
+            "frac": fl / t_a / (FP16_PEAK / 3.0), "traffic": None,
+            "kernel": "k_pack_vals + k_tube_scale + k_tube_mfma (tube blocks as split-FP16 products, one pass "
+                      "per assembly)",
+            "note": "achieved counts the method's products over entries (4 |L| |R| per pair); entries of one "
+                    "node in a half-ray are summed before the matrix-core product, so this rate can exceed "
+                    "the matrix-core work actually issued",
+            "avg_launch_ms": t_a * 1e3, "flops_per_unit": fl, "dtype": "f32 operands split into f16 hi + lo"}))
     roofline = max(cand, key=lambda c: c[0])[1] if cand else None
     other_roofline = min(cand, key=lambda c: c[0])[1] if len(cand) > 1 else None
 
@@ -801,6 +815,7 @@ def main():
         "mesh_generation_s": gen_s,
         "end_to_end_first_pass_s": (setup_ms + plan_ms) / 1e3 + ms_per_step / 1e3,
         "plan": info,
+        "device_mem_used_gb": mem_used_gb,
         "roofline": roofline,
         "roofline_other": other_roofline,
         "sections": sections,
