@@ -210,11 +210,32 @@ constexpr int kMaxBatch = 16;
 
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
 
+// The blocks of a vector that the workgroups of one triangular-solve launch
+// publish to each other are stored and loaded with relaxed device-scope
+// atomic accesses, which are coherent across the XCDs' L2 caches by
+// themselves: a publisher stores its block, waits until the stores have
+// completed (s_waitcnt), then sets the block's flag with a relaxed
+// device-scope store; a reader issues its loads of the block only after it
+// has seen the flag.  No release or acquire fence is needed, so no L2
+// write-back or invalidation (which would also evict the cached factor).
+__device__ __forceinline__ double ld_dev(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// After a workgroup's st_dev stores: every store has completed, then the
+// flag of block b carries `epoch` (thread 0).
+__device__ __forceinline__ void publish_block(int *flags, int b, int epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Whole-wave poll of the flags of blocks c, c + dir, ..., (count <= 64 of
 // them).  Returns how many leading ones carry `epoch` (>= 1), or 0 after
-// kSpinLimit polls without flag c.  The polls are relaxed device-scope loads
-// (no cache invalidation per poll); one acquire fence after the flags are
-// seen orders the reads of the published blocks after them.
+// kSpinLimit polls without flag c.  The polls are relaxed device-scope
+// loads; the published blocks are then read with ld_dev.
 __device__ __forceinline__ int poll_run(const int *flags, int c, int dir, int count, int epoch) {
   const int lane = threadIdx.x & 63;
   const int k = lane < count ? lane : count - 1;
@@ -222,7 +243,6 @@ __device__ __forceinline__ int poll_run(const int *flags, int c, int dir, int co
     const int v = __hip_atomic_load(&flags[c + dir * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long pub = __ballot(v == epoch);
     if (pub & 1ull) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const unsigned long long gap = ~pub;
       const int run = gap ? __ffsll((long long)gap) - 1 : 64;
       return run < count ? run : count;
@@ -332,7 +352,7 @@ __global__ void __launch_bounds__(256) k_trsv_rows(const T *__restrict__ A, int6
       ready = it + k;
     }
     const int64_t cc = (int64_t)c * NB + lane;
-    const double xv = cc < n ? x[cc] : 0.0;
+    const double xv = cc < n ? ld_dev(&x[cc]) : 0.0;
     const int64_t cn = col_of(it + 1 < nc ? c + step : c);
     T nxt[16];
 #pragma unroll
@@ -355,15 +375,10 @@ __global__ void __launch_bounds__(256) k_trsv_rows(const T *__restrict__ A, int6
   for (int q = 0; q < 16; q++) s = fma(li[q], rhs[16 * w + q], s);
   red[w][lane] = s;
   __syncthreads();
-  // the block of x is written by wavefront 0; after the barrier (which waits
-  // for those stores) lane 0 of the same wavefront publishes it with a
-  // device-scope release store, which makes them visible device-wide
-  if (tid < nb) x[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) set_flag(err, FPDE_EHIP);
-  }
+  // the block of x, written by wavefront 0 and published
+  if (tid < nb) st_dev(&x[r0 + tid], (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
+  publish_block(flags, b, epoch);
+  if (tid == 0 && !ok) set_flag(err, FPDE_EHIP);
 }
 
 // Host helpers (solve.hip).

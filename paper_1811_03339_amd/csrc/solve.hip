@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const T *__restrict__ L, int64
     const int64_t c0 = (int64_t)c * NB;
     const int nbc = rows_of(c);
     const int jl = 16 * w + (lane & 15);
-    const double ub = jl < nbc ? u[c0 + jl] : 0.0;
+    const double ub = jl < nbc ? ld_dev(&u[c0 + jl]) : 0.0;
     const int cn = (c - 1 > b) ? c - 1 : c;
     const int nbn = rows_of(cn);
     T nxt[16];
@@ -294,14 +294,10 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const T *__restrict__ L, int64
   __syncthreads();  // red is reused
   red[w][lane] = s;
   __syncthreads();
-  // written by wavefront 0, published by its lane 0 after the barrier (as
-  // in the forward solve)
-  if (tid < nb) u[r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(&flags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) set_flag(err, FPDE_EHIP);
-  }
+  // written by wavefront 0 and published (as in the forward solve)
+  if (tid < nb) st_dev(&u[r0 + tid], (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
+  publish_block(flags, b, epoch);
+  if (tid == 0 && !ok) set_flag(err, FPDE_EHIP);
 }
 
 __global__ void k_fill_i64(int64_t *p, int n, int64_t v) {
