@@ -210,6 +210,8 @@ int launch_load(fpde_mesh *m, const fpde_params *p, double *b, const double *f_g
 // y = K x from the stored derivative vectors (plan + values for p->alpha)
 int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
                   hipStream_t s) {
+  // the merged entries of the mixed-precision plan, when they hold these values
+  if (m->ndof > 0 && merged_apply_ready(*P)) return apply_merged(m, *P, p, x, y, s);
   if (!P->inc_wv) FPDE_TRY(dalloc(&P->inc_wv, P->n_ent > 0 ? P->n_ent : 1));
   ContractArgs c = contract_args(m, *P, p, 0);
   c.wv = P->inc_wv;

@@ -53,6 +53,8 @@ struct TubePlan {
   int4 *items = nullptr;          // pass-1 work: {tube, first block row, rows, |U_T|}
   int64_t *blk_off = nullptr;     // n_tubes + 1: offsets (doubles) of the |U_T|^2 blocks
   double *blk = nullptr;          // blk_n doubles of block scratch, allocated on first use
+  int32_t *cstart = nullptr;      // row pass: per tube, the first U_T position of every column chunk
+  int cs_chunk = 0;               // the chunk width cstart was built for
   // the matrix-core contraction (mixed precision): work items {tube, region
   // row, region column, |U_T|} over the upper 128 x 128 regions of every
   // block, and per tube the largest binary exponents of its two operands;
@@ -70,6 +72,18 @@ struct TubePlan {
   float *mk_val = nullptr;
   uint16_t *mg_idx = nullptr;
   int32_t *pk_tube = nullptr;
+  // the FP64 matrix-free product on the merged entries: per merged entry
+  // its node, FP64 value and position in node order (mpos); per node its
+  // merged entries (mrow_off; ascending merged index), per such incidence
+  // the partner's dot index | axis << 30 and w_g v; the per-pair-side
+  // dots.  The values are rebuilt at every assembly (version mk_version of
+  // the plan's values); mg_pair and mrow_q serve the plan only.
+  bool mapply_ok = false;
+  int32_t *mg_node = nullptr, *mg_pair = nullptr, *mrow_q = nullptr, *mpos = nullptr;
+  int64_t *mrow_off = nullptr;
+  uint32_t *mpart = nullptr;
+  double *mk_val64 = nullptr, *mwv = nullptr, *mdp = nullptr;
+  int64_t mk_version = -1;
 };
 
 // Symbolic phase of one rule: derivative-vector sizes and the row transpose.
@@ -222,6 +236,10 @@ int launch_form_tubes(fpde_mesh *m, Plan &P, const double cl[3], const double cr
 int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const int64_t *row_ptr,
                               const int32_t *col, double *val, hipStream_t s);
 // matrix-free y = K x and its scratch (assemble.hip)
+// y = K x on the merged entries of the mixed-precision tube plan, when they
+// hold the plan's current values (merged_apply_ready); FPDE_OK or an error.
+bool merged_apply_ready(const Plan &P);
+int apply_merged(fpde_mesh *m, Plan &P, const fpde_params *p, const double *x, double *y, hipStream_t s);
 int apply_matfree(fpde_mesh *m, Plan *P, const fpde_params *p, const double *x, double *y, double *dscratch,
                   hipStream_t s);
 int apply_scratch(fpde_mesh *m, Plan *P, double **d);

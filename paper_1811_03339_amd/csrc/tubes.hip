@@ -603,9 +603,29 @@ struct GatherArgs {
   const int32_t *tube_u;
   const int64_t *blk_off;
   const double *blk;
+  // per tube, the first position in U_T of every column chunk: cstart[T
+  // (nch + 1) + c] = #{nodes of U_T below c chunk} (U_T is increasing)
+  const int32_t *cstart;
   int64_t ndof, lda;
-  int chunk;
+  int chunk, nch;
 };
+
+// cstart for every (tube, chunk boundary): a binary search in U_T
+__global__ void k_chunk_starts(const int64_t *__restrict__ u_off, const int32_t *__restrict__ tube_u, int64_t n_tubes,
+                               int chunk, int nch, int32_t *__restrict__ cstart) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tubes * (nch + 1)) return;
+  const int64_t T = i / (nch + 1);
+  const int64_t lim = (int64_t)(i % (nch + 1)) * chunk;
+  int64_t lo = u_off[T], hi = u_off[T + 1];
+  const int64_t first = lo;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (tube_u[mid] < lim) lo = mid + 1;
+    else hi = mid;
+  }
+  cstart[i] = (int32_t)(lo - first);
+}
 
 __device__ __forceinline__ int64_t lane64(int64_t v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -613,36 +633,39 @@ __device__ __forceinline__ int64_t lane64(int64_t v, int l) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Row `row`, columns [c0, c0 + cw), of K into the LDS chunk racc: the sum
-// over the (tube, slot) places of the node of that slot's row of the tube
-// block, scattered through U_T (one wavefront per place).  The places'
-// metadata (tube, slot, node-set offset and size, block offset) is loaded
-// 64 places at a time, one per lane, and broadcast from there, so each
-// place costs one round of dependent loads instead of three.  Ends with
-// the chunk complete and visible to the whole workgroup.
-__device__ __forceinline__ void gather_row_chunk(const GatherArgs &a, int64_t row, int64_t c0, int64_t cw,
+// Row `row`, column chunk ci ([c0, c0 + cw)) of K into the LDS chunk racc:
+// the sum over the (tube, slot) places of the node of that slot's row of
+// the tube block, scattered through U_T (one wavefront per place).  Only
+// the part of the block row whose nodes fall in the chunk is read (U_T is
+// increasing, so it is the range [cstart(T, ci), cstart(T, ci + 1))).  The
+// places' metadata (tube, slot, node-set offset, block offset, range) is
+// loaded 64 places at a time, one per lane, and broadcast from there.
+// Ends with the chunk complete and visible to the whole workgroup.
+__device__ __forceinline__ void gather_row_chunk(const GatherArgs &a, int64_t row, int ci, int64_t c0, int64_t cw,
                                                  double *racc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p0 = a.row_off[row], np = a.row_off[row + 1] - p0;
   for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) racc[j] = 0.0;
   __syncthreads();
   for (int64_t pb = 0; pb < np; pb += 64) {
-    int64_t u0 = 0, U = 0, brow0 = 0;
+    int64_t u0 = 0, brow0 = 0;
+    int t0 = 0, t1 = 0;
     if (pb + lane < np) {
       const int2 ts = a.row_ts[p0 + pb + lane];
       u0 = a.u_off[ts.x];
-      U = a.u_off[ts.x + 1] - u0;
+      const int64_t U = a.u_off[ts.x + 1] - u0;
       brow0 = a.blk_off[ts.x] + (int64_t)ts.y * U;
+      const int32_t *cs = a.cstart + (int64_t)ts.x * (a.nch + 1) + ci;
+      t0 = cs[0];
+      t1 = cs[1];
     }
     const int cnt = (int)((np - pb) < 64 ? (np - pb) : 64);
     for (int k = wave; k < cnt; k += 4) {
-      const int64_t uk = lane64(u0, k), Uk = lane64(U, k);
+      const int64_t uk = lane64(u0, k);
       const double *brow = a.blk + lane64(brow0, k);
-      for (int64_t t = lane; t < Uk; t += 64) {
-        const int64_t d = (int64_t)a.tube_u[uk + t] - c0;
-        const double v = brow[t];
-        if ((uint64_t)d < (uint64_t)cw) atomicAdd(&racc[d], v);
-      }
+      const int tk1 = __builtin_amdgcn_readlane(t1, k);
+      for (int t = __builtin_amdgcn_readlane(t0, k) + lane; t < tk1; t += 64)
+        atomicAdd(&racc[(int64_t)a.tube_u[uk + t] - c0], brow[t]);
     }
   }
   __syncthreads();
@@ -663,9 +686,10 @@ __global__ void __launch_bounds__(256) k_tube_gather(GatherArgs a, TO *__restric
   for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
     const int64_t row = dealt_row(b, a.ndof);
     if (row >= a.ndof) continue;
-    for (int64_t c0 = 0; c0 < a.ndof; c0 += a.chunk) {
+    for (int ci = 0; ci < a.nch; ci++) {
+      const int64_t c0 = (int64_t)ci * a.chunk;
       const int64_t cw = (a.ndof - c0) < a.chunk ? (a.ndof - c0) : a.chunk;
-      gather_row_chunk(a, row, c0, cw, racc);
+      gather_row_chunk(a, row, ci, c0, cw, racc);
       TO *out = A + row * a.lda + c0;
       for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) out[j] = (TO)racc[j];
       __syncthreads();
@@ -684,9 +708,10 @@ __global__ void __launch_bounds__(256) k_tube_gather_csr(GatherArgs a, const int
     const int64_t row = dealt_row(b, a.ndof);
     if (row >= a.ndof) continue;
     const int64_t q0 = row_ptr[row], q1 = row_ptr[row + 1];
-    for (int64_t c0 = 0; c0 < a.ndof; c0 += a.chunk) {
+    for (int ci = 0; ci < a.nch; ci++) {
+      const int64_t c0 = (int64_t)ci * a.chunk;
       const int64_t cw = (a.ndof - c0) < a.chunk ? (a.ndof - c0) : a.chunk;
-      gather_row_chunk(a, row, c0, cw, racc);
+      gather_row_chunk(a, row, ci, c0, cw, racc);
       for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const int64_t d = (int64_t)col[q] - c0;
         if ((uint64_t)d < (uint64_t)cw) val[q] = racc[d];
@@ -742,7 +767,8 @@ struct TubeMfmaSmem {
 // occurrence (l's first, then r's).  COUNT: cnt[k] = the pair's merged
 // entries.  FILL: for every entry its merged index within the pair (midx),
 // and per merged entry slot | (inner column << 16), the column being
-// 2 (pair mod 16) + side; the pair's tube into pk_tube.  Slots must be
+// 2 (pair mod 16) + side, its node and its pair; the pair's tube into
+// pk_tube.  Slots must be
 // below kMergeSlots; COUNT also takes into *maxc (zero on entry) the
 // largest count above kMergeMax.
 template <bool FILL>
@@ -751,13 +777,16 @@ __global__ void __launch_bounds__(64) k_merge_pairs(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ ent_slot, int64_t *__restrict__ cnt,
                                                     const int64_t *__restrict__ mk_pair, uint16_t *__restrict__ midx,
                                                     uint32_t *__restrict__ mk_meta, int32_t *__restrict__ pk_tube,
-                                                    int *__restrict__ maxc) {
+                                                    int *__restrict__ maxc, const int64_t *__restrict__ u_off,
+                                                    const int32_t *__restrict__ tube_u, int32_t *__restrict__ mg_node,
+                                                    int32_t *__restrict__ mg_pair) {
   __shared__ int tbl[kMergeSlots];
   const int lane = threadIdx.x;
   const int64_t k = blockIdx.x;
   if (k >= n_pairs) return;  // the whole block (one wavefront)
   const int4 m = pm[k];
   uint32_t col0 = 0;
+  int64_t u0 = 0;
   if (FILL) {
     int64_t lo = 0, hi = n_tubes - 1;  // the pair's tube: the last T with tube_off[T] <= k
     while (lo < hi) {
@@ -767,6 +796,7 @@ __global__ void __launch_bounds__(64) k_merge_pairs(const int64_t *__restrict__ 
     }
     col0 = 2u * (uint32_t)((k - tube_off[lo]) % kChunkPairs);
     if (lane == 0) pk_tube[k] = (int32_t)lo;
+    u0 = u_off[lo];
   }
   int merged = 0;
   for (int side = 0; side < 2; side++) {
@@ -786,7 +816,12 @@ __global__ void __launch_bounds__(64) k_merge_pairs(const int64_t *__restrict__ 
       const int r = merged + __popcll(bal & ((1ull << lane) - 1ull));
       if (first) {
         tbl[sl] = -(r + 1);
-        if (FILL) mk_meta[mk_pair[k] + r] = (uint32_t)sl | ((col0 + (uint32_t)side) << 16);
+        if (FILL) {
+          const int64_t q = mk_pair[k] + r;
+          mk_meta[q] = (uint32_t)sl | ((col0 + (uint32_t)side) << 16);
+          mg_node[q] = tube_u[u0 + sl];
+          mg_pair[q] = (int32_t)k;
+        }
       }
       merged += __popcll(bal);
     }
@@ -814,7 +849,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // The merged values (every assembly): each entry's value added in FP64 into
-// its merged entry (LDS), rounded to FP32 into mk_val; and per tube the
+// its merged entry (LDS), kept in FP64 (mk_val64) and, times w_g, at its
+// node-order position mpos (mwv) for the matrix-free product (when mwv is
+// not null), and rounded to FP32 (mk_val, for the tube blocks); and per tube the
 // largest binary exponents of X (W_p |v|) and of Y (|v|) over the merged
 // values: texp must hold {INT_MIN, INT_MIN} per tube on entry and receives
 // atomic maxima (ilogb is monotone, so the maximum of the exponents is the
@@ -827,7 +864,9 @@ __global__ void __launch_bounds__(256) k_merge_vals(const int4 *__restrict__ pm,
                                                     const int32_t *__restrict__ pk_tube,
                                                     const uint16_t *__restrict__ midx, int64_t n_pairs,
                                                     const double *__restrict__ val, double KC0, double KC1, double KC2,
-                                                    float *__restrict__ mk_val, int2 *__restrict__ texp) {
+                                                    float *__restrict__ mk_val, double *__restrict__ mk_val64,
+                                                    const int32_t *__restrict__ mpos, double *__restrict__ mwv,
+                                                    int2 *__restrict__ texp) {
   __shared__ double acc[4][kMergeMax];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t waves = (int64_t)gridDim.x * 4;
@@ -885,8 +924,11 @@ __global__ void __launch_bounds__(256) k_merge_vals(const int4 *__restrict__ pm,
     wave_lds_sync();
     float vm = 0.f;
     for (int j = lane; j < nm; j += 64) {
-      const float fv = (float)a[j];
+      const double dv = a[j];
+      const float fv = (float)dv;
+      mk_val64[b0 + j] = dv;
       mk_val[b0 + j] = fv;
+      if (mwv) mwv[mpos[b0 + j]] = wk * dv;
       vm = fmaxf(vm, fabsf(fv));
     }
     wave_lds_sync();
@@ -913,6 +955,99 @@ __device__ __forceinline__ int tube_scale_exp(int e) {
   if (e == INT_MIN) return 0;
   e -= 13;
   return e < -120 ? -120 : (e > 120 ? 120 : e);
+}
+
+// ---- The FP64 matrix-free product on the merged entries ----
+// With d(k, s) = sum over the merged entries m of side s of pair k of
+// v_m x[node_m], (K x)_j = sum over the merged entries m at node j of
+// K_i c_alpha w_g v_m d(k_m, 1 - s_m): the quadrature of the element
+// products over the half-ray pairs, with the entries of one node in a
+// half-ray summed first (a third of the plan's entries at C5).  The
+// node -> merged entry lists keep increasing merged index (a stable sort),
+// so every sum has a fixed order.
+
+// off[j] = the first position of node j in the sorted node keys, j <= nd
+__global__ void k_node_bounds(const int32_t *__restrict__ keys, int64_t n, int64_t nd, int64_t *__restrict__ off) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > nd) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  off[j] = lo;
+}
+
+__global__ void k_iota32(int32_t *__restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+// per node-ordered merged incidence q: the index 2 k + (1 - s) of its
+// partner's dot | axis << 30
+__global__ void k_mpart(const int32_t *__restrict__ mrow_q, const int32_t *__restrict__ mg_pair,
+                        const uint32_t *__restrict__ mk_meta, const int4 *__restrict__ pm, int64_t n,
+                        uint32_t *__restrict__ mpart) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int32_t mq = mrow_q[q];
+  const int64_t k = mg_pair[mq];
+  const uint32_t side = (mk_meta[mq] >> 16) & 1u;
+  const uint32_t axis = (uint32_t)pm[k].w >> 30;
+  mpart[q] = (uint32_t)(2 * k + 1 - side) | (axis << 30);
+}
+
+// mpos[m] = the position of merged entry m in node order
+__global__ void k_inverse32(const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ inv) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) inv[perm[q]] = (int32_t)q;
+}
+
+// dp[2 k + s] = d(k, s); sixteen lanes per pair
+__global__ void __launch_bounds__(256) k_mpair_dot(const int64_t *__restrict__ mk_pair,
+                                                   const uint32_t *__restrict__ mk_meta,
+                                                   const double *__restrict__ mk_val64,
+                                                   const int32_t *__restrict__ mg_node, const double *__restrict__ x,
+                                                   int64_t n_pairs, double *__restrict__ dp) {
+  const int gl = threadIdx.x & 15;
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  if (k >= n_pairs) return;  // the whole group of 16 shares k
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t q = mk_pair[k] + gl; q < mk_pair[k + 1]; q += 16) {
+    const double v = mk_val64[q] * x[mg_node[q]];
+    if ((mk_meta[q] >> 16) & 1u) s1 += v;
+    else s0 += v;
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 16);
+    s1 += __shfl_xor(s1, o, 16);
+  }
+  if (gl == 0) {
+    dp[2 * k] = s0;
+    dp[2 * k + 1] = s1;
+  }
+}
+
+// y_j over node j's merged incidences; one wavefront per node
+__global__ void __launch_bounds__(256) k_mapply_rows(const int64_t *__restrict__ mrow_off,
+                                                     const uint32_t *__restrict__ mpart,
+                                                     const double *__restrict__ mwv, const double *__restrict__ dp,
+                                                     double KC0, double KC1, double KC2, int64_t ndof,
+                                                     double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= ndof) return;
+  double s = 0.0;
+  for (int64_t q = mrow_off[j] + lane; q < mrow_off[j + 1]; q += 64) {
+    const uint32_t pt = mpart[q];
+    const uint32_t ax = pt >> 30;
+    const double kc = ax == 0 ? KC0 : (ax == 1 ? KC1 : KC2);
+    s += mwv[q] * kc * dp[pt & 0x3fffffffu];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) y[j] = s;
 }
 
 struct TubeMfmaArgs {
@@ -997,11 +1132,11 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
   const int q = lane >> 4;
   // A chunk's merged entries are one contiguous range [e0, e1); thread t
   // takes e0 + t + 256 j.  Loads run ahead of their use: while chunk c is
-  // scattered and multiplied, the entries of chunk c + 1 and the bounds and
-  // pair weights of chunk c + 2 are in flight.
+  // scattered and multiplied, the entries of chunks c + 1 and c + 2, the
+  // bounds of chunk c + 3 and the pair weights of chunk c + 2 are in flight.
   constexpr int kPre = 4;
-  uint32_t cm[kPre], nm[kPre];
-  float cv[kPre], nv[kPre];
+  uint32_t cm[kPre], nm[kPre], fm[kPre];
+  float cv[kPre], nv[kPre], fv[kPre];
   auto bounds = [&](int64_t kc, int64_t &b0, int64_t &b1) {
     if (kc < k1) {
       b0 = mk_pair[kc];
@@ -1020,19 +1155,22 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
     }
   };
   auto weight = [&](int64_t kc) { return t < kChunkPairs && kc + t < k1 ? (float)(pw[kc + t] * xsc) : 0.f; };
-  int64_t c0, c1, n0, n1;  // bounds of the current and of the next chunk
+  // bounds of chunks c, c + 1, c + 2 (c = the current chunk)
+  int64_t c0, c1, n0, n1, f0, f1;
   bounds(k0, c0, c1);
   bounds(k0 + kChunkPairs, n0, n1);
+  bounds(k0 + 2 * kChunkPairs, f0, f1);
   entries(c0, c1, cm, cv);
+  entries(n0, n1, nm, nv);
   if (t < kChunkPairs) sw[0][t] = weight(k0);
   float wnext = weight(k0 + kChunkPairs);
   int buf = 0;
   for (int64_t kc = k0; kc < k1; kc += kChunkPairs) {
-    // issued now, used one iteration later: the next chunk's entries, the
-    // bounds and weights of the chunk after it
-    entries(n0, n1, nm, nv);
-    int64_t f0, f1;
-    bounds(kc + 2 * kChunkPairs, f0, f1);
+    // issued now, used two iterations later: the entries of chunk c + 2;
+    // one iteration later: the bounds of chunk c + 3, the weights of c + 2
+    entries(f0, f1, fm, fv);
+    int64_t g0, g1;
+    bounds(kc + 3 * kChunkPairs, g0, g1);
     const float wfar = weight(kc + 2 * kChunkPairs);
     // buffer buf ^ 1 was read by the previous chunk's products, which every
     // wavefront finished before this barrier; buffer buf was cleared during
@@ -1067,11 +1205,15 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
     for (int j = 0; j < kPre; j++) {
       cm[j] = nm[j];
       cv[j] = nv[j];
+      nm[j] = fm[j];
+      nv[j] = fv[j];
     }
     c0 = n0;
     c1 = n1;
     n0 = f0;
     n1 = f1;
+    f0 = g0;
+    f1 = g1;
     wnext = wfar;
   }
   // region (I, J) of the block and, off the diagonal of regions, its mirror
@@ -1100,6 +1242,9 @@ void free_tubes(TubePlan &tp) {
   dfree(tp.row_off); dfree(tp.row_ts); dfree(tp.items); dfree(tp.blk_off); dfree(tp.blk);
   dfree(tp.mitems); dfree(tp.texp);
   dfree(tp.mk_pair); dfree(tp.mk_meta); dfree(tp.mk_val); dfree(tp.mg_idx); dfree(tp.pk_tube);
+  dfree(tp.cstart);
+  dfree(tp.mg_node); dfree(tp.mg_pair); dfree(tp.mrow_q); dfree(tp.mrow_off); dfree(tp.mpart); dfree(tp.mpos);
+  dfree(tp.mk_val64); dfree(tp.mwv); dfree(tp.mdp);
   tp = TubePlan();
 }
 
@@ -1296,7 +1441,7 @@ static int build_mfma_plan(fpde_mesh *m, Plan &P, TubePlan &tp, hipStream_t s) {
   if (hipMemsetAsync(pcnt, 0, sizeof(int64_t) * (nP + 1), s) != hipSuccess) return done(FPDE_EHIP);
   if (hipMemsetAsync(maxc, 0, sizeof(int), s) != hipSuccess) return done(FPDE_EHIP);
   k_merge_pairs<false><<<(unsigned)nP, 64, 0, s>>>(tp.tube_off, nT, tp.pm, nP, tp.ent_slot, pcnt, nullptr, nullptr,
-                                                    nullptr, nullptr, maxc);
+                                                    nullptr, nullptr, maxc, nullptr, nullptr, nullptr, nullptr);
   int mc = 0;
   if (!to_host(maxc, &mc, sizeof(int))) return done(FPDE_EHIP);
   if (mc > kMergeMax) return done(FPDE_OK);
@@ -1308,9 +1453,57 @@ static int build_mfma_plan(fpde_mesh *m, Plan &P, TubePlan &tp, hipStream_t s) {
   if ((st = dalloc(&tp.mk_val, n_mk > 0 ? n_mk : 1)) != FPDE_OK) return done(st);
   if ((st = dalloc(&tp.mg_idx, P.n_ent > 0 ? P.n_ent : 1)) != FPDE_OK) return done(st);
   if ((st = dalloc(&tp.pk_tube, nP > 0 ? nP : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.mg_node, n_mk > 0 ? n_mk : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.mg_pair, n_mk > 0 ? n_mk : 1)) != FPDE_OK) return done(st);
+  if ((st = dalloc(&tp.mk_val64, n_mk > 0 ? n_mk : 1)) != FPDE_OK) return done(st);
   k_merge_pairs<true><<<(unsigned)nP, 64, 0, s>>>(tp.tube_off, nT, tp.pm, nP, tp.ent_slot, nullptr, tp.mk_pair,
-                                                   tp.mg_idx, tp.mk_meta, tp.pk_tube, nullptr);
+                                                   tp.mg_idx, tp.mk_meta, tp.pk_tube, nullptr, tp.u_off, tp.tube_u,
+                                                   tp.mg_node, tp.mg_pair);
   tp.n_mk = n_mk;
+  // node -> merged entries (stable by merged index) for the matrix-free
+  // product; its partner indices need 2 nP < 2^30
+  if (n_mk > 0 && n_mk < (int64_t(1) << 31) && 2 * nP + 1 < (int64_t(1) << 30)) {
+    const int64_t nd = m->ndof;
+    int32_t *keys = nullptr, *iota = nullptr;
+    auto fail_m = [&](int code) {
+      dfree(keys);
+      dfree(iota);
+      return done(code);
+    };
+    if ((st = dalloc(&keys, n_mk)) != FPDE_OK) return fail_m(st);
+    if ((st = dalloc(&iota, n_mk)) != FPDE_OK) return fail_m(st);
+    if ((st = dalloc(&tp.mrow_q, n_mk)) != FPDE_OK) return fail_m(st);
+    k_iota32<<<nblocks(n_mk), 256, 0, s>>>(iota, n_mk);
+    int bits = 1;
+    while ((int64_t(1) << bits) < nd) bits++;
+    size_t sneed = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, sneed, tp.mg_node, keys, iota, tp.mrow_q, (int)n_mk, 0, bits, s) !=
+        hipSuccess)
+      return fail_m(FPDE_EHIP);
+    if (sneed > have) {
+      if (tmp) (void)hipFree(tmp);
+      tmp = nullptr;
+      if (hipMalloc(&tmp, sneed) != hipSuccess) return fail_m(FPDE_ENOMEM);
+      have = sneed;
+    }
+    if (hipcub::DeviceRadixSort::SortPairs(tmp, sneed, tp.mg_node, keys, iota, tp.mrow_q, (int)n_mk, 0, bits, s) !=
+        hipSuccess)
+      return fail_m(FPDE_EHIP);
+    if ((st = dalloc(&tp.mrow_off, nd + 1)) != FPDE_OK) return fail_m(st);
+    k_node_bounds<<<nblocks(nd + 1), 256, 0, s>>>(keys, n_mk, nd, tp.mrow_off);
+    if ((st = dalloc(&tp.mpart, n_mk)) != FPDE_OK) return fail_m(st);
+    k_mpart<<<nblocks(n_mk), 256, 0, s>>>(tp.mrow_q, tp.mg_pair, tp.mk_meta, tp.pm, n_mk, tp.mpart);
+    if ((st = dalloc(&tp.mpos, n_mk)) != FPDE_OK) return fail_m(st);
+    k_inverse32<<<nblocks(n_mk), 256, 0, s>>>(tp.mrow_q, n_mk, tp.mpos);
+    if ((st = dalloc(&tp.mwv, n_mk)) != FPDE_OK) return fail_m(st);
+    if ((st = dalloc(&tp.mdp, 2 * nP)) != FPDE_OK) return fail_m(st);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail_m(FPDE_EHIP);
+    dfree(keys);
+    dfree(iota);
+    dfree(tp.mrow_q);
+    dfree(tp.mg_pair);
+    tp.mapply_ok = true;
+  }
   // Region work items, balanced over the eight XCDs (the hardware deals
   // workgroup b to XCD b mod 8): whole tubes, largest cost first, each to
   // the XCD with the least work so far (cost = regions x chunks of 16
@@ -1391,7 +1584,9 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
     // eight workgroups of four wavefronts per CU, each wavefront looping
     const unsigned mgrid = (unsigned)std::min<int64_t>(nblocks(nP, 4), 256 * 8);
     k_merge_vals<<<mgrid, 256, 0, s>>>(tp.pm, tp.pw, tp.mk_pair, tp.pk_tube, tp.mg_idx, nP, P.ent_val, a.KC0, a.KC1,
-                                       a.KC2, tp.mk_val, tp.texp);
+                                       a.KC2, tp.mk_val, tp.mk_val64, tp.mapply_ok ? tp.mpos : nullptr,
+                                       tp.mapply_ok ? tp.mwv : nullptr, tp.texp);
+    tp.mk_version = P.values_version;
     if (tp.n_mitems > 0) {
       TubeMfmaArgs ma{tp.tube_off, tp.pm, tp.pw, tp.mk_pair, tp.mk_meta, tp.mk_val, tp.blk_off, tp.blk,
                       a.KC0, a.KC1, a.KC2};
@@ -1407,19 +1602,34 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
   return FPDE_OK;
 }
 
-static GatherArgs gather_args(fpde_mesh *m, Plan &P, int64_t lda) {
+// Arguments of the row pass; the chunk starts of every tube are computed
+// on first use (and again if the chunk width changes).
+static int gather_args(fpde_mesh *m, Plan &P, int64_t lda, hipStream_t s, GatherArgs &gch) {
   TubePlan &tp = P.tubes;
-  GatherArgs gch{};
+  const int chunk = (int)(m->ndof < 8192 ? m->ndof : 8192);
+  const int nch = (int)((m->ndof + chunk - 1) / chunk);
+  if (!tp.cstart || tp.cs_chunk != chunk) {
+    dfree(tp.cstart);
+    tp.cs_chunk = 0;
+    const int64_t ncs = tp.n_tubes * (nch + 1);
+    FPDE_TRY(dalloc(&tp.cstart, ncs > 0 ? ncs : 1));
+    if (ncs > 0) k_chunk_starts<<<nblocks(ncs), 256, 0, s>>>(tp.u_off, tp.tube_u, tp.n_tubes, chunk, nch, tp.cstart);
+    FPDE_HIP(hipGetLastError());
+    tp.cs_chunk = chunk;
+  }
+  gch = GatherArgs{};
   gch.row_off = tp.row_off;
   gch.row_ts = tp.row_ts;
   gch.u_off = tp.u_off;
   gch.tube_u = tp.tube_u;
   gch.blk_off = tp.blk_off;
   gch.blk = tp.blk;
+  gch.cstart = tp.cstart;
   gch.ndof = m->ndof;
   gch.lda = lda;
-  gch.chunk = (int)(m->ndof < 8192 ? m->ndof : 8192);
-  return gch;
+  gch.chunk = chunk;
+  gch.nch = nch;
+  return FPDE_OK;
 }
 
 static unsigned gather_grid(int64_t ndof) {
@@ -1427,11 +1637,30 @@ static unsigned gather_grid(int64_t ndof) {
   return (unsigned)(slots < 65536 ? slots : 65536);
 }
 
+bool merged_apply_ready(const Plan &P) {
+  const TubePlan &tp = P.tubes;
+  return tp.mfma_ok && tp.mapply_ok && tp.mk_version == P.values_version;
+}
+
+int apply_merged(fpde_mesh *m, Plan &P, const fpde_params *p, const double *x, double *y, hipStream_t s) {
+  TubePlan &tp = P.tubes;
+  const int64_t nP = 3 * P.G;
+  Order o = order_scalars(p->alpha);
+  const long t = timer_begin(m, s, FPDE_STAGE_APPLY);
+  k_mpair_dot<<<nblocks(16 * nP), 256, 0, s>>>(tp.mk_pair, tp.mk_meta, tp.mk_val64, tp.mg_node, x, nP, tp.mdp);
+  k_mapply_rows<<<nblocks(m->ndof, 4), 256, 0, s>>>(tp.mrow_off, tp.mpart, tp.mwv, tp.mdp, p->K[0] * o.c_alpha,
+                                                    p->K[1] * o.c_alpha, p->K[2] * o.c_alpha, m->ndof, y);
+  timer_end(m, FPDE_STAGE_APPLY, t, s);
+  FPDE_HIP(hipGetLastError());
+  return FPDE_OK;
+}
+
 int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, int64_t lda, hipStream_t s) {
   if (m->ndof == 0) return FPDE_OK;
   const long t = timer_begin(m, s, FPDE_STAGE_CONTRACT);
   FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
-  GatherArgs gch = gather_args(m, P, lda);
+  GatherArgs gch;
+  FPDE_TRY(gather_args(m, P, lda, s, gch));
   const unsigned grid = gather_grid(m->ndof);
   if (p->precision == FPDE_MIXED)
     k_tube_gather<float><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (float *)A);
@@ -1465,7 +1694,8 @@ int launch_form_tubes(fpde_mesh *m, Plan &P, const double cl[3], const double cr
     a.cr[i] = cr[i];
   }
   if (tp.n_items > 0) k_tube_form<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
-  GatherArgs gch = gather_args(m, P, lda);
+  GatherArgs gch;
+  FPDE_TRY(gather_args(m, P, lda, s, gch));
   k_tube_gather<double><<<gather_grid(m->ndof), 256, sizeof(double) * gch.chunk, s>>>(gch, A);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
@@ -1476,7 +1706,8 @@ int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const
   if (m->ndof == 0) return FPDE_OK;
   const long t = timer_begin(m, s, FPDE_STAGE_CONTRACT);
   FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
-  GatherArgs gch = gather_args(m, P, 0);
+  GatherArgs gch;
+  FPDE_TRY(gather_args(m, P, 0, s, gch));
   k_tube_gather_csr<<<gather_grid(m->ndof), 256, sizeof(double) * gch.chunk, s>>>(gch, row_ptr, col, val);
   timer_end(m, FPDE_STAGE_CONTRACT, t, s);
   FPDE_HIP(hipGetLastError());
