@@ -94,12 +94,17 @@ __global__ void __launch_bounds__(256) k_row_split(const float *__restrict__ A, 
 // rows (one q), and the staging writes (two lanes per row, groups
 // 2 (t & 1) + g).
 constexpr int KC16 = 32;
+// The arrays are declared as 16-byte groups so that every operand read and
+// staging write is one ds_read_b128 / ds_write_b128 (with _Float16 arrays
+// the compiler cannot prove the alignment of a swizzled address and splits
+// the reads into ds_read2_b64, whose 8-byte halves conflict).
 struct Split16Smem {
-  _Float16 a[2][2][T128][KC16];
-  _Float16 b[2][2][T128][KC16];
+  half8 a[2][2][T128][KC16 / 8];
+  half8 b[2][2][T128][KC16 / 8];
 };
+// group slot of 16-byte group q in row `row`
 __device__ __forceinline__ int swz(int row, int q) {
-  return 8 * (q ^ ((((row >> 1) ^ (row >> 2)) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1)));
+  return q ^ ((((row >> 1) ^ (row >> 2)) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1));
 }
 
 // FP64 chunks: [buffer][row][k], padded to an odd number of doubles per row
@@ -171,14 +176,14 @@ __device__ __forceinline__ void split_load(const _Float16 *__restrict__ xrow, in
     for (int g = 0; g < 2; g++) c.v[2 * pl + g] = *(const half8 *)(xrow + pl * KD + kk + 8 * (g0 + g));
 }
 
-__device__ __forceinline__ void split_put(const SplitChunk &c, bool live, _Float16 (*hi)[KC16],
-                                          _Float16 (*lo)[KC16]) {
+__device__ __forceinline__ void split_put(const SplitChunk &c, bool live, half8 (*hi)[KC16 / 8],
+                                          half8 (*lo)[KC16 / 8]) {
   const int r = threadIdx.x >> 1, g0 = 2 * (threadIdx.x & 1);
   const half8 z = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int g = 0; g < 2; g++) {
-    *(half8 *)&hi[r][swz(r, g0 + g)] = live ? c.v[g] : z;
-    *(half8 *)&lo[r][swz(r, g0 + g)] = live ? c.v[2 + g] : z;
+    hi[r][swz(r, g0 + g)] = live ? c.v[g] : z;
+    lo[r][swz(r, g0 + g)] = live ? c.v[2 + g] : z;
   }
 }
 
@@ -224,10 +229,10 @@ __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi,
 #pragma unroll
     for (int x = 0; x < 4; x++) {
       const int ar = 64 * wr + 16 * x + (lane & 15), br = 64 * wc + 16 * x + (lane & 15);
-      ah[x] = *(const half8 *)&sm.a[buf][0][ar][swz(ar, q)];
-      al[x] = *(const half8 *)&sm.a[buf][1][ar][swz(ar, q)];
-      bh[x] = *(const half8 *)&sm.b[buf][0][br][swz(br, q)];
-      bl[x] = *(const half8 *)&sm.b[buf][1][br][swz(br, q)];
+      ah[x] = sm.a[buf][0][ar][swz(ar, q)];
+      al[x] = sm.a[buf][1][ar][swz(ar, q)];
+      bh[x] = sm.b[buf][0][br][swz(br, q)];
+      bl[x] = sm.b[buf][1][br][swz(br, q)];
     }
     // hi hi, then hi lo, then lo hi over all 16 tiles: consecutive matrix-core
     // operations write different accumulators

@@ -754,12 +754,14 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 // whether the LDS serves them 8 at a time in a 128-byte window or 16 at a
 // time in a 256-byte window
 __device__ __forceinline__ int tswz(int row, int q) {
-  return 8 * (q ^ ((((row >> 1) ^ (row >> 2)) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1)));
+  return q ^ ((((row >> 1) ^ (row >> 2)) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1));
 }
 
+// [buffer][hi, lo][row][16-byte group]: declared as 16-byte groups so that
+// the operand reads are single ds_read_b128
 struct TubeMfmaSmem {
-  _Float16 hx[2][2][kRegion][2 * kChunkPairs];  // [buffer][hi, lo][row][inner]
-  _Float16 hy[2][2][kRegion][2 * kChunkPairs];
+  half8 hx[2][2][kRegion][2 * kChunkPairs / 8];
+  half8 hy[2][2][kRegion][2 * kChunkPairs / 8];
 };
 
 // Merge structure of every sorted pair (plan time), one wavefront per pair:
@@ -1072,17 +1074,17 @@ __device__ __forceinline__ void tube_put(TubeMfmaSmem &sm, int b, uint32_t mt, f
   if ((unsigned)rx < (unsigned)kRegion) {
     const float x = wv[c >> 1] * v;
     const _Float16 h = (_Float16)x;
-    const int o = tswz(rx, c >> 3) + (c & 7);
-    sm.hx[b][0][rx][o] = h;
-    sm.hx[b][1][rx][o] = (_Float16)(x - (float)h);
+    const int g = tswz(rx, c >> 3);
+    ((_Float16 *)&sm.hx[b][0][rx][g])[c & 7] = h;
+    ((_Float16 *)&sm.hx[b][1][rx][g])[c & 7] = (_Float16)(x - (float)h);
   }
   if ((unsigned)ry < (unsigned)kRegion) {
     const float y = v * ysc;
     const _Float16 h = (_Float16)y;
     const int cy = c ^ 1;
-    const int o = tswz(ry, cy >> 3) + (cy & 7);
-    sm.hy[b][0][ry][o] = h;
-    sm.hy[b][1][ry][o] = (_Float16)(y - (float)h);
+    const int g = tswz(ry, cy >> 3);
+    ((_Float16 *)&sm.hy[b][0][ry][g])[cy & 7] = h;
+    ((_Float16 *)&sm.hy[b][1][ry][g])[cy & 7] = (_Float16)(y - (float)h);
   }
 }
 
@@ -1115,7 +1117,7 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
   // consecutive 16-byte slots
   const half8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
   auto clear = [&](int b) {
-    half8 *px = (half8 *)&sm.hx[b][0][0][0], *py = (half8 *)&sm.hy[b][0][0][0];
+    half8 *px = &sm.hx[b][0][0][0], *py = &sm.hy[b][0][0][0];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       px[t + 256 * j] = z8;
@@ -1187,10 +1189,10 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
 #pragma unroll
     for (int x = 0; x < 4; x++) {
       const int ar = 64 * wr + 16 * x + (lane & 15), br = 64 * wc + 16 * x + (lane & 15);
-      ah[x] = *(const half8 *)&sm.hx[buf][0][ar][tswz(ar, q)];
-      al[x] = *(const half8 *)&sm.hx[buf][1][ar][tswz(ar, q)];
-      bh[x] = *(const half8 *)&sm.hy[buf][0][br][tswz(br, q)];
-      bl[x] = *(const half8 *)&sm.hy[buf][1][br][tswz(br, q)];
+      ah[x] = sm.hx[buf][0][ar][tswz(ar, q)];
+      al[x] = sm.hx[buf][1][ar][tswz(ar, q)];
+      bh[x] = sm.hy[buf][0][br][tswz(br, q)];
+      bl[x] = sm.hy[buf][1][br][tswz(br, q)];
     }
 #pragma unroll
     for (int x = 0; x < 4; x++)
