@@ -676,9 +676,9 @@ def main():
         cand.append((live["potrf"][0], {
             "bound": "mfma", "achieved": fl / t_f / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": fl / t_f / peak, "traffic": read_traffic("factorization_fp32_c5"),
-            "kernel": "FP32 Cholesky of the n x n matrix: per group of four 64-column panels k_panel and "
-                      "k_syrk<float> strip updates, then k_row_split<256> and k_syrk128<float, 256> on the "
-                      "trailing matrix (128 x 128 tiles)",
+            "kernel": "FP32 Cholesky of the n x n matrix: per group of eight 64-column panels k_colupd (left-looking "
+                      "update of the panel's block column, factoring its diagonal block) and k_panel, then "
+                      "k_row_split<512> and k_syrk128<float, 512> on the trailing matrix (128 x 128 tiles)",
             "peak_note": "dense FP16 matrix-core peak (2.5 PFLOP/s) / 3: each FP32 product of the trailing "
                          "update is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16",
             "avg_launch_ms": t_f * 1e3, "flops_per_unit": fl,
@@ -689,11 +689,11 @@ def main():
         cand.append((live["accum"][0], {
             "bound": "mfma", "achieved": fl / t_a / 1e12, "peak": FP16_PEAK / 3.0 / 1e12, "unit": "TFLOP/s",
             "frac": fl / t_a / (FP16_PEAK / 3.0), "traffic": None,
-            "kernel": "k_pack_vals + k_tube_scale + k_tube_mfma (tube blocks as split-FP16 products, one pass "
-                      "per assembly)",
-            "note": "achieved counts the method's products over entries (4 |L| |R| per pair); entries of one "
-                    "node in a half-ray are summed before the matrix-core product, so this rate can exceed "
-                    "the matrix-core work actually issued",
+            "kernel": "k_merge_vals + k_tube_mfma (entries merged per node and side, tube blocks as split-FP16 "
+                      "products on 128 x 128 regions, one pass per assembly)",
+            "note": "achieved counts the method's products over entries (4 |L| |R| per pair); the kernel computes "
+                    "each 128 x 128 region of a tube block densely over the tube's pairs, so the matrix-core work "
+                    "it issues is larger than this count",
             "avg_launch_ms": t_a * 1e3, "flops_per_unit": fl, "dtype": "f32 operands split into f16 hi + lo"}))
     roofline = max(cand, key=lambda c: c[0])[1] if cand else None
     other_roofline = min(cand, key=lambda c: c[0])[1] if len(cand) > 1 else None
