@@ -731,7 +731,7 @@ __global__ void __launch_bounds__(256) k_tube_gather_csr(GatherArgs a, const int
 // half-ray (once per element the ray crosses around it); those entries are
 // summed first (in FP64, per assembly), so that a pair's side has one
 // merged entry per node and every inner column of X and Y receives each of
-// its rows at most once.  One workgroup (four wavefronts, 64 x 64 each)
+// its rows at most once.  One workgroup (eight wavefronts, 64 x 32 each)
 // computes a 128 x 128 region (I, J), I <= J, of B and writes it and its
 // mirror into the tube's block.  The pairs go through LDS sixteen at a
 // time (32 inner columns, one depth of v_mfma_f32_16x16x32_f16): the merged
@@ -742,6 +742,7 @@ __global__ void __launch_bounds__(256) k_tube_gather_csr(GatherArgs a, const int
 // below 2^-22 of each product).
 constexpr int kRegion = 128;
 constexpr int kChunkPairs = 16;
+constexpr int kTubeThreads = 512;  // eight wavefronts per region, 64 x 32 of it each
 constexpr int kMergeSlots = 4096;  // largest tube (|U_T|) of the matrix-core path
 constexpr int kMergeMax = 512;     // most merged entries of one pair on that path
 
@@ -1090,7 +1091,7 @@ __device__ __forceinline__ void tube_put(TubeMfmaSmem &sm, int b, uint32_t mt, f
 
 // Work item b = blockIdx.x of n_items (the grid); items {-1, ..} pad the
 // per-XCD lists and exit.
-__global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *__restrict__ items, int64_t n_items,
+__global__ void __launch_bounds__(kTubeThreads) k_tube_mfma(TubeMfmaArgs a, const int4 *__restrict__ items, int64_t n_items,
                                                    const int2 *__restrict__ texp) {
   __shared__ TubeMfmaSmem sm;
   __shared__ float sw[2][kChunkPairs];  // W_p 2^-ex of the chunk's pairs (double-buffered)
@@ -1100,7 +1101,7 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
   if (it.x < 0) return;
   const int64_t T = it.x;
   const int U = it.w, rx0 = kRegion * it.y, ry0 = kRegion * it.z;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 2, wc = w & 3;
   const int64_t *__restrict__ mk_pair = a.mk_pair;
   const uint32_t *__restrict__ mk_meta = a.mk_meta;
   const float *__restrict__ mk_val = a.mk_val;
@@ -1112,31 +1113,31 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
   const int axis = k1 > k0 ? (int)((unsigned)a.pm[k0].w >> 30) : 0;
   const double xsc = (axis == 0 ? a.KC0 : (axis == 1 ? a.KC1 : a.KC2)) * ldexp(1.0, -te.x);
   const float ysc = ldexpf(1.f, -te.y);
-  // both panel buffers start at zero; a clear is 4 x 16 bytes per thread
+  // both panel buffers start at zero; a clear is 2 x 16 bytes per thread
   // of the buffer's hx and of its hy (16 KB each), consecutive lanes on
   // consecutive 16-byte slots
   const half8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
   auto clear = [&](int b) {
     half8 *px = &sm.hx[b][0][0][0], *py = &sm.hy[b][0][0][0];
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      px[t + 256 * j] = z8;
-      py[t + 256 * j] = z8;
+    for (int j = 0; j < 1024 / kTubeThreads; j++) {
+      px[t + kTubeThreads * j] = z8;
+      py[t + kTubeThreads * j] = z8;
     }
   };
   clear(0);
   clear(1);
-  f32x4v acc[4][4];
+  f32x4v acc[4][2];
 #pragma unroll
   for (int x = 0; x < 4; x++)
 #pragma unroll
-    for (int y = 0; y < 4; y++) acc[x][y] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    for (int y = 0; y < 2; y++) acc[x][y] = f32x4v{0.f, 0.f, 0.f, 0.f};
   const int q = lane >> 4;
   // A chunk's merged entries are one contiguous range [e0, e1); thread t
-  // takes e0 + t + 256 j.  Loads run ahead of their use: while chunk c is
+  // takes e0 + t + kTubeThreads j.  Loads run ahead of their use: while chunk c is
   // scattered and multiplied, the entries of chunks c + 1 and c + 2, the
   // bounds of chunk c + 3 and the pair weights of chunk c + 2 are in flight.
-  constexpr int kPre = 4;
+  constexpr int kPre = 2;
   uint32_t cm[kPre], nm[kPre], fm[kPre];
   float cv[kPre], nv[kPre], fv[kPre];
   auto bounds = [&](int64_t kc, int64_t &b0, int64_t &b1) {
@@ -1150,7 +1151,7 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
   auto entries = [&](int64_t b0, int64_t b1, uint32_t(&em)[kPre], float(&ev)[kPre]) {
 #pragma unroll
     for (int j = 0; j < kPre; j++) {
-      const int64_t i = b0 + t + 256 * j;
+      const int64_t i = b0 + t + kTubeThreads * j;
       const int64_t ic = i < b1 ? i : b0;
       em[j] = b1 > b0 ? mk_meta[ic] : 0u;
       ev[j] = b1 > b0 ? mk_val[ic] : 0.f;
@@ -1181,23 +1182,27 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
     clear(buf ^ 1);
 #pragma unroll
     for (int j = 0; j < kPre; j++)
-      if (c0 + t + 256 * j < c1) tube_put(sm, buf, cm[j], cv[j], sw[buf], ysc, rx0, ry0);
-    for (int64_t i = c0 + t + 256 * kPre; i < c1; i += 256) tube_put(sm, buf, mk_meta[i], mk_val[i], sw[buf], ysc, rx0, ry0);
+      if (c0 + t + kTubeThreads * j < c1) tube_put(sm, buf, cm[j], cv[j], sw[buf], ysc, rx0, ry0);
+    for (int64_t i = c0 + t + kTubeThreads * kPre; i < c1; i += kTubeThreads) tube_put(sm, buf, mk_meta[i], mk_val[i], sw[buf], ysc, rx0, ry0);
     if (t < kChunkPairs) sw[buf ^ 1][t] = wnext;
     __syncthreads();
-    half8 ah[4], al[4], bh[4], bl[4];
+    half8 ah[4], al[4], bh[2], bl[2];
 #pragma unroll
     for (int x = 0; x < 4; x++) {
-      const int ar = 64 * wr + 16 * x + (lane & 15), br = 64 * wc + 16 * x + (lane & 15);
+      const int ar = 64 * wr + 16 * x + (lane & 15);
       ah[x] = sm.hx[buf][0][ar][tswz(ar, q)];
       al[x] = sm.hx[buf][1][ar][tswz(ar, q)];
-      bh[x] = sm.hy[buf][0][br][tswz(br, q)];
-      bl[x] = sm.hy[buf][1][br][tswz(br, q)];
+    }
+#pragma unroll
+    for (int y = 0; y < 2; y++) {
+      const int br = 32 * wc + 16 * y + (lane & 15);
+      bh[y] = sm.hy[buf][0][br][tswz(br, q)];
+      bl[y] = sm.hy[buf][1][br][tswz(br, q)];
     }
 #pragma unroll
     for (int x = 0; x < 4; x++)
 #pragma unroll
-      for (int y = 0; y < 4; y++) {
+      for (int y = 0; y < 2; y++) {
         acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[x], bh[y], acc[x][y], 0, 0, 0);
         acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[x], bl[y], acc[x][y], 0, 0, 0);
         acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[x], bh[y], acc[x][y], 0, 0, 0);
@@ -1224,11 +1229,11 @@ __global__ void __launch_bounds__(256) k_tube_mfma(TubeMfmaArgs a, const int4 *_
 #pragma unroll
   for (int x = 0; x < 4; x++)
 #pragma unroll
-    for (int y = 0; y < 4; y++)
+    for (int y = 0; y < 2; y++)
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         const int r = rx0 + 64 * wr + 16 * x + 4 * (lane >> 4) + i;
-        const int c = ry0 + 64 * wc + 16 * y + (lane & 15);
+        const int c = ry0 + 32 * wc + 16 * y + (lane & 15);
         if (r < U && c < U) {
           const double v = ldexp((double)acc[x][y][i], eu);
           out[(int64_t)r * U + c] = v;
@@ -1592,7 +1597,7 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
     if (tp.n_mitems > 0) {
       TubeMfmaArgs ma{tp.tube_off, tp.pm, tp.pw, tp.mk_pair, tp.mk_meta, tp.mk_val, tp.blk_off, tp.blk,
                       a.KC0, a.KC1, a.KC2};
-      k_tube_mfma<<<(unsigned)tp.n_mitems, 256, 0, s>>>(ma, tp.mitems, tp.n_mitems, tp.texp);
+      k_tube_mfma<<<(unsigned)tp.n_mitems, kTubeThreads, 0, s>>>(ma, tp.mitems, tp.n_mitems, tp.texp);
     }
     timer_end(m, FPDE_STAGE_ACCUM, ta, s);
     return FPDE_OK;
