@@ -421,8 +421,7 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
         // 128 x 128 tiles (FP32: split FP16 with per-row exponents over the
         // group's 512 columns)
         const int64_t base = k0 + kGroup * NB;
-        const int64_t T2 = (n - base + T128 - 1) / T128;
-        const int64_t work = T2 * (T2 + 1) / 2 * count;
+        const int64_t work = syrk128_slots(n - base) * count;
         if (escale)
           k_row_split<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
               (const float *)A, lda, n, base, k0, escale, xsplit, sA, n, sx);

@@ -317,16 +317,31 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
 
 // Trailing update over the lower 128 x 128 tiles of the matrix from
 // row/column base = k0 + KD, with X = columns [k0, k0 + KD); the workgroup
-// of tile (0, 0) factors the 64 x 64 diagonal block at base.  Work item
-// b = tile * nz + system (the tiles (0, 0) of all systems first), nwork of
-// them; the grid is 8 ceil(nwork / 8) blocks, dealt to the eight XCDs (which
-// take workgroups round-robin) in contiguous ranges of b, so that an XCD's
-// L2 serves consecutive tiles, which share their block row of X; blocks
-// past nwork exit.  FP32 only: escale and xs, the per-row exponents and
-// split rows of X from k_row_split, system z at escale + z se and xs + z sx.
+// of tile (0, 0) factors the 64 x 64 diagonal block at base.  The tiles are
+// taken in super-blocks of kSuper x kSuper: super-block (P, Q), Q <= P, in
+// row-major lower-triangular order, each kSuper^2 consecutive work items
+// (tile rows 8 P + (s >> 3), columns 8 Q + (s & 7) for item s of the
+// super-block); items above the diagonal of a diagonal super-block or past
+// the matrix end are empty.  Work item b = system * slots + item, nwork =
+// nz slots of them; the grid is 8 ceil(nwork / 8) blocks, dealt to the eight
+// XCDs (which take workgroups round-robin) in contiguous ranges of b.  An
+// XCD runs about 64 workgroups at once (32 compute units, two each): one
+// super-block, whose tiles share 8 block rows and 8 block columns of X, so
+// that each chunk of X that its L2 fetches serves eight tiles (64 tiles of
+// one tile row would fetch 64 distinct blocks of X_J, each for one tile).
+// FP32 only: escale and xs, the per-row exponents and split rows of X from
+// k_row_split, system z at escale + z se and xs + z sx.
+constexpr int kSuper = 8;
 __device__ __forceinline__ int64_t xcd_deal(int64_t b, int64_t nblocks) {
   const int64_t per = nblocks / 8;  // nblocks is a multiple of 8
   return (b % 8) * per + b / 8;
+}
+
+// work items of one system: super-blocks of the lower tiles of a trailing
+// matrix of m rows
+__host__ __device__ inline int64_t syrk128_slots(int64_t m) {
+  const int64_t t2 = (m + T128 - 1) / T128, s2 = (t2 + kSuper - 1) / kSuper;
+  return s2 * (s2 + 1) / 2 * kSuper * kSuper;
 }
 
 template <class T, int KD>
@@ -339,18 +354,21 @@ __global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda,
   constexpr bool F32 = std::is_same<T, float>::value;
   const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
   if (bw >= nwork) return;
-  const int64_t z = bw % nz;
-  const int64_t x = bw / nz;
+  const int64_t slots = nwork / nz;
+  const int64_t z = bw / slots;
+  const int64_t x = bw - z * slots;
+  const int64_t sb = x / (kSuper * kSuper), si = x % (kSuper * kSuper);
+  int64_t P = (int64_t)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
+  while ((P + 1) * (P + 2) / 2 <= sb) P++;
+  while (P * (P + 1) / 2 > sb) P--;
+  const int64_t I = kSuper * P + si / kSuper, J = kSuper * (sb - P * (P + 1) / 2) + si % kSuper;
+  const int64_t base = k0 + KD;
+  if (J > I || base + T128 * I >= n) return;  // an empty item
   A += z * sA;
   Linv_next += z * sL;
   LinvT_next += z * sL;
   aux += z;
   __shared__ Syrk128Smem<T> sm;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= x) I++;
-  while (I * (I + 1) / 2 > x) I--;
-  const int64_t J = x - I * (I + 1) / 2;
-  const int64_t base = k0 + KD;
   const int64_t ri = base + T128 * I, cj = base + T128 * J;
   const int prow = (int)((n - ri) < T128 ? (n - ri) : T128);
   const int qrow = (int)((n - cj) < T128 ? (n - cj) : T128);
