@@ -344,13 +344,16 @@ __host__ __device__ inline int64_t syrk128_slots(int64_t m) {
   return s2 * (s2 + 1) / 2 * kSuper * kSuper;
 }
 
+// FP64: the 64 x 64 FP64 accumulators of a wavefront take 128 registers; the
+// allocator is held to 256 in all so that two workgroups (two wavefronts per
+// SIMD, 2 x 68 KB of LDS) share a compute unit and one's barrier and LDS
+// waits overlap the other's matrix-core work.
 template <class T, int KD>
-__global__ void __launch_bounds__(256) k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                 T *__restrict__ Linv_next, T *__restrict__ LinvT_next,
-                                                 int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
-                                                 const int *__restrict__ escale, int64_t se,
-                                                 const _Float16 *__restrict__ xs, int64_t sx, int nz,
-                                                 int64_t nwork) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<T, double>::value ? 2 : 1)))
+k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__ Linv_next,
+          T *__restrict__ LinvT_next, int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
+          const int *__restrict__ escale, int64_t se, const _Float16 *__restrict__ xs, int64_t sx, int nz,
+          int64_t nwork) {
   constexpr bool F32 = std::is_same<T, float>::value;
   const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
   if (bw >= nwork) return;
