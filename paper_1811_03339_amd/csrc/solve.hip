@@ -363,12 +363,13 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
 template <class T>
 static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
                        fpde_mesh *m, hipStream_t s) {
-  // Panels per group: 8 for FP32 (the split-FP16 trailing update is bound
-  // by reading and writing the trailing matrix, so it runs once per 512
-  // columns), 4 for FP64 (bound by the FP64 matrix cores).  FP32: per-row
-  // exponents and split rows (2 x 512 halfs) of the trailing updates, count
-  // x n of each.
-  constexpr int kGroup = std::is_same<T, float>::value ? 8 : 4;
+  // Panels per group: 8, so that the trailing matrix is read and written
+  // once per 512 columns (its traffic, 8 (n - k)^2 bytes per FP64 update,
+  // would otherwise compete with the matrix cores; the strip updates inside
+  // the group grow, but stay a few percent of the factorization).  FP32:
+  // per-row exponents and split rows (2 x 512 halfs) of the trailing
+  // updates, count x n of each.
+  constexpr int kGroup = 8;
   int *escale = nullptr;
   _Float16 *xsplit = nullptr;
   const int64_t sx = n * 2 * kGroup * NB;
