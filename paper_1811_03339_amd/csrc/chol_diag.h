@@ -20,8 +20,10 @@ struct DiagSmem {
 
 // Factor the 64 x 64 diagonal block held in sm.L (rows/columns >= nb are
 // identity), write L over A's block at (k0, k0), inv(L) to Linv and
-// inv(L)^T to LinvT.  256 threads; wavefront w owns block row w of the four
-// 16-row block rows.  Right-looking over 16-column blocks cb:
+// inv(L)^T to LinvT.  The first 256 threads of the workgroup work
+// (wavefront w owns block row w of the four 16-row block rows); further
+// threads only take part in its barriers.  Right-looking over 16-column
+// blocks cb:
 //   1. wavefront cb factors the 16 x 16 diagonal block in registers (lane =
 //      row, pivots and multipliers broadcast across lanes, one rsqrt per
 //      pivot) and, interleaved, inverts it (lane = column); it then scales
@@ -108,7 +110,7 @@ __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict_
       }
     }
     __syncthreads();
-    if (wv > cb) {
+    if (wv > cb && wv < 4) {
       const int rb = 16 * wv, r = lane >> 2, cg = lane & 3;
       // L[wv][cb] = A[wv][cb] inv(L_cb)^T  (lane: row r, columns 4cg..4cg+3;
       // row values streamed from LDS, a few k at a time, to bound live registers)
@@ -150,7 +152,7 @@ __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict_
     __syncthreads();
     // trailing lower triangle, in place: 4 x 4 tile (rows 4ty.., columns 4tx..)
     // -= L[rows][cb] L[columns][cb]^T (upper halves of diagonal tiles untouched)
-    if ((tx >> 2) > cb && ty >= tx) {
+    if (ty < 16 && (tx >> 2) > cb && ty >= tx) {
       double t[4][4];
 #pragma unroll
       for (int i = 0; i < 4; i++)
@@ -181,6 +183,7 @@ __device__ __forceinline__ void diag_factor(DiagSmem &sm, int nb, T *__restrict_
     atomicCAS((unsigned long long *)aux, ~0ull, (unsigned long long)k0);
   }
   // L to A (lower part inside the matrix), X row-major to Linv, X^T to LinvT
+  if (tid >= 256) return;
 #pragma unroll 4
   for (int it = 0; it < 16; it++) {
     const int idx = tid + 256 * it, r = idx >> 6, m = idx & 63;

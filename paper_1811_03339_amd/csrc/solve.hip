@@ -426,7 +426,7 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
         if (escale)
           k_row_split<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
               (const float *)A, lda, n, base, k0, escale, xsplit, sA, n, sx);
-        k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), 256, 0, s>>>(
+        k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, s>>>(
             A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
       }
     }

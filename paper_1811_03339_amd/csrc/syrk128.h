@@ -1,17 +1,22 @@
 // Trailing update of the blocked Cholesky on 128 x 128 output tiles:
 //   C[I, J] -= X_I X_J^T  over the lower tiles I >= J of the trailing matrix,
-// X = the KD columns of the group of panels just factored (KD = 256 for
-// FP64 storage, 512 for FP32).  One workgroup
-// (256 threads, four wavefronts in a 2 x 2 arrangement, 64 x 64 each) per
-// output tile reads and writes its tile of C once and streams X_I and X_J
-// through LDS in chunks of the inner dimension, double-buffered: a 128-wide
-// tile halves the reads of X per output entry compared with 64-wide tiles.
+// X = the KD = 512 columns of the group of panels just factored.  One
+// workgroup per output tile reads and writes its tile of C once and streams
+// X_I and X_J through LDS in chunks of the inner dimension, double-buffered:
+// a 128-wide tile halves the reads of X per output entry compared with
+// 64-wide tiles.
 //
 // Two arithmetic forms:
-//  * FP64 storage: v_mfma_f64_16x16x4f64 tiles (a wavefront's 64 x 64 as
-//    4 x 4 accumulators of 16 x 16), 16-deep chunks.
+//  * FP64 storage: v_mfma_f64_16x16x4f64 tiles, 16-deep chunks; eight
+//    wavefronts in a 2 x 4 arrangement (64 x 32 each, 4 x 2 accumulators of
+//    16 x 16), so that a wavefront holds 64 accumulator registers and two
+//    workgroups give every SIMD four wavefronts to cover barrier and LDS
+//    waits (the FP64 matrix cores need few LDS bytes per operation).
 //  * FP32 storage (the factor of the mixed-precision solve): split FP16 on
-//    the FP16 matrix cores, 32-deep chunks.  Row r of X is scaled by a power
+//    the FP16 matrix cores, 32-deep chunks; four wavefronts in a 2 x 2
+//    arrangement (64 x 64 each: the split operands need twice the LDS bytes
+//    per operation, and smaller wavefront tiles would make the LDS the
+//    bound).  Row r of X is scaled by a power
 //    of two 2^-e_r (e_r from the row's largest magnitude over the KD
 //    columns, computed by k_row_split before the update) so that its largest
 //    entry lies in [2^13, 2^14), then split as x = hi + lo with hi = fp16(x)
@@ -114,6 +119,19 @@ struct F64Smem {
   double b[2][T128][KC64 + 1];
 };
 
+// workgroup shape: WC wavefronts across the tile's columns (two down its
+// rows), each holding BN 16-column blocks of its 64 rows
+template <class T>
+struct Syrk128Shape;
+template <>
+struct Syrk128Shape<float> {
+  static constexpr int WC = 2, BN = 4, THREADS = 256;
+};
+template <>
+struct Syrk128Shape<double> {
+  static constexpr int WC = 4, BN = 2, THREADS = 512;
+};
+
 template <class T>
 struct Syrk128Smem;
 template <>
@@ -131,29 +149,27 @@ struct Syrk128Smem<double> {
   };
 };
 
-// Global loads of one chunk, coalesced: the sixteen lanes of a row group
-// read one 128-byte row segment.  FP32 (32 columns per chunk): thread t
-// reads columns 2 (t & 15) and 2 (t & 15) + 1 of rows (t >> 4) + 16 it,
-// it < 8; FP64 (16 columns): column t & 15 of the same rows.  Rows at or
-// past the matrix end read a valid row and are zeroed when stored.
-__device__ __forceinline__ int stage_row(int it) { return (threadIdx.x >> 4) + 16 * it; }
+// FP64 global loads of one 16-column chunk (512 threads), coalesced: the
+// sixteen lanes of a row group read one 128-byte row segment; thread t reads
+// column t & 15 of rows (t >> 4) + 32 it, it < 4.  Rows at or past the
+// matrix end read a valid row and are zeroed when stored.
+__device__ __forceinline__ int stage_row(int it) { return (threadIdx.x >> 4) + 32 * it; }
 
-// element offsets (row r clamped into [0, rows)) * lda + this thread's first
-// column, for the eight staged rows; they fit 32 bits (128 lda < 2^31)
-template <int CPL>
-__device__ __forceinline__ void stage_offsets(int rows, int64_t lda, int (&off)[8]) {
+// element offsets (row r clamped into [0, rows)) * lda + this thread's
+// column, for the four staged rows; they fit 32 bits (128 lda < 2^31)
+__device__ __forceinline__ void stage_offsets(int rows, int64_t lda, int (&off)[4]) {
 #pragma unroll
-  for (int it = 0; it < 8; it++) {
+  for (int it = 0; it < 4; it++) {
     const int r = stage_row(it);
-    off[it] = (r < rows ? r : rows - 1) * (int)lda + CPL * (threadIdx.x & 15);
+    off[it] = (r < rows ? r : rows - 1) * (int)lda + (threadIdx.x & 15);
   }
 }
 
 __device__ __forceinline__ void chunk_load(const double *__restrict__ P, const double *__restrict__ Q,
-                                          const int (&po)[8], const int (&qo)[8], double (&pv)[8],
-                                          double (&qv)[8]) {
+                                          const int (&po)[4], const int (&qo)[4], double (&pv)[4],
+                                          double (&qv)[4]) {
 #pragma unroll
-  for (int it = 0; it < 8; it++) {
+  for (int it = 0; it < 4; it++) {
     pv[it] = P[po[it]];
     qv[it] = Q[qo[it]];
   }
@@ -261,24 +277,26 @@ __device__ __forceinline__ void product_split16(const _Float16 *__restrict__ xi,
   }
 }
 
-// The same product in FP64 on v_mfma_f64_16x16x4f64.  Result layout: lane l
-// holds rows 4 i + (l >> 4), column l & 15 of each 16 x 16 tile.
+// The same product in FP64 on v_mfma_f64_16x16x4f64, eight wavefronts:
+// wavefront w holds rows 64 (w >> 2).., columns 32 (w & 3)...  Result
+// layout: lane l holds rows 4 i + (l >> 4), column l & 15 of each 16 x 16
+// tile.
 template <int KD>
 __device__ __forceinline__ void product_f64(const double *__restrict__ P, const double *__restrict__ Q, int64_t lda,
-                                            int prow, int qrow, F64Smem &sm, f64x4 (&acc)[4][4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+                                            int prow, int qrow, F64Smem &sm, f64x4 (&acc)[4][2]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 2, wc = w & 3;
   const int c = t & 15;
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  int po[8], qo[8];
-  stage_offsets<1>(prow, lda, po);
-  stage_offsets<1>(qrow, lda, qo);
-  double pv[8], qv[8];
+    for (int b = 0; b < 2; b++) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  int po[4], qo[4];
+  stage_offsets(prow, lda, po);
+  stage_offsets(qrow, lda, qo);
+  double pv[4], qv[4];
   chunk_load(P, Q, po, qo, pv, qv);
 #pragma unroll
-  for (int it = 0; it < 8; it++) {
+  for (int it = 0; it < 4; it++) {
     const int r = stage_row(it);
     sm.a[0][r][c] = r < prow ? pv[it] : 0.0;
     sm.b[0][r][c] = r < qrow ? qv[it] : 0.0;
@@ -292,20 +310,19 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
     if (more) chunk_load(P + kk + KC64, Q + kk + KC64, po, qo, pv, qv);
 #pragma unroll
     for (int k4 = 0; k4 < KC64; k4 += 4) {
-      double av[4], bv[4];
+      double av[4], bv[2];
 #pragma unroll
-      for (int x = 0; x < 4; x++) {
-        av[x] = sm.a[buf][64 * wr + 16 * x + (lane & 15)][k4 + kq];
-        bv[x] = sm.b[buf][64 * wc + 16 * x + (lane & 15)][k4 + kq];
-      }
+      for (int x = 0; x < 4; x++) av[x] = sm.a[buf][64 * wr + 16 * x + (lane & 15)][k4 + kq];
+#pragma unroll
+      for (int y = 0; y < 2; y++) bv[y] = sm.b[buf][32 * wc + 16 * y + (lane & 15)][k4 + kq];
 #pragma unroll
       for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; b++) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     if (more) {
 #pragma unroll
-      for (int it = 0; it < 8; it++) {
+      for (int it = 0; it < 4; it++) {
         const int r = stage_row(it);
         sm.a[buf ^ 1][r][c] = r < prow ? pv[it] : 0.0;
         sm.b[buf ^ 1][r][c] = r < qrow ? qv[it] : 0.0;
@@ -344,12 +361,12 @@ __host__ __device__ inline int64_t syrk128_slots(int64_t m) {
   return s2 * (s2 + 1) / 2 * kSuper * kSuper;
 }
 
-// FP64: the 64 x 64 FP64 accumulators of a wavefront take 128 registers; the
-// allocator is held to 256 in all so that two workgroups (two wavefronts per
-// SIMD, 2 x 68 KB of LDS) share a compute unit and one's barrier and LDS
-// waits overlap the other's matrix-core work.
+// FP64: the allocator is held to 128 registers (the 64 x 32 FP64
+// accumulators take 64) so that two 512-thread workgroups (four wavefronts
+// per SIMD, 2 x 68 KB of LDS) share a compute unit.
 template <class T, int KD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<T, double>::value ? 2 : 1)))
+__global__ void __launch_bounds__(Syrk128Shape<T>::THREADS)
+__attribute__((amdgpu_waves_per_eu(std::is_same<T, double>::value ? 4 : 1)))
 k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__ Linv_next,
           T *__restrict__ LinvT_next, int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
           const int *__restrict__ escale, int64_t se, const _Float16 *__restrict__ xs, int64_t sx, int nz,
@@ -375,18 +392,19 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
   const int64_t ri = base + T128 * I, cj = base + T128 * J;
   const int prow = (int)((n - ri) < T128 ? (n - ri) : T128);
   const int qrow = (int)((n - cj) < T128 ? (n - cj) : T128);
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  constexpr int WC = Syrk128Shape<T>::WC, BN = Syrk128Shape<T>::BN, WCOL = T128 / WC;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w / WC, wc = w % WC;
   // the product: val(a, b, i) at tile row frow(a, i), column fcol(b)
   using Acc = std::conditional_t<F32, f32x4v, f64x4>;
-  Acc acc[4][4];
-  int ec[4] = {0, 0, 0, 0}, er[4][4] = {};
+  Acc acc[4][BN];
+  int ec[BN] = {}, er[4][4] = {};
   if constexpr (F32) {
     const int *es = escale + z * se;
     const _Float16 *x0 = xs + z * sx;
     product_split16<KD>(x0 + ri * (2 * KD), x0 + cj * (2 * KD), prow, qrow, sm.g, acc);
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int c = 64 * wc + 16 * b + (lane & 15);
+    for (int b = 0; b < BN; b++) {
+      const int c = WCOL * wc + 16 * b + (lane & 15);
       ec[b] = es[cj + (c < qrow ? c : qrow - 1)];
     }
 #pragma unroll
@@ -402,12 +420,13 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
   auto frow = [&](int a, int i) {
     return F32 ? 64 * wr + 16 * a + 4 * (lane >> 4) + i : 64 * wr + 16 * a + 4 * i + (lane >> 4);
   };
-  auto fcol = [&](int b) { return 64 * wc + 16 * b + (lane & 15); };
+  auto fcol = [&](int b) { return WCOL * wc + 16 * b + (lane & 15); };
   auto val = [&](int a, int b, int i) -> T {
     if constexpr (F32) return ldexpf(acc[a][b][i], er[a][i] + ec[b]);
     else return acc[a][b][i];
   };
-  const bool keep = x == 0 && w == 0;  // the next diagonal block, factored below
+  // the next diagonal block (the tile's top-left 64 x 64), factored below
+  const bool keep = x == 0 && wr == 0 && WCOL * wc < NB;
   // a tile strictly below the diagonal and inside the matrix needs neither
   // clamped loads nor guarded stores: 32-bit offsets from this lane's first
   // entry (128 lda < 2^31)
@@ -416,13 +435,13 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
     T *p0 = A + (ri + frow(0, 0)) * lda + cj + fcol(0);
 #pragma unroll
     for (int a = 0; a < 4; a++) {
-      T cv[4][4];
+      T cv[BN][4];
 #pragma unroll
-      for (int b = 0; b < 4; b++)
+      for (int b = 0; b < BN; b++)
 #pragma unroll
         for (int i = 0; i < 4; i++) cv[b][i] = p0[(frow(a, i) - frow(0, 0)) * (int)lda + 16 * b];
 #pragma unroll
-      for (int b = 0; b < 4; b++)
+      for (int b = 0; b < BN; b++)
 #pragma unroll
         for (int i = 0; i < 4; i++) p0[(frow(a, i) - frow(0, 0)) * (int)lda + 16 * b] = cv[b][i] - val(a, b, i);
     }
@@ -431,16 +450,16 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
     // (indices clamped into the matrix), then updated and stored
 #pragma unroll
     for (int a = 0; a < 4; a++) {
-      T cv[4][4];
+      T cv[BN][4];
 #pragma unroll
-      for (int b = 0; b < 4; b++)
+      for (int b = 0; b < BN; b++)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           const int64_t r = ri + frow(a, i), c = cj + fcol(b);
           cv[b][i] = A[(r < n ? r : n - 1) * lda + (c < n ? c : n - 1)];
         }
 #pragma unroll
-      for (int b = 0; b < 4; b++)
+      for (int b = 0; b < BN; b++)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           const int64_t r = ri + frow(a, i), c = cj + fcol(b);
@@ -449,15 +468,15 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
     }
   }
   if (x != 0) return;
-  // tile (0, 0): wavefront 0 holds the next 64 x 64 diagonal block; stage
-  // it in LDS (lower part; identity past the matrix end) and factor it
+  // tile (0, 0): the keep wavefronts hold the next 64 x 64 diagonal block;
+  // stage it in LDS (lower part; identity past the matrix end) and factor it
   __syncthreads();  // the product's LDS is free
   const int nb = prow < NB ? prow : NB;
   if (keep) {
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-      for (int b = 0; b < 4; b++)
+      for (int b = 0; b < BN; b++)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           const int r = frow(a, i), c = fcol(b);
