@@ -60,9 +60,10 @@ FP32_PEAK = 157.3e12     # FLOP/s, matrix cores
 FP16_PEAK = 2.5e15       # FLOP/s, dense matrix cores
 CSRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc")
 # HBM counter summaries (profiles/): unit -> (file, sources its kernels are built from)
+FACT_SRC = [os.path.join(CSRC, f) for f in ("solve.hip", "syrk128.h", "chol_diag.h", "dense.h")]
 PMC = {
-    "factorization_fp32_c5": (os.path.join(ROOT, "profiles", "potrf_fp32_ellipsoid400k_pmc.txt"),
-                              [os.path.join(CSRC, f) for f in ("solve.hip", "syrk128.h", "chol_diag.h", "dense.h")]),
+    "factorization_fp32_c5": (os.path.join(ROOT, "profiles", "potrf_fp32_ellipsoid400k_pmc.txt"), FACT_SRC),
+    "factorization_fp64_c5": (os.path.join(ROOT, "profiles", "potrf_fp64_ellipsoid400k_pmc.txt"), FACT_SRC),
 }
 
 
@@ -738,7 +739,8 @@ def main():
                 "stages_ms_per_pass": {k: v[0] / 3 for k, v in st64.items() if v[1] > 0},
                 "factorization": {"bound": "mfma", "ms": potrf64 * 1e3,
                                   "achieved": n ** 3 / 3.0 / potrf64 / 1e12, "peak": FP64_PEAK / 1e12,
-                                  "unit": "TFLOP/s", "frac": n ** 3 / 3.0 / potrf64 / FP64_PEAK}}
+                                  "unit": "TFLOP/s", "frac": n ** 3 / 3.0 / potrf64 / FP64_PEAK,
+                                  "traffic": read_traffic("factorization_fp64_c5")}}
         log(f"[bench] FP64 arm {fp64}")
         del A64
         torch.cuda.empty_cache()
