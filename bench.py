@@ -60,7 +60,7 @@ FP32_PEAK = 157.3e12     # FLOP/s, matrix cores
 FP16_PEAK = 2.5e15       # FLOP/s, dense matrix cores
 CSRC = os.path.join(ROOT, "paper_1811_03339_amd", "csrc")
 # HBM counter summaries (profiles/): unit -> (file, sources its kernels are built from)
-FACT_SRC = [os.path.join(CSRC, f) for f in ("solve.hip", "syrk128.h", "chol_diag.h", "dense.h")]
+FACT_SRC = [os.path.join(CSRC, f) for f in ("solve.hip", "syrk128.h", "chol_diag.h", "dense.h", "syrk256.h")]
 PMC = {
     "factorization_fp32_c5": (os.path.join(ROOT, "profiles", "potrf_fp32_ellipsoid400k_pmc.txt"), FACT_SRC),
     "factorization_fp64_c5": (os.path.join(ROOT, "profiles", "potrf_fp64_ellipsoid400k_pmc.txt"), FACT_SRC),

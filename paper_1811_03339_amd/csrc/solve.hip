@@ -24,6 +24,7 @@
 #include "chol_diag.h"
 #include "dense.h"
 #include "syrk128.h"
+#include "syrk256.h"
 
 namespace fpde {
 
@@ -422,12 +423,18 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
         // 128 x 128 tiles (FP32: split FP16 with per-row exponents over the
         // group's 512 columns)
         const int64_t base = k0 + kGroup * NB;
-        const int64_t work = syrk128_slots(n - base) * count;
-        if (escale)
+        if constexpr (std::is_same<T, float>::value) {
+          // FP32: 256 x 256 tiles of eight 128 x 64 wavefronts
+          const int64_t work = syrk256_slots(n - base) * count;
           k_row_split<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
               (const float *)A, lda, n, base, k0, escale, xsplit, sA, n, sx);
-        k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, s>>>(
-            A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
+          k_syrk256<kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), 512, 0, s>>>(
+              A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
+        } else {
+          const int64_t work = syrk128_slots(n - base) * count;
+          k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, s>>>(
+              A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
+        }
       }
     }
   }
