@@ -339,8 +339,9 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
 // row-major lower-triangular order, each kSuper^2 consecutive work items
 // (tile rows 8 P + (s >> 3), columns 8 Q + (s & 7) for item s of the
 // super-block); items above the diagonal of a diagonal super-block or past
-// the matrix end are empty.  Work item b = system * slots + item, nwork =
-// nz slots of them; the grid is 8 ceil(nwork / 8) blocks, dealt to the eight
+// the matrix end are empty.  nwork = nz slots work items: first item 0 of
+// every system, then system by system its items 1 .. slots - 1; the grid
+// is 8 ceil(nwork / 8) blocks, dealt to the eight
 // XCDs (which take workgroups round-robin) in contiguous ranges of b.  An
 // XCD runs about 64 workgroups at once (32 compute units, two each): one
 // super-block, whose tiles share 8 block rows and 8 block columns of X, so
@@ -374,9 +375,17 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
   constexpr bool F32 = std::is_same<T, float>::value;
   const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
   if (bw >= nwork) return;
+  // the tiles (0, 0) of all systems first (they factor the next diagonal
+  // blocks, on which the next panel waits), then each system's other items
   const int64_t slots = nwork / nz;
-  const int64_t z = bw / slots;
-  const int64_t x = bw - z * slots;
+  int64_t z, x;
+  if (bw < nz) {
+    z = bw;
+    x = 0;
+  } else {
+    z = (bw - nz) / (slots - 1);
+    x = 1 + (bw - nz) % (slots - 1);
+  }
   const int64_t sb = x / (kSuper * kSuper), si = x % (kSuper * kSuper);
   int64_t P = (int64_t)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
   while ((P + 1) * (P + 2) / 2 <= sb) P++;

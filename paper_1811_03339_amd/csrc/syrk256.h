@@ -114,7 +114,8 @@ __device__ __forceinline__ void product_split256(const _Float16 *__restrict__ xi
 // (0, 0) factors the 64 x 64 diagonal block at base.  Tiles in super-blocks
 // of kSuper256 x kSuper256, in row-major lower-triangular order (items above
 // the diagonal of a diagonal super-block or past the matrix end are empty),
-// work item b = system * slots + item; the grid is 8 ceil(nwork / 8) blocks
+// nwork = nz slots work items (item 0 of every system first, then system
+// by system its other items); the grid is 8 ceil(nwork / 8) blocks
 // dealt to the XCDs in contiguous ranges of b (xcd_deal).  An XCD runs 32
 // workgroups at once, two super-blocks, which share their block rows of X.
 template <int KD>
@@ -126,9 +127,17 @@ __global__ void __launch_bounds__(512) k_syrk256(float *__restrict__ A, int64_t 
                                                  int64_t nwork) {
   const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
   if (bw >= nwork) return;
+  // the tiles (0, 0) of all systems first (they factor the next diagonal
+  // blocks, on which the next panel waits), then each system's other items
   const int64_t slots = nwork / nz;
-  const int64_t z = bw / slots;
-  const int64_t x = bw - z * slots;
+  int64_t z, x;
+  if (bw < nz) {
+    z = bw;
+    x = 0;
+  } else {
+    z = (bw - nz) / (slots - 1);
+    x = 1 + (bw - nz) % (slots - 1);
+  }
   constexpr int S = kSuper256;
   const int64_t sb = x / (S * S), si = x % (S * S);
   int64_t P = (int64_t)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
