@@ -78,6 +78,12 @@ typedef struct {
   int max_steps;    /* cap on elements per half-ray, 0 = 4096 */
   double ir_tol;    /* FPDE_MIXED: stop at ||b - K u|| / ||b|| <= ir_tol, 0 = 1e-8 */
   int ir_max_iter;  /* FPDE_MIXED: refinement sweeps, 0 = 30 */
+  int deterministic; /* 1: the sums that build K (tube blocks, rows) run in one
+                        wavefront per work item, so their additions come in a
+                        fixed order and K is the same bit for bit on every run
+                        (for parity runs; the FP64 accumulation is several
+                        times slower); 0: the fastest order, K reproducible to
+                        rounding only.  Occupies the struct's tail padding. */
 } fpde_params;
 
 typedef struct {

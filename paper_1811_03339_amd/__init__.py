@@ -60,7 +60,7 @@ class FpdeError(RuntimeError):
 class fpde_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("K", ctypes.c_double * 3), ("quad_points", ctypes.c_int),
                 ("precision", ctypes.c_int), ("source", ctypes.c_int), ("max_steps", ctypes.c_int),
-                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int)]
+                ("ir_tol", ctypes.c_double), ("ir_max_iter", ctypes.c_int), ("deterministic", ctypes.c_int)]
 
 
 class fpde_div_params(ctypes.Structure):
@@ -165,7 +165,8 @@ def _stream(stream=None):
 
 
 def params(alpha: float, K=(1.0, 1.0, 1.0), quad_points: int = 4, precision: int = FPDE_FP64,
-           source: int = FPDE_SRC_ONE, max_steps: int = 0, ir_tol: float = 0.0, ir_max_iter: int = 0):
+           source: int = FPDE_SRC_ONE, max_steps: int = 0, ir_tol: float = 0.0, ir_max_iter: int = 0,
+           deterministic: bool = False):
     p = fpde_params()
     p.alpha = float(alpha)
     for i in range(3):
@@ -176,6 +177,7 @@ def params(alpha: float, K=(1.0, 1.0, 1.0), quad_points: int = 4, precision: int
     p.max_steps = int(max_steps)
     p.ir_tol = float(ir_tol)
     p.ir_max_iter = int(ir_max_iter)
+    p.deterministic = int(bool(deterministic))
     return p
 
 

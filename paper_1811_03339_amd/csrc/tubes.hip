@@ -643,7 +643,7 @@ __device__ __forceinline__ int64_t lane64(int64_t v, int l) {
 // Ends with the chunk complete and visible to the whole workgroup.
 __device__ __forceinline__ void gather_row_chunk(const GatherArgs &a, int64_t row, int ci, int64_t c0, int64_t cw,
                                                  double *racc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int64_t p0 = a.row_off[row], np = a.row_off[row + 1] - p0;
   for (int64_t j = threadIdx.x; j < cw; j += blockDim.x) racc[j] = 0.0;
   __syncthreads();
@@ -660,7 +660,7 @@ __device__ __forceinline__ void gather_row_chunk(const GatherArgs &a, int64_t ro
       t1 = cs[1];
     }
     const int cnt = (int)((np - pb) < 64 ? (np - pb) : 64);
-    for (int k = wave; k < cnt; k += 4) {
+    for (int k = wave; k < cnt; k += nwave) {
       const int64_t uk = lane64(u0, k);
       const double *brow = a.blk + lane64(brow0, k);
       const int tk1 = __builtin_amdgcn_readlane(t1, k);
@@ -1603,8 +1603,9 @@ static int accumulate_tube_blocks(fpde_mesh *m, Plan &P, const fpde_params *p, h
     return FPDE_OK;
   }
   const long ta = timer_begin(m, s, FPDE_STAGE_ACCUM);
+  // deterministic: one wavefront per item walks the tube's pairs in order
   if (tp.n_items > 0)
-    k_tube_accum<<<(unsigned)tp.n_items, 1024, sizeof(double) * kBandDoubles, s>>>(a);
+    k_tube_accum<<<(unsigned)tp.n_items, p->deterministic ? 64 : 1024, sizeof(double) * kBandDoubles, s>>>(a);
   timer_end(m, FPDE_STAGE_ACCUM, ta, s);
   return FPDE_OK;
 }
@@ -1669,10 +1670,12 @@ int launch_contract_tubes(fpde_mesh *m, Plan &P, const fpde_params *p, void *A, 
   GatherArgs gch;
   FPDE_TRY(gather_args(m, P, lda, s, gch));
   const unsigned grid = gather_grid(m->ndof);
+  // deterministic: one wavefront per row takes the row's tube slices in order
+  const unsigned gthreads = p->deterministic ? 64 : 256;
   if (p->precision == FPDE_MIXED)
-    k_tube_gather<float><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (float *)A);
+    k_tube_gather<float><<<grid, gthreads, sizeof(double) * gch.chunk, s>>>(gch, (float *)A);
   else
-    k_tube_gather<double><<<grid, 256, sizeof(double) * gch.chunk, s>>>(gch, (double *)A);
+    k_tube_gather<double><<<grid, gthreads, sizeof(double) * gch.chunk, s>>>(gch, (double *)A);
   timer_end(m, FPDE_STAGE_CONTRACT, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
@@ -1715,7 +1718,8 @@ int launch_contract_tubes_csr(fpde_mesh *m, Plan &P, const fpde_params *p, const
   FPDE_TRY(accumulate_tube_blocks(m, P, p, s));
   GatherArgs gch;
   FPDE_TRY(gather_args(m, P, 0, s, gch));
-  k_tube_gather_csr<<<gather_grid(m->ndof), 256, sizeof(double) * gch.chunk, s>>>(gch, row_ptr, col, val);
+  k_tube_gather_csr<<<gather_grid(m->ndof), p->deterministic ? 64 : 256, sizeof(double) * gch.chunk, s>>>(
+      gch, row_ptr, col, val);
   timer_end(m, FPDE_STAGE_CONTRACT, t, s);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;

@@ -64,9 +64,10 @@ def test_calls_on_null_handle_are_rejected():
 
 def test_params_layout_matches_header():
     # double alpha; double K[3]; int quad_points, precision, source, max_steps;
-    # double ir_tol; int ir_max_iter
+    # double ir_tol; int ir_max_iter, deterministic (in the former tail padding)
     assert ctypes.sizeof(F.fpde_params) == 8 + 24 + 16 + 8 + 8
     assert F.fpde_params.ir_tol.offset == 48
+    assert F.fpde_params.deterministic.offset == 60
     assert ctypes.sizeof(F.fpde_solve_info) == 24
 
 
