@@ -174,6 +174,7 @@ struct fpde_mesh {
   // against the caller's stream (created on first use)
   hipStream_t side = nullptr;
   hipEvent_t bev[33] = {};
+  hipEvent_t lev[2] = {};  // factorization look-ahead: split rows ready, side update done
 };
 
 namespace fpde {

@@ -568,6 +568,8 @@ extern "C" void fpde_mesh_destroy(fpde_mesh *m) {
   for (hipEvent_t e : m->timer.pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : m->bev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : m->lev)
+    if (e) (void)hipEventDestroy(e);
   if (m->side) (void)hipStreamDestroy(m->side);
   if (m->linv) (void)hipFree(m->linv);
   dfree(m->tsync);

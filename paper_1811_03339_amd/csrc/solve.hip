@@ -375,22 +375,43 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
   // (measured at N = 66 822: 8-11% faster above it, alike from 12k rows
   // down to it, slower below: fewer tiles than the CUs can run at once)
   constexpr int64_t kTiles256From = 16384;
+  // Look-ahead from this size on: a group's trailing update is split into
+  // (a) the next group's 512 columns (every row from there; its tile (0, 0)
+  // factors the next diagonal block) on the caller's stream and (b) the rest
+  // on the side stream, so that the next group's panel chain (strips,
+  // diagonal blocks, panels: a dependent sequence of small launches) runs
+  // beside (b).  (a) of the next group waits for (b), which updated its
+  // columns; the FP32 split rows alternate between two sets, so that a
+  // group's split does not overwrite the rows that the previous (b) reads.
+  constexpr int64_t kLookaheadFrom = 16384;
+  const bool la = n >= kLookaheadFrom;
+  if (la) {
+    if (!m->side && hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess) {
+      m->side = nullptr;
+      return FPDE_EHIP;
+    }
+    for (hipEvent_t &e : m->lev)
+      if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
+        return FPDE_EHIP;
+  }
+  const int nset = la ? 2 : 1;
   int *escale = nullptr;
   _Float16 *xsplit = nullptr;
   const int64_t sx = n * 2 * kGroup * NB;
   if (std::is_same<T, float>::value) {
-    const int64_t need = (int64_t)count * n;
+    const int64_t need = (int64_t)nset * count * n;
     if (m->escale_n < need) {
       dfree(m->escale);
       dfree(m->xsplit);
       m->escale_n = 0;
       FPDE_TRY(dalloc(&m->escale, (size_t)need));
-      FPDE_TRY(dalloc(&m->xsplit, (size_t)(count * sx)));
+      FPDE_TRY(dalloc(&m->xsplit, (size_t)(need / n * sx)));
       m->escale_n = need;
     }
     escale = m->escale;
     xsplit = m->xsplit;
   }
+  bool pending_b = false;  // a (b) update is enqueued on the side stream
   const long t = timer_begin(m, s, FPDE_STAGE_POTRF);
   // the first diagonal block on its own; every later one is factored by the
   // workgroup of tile (0, 0) inside the preceding trailing update
@@ -427,29 +448,53 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
         // 128 x 128 tiles (FP32: split FP16 with per-row exponents over the
         // group's 512 columns)
         const int64_t base = k0 + kGroup * NB;
-        if constexpr (std::is_same<T, float>::value) {
+        // this group's set of split rows
+        const int64_t q = la ? (k0 / (kGroup * NB)) & 1 : 0;
+        int *es = escale ? escale + q * count * n : nullptr;
+        _Float16 *xq = xsplit ? xsplit + q * count * sx : nullptr;
+        if constexpr (std::is_same<T, float>::value)
           k_row_split<kGroup * NB><<<dim3((unsigned)((n - base + 3) / 4), z), 256, 0, s>>>(
-              (const float *)A, lda, n, base, k0, escale, xsplit, sA, n, sx);
-          if (n - base >= kTiles256From) {
+              (const float *)A, lda, n, base, k0, es, xq, sA, n, sx);
+        // update of the region from rb on (lower tiles), X = the group's
+        // columns; factor: its tile (0, 0) factors the diagonal block at rb
+        auto region = [&](int64_t rb, int factor, hipStream_t st) {
+          const int64_t mr = n - rb;
+          if (std::is_same<T, float>::value && mr >= kTiles256From) {
             // 256 x 256 tiles of eight 128 x 64 wavefronts, one per CU
-            const int64_t work = syrk256_slots(n - base) * count;
-            k_syrk256<kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), 512, 0, s>>>(
-                A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
+            const int64_t work = syrk256_slots(mr) * count;
+            k_syrk256<kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), 512, 0, st>>>(
+                (float *)A, lda, n, k0, rb, factor, (float *)Ln, (float *)LnT, m->flag, aux, sA, sL, es, n, xq, sx,
+                count, work);
           } else {
-            // 128 x 128 tiles, two per CU
-            const int64_t work = syrk128_slots(n - base) * count;
-            k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, s>>>(
-                A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
+            // 128 x 128 tiles
+            const int64_t work = syrk128_slots(mr) * count;
+            k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, st>>>(
+                A, lda, n, k0, rb, 0, factor, Ln, LnT, m->flag, aux, sA, sL, es, n, xq, sx, count, work);
           }
+        };
+        if (!la) {
+          region(base, 1, s);
         } else {
-          const int64_t work = syrk128_slots(n - base) * count;
+          // (a) waits for the previous group's (b), which updated its columns
+          if (pending_b) FPDE_HIP(hipStreamWaitEvent(s, m->lev[1], 0));
+          const int ntc = kGroup * NB / T128;
+          const int64_t work = syrk128_strip_slots(n - base, ntc) * count;
           k_syrk128<T, kGroup * NB><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, s>>>(
-              A, lda, n, k0, Ln, LnT, m->flag, aux, sA, sL, escale, n, xsplit, sx, count, work);
+              A, lda, n, k0, base, ntc, 1, Ln, LnT, m->flag, aux, sA, sL, es, n, xq, sx, count, work);
+          if (n - base > kGroup * NB) {
+            // (b) after the split rows (and everything before them on s)
+            FPDE_HIP(hipEventRecord(m->lev[0], s));
+            FPDE_HIP(hipStreamWaitEvent(m->side, m->lev[0], 0));
+            region(base + kGroup * NB, 0, m->side);
+            FPDE_HIP(hipEventRecord(m->lev[1], m->side));
+            pending_b = true;
+          }
         }
       }
     }
   }
 factored:
+  if (pending_b) FPDE_HIP(hipStreamWaitEvent(s, m->lev[1], 0));  // the last (b) before anything after
   timer_end(m, FPDE_STAGE_POTRF, t, s, count);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;

@@ -332,10 +332,13 @@ __device__ __forceinline__ void product_f64(const double *__restrict__ P, const 
   }
 }
 
-// Trailing update over the lower 128 x 128 tiles of the matrix from
-// row/column base = k0 + KD, with X = columns [k0, k0 + KD); the workgroup
-// of tile (0, 0) factors the 64 x 64 diagonal block at base.  The tiles are
-// taken in super-blocks of kSuper x kSuper: super-block (P, Q), Q <= P, in
+// Trailing update over the lower 128 x 128 tiles of the region of the
+// matrix from row/column base (at least k0 + KD), with X = columns
+// [k0, k0 + KD); with factor set, the workgroup of tile (0, 0) factors the
+// 64 x 64 diagonal block at base.  ntc > 0: only the tiles of the region's
+// first ntc tile columns (a strip; work items row by row, syrk128_strip_slots).
+// ntc = 0: all its lower tiles, taken in super-blocks of kSuper x kSuper:
+// super-block (P, Q), Q <= P, in
 // row-major lower-triangular order, each kSuper^2 consecutive work items
 // (tile rows 8 P + (s >> 3), columns 8 Q + (s & 7) for item s of the
 // super-block); items above the diagonal of a diagonal super-block or past
@@ -362,16 +365,24 @@ __host__ __device__ inline int64_t syrk128_slots(int64_t m) {
   return s2 * (s2 + 1) / 2 * kSuper * kSuper;
 }
 
+// work items of one system in strip mode: the lower tiles of the first ntc
+// tile columns of a trailing matrix of m rows (a triangle of ntc rows, then
+// ntc per tile row; items of the triangle past the matrix end are empty)
+__host__ __device__ inline int64_t syrk128_strip_slots(int64_t m, int ntc) {
+  const int64_t t2 = (m + T128 - 1) / T128, tri = (int64_t)ntc * (ntc + 1) / 2;
+  return t2 <= ntc ? tri : tri + (t2 - ntc) * ntc;
+}
+
 // FP64: the allocator is held to 128 registers (the 64 x 32 FP64
 // accumulators take 64) so that two 512-thread workgroups (four wavefronts
 // per SIMD, 2 x 68 KB of LDS) share a compute unit.
 template <class T, int KD>
 __global__ void __launch_bounds__(Syrk128Shape<T>::THREADS)
 __attribute__((amdgpu_waves_per_eu(std::is_same<T, double>::value ? 4 : 1)))
-k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__ Linv_next,
-          T *__restrict__ LinvT_next, int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
-          const int *__restrict__ escale, int64_t se, const _Float16 *__restrict__ xs, int64_t sx, int nz,
-          int64_t nwork) {
+k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, int64_t base, int ntc, int factor,
+          T *__restrict__ Linv_next, T *__restrict__ LinvT_next, int32_t *flag, int64_t *aux, int64_t sA,
+          int64_t sL, const int *__restrict__ escale, int64_t se, const _Float16 *__restrict__ xs, int64_t sx,
+          int nz, int64_t nwork) {
   constexpr bool F32 = std::is_same<T, float>::value;
   const int64_t bw = xcd_deal(blockIdx.x, gridDim.x);
   if (bw >= nwork) return;
@@ -386,12 +397,26 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
     z = (bw - nz) / (slots - 1);
     x = 1 + (bw - nz) % (slots - 1);
   }
-  const int64_t sb = x / (kSuper * kSuper), si = x % (kSuper * kSuper);
-  int64_t P = (int64_t)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
-  while ((P + 1) * (P + 2) / 2 <= sb) P++;
-  while (P * (P + 1) / 2 > sb) P--;
-  const int64_t I = kSuper * P + si / kSuper, J = kSuper * (sb - P * (P + 1) / 2) + si % kSuper;
-  const int64_t base = k0 + KD;
+  int64_t I, J;
+  if (ntc > 0) {
+    const int64_t tri = (int64_t)ntc * (ntc + 1) / 2;
+    if (x < tri) {
+      I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+      while ((I + 1) * (I + 2) / 2 <= x) I++;
+      while (I * (I + 1) / 2 > x) I--;
+      J = x - I * (I + 1) / 2;
+    } else {
+      I = ntc + (x - tri) / ntc;
+      J = (x - tri) % ntc;
+    }
+  } else {
+    const int64_t sb = x / (kSuper * kSuper), si = x % (kSuper * kSuper);
+    int64_t P = (int64_t)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
+    while ((P + 1) * (P + 2) / 2 <= sb) P++;
+    while (P * (P + 1) / 2 > sb) P--;
+    I = kSuper * P + si / kSuper;
+    J = kSuper * (sb - P * (P + 1) / 2) + si % kSuper;
+  }
   if (J > I || base + T128 * I >= n) return;  // an empty item
   A += z * sA;
   Linv_next += z * sL;
@@ -435,7 +460,7 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
     else return acc[a][b][i];
   };
   // the next diagonal block (the tile's top-left 64 x 64), factored below
-  const bool keep = x == 0 && wr == 0 && WCOL * wc < NB;
+  const bool keep = factor && x == 0 && wr == 0 && WCOL * wc < NB;
   // a tile strictly below the diagonal and inside the matrix needs neither
   // clamped loads nor guarded stores: 32-bit offsets from this lane's first
   // entry (128 lda < 2^31)
@@ -476,7 +501,7 @@ k_syrk128(T *__restrict__ A, int64_t lda, int64_t n, int64_t k0, T *__restrict__
         }
     }
   }
-  if (x != 0) return;
+  if (x != 0 || !factor) return;
   // tile (0, 0): the keep wavefronts hold the next 64 x 64 diagonal block;
   // stage it in LDS (lower part; identity past the matrix end) and factor it
   __syncthreads();  // the product's LDS is free

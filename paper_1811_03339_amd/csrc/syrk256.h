@@ -108,10 +108,11 @@ __device__ __forceinline__ void product_split256(const _Float16 *__restrict__ xi
   }
 }
 
-// Trailing update over the lower 256 x 256 tiles of the matrix from
-// row/column base = k0 + KD, X = columns [k0, k0 + KD) as split rows (xs,
-// from k_row_split) with per-row exponents (escale); the workgroup of tile
-// (0, 0) factors the 64 x 64 diagonal block at base.  Tiles in super-blocks
+// Trailing update over the lower 256 x 256 tiles of the region of the
+// matrix from row/column base (at least k0 + KD), X = columns [k0, k0 + KD)
+// as split rows (xs, from k_row_split) with per-row exponents (escale); with
+// factor set, the workgroup of tile (0, 0) factors the 64 x 64 diagonal
+// block at base.  Tiles in super-blocks
 // of kSuper256 x kSuper256, in row-major lower-triangular order (items above
 // the diagonal of a diagonal super-block or past the matrix end are empty),
 // nwork = nz slots work items (item 0 of every system first, then system
@@ -120,7 +121,8 @@ __device__ __forceinline__ void product_split256(const _Float16 *__restrict__ xi
 // workgroups at once, two super-blocks, which share their block rows of X.
 template <int KD>
 __global__ void __launch_bounds__(512) k_syrk256(float *__restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                 float *__restrict__ Linv_next, float *__restrict__ LinvT_next,
+                                                 int64_t base, int factor, float *__restrict__ Linv_next,
+                                                 float *__restrict__ LinvT_next,
                                                  int32_t *flag, int64_t *aux, int64_t sA, int64_t sL,
                                                  const int *__restrict__ escale, int64_t se,
                                                  const _Float16 *__restrict__ xs, int64_t sx, int nz,
@@ -144,7 +146,6 @@ __global__ void __launch_bounds__(512) k_syrk256(float *__restrict__ A, int64_t 
   while ((P + 1) * (P + 2) / 2 <= sb) P++;
   while (P * (P + 1) / 2 > sb) P--;
   const int64_t I = S * P + si / S, J = S * (sb - P * (P + 1) / 2) + si % S;
-  const int64_t base = k0 + KD;
   if (J > I || base + T256 * I >= n) return;  // an empty item
   A += z * sA;
   Linv_next += z * sL;
@@ -169,7 +170,7 @@ __global__ void __launch_bounds__(512) k_syrk256(float *__restrict__ A, int64_t 
   auto fcol = [&](int b) { return 64 * wc + 16 * b + (lane & 15); };
   // wavefront 0 of tile (0, 0) holds the next diagonal block in its rows
   // 0..63 (blocks a < 4), factored below; its other rows are stored
-  const bool keepw = x == 0 && w == 0;
+  const bool keepw = factor && x == 0 && w == 0;
   // a tile strictly below the diagonal and inside the matrix needs neither
   // clamped loads nor guarded stores: 32-bit offsets from this lane's first
   // entry (256 lda < 2^31)
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(512) k_syrk256(float *__restrict__ A, int64_t 
         }
     }
   }
-  if (x != 0) return;
+  if (x != 0 || !factor) return;
   // tile (0, 0): stage the next diagonal block in LDS (lower part; identity
   // past the matrix end) and factor it
   __syncthreads();  // the product's LDS is free
