@@ -7,7 +7,7 @@ the C ABI.
   within 1e-10, max-norm relative.
 * A system that is not positive definite is reported for itself alone; the
   sizes cover one partial block (n < 64), several blocks with a ragged
-  tail, and the largest batch (16).
+  tail, the look-ahead factorization (n = 17 576) and the largest batch (16).
 """
 import numpy as np
 import pytest
@@ -48,6 +48,9 @@ def systems(gm, cases):
     ("cube8", [(1.2, 4), (1.5, 4), (1.8, 11)]),
     ("sphere_small", [(1.3, 4), (1.6, 11)]),
     ("sphere20k", [(1.2, 4), (1.5, 4), (1.8, 4), (1.2, 11), (1.5, 11), (1.8, 11)]),
+    # 17 576 unknowns: the factorization looks ahead (side-stream trailing
+    # updates) with two systems at once
+    ("cube27", [(1.3, 4), (1.6, 4)]),
 ])
 def test_batch_equals_single_and_oracle(name, cases):
     print(f"[case] batch {name} {cases}", flush=True)
