@@ -1007,7 +1007,36 @@ __global__ void k_inverse32(const int32_t *__restrict__ perm, int64_t n, int32_t
   if (q < n) inv[perm[q]] = (int32_t)q;
 }
 
-// dp[2 k + s] = d(k, s); sixteen lanes per pair
+// U entries per lane of the sixteen for one pair in flight at once: the
+// loads of all U first, then the gathers of x, then the sums in entry order
+template <int U>
+__device__ __forceinline__ void pair_dot_run(int64_t &q, int64_t qe, const uint32_t *__restrict__ mk_meta,
+                                             const double *__restrict__ mk_val64,
+                                             const int32_t *__restrict__ mg_node, const double *__restrict__ x,
+                                             double &s0, double &s1) {
+  for (; q + 16 * (U - 1) < qe; q += 16 * U) {
+    double w[U], xv[U];
+    int32_t nd[U];
+    uint32_t mt[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      w[u] = mk_val64[q + 16 * u];
+      nd[u] = mg_node[q + 16 * u];
+      mt[u] = mk_meta[q + 16 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) xv[u] = x[nd[u]];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const double v = w[u] * xv[u];
+      if ((mt[u] >> 16) & 1u) s1 += v;
+      else s0 += v;
+    }
+  }
+}
+
+// dp[2 k + s] = d(k, s); sixteen lanes per pair, each summing its entries in
+// ascending merged order
 __global__ void __launch_bounds__(256) k_mpair_dot(const int64_t *__restrict__ mk_pair,
                                                    const uint32_t *__restrict__ mk_meta,
                                                    const double *__restrict__ mk_val64,
@@ -1017,11 +1046,11 @@ __global__ void __launch_bounds__(256) k_mpair_dot(const int64_t *__restrict__ m
   const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   if (k >= n_pairs) return;  // the whole group of 16 shares k
   double s0 = 0.0, s1 = 0.0;
-  for (int64_t q = mk_pair[k] + gl; q < mk_pair[k + 1]; q += 16) {
-    const double v = mk_val64[q] * x[mg_node[q]];
-    if ((mk_meta[q] >> 16) & 1u) s1 += v;
-    else s0 += v;
-  }
+  const int64_t qe = mk_pair[k + 1];
+  int64_t q = mk_pair[k] + gl;
+  pair_dot_run<8>(q, qe, mk_meta, mk_val64, mg_node, x, s0, s1);
+  pair_dot_run<2>(q, qe, mk_meta, mk_val64, mg_node, x, s0, s1);
+  pair_dot_run<1>(q, qe, mk_meta, mk_val64, mg_node, x, s0, s1);
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) {
     s0 += __shfl_xor(s0, o, 16);
@@ -1030,6 +1059,30 @@ __global__ void __launch_bounds__(256) k_mpair_dot(const int64_t *__restrict__ m
   if (gl == 0) {
     dp[2 * k] = s0;
     dp[2 * k + 1] = s1;
+  }
+}
+
+// U incidences per lane of node j's wavefront in flight at once, summed in
+// ascending order
+template <int U>
+__device__ __forceinline__ void row_apply_run(int64_t &q, int64_t qe, const uint32_t *__restrict__ mpart,
+                                              const double *__restrict__ mwv, const double *__restrict__ dp,
+                                              double KC0, double KC1, double KC2, double &s) {
+  for (; q + 64 * (U - 1) < qe; q += 64 * U) {
+    uint32_t pt[U];
+    double w[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      pt[u] = mpart[q + 64 * u];
+      w[u] = mwv[q + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) d[u] = dp[pt[u] & 0x3fffffffu];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t ax = pt[u] >> 30;
+      s += w[u] * (ax == 0 ? KC0 : (ax == 1 ? KC1 : KC2)) * d[u];
+    }
   }
 }
 
@@ -1043,12 +1096,11 @@ __global__ void __launch_bounds__(256) k_mapply_rows(const int64_t *__restrict__
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= ndof) return;
   double s = 0.0;
-  for (int64_t q = mrow_off[j] + lane; q < mrow_off[j + 1]; q += 64) {
-    const uint32_t pt = mpart[q];
-    const uint32_t ax = pt >> 30;
-    const double kc = ax == 0 ? KC0 : (ax == 1 ? KC1 : KC2);
-    s += mwv[q] * kc * dp[pt & 0x3fffffffu];
-  }
+  const int64_t qe = mrow_off[j + 1];
+  int64_t q = mrow_off[j] + lane;
+  row_apply_run<4>(q, qe, mpart, mwv, dp, KC0, KC1, KC2, s);
+  row_apply_run<2>(q, qe, mpart, mwv, dp, KC0, KC1, KC2, s);
+  row_apply_run<1>(q, qe, mpart, mwv, dp, KC0, KC1, KC2, s);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) y[j] = s;
 }
