@@ -1189,7 +1189,7 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_mfma(TubeMfmaArgs a, cons
   // takes e0 + t + kTubeThreads j.  Loads run ahead of their use: while chunk c is
   // scattered and multiplied, the entries of chunks c + 1 and c + 2, the
   // bounds of chunk c + 3 and the pair weights of chunk c + 2 are in flight.
-  constexpr int kPre = 2;
+  constexpr int kPre = 4;
   uint32_t cm[kPre], nm[kPre], fm[kPre];
   float cv[kPre], nv[kPre], fv[kPre];
   auto bounds = [&](int64_t kc, int64_t &b0, int64_t &b1) {
