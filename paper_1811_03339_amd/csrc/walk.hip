@@ -138,6 +138,47 @@ __device__ __forceinline__ double lnpowr(double r, double e) {
   return l * exp(e * l);
 }
 
+// Per-thread staging of a half-ray's consecutive outputs.  A thread writes
+// its entries one at a time as the walk proceeds, and its neighbours in the
+// wavefront write other half-rays' ranges, so plain stores leave every
+// 64-byte segment of the output partly written for many steps (the caches
+// evict such segments and the memory takes several partial writes per
+// segment).  Instead each output goes to LDS slot (index mod L) of the
+// thread's column, and an aligned run of L outputs leaves as 16-byte stores
+// once its last element is known; the first and last runs of a half-ray,
+// which it shares with its neighbours, are written element by element.
+// The destination arrays are 256-byte aligned (device allocations).
+template <class T, int L>
+__device__ __forceinline__ void stage_put(T (*st)[256], T *__restrict__ out, int64_t base, int64_t e, T v) {
+  static_assert(L * sizeof(T) == 64, "runs are 64-byte segments");
+  const int tid = threadIdx.x;
+  const int sl = (int)(e & (L - 1));
+  st[sl][tid] = v;
+  if (sl != L - 1) return;
+  const int64_t c0 = e - (L - 1);
+  if (c0 >= base) {
+    if constexpr (sizeof(T) == 8) {
+      double2 *p = reinterpret_cast<double2 *>(out + c0);
+#pragma unroll
+      for (int u = 0; u < L / 2; u++) p[u] = make_double2(st[2 * u][tid], st[2 * u + 1][tid]);
+    } else {
+      int4 *p = reinterpret_cast<int4 *>(out + c0);
+#pragma unroll
+      for (int u = 0; u < L / 4; u++)
+        p[u] = make_int4(st[4 * u][tid], st[4 * u + 1][tid], st[4 * u + 2][tid], st[4 * u + 3][tid]);
+    }
+  } else {
+    for (int64_t q = base; q <= e; q++) out[q] = st[q & (L - 1)][tid];
+  }
+}
+
+// the outputs of the last, incomplete run [max(base, end rounded down), end)
+template <class T, int L>
+__device__ __forceinline__ void stage_flush(T (*st)[256], T *__restrict__ out, int64_t base, int64_t end) {
+  const int64_t c0 = end & ~(int64_t)(L - 1);
+  for (int64_t q = c0 > base ? c0 : base; q < end; q++) out[q] = st[q & (L - 1)][threadIdx.x];
+}
+
 // The walk is a chain of dependent element-record loads per thread; the
 // value pass is asked for 4 wavefronts per SIMD (at most 128 VGPRs) so more
 // chains are in flight.
@@ -180,13 +221,17 @@ k_walk(WalkArgs a) {
   double dot_u = 0.0, dot_l = 0.0, ddot_u = 0.0, ddot_l = 0.0;
   const double sgn = side ? -1.0 : 1.0;
 
+  // staging runs of the structure pass (node and half-ray ids) and of the
+  // value pass (values)
+  __shared__ int32_t st_dof[MODE == W_STRUCT ? 16 : 1][256], st_ray[MODE == W_STRUCT ? 16 : 1][256];
+  __shared__ double st_val[MODE == W_VALUES ? 8 : 1][256];
   auto emit = [&](int32_t d, double v, double dv) {
-    if (MODE == W_STRUCT) {
-      a.ent_dof[base + nemit] = d;
-      a.ent_ray[base + nemit] = (int32_t)h;
-    } else if (MODE == W_VALUES) {
-      a.ent_val[base + nemit] = v;
-    } else if (MODE == W_ADJ) {
+    if constexpr (MODE == W_STRUCT) {
+      stage_put<int32_t, 16>(st_dof, a.ent_dof, base, base + nemit, d);
+      stage_put<int32_t, 16>(st_ray, a.ent_ray, base, base + nemit, (int32_t)h);
+    } else if constexpr (MODE == W_VALUES) {
+      stage_put<double, 8>(st_val, a.ent_val, base, base + nemit, v);
+    } else if constexpr (MODE == W_ADJ) {
       const double uu = a.u[d], ll = a.lam[d];
       dot_u += v * uu;
       dot_l += v * ll;
@@ -351,6 +396,12 @@ k_walk(WalkArgs a) {
 #pragma unroll
   for (int j = 0; j < 4; j++)
     if (wd[j] >= 0) emit(wd[j], wv[j], wdv[j]);
+  if constexpr (MODE == W_STRUCT) {
+    stage_flush<int32_t, 16>(st_dof, a.ent_dof, base, base + nemit);
+    stage_flush<int32_t, 16>(st_ray, a.ent_ray, base, base + nemit);
+  } else if constexpr (MODE == W_VALUES) {
+    stage_flush<double, 8>(st_val, a.ent_val, base, base + nemit);
+  }
   if (MODE == W_COUNT) {
     a.cnt[k] = (int32_t)nemit;
     if (a.len) a.len[k] = nseg;
