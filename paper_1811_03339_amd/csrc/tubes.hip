@@ -1086,14 +1086,17 @@ __device__ __forceinline__ void row_apply_run(int64_t &q, int64_t qe, const uint
   }
 }
 
-// y_j over node j's merged incidences; one wavefront per node
+// y_j over node j's merged incidences; one wavefront per node, four nodes
+// per workgroup, the groups of four dealt to the XCDs in contiguous ranges
+// (neighbouring nodes read the dots of the same tubes' pairs, which then
+// stay in one L2); the grid is 8 ceil(ceil(ndof / 4) / 8) workgroups
 __global__ void __launch_bounds__(256) k_mapply_rows(const int64_t *__restrict__ mrow_off,
                                                      const uint32_t *__restrict__ mpart,
                                                      const double *__restrict__ mwv, const double *__restrict__ dp,
                                                      double KC0, double KC1, double KC2, int64_t ndof,
                                                      double *__restrict__ y) {
   const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t j = dealt_row(blockIdx.x, (ndof + 3) / 4) * 4 + (threadIdx.x >> 6);
   if (j >= ndof) return;
   double s = 0.0;
   const int64_t qe = mrow_off[j + 1];
@@ -1708,7 +1711,7 @@ int apply_merged(fpde_mesh *m, Plan &P, const fpde_params *p, const double *x, d
   Order o = order_scalars(p->alpha);
   const long t = timer_begin(m, s, FPDE_STAGE_APPLY);
   k_mpair_dot<<<nblocks(16 * nP), 256, 0, s>>>(tp.mk_pair, tp.mk_meta, tp.mk_val64, tp.mg_node, x, nP, tp.mdp);
-  k_mapply_rows<<<nblocks(m->ndof, 4), 256, 0, s>>>(tp.mrow_off, tp.mpart, tp.mwv, tp.mdp, p->K[0] * o.c_alpha,
+  k_mapply_rows<<<(unsigned)(8 * (((m->ndof + 3) / 4 + 7) / 8)), 256, 0, s>>>(tp.mrow_off, tp.mpart, tp.mwv, tp.mdp, p->K[0] * o.c_alpha,
                                                     p->K[1] * o.c_alpha, p->K[2] * o.c_alpha, m->ndof, y);
   timer_end(m, FPDE_STAGE_APPLY, t, s);
   FPDE_HIP(hipGetLastError());
