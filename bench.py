@@ -677,9 +677,9 @@ def main():
         cand.append((live["potrf"][0], {
             "bound": "mfma", "achieved": fl / t_f / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": fl / t_f / peak, "traffic": read_traffic("factorization_fp32_c5"),
-            "kernel": "FP32 Cholesky of the n x n matrix: per group of eight 64-column panels k_panel and the "
-                      "k_syrk<float, 64> strip update of the group's later block columns, then k_row_split<512> "
-                      "and k_syrk256<512> on the trailing matrix (256 x 256 tiles)",
+            "kernel": "FP32 Cholesky of the n x n matrix: per group of sixteen 64-column panels k_panel and the "
+                      "k_syrk<float, 64> strip update of the group's later block columns, then k_row_split<1024> "
+                      "and k_syrk256<1024> on the trailing matrix (256 x 256 tiles)",
             "peak_note": "dense FP16 matrix-core peak (2.5 PFLOP/s) / 3: each FP32 product of the trailing "
                          "update is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16",
             "avg_launch_ms": t_f * 1e3, "flops_per_unit": fl,

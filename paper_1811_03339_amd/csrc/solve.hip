@@ -364,19 +364,20 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
 template <class T>
 static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
                        fpde_mesh *m, hipStream_t s) {
-  // Panels per group: 8, so that the trailing matrix is read and written
-  // once per 512 columns (its traffic, 8 (n - k)^2 bytes per FP64 update,
+  // Panels per group: 16, so that the trailing matrix is read and written
+  // once per 1024 columns (its traffic, 8 (n - k)^2 bytes per FP64 update,
   // would otherwise compete with the matrix cores; the strip updates inside
-  // the group grow, but stay a few percent of the factorization).  FP32:
-  // per-row exponents and split rows (2 x 512 halfs) of the trailing
-  // updates, count x n of each.
-  constexpr int kGroup = 8;
+  // the group grow, but run beside the trailing update of the previous
+  // group).  Measured at N = 66 822: FP32 11% faster than groups of 8, FP64
+  // 3%; groups of 32 are slower again.  FP32: per-row exponents and split
+  // rows (2 x 1024 halfs) of the trailing updates, count x n of each.
+  constexpr int kGroup = 16;
   // FP32 trailing matrices of at least this many rows take 256 x 256 tiles
   // (measured at N = 66 822: 8-11% faster above it, alike from 12k rows
   // down to it, slower below: fewer tiles than the CUs can run at once)
   constexpr int64_t kTiles256From = 16384;
   // Look-ahead from this size on: a group's trailing update is split into
-  // (a) the next group's 512 columns (every row from there; its tile (0, 0)
+  // (a) the next group's 1024 columns (every row from there; its tile (0, 0)
   // factors the next diagonal block) on the caller's stream and (b) the rest
   // on the side stream, so that the next group's panel chain (strips,
   // diagonal blocks, panels: a dependent sequence of small launches) runs
@@ -445,8 +446,8 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
                                                                  count, inner);
       } else {
         // the group's update of the trailing matrix from k0 + 64 kGroup on
-        // 128 x 128 tiles (FP32: split FP16 with per-row exponents over the
-        // group's 512 columns)
+        // 128 x 128 or 256 x 256 tiles (FP32: split FP16 with per-row
+        // exponents over the group's 1024 columns)
         const int64_t base = k0 + kGroup * NB;
         // this group's set of split rows
         const int64_t q = la ? (k0 / (kGroup * NB)) & 1 : 0;
