@@ -1,14 +1,15 @@
 """The dense Cholesky solve (Table 4's solve stage) on its own, through the
 C ABI, at sizes that take every branch of the blocked factorization: one
-partial block, exactly one block, a pair of 64-column panels followed by a
-single last panel, pairs that end exactly at N, a partial last block, and
-trailing matrices of one and of several 128 x 128 update tiles, full and
-partial (N = 1000, 1728).
+partial block, exactly one block, panels inside one group of sixteen that
+end exactly at N or in a partial last block, a whole group and its
+in-group strips only (N = 1000), and a group followed by a trailing update
+of five full and one partial 128 x 128 tile rows (N = 1728).
 
-The FP32 factorization (split-FP16 trailing updates over groups of eight
-panels) is checked on assembled mixed-precision matrices: one group only
-(N = 512), one trailing update with a partial last group (1000), several
-groups with a ragged tail (1728) and several whole groups (4096).  Its
+The FP32 factorization (split-FP16 trailing updates over groups of sixteen
+panels, 1024 columns) is checked on assembled mixed-precision matrices:
+part of one group (N = 512, 1000), one group then a trailing update with a
+ragged tail (1728), whole groups (4096) and 17 576 unknowns (look-ahead,
+256 x 256 tiles).  Its
 factor must lie within 16 times LAPACK's own FP32 factorization's
 (spotrf) distance from the FP64 Cholesky factor of the same FP32 matrix:
 the panels apply each 64 x 64 diagonal block through its explicit inverse
@@ -84,8 +85,8 @@ def test_batch_matches_lapack(k):
         assert rel(u[z].cpu().numpy(), np.linalg.solve(S, rhs)) <= 1e-10, z
 
 
-# n = 512 ... 4096, and 17576, whose first trailing updates (from 17064 rows)
-# take the 256 x 256 tiles with a ragged last tile row
+# n = 512 ... 4096, and 17576, whose first trailing update (16 552 rows) takes
+# the 256 x 256 tiles with a ragged last tile row, under the look-ahead
 @pytest.mark.parametrize("k", [9, 11, 13, 17, 27])
 def test_fp32_factor_as_accurate_as_spotrf(k):
     if k in SIZES:
