@@ -165,7 +165,7 @@ struct fpde_mesh {
   int64_t *batch_aux = nullptr;   // device, kMaxBatch: failing column per system of a batched factorization
   int *escale = nullptr;          // device: per-row exponents of the split-FP16 trailing updates
   _Float16 *xsplit = nullptr;     // device: the split rows (hi, lo) of X for those updates
-  int64_t escale_n = 0;
+  int64_t escale_n = 0, xsplit_n = 0;  // entries allocated in escale, xsplit
   double *bvec = nullptr;         // device: intermediate vectors of a batched solve
   int64_t bvec_n = 0;
   int tsync_epoch = 0;

@@ -361,23 +361,46 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
 // systems run side by side.  Linv holds 2 nblk inverse blocks per system
 // (inverses, then transposes) at stride sL; aux[z] receives system z's
 // failing column.
-template <class T>
-static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
-                       fpde_mesh *m, hipStream_t s) {
-  // Panels per group: 16, so that the trailing matrix is read and written
-  // once per 1024 columns (its traffic, 8 (n - k)^2 bytes per FP64 update,
-  // would otherwise compete with the matrix cores; the strip updates inside
-  // the group grow, but run beside the trailing update of the previous
-  // group).  Measured at N = 66 822: FP32 11% faster than groups of 8, FP64
-  // 3%; groups of 32 are slower again.  FP32: per-row exponents and split
-  // rows (2 x 1024 halfs) of the trailing updates, count x n of each.
-  constexpr int kGroup = 16;
+// Inside a panel group: the KD / 64 block columns from hb on, every row
+// from hb, by the KD columns of the group just before hb (X = columns
+// [hb - KD, hb)), as a strip of 128 x 128 tiles (FP32: split FP16 rows of
+// X first, into xq and es); its tile (0, 0) factors the diagonal block at
+// hb into Ln, LnT.
+template <class T, int KD>
+static void group_part_update(T *A, int64_t lda, int64_t sA, int64_t n, int count, int64_t hb, T *Ln, T *LnT,
+                              int64_t sL, int64_t *aux, int32_t *flag, int *es, _Float16 *xq, int64_t sx,
+                              hipStream_t s) {
+  const int64_t kx = hb - KD;
+  if constexpr (std::is_same<T, float>::value)
+    k_row_split<KD><<<dim3((unsigned)((n - hb + 3) / 4), (unsigned)count), 256, 0, s>>>(
+        (const float *)A, lda, n, hb, kx, es, xq, sA, n, sx);
+  const int ntc = KD / T128;
+  const int64_t work = syrk128_strip_slots(n - hb, ntc) * count;
+  k_syrk128<T, KD><<<(unsigned)(8 * ((work + 7) / 8)), Syrk128Shape<T>::THREADS, 0, s>>>(
+      A, lda, n, kx, hb, ntc, 1, Ln, LnT, flag, aux, sA, sL, es, n, xq, sx, count, work);
+}
+
+template <class T, int kGroup, int kPart>
+static int potrf_batch_g(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
+                         fpde_mesh *m, hipStream_t s) {
+  // Panels per group: kGroup (16 or 32), so that the trailing matrix is
+  // read and written once per 64 kGroup columns (its traffic, 8 (n - k)^2
+  // bytes per FP64 update, would otherwise compete with the matrix cores).
+  // Inside a group the panels update the later block columns of their own
+  // part of kPart panels one by one (strips of at most kPart - 1 block
+  // columns).  With kPart < kGroup the update is recursive: whenever the
+  // group's first kPart d panels are done (d the largest power of two
+  // dividing the count over kPart, up to kGroup / 2 panels) the next kPart d
+  // panels' columns are updated by those kPart d at once, on 128 x 128 tiles
+  // with KD = 64 kPart d.  FP32: per-row exponents and split rows
+  // (2 x 64 kGroup halfs) of the trailing updates, count x n of each, which
+  // the parts inside the group use too.
   // FP32 trailing matrices of at least this many rows take 256 x 256 tiles
   // (measured at N = 66 822: 8-11% faster above it, alike from 12k rows
   // down to it, slower below: fewer tiles than the CUs can run at once)
   constexpr int64_t kTiles256From = 16384;
   // Look-ahead from this size on: a group's trailing update is split into
-  // (a) the next group's 1024 columns (every row from there; its tile (0, 0)
+  // (a) the next group's 64 kGroup columns (every row from there; its tile (0, 0)
   // factors the next diagonal block) on the caller's stream and (b) the rest
   // on the side stream, so that the next group's panel chain (strips,
   // diagonal blocks, panels: a dependent sequence of small launches) runs
@@ -400,14 +423,15 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
   _Float16 *xsplit = nullptr;
   const int64_t sx = n * 2 * kGroup * NB;
   if (std::is_same<T, float>::value) {
-    const int64_t need = (int64_t)nset * count * n;
-    if (m->escale_n < need) {
+    const int64_t need = (int64_t)nset * count * n, xneed = (int64_t)nset * count * sx;
+    if (m->escale_n < need || m->xsplit_n < xneed) {
       dfree(m->escale);
       dfree(m->xsplit);
-      m->escale_n = 0;
+      m->escale_n = m->xsplit_n = 0;
       FPDE_TRY(dalloc(&m->escale, (size_t)need));
-      FPDE_TRY(dalloc(&m->xsplit, (size_t)(need / n * sx)));
+      FPDE_TRY(dalloc(&m->xsplit, (size_t)xneed));
       m->escale_n = need;
+      m->xsplit_n = xneed;
     }
     escale = m->escale;
     xsplit = m->xsplit;
@@ -421,11 +445,12 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
   const unsigned z = (unsigned)count;
   k_potrf_diag<T><<<dim3(1, z), 256, 0, s>>>(A, lda, n, 0, Linv, LinvT, m->flag, aux, sA, sL);
   // Panels in groups of kGroup: after panel s of a group (X_s = B inv(L)^T
-  // for the 64 columns at ks, every row below), only the group's later block
-  // columns are updated by it (a strip, KD = 64; its tile (0, 0) factors the
-  // next diagonal block), and the trailing matrix beyond the group is
-  // updated once by the whole group (KD = 64 kGroup, 128 x 128 tiles): the
-  // trailing matrix is read and written once per kGroup panels.
+  // for the 64 columns at ks, every row below), only later block columns of
+  // its part of the group are updated by it (a strip, KD = 64; its tile
+  // (0, 0) factors the next diagonal block), at the end of a part the next
+  // part's columns by the part's panels, and the trailing matrix beyond the
+  // group once by the whole group (KD = 64 kGroup): the trailing matrix is
+  // read and written once per kGroup panels.
   for (int64_t k0 = 0; k0 < n; k0 += kGroup * NB) {
     for (int sp = 0; sp < kGroup; sp++) {
       const int64_t ks = k0 + sp * NB;
@@ -434,20 +459,38 @@ static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *L
       T *Lk = Linv + (ks / NB) * NB * NB;
       T *Ln = Lk + NB * NB, *LnT = LinvT + (ks / NB + 1) * NB * NB;
       k_panel<T><<<dim3(nblk(rest, 64), z), 256, 0, s>>>(A, lda, n, ks, Lk, sA, sL);
-      const int64_t Tn = (rest + 63) / 64;  // block rows (and columns) below panel sp
-      const int inner = kGroup - 1 - sp;    // block columns of the group after panel sp
+      const int64_t Tn = (rest + 63) / 64;              // block rows (and columns) below panel sp
+      const int inner = kPart - 1 - sp % kPart;  // block columns of the part after panel sp
       if (Tn <= inner) {
-        // the rest of the matrix lies inside the group: all of it, by this panel
+        // the rest of the matrix lies inside the part: all of it, by this panel
         k_syrk<T, NB><<<(unsigned)(Tn * (Tn + 1) / 2 * count), 256, 0, s>>>(A, lda, n, ks, Ln, LnT, m->flag,
                                                                                 aux, sA, sL, count, 0);
       } else if (inner > 0) {
         const int64_t tiles = (int64_t)inner * Tn - (int64_t)inner * (inner - 1) / 2;
         k_syrk<T, NB><<<(unsigned)(tiles * count), 256, 0, s>>>(A, lda, n, ks, Ln, LnT, m->flag, aux, sA, sL,
                                                                  count, inner);
+      } else if (sp + 1 < kGroup) {
+        // end of a part of the group: the next d panels' columns, every row
+        // from there, by the d panels just factored, at once.  FP32: the
+        // split rows go to this group's set, which nothing else reads
+        // before the group's own split.
+        const int64_t q = la ? (k0 / (kGroup * NB)) & 1 : 0;
+        int *es = escale ? escale + q * count * n : nullptr;
+        _Float16 *xq = xsplit ? xsplit + q * count * sx : nullptr;
+        // panels updating at once: the largest power of two dividing sp + 1
+        // (a multiple of kPart, at most kGroup / 2)
+        const int d = (sp + 1) & -(sp + 1);
+        static_assert((kGroup <= 32 && kPart == 4) || kPart == kGroup, "parts of 4 panels, or none");
+        if (d == 16)
+          group_part_update<T, 16 * NB>(A, lda, sA, n, count, ks + NB, Ln, LnT, sL, aux, m->flag, es, xq, sx, s);
+        else if (d == 8)
+          group_part_update<T, 8 * NB>(A, lda, sA, n, count, ks + NB, Ln, LnT, sL, aux, m->flag, es, xq, sx, s);
+        else
+          group_part_update<T, 4 * NB>(A, lda, sA, n, count, ks + NB, Ln, LnT, sL, aux, m->flag, es, xq, sx, s);
       } else {
         // the group's update of the trailing matrix from k0 + 64 kGroup on
         // 128 x 128 or 256 x 256 tiles (FP32: split FP16 with per-row
-        // exponents over the group's 1024 columns)
+        // exponents over the group's 64 kGroup columns)
         const int64_t base = k0 + kGroup * NB;
         // this group's set of split rows
         const int64_t q = la ? (k0 / (kGroup * NB)) & 1 : 0;
@@ -499,6 +542,21 @@ factored:
   timer_end(m, FPDE_STAGE_POTRF, t, s, count);
   FPDE_HIP(hipGetLastError());
   return FPDE_OK;
+}
+
+// From 16 384 unknowns on, groups of 32 panels in parts of 4; below, groups
+// of 16 with per-panel strips over the rest of the group.  Measured, FP32 /
+// FP64 factorization at N = 66 822: groups of 8 with per-panel strips
+// 415 ms / 1.83 s; of 16: 375 ms / 1.78 s; of 16 in halves: 353 ms /
+// 1.75 s; in parts of 4: 347 ms / 1.74 s; of 32 in parts of 4: 331 ms /
+// 1.70 s; of 64: 348 ms / 1.69 s.  At N = 3 072 (six systems) and
+// N = 4 494 (one system) the parts cost more launches than they save:
+// 3.6 / 4.7 ms against 3.1 / 4.0 ms with per-panel strips.
+template <class T>
+static int potrf_batch(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
+                       fpde_mesh *m, hipStream_t s) {
+  if (n >= 16384) return potrf_batch_g<T, 32, 4>(A, lda, sA, n, count, Linv, sL, aux, m, s);
+  return potrf_batch_g<T, 16, 16>(A, lda, sA, n, count, Linv, sL, aux, m, s);
 }
 
 template <class T>

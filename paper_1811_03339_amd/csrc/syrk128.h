@@ -1,6 +1,7 @@
 // Trailing update of the blocked Cholesky on 128 x 128 output tiles:
 //   C[I, J] -= X_I X_J^T  over the lower tiles I >= J of the trailing matrix,
-// X = the KD = 1024 columns of the group of panels just factored.  One
+// X = the KD columns of the panels just factored (2048 for a whole group,
+// 256 to 1024 inside one).  One
 // workgroup per output tile reads and writes its tile of C once and streams
 // X_I and X_J through LDS in chunks of the inner dimension, double-buffered:
 // a 128-wide tile halves the reads of X per output entry compared with
