@@ -5,11 +5,12 @@ end exactly at N or in a partial last block, a whole group and its
 in-group strips only (N = 1000), and a group followed by a trailing update
 of five full and one partial 128 x 128 tile rows (N = 1728).
 
-The FP32 factorization (split-FP16 trailing updates over groups of sixteen
-panels, 1024 columns) is checked on assembled mixed-precision matrices:
-part of one group (N = 512, 1000), one group then a trailing update with a
-ragged tail (1728), whole groups (4096) and 17 576 unknowns (look-ahead,
-256 x 256 tiles).  Its
+The FP32 factorization (split-FP16 trailing updates; groups of sixteen
+panels with per-panel strips below 16 384 unknowns, of 32 panels updated in
+four-panel parts from there) is checked on assembled mixed-precision
+matrices: part of one group (N = 512, 1000), one group then a trailing
+update with a ragged tail (1728), whole groups (4096) and 19 683 unknowns
+(parts, look-ahead, 256 x 256 tiles).  Its
 factor must lie within 16 times LAPACK's own FP32 factorization's
 (spotrf) distance from the FP64 Cholesky factor of the same FP32 matrix:
 the panels apply each 64 x 64 diagonal block through its explicit inverse
@@ -85,9 +86,10 @@ def test_batch_matches_lapack(k):
         assert rel(u[z].cpu().numpy(), np.linalg.solve(S, rhs)) <= 1e-10, z
 
 
-# n = 512 ... 4096, and 17576, whose first trailing update (16 552 rows) takes
-# the 256 x 256 tiles with a ragged last tile row, under the look-ahead
-@pytest.mark.parametrize("k", [9, 11, 13, 17, 27])
+# n = 512 ... 4096, and 19683 (groups of 32 panels in parts of four), whose
+# first trailing update (17 635 rows) takes the 256 x 256 tiles with a ragged
+# last tile row, under the look-ahead
+@pytest.mark.parametrize("k", [9, 11, 13, 17, 28])
 def test_fp32_factor_as_accurate_as_spotrf(k):
     if k in SIZES:
         gm = mesh(k)
