@@ -356,11 +356,6 @@ int ensure_linv(fpde_mesh *m, int64_t n, size_t elem, int sets, void **out) {
   return FPDE_OK;
 }
 
-// Factor `count` matrices of a strided batch (A + z sA, z < count) with one
-// launch sequence: grid.y is the system, so the diagonal-block chains of the
-// systems run side by side.  Linv holds 2 nblk inverse blocks per system
-// (inverses, then transposes) at stride sL; aux[z] receives system z's
-// failing column.
 // Inside a panel group: the KD / 64 block columns from hb on, every row
 // from hb, by the KD columns of the group just before hb (X = columns
 // [hb - KD, hb)), as a strip of 128 x 128 tiles (FP32: split FP16 rows of
@@ -380,6 +375,11 @@ static void group_part_update(T *A, int64_t lda, int64_t sA, int64_t n, int coun
       A, lda, n, kx, hb, ntc, 1, Ln, LnT, flag, aux, sA, sL, es, n, xq, sx, count, work);
 }
 
+// Factor `count` matrices of a strided batch (A + z sA, z < count) with one
+// launch sequence: grid.y is the system, so the diagonal-block chains of the
+// systems run side by side.  Linv holds 2 nblk inverse blocks per system
+// (inverses, then transposes) at stride sL; aux[z] receives system z's
+// failing column.
 template <class T, int kGroup, int kPart>
 static int potrf_batch_g(T *A, int64_t lda, int64_t sA, int64_t n, int count, T *Linv, int64_t sL, int64_t *aux,
                          fpde_mesh *m, hipStream_t s) {
