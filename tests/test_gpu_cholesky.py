@@ -25,6 +25,7 @@ at a time and as a batch.
 """
 import numpy as np
 import pytest
+import scipy.linalg
 import torch
 
 import paper_1811_03339_amd as F
@@ -68,6 +69,32 @@ def test_factor_and_solve_match_lapack(k):
     torch.cuda.synchronize()
     assert rel(np.tril(A.cpu().numpy()), np.linalg.cholesky(S)) <= 1e-10
     assert rel(u.cpu().numpy(), np.linalg.solve(S, rhs)) <= 1e-10
+
+
+def test_fp64_factor_groups_of_32_match_lapack():
+    """17 576 unknowns: groups of 32 panels updated in four-panel parts (part
+    updates over 256, 512 and 1024 columns), look-ahead on the side stream.
+    A missed or repeated contribution of any panel to any block column would
+    put the factor far outside the bound.  The matrix is a seeded random
+    symmetric one made diagonally dominant (SPD by Gershgorin)."""
+    cube = kuhn_cube(27)
+    gm = F.Mesh(cube.xyz, cube.tet)
+    n = gm.n_dof
+    print(f"[cholesky] groups of 32, n={n}", flush=True)
+    rng = np.random.default_rng(327)
+    S = rng.random((n, n))
+    S += S.T
+    S[np.diag_indices(n)] += 2.0 * n
+    rhs = rng.normal(size=n)
+    A = torch.tensor(S, device="cuda")
+    b = torch.tensor(rhs, device="cuda")
+    u = torch.empty_like(b)
+    gm.solve(F.params(1.5), A, b, u, info=False)
+    torch.cuda.synchronize()
+    L = np.linalg.cholesky(S)
+    assert rel(np.tril(A.cpu().numpy()), L) <= 1e-10
+    ref = scipy.linalg.cho_solve((L, True), rhs)
+    assert rel(u.cpu().numpy(), ref) <= 1e-10
 
 
 @pytest.mark.parametrize("k", [3, 6, 7, 9, 10, 11])
